@@ -1,0 +1,238 @@
+"""ctypes binding of the CPU oracle (liboracle.so).
+
+TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the CPU-baseline
+leg of the benchmark may import this module; the GPU library never does.
+
+Contour functions use the canonical storage of the paper (Eq. storage_herm):
+``mat`` [ntau+1, d, d], ``ret``/``les`` [(nt+1)(nt+2)/2, d, d] with slice n at
+offset n(n+1)/2, ``tv`` [(nt+1)(ntau+1), d, d], all complex128.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB = os.path.join(HERE, "liboracle.so")
+SOURCES = ["weights.cpp", "linalg.cpp", "convolution.cpp", "dyson.cpp", "sigma.cpp", "capi.cpp"]
+
+
+def build(verbose: bool = False) -> str:
+    """Compile liboracle.so with g++ (OpenMP over the independent loops)."""
+    cmd = ["g++", "-O2", "-std=c++17", "-fopenmp", "-fPIC", "-shared", "-Wall",
+           "-o", LIB + ".tmp"] + [os.path.join(HERE, s) for s in SOURCES]
+    subprocess.run(cmd, check=True, capture_output=not verbose)
+    os.replace(LIB + ".tmp", LIB)
+    return LIB
+
+
+class _Grid(C.Structure):
+    _fields_ = [("nt", C.c_int32), ("ntau", C.c_int32), ("d", C.c_int32), ("sig", C.c_int32),
+                ("k", C.c_int32), ("beta", C.c_double), ("h", C.c_double), ("mu", C.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            build()
+        _lib = C.CDLL(LIB)
+        _lib.oracle_gregory.restype = C.c_double
+        _lib.oracle_distance.restype = C.c_double
+    return _lib
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+class Grid:
+    def __init__(self, nt, ntau, d, sig=-1, k=5, beta=1.0, h=0.01, mu=0.0):
+        self.nt, self.ntau, self.d, self.sig, self.k = int(nt), int(ntau), int(d), int(sig), int(k)
+        self.beta, self.h, self.mu = float(beta), float(h), float(mu)
+
+    @property
+    def htau(self):
+        return self.beta / self.ntau
+
+    def c(self):
+        return _Grid(self.nt, self.ntau, self.d, self.sig, self.k, self.beta, self.h, self.mu)
+
+
+class HM:
+    """A hermitian contour function in the canonical layout (numpy owned)."""
+
+    def __init__(self, g: Grid):
+        self.g = g
+        d, nt, ntau = g.d, g.nt, g.ntau
+        self.mat = np.zeros((ntau + 1, d, d), np.complex128)
+        self.ret = np.zeros(((nt + 1) * (nt + 2) // 2, d, d), np.complex128)
+        self.les = np.zeros(((nt + 1) * (nt + 2) // 2, d, d), np.complex128)
+        self.tv = np.zeros(((nt + 1) * (ntau + 1), d, d), np.complex128)
+
+    def args(self):
+        return [_p(self.mat), _p(self.ret), _p(self.les), _p(self.tv)]
+
+    def copy(self):
+        o = HM(self.g)
+        for f in ("mat", "ret", "les", "tv"):
+            getattr(o, f)[...] = getattr(self, f)
+        return o
+
+    # element access (views)
+    def R(self, n, j):
+        return self.ret[n * (n + 1) // 2 + j]
+
+    def L(self, j, n):
+        return self.les[n * (n + 1) // 2 + j]
+
+    def T(self, n, m):
+        return self.tv[n * (self.g.ntau + 1) + m]
+
+    def M(self, m):
+        return self.mat[m]
+
+    def ret_row(self, n):
+        return self.ret[n * (n + 1) // 2: n * (n + 1) // 2 + n + 1]
+
+    def les_col(self, n):
+        return self.les[n * (n + 1) // 2: n * (n + 1) // 2 + n + 1]
+
+    def tv_row(self, n):
+        return self.tv[n * (self.g.ntau + 1): (n + 1) * (self.g.ntau + 1)]
+
+
+def weights(k):
+    n = k + 1
+    P, D = np.zeros(n * n), np.zeros(n * n)
+    Iw = np.zeros(n ** 3)
+    bdf, start, omega = np.zeros(n), np.zeros(n * n), np.zeros(n)
+    R = np.zeros(n ** 3)
+    if lib().oracle_weights(k, *(_p(x) for x in (P, D, Iw, bdf, start, omega, R))) != 0:
+        raise ValueError(k)
+    return dict(P=P.reshape(n, n), D=D.reshape(n, n), I=Iw.reshape(n, n, n), a=bdf,
+                s=start.reshape(n, n), omega=omega, R=R.reshape(n, n, n))
+
+
+def gregory(k, n, j):
+    return lib().oracle_gregory(k, n, j)
+
+
+def gregory_rational(k, n, j):
+    num, den = C.c_int64(), C.c_int64()
+    lib().oracle_gregory_rational(k, n, j, C.byref(num), C.byref(den))
+    return num.value, den.value
+
+
+def solve(A, B):
+    A = np.ascontiguousarray(A, np.complex128).copy()
+    B = np.ascontiguousarray(B, np.complex128).copy()
+    n = A.shape[0]
+    nrhs = 1 if B.ndim == 1 else B.shape[1]
+    if lib().oracle_solve(n, nrhs, _p(A), _p(B)) != 0:
+        raise np.linalg.LinAlgError("singular")
+    return B
+
+
+def eigh(A):
+    A = np.ascontiguousarray(A, np.complex128)
+    d = A.shape[0]
+    w = np.zeros(d)
+    V = np.zeros((d, d), np.complex128)
+    lib().oracle_eigh(d, _p(A), _p(w), _p(V))
+    return w, V
+
+
+def free_mat(g: Grid, eps):
+    out = np.zeros((g.ntau + 1, g.d, g.d), np.complex128)
+    lib().oracle_free_mat(C.byref(g.c()), _p(np.ascontiguousarray(eps, np.complex128)), _p(out))
+    return out
+
+
+def convolution_timestep(n, C_: HM, A: HM, Acc: HM, B: HM, Bcc: HM, f=None):
+    g = A.g
+    lib().oracle_convolution_timestep(n, C.byref(g.c()), *C_.args(), *A.args(), *Acc.args(),
+                                      *B.args(), *Bcc.args(), _p(f))
+
+
+def conv_les_diag(n, A: HM, B: HM):
+    out = np.zeros((A.g.d, A.g.d), np.complex128)
+    lib().oracle_conv_les_diag(n, C.byref(A.g.c()), *A.args(), *B.args(), _p(out))
+    return out
+
+
+def dyson_mat(G: HM, S: HM, eps_m1):
+    e = np.ascontiguousarray(eps_m1, np.complex128)
+    return lib().oracle_dyson_mat(C.byref(G.g.c()), *G.args(), *S.args(), _p(e))
+
+
+def dyson_start(G: HM, S: HM, eps):
+    e = np.ascontiguousarray(eps, np.complex128)
+    return lib().oracle_dyson_start(C.byref(G.g.c()), *G.args(), *S.args(), _p(e))
+
+
+def dyson_timestep(n, G: HM, S: HM, eps, variant="B"):
+    e = np.ascontiguousarray(eps, np.complex128)
+    return lib().oracle_dyson_timestep(n, C.byref(G.g.c()), *G.args(), *S.args(), _p(e),
+                                       ord(variant))
+
+
+def sigma_2b(n, G: HM, U, S: HM):
+    u = np.ascontiguousarray(U, np.float64)
+    lib().oracle_sigma_2b(n, C.byref(G.g.c()), *G.args(), _p(u), *S.args())
+
+
+def hartree(n, G: HM, U, eps0, eps_mf, nbar=0.5):
+    lib().oracle_hartree(n, C.byref(G.g.c()), *G.args(), _p(np.ascontiguousarray(U, np.float64)),
+                         _p(eps0), _p(eps_mf), C.c_double(nbar))
+
+
+def density_matrix(n, G: HM):
+    out = np.zeros((G.g.d, G.g.d), np.complex128)
+    lib().oracle_density_matrix(n, C.byref(G.g.c()), *G.args(), _p(out))
+    return out
+
+
+def extrapolate(n, G: HM):
+    lib().oracle_extrapolate(n, C.byref(G.g.c()), *G.args())
+
+
+def distance(n, A: HM, B: HM):
+    return lib().oracle_distance(n, C.byref(A.g.c()), *A.args(), *B.args())
+
+
+def solve_fixed(G: HM, S: HM, eps, nt_stop=None, variant="B"):
+    e = np.ascontiguousarray(eps, np.complex128)
+    secs = np.zeros(3)
+    nt_stop = G.g.nt if nt_stop is None else nt_stop
+    rc = lib().oracle_solve_fixed(C.byref(G.g.c()), *G.args(), *S.args(), _p(e), nt_stop,
+                                  ord(variant), _p(secs))
+    return rc, secs
+
+
+def solve_2b(G: HM, S: HM, eps0, U, nbar=0.5, mats_maxit=200, mats_tol=1e-14, boot_maxit=100,
+             boot_tol=1e-14, ncorr=6, corr_tol=0.0, nt_stop=None, variant="B"):
+    """Self-consistent 2B + Hartree run; returns (rc, eps_mf, stats)."""
+    g = G.g
+    e0 = np.ascontiguousarray(eps0, np.complex128)
+    emf = np.zeros_like(e0)
+    Gold = HM(g)
+    stats = np.zeros(6)
+    nt_stop = g.nt if nt_stop is None else nt_stop
+    rc = lib().oracle_solve_2b(C.byref(g.c()), *G.args(), *S.args(), *Gold.args(), _p(e0),
+                               _p(np.ascontiguousarray(U, np.float64)), _p(emf), C.c_double(nbar),
+                               mats_maxit, C.c_double(mats_tol), boot_maxit, C.c_double(boot_tol),
+                               ncorr, C.c_double(corr_tol), nt_stop, ord(variant), _p(stats))
+    return rc, emf, dict(mats_iter=int(stats[0]), boot_iter=int(stats[1]),
+                         corr_total=int(stats[2]), mats_err=stats[3], boot_err=stats[4],
+                         corr_err_max=stats[5])
+
+
+def num_threads():
+    return lib().oracle_num_threads()

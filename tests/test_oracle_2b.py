@@ -1,0 +1,153 @@
+"""Pins of the oracle's second-Born self-energy, mean field, extrapolation
+and the self-consistent propagation (invariants of field-free 2B)."""
+import numpy as np
+import pytest
+
+from paper_1911_01211_amd import workloads as W
+from tests.test_oracle_dyson import grid, hm
+
+
+def full_two_time(O, G, g):
+    """Dense G^>(t,t') and G^<(t,t') on the real-time grid, [nt+1, nt+1, d, d],
+    assembled from the stored triangles with the hermitian symmetry."""
+    n1, d = g.nt + 1, g.d
+    gl = np.zeros((n1, n1, d, d), np.complex128)
+    gg = np.zeros_like(gl)
+    for n in range(n1):
+        for j in range(n + 1):
+            L = G.L(j, n)
+            gl[j, n] = L
+            gl[n, j] = -L.conj().T
+    for n in range(n1):
+        for j in range(n + 1):
+            gg[n, j] = G.R(n, j) + gl[n, j]        # G^> = G^R + G^< for t >= t'
+            gg[j, n] = -gg[n, j].conj().T
+    return gl, gg
+
+
+def test_sigma_2b_against_dense_contour_product(O):
+    g = W.GridSpec(nt=9, ntau=12, d=3, beta=2.0, h=0.1, k=3)
+    r = W.rng(7)
+    c = W.random_contour(r, g, 0.7)
+    for n in range(g.nt + 1):  # equal-time R and < blocks are anti-hermitian
+        for key in ("les", "ret"):
+            x = c[key][n * (n + 1) // 2 + n]
+            c[key][n * (n + 1) // 2 + n] = (x - x.conj().T) / 2
+    G = hm(O, g, c)
+    U = r.uniform(0.5, 2.0, g.nt + 2)
+    S = hm(O, g)
+    for n in range(-1, g.nt + 1):
+        O.sigma_2b(n, G, U, S)
+    gl, gg = full_two_time(O, G, g)
+    u = U[1:]
+    for n in range(g.nt + 1):
+        for j in range(n + 1):
+            # Sigma^<(t_j, t_n) = U U (G^<_ab(j,n))^2 G^>_ba(n,j), Eq. sigma_hubb_2b
+            ref_l = u[j] * u[n] * gl[j, n] ** 2 * gg[n, j].T
+            assert np.allclose(S.L(j, n), ref_l, atol=1e-12)
+            sg = u[n] * u[j] * gg[n, j] ** 2 * gl[j, n].T
+            sl = u[n] * u[j] * gl[n, j] ** 2 * gg[j, n].T
+            assert np.allclose(S.R(n, j), sg - sl, atol=1e-12)
+        for m in range(g.ntau + 1):
+            vt = -g.sig * G.T(n, g.ntau - m).conj()       # G^lceil_ba(m, n)
+            assert np.allclose(S.T(n, m), u[n] * U[0] * G.T(n, m) ** 2 * vt, atol=1e-12)
+    for m in range(g.ntau + 1):
+        ref = -g.sig * U[0] ** 2 * G.mat[m] ** 2 * G.mat[g.ntau - m].T
+        assert np.allclose(S.mat[m], ref, atol=1e-12)
+
+
+def test_sigma_2b_keeps_hermitian_symmetry(O):
+    # For G with hermitian symmetry, Sigma^<(t_j,t_n) = -[Sigma^<(t_n,t_j)]^dag
+    # where the right side is built from the formula for t_n >= t_j.
+    g = W.GridSpec(nt=12, ntau=20, d=2, beta=3.0, h=0.05, k=5)
+    eps, Sf, _ = W.two_level_embedding(g)
+    G = hm(O, g)
+    O.solve_fixed(G, hm(O, g, Sf), eps)
+    U = np.full(g.nt + 2, 1.3)
+    S = hm(O, g)
+    for n in range(-1, g.nt + 1):
+        O.sigma_2b(n, G, U, S)
+    for m in range(g.ntau + 1):
+        assert np.allclose(S.mat[m], S.mat[m].conj().T, atol=1e-13)
+    gl, gg = full_two_time(O, G, g)
+    for n in range(g.nt + 1):
+        for j in range(n):
+            snj = U[1] ** 2 * gl[n, j] ** 2 * gg[j, n].T
+            assert np.allclose(S.L(j, n), -snj.conj().T, atol=1e-12)
+
+
+def test_extrapolation_exact_on_polynomials(O):
+    # Eq. polyextrap is exact when every component is a polynomial of degree
+    # <= k along the extrapolation lines.
+    k = 4
+    g = W.GridSpec(nt=14, ntau=6, d=2, beta=1.0, h=0.1, k=k)
+    r = W.rng(8)
+    c = r.normal(size=(k + 1, 4, 2, 2)) + 1j * r.normal(size=(k + 1, 4, 2, 2))
+    poly = lambda t, i: sum(c[a, i] * t ** a for a in range(k + 1))
+    G = hm(O, g)
+    # R and L depend on (t - t') (diagonal lines) plus columns j <= k; choose
+    # time-translation invariant polynomials so both rules are exact.
+    for n in range(g.nt + 1):
+        for j in range(n + 1):
+            G.R(n, j)[...] = poly(n - j, 0)
+            G.L(j, n)[...] = poly(j - n, 1)
+            if j < n:
+                pass
+        for m in range(g.ntau + 1):
+            G.T(n, m)[...] = poly(n, 2) * (m + 1)
+    # L must be consistent with hermitian symmetry for the rows j <= k:
+    # L_{a,b} = -L_{b,a}^dag; use an anti-hermitian polynomial in (j - n).
+    for n in range(g.nt + 1):
+        for j in range(n + 1):
+            x = j - n
+            G.L(j, n)[...] = sum((c[a, 1] - (-1) ** a * c[a, 1].conj().T) * x ** a for a in range(k + 1))
+            G.R(n, j)[...] = sum((c[a, 0] - (-1) ** a * c[a, 0].conj().T) * (n - j) ** a
+                                 for a in range(k + 1))
+    ref = G.copy()
+    n = 10
+    O.extrapolate(n - 1, G)
+    assert np.allclose(G.tv_row(n), ref.tv_row(n), atol=1e-9)
+    assert np.allclose(G.ret_row(n), ref.ret_row(n), atol=1e-8)
+    assert np.allclose(G.les_col(n), ref.les_col(n), atol=1e-8)
+
+
+def _gm_energy(O, G, S, e0, emf):
+    E, N = [], []
+    for n in range(G.g.nt + 1):
+        rho = O.density_matrix(n, G)
+        ec = O.conv_les_diag(n, S, G)
+        E.append(0.5 * np.trace(rho @ (e0[n + 1] + emf[n + 1])).real + 0.5 * np.trace(ec).imag)
+        N.append(np.trace(rho).real)
+    return np.array(E), np.array(N)
+
+
+@pytest.mark.parametrize("U0", [0.0, 1.0])
+def test_2b_dimer_quench_conservation_order(O, U0):
+    # Field-free 2B is conserving: total energy (Galitskii-Migdal, Eq.
+    # Total_ener) and particle number are constant after the quench, up to the
+    # O(h^k) discretisation error (Sec. "Hubbard chain").
+    drift = []
+    for h in (0.05, 0.025):
+        g = W.GridSpec(nt=int(round(3.0 / h)), ntau=100, d=2, beta=10.0, h=h, k=5)
+        e0, U = W.dimer_quench(g, U=U0, w0=3.0)
+        G, S = hm(O, g), hm(O, g)
+        rc, emf, st = O.solve_2b(G, S, e0, U, ncorr=6)
+        assert rc == 0 and st["corr_err_max"] < 1e-10
+        E, N = _gm_energy(O, G, S, e0, emf)
+        drift.append((np.ptp(E), np.ptp(N)))
+    (e1, n1), (e2, n2) = drift
+    assert e2 < 1e-4 and np.log2(e1 / e2) > 4.0, drift
+    assert n2 < 1e-4 and np.log2(n1 / n2) > 4.0, drift
+
+
+def test_2b_half_filled_chain_density(O):
+    # Open chains at half filling are particle-hole symmetric: n_i = 1/2 in
+    # equilibrium and during a uniform U ramp.
+    g = W.GridSpec(nt=30, ntau=100, d=4, beta=10.0, h=0.02, k=5)
+    e0, U = W.hubbard_ramp(g)
+    G, S = hm(O, g), hm(O, g)
+    rc, emf, st = O.solve_2b(G, S, e0, U, ncorr=5)
+    assert rc == 0
+    for n in (-1, 0, 10, 30):
+        rho = O.density_matrix(n, G)
+        assert np.allclose(np.diag(rho).real, 0.5, atol=1e-10), (n, np.diag(rho))
