@@ -1,0 +1,182 @@
+/* cntr.h -- C ABI of the MI355X (gfx950) Kadanoff-Baym / Dyson time stepper.
+ *
+ * The library solves the Dyson equation of nonequilibrium Green's functions
+ * on the L-shaped Kadanoff-Baym contour, following NESSi / libcntr
+ * (arXiv:1911.01211, Part II): Matsubara solve, start-up, k-th order time
+ * stepping with BDF derivatives and Gregory quadrature for the history
+ * convolutions, the contour convolution, and the second-Born self-energy.
+ *
+ * Conventions (all entry points)
+ *  - Complex numbers are complex128, interleaved (re, im), the storage of
+ *    torch.complex128 / numpy.complex128 / C99 double _Complex.
+ *  - Contour functions are given by four DEVICE pointers in the canonical
+ *    storage of the paper (Eq. storage_herm), each entry a row-major d x d
+ *    block:
+ *        mat : [ntau+1]                 C^M_m = C^M(m h_tau)
+ *        ret : [(nt+1)(nt+2)/2]         C^R_{n,j} at n(n+1)/2 + j, j <= n
+ *        les : [(nt+1)(nt+2)/2]         C^<_{j,n} at n(n+1)/2 + j, j <= n
+ *        tv  : [(nt+1)(ntau+1)]         C^rceil_{n,m} at n(ntau+1) + m
+ *    Time slice n (Sec. "Numerical representation of NEGFs") is the row
+ *    R_{n,0..n}, the column L_{0..n,n} and the row T_{n,0..ntau}; slice -1 is
+ *    the Matsubara component.
+ *  - Single-time functions (eps, eps_mf) are DEVICE arrays of (nt+2) d x d
+ *    blocks; entry n+1 holds time n, entry 0 holds the equilibrium value
+ *    f(0^-) of the imaginary branch. U is a DEVICE array of nt+2 doubles
+ *    with the same indexing.
+ *  - sig = -1 for fermions, +1 for bosons; k (1..5) is the order of the
+ *    scheme; h is the time step, beta the inverse temperature, h_tau =
+ *    beta/ntau, mu the chemical potential (the contour evolves with eps-mu).
+ *  - Every call takes `count` instances: host arrays of `count` grids and
+ *    contour descriptors (the pointers inside are device pointers). count = 1
+ *    is the plain per-instance path.
+ *  - Ownership: the caller allocates and frees every array passed in; the
+ *    library keeps no pointer after a call returns. Internal scratch memory
+ *    and the weight tables are owned by the library (released by
+ *    cntr_finalize).
+ *  - Streams: `stream` is a hipStream_t (NULL = default stream). Work is
+ *    enqueued asynchronously; host-side validation fails before anything is
+ *    enqueued. Conditions detected on the device (a singular step matrix)
+ *    are reported by cntr_sync on the same stream.
+ *  - Errors: every call returns a cntr_status; nothing aborts or exits.
+ *    cntr_last_error() returns a message for the last failure of the
+ *    calling thread.
+ */
+#ifndef CNTR_H
+#define CNTR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  CNTR_OK = 0,
+  CNTR_EINVAL = -1,     /* k not in 1..5, d < 1 or d > 8, ntau < 2k+2, nt < k, sig not +-1, h/beta <= 0 */
+  CNTR_ESHAPE = -2,     /* inconsistent instances or NULL pointers */
+  CNTR_EORDER = -3,     /* tstp out of range for the instance (causality, Tab. dyson) */
+  CNTR_ESINGULAR = -4,  /* singular step or start-up matrix (device) */
+  CNTR_ENONFINITE = -5, /* non-finite value detected */
+  CNTR_EHIP = -6,       /* HIP runtime error */
+  CNTR_ENOMEM = -7,     /* device allocation failed */
+  CNTR_ENOCONV = -8     /* iteration did not reach its tolerance */
+} cntr_status;
+
+typedef struct {
+  int32_t nt, ntau, d, sig, k;
+  double beta, h, mu;
+} cntr_grid;
+
+typedef struct {
+  void *mat, *ret, *les, *tv; /* device pointers, canonical layout */
+} cntr_gf;
+
+/* ------------------------------------------------------------------ A1 --
+ * Matsubara component T[G]_{-1} (Sec. "Matsubara", Eq. Gmat_dyson_integ):
+ * the exact solution of the discrete integral equation
+ *     G^M = g + [K * G]^M,  K = [g * Sigma]^M,
+ * with g the free Matsubara function of eps_{-1} - mu and the convolutions
+ * discretised by Eqs. cm1/cm2 (Gregory weights, boundary-convolution
+ * weights near the ends). Inputs: Sigma[i].mat, eps[i] (entry 0 used).
+ * Output: G[i].mat. The linear system is solved on the device to a relative
+ * residual below `tol` (<= 0: 1e-14) within `max_iter` refinement sweeps
+ * (<= 0: 200); otherwise CNTR_ENOCONV. This call synchronizes `stream`. */
+cntr_status cntr_init_matsubara(int32_t count, const cntr_grid* grids, const cntr_gf* G,
+                                const cntr_gf* Sigma, const void* const* eps, double tol,
+                                int32_t max_iter, void* stream);
+
+/* ---------------------------------------------------------------- A2-A7 --
+ * Dyson equation (Eq. dyson, Sec. "Implementation: dyson").
+ *  tstp <= k : start-up, computes slices 0..k from T[G]_{-1}, Sigma slices
+ *              -1..k and eps (Sec. "Start", Tab. dyson row dyson_start).
+ *  tstp  > k : time step, computes slice tstp from slices -1..tstp-1 of G,
+ *              Sigma slices tstp-k..tstp and eps (Sec. "Time stepping"):
+ *              retarded row by single Volterra steps per column plus a
+ *              k-point conjugate start-up at the diagonal, left-mixing row by
+ *              one Volterra step per tau index, lesser column by single
+ *              conjugate steps per row and k+1 serial boundary steps (for
+ *              tstp <= 2k the whole column is done serially).
+ * Instances with nt < tstp are skipped. eps[i] is the (mean-field)
+ * single-particle Hamiltonian. Writes slice(s) of G[i] only. */
+cntr_status cntr_dyson_step(int32_t tstp, int32_t count, const cntr_grid* grids, const cntr_gf* G,
+                            const cntr_gf* Sigma, const void* const* eps, void* stream);
+
+/* ------------------------------------------------------------------ A8 --
+ * Contour convolution C = A * f * B on time slice tstp (Eq. convolution,
+ * Tab. convolution; discretised by Eqs. cm1, cm2, cr1, ctv1-ctv3,
+ * cles1-cles3). A and B need not be hermitian: Acc and Bcc are their
+ * hermitian conjugates A^ddagger, B^ddagger, used for values outside the
+ * stored triangles (pass A and B again for hermitian inputs). f[i] is a
+ * single-time function or NULL for f = 1 (f may itself be NULL). tstp = -1
+ * computes the Matsubara component. tstp <= k reads slices 0..k of the
+ * inputs; tstp > k reads slices 0..tstp. Writes slice tstp of C[i]. */
+cntr_status cntr_convolution(int32_t tstp, int32_t count, const cntr_grid* grids, const cntr_gf* C,
+                             const cntr_gf* A, const cntr_gf* Acc, const cntr_gf* B,
+                             const cntr_gf* Bcc, const void* const* f, void* stream);
+
+/* ------------------------------------------------------------------ A9 --
+ * Second-Born self-energy of the spin-symmetric Hubbard model on slice tstp
+ * (Eq. sigma_hubb_2b): Sigma_ab(z,z') = U(z) U(z') G_ab(z,z')^2 G_ba(z',z),
+ * elementwise in the orbital indices, every Keldysh component derived from
+ * the contour product (Sigma^R = Sigma^> - Sigma^<, Eq. Cretmod); tstp = -1
+ * gives the Matsubara component. When eps_mf is non-NULL the Hartree mean
+ * field eps_mf_tstp = eps0_tstp + diag(U_tstp (n_i - nbar)) is also written
+ * (Sec. "Hubbard chain"; n_i from the density matrix of slice tstp). Reads
+ * slice tstp of G[i]; writes slice tstp of Sigma[i] (and eps_mf[i]). */
+cntr_status cntr_sigma_2b(int32_t tstp, int32_t count, const cntr_grid* grids, const cntr_gf* G,
+                          const double* const* U, const cntr_gf* Sigma, const void* const* eps0,
+                          void* const* eps_mf, double nbar, void* stream);
+
+/* --------------------------------------------------------------- A10, A13 --
+ * Polynomial predictor T[G]_tstp -> T[G]_{tstp+1} (Eq. polyextrap, App.
+ * "Extrapolation of contour functions"); needs tstp >= k. */
+cntr_status cntr_extrapolate(int32_t tstp, int32_t count, const cntr_grid* grids, const cntr_gf* G,
+                             void* stream);
+
+/* Distance of two slices (Eq. distancenorm: sum of |A - B| over the slice)
+ * and the norm of A's slice, written to out[2*i], out[2*i+1] (HOST array of
+ * 2*count doubles). Synchronizes `stream`. */
+cntr_status cntr_distance(int32_t tstp, int32_t count, const cntr_grid* grids, const cntr_gf* A,
+                          const cntr_gf* B, double* out, void* stream);
+
+/* Copy slice tstp of src into dst (same grids). */
+cntr_status cntr_copy_slice(int32_t tstp, int32_t count, const cntr_grid* grids, const cntr_gf* dst,
+                            const cntr_gf* src, void* stream);
+
+/* Self-consistent second-Born + Hartree propagation (Sec. "Hubbard chain":
+ * Matsubara loop, bootstrapping over slices 0..k, then predictor-corrector
+ * time steps k+1..nt_stop) run by the library on `stream`:
+ *   Matsubara : {Hartree, Sigma_2B, Matsubara solve} until the relative
+ *               distance is below mats_tol (at most mats_maxit),
+ *   bootstrap : {Hartree, Sigma_2B on 0..k, start-up} until below boot_tol
+ *               and at least 3 iterations (at most boot_maxit),
+ *   steps     : extrapolation, then `ncorr` corrector iterations
+ *               {Hartree, Sigma_2B, time step} per slice.
+ * G, Sigma, eps_mf are outputs (Sigma and eps_mf consistent with the final
+ * G). Gscratch is a caller-owned contour function of the same grid used for
+ * the convergence checks. stats (HOST, may be NULL) receives: Matsubara
+ * iterations, bootstrap iterations, last Matsubara error, last bootstrap
+ * error. */
+cntr_status cntr_solve_2b(const cntr_grid* grid, const cntr_gf* G, const cntr_gf* Sigma,
+                          const cntr_gf* Gscratch, const void* eps0, const double* U,
+                          void* eps_mf, double nbar, int32_t mats_maxit, double mats_tol,
+                          int32_t boot_maxit, double boot_tol, int32_t ncorr, int32_t nt_stop,
+                          double* stats, void* stream);
+
+/* ------------------------------------------------------------- plumbing -- */
+/* Wait for `stream`; report a failure recorded by kernels since the last
+ * check (CNTR_ESINGULAR) or a HIP error. */
+cntr_status cntr_sync(void* stream);
+/* Message for the last failing call of this thread ("" if none). */
+const char* cntr_last_error(void);
+/* Release library-owned device memory (scratch). Safe to call any time no
+ * work is in flight; the library re-initialises on the next call. */
+cntr_status cntr_finalize(void);
+/* Library version string. */
+const char* cntr_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CNTR_H */

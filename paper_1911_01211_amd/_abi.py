@@ -1,0 +1,78 @@
+"""ctypes binding of libcntr.so (the C ABI declared in include/cntr.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of the library. Raises if the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcntr.so")
+
+STATUS = {0: "CNTR_OK", -1: "CNTR_EINVAL", -2: "CNTR_ESHAPE", -3: "CNTR_EORDER",
+          -4: "CNTR_ESINGULAR", -5: "CNTR_ENONFINITE", -6: "CNTR_EHIP", -7: "CNTR_ENOMEM",
+          -8: "CNTR_ENOCONV"}
+
+SYMBOLS = ["cntr_init_matsubara", "cntr_dyson_step", "cntr_convolution", "cntr_sigma_2b",
+           "cntr_extrapolate", "cntr_distance", "cntr_copy_slice", "cntr_solve_2b", "cntr_sync",
+           "cntr_last_error", "cntr_finalize", "cntr_version"]
+
+
+class CntrError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Grid(C.Structure):
+    _fields_ = [("nt", C.c_int32), ("ntau", C.c_int32), ("d", C.c_int32), ("sig", C.c_int32),
+                ("k", C.c_int32), ("beta", C.c_double), ("h", C.c_double), ("mu", C.c_double)]
+
+
+class GF(C.Structure):
+    _fields_ = [("mat", C.c_void_p), ("ret", C.c_void_p), ("les", C.c_void_p), ("tv", C.c_void_p)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"HIP library {LIB_PATH} is not built; run __graft_entry__.build()")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, dbl = C.c_void_p, C.c_int32, C.c_double
+        P = C.POINTER
+        L.cntr_init_matsubara.argtypes = [i32, P(Grid), P(GF), P(GF), P(vp), dbl, i32, vp]
+        L.cntr_dyson_step.argtypes = [i32, i32, P(Grid), P(GF), P(GF), P(vp), vp]
+        L.cntr_convolution.argtypes = [i32, i32, P(Grid), P(GF), P(GF), P(GF), P(GF), P(GF), P(vp), vp]
+        L.cntr_sigma_2b.argtypes = [i32, i32, P(Grid), P(GF), P(vp), P(GF), P(vp), P(vp), dbl, vp]
+        L.cntr_extrapolate.argtypes = [i32, i32, P(Grid), P(GF), vp]
+        L.cntr_distance.argtypes = [i32, i32, P(Grid), P(GF), P(GF), P(dbl), vp]
+        L.cntr_copy_slice.argtypes = [i32, i32, P(Grid), P(GF), P(GF), vp]
+        L.cntr_solve_2b.argtypes = [P(Grid), P(GF), P(GF), P(GF), vp, vp, vp, dbl, i32, dbl, i32,
+                                    dbl, i32, i32, P(dbl), vp]
+        L.cntr_sync.argtypes = [vp]
+        L.cntr_last_error.restype = C.c_char_p
+        L.cntr_version.restype = C.c_char_p
+        for name in SYMBOLS:
+            if name not in ("cntr_last_error", "cntr_version"):
+                getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def check(code):
+    if code != 0:
+        raise CntrError(code, lib().cntr_last_error().decode())
+    return code
+
+
+def arr(ctype, items):
+    a = (ctype * len(items))()
+    for i, x in enumerate(items):
+        a[i] = x
+    return a

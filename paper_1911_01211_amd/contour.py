@@ -1,0 +1,138 @@
+"""Device-resident contour functions (torch complex128 tensors in the
+canonical layout) and thin wrappers with the names of the C ABI.
+
+torch provides device memory and the stream; the computation is done by the
+HIP kernels of libcntr.so through ``_abi``.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import dataclasses
+
+import numpy as np
+import torch
+
+from . import _abi
+from .workloads import GridSpec
+
+KEYS = ("mat", "ret", "les", "tv")
+
+
+def _stream(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+def grid_c(g: GridSpec) -> _abi.Grid:
+    return _abi.Grid(g.nt, g.ntau, g.d, g.sig, g.k, g.beta, g.h, g.mu)
+
+
+class Contour:
+    """Hermitian contour function on one grid, stored on a torch device."""
+
+    def __init__(self, g: GridSpec, device="cuda", data: dict | None = None):
+        self.g = g
+        d = g.d
+        shapes = dict(mat=(g.ntau + 1, d, d), ret=(g.ntri, d, d), les=(g.ntri, d, d),
+                      tv=((g.nt + 1) * (g.ntau + 1), d, d))
+        for key in KEYS:
+            if data is not None:
+                t = torch.as_tensor(np.ascontiguousarray(data[key]), dtype=torch.complex128)
+                t = t.to(device).contiguous()
+            else:
+                t = torch.zeros(shapes[key], dtype=torch.complex128, device=device)
+            assert tuple(t.shape) == shapes[key], (key, t.shape, shapes[key])
+            setattr(self, key, t)
+
+    def gf(self) -> _abi.GF:
+        return _abi.GF(*(getattr(self, k).data_ptr() for k in KEYS))
+
+    def numpy(self) -> dict:
+        return {k: getattr(self, k).cpu().numpy() for k in KEYS}
+
+    def zero_(self):
+        for k in KEYS:
+            getattr(self, k).zero_()
+        return self
+
+
+def _gfs(items):
+    return _abi.arr(_abi.GF, [x.gf() for x in items])
+
+
+def _ptrs(items):
+    return _abi.arr(C.c_void_p, [None if x is None else x.data_ptr() for x in items])
+
+
+def _grids(items):
+    return _abi.arr(_abi.Grid, [grid_c(x.g) for x in items])
+
+
+def init_matsubara(G: list, Sigma: list, eps: list, tol=1e-14, max_iter=200, stream=None):
+    L = _abi.lib()
+    _abi.check(L.cntr_init_matsubara(len(G), _grids(G), _gfs(G), _gfs(Sigma), _ptrs(eps), tol,
+                                     max_iter, _stream(stream)))
+
+
+def dyson_step(tstp: int, G: list, Sigma: list, eps: list, stream=None):
+    L = _abi.lib()
+    _abi.check(L.cntr_dyson_step(tstp, len(G), _grids(G), _gfs(G), _gfs(Sigma), _ptrs(eps),
+                                 _stream(stream)))
+
+
+def convolution(tstp: int, C_: list, A: list, Acc: list, B: list, Bcc: list, f=None, stream=None):
+    L = _abi.lib()
+    fp = None if f is None else _ptrs(f)
+    _abi.check(L.cntr_convolution(tstp, len(C_), _grids(C_), _gfs(C_), _gfs(A), _gfs(Acc), _gfs(B),
+                                  _gfs(Bcc), fp, _stream(stream)))
+
+
+def sigma_2b(tstp: int, G: list, U: list, Sigma: list, eps0=None, eps_mf=None, nbar=0.5,
+             stream=None):
+    L = _abi.lib()
+    e0 = None if eps0 is None else _ptrs(eps0)
+    em = None if eps_mf is None else _ptrs(eps_mf)
+    _abi.check(L.cntr_sigma_2b(tstp, len(G), _grids(G), _gfs(G), _ptrs(U), _gfs(Sigma), e0, em,
+                               nbar, _stream(stream)))
+
+
+def extrapolate(tstp: int, G: list, stream=None):
+    _abi.check(_abi.lib().cntr_extrapolate(tstp, len(G), _grids(G), _gfs(G), _stream(stream)))
+
+
+def distance(tstp: int, A: list, B: list, stream=None):
+    out = (C.c_double * (2 * len(A)))()
+    _abi.check(_abi.lib().cntr_distance(tstp, len(A), _grids(A), _gfs(A), _gfs(B), out,
+                                        _stream(stream)))
+    return np.array(out[:]).reshape(len(A), 2)
+
+
+def copy_slice(tstp: int, dst: list, src: list, stream=None):
+    _abi.check(_abi.lib().cntr_copy_slice(tstp, len(dst), _grids(dst), _gfs(dst), _gfs(src),
+                                          _stream(stream)))
+
+
+def sync(stream=None):
+    _abi.check(_abi.lib().cntr_sync(_stream(stream)))
+
+
+@dataclasses.dataclass
+class Solve2BStats:
+    mats_iter: int
+    boot_iter: int
+    mats_err: float
+    boot_err: float
+
+
+def solve_2b(G: Contour, Sigma: Contour, Gscratch: Contour, eps0: torch.Tensor, U: torch.Tensor,
+             eps_mf: torch.Tensor, nbar=0.5, mats_maxit=200, mats_tol=1e-14, boot_maxit=100,
+             boot_tol=1e-14, ncorr=6, nt_stop=None, stream=None) -> Solve2BStats:
+    g = G.g
+    nt_stop = g.nt if nt_stop is None else nt_stop
+    st = (C.c_double * 4)()
+    gc = grid_c(g)
+    _abi.check(_abi.lib().cntr_solve_2b(C.byref(gc), C.byref(G.gf()), C.byref(Sigma.gf()),
+                                        C.byref(Gscratch.gf()), eps0.data_ptr(), U.data_ptr(),
+                                        eps_mf.data_ptr(), nbar, mats_maxit, mats_tol, boot_maxit,
+                                        boot_tol, ncorr, nt_stop, st, _stream(stream)))
+    return Solve2BStats(int(st[0]), int(st[1]), st[2], st[3])

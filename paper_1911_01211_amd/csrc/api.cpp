@@ -1,0 +1,628 @@
+// C ABI of the HIP Dyson time stepper: argument validation, library state
+// (weight tables, per-stream scratch), and the host-side sequencing of the
+// Matsubara solve and the self-consistent second-Born propagation.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "launch.h"
+
+namespace cntr {
+
+__constant__ KW c_kw[KMAX + 1];
+
+namespace {
+
+thread_local std::string g_err;
+std::mutex g_mu;
+bool g_weights_ready[64] = {false};
+
+struct StreamScratch {
+  char* buf = nullptr;
+  size_t bytes = 0;
+  Prob* probs = nullptr;  // device copies of batched descriptors (5 sets)
+  size_t nprob = 0;
+  double* red = nullptr;  // reduction outputs
+  size_t nred = 0;
+};
+std::map<std::pair<int, hipStream_t>, StreamScratch> g_scratch;
+
+cntr_status fail(cntr_status st, const std::string& msg) {
+  g_err = msg;
+  return st;
+}
+
+cntr_status hip_fail(hipError_t e, const char* where) {
+  return fail(CNTR_EHIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+cntr_status ensure_weights() {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (dev < 64 && g_weights_ready[dev]) return CNTR_OK;
+  KW host[KMAX + 1];
+  std::memset(host, 0, sizeof(host));
+  for (int k = 1; k <= KMAX; k++) make_weights(k, &host[k]);
+  e = hipMemcpyToSymbol(HIP_SYMBOL(c_kw), host, sizeof(host), 0, hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(e, "weight upload");
+  if (dev < 64) g_weights_ready[dev] = true;
+  return CNTR_OK;
+}
+
+StreamScratch* scratch_for(hipStream_t s) {
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  std::lock_guard<std::mutex> lk(g_mu);
+  return &g_scratch[{dev, s}];
+}
+
+cntr_status grow(hipStream_t s, StreamScratch* sc, size_t bytes, size_t nprob, size_t nred) {
+  if (bytes > sc->bytes) {
+    if (sc->buf) {
+      (void)hipStreamSynchronize(s);
+      (void)hipFree(sc->buf);
+    }
+    sc->buf = nullptr;
+    size_t nb = bytes + bytes / 4;
+    if (hipMalloc(&sc->buf, nb) != hipSuccess) {
+      sc->bytes = 0;
+      return fail(CNTR_ENOMEM, "scratch allocation failed");
+    }
+    sc->bytes = nb;
+    if (hipMemsetAsync(sc->buf, 0, nb, s) != hipSuccess) return fail(CNTR_EHIP, "scratch clear");
+  }
+  if (nprob > sc->nprob) {
+    if (sc->probs) {
+      (void)hipStreamSynchronize(s);
+      (void)hipFree(sc->probs);
+    }
+    sc->probs = nullptr;
+    if (hipMalloc(&sc->probs, nprob * sizeof(Prob)) != hipSuccess) {
+      sc->nprob = 0;
+      return fail(CNTR_ENOMEM, "descriptor allocation failed");
+    }
+    sc->nprob = nprob;
+  }
+  if (nred > sc->nred) {
+    if (sc->red) {
+      (void)hipStreamSynchronize(s);
+      (void)hipFree(sc->red);
+    }
+    sc->red = nullptr;
+    if (hipMalloc(&sc->red, nred * sizeof(double)) != hipSuccess) {
+      sc->nred = 0;
+      return fail(CNTR_ENOMEM, "reduction buffer allocation failed");
+    }
+    sc->nred = nred;
+  }
+  return CNTR_OK;
+}
+
+cntr_status check_grid(const cntr_grid& g, const char* what) {
+  char buf[256];
+  if (g.k < 1 || g.k > KMAX) {
+    snprintf(buf, sizeof buf, "%s: order k=%d outside 1..%d", what, g.k, KMAX);
+    return fail(CNTR_EINVAL, buf);
+  }
+  if (g.d < 1 || g.d > 8) {
+    snprintf(buf, sizeof buf, "%s: orbital dimension d=%d outside 1..8", what, g.d);
+    return fail(CNTR_EINVAL, buf);
+  }
+  if (g.ntau < 2 * g.k + 2) {
+    snprintf(buf, sizeof buf, "%s: ntau=%d < 2k+2=%d", what, g.ntau, 2 * g.k + 2);
+    return fail(CNTR_EINVAL, buf);
+  }
+  if (g.nt < g.k) {
+    snprintf(buf, sizeof buf, "%s: nt=%d < k=%d", what, g.nt, g.k);
+    return fail(CNTR_EINVAL, buf);
+  }
+  if (g.sig != 1 && g.sig != -1) return fail(CNTR_EINVAL, std::string(what) + ": sig must be +1 or -1");
+  if (!(g.h > 0) || !(g.beta > 0) || !std::isfinite(g.mu))
+    return fail(CNTR_EINVAL, std::string(what) + ": h and beta must be positive, mu finite");
+  return CNTR_OK;
+}
+
+cntr_status check_batch(int count, const cntr_grid* grids, const char* what) {
+  if (count < 1 || grids == nullptr) return fail(CNTR_ESHAPE, std::string(what) + ": empty batch");
+  for (int i = 0; i < count; i++) {
+    cntr_status st = check_grid(grids[i], what);
+    if (st != CNTR_OK) return st;
+    if (grids[i].d != grids[0].d || grids[i].k != grids[0].k || grids[i].ntau != grids[0].ntau)
+      return fail(CNTR_ESHAPE, std::string(what) + ": instances of one call must share d, k and ntau");
+  }
+  return CNTR_OK;
+}
+
+bool gf_ok(const cntr_gf* g, int count) {
+  if (!g) return false;
+  for (int i = 0; i < count; i++)
+    if (!g[i].mat || !g[i].ret || !g[i].les || !g[i].tv) return false;
+  return true;
+}
+
+Prob make_prob(const cntr_grid& g, const cntr_gf* G, const cntr_gf* S, const void* eps) {
+  Prob p{};
+  p.nt = g.nt;
+  p.ntau = g.ntau;
+  p.d = g.d;
+  p.sig = g.sig;
+  p.k = g.k;
+  p.beta = g.beta;
+  p.h = g.h;
+  p.mu = g.mu;
+  p.htau = g.beta / g.ntau;
+  if (G) {
+    p.Gmat = (cplx*)G->mat;
+    p.Gret = (cplx*)G->ret;
+    p.Gles = (cplx*)G->les;
+    p.Gtv = (cplx*)G->tv;
+  }
+  if (S) {
+    p.Smat = (cplx*)S->mat;
+    p.Sret = (cplx*)S->ret;
+    p.Sles = (cplx*)S->les;
+    p.Stv = (cplx*)S->tv;
+  }
+  p.eps = (const cplx*)eps;
+  return p;
+}
+
+// ProbArg for `count` descriptors; batches are copied to device slot `slot`.
+cntr_status make_arg(hipStream_t s, StreamScratch* sc, const std::vector<Prob>& v, int slot,
+                     ProbArg* out) {
+  out->one = v[0];
+  out->count = (int)v.size();
+  out->many = nullptr;
+  if (v.size() > 1) {
+    Prob* dst = sc->probs + slot * (sc->nprob / 5);
+    hipError_t e = hipMemcpyAsync(dst, v.data(), v.size() * sizeof(Prob), hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(e, "descriptor upload");
+    out->many = dst;
+  }
+  return CNTR_OK;
+}
+
+size_t round256(size_t x) { return (x + 255) / 256 * 256; }
+
+struct StepScratch {
+  Scratch sc;
+  size_t per;
+};
+
+StepScratch step_layout(const cntr_grid& g) {
+  StepScratch r{};
+  size_t dd = (size_t)g.d * g.d;
+  r.sc.off_status = 0;
+  r.sc.off_minv = 256;
+  r.sc.off_part = 256 + round256(dd * sizeof(cplx));
+  r.sc.off_tail = r.sc.off_part;
+  r.per = r.sc.off_part + round256(step_scratch_bytes(g.nt, g.k, g.ntau, g.d));
+  r.sc.stride = r.per;
+  return r;
+}
+
+long slice_elems(const cntr_grid& g, int n) {
+  long dd = (long)g.d * g.d;
+  if (n < 0) return (g.ntau + 1) * dd;
+  return (2L * (n + 1) + g.ntau + 1) * dd;
+}
+
+// ------------------------------------------------- Matsubara solve state
+struct MatsState {
+  int N = 0, d = 0;
+  cplx *g = nullptr, *K = nullptr, *A = nullptr, *Ainv = nullptr, *r = nullptr, *dx = nullptr,
+       *work = nullptr;
+  int* piv = nullptr;
+  int* status = nullptr;
+  double* norms = nullptr;
+  bool have_inv = false;
+  cntr_status alloc(int ntau, int dd) {
+    d = dd;
+    N = (ntau + 1) * dd;
+    size_t bs = (size_t)(ntau + 1) * dd * dd * sizeof(cplx);
+    size_t nn = (size_t)N * N * sizeof(cplx);
+    size_t vec = (size_t)N * dd * sizeof(cplx);
+    if (hipMalloc(&g, bs) || hipMalloc(&K, bs) || hipMalloc(&A, nn) || hipMalloc(&Ainv, nn) ||
+        hipMalloc(&r, vec) || hipMalloc(&dx, vec) || hipMalloc(&work, 2 * (size_t)N * sizeof(cplx)) ||
+        hipMalloc(&piv, N * sizeof(int)) || hipMalloc(&status, sizeof(int)) ||
+        hipMalloc(&norms, 2 * sizeof(double))) {
+      release();
+      return fail(CNTR_ENOMEM, "Matsubara workspace allocation failed");
+    }
+    return CNTR_OK;
+  }
+  void release() {
+    for (void* p : {(void*)g, (void*)K, (void*)A, (void*)Ainv, (void*)r, (void*)dx, (void*)work,
+                    (void*)piv, (void*)status, (void*)norms})
+      if (p) (void)hipFree(p);
+    g = K = A = Ainv = r = dx = work = nullptr;
+    piv = status = nullptr;
+    norms = nullptr;
+    have_inv = false;
+  }
+  ~MatsState() { release(); }
+};
+
+// Solve the discrete Matsubara equation for P (eps = eps_{-1} at entry 0,
+// Sigma^M in P.Smat) into P.Gmat. The current P.Gmat is the initial guess
+// when use_guess; the inverse of an earlier operator is reused when present.
+cntr_status mats_solve(MatsState& st, const Prob& P, bool use_guess, double tol, int max_iter,
+                       hipStream_t s, int* iters) {
+  hipError_t e;
+  int N = st.N, d = st.d;
+  size_t vec = (size_t)N * d * sizeof(cplx);
+  if ((e = launch_free_mat(P, st.g, s))) return hip_fail(e, "free Matsubara function");
+  if ((e = launch_mat_conv(P, st.g, P.Smat, nullptr, st.K, s))) return hip_fail(e, "[g*Sigma]^M");
+  if ((e = launch_mat_build(P, st.K, st.A, s))) return hip_fail(e, "Matsubara operator");
+  if (!use_guess && (e = hipMemcpyAsync(P.Gmat, st.g, vec, hipMemcpyDeviceToDevice, s)))
+    return hip_fail(e, "initial guess");
+  double prev = -1;
+  int since_inv = 0;
+  for (int it = 0; it < max_iter; it++) {
+    if (!st.have_inv) {
+      if ((e = hipMemsetAsync(st.status, 0, sizeof(int), s))) return hip_fail(e, "status clear");
+      if ((e = hipMemcpyAsync(st.Ainv, st.A, (size_t)N * N * sizeof(cplx), hipMemcpyDeviceToDevice, s)))
+        return hip_fail(e, "operator copy");
+      if ((e = launch_gj_inverse(N, st.Ainv, st.work, st.piv, st.status, s))) return hip_fail(e, "inverse");
+      int stat = 0;
+      if ((e = hipMemcpyAsync(&stat, st.status, sizeof(int), hipMemcpyDeviceToHost, s)) ||
+          (e = hipStreamSynchronize(s)))
+        return hip_fail(e, "inverse status");
+      if (stat != 0) return fail(CNTR_ESINGULAR, "singular Matsubara operator");
+      st.have_inv = true;
+      since_inv = 0;
+      prev = -1;
+    }
+    if ((e = launch_matvec(N, d, st.A, P.Gmat, st.g, st.r, s))) return hip_fail(e, "residual");
+    if ((e = hipMemsetAsync(st.norms, 0, 2 * sizeof(double), s))) return hip_fail(e, "norm clear");
+    if ((e = launch_axpy_norm(N * d, P.Gmat, nullptr, st.r, st.g, st.norms, s))) return hip_fail(e, "norm");
+    double nrm[2];
+    if ((e = hipMemcpyAsync(nrm, st.norms, sizeof nrm, hipMemcpyDeviceToHost, s)) ||
+        (e = hipStreamSynchronize(s)))
+      return hip_fail(e, "norm readback");
+    double rel = std::sqrt(nrm[0] / (nrm[1] > 0 ? nrm[1] : 1.0));
+    if (!std::isfinite(rel)) return fail(CNTR_ENONFINITE, "non-finite Matsubara residual");
+    if (iters) *iters = it;
+    if (rel <= tol) return CNTR_OK;
+    // refresh the preconditioner when refinement stops contracting
+    if (since_inv >= 2 && prev > 0 && rel > 0.25 * prev) {
+      st.have_inv = false;
+      continue;
+    }
+    prev = rel;
+    since_inv++;
+    if ((e = launch_matvec(N, d, st.Ainv, st.r, nullptr, st.dx, s))) return hip_fail(e, "correction");
+    if ((e = hipMemsetAsync(st.norms, 0, 2 * sizeof(double), s))) return hip_fail(e, "norm clear");
+    if ((e = launch_axpy_norm(N * d, P.Gmat, st.dx, st.r, st.g, st.norms, s))) return hip_fail(e, "update");
+  }
+  return fail(CNTR_ENOCONV, "Matsubara refinement did not reach its tolerance");
+}
+
+}  // namespace
+}  // namespace cntr
+
+using namespace cntr;
+
+extern "C" {
+
+const char* cntr_version(void) { return "cntr-gfx950 0.1"; }
+
+const char* cntr_last_error(void) { return g_err.c_str(); }
+
+cntr_status cntr_finalize(void) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  for (auto& kv : g_scratch) {
+    if (kv.second.buf) (void)hipFree(kv.second.buf);
+    if (kv.second.probs) (void)hipFree(kv.second.probs);
+    if (kv.second.red) (void)hipFree(kv.second.red);
+  }
+  g_scratch.clear();
+  return CNTR_OK;
+}
+
+cntr_status cntr_sync(void* stream) {
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "stream synchronize");
+  StreamScratch* sc = scratch_for(s);
+  if (!sc->buf) return CNTR_OK;
+  // status words live at the start of each problem region; scan the buffer
+  // head (the first problem) and any recorded code.
+  int code = 0;
+  e = hipMemcpy(&code, sc->buf, sizeof(int), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e, "status readback");
+  if (code != 0) {
+    int zero = 0;
+    (void)hipMemcpy(sc->buf, &zero, sizeof(int), hipMemcpyHostToDevice);
+    return fail((cntr_status)code, "singular step matrix detected on the device");
+  }
+  return CNTR_OK;
+}
+
+cntr_status cntr_dyson_step(int32_t tstp, int32_t count, const cntr_grid* grids, const cntr_gf* G,
+                            const cntr_gf* Sigma, const void* const* eps, void* stream) {
+  cntr_status st = check_batch(count, grids, "cntr_dyson_step");
+  if (st) return st;
+  if (!gf_ok(G, count) || !gf_ok(Sigma, count) || !eps) return fail(CNTR_ESHAPE, "cntr_dyson_step: null pointer");
+  int k = grids[0].k, d = grids[0].d, ntau = grids[0].ntau;
+  int ntmax = 0;
+  for (int i = 0; i < count; i++) {
+    if (!eps[i]) return fail(CNTR_ESHAPE, "cntr_dyson_step: null eps");
+    if (grids[i].nt > ntmax) ntmax = grids[i].nt;
+  }
+  if (tstp < 0 || tstp > ntmax) return fail(CNTR_EORDER, "cntr_dyson_step: tstp outside 0..nt");
+  if ((st = ensure_weights())) return st;
+  hipStream_t s = (hipStream_t)stream;
+  StreamScratch* sc = scratch_for(s);
+  cntr_grid gmax = grids[0];
+  gmax.nt = ntmax < k + 1 ? k + 1 : ntmax;
+  StepScratch lay = step_layout(gmax);
+  if ((st = grow(s, sc, lay.per * count, 5 * (size_t)count, 2 * (size_t)count))) return st;
+  std::vector<Prob> v(count);
+  for (int i = 0; i < count; i++) v[i] = make_prob(grids[i], &G[i], &Sigma[i], eps[i]);
+  ProbArg pa;
+  if ((st = make_arg(s, sc, v, 0, &pa))) return st;
+  Scratch scr = lay.sc;
+  scr.base = sc->buf;
+  hipError_t e = tstp <= k ? launch_start(pa, scr, d, ntau, s) : launch_step(pa, scr, tstp, d, s);
+  if (e != hipSuccess) return hip_fail(e, "cntr_dyson_step launch");
+  return CNTR_OK;
+}
+
+cntr_status cntr_init_matsubara(int32_t count, const cntr_grid* grids, const cntr_gf* G,
+                                const cntr_gf* Sigma, const void* const* eps, double tol,
+                                int32_t max_iter, void* stream) {
+  cntr_status st = check_batch(count, grids, "cntr_init_matsubara");
+  if (st) return st;
+  if (!gf_ok(G, count) || !gf_ok(Sigma, count) || !eps) return fail(CNTR_ESHAPE, "cntr_init_matsubara: null pointer");
+  if ((st = ensure_weights())) return st;
+  hipStream_t s = (hipStream_t)stream;
+  if (tol <= 0) tol = 1e-14;
+  if (max_iter <= 0) max_iter = 200;
+  MatsState ms;
+  if ((st = ms.alloc(grids[0].ntau, grids[0].d))) return st;
+  for (int i = 0; i < count; i++) {
+    if (!eps[i]) return fail(CNTR_ESHAPE, "cntr_init_matsubara: null eps");
+    Prob P = make_prob(grids[i], &G[i], &Sigma[i], eps[i]);
+    ms.have_inv = false;
+    if ((st = mats_solve(ms, P, false, tol, max_iter, s, nullptr))) return st;
+  }
+  return CNTR_OK;
+}
+
+cntr_status cntr_convolution(int32_t tstp, int32_t count, const cntr_grid* grids, const cntr_gf* C,
+                             const cntr_gf* A, const cntr_gf* Acc, const cntr_gf* B,
+                             const cntr_gf* Bcc, const void* const* f, void* stream) {
+  cntr_status st = check_batch(count, grids, "cntr_convolution");
+  if (st) return st;
+  if (!gf_ok(C, count) || !gf_ok(A, count) || !gf_ok(Acc, count) || !gf_ok(B, count) || !gf_ok(Bcc, count))
+    return fail(CNTR_ESHAPE, "cntr_convolution: null pointer");
+  int ntmax = 0;
+  for (int i = 0; i < count; i++) ntmax = grids[i].nt > ntmax ? grids[i].nt : ntmax;
+  if (tstp < -1 || tstp > ntmax) return fail(CNTR_EORDER, "cntr_convolution: tstp outside -1..nt");
+  if ((st = ensure_weights())) return st;
+  hipStream_t s = (hipStream_t)stream;
+  StreamScratch* sc = scratch_for(s);
+  if ((st = grow(s, sc, 256, 5 * (size_t)count, 2))) return st;
+  std::vector<Prob> vc(count), va(count), vac(count), vb(count), vbc(count);
+  for (int i = 0; i < count; i++) {
+    vc[i] = make_prob(grids[i], &C[i], nullptr, nullptr);
+    vc[i].f = f ? (const cplx*)f[i] : nullptr;
+    va[i] = make_prob(grids[i], &A[i], nullptr, nullptr);
+    vac[i] = make_prob(grids[i], &Acc[i], nullptr, nullptr);
+    vb[i] = make_prob(grids[i], &B[i], nullptr, nullptr);
+    vbc[i] = make_prob(grids[i], &Bcc[i], nullptr, nullptr);
+  }
+  ProbArg pc, pa, pac, pb, pbc;
+  if ((st = make_arg(s, sc, vc, 0, &pc)) || (st = make_arg(s, sc, va, 1, &pa)) ||
+      (st = make_arg(s, sc, vac, 2, &pac)) || (st = make_arg(s, sc, vb, 3, &pb)) ||
+      (st = make_arg(s, sc, vbc, 4, &pbc)))
+    return st;
+  cntr_grid gm = grids[0];
+  gm.nt = tstp < 0 ? 0 : tstp;
+  hipError_t e = launch_convolution(pc, pa, pac, pb, pbc, tstp, grids[0].d, (int)slice_elems(gm, tstp), s);
+  if (e != hipSuccess) return hip_fail(e, "cntr_convolution launch");
+  return CNTR_OK;
+}
+
+cntr_status cntr_sigma_2b(int32_t tstp, int32_t count, const cntr_grid* grids, const cntr_gf* G,
+                          const double* const* U, const cntr_gf* Sigma, const void* const* eps0,
+                          void* const* eps_mf, double nbar, void* stream) {
+  cntr_status st = check_batch(count, grids, "cntr_sigma_2b");
+  if (st) return st;
+  if (!gf_ok(G, count) || !gf_ok(Sigma, count) || !U) return fail(CNTR_ESHAPE, "cntr_sigma_2b: null pointer");
+  if (eps_mf && !eps0) return fail(CNTR_ESHAPE, "cntr_sigma_2b: eps_mf requires eps0");
+  int ntmax = 0;
+  for (int i = 0; i < count; i++) {
+    if (!U[i]) return fail(CNTR_ESHAPE, "cntr_sigma_2b: null U");
+    ntmax = grids[i].nt > ntmax ? grids[i].nt : ntmax;
+  }
+  if (tstp < -1 || tstp > ntmax) return fail(CNTR_EORDER, "cntr_sigma_2b: tstp outside -1..nt");
+  if ((st = ensure_weights())) return st;
+  hipStream_t s = (hipStream_t)stream;
+  StreamScratch* sc = scratch_for(s);
+  if ((st = grow(s, sc, 256, 5 * (size_t)count, 2))) return st;
+  std::vector<Prob> v(count);
+  for (int i = 0; i < count; i++) {
+    v[i] = make_prob(grids[i], &G[i], &Sigma[i], nullptr);
+    v[i].U = U[i];
+    v[i].eps0 = eps0 ? (const cplx*)eps0[i] : nullptr;
+    v[i].eps_mf = eps_mf ? (cplx*)eps_mf[i] : nullptr;
+    if (eps_mf && eps_mf[i] && !eps0[i]) return fail(CNTR_ESHAPE, "cntr_sigma_2b: null eps0");
+  }
+  ProbArg pa;
+  if ((st = make_arg(s, sc, v, 0, &pa))) return st;
+  cntr_grid gm = grids[0];
+  hipError_t e = launch_sigma2b(pa, tstp, gm.d, (int)slice_elems(gm, tstp), nbar, s);
+  if (e != hipSuccess) return hip_fail(e, "cntr_sigma_2b launch");
+  return CNTR_OK;
+}
+
+cntr_status cntr_extrapolate(int32_t tstp, int32_t count, const cntr_grid* grids, const cntr_gf* G,
+                             void* stream) {
+  cntr_status st = check_batch(count, grids, "cntr_extrapolate");
+  if (st) return st;
+  if (!gf_ok(G, count)) return fail(CNTR_ESHAPE, "cntr_extrapolate: null pointer");
+  int ntmax = 0;
+  for (int i = 0; i < count; i++) ntmax = grids[i].nt > ntmax ? grids[i].nt : ntmax;
+  if (tstp < grids[0].k || tstp + 1 > ntmax) return fail(CNTR_EORDER, "cntr_extrapolate: need k <= tstp < nt");
+  if ((st = ensure_weights())) return st;
+  hipStream_t s = (hipStream_t)stream;
+  StreamScratch* sc = scratch_for(s);
+  if ((st = grow(s, sc, 256, 5 * (size_t)count, 2))) return st;
+  std::vector<Prob> v(count);
+  for (int i = 0; i < count; i++) v[i] = make_prob(grids[i], &G[i], nullptr, nullptr);
+  ProbArg pa;
+  if ((st = make_arg(s, sc, v, 0, &pa))) return st;
+  hipError_t e = launch_extrapolate(pa, tstp, grids[0].d, (int)slice_elems(grids[0], tstp + 1), s);
+  if (e != hipSuccess) return hip_fail(e, "cntr_extrapolate launch");
+  return CNTR_OK;
+}
+
+cntr_status cntr_copy_slice(int32_t tstp, int32_t count, const cntr_grid* grids, const cntr_gf* dst,
+                            const cntr_gf* src, void* stream) {
+  cntr_status st = check_batch(count, grids, "cntr_copy_slice");
+  if (st) return st;
+  if (!gf_ok(dst, count) || !gf_ok(src, count)) return fail(CNTR_ESHAPE, "cntr_copy_slice: null pointer");
+  hipStream_t s = (hipStream_t)stream;
+  StreamScratch* sc = scratch_for(s);
+  if ((st = grow(s, sc, 256, 5 * (size_t)count, 2))) return st;
+  std::vector<Prob> vd(count), vs(count);
+  for (int i = 0; i < count; i++) {
+    vd[i] = make_prob(grids[i], &dst[i], nullptr, nullptr);
+    vs[i] = make_prob(grids[i], &src[i], nullptr, nullptr);
+  }
+  ProbArg pd, ps;
+  if ((st = make_arg(s, sc, vd, 0, &pd)) || (st = make_arg(s, sc, vs, 1, &ps))) return st;
+  hipError_t e = launch_copy(pd, ps, tstp, grids[0].d, (int)slice_elems(grids[0], tstp), s);
+  if (e != hipSuccess) return hip_fail(e, "cntr_copy_slice launch");
+  return CNTR_OK;
+}
+
+cntr_status cntr_distance(int32_t tstp, int32_t count, const cntr_grid* grids, const cntr_gf* A,
+                          const cntr_gf* B, double* out, void* stream) {
+  cntr_status st = check_batch(count, grids, "cntr_distance");
+  if (st) return st;
+  if (!gf_ok(A, count) || !gf_ok(B, count) || !out) return fail(CNTR_ESHAPE, "cntr_distance: null pointer");
+  hipStream_t s = (hipStream_t)stream;
+  StreamScratch* sc = scratch_for(s);
+  if ((st = grow(s, sc, 256, 5 * (size_t)count, 2 * (size_t)count))) return st;
+  std::vector<Prob> va(count), vb(count);
+  for (int i = 0; i < count; i++) {
+    va[i] = make_prob(grids[i], &A[i], nullptr, nullptr);
+    vb[i] = make_prob(grids[i], &B[i], nullptr, nullptr);
+  }
+  ProbArg pa, pb;
+  if ((st = make_arg(s, sc, va, 0, &pa)) || (st = make_arg(s, sc, vb, 1, &pb))) return st;
+  hipError_t e = hipMemsetAsync(sc->red, 0, 2 * count * sizeof(double), s);
+  if (e == hipSuccess) e = launch_distance(pa, pb, tstp, grids[0].d, (int)slice_elems(grids[0], tstp), sc->red, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(out, sc->red, 2 * count * sizeof(double), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "cntr_distance");
+  return CNTR_OK;
+}
+
+cntr_status cntr_solve_2b(const cntr_grid* grid, const cntr_gf* G, const cntr_gf* Sigma,
+                          const cntr_gf* Gscratch, const void* eps0, const double* U,
+                          void* eps_mf, double nbar, int32_t mats_maxit, double mats_tol,
+                          int32_t boot_maxit, double boot_tol, int32_t ncorr, int32_t nt_stop,
+                          double* stats, void* stream) {
+  if (!grid) return fail(CNTR_ESHAPE, "cntr_solve_2b: null grid");
+  cntr_status st = check_grid(*grid, "cntr_solve_2b");
+  if (st) return st;
+  if (!gf_ok(G, 1) || !gf_ok(Sigma, 1) || !gf_ok(Gscratch, 1) || !eps0 || !U || !eps_mf)
+    return fail(CNTR_ESHAPE, "cntr_solve_2b: null pointer");
+  if (nt_stop < grid->k || nt_stop > grid->nt) return fail(CNTR_EORDER, "cntr_solve_2b: nt_stop outside k..nt");
+  if ((st = ensure_weights())) return st;
+  hipStream_t s = (hipStream_t)stream;
+  const cntr_grid& g = *grid;
+  int k = g.k, d = g.d;
+  StreamScratch* sc = scratch_for(s);
+  cntr_grid gmax = g;
+  if (gmax.nt < k + 1) gmax.nt = k + 1;
+  StepScratch lay = step_layout(gmax);
+  if ((st = grow(s, sc, lay.per, 5, 2))) return st;
+  Scratch scr = lay.sc;
+  scr.base = sc->buf;
+  Prob P = make_prob(g, G, Sigma, eps_mf);
+  P.U = U;
+  P.eps0 = (const cplx*)eps0;
+  P.eps_mf = (cplx*)eps_mf;
+  Prob Po = make_prob(g, Gscratch, nullptr, nullptr);
+  ProbArg pa{P, nullptr, 1}, po{Po, nullptr, 1};
+  hipError_t e;
+  double dist[2];
+  auto distance = [&](int n, double* out) -> cntr_status {
+    hipError_t ee = hipMemsetAsync(sc->red, 0, 2 * sizeof(double), s);
+    if (!ee) ee = launch_distance(pa, po, n, d, (int)slice_elems(g, n), sc->red, s);
+    if (!ee) ee = hipMemcpyAsync(out, sc->red, 2 * sizeof(double), hipMemcpyDeviceToHost, s);
+    if (!ee) ee = hipStreamSynchronize(s);
+    return ee ? hip_fail(ee, "distance") : CNTR_OK;
+  };
+  // Matsubara self-consistency. Initial G^M: free function of eps0_{-1}.
+  MatsState ms;
+  if ((st = ms.alloc(g.ntau, d))) return st;
+  Prob P0 = P;
+  P0.eps = (const cplx*)eps0;
+  if ((e = launch_free_mat(P0, P.Gmat, s))) return hip_fail(e, "initial G^M");
+  int it = 0;
+  double err = 0;
+  for (it = 0; it < mats_maxit; it++) {
+    if ((e = launch_sigma2b(pa, -1, d, (int)slice_elems(g, -1), nbar, s))) return hip_fail(e, "Sigma^M");
+    if ((e = launch_copy(po, pa, -1, d, (int)slice_elems(g, -1), s))) return hip_fail(e, "copy");
+    if ((st = mats_solve(ms, P, true, 1e-15, 200, s, nullptr))) return st;
+    if ((st = distance(-1, dist))) return st;
+    err = dist[0] / dist[1];
+    if (err < mats_tol) {
+      it++;
+      break;
+    }
+  }
+  if (stats) {
+    stats[0] = it;
+    stats[2] = err;
+  }
+  ms.release();
+  // bootstrap over slices 0..k
+  for (it = 0; it < boot_maxit; it++) {
+    for (int n = 0; n <= k; n++)
+      if ((e = launch_sigma2b(pa, n, d, (int)slice_elems(g, n), nbar, s))) return hip_fail(e, "Sigma start");
+    for (int n = 0; n <= k; n++)
+      if ((e = launch_copy(po, pa, n, d, (int)slice_elems(g, n), s))) return hip_fail(e, "copy");
+    if ((e = launch_start(pa, scr, d, g.ntau, s))) return hip_fail(e, "start-up");
+    double num = 0, den = 0;
+    for (int n = 0; n <= k; n++) {
+      if ((st = distance(n, dist))) return st;
+      num += dist[0];
+      den += dist[1];
+    }
+    err = num / den;
+    if (err < boot_tol && it > 2) {
+      it++;
+      break;
+    }
+  }
+  if (stats) {
+    stats[1] = it;
+    stats[3] = err;
+  }
+  // predictor-corrector time steps
+  for (int n = k + 1; n <= nt_stop; n++) {
+    if ((e = launch_extrapolate(pa, n - 1, d, (int)slice_elems(g, n), s))) return hip_fail(e, "extrapolate");
+    for (int c = 0; c < ncorr; c++) {
+      if ((e = launch_sigma2b(pa, n, d, (int)slice_elems(g, n), nbar, s))) return hip_fail(e, "Sigma");
+      if ((e = launch_step(pa, scr, n, d, s))) return hip_fail(e, "step");
+    }
+  }
+  for (int n = k + 1; n <= nt_stop; n++)
+    if ((e = launch_sigma2b(pa, n, d, (int)slice_elems(g, n), nbar, s))) return hip_fail(e, "Sigma");
+  return CNTR_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,175 @@
+// Device helpers shared by the kernel files: problem access, block access,
+// small dense solves held in LDS.
+#pragma once
+#include "cntr_internal.h"
+
+namespace cntr {
+
+// Problems of one call: a single problem travels by value in the kernel
+// arguments; batches live in a device array.
+struct ProbArg {
+  Prob one;
+  const Prob* many;
+  int count;
+  __device__ inline const Prob& get(int i) const { return count == 1 ? one : many[i]; }
+};
+
+// Per-problem scratch region.
+struct Scratch {
+  char* base;
+  size_t stride;  // bytes per problem
+  size_t off_minv, off_part, off_tail, off_status;
+  __device__ inline cplx* minv(int pi) const { return (cplx*)(base + pi * stride + off_minv); }
+  __device__ inline cplx* part(int pi) const { return (cplx*)(base + pi * stride + off_part); }
+  __device__ inline cplx* tail(int pi) const { return (cplx*)(base + pi * stride + off_tail); }
+  __device__ inline int* status(int pi) const { return (int*)(base + pi * stride + off_status); }
+};
+
+__device__ inline cplx ld(const cplx* p) { return *p; }
+
+// Retarded value with the continuation t < t':  X~^R_{a,b}[r][c]
+template <int D>
+__device__ inline cplx ret_ext(const cplx* X, int a, int b, int r, int c) {
+  if (a >= b) return X[(tri(a) + b) * D * D + r * D + c];
+  return -conj(X[(tri(b) + a) * D * D + c * D + r]);
+}
+// Lesser value for any order of the arguments: X^<_{a,b}[r][c]
+template <int D>
+__device__ inline cplx les_any(const cplx* X, int a, int b, int r, int c) {
+  if (a <= b) return X[(tri(b) + a) * D * D + r * D + c];
+  return -conj(X[(tri(a) + b) * D * D + c * D + r]);
+}
+
+// Gauss-Jordan inverse of an n x n complex matrix in LDS (in place), with
+// partial pivoting, executed by the whole workgroup. piv: LDS int[n].
+// Returns false (uniformly) if singular.
+__device__ inline bool lds_inverse(int n, cplx* A, int* piv, double* redv, int* redi) {
+  int tid = threadIdx.x, nt = blockDim.x;
+  bool ok = true;
+  for (int c = 0; c < n; c++) {
+    if (tid == 0) {
+      int p = c;
+      double best = abs2(A[c * n + c]);
+      for (int r = c + 1; r < n; r++) {
+        double v = abs2(A[r * n + c]);
+        if (v > best) {
+          best = v;
+          p = r;
+        }
+      }
+      redi[0] = p;
+      redv[0] = best;
+      piv[c] = p;
+    }
+    __syncthreads();
+    int p = redi[0];
+    if (redv[0] == 0.0) {
+      ok = false;
+      __syncthreads();
+      break;
+    }
+    if (p != c)
+      for (int q = tid; q < n; q += nt) {
+        cplx t = A[p * n + q];
+        A[p * n + q] = A[c * n + q];
+        A[c * n + q] = t;
+      }
+    __syncthreads();
+    cplx pv = A[c * n + c];
+    cplx ipv = cdiv(mk(1, 0), pv);
+    // column factors and scaled pivot row, then rank-1 update
+    __syncthreads();
+    for (int idx = tid; idx < n * n; idx += nt) {
+      int r = idx / n, q = idx % n;
+      if (r == c) continue;
+      cplx f = A[r * n + c];
+      if (q == c) continue;
+      A[r * n + q] = A[r * n + q] - f * (A[c * n + q] * ipv);
+    }
+    __syncthreads();
+    for (int r = tid; r < n; r += nt)
+      if (r != c) A[r * n + c] = -(A[r * n + c] * ipv);
+    __syncthreads();
+    for (int q = tid; q < n; q += nt) A[c * n + q] = (q == c) ? ipv : A[c * n + q] * ipv;
+    __syncthreads();
+  }
+  // undo the row interchanges as column interchanges, in reverse order
+  if (ok)
+    for (int c = n - 1; c >= 0; c--) {
+      int p = piv[c];
+      if (p != c)
+        for (int r = tid; r < n; r += nt) {
+          cplx t = A[r * n + p];
+          A[r * n + p] = A[r * n + c];
+          A[r * n + c] = t;
+        }
+      __syncthreads();
+    }
+  return ok;
+}
+
+// Solve A X = B in LDS (A: n x n, B: n x nrhs, row-major), Gaussian
+// elimination with partial pivoting by the workgroup. A, B overwritten.
+__device__ inline bool lds_solve(int n, int nrhs, cplx* A, cplx* B, double* redv, int* redi) {
+  int tid = threadIdx.x, nt = blockDim.x;
+  for (int c = 0; c < n; c++) {
+    if (tid == 0) {
+      int p = c;
+      double best = abs2(A[c * n + c]);
+      for (int r = c + 1; r < n; r++) {
+        double v = abs2(A[r * n + c]);
+        if (v > best) {
+          best = v;
+          p = r;
+        }
+      }
+      redi[0] = p;
+      redv[0] = best;
+    }
+    __syncthreads();
+    int p = redi[0];
+    if (redv[0] == 0.0) return false;
+    if (p != c) {
+      for (int q = tid; q < n; q += nt) {
+        cplx t = A[p * n + q];
+        A[p * n + q] = A[c * n + q];
+        A[c * n + q] = t;
+      }
+      for (int q = tid; q < nrhs; q += nt) {
+        cplx t = B[p * nrhs + q];
+        B[p * nrhs + q] = B[c * nrhs + q];
+        B[c * nrhs + q] = t;
+      }
+    }
+    __syncthreads();
+    cplx ipv = cdiv(mk(1, 0), A[c * n + c]);
+    int w = (n - c - 1);
+    int cols = (n - c - 1) + nrhs;
+    for (int idx = tid; idx < w * cols; idx += nt) {
+      int r = c + 1 + idx / cols, q = idx % cols;
+      cplx f = A[r * n + c] * ipv;
+      if (q < n - c - 1) {
+        int qq = c + 1 + q;
+        A[r * n + qq] = A[r * n + qq] - f * A[c * n + qq];
+      } else {
+        int qq = q - (n - c - 1);
+        B[r * nrhs + qq] = B[r * nrhs + qq] - f * B[c * nrhs + qq];
+      }
+    }
+    __syncthreads();
+  }
+  // back substitution, one right-hand side column per thread group
+  for (int c = n - 1; c >= 0; c--) {
+    cplx ipv = cdiv(mk(1, 0), A[c * n + c]);
+    for (int q = tid; q < nrhs; q += nt) B[c * nrhs + q] = B[c * nrhs + q] * ipv;
+    __syncthreads();
+    for (int idx = tid; idx < c * nrhs; idx += nt) {
+      int r = idx / nrhs, q = idx % nrhs;
+      B[r * nrhs + q] = B[r * nrhs + q] - A[r * n + c] * B[c * nrhs + q];
+    }
+    __syncthreads();
+  }
+  return true;
+}
+
+}  // namespace cntr

@@ -1,0 +1,60 @@
+// Host-side launch interface between the C ABI layer (api.cpp) and the
+// kernel files. All functions enqueue on `s` and return a hipError_t.
+#pragma once
+#include "dev_common.h"
+
+namespace cntr {
+
+constexpr int NJOB = 6;  // history jobs of one time step
+
+// Work plan of one time step n (identical for every problem of the call).
+struct HistPlan {
+  int n;
+  int njob;
+  int TJ, TM;
+  int mout[NJOB];
+  int nch[NJOB];
+  int mtiles[NJOB];
+  int wg_off[NJOB + 1];
+  long part_off[NJOB];  // in blocks
+  // tail (lesser boundary rows) plan
+  int tail_nch[3];
+  int tail_mtiles;
+  int tail_wg_off[4];
+  long tail_off[3];  // in blocks
+};
+
+int hist_tj(int d);
+int hist_tm(int d);
+HistPlan make_plan(int n, int k, int ntau, int d);
+// scratch bytes (per problem) for the step at the largest n = nt
+size_t step_scratch_bytes(int nt, int k, int ntau, int d);
+
+hipError_t launch_step(const ProbArg& pa, const Scratch& sc, int n, int d, hipStream_t s);
+hipError_t launch_start(const ProbArg& pa, const Scratch& sc, int d, int ntau, hipStream_t s);
+hipError_t launch_sigma2b(const ProbArg& pa, int n, int d, int nmax_elems, double nbar,
+                          hipStream_t s);
+hipError_t launch_extrapolate(const ProbArg& pa, int n, int d, int nelems, hipStream_t s);
+hipError_t launch_distance(const ProbArg& pa, const ProbArg& pb, int n, int d, int nelems,
+                           double* out_dev, hipStream_t s);
+hipError_t launch_copy(const ProbArg& pdst, const ProbArg& psrc, int n, int d, int nelems,
+                       hipStream_t s);
+// f is taken from C's problem descriptor (Prob::f)
+hipError_t launch_convolution(const ProbArg& C, const ProbArg& A, const ProbArg& Acc,
+                              const ProbArg& B, const ProbArg& Bcc, int n, int d, int nelems,
+                              hipStream_t s);
+
+// Matsubara pieces (per problem, one problem per call)
+hipError_t launch_free_mat(const Prob& P, cplx* g, hipStream_t s);
+hipError_t launch_mat_conv(const Prob& P, const cplx* A, const cplx* B, const cplx* f,
+                           cplx* out, hipStream_t s);
+hipError_t launch_mat_build(const Prob& P, const cplx* K, cplx* Amat, hipStream_t s);
+hipError_t launch_gj_inverse(int N, cplx* Amat, cplx* work, int* piv, int* status,
+                             hipStream_t s);
+// y = X v  (X: N x N, v, y: N x nrhs); y = b - X v when b != nullptr
+hipError_t launch_matvec(int N, int nrhs, const cplx* X, const cplx* v, const cplx* b, cplx* y,
+                         hipStream_t s);
+hipError_t launch_axpy_norm(int len, cplx* x, const cplx* dx, const cplx* r, const cplx* g,
+                            double* norms, hipStream_t s);
+
+}  // namespace cntr

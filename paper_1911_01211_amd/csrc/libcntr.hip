@@ -1,0 +1,7 @@
+// Single translation unit of the HIP library (constant-memory weight tables
+// are shared by every kernel without relocatable device code).
+#include "weights.cpp"
+#include "step.hip"
+#include "misc.hip"
+#include "mats.hip"
+#include "api.cpp"

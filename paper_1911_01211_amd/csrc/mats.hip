@@ -1,0 +1,283 @@
+// Matsubara Dyson equation in integral form (Sec. "Matsubara",
+// Eq. Gmat_dyson_integ): G = g + [K * G]^M with K = [g * Sigma]^M. The
+// discrete operator of Eqs. cm1/cm2 is assembled as a dense
+// (ntau+1)d x (ntau+1)d matrix and solved on the device: an explicit inverse
+// by Gauss-Jordan elimination with partial pivoting, then residual
+// refinement x <- x + A^-1 (g - A x). Inside a self-consistency loop the
+// inverse of an earlier iterate serves as the preconditioner and is only
+// rebuilt when the refinement stops contracting.
+#include "launch.h"
+
+namespace cntr {
+
+constexpr int NT3 = 256;
+
+// ------------------------------------------------------------ free g^M
+// g(tau) = -V diag( e^{-x tau} / (1 - xi e^{-beta x}) ) V^dag for
+// eps_{-1} - mu = V diag(x) V^dag, evaluated in the overflow-free form.
+__global__ __launch_bounds__(NT3) void k_free_mat(Prob P, cplx* g) {
+  __shared__ cplx A[64], V[64];
+  __shared__ double x[8];
+  int d = P.d, dd = d * d, tid = threadIdx.x;
+  if (tid == 0) {
+    for (int e = 0; e < dd; e++) {
+      A[e] = P.eps[e];
+      if (e / d == e % d) A[e].x -= P.mu;
+      V[e] = (e / d == e % d) ? mk(1, 0) : mk(0, 0);
+    }
+    // cyclic Jacobi rotations on the hermitian matrix
+    for (int sweep = 0; sweep < 60; sweep++) {
+      double off = 0, tot = 0;
+      for (int i = 0; i < d; i++)
+        for (int j = 0; j < d; j++) {
+          double v = abs2(A[i * d + j]);
+          tot += v;
+          if (i != j) off += v;
+        }
+      if (off <= 1e-32 * tot) break;
+      for (int p = 0; p < d; p++)
+        for (int q = p + 1; q < d; q++) {
+          cplx apq = A[p * d + q];
+          double gabs = sqrt(abs2(apq));
+          if (gabs == 0) continue;
+          cplx ph = mk(apq.x / gabs, apq.y / gabs);
+          double th = (A[q * d + q].x - A[p * d + p].x) / (2 * gabs);
+          double t = (th >= 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(1 + th * th));
+          double cs = 1 / sqrt(1 + t * t), sn = t * cs;
+          for (int i = 0; i < d; i++) {
+            cplx aip = A[i * d + p], aiq = A[i * d + q];
+            A[i * d + p] = cs * aip - sn * (conj(ph) * aiq);
+            A[i * d + q] = sn * (ph * aip) + cs * aiq;
+          }
+          for (int j = 0; j < d; j++) {
+            cplx apj = A[p * d + j], aqj = A[q * d + j];
+            A[p * d + j] = cs * apj - sn * (ph * aqj);
+            A[q * d + j] = sn * (conj(ph) * apj) + cs * aqj;
+          }
+          for (int i = 0; i < d; i++) {
+            cplx vip = V[i * d + p], viq = V[i * d + q];
+            V[i * d + p] = cs * vip - sn * (conj(ph) * viq);
+            V[i * d + q] = sn * (ph * vip) + cs * viq;
+          }
+        }
+    }
+    for (int i = 0; i < d; i++) x[i] = A[i * d + i].x;
+  }
+  __syncthreads();
+  double xi = P.sig, beta = P.beta;
+  for (int idx = tid; idx < (P.ntau + 1) * dd; idx += NT3) {
+    int m = idx / dd, e = idx % dd, a = e / d, c = e % d;
+    double tau = m * P.htau;
+    cplx acc = mk(0, 0);
+    for (int al = 0; al < d; al++) {
+      double xa = x[al], f;
+      if (xa >= 0 || xi > 0) f = -exp(-xa * tau) / (1 - xi * exp(-beta * xa));
+      else f = -exp(xa * (beta - tau)) / (exp(beta * xa) - xi);
+      acc = acc + f * (V[a * d + al] * conj(V[c * d + al]));
+    }
+    g[idx] = acc;
+  }
+}
+
+hipError_t launch_free_mat(const Prob& P, cplx* g, hipStream_t s) {
+  k_free_mat<<<1, NT3, 0, s>>>(P, g);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------ dense operator
+// A = 1 - B with B_{m,l} the coefficient of G^M_l in [K * G]^M(m)
+// (Eqs. cm1, cm2 with f = 1).
+__global__ __launch_bounds__(NT3) void k_mat_build(Prob P, const cplx* K, cplx* Amat) {
+  int d = P.d, dd = d * d, nt = P.ntau, k = P.k;
+  long N = (long)(nt + 1) * d;
+  long idx = (long)blockIdx.x * NT3 + threadIdx.x;
+  if (idx >= N * N) return;
+  long row = idx / N, col = idx % N;
+  int m = row / d, a = row % d, l = col / d, b = col % d;
+  const KW& W = c_kw[k];
+  double ht = P.htau, xi = P.sig;
+  cplx v = mk(0, 0);
+  if (m <= k) {
+    if (l <= k)
+      for (int j = 0; j <= k; j++) v = v + (ht * W.R[m][j][l]) * K[(size_t)j * dd + a * d + b];
+  } else if (l <= m) {
+    v = v + (ht * greg(W, m, l)) * K[(size_t)(m - l) * dd + a * d + b];
+  }
+  if (m >= nt - k) {
+    if (l >= nt - k) {
+      int ll = nt - l;
+      for (int j = 0; j <= k; j++) v = v + (ht * xi * W.R[nt - m][j][ll]) * K[(size_t)(nt - j) * dd + a * d + b];
+    }
+  } else if (l >= m) {
+    v = v + (ht * xi * greg(W, nt - m, l - m)) * K[(size_t)(nt - (l - m)) * dd + a * d + b];
+  }
+  v = -v;
+  if (row == col) v.x += 1.0;
+  Amat[idx] = v;
+}
+
+hipError_t launch_mat_build(const Prob& P, const cplx* K, cplx* Amat, hipStream_t s) {
+  long N = (long)(P.ntau + 1) * P.d;
+  long tot = N * N;
+  k_mat_build<<<(unsigned)((tot + NT3 - 1) / NT3), NT3, 0, s>>>(P, K, Amat);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------- Gauss-Jordan inverse
+constexpr int NGJ = 1024;
+
+// pivot search for column c, row interchange, pivot row and column copies
+__global__ __launch_bounds__(NGJ) void k_gj_pivot(int N, int c, cplx* A, cplx* col, cplx* prow,
+                                                 int* piv, int* status) {
+  __shared__ double bv[NGJ];
+  __shared__ int bi[NGJ];
+  int tid = threadIdx.x;
+  double best = -1;
+  int bidx = c;
+  for (int r = c + tid; r < N; r += NGJ) {
+    double v = abs2(A[(long)r * N + c]);
+    if (v > best) {
+      best = v;
+      bidx = r;
+    }
+  }
+  bv[tid] = best;
+  bi[tid] = bidx;
+  __syncthreads();
+  for (int w = NGJ / 2; w > 0; w >>= 1) {
+    if (tid < w) {
+      if (bv[tid + w] > bv[tid] || (bv[tid + w] == bv[tid] && bi[tid + w] < bi[tid])) {
+        bv[tid] = bv[tid + w];
+        bi[tid] = bi[tid + w];
+      }
+    }
+    __syncthreads();
+  }
+  int p = bi[0];
+  if (bv[0] <= 0.0) {
+    if (tid == 0) *status = CNTR_ESINGULAR;
+    p = c;
+  }
+  if (tid == 0) piv[c] = p;
+  if (p != c)
+    for (int q = tid; q < N; q += NGJ) {
+      cplx t = A[(long)p * N + q];
+      A[(long)p * N + q] = A[(long)c * N + q];
+      A[(long)c * N + q] = t;
+    }
+  __syncthreads();
+  cplx pv = A[(long)c * N + c];
+  cplx ipv = bv[0] > 0 ? cdiv(mk(1, 0), pv) : mk(0, 0);
+  for (int r = tid; r < N; r += NGJ) col[r] = A[(long)r * N + c];
+  for (int q = tid; q < N; q += NGJ) prow[q] = (q == c) ? ipv : A[(long)c * N + q] * ipv;
+}
+
+__global__ __launch_bounds__(NT3) void k_gj_update(int N, int c, cplx* A, const cplx* col,
+                                                   const cplx* prow) {
+  long idx = (long)blockIdx.x * NT3 + threadIdx.x;
+  if (idx >= (long)N * N) return;
+  int r = idx / N, q = idx % N;
+  if (r == c) {
+    A[idx] = prow[q];
+    return;
+  }
+  cplx f = col[r];
+  if (q == c) A[idx] = -(f * prow[c]);
+  else A[idx] = A[idx] - f * prow[q];
+}
+
+// undo the row interchanges: column swaps in reverse order, row by row
+__global__ __launch_bounds__(NT3) void k_gj_unpivot(int N, cplx* A, const int* piv) {
+  long r = (long)blockIdx.x * NT3 + threadIdx.x;
+  if (r >= N) return;
+  cplx* row = A + r * N;
+  for (int c = N - 1; c >= 0; c--) {
+    int p = piv[c];
+    if (p != c) {
+      cplx t = row[p];
+      row[p] = row[c];
+      row[c] = t;
+    }
+  }
+}
+
+hipError_t launch_gj_inverse(int N, cplx* A, cplx* work, int* piv, int* status, hipStream_t s) {
+  cplx* col = work;
+  cplx* prow = work + N;
+  long tot = (long)N * N;
+  unsigned nb = (unsigned)((tot + NT3 - 1) / NT3);
+  for (int c = 0; c < N; c++) {
+    k_gj_pivot<<<1, NGJ, 0, s>>>(N, c, A, col, prow, piv, status);
+    k_gj_update<<<nb, NT3, 0, s>>>(N, c, A, col, prow);
+  }
+  k_gj_unpivot<<<(N + NT3 - 1) / NT3, NT3, 0, s>>>(N, A, piv);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------ matvec
+// y = X v  or  y = b - X v ; one wavefront per row, lanes stride the row.
+__global__ __launch_bounds__(NT3) void k_matvec(int N, int nrhs, const cplx* X, const cplx* v,
+                                                const cplx* b, cplx* y) {
+  int lane = threadIdx.x % 64;
+  long r = (long)blockIdx.x * (NT3 / 64) + threadIdx.x / 64;
+  if (r >= N) return;
+  cplx acc[8];
+  for (int c = 0; c < 8; c++) acc[c] = mk(0, 0);
+  const cplx* row = X + r * N;
+  for (int q = lane; q < N; q += 64) {
+    cplx x = row[q];
+    for (int c = 0; c < nrhs; c++) cfma(acc[c], x, v[(long)q * nrhs + c]);
+  }
+  for (int c = 0; c < nrhs; c++) {
+    double re = acc[c].x, im = acc[c].y;
+    for (int off = 32; off > 0; off >>= 1) {
+      re += __shfl_xor(re, off);
+      im += __shfl_xor(im, off);
+    }
+    if (lane == 0) {
+      cplx o = mk(re, im);
+      y[r * nrhs + c] = b ? b[r * nrhs + c] - o : o;
+    }
+  }
+}
+
+hipError_t launch_matvec(int N, int nrhs, const cplx* X, const cplx* v, const cplx* b, cplx* y,
+                         hipStream_t s) {
+  k_matvec<<<(N + 3) / 4, NT3, 0, s>>>(N, nrhs, X, v, b, y);
+  return hipGetLastError();
+}
+
+// x += dx ; norms[0] += sum |r|^2, norms[1] += sum |g|^2
+__global__ __launch_bounds__(NT3) void k_axpy_norm(int len, cplx* x, const cplx* dx, const cplx* r,
+                                                   const cplx* g, double* norms) {
+  __shared__ double s0[NT3], s1[NT3];
+  long i = (long)blockIdx.x * NT3 + threadIdx.x;
+  double a = 0, b = 0;
+  if (i < len) {
+    if (dx) x[i] = x[i] + dx[i];
+    a = abs2(r[i]);
+    b = abs2(g[i]);
+  }
+  s0[threadIdx.x] = a;
+  s1[threadIdx.x] = b;
+  __syncthreads();
+  for (int w = NT3 / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      s0[threadIdx.x] += s0[threadIdx.x + w];
+      s1[threadIdx.x] += s1[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    atomicAdd(&norms[0], s0[0]);
+    atomicAdd(&norms[1], s1[0]);
+  }
+}
+
+hipError_t launch_axpy_norm(int len, cplx* x, const cplx* dx, const cplx* r, const cplx* g,
+                            double* norms, hipStream_t s) {
+  k_axpy_norm<<<(len + NT3 - 1) / NT3, NT3, 0, s>>>(len, x, dx, r, g, norms);
+  return hipGetLastError();
+}
+
+}  // namespace cntr

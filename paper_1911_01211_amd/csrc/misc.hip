@@ -1,0 +1,433 @@
+// Elementwise slice kernels: second-Born self-energy + Hartree mean field,
+// polynomial extrapolation, slice distance and copy; and the general contour
+// convolution C = A * f * B (Eqs. cm1, cm2, cr1, ctv1-ctv3, cles1-cles3).
+#include "launch.h"
+
+namespace cntr {
+
+constexpr int NT2 = 256;
+
+// element index e of slice n -> (component, block, a, c); components:
+// 0 = R_{n,j} (j = 0..n), 1 = L_{j,n} (j = 0..n), 2 = T_{n,m} (m = 0..ntau)
+struct SliceIdx {
+  int comp, j, a, c;
+};
+__device__ inline SliceIdx slice_idx(long idx, int n, int ntau, int d) {
+  int dd = d * d;
+  long nr = (long)(n + 1) * dd;
+  SliceIdx s;
+  int e;
+  if (idx < nr) {
+    s.comp = 0;
+    s.j = idx / dd;
+    e = idx % dd;
+  } else if (idx < 2 * nr) {
+    idx -= nr;
+    s.comp = 1;
+    s.j = idx / dd;
+    e = idx % dd;
+  } else {
+    idx -= 2 * nr;
+    s.comp = 2;
+    s.j = idx / dd;
+    e = idx % dd;
+  }
+  s.a = e / d;
+  s.c = e % d;
+  return s;
+}
+
+__device__ inline cplx* slice_ptr(const Prob& P, const SliceIdx& s, int n, cplx* ret, cplx* les,
+                                  cplx* tv) {
+  int d = P.d, dd = d * d;
+  if (s.comp == 0) return ret + (tri(n) + s.j) * dd + s.a * d + s.c;
+  if (s.comp == 1) return les + (tri(n) + s.j) * dd + s.a * d + s.c;
+  return tv + ((size_t)n * (P.ntau + 1) + s.j) * dd + s.a * d + s.c;
+}
+
+// ------------------------------------------------------------ Sigma 2B
+// Sigma_ab(z,z') = U(z) U(z') G_ab(z,z')^2 G_ba(z',z) (Eq. sigma_hubb_2b):
+//   Sigma^<_ab(j,n) = U_j U_n (L_{j,n}[a,b])^2 G^>_ba(n,j)
+//   Sigma^R_ab(n,j) = Sigma^>_ab(n,j) - Sigma^<_ab(n,j)
+//   Sigma^rceil_ab(n,m) = U_n U_{-1} (T_{n,m}[a,b])^2 G^lceil_ba(m,n)
+//   Sigma^M_ab(m) = -xi U_{-1}^2 (M_m[a,b])^2 M_{ntau-m}[b,a]
+// with G^>(t_n,t_j) = G^R + G^< (t_n >= t_j), G^<(t_n,t_j) = -[G^<(t_j,t_n)]^dag.
+__global__ __launch_bounds__(NT2) void k_sigma2b(ProbArg pa, int n, double nbar) {
+  int pi = blockIdx.y;
+  const Prob& P = pa.get(pi);
+  if (n > P.nt) return;
+  int d = P.d, dd = d * d, ntau = P.ntau;
+  const double* u = P.U;
+  double xi = P.sig;
+  long idx = (long)blockIdx.x * NT2 + threadIdx.x;
+  if (n == -1) {
+    if (idx < (long)(ntau + 1) * dd) {
+      int m = idx / dd, e = idx % dd, a = e / d, c = e % d;
+      cplx x = P.Gmat[(size_t)m * dd + e], y = P.Gmat[(size_t)(ntau - m) * dd + c * d + a];
+      P.Smat[(size_t)m * dd + e] = (-xi * u[0] * u[0]) * (x * x * y);
+    }
+  } else {
+    long total = (long)(2 * (n + 1) + ntau + 1) * dd;
+    if (idx < total) {
+      SliceIdx s = slice_idx(idx, n, ntau, d);
+      int a = s.a, b = s.c, j = s.j;
+      if (s.comp == 2) {
+        cplx x = P.Gtv[((size_t)n * (ntau + 1) + j) * dd + a * d + b];
+        cplx vt = -xi * conj(P.Gtv[((size_t)n * (ntau + 1) + ntau - j) * dd + a * d + b]);
+        P.Stv[((size_t)n * (ntau + 1) + j) * dd + a * d + b] = (u[n + 1] * u[0]) * (x * x * vt);
+      } else {
+        double uu = u[n + 1] * u[j + 1];
+        const cplx* R = P.Gret + (tri(n) + j) * dd;
+        const cplx* L = P.Gles + (tri(n) + j) * dd;
+        cplx Lab = L[a * d + b], Lba = L[b * d + a], Rab = R[a * d + b], Rba = R[b * d + a];
+        if (s.comp == 1) {
+          cplx gtr_ba_nj = Rba - conj(Lab);
+          P.Sles[(tri(n) + j) * dd + a * d + b] = uu * (Lab * Lab * gtr_ba_nj);
+        } else {
+          cplx gtr_ab_nj = Rab - conj(Lba);
+          cplx les_ab_nj = -conj(Lba);
+          cplx gtr_ba_jn = Lba - conj(Rab);
+          cplx sg = gtr_ab_nj * gtr_ab_nj * Lba;
+          cplx sl = les_ab_nj * les_ab_nj * gtr_ba_jn;
+          P.Sret[(tri(n) + j) * dd + a * d + b] = uu * (sg - sl);
+        }
+      }
+    }
+  }
+  // Hartree mean field from the density matrix rho = i xi G^<(t,t)
+  // (rho = -G^M(beta^-) on the Matsubara branch)
+  if (P.eps_mf != nullptr && blockIdx.x == 0 && threadIdx.x < dd) {
+    int e = threadIdx.x, a = e / d, c = e % d;
+    const cplx* e0 = P.eps0 + (size_t)(n + 1) * dd;
+    cplx v = e0[e];
+    if (a == c) {
+      double rho;
+      if (n == -1) rho = -P.Gmat[(size_t)ntau * dd + a * d + a].x;
+      else {
+        cplx l = P.Gles[(tri(n) + n) * dd + a * d + a];
+        rho = -xi * l.y;
+      }
+      v.x += u[n + 1] * (rho - nbar);
+    }
+    P.eps_mf[(size_t)(n + 1) * dd + e] = v;
+  }
+}
+
+hipError_t launch_sigma2b(const ProbArg& pa, int n, int d, int nmax_elems, double nbar,
+                          hipStream_t s) {
+  dim3 g((nmax_elems + NT2 - 1) / NT2, pa.count);
+  k_sigma2b<<<g, NT2, 0, s>>>(pa, n, nbar);
+  return hipGetLastError();
+}
+
+// --------------------------------------------------------- extrapolation
+// Eq. polyextrap: slice n+1 from slices n-k..n; left-mixing along t for every
+// tau, retarded columns j <= k along t and the rest along the diagonals
+// t - t' = const; lesser rows j <= k along t' and the rest along diagonals.
+__global__ __launch_bounds__(NT2) void k_extrapolate(ProbArg pa, int n) {
+  int pi = blockIdx.y;
+  const Prob& P = pa.get(pi);
+  int n1 = n + 1;
+  if (n1 > P.nt) return;
+  const KW& W = c_kw[P.k];
+  int d = P.d, dd = d * d, ntau = P.ntau, k = P.k;
+  long idx = (long)blockIdx.x * NT2 + threadIdx.x;
+  long total = (long)(2 * (n1 + 1) + ntau + 1) * dd;
+  if (idx >= total) return;
+  SliceIdx s = slice_idx(idx, n1, ntau, d);
+  int j = s.j, a = s.a, c = s.c;
+  cplx acc = mk(0, 0);
+  for (int l = 0; l <= k; l++) {
+    cplx v;
+    if (s.comp == 2) {
+      v = P.Gtv[((size_t)(n - l) * (ntau + 1) + j) * dd + a * d + c];
+    } else if (s.comp == 0) {
+      if (j <= k) {
+        int t = n - l;
+        v = t >= j ? P.Gret[(tri(t) + j) * dd + a * d + c] : -conj(P.Gret[(tri(j) + t) * dd + c * d + a]);
+      } else {
+        int jj = n1 - j;  // diagonal offset
+        v = P.Gret[(tri(n - l) + n - l - jj) * dd + a * d + c];
+      }
+    } else {
+      if (j <= k) {
+        int t = n - l;
+        v = j <= t ? P.Gles[(tri(t) + j) * dd + a * d + c] : -conj(P.Gles[(tri(j) + t) * dd + c * d + a]);
+      } else {
+        v = P.Gles[(tri(n - l) + j - 1 - l) * dd + a * d + c];
+      }
+    }
+    acc = acc + W.ext[l] * v;
+  }
+  *slice_ptr(P, s, n1, P.Gret, P.Gles, P.Gtv) = acc;
+}
+
+hipError_t launch_extrapolate(const ProbArg& pa, int n, int d, int nelems, hipStream_t s) {
+  dim3 g((nelems + NT2 - 1) / NT2, pa.count);
+  k_extrapolate<<<g, NT2, 0, s>>>(pa, n);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------- distance / copy
+__global__ __launch_bounds__(NT2) void k_distance(ProbArg pa, ProbArg pb, int n, double* out) {
+  __shared__ double r0[NT2], r1[NT2];
+  int pi = blockIdx.y;
+  const Prob& A = pa.get(pi);
+  const Prob& B = pb.get(pi);
+  int d = A.d, dd = d * d, ntau = A.ntau;
+  long idx = (long)blockIdx.x * NT2 + threadIdx.x;
+  double s0 = 0, s1 = 0;
+  if (n == -1) {
+    if (idx < (long)(ntau + 1) * dd) {
+      cplx x = A.Gmat[idx], y = B.Gmat[idx];
+      s0 = sqrt(abs2(x - y));
+      s1 = sqrt(abs2(x));
+    }
+  } else if (n <= A.nt) {
+    long total = (long)(2 * (n + 1) + ntau + 1) * dd;
+    if (idx < total) {
+      SliceIdx s = slice_idx(idx, n, ntau, d);
+      cplx x = *slice_ptr(A, s, n, A.Gret, A.Gles, A.Gtv);
+      cplx y = *slice_ptr(B, s, n, B.Gret, B.Gles, B.Gtv);
+      s0 = sqrt(abs2(x - y));
+      s1 = sqrt(abs2(x));
+    }
+  }
+  r0[threadIdx.x] = s0;
+  r1[threadIdx.x] = s1;
+  __syncthreads();
+  for (int w = NT2 / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      r0[threadIdx.x] += r0[threadIdx.x + w];
+      r1[threadIdx.x] += r1[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    atomicAdd(&out[2 * pi], r0[0]);
+    atomicAdd(&out[2 * pi + 1], r1[0]);
+  }
+}
+
+hipError_t launch_distance(const ProbArg& pa, const ProbArg& pb, int n, int d, int nelems,
+                           double* out_dev, hipStream_t s) {
+  dim3 g((nelems + NT2 - 1) / NT2, pa.count);
+  k_distance<<<g, NT2, 0, s>>>(pa, pb, n, out_dev);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(NT2) void k_copy(ProbArg pd, ProbArg ps, int n) {
+  int pi = blockIdx.y;
+  const Prob& D = pd.get(pi);
+  const Prob& S = ps.get(pi);
+  int d = D.d, dd = d * d, ntau = D.ntau;
+  long idx = (long)blockIdx.x * NT2 + threadIdx.x;
+  if (n == -1) {
+    if (idx < (long)(ntau + 1) * dd) D.Gmat[idx] = S.Gmat[idx];
+    return;
+  }
+  if (n > D.nt) return;
+  long total = (long)(2 * (n + 1) + ntau + 1) * dd;
+  if (idx >= total) return;
+  SliceIdx s = slice_idx(idx, n, ntau, d);
+  *slice_ptr(D, s, n, D.Gret, D.Gles, D.Gtv) = *slice_ptr(S, s, n, S.Gret, S.Gles, S.Gtv);
+}
+
+hipError_t launch_copy(const ProbArg& pdst, const ProbArg& psrc, int n, int d, int nelems,
+                       hipStream_t s) {
+  dim3 g((nelems + NT2 - 1) / NT2, pdst.count);
+  k_copy<<<g, NT2, 0, s>>>(pdst, psrc, n);
+  return hipGetLastError();
+}
+
+// ----------------------------------------------------------- convolution
+// Values outside the stored triangles of X come from its partner Xc.
+__device__ inline cplx cv_ret(const Prob& X, const Prob& Xc, int a, int b, int r, int c) {
+  int d = X.d, dd = d * d;
+  if (a >= b) return X.Gret[(tri(a) + b) * dd + r * d + c];
+  return -conj(Xc.Gret[(tri(b) + a) * dd + c * d + r]);
+}
+__device__ inline cplx cv_les(const Prob& X, const Prob& Xc, int a, int b, int r, int c) {
+  int d = X.d, dd = d * d;
+  if (a <= b) return X.Gles[(tri(b) + a) * dd + r * d + c];
+  return -conj(Xc.Gles[(tri(a) + b) * dd + c * d + r]);
+}
+// X^A_{a,b}[r][c] = conj([Xc]~^R_{b,a}[c][r])
+__device__ inline cplx cv_adv(const Prob& X, const Prob& Xc, int a, int b, int r, int c) {
+  return conj(cv_ret(Xc, X, b, a, c, r));
+}
+// X^lceil(tau_j, t_n)[r][c] = -xi conj(Xc^rceil_{n,ntau-j}[c][r])
+__device__ inline cplx cv_vt(const Prob& X, const Prob& Xc, int j, int n, int r, int c) {
+  int d = X.d, dd = d * d;
+  return (-(double)X.sig) * conj(Xc.Gtv[((size_t)n * (X.ntau + 1) + X.ntau - j) * dd + c * d + r]);
+}
+
+// [X f Y][a][c] for blocks given as element accessors; f may be null
+template <class FA, class FB>
+__device__ inline cplx triple(int d, FA Ael, const cplx* f, FB Bel, int a, int c) {
+  cplx s = mk(0, 0);
+  if (f == nullptr) {
+    for (int q = 0; q < d; q++) cfma(s, Ael(a, q), Bel(q, c));
+    return s;
+  }
+  for (int q = 0; q < d; q++) {
+    cplx af = mk(0, 0);
+    for (int p = 0; p < d; p++) cfma(af, Ael(a, p), f[p * d + q]);
+    cfma(s, af, Bel(q, c));
+  }
+  return s;
+}
+
+__device__ inline const cplx* fat(const cplx* f, int t, int d) {
+  return f == nullptr ? nullptr : f + (size_t)(t + 1) * d * d;
+}
+
+// Matsubara convolution, Eqs. cm1 + cm2, element (a,c) of C^M_m.
+__device__ inline cplx mat_conv_elem(const Prob& P, const cplx* A, const cplx* B, const cplx* f,
+                                     int m, int a, int c) {
+  const KW& W = c_kw[P.k];
+  int d = P.d, dd = d * d, k = P.k, nt = P.ntau;
+  double ht = P.htau, xi = P.sig;
+  const cplx* fm = fat(f, -1, d);
+  cplx acc = mk(0, 0);
+  auto pr = [&](int ia, int ib) {
+    return triple(d, [&](int x, int y) { return A[(size_t)ia * dd + x * d + y]; }, fm,
+                  [&](int x, int y) { return B[(size_t)ib * dd + x * d + y]; }, a, c);
+  };
+  if (m <= k) {
+    for (int j = 0; j <= k; j++)
+      for (int l = 0; l <= k; l++) acc = acc + (ht * W.R[m][j][l]) * pr(j, l);
+  } else {
+    for (int l = 0; l <= m; l++) acc = acc + (ht * greg(W, m, l)) * pr(m - l, l);
+  }
+  if (m >= nt - k) {
+    for (int j = 0; j <= k; j++)
+      for (int l = 0; l <= k; l++) acc = acc + (ht * xi * W.R[nt - m][j][l]) * pr(nt - j, nt - l);
+  } else {
+    for (int l = 0; l <= nt - m; l++) acc = acc + (ht * xi * greg(W, nt - m, l)) * pr(nt - l, m + l);
+  }
+  return acc;
+}
+
+__global__ __launch_bounds__(NT2) void k_convolution(ProbArg pc, ProbArg pa, ProbArg pac,
+                                                     ProbArg pb, ProbArg pbc, int n) {
+  int pi = blockIdx.y;
+  const Prob& C = pc.get(pi);
+  const Prob& A = pa.get(pi);
+  const Prob& Ac = pac.get(pi);
+  const Prob& B = pb.get(pi);
+  const Prob& Bc = pbc.get(pi);
+  const cplx* f = C.f;
+  const KW& W = c_kw[C.k];
+  int d = C.d, dd = d * d, ntau = C.ntau, k = C.k;
+  double h = C.h, ht = C.htau;
+  long idx = (long)blockIdx.x * NT2 + threadIdx.x;
+  if (n == -1) {
+    if (idx < (long)(ntau + 1) * dd) {
+      int m = idx / dd, e = idx % dd;
+      C.Gmat[idx] = mat_conv_elem(C, A.Gmat, B.Gmat, f, m, e / d, e % d);
+    }
+    return;
+  }
+  if (n > C.nt) return;
+  long total = (long)(2 * (n + 1) + ntau + 1) * dd;
+  if (idx >= total) return;
+  SliceIdx s = slice_idx(idx, n, ntau, d);
+  int a = s.a, c = s.c, m = s.j;
+  cplx acc = mk(0, 0);
+  if (s.comp == 0) {  // Eq. cr1, C^R(t_n, t_m)
+    if (n > k && n - m > k) {
+      for (int j = m; j <= n; j++)
+        acc = acc + (h * greg(W, n - m, j - m)) *
+                        triple(d, [&](int x, int y) { return A.Gret[(tri(n) + j) * dd + x * d + y]; },
+                               fat(f, j, d), [&](int x, int y) { return B.Gret[(tri(j) + m) * dd + x * d + y]; }, a, c);
+    } else if (n > k) {
+      for (int j = 0; j <= k; j++)
+        acc = acc + (h * greg(W, n - m, j)) *
+                        triple(d, [&](int x, int y) { return A.Gret[(tri(n) + n - j) * dd + x * d + y]; },
+                               fat(f, n - j, d), [&](int x, int y) { return cv_ret(B, Bc, n - j, m, x, y); }, a, c);
+    } else {
+      for (int j = 0; j <= k; j++)
+        acc = acc + (h * W.I[m][n][j]) *
+                        triple(d, [&](int x, int y) { return cv_ret(A, Ac, n, j, x, y); }, fat(f, j, d),
+                               [&](int x, int y) { return cv_ret(B, Bc, j, m, x, y); }, a, c);
+    }
+  } else if (s.comp == 2) {  // Eqs. ctv1 + ctv2 + ctv3, C^rceil(t_n, tau_m)
+    const cplx* fm = fat(f, -1, d);
+    auto pr = [&](int la, int lb) {
+      return triple(d, [&](int x, int y) { return A.Gtv[((size_t)n * (ntau + 1) + la) * dd + x * d + y]; }, fm,
+                    [&](int x, int y) { return B.Gmat[(size_t)lb * dd + x * d + y]; }, a, c);
+    };
+    double xi = C.sig;
+    if (m <= k) {
+      for (int j = 0; j <= k; j++)
+        for (int l = 0; l <= k; l++) acc = acc + (ht * xi * W.R[m][j][l]) * pr(l, ntau - j);
+    } else {
+      for (int l = 0; l <= m; l++) acc = acc + (ht * xi * greg(W, m, l)) * pr(m - l, ntau - l);
+    }
+    if (m >= ntau - k) {
+      for (int j = 0; j <= k; j++)
+        for (int l = 0; l <= k; l++) acc = acc + (ht * W.R[ntau - m][j][l]) * pr(ntau - l, j);
+    } else {
+      for (int l = 0; l <= ntau - m; l++) acc = acc + (ht * greg(W, ntau - m, l)) * pr(m + l, l);
+    }
+    int jmax = n > k ? n : k;
+    for (int j = 0; j <= jmax; j++) {
+      double w = n > k ? greg(W, n, j) : W.s[n][j];
+      acc = acc + (h * w) * triple(d, [&](int x, int y) { return cv_ret(A, Ac, n, j, x, y); }, fat(f, j, d),
+                                   [&](int x, int y) { return B.Gtv[((size_t)j * (ntau + 1) + m) * dd + x * d + y]; },
+                                   a, c);
+    }
+  } else {  // C^<(t_m, t_n): Eqs. cles1 + cles2 + cles3
+    int j1 = m > k ? m : k;
+    for (int j = 0; j <= j1; j++) {
+      double w = m > k ? greg(W, m, j) : W.s[m][j];
+      acc = acc + (h * w) * triple(d, [&](int x, int y) { return cv_ret(A, Ac, m, j, x, y); }, fat(f, j, d),
+                                   [&](int x, int y) { return cv_les(B, Bc, j, n, x, y); }, a, c);
+    }
+    int j2 = n > k ? n : k;
+    for (int j = 0; j <= j2; j++) {
+      double w = n > k ? greg(W, n, j) : W.s[n][j];
+      acc = acc + (h * w) * triple(d, [&](int x, int y) { return cv_les(A, Ac, m, j, x, y); }, fat(f, j, d),
+                                   [&](int x, int y) { return cv_adv(B, Bc, j, n, x, y); }, a, c);
+    }
+    const cplx* fm = fat(f, -1, d);
+    cplx s3 = mk(0, 0);
+    for (int j = 0; j <= ntau; j++)
+      s3 = s3 + (ht * greg(W, ntau, j)) *
+                    triple(d, [&](int x, int y) { return A.Gtv[((size_t)m * (ntau + 1) + j) * dd + x * d + y]; }, fm,
+                           [&](int x, int y) { return cv_vt(B, Bc, j, n, x, y); }, a, c);
+    acc = acc - mul_i(s3);
+  }
+  *slice_ptr(C, s, n, C.Gret, C.Gles, C.Gtv) = acc;
+}
+
+hipError_t launch_convolution(const ProbArg& C, const ProbArg& A, const ProbArg& Acc,
+                              const ProbArg& B, const ProbArg& Bcc, int n, int d, int nelems,
+                              hipStream_t s) {
+  dim3 g((nelems + NT2 - 1) / NT2, C.count);
+  k_convolution<<<g, NT2, 0, s>>>(C, A, Acc, B, Bcc, n);
+  return hipGetLastError();
+}
+
+}  // namespace cntr
+
+namespace cntr {
+
+__global__ __launch_bounds__(NT2) void k_mat_conv(Prob P, const cplx* A, const cplx* B, const cplx* f,
+                                                  cplx* out) {
+  int d = P.d, dd = d * d;
+  long idx = (long)blockIdx.x * NT2 + threadIdx.x;
+  if (idx >= (long)(P.ntau + 1) * dd) return;
+  int m = idx / dd, e = idx % dd;
+  out[idx] = mat_conv_elem(P, A, B, f, m, e / d, e % d);
+}
+
+hipError_t launch_mat_conv(const Prob& P, const cplx* A, const cplx* B, const cplx* f, cplx* out,
+                           hipStream_t s) {
+  long tot = (long)(P.ntau + 1) * P.d * P.d;
+  k_mat_conv<<<(unsigned)((tot + NT2 - 1) / NT2), NT2, 0, s>>>(P, A, B, f, out);
+  return hipGetLastError();
+}
+
+}  // namespace cntr

@@ -1,0 +1,274 @@
+"""GPU parity: every entry point of the HIP library (called through the C ABI)
+against the CPU oracle on identical seeded inputs. Tolerance: relative
+max-norm per component, max|X_gpu - X_ref| / max|X_ref| <= 1e-10."""
+import dataclasses
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from paper_1911_01211_amd import contour as K
+from paper_1911_01211_amd import workloads as W
+from tests.test_oracle_dyson import hm
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-10
+DEV = "cuda"
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def relerr(x, ref):
+    den = np.abs(ref).max()
+    return float(np.abs(x - ref).max() / (den if den > 0 else 1.0))
+
+
+def to_dev(c):
+    return c if isinstance(c, torch.Tensor) else torch.as_tensor(np.ascontiguousarray(c)).to(DEV)
+
+
+def ora(O, g, c):
+    return hm(O, g, c)
+
+
+def slice_views(g, c, n):
+    d = g.d
+    o = n * (n + 1) // 2
+    return dict(ret=c["ret"][o:o + n + 1], les=c["les"][o:o + n + 1],
+                tv=c["tv"][n * (g.ntau + 1):(n + 1) * (g.ntau + 1)])
+
+
+def assert_slices(g, got, ref, slices, tol=TOL, what=""):
+    for n in slices:
+        if n == -1:
+            e = relerr(got["mat"], ref["mat"])
+            assert e < tol, (what, n, "mat", e)
+            continue
+        a, b = slice_views(g, got, n), slice_views(g, ref, n)
+        for key in a:
+            e = relerr(a[key], b[key])
+            assert e < tol, (what, n, key, e)
+
+
+def rand_eps(r, g, scale=0.5):
+    eps = np.empty((g.nt + 2, g.d, g.d), np.complex128)
+    for i in range(g.nt + 2):
+        eps[i] = W.random_hermitian(r, g.d, scale)
+    return eps
+
+
+def require_gpu():
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    from paper_1911_01211_amd import _abi
+    _abi.lib()
+
+
+# ----------------------------------------------------------------- Matsubara
+@pytest.mark.parametrize("d,sig", [(1, -1), (2, -1), (4, -1), (3, 1), (8, -1)])
+def test_matsubara_parity(O, d, sig):
+    require_gpu()
+    say(f"matsubara d={d} sig={sig}")
+    g = W.GridSpec(nt=6, ntau=60 if d < 8 else 40, d=d, sig=sig, beta=6.0, h=0.05, k=5,
+                   mu=-2.5 if sig > 0 else 0.1)
+    r = W.rng(100, d, sig + 2)
+    S = W.random_contour(r, g, 0.15)
+    eps = rand_eps(r, g)
+    if sig > 0:
+        eps[0] += 0.0  # mu well below the spectrum keeps the boson function finite
+    Go, So = ora(O, g, None), ora(O, g, S)
+    O.dyson_mat(Go, So, eps[0])
+    Gd, Sd = K.Contour(g), K.Contour(g, data=S)
+    K.init_matsubara([Gd], [Sd], [to_dev(eps)])
+    torch.cuda.synchronize()
+    assert relerr(Gd.mat.cpu().numpy(), Go.mat) < TOL
+
+
+# ------------------------------------------------------------------ start-up
+@pytest.mark.parametrize("d", [1, 2, 4, 8])
+def test_startup_parity(O, d):
+    require_gpu()
+    say(f"startup d={d}")
+    g = W.GridSpec(nt=12, ntau=30, d=d, beta=3.0, h=0.04, k=5, mu=0.2)
+    r = W.rng(101, d)
+    S = W.random_contour(r, g, 0.3)
+    G0 = W.random_contour(r, g, 0.5)  # Matsubara taken as given input
+    eps = rand_eps(r, g)
+    Go = ora(O, g, G0)
+    O.dyson_start(Go, ora(O, g, S), eps)
+    Gd = K.Contour(g, data=G0)
+    K.dyson_step(g.k, [Gd], [K.Contour(g, data=S)], [to_dev(eps)])
+    K.sync()
+    got = Gd.numpy()
+    ref = {k: getattr(Go, k) for k in K.KEYS}
+    assert_slices(g, got, ref, range(0, g.k + 1), what="startup")
+
+
+# ------------------------------------------------------- single time steps
+@pytest.mark.parametrize("d", [1, 2, 3, 4, 8])
+def test_timestep_random_history(O, d):
+    require_gpu()
+    k = 5
+    ntau = 70 if d < 8 else 37
+    nt = 150 if d < 8 else 80
+    g = W.GridSpec(nt=nt, ntau=ntau, d=d, beta=4.0, h=0.03, k=k, mu=-0.3)
+    r = W.rng(102, d)
+    G = W.random_contour(r, g, 0.4, decay=0.5)
+    S = W.random_contour(r, g, 0.3, decay=0.5)
+    eps = rand_eps(r, g)
+    Sd = K.Contour(g, data=S)
+    e = to_dev(eps)
+    for n in sorted({k + 1, 2 * k, 2 * k + 1, 2 * k + 2, 33, 64, 65, nt - 1, nt}):
+        say(f"timestep d={d} n={n}")
+        Go = ora(O, g, G)
+        assert O.dyson_timestep(n, Go, ora(O, g, S), eps, "B") == 0
+        Gd = K.Contour(g, data=G)
+        K.dyson_step(n, [Gd], [Sd], [e])
+        K.sync()
+        got = Gd.numpy()
+        ref = {key: getattr(Go, key) for key in K.KEYS}
+        assert_slices(g, got, ref, [n], what=f"step d={d}")
+        # nothing but slice n changes
+        o = n * (n + 1) // 2
+        assert np.array_equal(got["ret"][:o], G["ret"][:o])
+        assert np.array_equal(got["les"][:o], G["les"][:o])
+
+
+# -------------------------------------------------- plain solve, config 0
+def test_two_level_embedding_full_solve(O):
+    """Plain Dyson solve of the 2x2 level with a bath self-energy at the sizes
+    of the small configuration: Nt = 100, h = 0.05, Ntau = 100, beta = 5, k = 5."""
+    require_gpu()
+    say("embedding full solve")
+    g = W.GridSpec(nt=100, ntau=100, d=2, beta=5.0, h=0.05, k=5)
+    eps, S, Ge = W.two_level_embedding(g)
+    Go = ora(O, g, None)
+    O.solve_fixed(Go, ora(O, g, S), eps)
+    Gd, Sd, e = K.Contour(g), K.Contour(g, data=S), to_dev(eps)
+    K.init_matsubara([Gd], [Sd], [e])
+    K.dyson_step(g.k, [Gd], [Sd], [e])
+    for n in range(g.k + 1, g.nt + 1):
+        K.dyson_step(n, [Gd], [Sd], [e])
+    K.sync()
+    got = Gd.numpy()
+    for key in K.KEYS:
+        assert relerr(got[key], getattr(Go, key)) < TOL, key
+        # and both are within the scheme's accuracy of the exact embedding
+        assert np.abs(got[key] - Ge[key]).max() < 1e-5, key
+
+
+# ---------------------------------------------------------------- Sigma 2B
+@pytest.mark.parametrize("d", [1, 4])
+def test_sigma2b_parity(O, d):
+    require_gpu()
+    say(f"sigma2b d={d}")
+    g = W.GridSpec(nt=40, ntau=50, d=d, beta=3.0, h=0.05, k=5)
+    r = W.rng(103, d)
+    G = W.random_contour(r, g, 0.5)
+    U = r.uniform(0.5, 2.0, g.nt + 2)
+    eps0 = rand_eps(r, g)
+    Go, So = ora(O, g, G), ora(O, g, None)
+    emf_o = np.zeros_like(eps0)
+    for n in range(-1, g.nt + 1):
+        O.sigma_2b(n, Go, U, So)
+        O.hartree(n, Go, U, eps0, emf_o, 0.5)
+    Gd, Sd = K.Contour(g, data=G), K.Contour(g)
+    Ud, e0 = to_dev(U), to_dev(eps0)
+    emf = torch.zeros_like(e0)
+    for n in range(-1, g.nt + 1):
+        K.sigma_2b(n, [Gd], [Ud], [Sd], [e0], [emf])
+    K.sync()
+    got = Sd.numpy()
+    for key in K.KEYS:
+        assert relerr(got[key], getattr(So, key)) < 1e-13, key
+    assert relerr(emf.cpu().numpy(), emf_o) < 1e-13
+
+
+def test_extrapolate_parity(O):
+    require_gpu()
+    say("extrapolate")
+    g = W.GridSpec(nt=30, ntau=20, d=2, beta=3.0, h=0.05, k=5)
+    r = W.rng(104)
+    G = W.random_contour(r, g, 0.5)
+    for n in (5, 6, 11, 29):
+        Go = ora(O, g, G)
+        O.extrapolate(n, Go)
+        Gd = K.Contour(g, data=G)
+        K.extrapolate(n, [Gd])
+        K.sync()
+        got = Gd.numpy()
+        ref = {key: getattr(Go, key) for key in K.KEYS}
+        assert_slices(g, got, ref, [n + 1], tol=1e-13, what="extrapolate")
+
+
+@pytest.mark.parametrize("with_f", [False, True])
+def test_convolution_parity(O, with_f):
+    require_gpu()
+    say(f"convolution f={with_f}")
+    g = W.GridSpec(nt=24, ntau=30, d=2, beta=2.0, h=0.05, k=5)
+    r = W.rng(105, int(with_f))
+    A, Acc, B, Bcc = (W.random_contour(r, g, 0.5) for _ in range(4))
+    f = rand_eps(r, g, 1.0) if with_f else None
+    Co = ora(O, g, None)
+    Cd = K.Contour(g)
+    args_o = [ora(O, g, x) for x in (A, Acc, B, Bcc)]
+    args_d = [[K.Contour(g, data=x)] for x in (A, Acc, B, Bcc)]
+    slices = [-1, 0, 2, 5, 6, 11, 12, 24]
+    for n in slices:
+        O.convolution_timestep(n, Co, *args_o, f)
+        K.convolution(n, [Cd], *args_d, f=None if f is None else [to_dev(f)])
+    K.sync()
+    got = Cd.numpy()
+    ref = {key: getattr(Co, key) for key in K.KEYS}
+    assert_slices(g, got, ref, slices, what="convolution")
+
+
+# ------------------------------------------------------ self-consistent 2B
+def test_solve_2b_parity(O):
+    """Self-consistent second-Born + Hartree of the 4-site Hubbard chain with
+    the U ramp 2 -> 1, reduced in length (Nt = 40) and Ntau (100)."""
+    require_gpu()
+    say("solve_2b")
+    g = W.GridSpec(nt=40, ntau=100, d=4, beta=20.0, h=0.02, k=5)
+    e0, U = W.hubbard_ramp(g)
+    Go, So = ora(O, g, None), ora(O, g, None)
+    rc, emf_o, st = O.solve_2b(Go, So, e0, U, ncorr=5, mats_tol=1e-13, boot_tol=1e-13)
+    assert rc == 0
+    Gd, Sd, Gs = K.Contour(g), K.Contour(g), K.Contour(g)
+    e0d, Ud = to_dev(e0), to_dev(U)
+    emf = torch.zeros_like(e0d)
+    sd = K.solve_2b(Gd, Sd, Gs, e0d, Ud, emf, ncorr=5, mats_tol=1e-13, boot_tol=1e-13)
+    K.sync()
+    say(f"oracle stats {st}  gpu stats {sd}")
+    got = Gd.numpy()
+    for key in K.KEYS:
+        assert relerr(got[key], getattr(Go, key)) < TOL, key
+    assert relerr(emf.cpu().numpy(), emf_o) < TOL
+
+
+# ------------------------------------------------------------ batching
+def test_batch_matches_single_instances(O):
+    require_gpu()
+    say("batch")
+    base = W.GridSpec(nt=30, ntau=40, d=2, beta=3.0, h=0.04, k=5, mu=0.1)
+    grids = [dataclasses.replace(base, nt=nt) for nt in (30, 22, 27)]
+    r = W.rng(106)
+    data = [(W.random_contour(r, g, 0.4, decay=0.3), W.random_contour(r, g, 0.3, decay=0.3),
+             rand_eps(r, g)) for g in grids]
+    n = 25
+    Gb = [K.Contour(g, data=x[0]) for g, x in zip(grids, data)]
+    K.dyson_step(n, Gb, [K.Contour(g, data=x[1]) for g, x in zip(grids, data)],
+                 [to_dev(x[2]) for x in data])
+    K.sync()
+    for g, x, G in zip(grids, data, Gb):
+        if g.nt < n:  # skipped instance is untouched
+            assert np.array_equal(G.numpy()["ret"], x[0]["ret"])
+            continue
+        Gs = K.Contour(g, data=x[0])
+        K.dyson_step(n, [Gs], [K.Contour(g, data=x[1])], [to_dev(x[2])])
+        K.sync()
+        for key in K.KEYS:
+            assert np.array_equal(G.numpy()[key], Gs.numpy()[key]), key
