@@ -1,0 +1,182 @@
+"""Benchmark: self-consistent second-Born Kadanoff-Baym propagation on one GPU.
+
+Workload (one bench step = the whole hot path once): 4-site open Hubbard
+chain at half filling, spin-symmetric second-Born self-energy + Hartree mean
+field, U ramped linearly 2 -> 1 over t in [0, 5], beta = 20, ntau = 400,
+nt = 1000, h = 0.02, k = 5, complex128. A step is the Matsubara
+self-consistency (with the dense Matsubara solve), the bootstrap of slices
+0..k, and the predictor-corrector time steps k+1..nt (ncorr corrector
+iterations each), all on the device through the C ABI (cntr_solve_2b).
+
+value = Dyson time steps (slices n > k) completed per second of wall time,
+including every corrector iteration. The JSON line also carries the FP64
+rate, the roofline fraction of the history-sum kernel (HIP events on its
+launch stream) and the oracle timed on the host cores as a CPU baseline.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Dyson time-steps/s + FP64 TFLOP/s, batched/adjoint vs plain at <=1e-10 rel err"
+HBM_PEAK_GBS = 8000.0
+
+
+def workload_grid():
+    from paper_1911_01211_amd import workloads as W
+    return W.GridSpec(nt=1000, ntau=400, d=4, sig=-1, k=5, beta=20.0, h=0.02, mu=0.0)
+
+
+def run_gpu(args):
+    import torch
+
+    from paper_1911_01211_amd import contour as K
+    from paper_1911_01211_amd import workloads as W
+
+    g = workload_grid()
+    e0np, Unp = W.hubbard_ramp(g)
+    dev = "cuda:0"
+    G, S, Gs = K.Contour(g, dev), K.Contour(g, dev), K.Contour(g, dev)
+    e0 = torch.as_tensor(e0np).to(dev)
+    U = torch.as_tensor(Unp).to(dev)
+    emf = torch.zeros_like(e0)
+
+    def one_step():
+        G.zero_()
+        S.zero_()
+        return K.solve_2b(G, S, Gs, e0, U, emf, ncorr=args.ncorr, mats_tol=1e-14, mats_mix=0.5,
+                          boot_tol=1e-14)
+
+    stats = None
+    for w in range(args.warmup):
+        stats = one_step()
+        torch.cuda.synchronize()
+        print(f"# warmup {w} done: {stats}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    K.profile_begin()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        stats = one_step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = K.profile_end()
+    elapsed = t1 - t0
+    # physical sanity of the last run: half filling on every site at t_nt
+    L = G.les[-1].cpu().numpy()
+    dens_dev = float(abs((L.diagonal().imag) - 0.5).max())
+    return g, elapsed, prof, stats, dens_dev
+
+
+def cpu_baseline(g, ncorr, mats_iter, budget_s):
+    """The oracle (OpenMP over the independent loops) on a bounded sample of the
+    same workload: one corrector iteration (Sigma_2B + time step) at a few
+    slices n of a history with the workload's shape (seeded random values),
+    one Matsubara solve and one start-up; the full run is assembled from a
+    quadratic fit of the per-slice cost in n."""
+    import numpy as np
+
+    from oracle import oracle as O
+    from paper_1911_01211_amd import workloads as W
+
+    og = O.Grid(g.nt, g.ntau, g.d, g.sig, g.k, g.beta, g.h, g.mu)
+    r = W.rng(900)
+    G, S = O.HM(og), O.HM(og)
+    c = W.random_contour(r, g, 0.3, decay=0.2)
+    for key in ("mat", "ret", "les", "tv"):
+        getattr(G, key)[...] = c[key]
+    c = W.random_contour(r, g, 0.3, decay=0.2)
+    for key in ("mat", "ret", "les", "tv"):
+        getattr(S, key)[...] = c[key]
+    e0, U = W.hubbard_ramp(g)
+    t_start = time.perf_counter()
+    samples = []
+    for n in (g.nt // 5, g.nt // 2, g.nt):
+        t = time.perf_counter()
+        O.sigma_2b(n, G, U, S)
+        O.dyson_timestep(n, G, S, e0, "B")
+        samples.append((n, time.perf_counter() - t))
+        if time.perf_counter() - t_start > budget_s:
+            break
+    ns = np.array([s[0] for s in samples], float)
+    ts = np.array([s[1] for s in samples])
+    coef = np.polyfit(ns, ts, min(2, len(ns) - 1))
+    steps = np.arange(g.k + 1, g.nt + 1)
+    t_steps = ncorr * np.polyval(coef, steps).clip(min=0).sum()
+    t = time.perf_counter()
+    O.dyson_mat(G, S, e0[0])
+    t_mat = time.perf_counter() - t
+    t = time.perf_counter()
+    O.dyson_start(G, S, e0)
+    t_start_up = time.perf_counter() - t
+    total = t_steps + mats_iter * t_mat + 10 * t_start_up
+    return {
+        "value": (g.nt - g.k) / total,
+        "unit": "time-steps/s",
+        "cores": O.num_threads(),
+        "kind": "oracle",
+        "sample": (f"oracle (B) time step + Sigma_2B at n={[s[0] for s in samples]} on a seeded "
+                   f"history of the workload's shape, one {g.ntau + 1}x{g.d} Matsubara solve and "
+                   f"one start-up, timed in {time.perf_counter() - t_start:.1f}s; full run = "
+                   f"{ncorr} x sum_n quadratic-fit t(n) + {mats_iter} Matsubara solves + 10 start-ups "
+                   f"= {total:.1f}s"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--ncorr", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=20.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(the per-GPU share of a sharded run is the single-GPU workload).", file=sys.stderr)
+        sys.exit(2)
+    g, elapsed, prof, stats, dens_dev = run_gpu(args)
+    nsteps = (g.nt - g.k) * args.steps
+    value = nsteps / elapsed
+    hist_gbs = prof["hist_bytes"] / (prof["hist_ms"] * 1e-3) / 1e9 if prof["hist_ms"] > 0 else None
+    tflops = prof["hist_flops"] / elapsed / 1e12
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "time-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c128",
+        "data": "synthetic",
+        "config": {"workload": "second-Born Hubbard chain, 4 sites, U ramp 2->1 on [0,5], "
+                               "beta=20, ntau=400, nt=1000, h=0.02, k=5",
+                   "nt": g.nt, "ntau": g.ntau, "n_orb": g.d, "k": g.k, "h": g.h, "beta": g.beta,
+                   "corrector_iterations": args.ncorr, "mats_iterations": stats.mats_iter,
+                   "boot_iterations": stats.boot_iter},
+        "fp64_tflops": tflops,
+        "time_step_share": prof["step_ms"] / (elapsed * 1e3),
+        "roofline": {"bound": "hbm", "kernel": "k_history<4>", "achieved": hist_gbs,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": (hist_gbs / HBM_PEAK_GBS) if hist_gbs else None, "traffic": None,
+                     "launches": prof["hist_launches"],
+                     "avg_launch_us": prof["hist_ms"] * 1e3 / max(1, prof["hist_launches"])},
+        "check": {"max_density_deviation_at_nt": dens_dev},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(g, args.ncorr, stats.mats_iter, args.cpu_budget)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

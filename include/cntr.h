@@ -148,7 +148,10 @@ cntr_status cntr_copy_slice(int32_t tstp, int32_t count, const cntr_grid* grids,
  * Matsubara loop, bootstrapping over slices 0..k, then predictor-corrector
  * time steps k+1..nt_stop) run by the library on `stream`:
  *   Matsubara : {Hartree, Sigma_2B, Matsubara solve} until the relative
- *               distance is below mats_tol (at most mats_maxit),
+ *               distance is below mats_tol (at most mats_maxit); the new
+ *               input (Sigma^M, eps_mf_{-1}) is mixed with the previous one,
+ *               x <- mats_mix x + (1 - mats_mix) x_prev, 0 < mats_mix <= 1
+ *               (1 = plain iteration), which leaves the fixed point unchanged,
  *   bootstrap : {Hartree, Sigma_2B on 0..k, start-up} until below boot_tol
  *               and at least 3 iterations (at most boot_maxit),
  *   steps     : extrapolation, then `ncorr` corrector iterations
@@ -161,8 +164,29 @@ cntr_status cntr_copy_slice(int32_t tstp, int32_t count, const cntr_grid* grids,
 cntr_status cntr_solve_2b(const cntr_grid* grid, const cntr_gf* G, const cntr_gf* Sigma,
                           const cntr_gf* Gscratch, const void* eps0, const double* U,
                           void* eps_mf, double nbar, int32_t mats_maxit, double mats_tol,
-                          int32_t boot_maxit, double boot_tol, int32_t ncorr, int32_t nt_stop,
-                          double* stats, void* stream);
+                          double mats_mix, int32_t boot_maxit, double boot_tol, int32_t ncorr,
+                          int32_t nt_stop, double* stats, void* stream);
+
+/* ------------------------------------------------------------ profiling --
+ * Device-time accounting of the time step, measured with HIP events
+ * recorded on the stream each kernel is launched on. Between
+ * cntr_profile_begin and cntr_profile_end every time step (n > k) records
+ * events around its history-sum kernel and around the whole step. The
+ * algorithmic counts per history launch at slice n are
+ *   bytes = 16 d^2 [ n(n+1) + n (ntau+1) ]   (every stored R, <, rceil
+ *           history block of slices 0..n-1 once; lesser part only for n > 2k)
+ *   flops = 8 d^3 x (number of d x d block multiply-adds of the sums).
+ * cntr_profile_end synchronizes the device. */
+typedef struct {
+  double hist_ms;       /* summed device time of the history-sum kernel */
+  int64_t hist_launches;
+  double hist_bytes;    /* summed algorithmic bytes of those launches */
+  double hist_flops;    /* summed algorithmic flops of those launches */
+  double step_ms;       /* summed device time of whole time steps */
+  int64_t steps;
+} cntr_profile;
+cntr_status cntr_profile_begin(void);
+cntr_status cntr_profile_end(cntr_profile* out);
 
 /* ------------------------------------------------------------- plumbing -- */
 /* Wait for `stream`; report a failure recorded by kernels since the last

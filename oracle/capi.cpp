@@ -117,8 +117,8 @@ double oracle_distance(int n, const oracle_grid* g, HMARGS(A), HMARGS(B)) {
 // iterations, last mats error, last boot error, max last corrector error.
 int oracle_solve_2b(const oracle_grid* g, HMARGS(G), HMARGS(S), HMARGS(Gold), const void* eps0,
                     const double* U, void* eps_mf, double nbar, int mats_maxit, double mats_tol,
-                    int boot_maxit, double boot_tol, int ncorr, double corr_tol, int nt_stop,
-                    int variant, double* stats) {
+                    double mats_mix, int boot_maxit, double boot_tol, int ncorr, double corr_tol,
+                    int nt_stop, int variant, double* stats) {
   HM G = HMV(g, G), S = HMV(g, S), Go = HMV(g, Gold);
   const cd* e0 = (const cd*)eps0;
   cd* emf = (cd*)eps_mf;
@@ -128,9 +128,21 @@ int oracle_solve_2b(const oracle_grid* g, HMARGS(G), HMARGS(S), HMARGS(Gold), co
   free_mat(G.g, e0, G.mat);
   int it;
   double err = 0.0;
+  size_t bs = (size_t)g->d * g->d, nm = (g->ntau + 1) * bs;
+  std::vector<cd> s_in(nm), e_in(bs);
   for (it = 0; it < mats_maxit; it++) {
     hartree(-1, G, U, e0, emf, nbar);
     sigma_2b(-1, G, U, S);
+    // Reading: the plain Sigma <-> G iteration of the Matsubara loop has an
+    // oscillating unstable mode for strong coupling; linear mixing of the
+    // input (Sigma^M, eps_mf_{-1}) with the previous input keeps the same
+    // fixed point and converges.
+    if (it > 0)
+      for (size_t i = 0; i < nm; i++) S.mat[i] = mats_mix * S.mat[i] + (1.0 - mats_mix) * s_in[i];
+    if (it > 0)
+      for (size_t i = 0; i < bs; i++) emf[i] = mats_mix * emf[i] + (1.0 - mats_mix) * e_in[i];
+    std::copy(S.mat, S.mat + nm, s_in.begin());
+    std::copy(emf, emf + bs, e_in.begin());
     copy_timestep(-1, Go, G);
     ok = dyson_mat(G, S, emf) && ok;
     err = distance_norm2(-1, G, Go) / slice_norm(-1, G);

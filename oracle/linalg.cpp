@@ -50,6 +50,7 @@ bool solve(int n, int nrhs, cd* A, cd* B) {
       for (int q = 0; q < nrhs; q++) std::swap(B[(size_t)p * nrhs + q], B[(size_t)c * nrhs + q]);
     }
     cd piv = A[(size_t)c * n + c];
+#pragma omp parallel for schedule(static) if (n > 256)
     for (int r = c + 1; r < n; r++) {
       cd f = A[(size_t)r * n + c] / piv;
       if (f == cd(0.0, 0.0)) continue;

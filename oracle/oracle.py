@@ -216,8 +216,8 @@ def solve_fixed(G: HM, S: HM, eps, nt_stop=None, variant="B"):
     return rc, secs
 
 
-def solve_2b(G: HM, S: HM, eps0, U, nbar=0.5, mats_maxit=200, mats_tol=1e-14, boot_maxit=100,
-             boot_tol=1e-14, ncorr=6, corr_tol=0.0, nt_stop=None, variant="B"):
+def solve_2b(G: HM, S: HM, eps0, U, nbar=0.5, mats_maxit=200, mats_tol=1e-14, mats_mix=0.5,
+             boot_maxit=100, boot_tol=1e-14, ncorr=6, corr_tol=0.0, nt_stop=None, variant="B"):
     """Self-consistent 2B + Hartree run; returns (rc, eps_mf, stats)."""
     g = G.g
     e0 = np.ascontiguousarray(eps0, np.complex128)
@@ -227,7 +227,8 @@ def solve_2b(G: HM, S: HM, eps0, U, nbar=0.5, mats_maxit=200, mats_tol=1e-14, bo
     nt_stop = g.nt if nt_stop is None else nt_stop
     rc = lib().oracle_solve_2b(C.byref(g.c()), *G.args(), *S.args(), *Gold.args(), _p(e0),
                                _p(np.ascontiguousarray(U, np.float64)), _p(emf), C.c_double(nbar),
-                               mats_maxit, C.c_double(mats_tol), boot_maxit, C.c_double(boot_tol),
+                               mats_maxit, C.c_double(mats_tol), C.c_double(mats_mix), boot_maxit,
+                               C.c_double(boot_tol),
                                ncorr, C.c_double(corr_tol), nt_stop, ord(variant), _p(stats))
     return rc, emf, dict(mats_iter=int(stats[0]), boot_iter=int(stats[1]),
                          corr_total=int(stats[2]), mats_err=stats[3], boot_err=stats[4],

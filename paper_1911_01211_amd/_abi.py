@@ -17,7 +17,8 @@ STATUS = {0: "CNTR_OK", -1: "CNTR_EINVAL", -2: "CNTR_ESHAPE", -3: "CNTR_EORDER",
 
 SYMBOLS = ["cntr_init_matsubara", "cntr_dyson_step", "cntr_convolution", "cntr_sigma_2b",
            "cntr_extrapolate", "cntr_distance", "cntr_copy_slice", "cntr_solve_2b", "cntr_sync",
-           "cntr_last_error", "cntr_finalize", "cntr_version"]
+           "cntr_last_error", "cntr_finalize", "cntr_version", "cntr_profile_begin",
+           "cntr_profile_end"]
 
 
 class CntrError(RuntimeError):
@@ -29,6 +30,11 @@ class CntrError(RuntimeError):
 class Grid(C.Structure):
     _fields_ = [("nt", C.c_int32), ("ntau", C.c_int32), ("d", C.c_int32), ("sig", C.c_int32),
                 ("k", C.c_int32), ("beta", C.c_double), ("h", C.c_double), ("mu", C.c_double)]
+
+
+class Profile(C.Structure):
+    _fields_ = [("hist_ms", C.c_double), ("hist_launches", C.c_int64), ("hist_bytes", C.c_double),
+                ("hist_flops", C.c_double), ("step_ms", C.c_double), ("steps", C.c_int64)]
 
 
 class GF(C.Structure):
@@ -53,9 +59,11 @@ def lib():
         L.cntr_extrapolate.argtypes = [i32, i32, P(Grid), P(GF), vp]
         L.cntr_distance.argtypes = [i32, i32, P(Grid), P(GF), P(GF), P(dbl), vp]
         L.cntr_copy_slice.argtypes = [i32, i32, P(Grid), P(GF), P(GF), vp]
-        L.cntr_solve_2b.argtypes = [P(Grid), P(GF), P(GF), P(GF), vp, vp, vp, dbl, i32, dbl, i32,
-                                    dbl, i32, i32, P(dbl), vp]
+        L.cntr_solve_2b.argtypes = [P(Grid), P(GF), P(GF), P(GF), vp, vp, vp, dbl, i32, dbl, dbl,
+                                    i32, dbl, i32, i32, P(dbl), vp]
         L.cntr_sync.argtypes = [vp]
+        L.cntr_profile_begin.argtypes = []
+        L.cntr_profile_end.argtypes = [P(Profile)]
         L.cntr_last_error.restype = C.c_char_p
         L.cntr_version.restype = C.c_char_p
         for name in SYMBOLS:

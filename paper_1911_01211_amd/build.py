@@ -27,7 +27,7 @@ def build(verbose: bool = False) -> str:
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)
         raise RuntimeError("hipcc failed for libcntr.so")
-    if verbose and r.stderr:
+    if verbose and r.stderr and "error" in r.stderr:
         sys.stderr.write(r.stderr)
     os.replace(tmp, LIB)
     return LIB

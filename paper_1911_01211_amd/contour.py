@@ -116,6 +116,16 @@ def sync(stream=None):
     _abi.check(_abi.lib().cntr_sync(_stream(stream)))
 
 
+def profile_begin():
+    _abi.check(_abi.lib().cntr_profile_begin())
+
+
+def profile_end() -> dict:
+    p = _abi.Profile()
+    _abi.check(_abi.lib().cntr_profile_end(C.byref(p)))
+    return {f: getattr(p, f) for f, _ in _abi.Profile._fields_}
+
+
 @dataclasses.dataclass
 class Solve2BStats:
     mats_iter: int
@@ -125,14 +135,15 @@ class Solve2BStats:
 
 
 def solve_2b(G: Contour, Sigma: Contour, Gscratch: Contour, eps0: torch.Tensor, U: torch.Tensor,
-             eps_mf: torch.Tensor, nbar=0.5, mats_maxit=200, mats_tol=1e-14, boot_maxit=100,
-             boot_tol=1e-14, ncorr=6, nt_stop=None, stream=None) -> Solve2BStats:
+             eps_mf: torch.Tensor, nbar=0.5, mats_maxit=200, mats_tol=1e-14, mats_mix=0.5,
+             boot_maxit=100, boot_tol=1e-14, ncorr=6, nt_stop=None, stream=None) -> Solve2BStats:
     g = G.g
     nt_stop = g.nt if nt_stop is None else nt_stop
     st = (C.c_double * 4)()
     gc = grid_c(g)
     _abi.check(_abi.lib().cntr_solve_2b(C.byref(gc), C.byref(G.gf()), C.byref(Sigma.gf()),
                                         C.byref(Gscratch.gf()), eps0.data_ptr(), U.data_ptr(),
-                                        eps_mf.data_ptr(), nbar, mats_maxit, mats_tol, boot_maxit,
+                                        eps_mf.data_ptr(), nbar, mats_maxit, mats_tol, mats_mix,
+                                        boot_maxit,
                                         boot_tol, ncorr, nt_stop, st, _stream(stream)))
     return Solve2BStats(int(st[0]), int(st[1]), st[2], st[3])

@@ -200,7 +200,7 @@ StepScratch step_layout(const cntr_grid& g) {
   size_t dd = (size_t)g.d * g.d;
   r.sc.off_status = 0;
   r.sc.off_minv = 256;
-  r.sc.off_part = 256 + round256(dd * sizeof(cplx));
+  r.sc.off_part = 256 + round256((KMAX + 3) * dd * sizeof(cplx));
   r.sc.off_tail = r.sc.off_part;
   r.per = r.sc.off_part + round256(step_scratch_bytes(g.nt, g.k, g.ntau, g.d));
   r.sc.stride = r.per;
@@ -217,7 +217,7 @@ long slice_elems(const cntr_grid& g, int n) {
 struct MatsState {
   int N = 0, d = 0;
   cplx *g = nullptr, *K = nullptr, *A = nullptr, *Ainv = nullptr, *r = nullptr, *dx = nullptr,
-       *work = nullptr;
+       *work = nullptr, *smix = nullptr, *emix = nullptr;
   int* piv = nullptr;
   int* status = nullptr;
   double* norms = nullptr;
@@ -231,7 +231,8 @@ struct MatsState {
     if (hipMalloc(&g, bs) || hipMalloc(&K, bs) || hipMalloc(&A, nn) || hipMalloc(&Ainv, nn) ||
         hipMalloc(&r, vec) || hipMalloc(&dx, vec) || hipMalloc(&work, 2 * (size_t)N * sizeof(cplx)) ||
         hipMalloc(&piv, N * sizeof(int)) || hipMalloc(&status, sizeof(int)) ||
-        hipMalloc(&norms, 2 * sizeof(double))) {
+        hipMalloc(&norms, 2 * sizeof(double)) || hipMalloc(&smix, bs) ||
+        hipMalloc(&emix, (size_t)dd * dd * sizeof(cplx))) {
       release();
       return fail(CNTR_ENOMEM, "Matsubara workspace allocation failed");
     }
@@ -239,9 +240,9 @@ struct MatsState {
   }
   void release() {
     for (void* p : {(void*)g, (void*)K, (void*)A, (void*)Ainv, (void*)r, (void*)dx, (void*)work,
-                    (void*)piv, (void*)status, (void*)norms})
+                    (void*)piv, (void*)status, (void*)norms, (void*)smix, (void*)emix})
       if (p) (void)hipFree(p);
-    g = K = A = Ainv = r = dx = work = nullptr;
+    g = K = A = Ainv = r = dx = work = smix = emix = nullptr;
     piv = status = nullptr;
     norms = nullptr;
     have_inv = false;
@@ -313,6 +314,38 @@ extern "C" {
 
 const char* cntr_version(void) { return "cntr-gfx950 0.1"; }
 
+cntr_status cntr_profile_begin(void) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_prof.on = true;
+  g_prof.used = 0;
+  g_prof.rec.clear();
+  return CNTR_OK;
+}
+
+cntr_status cntr_profile_end(cntr_profile* out) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_prof.on = false;
+  cntr_profile p{};
+  for (const ProfRec& r : g_prof.rec) {
+    hipError_t e = hipEventSynchronize(r.after_step);
+    if (e != hipSuccess) return hip_fail(e, "profile event");
+    float a = 0, b = 0;
+    if (hipEventElapsedTime(&a, r.before, r.after_hist) != hipSuccess ||
+        hipEventElapsedTime(&b, r.before, r.after_step) != hipSuccess)
+      return fail(CNTR_EHIP, "profile elapsed time");
+    p.hist_ms += a;
+    p.step_ms += b;
+    p.hist_launches++;
+    p.steps++;
+    p.hist_bytes += r.bytes;
+    p.hist_flops += r.flops;
+  }
+  g_prof.rec.clear();
+  g_prof.used = 0;
+  if (out) *out = p;
+  return CNTR_OK;
+}
+
 const char* cntr_last_error(void) { return g_err.c_str(); }
 
 cntr_status cntr_finalize(void) {
@@ -323,6 +356,10 @@ cntr_status cntr_finalize(void) {
     if (kv.second.red) (void)hipFree(kv.second.red);
   }
   g_scratch.clear();
+  for (hipEvent_t e : g_prof.pool) (void)hipEventDestroy(e);
+  g_prof.pool.clear();
+  g_prof.rec.clear();
+  g_prof.used = 0;
   return CNTR_OK;
 }
 
@@ -531,8 +568,8 @@ cntr_status cntr_distance(int32_t tstp, int32_t count, const cntr_grid* grids, c
 cntr_status cntr_solve_2b(const cntr_grid* grid, const cntr_gf* G, const cntr_gf* Sigma,
                           const cntr_gf* Gscratch, const void* eps0, const double* U,
                           void* eps_mf, double nbar, int32_t mats_maxit, double mats_tol,
-                          int32_t boot_maxit, double boot_tol, int32_t ncorr, int32_t nt_stop,
-                          double* stats, void* stream) {
+                          double mats_mix, int32_t boot_maxit, double boot_tol, int32_t ncorr,
+                          int32_t nt_stop, double* stats, void* stream) {
   if (!grid) return fail(CNTR_ESHAPE, "cntr_solve_2b: null grid");
   cntr_status st = check_grid(*grid, "cntr_solve_2b");
   if (st) return st;
@@ -573,8 +610,13 @@ cntr_status cntr_solve_2b(const cntr_grid* grid, const cntr_gf* G, const cntr_gf
   if ((e = launch_free_mat(P0, P.Gmat, s))) return hip_fail(e, "initial G^M");
   int it = 0;
   double err = 0;
+  if (!(mats_mix > 0 && mats_mix <= 1)) return fail(CNTR_EINVAL, "cntr_solve_2b: mats_mix outside (0,1]");
   for (it = 0; it < mats_maxit; it++) {
     if ((e = launch_sigma2b(pa, -1, d, (int)slice_elems(g, -1), nbar, s))) return hip_fail(e, "Sigma^M");
+    // mix the new input (Sigma^M, eps_mf_{-1}) with the previous one
+    if ((e = launch_mix((g.ntau + 1) * d * d, P.Smat, ms.smix, mats_mix, it == 0, s)) ||
+        (e = launch_mix(d * d, (cplx*)eps_mf, ms.emix, mats_mix, it == 0, s)))
+      return hip_fail(e, "mixing");
     if ((e = launch_copy(po, pa, -1, d, (int)slice_elems(g, -1), s))) return hip_fail(e, "copy");
     if ((st = mats_solve(ms, P, true, 1e-15, 200, s, nullptr))) return st;
     if ((st = distance(-1, dist))) return st;

@@ -5,7 +5,7 @@
 #include <cstddef>
 #include <cstdint>
 
-#include "../../include/cntr.h"
+#include "cntr.h"
 
 namespace cntr {
 

@@ -23,6 +23,8 @@ struct Scratch {
   __device__ inline cplx* part(int pi) const { return (cplx*)(base + pi * stride + off_part); }
   __device__ inline cplx* tail(int pi) const { return (cplx*)(base + pi * stride + off_tail); }
   __device__ inline int* status(int pi) const { return (int*)(base + pi * stride + off_status); }
+  // completion counter of the boundary-row kernel (reset to 0 by its user)
+  __device__ inline int* counter(int pi) const { return (int*)(base + pi * stride + off_status + 64); }
 };
 
 __device__ inline cplx ld(const cplx* p) { return *p; }
@@ -170,6 +172,118 @@ __device__ inline bool lds_solve(int n, int nrhs, cplx* A, cplx* B, double* redv
     __syncthreads();
   }
   return true;
+}
+
+// ------------------------------------------------ single-wavefront solvers
+// Executed by exactly one wavefront (64 lanes); the other waves of the
+// workgroup do not take part. Synchronisation is wave-local (instruction
+// order plus a compiler barrier), never a workgroup barrier.
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Index of the largest v over the wave (ties: smallest index); every lane
+// gets the same answer.
+__device__ inline int wave_argmax(double v, int idx, double* vmax) {
+  for (int off = 32; off > 0; off >>= 1) {
+    double ov = __shfl_xor(v, off);
+    int oi = __shfl_xor(idx, off);
+    if (ov > v || (ov == v && oi < idx)) {
+      v = ov;
+      idx = oi;
+    }
+  }
+  *vmax = v;
+  return idx;
+}
+
+// In-place inverse of an n x n matrix in LDS (Gauss-Jordan, partial pivoting).
+// piv: LDS int[n]. Returns false if singular (the matrix is then garbage).
+__device__ inline bool wave_inverse(int n, cplx* A, int* piv) {
+  int lane = threadIdx.x & 63;
+  bool ok = true;
+  for (int c = 0; c < n; c++) {
+    double best;
+    int p = wave_argmax((lane >= c && lane < n) ? abs2(A[lane * n + c]) : -1.0, lane, &best);
+    if (!(best > 0)) ok = false;
+    if (lane == 0) piv[c] = p;
+    if (p != c)
+      for (int q = lane; q < n; q += 64) {
+        cplx t = A[p * n + q];
+        A[p * n + q] = A[c * n + q];
+        A[c * n + q] = t;
+      }
+    wave_sync();
+    cplx ipv = best > 0 ? cdiv(mk(1, 0), A[c * n + c]) : mk(0, 0);
+    for (int idx = lane; idx < n * n; idx += 64) {
+      int r = idx / n, q = idx % n;
+      if (r == c || q == c) continue;
+      A[idx] = A[idx] - A[r * n + c] * (A[c * n + q] * ipv);
+    }
+    wave_sync();
+    for (int r = lane; r < n; r += 64)
+      if (r != c) A[r * n + c] = -(A[r * n + c] * ipv);
+    for (int q = lane; q < n; q += 64) A[c * n + q] = (q == c) ? ipv : A[c * n + q] * ipv;
+    wave_sync();
+  }
+  for (int c = n - 1; c >= 0; c--) {
+    int p = piv[c];
+    if (p != c)
+      for (int r = lane; r < n; r += 64) {
+        cplx t = A[r * n + p];
+        A[r * n + p] = A[r * n + c];
+        A[r * n + c] = t;
+      }
+    wave_sync();
+  }
+  return ok;
+}
+
+// Solve A X = B in LDS (A: n x n, B: n x nrhs), Gaussian elimination with
+// partial pivoting and back substitution; A and B are overwritten.
+__device__ inline bool wave_solve(int n, int nrhs, cplx* A, cplx* B) {
+  int lane = threadIdx.x & 63;
+  bool ok = true;
+  for (int c = 0; c < n; c++) {
+    double best;
+    int p = wave_argmax((lane >= c && lane < n) ? abs2(A[lane * n + c]) : -1.0, lane, &best);
+    if (!(best > 0)) ok = false;
+    if (p != c) {
+      for (int q = lane; q < n; q += 64) {
+        cplx t = A[p * n + q];
+        A[p * n + q] = A[c * n + q];
+        A[c * n + q] = t;
+      }
+      for (int q = lane; q < nrhs; q += 64) {
+        cplx t = B[p * nrhs + q];
+        B[p * nrhs + q] = B[c * nrhs + q];
+        B[c * nrhs + q] = t;
+      }
+    }
+    wave_sync();
+    cplx ipv = best > 0 ? cdiv(mk(1, 0), A[c * n + c]) : mk(0, 0);
+    int w = n - c - 1, cols = w + nrhs;
+    for (int idx = lane; idx < w * cols; idx += 64) {
+      int r = c + 1 + idx / cols, q = idx % cols;
+      cplx f = A[r * n + c] * ipv;
+      if (q < w) A[r * n + c + 1 + q] = A[r * n + c + 1 + q] - f * A[c * n + c + 1 + q];
+      else B[r * nrhs + q - w] = B[r * nrhs + q - w] - f * B[c * nrhs + q - w];
+    }
+    wave_sync();
+  }
+  for (int c = n - 1; c >= 0; c--) {
+    cplx ipv = cdiv(mk(1, 0), A[c * n + c]);
+    for (int q = lane; q < nrhs; q += 64) B[c * nrhs + q] = B[c * nrhs + q] * ipv;
+    wave_sync();
+    for (int idx = lane; idx < c * nrhs; idx += 64) {
+      int r = idx / nrhs, q = idx % nrhs;
+      B[r * nrhs + q] = B[r * nrhs + q] - A[r * n + c] * B[c * nrhs + q];
+    }
+    wave_sync();
+  }
+  return ok;
 }
 
 }  // namespace cntr

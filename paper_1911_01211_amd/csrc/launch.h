@@ -1,11 +1,13 @@
 // Host-side launch interface between the C ABI layer (api.cpp) and the
 // kernel files. All functions enqueue on `s` and return a hipError_t.
 #pragma once
+#include <vector>
+
 #include "dev_common.h"
 
 namespace cntr {
 
-constexpr int NJOB = 6;  // history jobs of one time step
+constexpr int NJOB = 7;  // history jobs of one time step
 
 // Work plan of one time step n (identical for every problem of the call).
 struct HistPlan {
@@ -17,12 +19,25 @@ struct HistPlan {
   int mtiles[NJOB];
   int wg_off[NJOB + 1];
   long part_off[NJOB];  // in blocks
-  // tail (lesser boundary rows) plan
-  int tail_nch[3];
-  int tail_mtiles;
-  int tail_wg_off[4];
-  long tail_off[3];  // in blocks
+  // reduce tiles of the retarded, mixing and lesser rows; partial sums of
+  // the lesser boundary rows, one set per reduce tile
+  int red_tiles[3];
+  long tail_off;      // in blocks
+  long total_blocks;  // scratch blocks of the step
 };
+
+// event-based device timing of time steps (cntr_profile_begin/end)
+struct ProfRec {
+  hipEvent_t before, after_hist, after_step;
+  double bytes, flops;
+};
+struct ProfState {
+  bool on = false;
+  std::vector<hipEvent_t> pool;
+  size_t used = 0;
+  std::vector<ProfRec> rec;
+};
+extern ProfState g_prof;
 
 int hist_tj(int d);
 int hist_tm(int d);
@@ -54,6 +69,7 @@ hipError_t launch_gj_inverse(int N, cplx* Amat, cplx* work, int* piv, int* statu
 // y = X v  (X: N x N, v, y: N x nrhs); y = b - X v when b != nullptr
 hipError_t launch_matvec(int N, int nrhs, const cplx* X, const cplx* v, const cplx* b, cplx* y,
                          hipStream_t s);
+hipError_t launch_mix(int len, cplx* x, cplx* keep, double a, bool first, hipStream_t s);
 hipError_t launch_axpy_norm(int len, cplx* x, const cplx* dx, const cplx* r, const cplx* g,
                             double* norms, hipStream_t s);
 

@@ -280,4 +280,20 @@ hipError_t launch_axpy_norm(int len, cplx* x, const cplx* dx, const cplx* r, con
   return hipGetLastError();
 }
 
+// Linear mixing of a self-consistency input with the previous input:
+// x <- a x + (1-a) keep (unless first), keep <- x.
+__global__ __launch_bounds__(NT3) void k_mix(int len, cplx* x, cplx* keep, double a, int first) {
+  long i = (long)blockIdx.x * NT3 + threadIdx.x;
+  if (i >= len) return;
+  cplx v = x[i];
+  if (!first) v = a * v + (1.0 - a) * keep[i];
+  x[i] = v;
+  keep[i] = v;
+}
+
+hipError_t launch_mix(int len, cplx* x, cplx* keep, double a, bool first, hipStream_t s) {
+  k_mix<<<(len + NT3 - 1) / NT3, NT3, 0, s>>>(len, x, keep, a, first ? 1 : 0);
+  return hipGetLastError();
+}
+
 }  // namespace cntr

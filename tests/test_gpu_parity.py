@@ -249,6 +249,75 @@ def test_solve_2b_parity(O):
     assert relerr(emf.cpu().numpy(), emf_o) < TOL
 
 
+# ------------------------------------------- full sizes of the bench workload
+FULL = W.GridSpec(nt=1000, ntau=400, d=4, sig=-1, k=5, beta=20.0, h=0.02, mu=0.0)
+
+
+def test_full_size_time_step(O):
+    """The step at the benchmark's full size (nt = 1000, ntau = 400, d = 4) on a
+    seeded history, at the last slices, in the bench's launch configuration."""
+    require_gpu()
+    g = FULL
+    r = W.rng(107)
+    G = W.random_contour(r, g, 0.3, decay=0.2)
+    S = W.random_contour(r, g, 0.3, decay=0.2)
+    eps, _ = W.hubbard_ramp(g)
+    Sd, e = K.Contour(g, data=S), to_dev(eps)
+    for n in (g.nt - 1, g.nt):
+        say(f"full-size step n={n}")
+        Go = ora(O, g, G)
+        assert O.dyson_timestep(n, Go, ora(O, g, S), eps, "B") == 0
+        Gd = K.Contour(g, data=G)
+        K.dyson_step(n, [Gd], [Sd], [e])
+        K.sync()
+        got = Gd.numpy()
+        ref = {key: getattr(Go, key) for key in K.KEYS}
+        assert_slices(g, got, ref, [n], what="full-size step")
+
+
+def test_full_size_matsubara(O):
+    require_gpu()
+    say("full-size Matsubara")
+    g = FULL
+    r = W.rng(108)
+    S = W.random_contour(W.rng(108), dataclasses.replace(g, nt=6), 0.1)
+    eps, _ = W.hubbard_ramp(g)
+    gs = dataclasses.replace(g, nt=6)
+    Go = ora(O, gs, None)
+    O.dyson_mat(Go, ora(O, gs, S), eps[0])
+    Gd = K.Contour(gs)
+    K.init_matsubara([Gd], [K.Contour(gs, data=S)], [to_dev(eps[:gs.nt + 2])])
+    K.sync()
+    assert relerr(Gd.mat.cpu().numpy(), Go.mat) < TOL
+    assert r is not None
+
+
+def test_full_size_2b_prefix(O):
+    """Self-consistent 2B on the benchmark's full grid (arrays for nt = 1000,
+    ntau = 400) stopped after 24 slices, against the oracle run of length 24
+    (slices n <= 24 do not depend on later input)."""
+    require_gpu()
+    say("full-size 2B prefix")
+    g = FULL
+    nstop = 24
+    e0, U = W.hubbard_ramp(g)
+    gs = dataclasses.replace(g, nt=nstop)
+    Go, So = ora(O, gs, None), ora(O, gs, None)
+    rc, emf_o, st = O.solve_2b(Go, So, e0[:nstop + 2], U[:nstop + 2], ncorr=5)
+    assert rc == 0
+    Gd, Sd, Gs = K.Contour(g), K.Contour(g), K.Contour(g)
+    e0d, Ud = to_dev(e0), to_dev(U)
+    emf = torch.zeros_like(e0d)
+    sd = K.solve_2b(Gd, Sd, Gs, e0d, Ud, emf, ncorr=5, nt_stop=nstop)
+    K.sync()
+    say(f"oracle {st} gpu {sd}")
+    got = Gd.numpy()
+    ref = {key: getattr(Go, key) for key in K.KEYS}
+    assert_slices(gs, {"mat": got["mat"], **{k: got[k] for k in ("ret", "les", "tv")}}, ref,
+                  [-1] + list(range(nstop + 1)), what="2B prefix")
+    assert relerr(emf.cpu().numpy()[:nstop + 2], emf_o) < TOL
+
+
 # ------------------------------------------------------------ batching
 def test_batch_matches_single_instances(O):
     require_gpu()
