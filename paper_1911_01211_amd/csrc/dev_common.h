@@ -286,4 +286,94 @@ __device__ inline bool wave_solve(int n, int nrhs, cplx* A, cplx* B) {
   return ok;
 }
 
+// ------------------------------------------- register-resident wave solves
+// Maximum of an unsigned value over the 64 lanes (DPP butterfly inside each
+// row of 16 lanes, then row broadcasts; the total ends in lane 63).
+__device__ inline unsigned wave_umax(unsigned v) {
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp((int)v, (int)v, 0xB1, 0xF, 0xF, false));   // quad [1,0,3,2]
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x4E, 0xF, 0xF, false));   // quad [2,3,0,1]
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x141, 0xF, 0xF, false));  // row half mirror
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x140, 0xF, 0xF, false));  // row mirror
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x142, 0xA, 0xF, false));  // row bcast 15
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x143, 0xC, 0xF, false));  // row bcast 31
+  return (unsigned)__builtin_amdgcn_readlane((int)v, 63);
+}
+
+// Value of x held by lane l (l uniform over the wave).
+__device__ inline double rdlane(double x, int l) {
+  long long b = __double_as_longlong(x);
+  int lo = __builtin_amdgcn_readlane((int)(unsigned)(b & 0xffffffffll), l);
+  int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+__device__ inline cplx rdlane(cplx x, int l) { return mk(rdlane(x.x, l), rdlane(x.y, l)); }
+
+// Gauss-Jordan elimination with partial pivoting of an N x N system, one row
+// per lane: lane r < N holds row r of A (a[0..N), zero beyond) and of the
+// right-hand sides B (b). Each step picks the unused row with the largest
+// |a_c| (magnitudes compared in single precision, ties to the lowest lane),
+// broadcasts it with readlane and eliminates column c from every other row.
+// On return the lane that pivoted column `col` holds row `col` of A^-1 B in b.
+// Returns false if a pivot was zero (the result is then garbage). Executed by
+// one wavefront; lanes >= N take part but never pivot.
+template <int NM, int NR>
+__device__ inline bool lane_gauss_jordan(int N, cplx (&a)[NM], cplx (&b)[NR], int& col) {
+  int lane = threadIdx.x & 63;
+  bool used = lane >= N;
+  bool ok = true;
+  cplx piv = mk(1, 0);
+  col = -1;
+#pragma unroll
+  for (int c = 0; c < NM; c++) {
+    if (c < N) {
+      float fv = (float)abs2(a[c]);
+      unsigned key = used ? 0u : ((__float_as_uint(fv) & ~63u) | (unsigned)(63 - lane));
+      unsigned kmax = wave_umax(key);
+      int p = 63 - (int)(kmax & 63u);
+      cplx pv = rdlane(a[c], p);
+      if (!(abs2(pv) > 0)) ok = false;
+      cplx ipv = ok ? cdiv(mk(1, 0), pv) : mk(0, 0);
+      cplx f = a[c] * ipv;
+      bool me = lane == p;
+      if (me) {
+        used = true;
+        col = c;
+        piv = pv;
+      }
+#pragma unroll
+      for (int q = c + 1; q < NM; q++) {
+        cplx t = rdlane(a[q], p);
+        if (!me) a[q] = a[q] - f * t;
+      }
+#pragma unroll
+      for (int q = 0; q < NR; q++) {
+        cplx t = rdlane(b[q], p);
+        if (!me) b[q] = b[q] - f * t;
+      }
+    }
+  }
+  cplx ip = cdiv(mk(1, 0), piv);
+#pragma unroll
+  for (int q = 0; q < NR; q++) b[q] = b[q] * ip;
+  return ok;
+}
+
+// Gregory weights w(N, j), N > k, from a copy of the end weights in LDS
+// (per-lane indices never reach constant or private memory in the loops).
+struct WReg {
+  const double* om;  // LDS, KMAX + 1 entries
+  int k;
+  // every thread of the workgroup calls this before a barrier
+  __device__ inline void load(const KW& W, double* lds_om) {
+    k = W.k;
+    if (threadIdx.x <= KMAX) lds_om[threadIdx.x] = W.omega[threadIdx.x];
+    om = lds_om;
+  }
+  __device__ inline double w(int N, int j) const {
+    bool left = j <= k, right = N - j <= k;
+    double wl = om[left ? j : 0], wr = om[right ? N - j : 0];
+    return left ? (right ? wl + wr - 1.0 : wl) : (right ? wr : 1.0);
+  }
+};
+
 }  // namespace cntr

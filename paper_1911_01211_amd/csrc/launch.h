@@ -13,7 +13,7 @@ constexpr int NJOB = 7;  // history jobs of one time step
 struct HistPlan {
   int n;
   int njob;
-  int TJ, TM;
+  int TJ, TM, TJS;  // term chunk, outputs per tile, tau-source chunk
   int mout[NJOB];
   int nch[NJOB];
   int mtiles[NJOB];

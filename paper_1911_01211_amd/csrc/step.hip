@@ -22,8 +22,11 @@ namespace cntr {
 
 constexpr int NTHR = 256;
 
-int hist_tm(int d) { return NTHR / (d * d) > 0 ? NTHR / (d * d) : 1; }
+// d <= 4: one output block per lane (64 outputs per workgroup); larger d:
+// one output element per thread
+int hist_tm(int d) { return d <= 4 ? 64 : (NTHR / (d * d) > 0 ? NTHR / (d * d) : 1); }
 int hist_tj(int d) { return d >= 8 ? 32 : 64; }
+static int hist_tjs(int d) { return d <= 4 ? 16 : (d >= 8 ? 16 : 32); }
 
 static int cdiv_i(int a, int b) { return (a + b - 1) / b; }
 
@@ -32,6 +35,7 @@ HistPlan make_plan(int n, int k, int ntau, int d) {
   p.n = n;
   p.TJ = hist_tj(d);
   p.TM = hist_tm(d);
+  p.TJS = hist_tjs(d);
   int nb = n - k;  // bulk outputs m = 0..n-k-1
   bool les_bulk = n >= 2 * k + 1;
   p.njob = NJOB;
@@ -42,7 +46,7 @@ HistPlan make_plan(int n, int k, int ntau, int d) {
   p.wg_off[0] = 0;
   for (int j = 0; j < NJOB; j++) {
     p.mout[j] = mout[j];
-    int tj = j == 2 ? (d >= 8 ? 16 : 32) : p.TJ;  // tau-source chunk
+    int tj = j == 2 ? p.TJS : p.TJ;  // tau-source chunk
     p.nch[j] = mout[j] > 0 ? cdiv_i(span[j], tj) : 0;
     p.mtiles[j] = mout[j] > 0 ? cdiv_i(mout[j], p.TM) : 0;
     if (j == 6) p.nch[j] = p.mtiles[j] = 1;  // one workgroup: both tau ends
@@ -52,9 +56,11 @@ HistPlan make_plan(int n, int k, int ntau, int d) {
   }
   // reduce tiles (retarded, mixing, lesser) and the per-tile partial sums of
   // the k+1 lesser boundary rows
-  p.red_tiles[0] = cdiv_i(nb, p.TM);
-  p.red_tiles[1] = cdiv_i(ntau + 1, p.TM);
-  p.red_tiles[2] = les_bulk ? cdiv_i(nb, p.TM) : 0;
+  // (k_reduce: one output element per thread, NTHR / d^2 outputs per tile)
+  int rtm = NTHR / (d * d) > 0 ? NTHR / (d * d) : 1;
+  p.red_tiles[0] = cdiv_i(nb, rtm);
+  p.red_tiles[1] = cdiv_i(ntau + 1, rtm);
+  p.red_tiles[2] = les_bulk ? cdiv_i(nb, rtm) : 0;
   p.tail_off = off;
   off += (long)(p.red_tiles[0] + p.red_tiles[1] + p.red_tiles[2]) * (k + 1);
   p.total_blocks = off;
@@ -124,6 +130,60 @@ __device__ void prep_step(const Prob& P, const Scratch& sc, int pi, int n, cplx*
     if (x == y) v.x += W.a[0] / h;
     return v;
   };
+  if constexpr (D <= 4) {
+    // register-resident solves, one system per wavefront
+    if (wave == 0) {
+      // retarded boundary (transposed conjugate start-up): row r = (p-1)D + y
+      // of  sum_l C_{l,p}^T Y_l^T = i C_{0,p}^T  with
+      // C_{l,p}[x][y] = h^-1 D_{p,l} delta_xy + delta_pl i e_{n-p} + i h s_{p,l} Sigma~^R_{n-l,n-p}
+      constexpr int NM = KMAX * D;
+      cplx a[NM], bb[D];
+      bool row = lane < N;
+      int p = row ? lane / D + 1 : 1, y = lane % D;
+      auto Cv = [&](int l, int x) -> cplx {
+        cplx v = (h * W.s[p][l]) * mul_i(sig(k - l, k - p, x, y));
+        if (p == l) v = v + mul_i(ew[(k - p) * DD + x * D + y]);
+        if (x == y) v.x += W.D[p][l] / h;
+        return v;
+      };
+#pragma unroll
+      for (int q = 0; q < NM; q++) a[q] = (row && q < N) ? Cv(q / D + 1, q % D) : mk(0, 0);
+#pragma unroll
+      for (int cc = 0; cc < D; cc++) bb[cc] = row ? mul_i(Cv(0, cc)) : mk(0, 0);
+      int col;
+      bool ok = lane_gauss_jordan<NM, D>(N, a, bb, col);
+      if (!ok && lane == 0) atomicExch(sc.status(pi), CNTR_ESINGULAR);
+      // unknown col = (l-1) D + c2 holds R_{n,n-l}[cc][c2] in bb[cc]
+      if (row && col >= 0) {
+        int l = col / D + 1, c2 = col % D;
+#pragma unroll
+        for (int cc = 0; cc < D; cc++) P.Gret[(tri(n) + n - l) * DD + cc * D + c2] = bb[cc];
+      }
+      if (lane < DD) P.Gret[(tri(n) + n) * DD + lane] = (lane / D == lane % D) ? mk(0, -1) : mk(0, 0);
+    } else {
+      // M_R^-1 (wave 1) and, for n >= 2k+1, the inverted step matrices of the
+      // lesser boundary rows m = n-k..n (all three waves)
+      for (int r = wave - 2; r <= k; r += 3) {
+        if (r < 0 || n >= 2 * k + 1) {
+          int i = r < 0 ? k : r;
+          cplx a[D], bb[D];
+#pragma unroll
+          for (int q = 0; q < D; q++) {
+            a[q] = lane < D ? stepmat(i, lane * D + q) : mk(0, 0);
+            bb[q] = (lane == q) ? mk(1, 0) : mk(0, 0);
+          }
+          int col;
+          bool ok = lane_gauss_jordan<D, D>(D, a, bb, col);
+          if (!ok && lane == 0) atomicExch(sc.status(pi), CNTR_ESINGULAR);
+          cplx* dst = sc.minv(pi) + (r < 0 ? 0 : (1 + r) * DD);
+          if (lane < D && col >= 0)
+#pragma unroll
+            for (int q = 0; q < D; q++) dst[col * D + q] = bb[q];
+        }
+      }
+    }
+    return;
+  }
   if (wave == 0) {
     // M_R = step matrix of row n and its inverse
     cplx* mr = mw;
@@ -285,6 +345,277 @@ __device__ void tau_boundary(const Prob& P, const Scratch& sc, int pi, int n, co
   }
 }
 
+// ------------------------------------------- HISTORY, one block per lane
+// For d <= 4 every lane owns one output block. The four waves of a workgroup
+// share a tile of 64 consecutive outputs and split the chunk's terms
+// (interleaved); a lane reads whole d x d history blocks (d^2 independent
+// loads per term, the next term's block prefetched into registers). The
+// operand shared by the tile (the Sigma row of slice n, or G^M) is staged in
+// LDS; the four waves' sums are added in a fixed order through LDS.
+
+// acc += conj(x y)
+__device__ inline void cfma_cc(cplx& acc, cplx x, cplx y) {
+  acc.x = fma(x.x, y.x, acc.x);
+  acc.x = fma(-x.y, y.y, acc.x);
+  acc.y = fma(-x.x, y.y, acc.y);
+  acc.y = fma(-x.y, y.x, acc.y);
+}
+
+template <int DD>
+__device__ inline void ld_blk(cplx (&h)[DD], const cplx* p) {
+#pragma unroll
+  for (int e = 0; e < DD; e++) h[e] = p[e];
+}
+
+// acc += w S H  (S shared, in LDS)
+template <int D>
+__device__ inline void f_left(cplx (&acc)[D * D], double w, const cplx* S, const cplx (&H)[D * D]) {
+#pragma unroll
+  for (int a = 0; a < D; a++)
+#pragma unroll
+    for (int q = 0; q < D; q++) {
+      cplx s = w * S[a * D + q];
+#pragma unroll
+      for (int c = 0; c < D; c++) cfma(acc[a * D + c], s, H[q * D + c]);
+    }
+}
+// acc += w H S
+template <int D>
+__device__ inline void f_right(cplx (&acc)[D * D], double w, const cplx* S, const cplx (&H)[D * D]) {
+#pragma unroll
+  for (int q = 0; q < D; q++)
+#pragma unroll
+    for (int c = 0; c < D; c++) {
+      cplx s = w * S[q * D + c];
+#pragma unroll
+      for (int a = 0; a < D; a++) cfma(acc[a * D + c], H[a * D + q], s);
+    }
+}
+// acc += w H' S with H' = -H^dag
+template <int D>
+__device__ inline void f_right_t(cplx (&acc)[D * D], double w, const cplx* S, const cplx (&H)[D * D]) {
+#pragma unroll
+  for (int q = 0; q < D; q++)
+#pragma unroll
+    for (int c = 0; c < D; c++) {
+      cplx s = (-w) * S[q * D + c];
+#pragma unroll
+      for (int a = 0; a < D; a++) cfma_cb(acc[a * D + c], s, H[q * D + a]);
+    }
+}
+// acc += w H S^dag
+template <int D>
+__device__ inline void f_right_c(cplx (&acc)[D * D], double w, const cplx* S, const cplx (&H)[D * D]) {
+#pragma unroll
+  for (int c = 0; c < D; c++)
+#pragma unroll
+    for (int q = 0; q < D; q++) {
+      cplx s = w * S[c * D + q];
+#pragma unroll
+      for (int a = 0; a < D; a++) cfma_cb(acc[a * D + c], H[a * D + q], s);
+    }
+}
+// acc += w H' S^dag with H' = -H^dag
+template <int D>
+__device__ inline void f_right_tc(cplx (&acc)[D * D], double w, const cplx* S, const cplx (&H)[D * D]) {
+#pragma unroll
+  for (int c = 0; c < D; c++)
+#pragma unroll
+    for (int q = 0; q < D; q++) {
+      cplx s = (-w) * S[c * D + q];
+#pragma unroll
+      for (int a = 0; a < D; a++) cfma_cc(acc[a * D + c], H[q * D + a], s);
+    }
+}
+
+// Terms j = jb, jb+4, ... < je of one lane: addr(j) gives the history block
+// (nullptr when the term does not apply to this lane), add(j, H) accumulates.
+template <int D, class Addr, class Add>
+__device__ inline void term_loop(int jb, int je, Addr addr, Add add) {
+  constexpr int DD = D * D;
+  cplx hc[DD], hn[DD];
+  int j = jb;
+  const cplx* pc = j < je ? addr(j) : nullptr;
+  if (pc) ld_blk<DD>(hc, pc);
+  while (j < je) {
+    int jn = j + 4;
+    const cplx* pn = jn < je ? addr(jn) : nullptr;
+    if (pn) ld_blk<DD>(hn, pn);
+    if (pc) add(j, hc);
+#pragma unroll
+    for (int e = 0; e < DD; e++) hc[e] = hn[e];
+    pc = pn;
+    j = jn;
+  }
+}
+
+// Adds the four waves' sums (fixed order) and writes the partial of each
+// output of the tile. red: LDS, 3 * DD * 64 blocks.
+template <int D>
+__device__ inline void wave_sum_store(cplx (&acc)[D * D], cplx* red, bool valid, cplx* dst) {
+  constexpr int DD = D * D;
+  int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  __syncthreads();
+  if (wave > 0)
+#pragma unroll
+    for (int e = 0; e < DD; e++) red[((wave - 1) * DD + e) * 64 + lane] = acc[e];
+  __syncthreads();
+  if (wave == 0 && valid)
+#pragma unroll
+    for (int e = 0; e < DD; e++)
+      dst[e] = ((acc[e] + red[e * 64 + lane]) + red[(DD + e) * 64 + lane]) + red[(2 * DD + e) * 64 + lane];
+}
+
+template <int D>
+__device__ void hist_blk(const Prob& P, const Scratch& sc, int pi, int n, const HistPlan& pl, int job,
+                         int mt, int ch, cplx* lds) {
+  constexpr int DD = D * D;
+  const KW& W = c_kw[P.k];
+  __shared__ double s_om[KMAX + 1];
+  WReg wr;
+  wr.load(W, s_om);
+  int k = P.k, ntau = P.ntau, tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  int TJ = pl.TJ, mout = pl.mout[job];
+  int mlo = mt * 64, mhi = min(mlo + 64, mout) - 1;
+  int m = mlo + lane;
+  bool valid = m < mout;
+  int j0 = ch * TJ;
+  if (job == 0 && j0 + TJ - 1 < mlo) return;
+  if (job == 4 && j0 > max(mhi, k)) return;
+  cplx* sh = lds;
+  size_t T1 = (size_t)n * (ntau + 1);
+  for (int idx = tid; idx < TJ * DD; idx += NTHR) {
+    int jj = idx / DD, ee = idx % DD, j = j0 + jj;
+    cplx v = mk(0, 0);
+    switch (job) {
+      case 0:
+      case 1:
+      case 3:
+        if (j < n) v = P.Sret[(tri(n) + j) * DD + ee];
+        break;
+      case 4:
+        if (j <= n) v = P.Sles[(tri(n) + j) * DD + ee];
+        break;
+      case 5:
+        if (j <= ntau) v = P.Stv[((size_t)T1 + ntau - j) * DD + ee];
+        break;
+    }
+    sh[idx] = v;
+  }
+  __syncthreads();
+  cplx acc[DD];
+#pragma unroll
+  for (int e = 0; e < DD; e++) acc[e] = mk(0, 0);
+  int jb = j0 + wave;
+  double xi = P.sig;
+  if (valid) {
+    switch (job) {
+      case 0: {  // retarded bulk: sum_j w(n-m, j-m) S^R_{n,j} R_{j,m}
+        int je = min(n, j0 + TJ);
+        term_loop<D>(
+            jb, je, [&](int j) -> const cplx* { return j >= m ? P.Gret + (tri(j) + m) * DD : nullptr; },
+            [&](int j, const cplx(&H)[DD]) { f_left<D>(acc, wr.w(n - m, j - m), sh + (j - j0) * DD, H); });
+      } break;
+      case 1: {  // left-mixing history: sum_j w(n,j) S^R_{n,j} T_{j,m}
+        int je = min(n, j0 + TJ);
+        term_loop<D>(
+            jb, je, [&](int j) -> const cplx* { return P.Gtv + ((size_t)j * (ntau + 1) + m) * DD; },
+            [&](int j, const cplx(&H)[DD]) { f_left<D>(acc, wr.w(n, j), sh + (j - j0) * DD, H); });
+      } break;
+      case 3: {  // lesser history: sum_l w(n,l) L^_{m,l} (S^R_{n,l})^dag
+        int je = min(n, j0 + TJ);
+        term_loop<D>(
+            jb, je,
+            [&](int l) -> const cplx* {
+              return l >= m ? P.Gles + (tri(l) + m) * DD : P.Gles + (tri(m) + l) * DD;
+            },
+            [&](int l, const cplx(&H)[DD]) {
+              if (l >= m) f_right_c<D>(acc, wr.w(n, l), sh + (l - j0) * DD, H);
+              else f_right_tc<D>(acc, wr.w(n, l), sh + (l - j0) * DD, H);
+            });
+      } break;
+      case 4: {  // source C^<_1[G,1,Sigma](m,n): sum_j w(m,j) R~_{m,j} S^<_{j,n}
+        int jmax = m > k ? m : k;
+        int je = min(max(mhi, k) + 1, j0 + TJ);
+        term_loop<D>(
+            jb, je,
+            [&](int j) -> const cplx* {
+              if (j > jmax) return nullptr;
+              return j <= m ? P.Gret + (tri(m) + j) * DD : P.Gret + (tri(j) + m) * DD;
+            },
+            [&](int j, const cplx(&H)[DD]) {
+              double w = m > k ? wr.w(m, j) : W.s[m][j];
+              if (j <= m) f_right<D>(acc, w, sh + (j - j0) * DD, H);
+              else f_right_t<D>(acc, w, sh + (j - j0) * DD, H);
+            });
+      } break;
+      case 5: {  // source C^<_3 without -i: sum_j (-xi) w(ntau,j) T_{m,j} (S^rceil_{n,ntau-j})^dag
+        int je = min(ntau + 1, j0 + TJ);
+        term_loop<D>(
+            jb, je, [&](int j) -> const cplx* { return P.Gtv + ((size_t)m * (ntau + 1) + j) * DD; },
+            [&](int j, const cplx(&H)[DD]) {
+              f_right_c<D>(acc, -xi * wr.w(ntau, j), sh + (j - j0) * DD, H);
+            });
+      } break;
+    }
+  }
+  wave_sum_store<D>(acc, lds, valid, sc.part(pi) + (pl.part_off[job] + (long)ch * mout + m) * DD);
+}
+
+// Tau source (Gregory parts of Eqs. ctv2, ctv3), one output block per lane:
+//   sum_J xi w(m,J) Sigma^rceil_{n,m-J} G^M_{ntau-J}        (m > k, J <= m)
+//   sum_J w(ntau-m, J-m) Sigma^rceil_{n,J} G^M_{J-m}        (m < ntau-k, J >= m)
+// The operands indexed by J alone are staged in LDS, the banded ones are read
+// per lane from the (cache-resident) Sigma row and G^M.
+template <int D>
+__device__ void tau_blk(const Prob& P, const Scratch& sc, int pi, int n, const HistPlan& pl, int mt, int ch,
+                        cplx* lds) {
+  constexpr int DD = D * D;
+  const KW& W = c_kw[P.k];
+  __shared__ double s_om[KMAX + 1];
+  WReg wr;
+  wr.load(W, s_om);
+  int k = P.k, ntau = P.ntau, tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  int TJS = pl.TJS;
+  int m = mt * 64 + lane;
+  bool valid = m <= ntau;
+  int j0 = ch * TJS;
+  const cplx* Srow = P.Stv + (size_t)n * (ntau + 1) * DD;
+  cplx* sA = lds;             // Sigma^rceil_{n,J}
+  cplx* sB = lds + TJS * DD;  // G^M_{ntau-J}
+  for (int idx = tid; idx < TJS * DD; idx += NTHR) {
+    int J = j0 + idx / DD, ee = idx % DD;
+    bool in = J <= ntau;
+    sA[idx] = in ? Srow[(size_t)J * DD + ee] : mk(0, 0);
+    sB[idx] = in ? P.Gmat[(size_t)(ntau - J) * DD + ee] : mk(0, 0);
+  }
+  __syncthreads();
+  cplx acc[DD];
+#pragma unroll
+  for (int e = 0; e < DD; e++) acc[e] = mk(0, 0);
+  double xi = P.sig;
+  if (valid) {
+    int je = min(ntau + 1, j0 + TJS);
+    // band 1: per-lane left operand Sigma^rceil_{n,m-J}, shared right G^M_{ntau-J}
+    if (m > k)
+      term_loop<D>(
+          j0 + wave, min(je, m + 1), [&](int J) -> const cplx* { return Srow + (size_t)(m - J) * DD; },
+          [&](int J, const cplx(&H)[DD]) {
+            // acc += xi w(m,J) H G^M_{ntau-J}
+            f_right<D>(acc, xi * wr.w(m, J), sB + (J - j0) * DD, H);
+          });
+    // band 2: shared left Sigma^rceil_{n,J}, per-lane right G^M_{J-m}
+    if (m < ntau - k) {
+      int jb = max(j0, m);
+      jb += ((j0 + wave - jb) % 4 + 4) % 4;  // keep this wave's residue mod 4
+      term_loop<D>(
+          jb, je, [&](int J) -> const cplx* { return P.Gmat + (size_t)(J - m) * DD; },
+          [&](int J, const cplx(&H)[DD]) { f_left<D>(acc, wr.w(ntau - m, J - m), sA + (J - j0) * DD, H); });
+    }
+  }
+  wave_sum_store<D>(acc, lds, valid, sc.part(pi) + (pl.part_off[2] + (long)ch * (ntau + 1) + m) * DD);
+}
+
 // ------------------------------------------------------------- HISTORY
 template <int D>
 __global__ __launch_bounds__(NTHR) void k_history(ProbArg pa, Scratch sc, HistPlan pl) {
@@ -295,14 +626,17 @@ __global__ __launch_bounds__(NTHR) void k_history(ProbArg pa, Scratch sc, HistPl
                         (KMAX + 1) * DD;
   constexpr int TSN = 2 * (D >= 8 ? 16 : 32) * DD + 2 * (TM + (D >= 8 ? 16 : 32) - 1) * DD;
   constexpr int LDSA = (2 * TJ * DD) > PREPN ? (2 * TJ * DD) : PREPN;
-  constexpr int LDSN = LDSA > TSN ? LDSA : TSN;
+  constexpr int LDSB = LDSA > TSN ? LDSA : TSN;
+  constexpr int LDSR = D <= 4 ? 3 * DD * 64 : 0;  // wave sums of the block-per-lane path
+  constexpr int LDSN = LDSB > LDSR ? LDSB : LDSR;
   __shared__ cplx lds[LDSN];
   int pi = blockIdx.y;
   const Prob& P = pa.get(pi);
   int n = pl.n;
   if (n > P.nt) return;
-  int b = blockIdx.x;
-  if (b >= pl.wg_off[NJOB]) {
+  // workgroup 0 sets up the step (dispatched first, it overlaps the sums)
+  int b = blockIdx.x - 1;
+  if (b < 0) {
     prep_step<D>(P, sc, pi, n, lds);
     return;
   }
@@ -312,6 +646,11 @@ __global__ __launch_bounds__(NTHR) void k_history(ProbArg pa, Scratch sc, HistPl
   int mt = local / pl.nch[job], ch = local % pl.nch[job];
   if (job == 6) {
     tau_boundary<D>(P, sc, pi, n, pl, lds);
+    return;
+  }
+  if constexpr (D <= 4) {
+    if (job == 2) tau_blk<D>(P, sc, pi, n, pl, mt, ch, lds);
+    else hist_blk<D>(P, sc, pi, n, pl, job, mt, ch, lds);
     return;
   }
   if (job == 2) {
@@ -474,7 +813,7 @@ template <int D>
 __global__ __launch_bounds__(NTHR) void k_reduce(ProbArg pa, Scratch sc, HistPlan pl) {
   constexpr int DD = D * D;
   constexpr int TM = NTHR / DD > 0 ? NTHR / DD : 1;
-  constexpr int TJ = D >= 8 ? 32 : 64;
+  const int TJ = pl.TJ;
   constexpr int NVMAX = (KMAX + 1) * DD;
   constexpr int NSTAGE = NVMAX > NTHR ? NVMAX : NTHR;
   __shared__ cplx outs[TM * DD];
