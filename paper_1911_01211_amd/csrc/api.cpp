@@ -200,7 +200,8 @@ StepScratch step_layout(const cntr_grid& g) {
   size_t dd = (size_t)g.d * g.d;
   r.sc.off_status = 0;
   r.sc.off_minv = 256;
-  r.sc.off_part = 256 + round256((KMAX + 3) * dd * sizeof(cplx));
+  // step inverses (KMAX + 2 blocks) and the boundary-row source terms (KMAX + 1)
+  r.sc.off_part = 256 + round256((2 * KMAX + 4) * dd * sizeof(cplx));
   r.sc.off_tail = r.sc.off_part;
   r.per = r.sc.off_part + round256(step_scratch_bytes(g.nt, g.k, g.ntau, g.d));
   r.sc.stride = r.per;

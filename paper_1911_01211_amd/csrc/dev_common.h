@@ -20,6 +20,9 @@ struct Scratch {
   size_t stride;  // bytes per problem
   size_t off_minv, off_part, off_tail, off_status;
   __device__ inline cplx* minv(int pi) const { return (cplx*)(base + pi * stride + off_minv); }
+  // boundary-row source terms of the retarded boundary columns (after the
+  // KMAX + 2 inverses), d x d blocks of d = dd
+  __device__ inline cplx* bsrc(int pi, int dd) const { return minv(pi) + (KMAX + 2) * dd; }
   __device__ inline cplx* part(int pi) const { return (cplx*)(base + pi * stride + off_part); }
   __device__ inline cplx* tail(int pi) const { return (cplx*)(base + pi * stride + off_tail); }
   __device__ inline int* status(int pi) const { return (int*)(base + pi * stride + off_status); }
@@ -28,6 +31,26 @@ struct Scratch {
 };
 
 __device__ inline cplx ld(const cplx* p) { return *p; }
+
+// Loads and stores through global-address-space pointers. The contour
+// pointers reach the kernels inside structures, so the compiler would emit
+// flat accesses, which also count against the LDS wait counter and force
+// every LDS wait to drain the outstanding HBM loads.
+// (The qualifier exists only in the device pass; the host pass of the same
+// source sees plain pointers.)
+#if defined(__HIP_DEVICE_COMPILE__)
+#define CNTR_GLOBAL __attribute__((address_space(1)))
+#else
+#define CNTR_GLOBAL
+#endif
+template <class T>
+__device__ inline T gld(const T* p) {
+  return *(const CNTR_GLOBAL T*)p;
+}
+template <class T>
+__device__ inline void gst(T* p, T v) {
+  *(CNTR_GLOBAL T*)p = v;
+}
 
 // Retarded value with the continuation t < t':  X~^R_{a,b}[r][c]
 template <int D>

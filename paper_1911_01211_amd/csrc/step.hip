@@ -104,9 +104,20 @@ __device__ void prep_step(const Prob& P, const Scratch& sc, int pi, int n, cplx*
   cplx* sw = mw + 4 * DD;          // Sigma^R_{n0+i, n0+j}, j <= i, (k+1)^2 blocks
   cplx* ew = sw + K1M * K1M * DD;  // eps_{n0+i} - mu, k+1 blocks
   __shared__ int piv[4][8];
+  // weight tables used below, staged with the operands in one memory round
+  __shared__ double tS[K1M * K1M], tD[K1M * K1M], tG[K1M], ta0;
   // the boundary-row work of this step starts its completion count at 0
   if (tid == 0) *sc.counter(pi) = 0;
+  if (tid < K1M * K1M) {
+    tS[tid] = W.s[tid / K1M][tid % K1M];
+    tD[tid] = W.D[tid / K1M][tid % K1M];
+  }
+  __shared__ double tGn[K1M];
+  if (tid <= KMAX) tG[tid] = tid <= k ? greg(W, n0 + tid, n0 + tid) : 0.0;
+  if (tid <= KMAX) tGn[tid] = tid <= k ? greg(W, n, n0 + tid) : 0.0;
+  if (tid == 0) ta0 = W.a[0];
   // stage the window of Sigma^R and eps used by the solves below
+#pragma unroll 4
   for (int idx = tid; idx < K1 * K1 * DD; idx += NTHR) {
     int i = idx / (K1 * DD), j = (idx / DD) % K1, e = idx % DD;
     sw[(i * K1M + j) * DD + e] = j <= i ? P.Sret[(tri(n0 + i) + n0 + j) * DD + e] : mk(0, 0);
@@ -117,6 +128,15 @@ __device__ void prep_step(const Prob& P, const Scratch& sc, int pi, int n, cplx*
     if (e / D == e % D) v.x -= P.mu;
     ew[idx] = v;
   }
+  // Sigma^<_{n0+i, n0+j}[x][y] (any order of i, j) for the boundary-row
+  // source terms, d <= 4 and n >= 2k+1 only
+  cplx* lw = ew + K1M * DD;
+  if (D <= 4 && n >= 2 * k + 1)
+#pragma unroll 4
+    for (int idx = tid; idx < K1 * K1 * DD; idx += NTHR) {
+      int i = idx / (K1 * DD), j = (idx / DD) % K1, e = idx % DD;
+      lw[(i * K1M + j) * DD + e] = les_any<D>(P.Sles, n0 + i, n0 + j, e / D, e % D);
+    }
   __syncthreads();
   // Sigma~^R_{n0+i, n0+j}[x][y] for any i, j in the window
   auto sig = [&](int i, int j, int x, int y) -> cplx {
@@ -126,8 +146,8 @@ __device__ void prep_step(const Prob& P, const Scratch& sc, int pi, int n, cplx*
   // step matrix h^-1 a_0 + i e_m + i h w(m,m) Sigma^R_{m,m} of row m = n0 + i
   auto stepmat = [&](int i, int e) -> cplx {
     int x = e / D, y = e % D;
-    cplx v = mul_i(ew[i * DD + e]) + (h * greg(W, n0 + i, n0 + i)) * mul_i(sw[(i * K1M + i) * DD + e]);
-    if (x == y) v.x += W.a[0] / h;
+    cplx v = mul_i(ew[i * DD + e]) + (h * tG[i]) * mul_i(sw[(i * K1M + i) * DD + e]);
+    if (x == y) v.x += ta0 / h;
     return v;
   };
   if constexpr (D <= 4) {
@@ -141,9 +161,9 @@ __device__ void prep_step(const Prob& P, const Scratch& sc, int pi, int n, cplx*
       bool row = lane < N;
       int p = row ? lane / D + 1 : 1, y = lane % D;
       auto Cv = [&](int l, int x) -> cplx {
-        cplx v = (h * W.s[p][l]) * mul_i(sig(k - l, k - p, x, y));
+        cplx v = (h * tS[p * K1M + l]) * mul_i(sig(k - l, k - p, x, y));
         if (p == l) v = v + mul_i(ew[(k - p) * DD + x * D + y]);
-        if (x == y) v.x += W.D[p][l] / h;
+        if (x == y) v.x += tD[p * K1M + l] / h;
         return v;
       };
 #pragma unroll
@@ -160,6 +180,32 @@ __device__ void prep_step(const Prob& P, const Scratch& sc, int pi, int n, cplx*
         for (int cc = 0; cc < D; cc++) P.Gret[(tri(n) + n - l) * DD + cc * D + c2] = bb[cc];
       }
       if (lane < DD) P.Gret[(tri(n) + n) * DD + lane] = (lane / D == lane % D) ? mk(0, -1) : mk(0, 0);
+      if (n >= 2 * k + 1) {
+        // source terms of the lesser boundary rows m_r = n-k+r from the
+        // retarded boundary columns j = n-k..n:
+        //   -i h sum_j w(n,j) Sigma^<_{m_r,j} (R_{n,j})^dag
+        cplx* rb = A;  // R_{n,n-l} blocks, l = 0..k (LDS, wave 0 only)
+        if (row && col >= 0) {
+          int l = col / D + 1, c2 = col % D;
+#pragma unroll
+          for (int cc = 0; cc < D; cc++) rb[l * DD + cc * D + c2] = bb[cc];
+        }
+        if (lane < DD) rb[lane] = (lane / D == lane % D) ? mk(0, -1) : mk(0, 0);
+        wave_sync();
+        for (int v = lane; v < (k + 1) * DD; v += 64) {
+          int r = v / DD, ee = v % DD, a2 = ee / D, c2 = ee % D;
+          cplx pb = mk(0, 0);
+          for (int jj = 0; jj <= k; jj++) {
+            const cplx* sb = lw + (r * K1M + jj) * DD + a2 * D;
+            const cplx* rr = rb + (k - jj) * DD + c2 * D;  // R_{n, n-k+jj}
+            cplx t = mk(0, 0);
+#pragma unroll
+            for (int q = 0; q < D; q++) cfma_cb(t, sb[q], rr[q]);
+            pb = pb + tGn[jj] * t;
+          }
+          sc.bsrc(pi, DD)[v] = -h * mul_i(pb);
+        }
+      }
     } else {
       // M_R^-1 (wave 1) and, for n >= 2k+1, the inverted step matrices of the
       // lesser boundary rows m = n-k..n (all three waves)
@@ -195,9 +241,9 @@ __device__ void prep_step(const Prob& P, const Scratch& sc, int pi, int n, cplx*
     // retarded boundary: sum_l C_{l,p}^T Y_l^T = i C_{0,p}^T  (Y_0 = -i) with
     // C_{l,p} = h^-1 D_{p,l} + delta_{pl} i e_{n-p} + i h s_{p,l} Sigma~^R_{n-l,n-p}
     auto Cval = [&](int l, int p, int x, int y) -> cplx {
-      cplx v = (h * W.s[p][l]) * mul_i(sig(k - l, k - p, x, y));
+      cplx v = (h * tS[p * K1M + l]) * mul_i(sig(k - l, k - p, x, y));
       if (p == l) v = v + mul_i(ew[(k - p) * DD + x * D + y]);
-      if (x == y) v.x += W.D[p][l] / h;
+      if (x == y) v.x += tD[p * K1M + l] / h;
       return v;
     };
     for (int idx = lane; idx < N * N; idx += 64) {
@@ -361,8 +407,12 @@ __device__ inline void cfma_cc(cplx& acc, cplx x, cplx y) {
   acc.y = fma(-x.y, y.x, acc.y);
 }
 
+// pointer to read-only device memory in the global address space
+using gcp = const CNTR_GLOBAL cplx*;
+__device__ inline gcp G(const cplx* p) { return (gcp)p; }
+
 template <int DD>
-__device__ inline void ld_blk(cplx (&h)[DD], const cplx* p) {
+__device__ inline void ld_blk(cplx (&h)[DD], gcp p) {
 #pragma unroll
   for (int e = 0; e < DD; e++) h[e] = p[e];
 }
@@ -428,24 +478,25 @@ __device__ inline void f_right_tc(cplx (&acc)[D * D], double w, const cplx* S, c
     }
 }
 
-// Terms j = jb, jb+4, ... < je of one lane: addr(j) gives the history block
-// (nullptr when the term does not apply to this lane), add(j, H) accumulates.
+// Terms j = jb, jb+4, ... < je (uniform over the wave) of one lane.
+// addr(j) gives a readable history block for every lane (clamped where the
+// term does not apply), add(j, H) accumulates it (weight 0 where the term does
+// not apply). Two register buffers alternate; every load is unconditional
+// and the control flow uniform, so the loads of the next term stay in flight
+// while the current one is multiplied.
 template <int D, class Addr, class Add>
 __device__ inline void term_loop(int jb, int je, Addr addr, Add add) {
   constexpr int DD = D * D;
-  cplx hc[DD], hn[DD];
-  int j = jb;
-  const cplx* pc = j < je ? addr(j) : nullptr;
-  if (pc) ld_blk<DD>(hc, pc);
-  while (j < je) {
-    int jn = j + 4;
-    const cplx* pn = jn < je ? addr(jn) : nullptr;
-    if (pn) ld_blk<DD>(hn, pn);
-    if (pc) add(j, hc);
-#pragma unroll
-    for (int e = 0; e < DD; e++) hc[e] = hn[e];
-    pc = pn;
-    j = jn;
+  if (jb >= je) return;
+  cplx ha[DD], hb[DD];
+  int jl = je - 1;
+  ld_blk<DD>(ha, addr(jb));
+  for (int j = jb; j < je; j += 8) {
+    ld_blk<DD>(hb, addr(min(j + 4, jl)));
+    add(j, ha);
+    if (j + 4 >= je) break;
+    ld_blk<DD>(ha, addr(min(j + 8, jl)));
+    add(j + 4, hb);
   }
 }
 
@@ -463,25 +514,31 @@ __device__ inline void wave_sum_store(cplx (&acc)[D * D], cplx* red, bool valid,
   if (wave == 0 && valid)
 #pragma unroll
     for (int e = 0; e < DD; e++)
-      dst[e] = ((acc[e] + red[e * 64 + lane]) + red[(DD + e) * 64 + lane]) + red[(2 * DD + e) * 64 + lane];
+      gst(dst + e, ((acc[e] + red[e * 64 + lane]) + red[(DD + e) * 64 + lane]) + red[(2 * DD + e) * 64 + lane]);
 }
 
 template <int D>
 __device__ void hist_blk(const Prob& P, const Scratch& sc, int pi, int n, const HistPlan& pl, int job,
                          int mt, int ch, cplx* lds) {
   constexpr int DD = D * D;
+  constexpr int K1 = KMAX + 1;
   const KW& W = c_kw[P.k];
-  __shared__ double s_om[KMAX + 1];
+  __shared__ double s_om[K1];
+  __shared__ double s_s[K1 * K1];
   WReg wr;
   wr.load(W, s_om);
-  int k = P.k, ntau = P.ntau, tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  int k = P.k, ntau = P.ntau, tid = threadIdx.x, lane = tid & 63;
+  int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform in the wave
+  if (tid < K1 * K1) s_s[tid] = W.s[tid / K1][tid % K1];
   int TJ = pl.TJ, mout = pl.mout[job];
   int mlo = mt * 64, mhi = min(mlo + 64, mout) - 1;
   int m = mlo + lane;
   bool valid = m < mout;
+  int mc = valid ? m : mhi;  // in-range output index for address arithmetic
   int j0 = ch * TJ;
   if (job == 0 && j0 + TJ - 1 < mlo) return;
   if (job == 4 && j0 > max(mhi, k)) return;
+  gcp Gret = G(P.Gret), Gles = G(P.Gles), Gtv = G(P.Gtv);
   cplx* sh = lds;
   size_t T1 = (size_t)n * (ntau + 1);
   for (int idx = tid; idx < TJ * DD; idx += NTHR) {
@@ -491,13 +548,13 @@ __device__ void hist_blk(const Prob& P, const Scratch& sc, int pi, int n, const 
       case 0:
       case 1:
       case 3:
-        if (j < n) v = P.Sret[(tri(n) + j) * DD + ee];
+        if (j < n) v = gld(P.Sret + (tri(n) + j) * DD + ee);
         break;
       case 4:
-        if (j <= n) v = P.Sles[(tri(n) + j) * DD + ee];
+        if (j <= n) v = gld(P.Sles + (tri(n) + j) * DD + ee);
         break;
       case 5:
-        if (j <= ntau) v = P.Stv[((size_t)T1 + ntau - j) * DD + ee];
+        if (j <= ntau) v = gld(P.Stv + (T1 + ntau - j) * DD + ee);
         break;
     }
     sh[idx] = v;
@@ -508,56 +565,58 @@ __device__ void hist_blk(const Prob& P, const Scratch& sc, int pi, int n, const 
   for (int e = 0; e < DD; e++) acc[e] = mk(0, 0);
   int jb = j0 + wave;
   double xi = P.sig;
-  if (valid) {
-    switch (job) {
-      case 0: {  // retarded bulk: sum_j w(n-m, j-m) S^R_{n,j} R_{j,m}
-        int je = min(n, j0 + TJ);
-        term_loop<D>(
-            jb, je, [&](int j) -> const cplx* { return j >= m ? P.Gret + (tri(j) + m) * DD : nullptr; },
-            [&](int j, const cplx(&H)[DD]) { f_left<D>(acc, wr.w(n - m, j - m), sh + (j - j0) * DD, H); });
-      } break;
-      case 1: {  // left-mixing history: sum_j w(n,j) S^R_{n,j} T_{j,m}
-        int je = min(n, j0 + TJ);
-        term_loop<D>(
-            jb, je, [&](int j) -> const cplx* { return P.Gtv + ((size_t)j * (ntau + 1) + m) * DD; },
-            [&](int j, const cplx(&H)[DD]) { f_left<D>(acc, wr.w(n, j), sh + (j - j0) * DD, H); });
-      } break;
-      case 3: {  // lesser history: sum_l w(n,l) L^_{m,l} (S^R_{n,l})^dag
-        int je = min(n, j0 + TJ);
-        term_loop<D>(
-            jb, je,
-            [&](int l) -> const cplx* {
-              return l >= m ? P.Gles + (tri(l) + m) * DD : P.Gles + (tri(m) + l) * DD;
-            },
-            [&](int l, const cplx(&H)[DD]) {
-              if (l >= m) f_right_c<D>(acc, wr.w(n, l), sh + (l - j0) * DD, H);
-              else f_right_tc<D>(acc, wr.w(n, l), sh + (l - j0) * DD, H);
-            });
-      } break;
-      case 4: {  // source C^<_1[G,1,Sigma](m,n): sum_j w(m,j) R~_{m,j} S^<_{j,n}
-        int jmax = m > k ? m : k;
-        int je = min(max(mhi, k) + 1, j0 + TJ);
-        term_loop<D>(
-            jb, je,
-            [&](int j) -> const cplx* {
-              if (j > jmax) return nullptr;
-              return j <= m ? P.Gret + (tri(m) + j) * DD : P.Gret + (tri(j) + m) * DD;
-            },
-            [&](int j, const cplx(&H)[DD]) {
-              double w = m > k ? wr.w(m, j) : W.s[m][j];
-              if (j <= m) f_right<D>(acc, w, sh + (j - j0) * DD, H);
-              else f_right_t<D>(acc, w, sh + (j - j0) * DD, H);
-            });
-      } break;
-      case 5: {  // source C^<_3 without -i: sum_j (-xi) w(ntau,j) T_{m,j} (S^rceil_{n,ntau-j})^dag
-        int je = min(ntau + 1, j0 + TJ);
-        term_loop<D>(
-            jb, je, [&](int j) -> const cplx* { return P.Gtv + ((size_t)m * (ntau + 1) + j) * DD; },
-            [&](int j, const cplx(&H)[DD]) {
-              f_right_c<D>(acc, -xi * wr.w(ntau, j), sh + (j - j0) * DD, H);
-            });
-      } break;
-    }
+  size_t NT1 = ntau + 1;
+  switch (job) {
+    case 0: {  // retarded bulk: sum_j w(n-m, j-m) S^R_{n,j} R_{j,m}, j >= m
+      int je = min(n, j0 + TJ);
+      term_loop<D>(
+          jb, je, [&](int j) { return Gret + (tri(max(j, mc)) + mc) * DD; },
+          [&](int j, const cplx(&H)[DD]) {
+            double w = (valid && j >= m) ? wr.w(n - m, j - m) : 0.0;
+            f_left<D>(acc, w, sh + (j - j0) * DD, H);
+          });
+    } break;
+    case 1: {  // left-mixing history: sum_j w(n,j) S^R_{n,j} T_{j,m}
+      int je = min(n, j0 + TJ);
+      term_loop<D>(
+          jb, je, [&](int j) { return Gtv + ((size_t)j * NT1 + mc) * DD; },
+          [&](int j, const cplx(&H)[DD]) { f_left<D>(acc, valid ? wr.w(n, j) : 0.0, sh + (j - j0) * DD, H); });
+    } break;
+    case 3: {  // lesser history: sum_l w(n,l) L^_{m,l} (S^R_{n,l})^dag
+      int je = min(n, j0 + TJ);
+      term_loop<D>(
+          jb, je,
+          [&](int l) { return l >= mc ? Gles + (tri(l) + mc) * DD : Gles + (tri(mc) + l) * DD; },
+          [&](int l, const cplx(&H)[DD]) {
+            double w = valid ? wr.w(n, l) : 0.0;
+            if (l >= mc) f_right_c<D>(acc, w, sh + (l - j0) * DD, H);
+            else f_right_tc<D>(acc, w, sh + (l - j0) * DD, H);
+          });
+    } break;
+    case 4: {  // source C^<_1[G,1,Sigma](m,n): sum_j w(m,j) R~_{m,j} S^<_{j,n}, j <= max(m,k)
+      int jmax = mc > k ? mc : k;
+      int je = min(max(mhi, k) + 1, j0 + TJ);
+      term_loop<D>(
+          jb, je,
+          [&](int j) {
+            int jj = min(j, jmax);
+            return jj <= mc ? Gret + (tri(mc) + jj) * DD : Gret + (tri(jj) + mc) * DD;
+          },
+          [&](int j, const cplx(&H)[DD]) {
+            double w = 0.0;
+            if (valid && j <= jmax) w = m > k ? wr.w(m, j) : s_s[m * K1 + j];
+            if (j <= mc) f_right<D>(acc, w, sh + (j - j0) * DD, H);
+            else f_right_t<D>(acc, w, sh + (j - j0) * DD, H);
+          });
+    } break;
+    case 5: {  // source C^<_3 without -i: sum_j (-xi) w(ntau,j) T_{m,j} (S^rceil_{n,ntau-j})^dag
+      int je = min(ntau + 1, j0 + TJ);
+      term_loop<D>(
+          jb, je, [&](int j) { return Gtv + ((size_t)mc * NT1 + j) * DD; },
+          [&](int j, const cplx(&H)[DD]) {
+            f_right_c<D>(acc, valid ? -xi * wr.w(ntau, j) : 0.0, sh + (j - j0) * DD, H);
+          });
+    } break;
   }
   wave_sum_store<D>(acc, lds, valid, sc.part(pi) + (pl.part_off[job] + (long)ch * mout + m) * DD);
 }
@@ -575,44 +634,44 @@ __device__ void tau_blk(const Prob& P, const Scratch& sc, int pi, int n, const H
   __shared__ double s_om[KMAX + 1];
   WReg wr;
   wr.load(W, s_om);
-  int k = P.k, ntau = P.ntau, tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  int k = P.k, ntau = P.ntau, tid = threadIdx.x, lane = tid & 63;
+  int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform in the wave
   int TJS = pl.TJS;
   int m = mt * 64 + lane;
   bool valid = m <= ntau;
+  int mc = valid ? m : ntau;
   int j0 = ch * TJS;
   const cplx* Srow = P.Stv + (size_t)n * (ntau + 1) * DD;
+  gcp gS = G(Srow), gM = G(P.Gmat);
   cplx* sA = lds;             // Sigma^rceil_{n,J}
   cplx* sB = lds + TJS * DD;  // G^M_{ntau-J}
   for (int idx = tid; idx < TJS * DD; idx += NTHR) {
     int J = j0 + idx / DD, ee = idx % DD;
     bool in = J <= ntau;
-    sA[idx] = in ? Srow[(size_t)J * DD + ee] : mk(0, 0);
-    sB[idx] = in ? P.Gmat[(size_t)(ntau - J) * DD + ee] : mk(0, 0);
+    sA[idx] = in ? gld(Srow + (size_t)J * DD + ee) : mk(0, 0);
+    sB[idx] = in ? gld(P.Gmat + (size_t)(ntau - J) * DD + ee) : mk(0, 0);
   }
   __syncthreads();
   cplx acc[DD];
 #pragma unroll
   for (int e = 0; e < DD; e++) acc[e] = mk(0, 0);
   double xi = P.sig;
-  if (valid) {
-    int je = min(ntau + 1, j0 + TJS);
-    // band 1: per-lane left operand Sigma^rceil_{n,m-J}, shared right G^M_{ntau-J}
-    if (m > k)
-      term_loop<D>(
-          j0 + wave, min(je, m + 1), [&](int J) -> const cplx* { return Srow + (size_t)(m - J) * DD; },
-          [&](int J, const cplx(&H)[DD]) {
-            // acc += xi w(m,J) H G^M_{ntau-J}
-            f_right<D>(acc, xi * wr.w(m, J), sB + (J - j0) * DD, H);
-          });
-    // band 2: shared left Sigma^rceil_{n,J}, per-lane right G^M_{J-m}
-    if (m < ntau - k) {
-      int jb = max(j0, m);
-      jb += ((j0 + wave - jb) % 4 + 4) % 4;  // keep this wave's residue mod 4
-      term_loop<D>(
-          jb, je, [&](int J) -> const cplx* { return P.Gmat + (size_t)(J - m) * DD; },
-          [&](int J, const cplx(&H)[DD]) { f_left<D>(acc, wr.w(ntau - m, J - m), sA + (J - j0) * DD, H); });
-    }
-  }
+  int je = min(ntau + 1, j0 + TJS);
+  int jb = j0 + wave;
+  // band 1: per-lane left operand Sigma^rceil_{n,m-J}, shared right G^M_{ntau-J}
+  term_loop<D>(
+      jb, je, [&](int J) { return gS + (size_t)max(mc - J, 0) * DD; },
+      [&](int J, const cplx(&H)[DD]) {
+        double w = (valid && m > k && J <= m) ? xi * wr.w(m, J) : 0.0;
+        f_right<D>(acc, w, sB + (J - j0) * DD, H);
+      });
+  // band 2: shared left Sigma^rceil_{n,J}, per-lane right G^M_{J-m}
+  term_loop<D>(
+      jb, je, [&](int J) { return gM + (size_t)max(J - mc, 0) * DD; },
+      [&](int J, const cplx(&H)[DD]) {
+        double w = (valid && m < ntau - k && J >= m) ? wr.w(ntau - m, J - m) : 0.0;
+        f_left<D>(acc, w, sA + (J - j0) * DD, H);
+      });
   wave_sum_store<D>(acc, lds, valid, sc.part(pi) + (pl.part_off[2] + (long)ch * (ntau + 1) + m) * DD);
 }
 
@@ -809,6 +868,37 @@ __global__ __launch_bounds__(NTHR) void k_history(ProbArg pa, Scratch sc, HistPl
 // and the last workgroup to finish (completion counter, no waiting) sums the
 // per-workgroup partials, adds the terms of the boundary rows themselves and
 // runs the k+1 serial steps with the inverses prepared by the step set-up.
+// Sum of cnt values p[i * stride] (in a fixed order), eight loads in flight.
+__device__ inline cplx psum(const cplx* p, long stride, int cnt) {
+  cplx s[8];
+#pragma unroll
+  for (int u = 0; u < 8; u++) s[u] = mk(0, 0);
+  int i = 0;
+  for (; i + 8 <= cnt; i += 8) {
+    cplx v[8];
+#pragma unroll
+    for (int u = 0; u < 8; u++) v[u] = gld(p + (long)(i + u) * stride);
+#pragma unroll
+    for (int u = 0; u < 8; u++) s[u] = s[u] + v[u];
+  }
+  for (; i < cnt; i++) s[0] = s[0] + gld(p + (long)i * stride);
+  return ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
+}
+
+// BDF part -h^-1 sum_{l=1..k} a_l X_{n-l} of one element; x(l) gives the
+// address of X_{n-l} (all loads issued together).
+template <class F>
+__device__ inline cplx bdf_sum(const KW& W, int k, double h, F x) {
+  cplx v[KMAX];
+#pragma unroll
+  for (int l = 1; l <= KMAX; l++) v[l - 1] = l <= k ? gld(x(l)) : mk(0, 0);
+  cplx r = mk(0, 0);
+#pragma unroll
+  for (int l = 1; l <= KMAX; l++)
+    if (l <= k) r = r - (W.a[l] / h) * v[l - 1];
+  return r;
+}
+
 template <int D>
 __global__ __launch_bounds__(NTHR) void k_reduce(ProbArg pa, Scratch sc, HistPlan pl) {
   constexpr int DD = D * D;
@@ -850,31 +940,44 @@ __global__ __launch_bounds__(NTHR) void k_reduce(ProbArg pa, Scratch sc, HistPla
   bool valid = mo < TM && m < mout;
   if (tid < DD) minv[tid] = sc.minv(pi)[tid];
   const cplx* part = sc.part(pi);
+  int mlo = mt * TM, mhi = min(mlo + TM, mout) - 1, nm = mhi - mlo + 1;
+  if (n >= 2 * k + 1) {
+    // self-energy blocks of the boundary rows paired with this tile (used
+    // after the outputs are formed; loaded now, in the same memory round)
+#pragma unroll 8
+    for (int idx = tid; idx < (k + 1) * nm * DD; idx += NTHR) {
+      int r = idx / (nm * DD), rem = idx % (nm * DD), mm = mlo + rem / DD, ee = rem % DD;
+      int mr = n - k + r;
+      cplx v;
+      if (fam == 0) v = gld(P.Sles + (tri(mr) + mm) * DD + ee);  // Sigma^<_{mm,mr}, mm < mr
+      else if (fam == 1) v = gld(P.Stv + ((size_t)mr * (ntau + 1) + ntau - mm) * DD + ee);
+      else v = gld(P.Sret + (tri(mr) + mm) * DD + ee);
+      sigs[idx] = v;
+    }
+  }
   if (valid) {
     cplx r = mk(0, 0);
+    long cs = (long)mout * DD;  // stride between the chunks of one output
+    auto pp = [&](int job, int ch0) { return part + (pl.part_off[job] + (long)ch0 * mout + m) * DD + e; };
     if (fam == 0) {
-      cplx hs = mk(0, 0);
-      for (int ch = m / TJ; ch < pl.nch[0]; ch++) hs = hs + part[(pl.part_off[0] + (long)ch * mout + m) * DD + e];
-      r = -(h * mul_i(hs));
-      for (int l = 1; l <= k; l++) r = r - (W.a[l] / h) * P.Gret[(tri(n - l) + m) * DD + e];
+      int c0 = m / TJ;
+      cplx hs = psum(pp(0, c0), cs, pl.nch[0] - c0);
+      cplx bd = bdf_sum(W, k, h, [&](int l) { return P.Gret + (tri(n - l) + m) * DD + e; });
+      r = bd - h * mul_i(hs);
     } else if (fam == 1) {
-      cplx ts = mk(0, 0);
-      for (int ch = 0; ch < pl.nch[2]; ch++) ts = ts + part[(pl.part_off[2] + (long)ch * mout + m) * DD + e];
-      if (m <= k || m >= ntau - k) ts = ts + part[(pl.part_off[6] + m) * DD + e];
+      cplx ts = psum(pp(2, 0), cs, pl.nch[2]);
+      if (m <= k || m >= ntau - k) ts = ts + gld(part + (pl.part_off[6] + m) * DD + e);
       ts = ht * ts;
-      cplx hs = mk(0, 0);
-      for (int ch = 0; ch < pl.nch[1]; ch++) hs = hs + part[(pl.part_off[1] + (long)ch * mout + m) * DD + e];
-      r = -mul_i(ts) - h * mul_i(hs);
-      for (int l = 1; l <= k; l++)
-        r = r - (W.a[l] / h) * P.Gtv[((size_t)(n - l) * (ntau + 1) + m) * DD + e];
+      cplx hs = psum(pp(1, 0), cs, pl.nch[1]);
+      cplx bd = bdf_sum(W, k, h, [&](int l) { return P.Gtv + ((size_t)(n - l) * (ntau + 1) + m) * DD + e; });
+      r = bd - mul_i(ts) - h * mul_i(hs);
     } else {
-      cplx s3 = mk(0, 0), s4 = mk(0, 0), s5 = mk(0, 0);
-      for (int ch = 0; ch < pl.nch[3]; ch++) s3 = s3 + part[(pl.part_off[3] + (long)ch * mout + m) * DD + e];
       int jmax = m > k ? m : k;
-      for (int ch = 0; ch <= jmax / TJ; ch++) s4 = s4 + part[(pl.part_off[4] + (long)ch * mout + m) * DD + e];
-      for (int ch = 0; ch < pl.nch[5]; ch++) s5 = s5 + part[(pl.part_off[5] + (long)ch * mout + m) * DD + e];
-      r = h * mul_i(s4) + ht * s5 + h * mul_i(s3);
-      for (int l = 1; l <= k; l++) r = r - (W.a[l] / h) * P.Gles[(tri(n - l) + m) * DD + e];
+      cplx s3 = psum(pp(3, 0), cs, pl.nch[3]);
+      cplx s4 = psum(pp(4, 0), cs, jmax / TJ + 1);
+      cplx s5 = psum(pp(5, 0), cs, pl.nch[5]);
+      cplx bd = bdf_sum(W, k, h, [&](int l) { return P.Gles + (tri(n - l) + m) * DD + e; });
+      r = bd + h * mul_i(s4) + ht * s5 + h * mul_i(s3);
     }
     outs[mo * DD + e] = r;
   }
@@ -899,19 +1002,6 @@ __global__ __launch_bounds__(NTHR) void k_reduce(ProbArg pa, Scratch sc, HistPla
   int nwg = t0 + t1 + t2;
   int NV = (k + 1) * DD;
   cplx* tpart = sc.part(pi) + pl.tail_off * DD;
-  int mlo = mt * TM, mhi = min(mlo + TM, mout) - 1, nm = mhi - mlo + 1;
-  // stage the self-energy blocks of the boundary rows paired with this tile
-  // (contiguous along the tile in every family)
-  for (int idx = tid; idx < (k + 1) * nm * DD; idx += NTHR) {
-    int r = idx / (nm * DD), rem = idx % (nm * DD), mm = mlo + rem / DD, ee = rem % DD;
-    int mr = n - k + r;
-    cplx v;
-    if (fam == 0) v = P.Sles[(tri(mr) + mm) * DD + ee];  // Sigma^<_{mm,mr}, mm < mr
-    else if (fam == 1) v = P.Stv[((size_t)mr * (ntau + 1) + ntau - mm) * DD + ee];
-    else v = P.Sret[(tri(mr) + mm) * DD + ee];
-    sigs[idx] = v;
-  }
-  __syncthreads();
   for (int v = tid; v < NV; v += NTHR) {
     int r = v / DD, ee = v % DD, a2 = ee / D, c2 = ee % D;
     int mr = n - k + r;
@@ -944,58 +1034,77 @@ __global__ __launch_bounds__(NTHR) void k_reduce(ProbArg pa, Scratch sc, HistPla
   __syncthreads();
   if (!is_last) return;
   __threadfence();
-  // last workgroup: sum the partials of all workgroups, G groups per value,
-  // eight independent loads in flight per thread
+  // last workgroup. The operands of the serial steps are loaded first (into
+  // registers), then the partials of all workgroups are summed (G groups per
+  // value); the loads of both overlap.
+  int npk = k * (k + 1) / 2;
+  cplx* s_r = ser;  // Sigma^R_{m_r, n-k+jj}, jj < r, packed at r(r-1)/2 + jj
+  cplx* s_l = s_r + npk * DD;  // L_{n-2k..n-k-1, n} (BDF of the first rows)
+  cplx* s_b = s_l + k * DD;    // inverted boundary step matrices
+  constexpr int NSR = (KMAX * (KMAX + 1) / 2 * DD + NTHR - 1) / NTHR;
+  constexpr int NSL = (KMAX * DD + NTHR - 1) / NTHR;
+  constexpr int NSB = ((KMAX + 1) * DD + NTHR - 1) / NTHR;
+  cplx vr[NSR], vl[NSL], vb[NSB];
+#pragma unroll
+  for (int u = 0; u < NSR; u++) {
+    int idx = tid + u * NTHR;
+    if (idx < npk * DD) {
+      int pr = idx / DD, ee = idx % DD, r = 1;
+      while (r * (r + 1) / 2 <= pr) r++;
+      int jj = pr - r * (r - 1) / 2;
+      vr[u] = gld(P.Sret + (tri(n - k + r) + n - k + jj) * DD + ee);
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < NSL; u++) {
+    int idx = tid + u * NTHR;
+    if (idx < k * DD) vl[u] = gld(P.Gles + (tri(n) + n - 2 * k + idx / DD) * DD + idx % DD);
+  }
+#pragma unroll
+  for (int u = 0; u < NSB; u++) {
+    int idx = tid + u * NTHR;
+    if (idx < (k + 1) * DD) vb[u] = gld(sc.minv(pi) + DD + idx);
+  }
   int G = NV >= NTHR ? 1 : NTHR / NV;
   for (int vv = tid; vv < G * NV; vv += NTHR) {
     int g = vv / NV, v = vv % NV;
-    cplx s0 = mk(0, 0), s1 = s0, s2 = s0, s3 = s0, s4 = s0, s5 = s0, s6 = s0, s7 = s0;
-    int w = g;
-    for (; w + 7 * G < nwg; w += 8 * G) {
-      s0 = s0 + tpart[(size_t)(w)*NV + v];
-      s1 = s1 + tpart[(size_t)(w + G) * NV + v];
-      s2 = s2 + tpart[(size_t)(w + 2 * G) * NV + v];
-      s3 = s3 + tpart[(size_t)(w + 3 * G) * NV + v];
-      s4 = s4 + tpart[(size_t)(w + 4 * G) * NV + v];
-      s5 = s5 + tpart[(size_t)(w + 5 * G) * NV + v];
-      s6 = s6 + tpart[(size_t)(w + 6 * G) * NV + v];
-      s7 = s7 + tpart[(size_t)(w + 7 * G) * NV + v];
-    }
-    for (; w < nwg; w += G) s0 = s0 + tpart[(size_t)w * NV + v];
-    stage[vv] = ((s0 + s1) + (s2 + s3)) + ((s4 + s5) + (s6 + s7));
+    // workgroups g, g+G, g+2G, ... of value v
+    stage[vv] = psum(tpart + (size_t)g * NV + v, (long)G * NV, g < nwg ? (nwg - g + G - 1) / G : 0);
   }
+#pragma unroll
+  for (int u = 0; u < NSR; u++)
+    if (tid + u * NTHR < npk * DD) s_r[tid + u * NTHR] = vr[u];
+#pragma unroll
+  for (int u = 0; u < NSL; u++)
+    if (tid + u * NTHR < k * DD) s_l[tid + u * NTHR] = vl[u];
+#pragma unroll
+  for (int u = 0; u < NSB; u++)
+    if (tid + u * NTHR < (k + 1) * DD) s_b[tid + u * NTHR] = vb[u];
   __syncthreads();
   for (int v = tid; v < NV; v += NTHR) {
     int r = v / DD, ee = v % DD, a2 = ee / D, c2 = ee % D;
     int mr = n - k + r;
     cplx s = mk(0, 0);
     for (int g = 0; g < G; g++) s = s + stage[g * NV + v];
-    // retarded boundary columns j = n-k..n of the source sum
-    cplx pb = mk(0, 0);
-    for (int j = n - k; j <= n; j++) {
-      cplx t = mk(0, 0);
-      for (int q = 0; q < D; q++)
-        cfma_cb(t, les_any<D>(P.Sles, mr, j, a2, q), P.Gret[(tri(n) + j) * DD + c2 * D + q]);
-      pb = pb + greg(W, n, j) * t;
+    if constexpr (D <= 4) {
+      // the retarded boundary columns j = n-k..n were summed by the step set-up
+      pre[v] = s + gld(sc.bsrc(pi, DD) + v);
+    } else {
+      cplx pb = mk(0, 0);
+#pragma unroll
+      for (int jj = 0; jj <= KMAX; jj++) {
+        if (jj <= k) {
+          int j = n - k + jj;
+          cplx t = mk(0, 0);
+#pragma unroll
+          for (int q = 0; q < D; q++)
+            cfma_cb(t, les_any<D>(P.Sles, mr, j, a2, q), gld(P.Gret + (tri(n) + j) * DD + c2 * D + q));
+          pb = pb + greg(W, n, j) * t;
+        }
+      }
+      pre[v] = s - h * mul_i(pb);
     }
-    pre[v] = s - h * mul_i(pb);
   }
-  __syncthreads();
-  // stage the operands of the serial steps: Sigma^R_{m_r, n-k+jj} (jj < r,
-  // packed at r(r-1)/2 + jj), the rows L_{n-2k..n-k-1, n} of the BDF and the
-  // inverted boundary step matrices
-  int npk = k * (k + 1) / 2;
-  cplx* s_r = ser;
-  cplx* s_l = s_r + npk * DD;
-  cplx* s_b = s_l + k * DD;
-  for (int idx = tid; idx < npk * DD; idx += NTHR) {
-    int pr = idx / DD, ee = idx % DD, r = 1;
-    while (r * (r + 1) / 2 <= pr) r++;
-    int jj = pr - r * (r - 1) / 2;
-    s_r[idx] = P.Sret[(tri(n - k + r) + n - k + jj) * DD + ee];
-  }
-  for (int idx = tid; idx < k * DD; idx += NTHR) s_l[idx] = P.Gles[(tri(n) + n - 2 * k + idx / DD) * DD + idx % DD];
-  for (int idx = tid; idx < (k + 1) * DD; idx += NTHR) s_b[idx] = sc.minv(pi)[DD + idx];
   __syncthreads();
   if (tid >= 64) return;  // the serial steps run on one wavefront, from LDS
   for (int r = 0; r <= k; r++) {
