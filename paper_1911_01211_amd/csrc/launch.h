@@ -7,13 +7,16 @@
 
 namespace cntr {
 
-constexpr int NJOB = 7;  // history jobs of one time step
+constexpr int NJOB = 8;  // history jobs of one time step
 
 // Work plan of one time step n (identical for every problem of the call).
 struct HistPlan {
   int n;
   int njob;
+  int staged;       // history blocks staged through LDS (d = 1, 2, 4)
   int TJ, TM, TJS;  // term chunk, outputs per tile, tau-source chunk
+  int tj[NJOB];     // term chunk of each job
+  int tm[NJOB];     // outputs per tile of each job
   int mout[NJOB];
   int nch[NJOB];
   int mtiles[NJOB];

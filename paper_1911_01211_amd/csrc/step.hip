@@ -27,12 +27,21 @@ constexpr int NTHR = 256;
 int hist_tm(int d) { return d <= 4 ? 64 : (NTHR / (d * d) > 0 ? NTHR / (d * d) : 1); }
 int hist_tj(int d) { return d >= 8 ? 32 : 64; }
 static int hist_tjs(int d) { return d <= 4 ? 16 : (d >= 8 ? 16 : 32); }
+// staged path: term chunk of the history jobs and of the tau source
+constexpr int STG_TJ = 32, STG_TJS = 16;
 
 static int cdiv_i(int a, int b) { return (a + b - 1) / b; }
+
+// Jobs: 0 retarded bulk, 1 left-mixing history, 2 tau source, 3 lesser
+// history (for the staged path only its part l >= m), 4 source C^<_1,
+// 5 source C^<_3, 6 tau-boundary corrections, 7 lesser history l < m (staged
+// path only).
+bool hist_staged(int d) { return d == 1 || d == 2 || d == 4; }
 
 HistPlan make_plan(int n, int k, int ntau, int d) {
   HistPlan p{};
   p.n = n;
+  p.staged = hist_staged(d);
   p.TJ = hist_tj(d);
   p.TM = hist_tm(d);
   p.TJS = hist_tjs(d);
@@ -40,15 +49,26 @@ HistPlan make_plan(int n, int k, int ntau, int d) {
   bool les_bulk = n >= 2 * k + 1;
   p.njob = NJOB;
   int mout[NJOB] = {nb, ntau + 1, ntau + 1, les_bulk ? nb : 0, les_bulk ? nb : 0, les_bulk ? nb : 0,
-                    ntau + 1};
-  int span[NJOB] = {n, n, ntau + 1, n, nb > k + 1 ? nb : k + 1, ntau + 1, 1};
+                    ntau + 1, (les_bulk && p.staged) ? nb : 0};
+  int span[NJOB] = {n, n, ntau + 1, n, nb > k + 1 ? nb : k + 1, ntau + 1, 1, nb};
+  for (int j = 0; j < NJOB; j++) {
+    if (p.staged) {
+      // column jobs (one term, 64 outputs per wave step) and row jobs (16
+      // outputs x 4 terms per wave step)
+      bool row = j == 4 || j == 5 || j == 7;
+      p.tm[j] = row ? 16 : 64;
+      p.tj[j] = j == 2 ? STG_TJS : STG_TJ;
+    } else {
+      p.tm[j] = p.TM;
+      p.tj[j] = j == 2 ? p.TJS : p.TJ;
+    }
+  }
   long off = 0;
   p.wg_off[0] = 0;
   for (int j = 0; j < NJOB; j++) {
     p.mout[j] = mout[j];
-    int tj = j == 2 ? p.TJS : p.TJ;  // tau-source chunk
-    p.nch[j] = mout[j] > 0 ? cdiv_i(span[j], tj) : 0;
-    p.mtiles[j] = mout[j] > 0 ? cdiv_i(mout[j], p.TM) : 0;
+    p.nch[j] = mout[j] > 0 ? cdiv_i(span[j], p.tj[j]) : 0;
+    p.mtiles[j] = mout[j] > 0 ? cdiv_i(mout[j], p.tm[j]) : 0;
     if (j == 6) p.nch[j] = p.mtiles[j] = 1;  // one workgroup: both tau ends
     p.wg_off[j + 1] = p.wg_off[j] + p.nch[j] * p.mtiles[j];
     p.part_off[j] = off;
@@ -675,6 +695,303 @@ __device__ void tau_blk(const Prob& P, const Scratch& sc, int pi, int n, const H
   wave_sum_store<D>(acc, lds, valid, sc.part(pi) + (pl.part_off[2] + (long)ch * (ntau + 1) + m) * DD);
 }
 
+// ------------------------------------------- HISTORY, staged through LDS
+// d = 1, 2, 4. One wave step covers 64 history blocks. They are copied
+// HBM -> LDS with direct-to-LDS loads in which every instruction reads 1 KB of
+// contiguous memory (lane L loads 16 B), then each lane reads its own block
+// from LDS and multiplies it from registers. The LDS copy of a step keeps one
+// spare 16 B unit per 1 KB, and block b goes to lane ilane(b), so that the
+// lanes' block reads are free of bank conflicts. While a lane multiplies the
+// block of step s, the copy of step s + 1 is in flight.
+//
+// Column steps: 64 consecutive outputs m at one term j (blocks contiguous in
+// one stored slice). Row steps: 16 outputs m at 4 consecutive terms (each
+// output's 4 blocks contiguous in its own slice).
+#if defined(__HIP_DEVICE_COMPILE__)
+#define CNTR_LDS __attribute__((address_space(3)))
+#else
+#define CNTR_LDS
+#endif
+
+template <int D>
+struct Stg {
+  static constexpr int DD = D * D;
+  static constexpr int NI = DD;         // copy instructions per step
+  static constexpr int BPI = 64 / DD;   // blocks per instruction
+  static constexpr int WBUF = NI * 65;  // 16 B units per wave buffer
+  // block handled by a lane, and the lane handling a block
+  __device__ static inline int blk(int lane) { return BPI * (lane % NI) + lane / NI; }
+  // LDS unit of piece e of block b
+  __device__ static inline int unit(int b, int e) {
+    int P = b * DD + e;
+    return P + P / 64;
+  }
+};
+
+// Copy the 64 blocks of one step into wbuf; baddr(b) gives block b (readable).
+template <int D, class BAddr>
+__device__ inline void stg_copy(cplx* wbuf, BAddr baddr) {
+  using S = Stg<D>;
+  int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int i = 0; i < S::NI; i++) {
+    int P = i * 64 + lane, b = P / S::DD, e = P % S::DD;
+    gcp src = baddr(b) + e;
+    __builtin_amdgcn_global_load_lds((const CNTR_GLOBAL void*)src, (CNTR_LDS void*)(wbuf + i * 65), 16, 0, 0);
+  }
+}
+
+// The steps s = 0..nsteps-1 of one wave: baddr(s, b), add(s, H).
+template <int D, class BAddr, class Add>
+__device__ inline void stg_loop(int nsteps, cplx* wbuf, BAddr baddr, Add add) {
+  using S = Stg<D>;
+  constexpr int DD = D * D;
+  if (nsteps <= 0) return;
+  int lane = threadIdx.x & 63, b = S::blk(lane);
+  stg_copy<D>(wbuf, [&](int bb) { return baddr(0, bb); });
+  for (int s = 0; s < nsteps; s++) {
+    cplx H[DD];
+#pragma unroll
+    for (int e = 0; e < DD; e++) H[e] = wbuf[S::unit(b, e)];
+    // the buffer is free once the reads are done; copy the next step
+    __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0)
+    if (s + 1 < nsteps) stg_copy<D>(wbuf, [&](int bb) { return baddr(s + 1, bb); });
+    add(s, H);
+  }
+}
+
+// Adds the 4 x 64 lane sums of the workgroup (fixed order) into the partials
+// of the tile's outputs. Column tiles: lane b of every wave adds to output b;
+// row tiles: lanes of blocks 4o..4o+3 of every wave add to output o.
+template <int D>
+__device__ inline void stg_sum_store(cplx (&acc)[D * D], cplx* red, bool row, int m0, int mout,
+                                     cplx* dst0) {
+  using S = Stg<D>;
+  constexpr int DD = D * D;
+  int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  __syncthreads();
+#pragma unroll
+  for (int e = 0; e < DD; e++) red[(wave * DD + e) * 64 + lane] = acc[e];
+  __syncthreads();
+  int nout = row ? 16 : 64, ncon = row ? 4 : 1;
+  for (int v = tid; v < nout * DD; v += NTHR) {
+    int o = v / DD, e = v % DD;
+    int m = m0 + o;
+    if (m >= mout) continue;
+    cplx sum = mk(0, 0);
+    for (int w = 0; w < 4; w++)
+      for (int r = 0; r < ncon; r++) {
+        int b = row ? 4 * o + r : o;
+        int L = S::NI * (b % S::BPI) + b / S::BPI;
+        sum = sum + red[(w * DD + e) * 64 + L];
+      }
+    gst(dst0 + (size_t)m * DD + e, sum);
+  }
+}
+
+template <int D>
+__device__ void hist_stg(const Prob& P, const Scratch& sc, int pi, int n, const HistPlan& pl, int job,
+                         int mt, int ch, cplx* lds, cplx* sh) {
+  using S = Stg<D>;
+  constexpr int DD = D * D;
+  constexpr int K1 = KMAX + 1;
+  const KW& W = c_kw[P.k];
+  __shared__ double s_om[K1];
+  __shared__ double s_s[K1 * K1];
+  WReg wr;
+  wr.load(W, s_om);
+  int k = P.k, ntau = P.ntau, tid = threadIdx.x, lane = tid & 63;
+  int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  if (tid < K1 * K1) s_s[tid] = W.s[tid / K1][tid % K1];
+  bool row = job == 4 || job == 5 || job == 7;
+  int TJ = pl.tj[job], TMj = pl.tm[job], mout = pl.mout[job];
+  int m0 = mt * TMj, mhi = min(m0 + TMj, mout) - 1;
+  int j0 = ch * TJ;
+  if ((job == 0 || job == 3) && j0 + TJ - 1 < m0) return;  // terms j >= m only
+  if (job == 4 && j0 > max(mhi, k)) return;                // terms j <= max(m, k)
+  if (job == 7 && j0 >= mhi) return;                       // terms l < m
+  cplx* wbuf = lds + wave * S::WBUF;
+  gcp Gret = G(P.Gret), Gles = G(P.Gles), Gtv = G(P.Gtv);
+  size_t T1 = (size_t)n * (ntau + 1), NT1 = ntau + 1;
+  for (int idx = tid; idx < TJ * DD; idx += NTHR) {
+    int jj = idx / DD, ee = idx % DD, j = j0 + jj;
+    cplx v = mk(0, 0);
+    switch (job) {
+      case 0:
+      case 1:
+      case 3:
+      case 7:
+        if (j < n) v = gld(P.Sret + (tri(n) + j) * DD + ee);
+        break;
+      case 4:
+        if (j <= n) v = gld(P.Sles + (tri(n) + j) * DD + ee);
+        break;
+      case 5:
+        if (j <= ntau) v = gld(P.Stv + (T1 + ntau - j) * DD + ee);
+        break;
+    }
+    sh[idx] = v;
+  }
+  __syncthreads();
+  cplx acc[DD];
+#pragma unroll
+  for (int e = 0; e < DD; e++) acc[e] = mk(0, 0);
+  double xi = P.sig;
+  int b = S::blk(lane);
+  // this lane's output, and for row steps its term offset
+  int mo = row ? m0 + b / 4 : m0 + b, r4 = b % 4;
+  bool valid = mo < mout;
+  int mc = valid ? mo : mhi;
+  int je;  // end of the chunk's terms (exclusive)
+  switch (job) {
+    case 4: je = min(max(mhi, k) + 1, j0 + TJ); break;
+    case 5: je = min(ntau + 1, j0 + TJ); break;
+    case 7: je = min(mhi, j0 + TJ); break;
+    default: je = min(n, j0 + TJ); break;
+  }
+  int jl = je - 1;  // last term of the chunk (clamp for addresses)
+  if (!row) {
+    // column steps: term j = j0 + wave + 4 s, outputs m0 + b
+    int nst = je > j0 + wave ? (je - j0 - wave + 3) / 4 : 0;
+    auto jof = [&](int s) { return min(j0 + wave + 4 * s, jl); };
+    auto mcl = [&](int bb) { return min(m0 + bb, mhi); };
+    switch (job) {
+      case 0:  // sum_j w(n-m, j-m) S^R_{n,j} R_{j,m}, j >= m
+        stg_loop<D>(
+            nst, wbuf, [&](int s, int bb) { int j = jof(s); return Gret + (tri(j) + min(mcl(bb), j)) * DD; },
+            [&](int s, const cplx(&H)[DD]) {
+              int j = j0 + wave + 4 * s;
+              double w = (valid && j < je && j >= mo) ? wr.w(n - mo, j - mo) : 0.0;
+              f_left<D>(acc, w, sh + (min(j, jl) - j0) * DD, H);
+            });
+        break;
+      case 1:  // sum_j w(n,j) S^R_{n,j} T_{j,m}
+        stg_loop<D>(
+            nst, wbuf, [&](int s, int bb) { return Gtv + ((size_t)jof(s) * NT1 + mcl(bb)) * DD; },
+            [&](int s, const cplx(&H)[DD]) {
+              int j = j0 + wave + 4 * s;
+              double w = (valid && j < je) ? wr.w(n, j) : 0.0;
+              f_left<D>(acc, w, sh + (min(j, jl) - j0) * DD, H);
+            });
+        break;
+      case 3:  // sum_{l >= m} w(n,l) L_{m,l} (S^R_{n,l})^dag
+        stg_loop<D>(
+            nst, wbuf, [&](int s, int bb) { int l = jof(s); return Gles + (tri(l) + min(mcl(bb), l)) * DD; },
+            [&](int s, const cplx(&H)[DD]) {
+              int l = j0 + wave + 4 * s;
+              double w = (valid && l < je && l >= mo) ? wr.w(n, l) : 0.0;
+              f_right_c<D>(acc, w, sh + (min(l, jl) - j0) * DD, H);
+            });
+        break;
+    }
+  } else {
+    // row steps: terms jb + 0..3 with jb = j0 + 4 wave + 16 s, outputs m0 + b / 4
+    int nst = je > j0 + 4 * wave ? (je - j0 - 4 * wave + 15) / 16 : 0;
+    auto tof = [&](int s, int bb) { return j0 + 4 * wave + 16 * s + bb % 4; };
+    auto mcl = [&](int bb) { return min(m0 + bb / 4, mhi); };
+    switch (job) {
+      case 4: {  // sum_j w(m,j) R~_{m,j} S^<_{j,n}, j <= max(m,k)
+        int jmax = mc > k ? mc : k;
+        stg_loop<D>(
+            nst, wbuf,
+            [&](int s, int bb) {
+              int m = mcl(bb), jm = m > k ? m : k, j = min(min(tof(s, bb), jl), jm);
+              return j <= m ? Gret + (tri(m) + j) * DD : Gret + (tri(j) + m) * DD;
+            },
+            [&](int s, const cplx(&H)[DD]) {
+              int j = j0 + 4 * wave + 16 * s + r4;
+              double w = 0.0;
+              if (valid && j < je && j <= jmax) w = mo > k ? wr.w(mo, j) : s_s[mo * K1 + j];
+              const cplx* Sb = sh + (min(j, jl) - j0) * DD;
+              if (j <= mc || !(j <= jmax)) f_right<D>(acc, w, Sb, H);
+              else f_right_t<D>(acc, w, Sb, H);
+            });
+      } break;
+      case 5:  // sum_j (-xi) w(ntau,j) T_{m,j} (S^rceil_{n,ntau-j})^dag
+        stg_loop<D>(
+            nst, wbuf, [&](int s, int bb) { return Gtv + ((size_t)mcl(bb) * NT1 + min(tof(s, bb), jl)) * DD; },
+            [&](int s, const cplx(&H)[DD]) {
+              int j = j0 + 4 * wave + 16 * s + r4;
+              double w = (valid && j < je) ? -xi * wr.w(ntau, j) : 0.0;
+              f_right_c<D>(acc, w, sh + (min(j, jl) - j0) * DD, H);
+            });
+        break;
+      case 7:  // sum_{l < m} w(n,l) L^_{m,l} (S^R_{n,l})^dag, L^_{m,l} = -(L_{l,m})^dag
+        stg_loop<D>(
+            nst, wbuf,
+            [&](int s, int bb) {
+              int m = mcl(bb), l = min(min(tof(s, bb), jl), max(m - 1, 0));
+              return Gles + (tri(m) + l) * DD;
+            },
+            [&](int s, const cplx(&H)[DD]) {
+              int l = j0 + 4 * wave + 16 * s + r4;
+              double w = (valid && l < je && l < mo) ? wr.w(n, l) : 0.0;
+              f_right_tc<D>(acc, w, sh + (min(l, jl) - j0) * DD, H);
+            });
+        break;
+    }
+  }
+  stg_sum_store<D>(acc, lds, row, m0, mout, sc.part(pi) + (pl.part_off[job] + (long)ch * mout) * DD);
+}
+
+// Tau source (Gregory parts of Eqs. ctv2, ctv3), column steps over J: band 1
+// xi w(m,J) Sigma^rceil_{n,m-J} G^M_{ntau-J} (m > k, J <= m) and band 2
+// w(ntau-m, J-m) Sigma^rceil_{n,J} G^M_{J-m} (m < ntau-k, J >= m).
+template <int D>
+__device__ void tau_stg(const Prob& P, const Scratch& sc, int pi, int n, const HistPlan& pl, int mt, int ch,
+                        cplx* lds, cplx* sh) {
+  using S = Stg<D>;
+  constexpr int DD = D * D;
+  const KW& W = c_kw[P.k];
+  __shared__ double s_om[KMAX + 1];
+  cplx* sA = sh;                   // Sigma^rceil_{n,J}
+  cplx* sB = sh + STG_TJS * DD;    // G^M_{ntau-J}
+  WReg wr;
+  wr.load(W, s_om);
+  int k = P.k, ntau = P.ntau, tid = threadIdx.x, lane = tid & 63;
+  int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  int TJS = pl.tj[2];
+  int m0 = mt * 64, j0 = ch * TJS;
+  const cplx* Srow = P.Stv + (size_t)n * (ntau + 1) * DD;
+  gcp gS = G(Srow), gM = G(P.Gmat);
+  for (int idx = tid; idx < TJS * DD; idx += NTHR) {
+    int J = j0 + idx / DD, ee = idx % DD;
+    bool in = J <= ntau;
+    sA[idx] = in ? gld(Srow + (size_t)J * DD + ee) : mk(0, 0);
+    sB[idx] = in ? gld(P.Gmat + (size_t)(ntau - J) * DD + ee) : mk(0, 0);
+  }
+  __syncthreads();
+  cplx* wbuf = lds + wave * S::WBUF;
+  cplx acc[DD];
+#pragma unroll
+  for (int e = 0; e < DD; e++) acc[e] = mk(0, 0);
+  double xi = P.sig;
+  int b = S::blk(lane), m = m0 + b;
+  bool valid = m <= ntau;
+  int je = min(ntau + 1, j0 + TJS), jl = je - 1;
+  int nst = je > j0 + wave ? (je - j0 - wave + 3) / 4 : 0;
+  auto mcl = [&](int bb) { return min(m0 + bb, ntau); };
+  // steps 0..nst-1: band 1 at J = j0 + wave + 4 s; steps nst..2 nst-1: band 2
+  stg_loop<D>(
+      2 * nst, wbuf,
+      [&](int s, int bb) {
+        int J = min(j0 + wave + 4 * (s < nst ? s : s - nst), jl), mm = mcl(bb);
+        return s < nst ? gS + (size_t)max(mm - J, 0) * DD : gM + (size_t)max(J - mm, 0) * DD;
+      },
+      [&](int s, const cplx(&H)[DD]) {
+        int J = j0 + wave + 4 * (s < nst ? s : s - nst);
+        int Jc = min(J, jl);
+        if (s < nst) {
+          double w = (valid && J < je && m > k && J <= m) ? xi * wr.w(m, J) : 0.0;
+          f_right<D>(acc, w, sB + (Jc - j0) * DD, H);
+        } else {
+          double w = (valid && J < je && m < ntau - k && J >= m) ? wr.w(ntau - m, J - m) : 0.0;
+          f_left<D>(acc, w, sA + (Jc - j0) * DD, H);
+        }
+      });
+  stg_sum_store<D>(acc, lds, false, m0, ntau + 1, sc.part(pi) + (pl.part_off[2] + (long)ch * (ntau + 1)) * DD);
+}
+
 // ------------------------------------------------------------- HISTORY
 template <int D>
 __global__ __launch_bounds__(NTHR) void k_history(ProbArg pa, Scratch sc, HistPlan pl) {
@@ -682,13 +999,18 @@ __global__ __launch_bounds__(NTHR) void k_history(ProbArg pa, Scratch sc, HistPl
   constexpr int TM = NTHR / DD > 0 ? NTHR / DD : 1;
   constexpr int TJ = D >= 8 ? 32 : 64;
   constexpr int PREPN = (KMAX * D) * (KMAX * D) + KMAX * D * D + 4 * DD + (KMAX + 1) * (KMAX + 1) * DD +
-                        (KMAX + 1) * DD;
+                        (KMAX + 1) * DD + (D <= 4 ? (KMAX + 1) * (KMAX + 1) * DD : 0);
   constexpr int TSN = 2 * (D >= 8 ? 16 : 32) * DD + 2 * (TM + (D >= 8 ? 16 : 32) - 1) * DD;
   constexpr int LDSA = (2 * TJ * DD) > PREPN ? (2 * TJ * DD) : PREPN;
   constexpr int LDSB = LDSA > TSN ? LDSA : TSN;
-  constexpr int LDSR = D <= 4 ? 3 * DD * 64 : 0;  // wave sums of the block-per-lane path
-  constexpr int LDSN = LDSB > LDSR ? LDSB : LDSR;
+  constexpr int LDSR0 = D <= 4 ? 3 * DD * 64 : 0;  // wave sums of the block-per-lane path
+  constexpr int LDSR = (D == 1 || D == 2 || D == 4) ? 4 * Stg<D>::WBUF : LDSR0;  // staged path buffers
+  constexpr bool STG = D == 1 || D == 2 || D == 4;
+  constexpr int LDSN = STG ? (PREPN > LDSR ? PREPN : LDSR) : (LDSB > LDSR ? LDSB : LDSR);
   __shared__ cplx lds[LDSN];
+  // shared operand of a staged chunk (a separate array: its reads never wait
+  // for the copies in flight into lds)
+  __shared__ cplx shop[STG ? STG_TJ * DD : 1];
   int pi = blockIdx.y;
   const Prob& P = pa.get(pi);
   int n = pl.n;
@@ -707,7 +1029,11 @@ __global__ __launch_bounds__(NTHR) void k_history(ProbArg pa, Scratch sc, HistPl
     tau_boundary<D>(P, sc, pi, n, pl, lds);
     return;
   }
-  if constexpr (D <= 4) {
+  if constexpr (D == 1 || D == 2 || D == 4) {
+    if (job == 2) tau_stg<D>(P, sc, pi, n, pl, mt, ch, lds, shop);
+    else hist_stg<D>(P, sc, pi, n, pl, job, mt, ch, lds, shop);
+    return;
+  } else if constexpr (D <= 4) {
     if (job == 2) tau_blk<D>(P, sc, pi, n, pl, mt, ch, lds);
     else hist_blk<D>(P, sc, pi, n, pl, job, mt, ch, lds);
     return;
@@ -903,7 +1229,6 @@ template <int D>
 __global__ __launch_bounds__(NTHR) void k_reduce(ProbArg pa, Scratch sc, HistPlan pl) {
   constexpr int DD = D * D;
   constexpr int TM = NTHR / DD > 0 ? NTHR / DD : 1;
-  const int TJ = pl.TJ;
   constexpr int NVMAX = (KMAX + 1) * DD;
   constexpr int NSTAGE = NVMAX > NTHR ? NVMAX : NTHR;
   __shared__ cplx outs[TM * DD];
@@ -960,7 +1285,7 @@ __global__ __launch_bounds__(NTHR) void k_reduce(ProbArg pa, Scratch sc, HistPla
     long cs = (long)mout * DD;  // stride between the chunks of one output
     auto pp = [&](int job, int ch0) { return part + (pl.part_off[job] + (long)ch0 * mout + m) * DD + e; };
     if (fam == 0) {
-      int c0 = m / TJ;
+      int c0 = m / pl.tj[0];
       cplx hs = psum(pp(0, c0), cs, pl.nch[0] - c0);
       cplx bd = bdf_sum(W, k, h, [&](int l) { return P.Gret + (tri(n - l) + m) * DD + e; });
       r = bd - h * mul_i(hs);
@@ -973,8 +1298,11 @@ __global__ __launch_bounds__(NTHR) void k_reduce(ProbArg pa, Scratch sc, HistPla
       r = bd - mul_i(ts) - h * mul_i(hs);
     } else {
       int jmax = m > k ? m : k;
-      cplx s3 = psum(pp(3, 0), cs, pl.nch[3]);
-      cplx s4 = psum(pp(4, 0), cs, jmax / TJ + 1);
+      // lesser history: one job over all l, or (staged) l >= m and l < m
+      int c3 = pl.staged ? m / pl.tj[3] : 0;
+      cplx s3 = psum(pp(3, c3), cs, pl.nch[3] - c3);
+      if (pl.staged && m > 0) s3 = s3 + psum(pp(7, 0), cs, (m - 1) / pl.tj[7] + 1);
+      cplx s4 = psum(pp(4, 0), cs, jmax / pl.tj[4] + 1);
       cplx s5 = psum(pp(5, 0), cs, pl.nch[5]);
       cplx bd = bdf_sum(W, k, h, [&](int l) { return P.Gles + (tri(n - l) + m) * DD + e; });
       r = bd + h * mul_i(s4) + ht * s5 + h * mul_i(s3);
