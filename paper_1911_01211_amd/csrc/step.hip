@@ -74,6 +74,24 @@ HistPlan make_plan(int n, int k, int ntau, int d) {
     p.part_off[j] = off;
     off += (long)p.nch[j] * mout[j];
   }
+  p.grid = p.wg_off[NJOB];
+  // Band order pays once the history panels of a problem no longer fit in the
+  // 256 MB last-level (Infinity) cache, so that a block's second consumer
+  // would otherwise read it from HBM again.
+  double hist_bytes = 16.0 * d * d * ((double)n * (n + 1) + (double)n * (ntau + 1));
+  p.banded = p.staged && hist_bytes > 160e6;
+  if (p.banded) {
+    static const int BJ[6] = {0, 4, 1, 5, 3, 7};
+    p.nband = p.nch[0];
+    p.bo[0] = 0;
+    for (int i = 0; i < 6; i++) {
+      int j = BJ[i];
+      bool row = j == 4 || j == 5 || j == 7;
+      p.bo[i + 1] = p.bo[i] + (row ? 2 * p.nch[j] : p.mtiles[j]);
+    }
+    p.wpb = p.bo[6];
+    p.grid = p.nband * p.wpb + p.nch[2] * p.mtiles[2] + 1;
+  }
   // reduce tiles (retarded, mixing, lesser) and the per-tile partial sums of
   // the k+1 lesser boundary rows
   // (k_reduce: one output element per thread, NTHR / d^2 outputs per tile)
@@ -1021,10 +1039,39 @@ __global__ __launch_bounds__(NTHR) void k_history(ProbArg pa, Scratch sc, HistPl
     prep_step<D>(P, sc, pi, n, lds);
     return;
   }
-  int job = 0;
-  while (b >= pl.wg_off[job + 1]) job++;
-  int local = b - pl.wg_off[job];
-  int mt = local / pl.nch[job], ch = local % pl.nch[job];
+  int job = 0, mt, ch;
+  if (pl.banded) {
+    // tau source and tau boundary first (short, latency-bound), then the bands
+    int ntw = pl.nch[2] * pl.mtiles[2];
+    if (b < ntw) {
+      job = 2;
+      mt = b / pl.nch[2];
+      ch = b % pl.nch[2];
+    } else if (b == ntw) {
+      job = 6;
+      mt = ch = 0;
+    } else {
+      b -= ntw + 1;
+      int c = b / pl.wpb, r = b % pl.wpb, i = 0;
+      while (r >= pl.bo[i + 1]) i++;
+      const int BJ[6] = {0, 4, 1, 5, 3, 7};
+      job = BJ[i];
+      int local = r - pl.bo[i];
+      if (job == 4 || job == 5 || job == 7) {
+        mt = 2 * c + local / pl.nch[job];
+        ch = local % pl.nch[job];
+      } else {
+        mt = local;
+        ch = c;
+      }
+      if (mt >= pl.mtiles[job] || ch >= pl.nch[job]) return;
+    }
+  } else {
+    while (b >= pl.wg_off[job + 1]) job++;
+    int local = b - pl.wg_off[job];
+    mt = local / pl.nch[job];
+    ch = local % pl.nch[job];
+  }
   if (job == 6) {
     tau_boundary<D>(P, sc, pi, n, pl, lds);
     return;
@@ -1745,7 +1792,7 @@ static hipError_t step_d(const ProbArg& pa, const Scratch& sc, int n, hipStream_
   const Prob& P0 = pa.one;  // d, k and ntau are uniform within a call
   int k = P0.k, ntau = P0.ntau;
   HistPlan pl = make_plan(n, k, ntau, D);
-  dim3 g1(pl.wg_off[NJOB] + 1, pa.count);
+  dim3 g1(pl.grid + 1, pa.count);
   hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr;
   if (g_prof.on) {
     e0 = prof_event();
