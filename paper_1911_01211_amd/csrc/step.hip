@@ -1258,13 +1258,33 @@ __device__ inline cplx psum(const cplx* p, long stride, int cnt) {
   return ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
 }
 
+// Sums of NS sequences p[s][i * stride], i < cnt[s]: the first eight terms of
+// every sequence are loaded together (one memory round when all counts are
+// <= 8), longer tails follow with psum. Fixed summation order.
+template <int NS>
+__device__ inline void msum(const cplx* const (&p)[NS], const int (&cnt)[NS], long stride, cplx (&out)[NS]) {
+  cplx v[NS][8];
+#pragma unroll
+  for (int q = 0; q < NS; q++)
+#pragma unroll
+    for (int u = 0; u < 8; u++) v[q][u] = u < cnt[q] ? gld(p[q] + (long)u * stride) : mk(0, 0);
+#pragma unroll
+  for (int q = 0; q < NS; q++) {
+    out[q] = ((v[q][0] + v[q][1]) + (v[q][2] + v[q][3])) + ((v[q][4] + v[q][5]) + (v[q][6] + v[q][7]));
+    if (cnt[q] > 8) out[q] = out[q] + psum(p[q] + 8 * stride, stride, cnt[q] - 8);
+  }
+}
+
 // BDF part -h^-1 sum_{l=1..k} a_l X_{n-l} of one element; x(l) gives the
 // address of X_{n-l} (all loads issued together).
+// (bdf_load issues the loads; bdf_add combines them later, so that other
+// loads can be issued in between.)
 template <class F>
-__device__ inline cplx bdf_sum(const KW& W, int k, double h, F x) {
-  cplx v[KMAX];
+__device__ inline void bdf_load(int k, F x, cplx (&v)[KMAX]) {
 #pragma unroll
   for (int l = 1; l <= KMAX; l++) v[l - 1] = l <= k ? gld(x(l)) : mk(0, 0);
+}
+__device__ inline cplx bdf_add(const KW& W, int k, double h, const cplx (&v)[KMAX]) {
   cplx r = mk(0, 0);
 #pragma unroll
   for (int l = 1; l <= KMAX; l++)
@@ -1284,6 +1304,7 @@ __global__ __launch_bounds__(NTHR) void k_reduce(ProbArg pa, Scratch sc, HistPla
   __shared__ cplx lrow[NVMAX];
   __shared__ cplx stage[NSTAGE];
   __shared__ cplx sigs[(KMAX + 1) * TM * DD];
+  __shared__ double twt[(KMAX + 1) * TM];  // quadrature weights of the tile terms
   __shared__ cplx ser[(KMAX * (KMAX + 1) / 2 + 2 * KMAX + 1) * DD];
   __shared__ int is_last;
   int pi = blockIdx.y;
@@ -1326,33 +1347,52 @@ __global__ __launch_bounds__(NTHR) void k_reduce(ProbArg pa, Scratch sc, HistPla
       else v = gld(P.Sret + (tri(mr) + mm) * DD + ee);
       sigs[idx] = v;
     }
+    for (int idx = tid; idx < (k + 1) * nm; idx += NTHR) {
+      int r = idx / nm, mm = mlo + idx % nm;
+      double w;
+      if (fam == 0) w = greg(W, n, mm);
+      else if (fam == 1) w = -xi * greg(W, ntau, ntau - mm);
+      else w = greg(W, n - k + r, mm);
+      twt[idx] = w;
+    }
   }
   if (valid) {
     cplx r = mk(0, 0);
     long cs = (long)mout * DD;  // stride between the chunks of one output
     auto pp = [&](int job, int ch0) { return part + (pl.part_off[job] + (long)ch0 * mout + m) * DD + e; };
+    // every load of this output (partials, BDF history) in one round
     if (fam == 0) {
       int c0 = m / pl.tj[0];
-      cplx hs = psum(pp(0, c0), cs, pl.nch[0] - c0);
-      cplx bd = bdf_sum(W, k, h, [&](int l) { return P.Gret + (tri(n - l) + m) * DD + e; });
-      r = bd - h * mul_i(hs);
+      cplx bv[KMAX];
+      bdf_load(k, [&](int l) { return P.Gret + (tri(n - l) + m) * DD + e; }, bv);
+      const cplx* ps[1] = {pp(0, c0)};
+      int cn[1] = {pl.nch[0] - c0};
+      cplx sm[1];
+      msum<1>(ps, cn, cs, sm);
+      r = bdf_add(W, k, h, bv) - h * mul_i(sm[0]);
     } else if (fam == 1) {
-      cplx ts = psum(pp(2, 0), cs, pl.nch[2]);
-      if (m <= k || m >= ntau - k) ts = ts + gld(part + (pl.part_off[6] + m) * DD + e);
-      ts = ht * ts;
-      cplx hs = psum(pp(1, 0), cs, pl.nch[1]);
-      cplx bd = bdf_sum(W, k, h, [&](int l) { return P.Gtv + ((size_t)(n - l) * (ntau + 1) + m) * DD + e; });
-      r = bd - mul_i(ts) - h * mul_i(hs);
+      cplx bv[KMAX];
+      bdf_load(k, [&](int l) { return P.Gtv + ((size_t)(n - l) * (ntau + 1) + m) * DD + e; }, bv);
+      cplx tb = (m <= k || m >= ntau - k) ? gld(part + (pl.part_off[6] + m) * DD + e) : mk(0, 0);
+      const cplx* ps[2] = {pp(2, 0), pp(1, 0)};
+      int cn[2] = {pl.nch[2], pl.nch[1]};
+      cplx sm[2];
+      msum<2>(ps, cn, cs, sm);
+      cplx ts = ht * (sm[0] + tb);
+      r = bdf_add(W, k, h, bv) - mul_i(ts) - h * mul_i(sm[1]);
     } else {
       int jmax = m > k ? m : k;
+      cplx bv[KMAX];
+      bdf_load(k, [&](int l) { return P.Gles + (tri(n - l) + m) * DD + e; }, bv);
       // lesser history: one job over all l, or (staged) l >= m and l < m
       int c3 = pl.staged ? m / pl.tj[3] : 0;
-      cplx s3 = psum(pp(3, c3), cs, pl.nch[3] - c3);
-      if (pl.staged && m > 0) s3 = s3 + psum(pp(7, 0), cs, (m - 1) / pl.tj[7] + 1);
-      cplx s4 = psum(pp(4, 0), cs, jmax / pl.tj[4] + 1);
-      cplx s5 = psum(pp(5, 0), cs, pl.nch[5]);
-      cplx bd = bdf_sum(W, k, h, [&](int l) { return P.Gles + (tri(n - l) + m) * DD + e; });
-      r = bd + h * mul_i(s4) + ht * s5 + h * mul_i(s3);
+      int n7 = (pl.staged && m > 0) ? (m - 1) / pl.tj[7] + 1 : 0;
+      const cplx* ps[4] = {pp(3, c3), pl.staged ? pp(7, 0) : part, pp(4, 0), pp(5, 0)};
+      int cn[4] = {pl.nch[3] - c3, n7, jmax / pl.tj[4] + 1, pl.nch[5]};
+      cplx sm[4];
+      msum<4>(ps, cn, cs, sm);
+      cplx s3 = sm[0] + sm[1];
+      r = bdf_add(W, k, h, bv) + h * mul_i(sm[2]) + ht * sm[3] + h * mul_i(s3);
     }
     outs[mo * DD + e] = r;
   }
@@ -1388,15 +1428,15 @@ __global__ __launch_bounds__(NTHR) void k_reduce(ProbArg pa, Scratch sc, HistPla
       if (fam == 0) {  // Sigma^<_{mr,mm} = -[Sigma^<_{mm,mr}]^dag
 #pragma unroll
         for (int q = 0; q < D; q++) cfma_cb(s, -conj(sb[q * D + a2]), ob[c2 * D + q]);
-        acc = acc + greg(W, n, mm) * s;
+        acc = acc + twt[r * nm + mm - mlo] * s;
       } else if (fam == 1) {
 #pragma unroll
         for (int q = 0; q < D; q++) cfma_cb(s, sb[a2 * D + q], ob[c2 * D + q]);
-        acc = acc + (-xi * greg(W, ntau, ntau - mm)) * s;
+        acc = acc + twt[r * nm + mm - mlo] * s;
       } else {
 #pragma unroll
         for (int q = 0; q < D; q++) cfma(s, sb[a2 * D + q], ob[q * D + c2]);
-        acc = acc + greg(W, mr, mm) * s;
+        acc = acc + twt[r * nm + mm - mlo] * s;
       }
     }
     cplx coef = fam == 1 ? mk(-ht, 0) : mk(0, -h);
