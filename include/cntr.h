@@ -128,6 +128,25 @@ cntr_status cntr_sigma_2b(int32_t tstp, int32_t count, const cntr_grid* grids, c
                           const double* const* U, const cntr_gf* Sigma, const void* const* eps0,
                           void* const* eps_mf, double nbar, void* stream);
 
+/* ----------------------------------------------------------------- A13 --
+ * Observables of slice tstp >= 0, per spin (density matrix and Eq.
+ * Total_ener, the Galitskii-Migdal energy):
+ *   rho = i xi G^<(t, t)                              (d x d)
+ *   obs[5*i + 0] = Re Tr rho                          particle number
+ *   obs[5*i + 1] = Re Tr[rho eps0(t)]                 one-body energy
+ *   obs[5*i + 2] = Re Tr[rho eps_mf(t)]               (eps0 when eps_mf is NULL)
+ *   obs[5*i + 3] = 1/2 Im Tr[Sigma * G]^<(t, t)       correlation energy
+ *   obs[5*i + 4] = (obs[1] + obs[2]) / 2 + obs[3]     total energy
+ * The convolution [Sigma * G]^<(t_n, t_n) uses the Gregory weights of the
+ * time step (start weights for tstp <= k). eps0 / eps_mf: arrays of DEVICE
+ * pointers as in cntr_sigma_2b (eps_mf may be NULL). obs: DEVICE array of
+ * 5*count doubles; rho: DEVICE array of count d x d blocks, or NULL. Reads
+ * slice tstp of G and Sigma. */
+#define CNTR_NOBS 5
+cntr_status cntr_observables(int32_t tstp, int32_t count, const cntr_grid* grids, const cntr_gf* G,
+                             const cntr_gf* Sigma, const void* const* eps0, const void* const* eps_mf,
+                             double* obs, void* rho, void* stream);
+
 /* --------------------------------------------------------------- A10, A13 --
  * Polynomial predictor T[G]_tstp -> T[G]_{tstp+1} (Eq. polyextrap, App.
  * "Extrapolation of contour functions"); needs tstp >= k. */

@@ -188,6 +188,19 @@ def sigma_2b(n, G: HM, U, S: HM):
     lib().oracle_sigma_2b(n, C.byref(G.g.c()), *G.args(), _p(u), *S.args())
 
 
+def observables(n, G: HM, S: HM, eps0, eps_mf=None):
+    """Per-spin observables of slice n (density matrix, Eq. Total_ener):
+    [Re Tr rho, Re Tr rho eps0_n, Re Tr rho eps_mf_n, 1/2 Im Tr [S*G]^<(n,n),
+    total energy], and rho."""
+    em = eps0 if eps_mf is None else eps_mf
+    rho = density_matrix(n, G)
+    ec = conv_les_diag(n, S, G)
+    e1 = np.trace(rho @ eps0[n + 1]).real
+    emf = np.trace(rho @ em[n + 1]).real
+    ecorr = 0.5 * np.trace(ec).imag
+    return np.array([np.trace(rho).real, e1, emf, ecorr, 0.5 * (e1 + emf) + ecorr]), rho
+
+
 def hartree(n, G: HM, U, eps0, eps_mf, nbar=0.5):
     lib().oracle_hartree(n, C.byref(G.g.c()), *G.args(), _p(np.ascontiguousarray(U, np.float64)),
                          _p(eps0), _p(eps_mf), C.c_double(nbar))

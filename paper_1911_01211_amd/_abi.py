@@ -18,7 +18,7 @@ STATUS = {0: "CNTR_OK", -1: "CNTR_EINVAL", -2: "CNTR_ESHAPE", -3: "CNTR_EORDER",
 SYMBOLS = ["cntr_init_matsubara", "cntr_dyson_step", "cntr_convolution", "cntr_sigma_2b",
            "cntr_extrapolate", "cntr_distance", "cntr_copy_slice", "cntr_solve_2b", "cntr_sync",
            "cntr_last_error", "cntr_finalize", "cntr_version", "cntr_profile_begin",
-           "cntr_profile_end"]
+           "cntr_profile_end", "cntr_observables"]
 
 
 class CntrError(RuntimeError):

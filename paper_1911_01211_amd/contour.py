@@ -96,6 +96,25 @@ def sigma_2b(tstp: int, G: list, U: list, Sigma: list, eps0=None, eps_mf=None, n
                                nbar, _stream(stream)))
 
 
+OBS_NAMES = ("N", "E1", "Emf", "Ecorr", "Etot")
+
+
+def observables(tstp: int, G: list, Sigma: list, eps0: list, eps_mf=None, stream=None):
+    """Per-spin observables of slice tstp (cntr_observables): a (count, 5)
+    float64 device tensor [N, Tr rho eps0, Tr rho eps_mf, E_corr, E_total] and
+    the (count, d, d) density matrices."""
+    import torch
+    dev = G[0].mat.device
+    d = G[0].g.d
+    obs = torch.empty((len(G), 5), dtype=torch.float64, device=dev)
+    rho = torch.empty((len(G), d, d), dtype=torch.complex128, device=dev)
+    em = None if eps_mf is None else _ptrs(eps_mf)
+    _abi.check(_abi.lib().cntr_observables(tstp, len(G), _grids(G), _gfs(G), _gfs(Sigma), _ptrs(eps0), em,
+                                           C.c_void_p(obs.data_ptr()), C.c_void_p(rho.data_ptr()),
+                                           _stream(stream)))
+    return obs, rho
+
+
 def extrapolate(tstp: int, G: list, stream=None):
     _abi.check(_abi.lib().cntr_extrapolate(tstp, len(G), _grids(G), _gfs(G), _stream(stream)))
 

@@ -502,6 +502,36 @@ cntr_status cntr_sigma_2b(int32_t tstp, int32_t count, const cntr_grid* grids, c
   return CNTR_OK;
 }
 
+cntr_status cntr_observables(int32_t tstp, int32_t count, const cntr_grid* grids, const cntr_gf* G,
+                             const cntr_gf* Sigma, const void* const* eps0, const void* const* eps_mf,
+                             double* obs, void* rho, void* stream) {
+  cntr_status st = check_batch(count, grids, "cntr_observables");
+  if (st) return st;
+  if (!gf_ok(G, count) || !gf_ok(Sigma, count) || !eps0 || !obs)
+    return fail(CNTR_ESHAPE, "cntr_observables: null pointer");
+  int ntmax = 0;
+  for (int i = 0; i < count; i++) {
+    if (!eps0[i]) return fail(CNTR_ESHAPE, "cntr_observables: null eps0");
+    ntmax = grids[i].nt > ntmax ? grids[i].nt : ntmax;
+  }
+  if (tstp < 0 || tstp > ntmax) return fail(CNTR_EORDER, "cntr_observables: tstp outside 0..nt");
+  if ((st = ensure_weights())) return st;
+  hipStream_t s = (hipStream_t)stream;
+  StreamScratch* sc = scratch_for(s);
+  if ((st = grow(s, sc, 256, 5 * (size_t)count, 2))) return st;
+  std::vector<Prob> v(count);
+  for (int i = 0; i < count; i++) {
+    v[i] = make_prob(grids[i], &G[i], &Sigma[i], nullptr);
+    v[i].eps0 = (const cplx*)eps0[i];
+    v[i].eps_mf = eps_mf ? (cplx*)eps_mf[i] : nullptr;
+  }
+  ProbArg pa;
+  if ((st = make_arg(s, sc, v, 0, &pa))) return st;
+  hipError_t e = launch_observables(pa, tstp, obs, (cplx*)rho, s);
+  if (e != hipSuccess) return hip_fail(e, "cntr_observables launch");
+  return CNTR_OK;
+}
+
 cntr_status cntr_extrapolate(int32_t tstp, int32_t count, const cntr_grid* grids, const cntr_gf* G,
                              void* stream) {
   cntr_status st = check_batch(count, grids, "cntr_extrapolate");

@@ -65,6 +65,16 @@ __device__ inline cplx les_any(const cplx* X, int a, int b, int r, int c) {
   return -conj(X[(tri(a) + b) * D * D + c * D + r]);
 }
 
+// The same for a block size d known only at run time.
+__device__ inline cplx ret_ext_d(const cplx* X, int a, int b, int r, int c, int d) {
+  if (a >= b) return X[(tri(a) + b) * d * d + r * d + c];
+  return -conj(X[(tri(b) + a) * d * d + c * d + r]);
+}
+__device__ inline cplx les_any_d(const cplx* X, int a, int b, int r, int c, int d) {
+  if (a <= b) return X[(tri(b) + a) * d * d + r * d + c];
+  return -conj(X[(tri(a) + b) * d * d + c * d + r]);
+}
+
 // Gauss-Jordan inverse of an n x n complex matrix in LDS (in place), with
 // partial pivoting, executed by the whole workgroup. piv: LDS int[n].
 // Returns false (uniformly) if singular.

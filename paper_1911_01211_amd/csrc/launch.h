@@ -68,6 +68,8 @@ hipError_t launch_convolution(const ProbArg& C, const ProbArg& A, const ProbArg&
                               const ProbArg& B, const ProbArg& Bcc, int n, int d, int nelems,
                               hipStream_t s);
 
+hipError_t launch_observables(const ProbArg& pa, int n, double* out, cplx* rho, hipStream_t s);
+
 // Matsubara pieces (per problem, one problem per call)
 hipError_t launch_free_mat(const Prob& P, cplx* g, hipStream_t s);
 hipError_t launch_mat_conv(const Prob& P, const cplx* A, const cplx* B, const cplx* f,

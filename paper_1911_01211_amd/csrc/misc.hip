@@ -402,6 +402,95 @@ __global__ __launch_bounds__(NT2) void k_convolution(ProbArg pc, ProbArg pa, Pro
   *slice_ptr(C, s, n, C.Gret, C.Gles, C.Gtv) = acc;
 }
 
+// ------------------------------------------------------------ observables
+// Observables of slice n (per spin; Eq. Total_ener and the density matrix):
+//   rho = i xi G^<(t_n, t_n)
+//   out[0] = Re Tr rho                     particle number
+//   out[1] = Re Tr[rho eps0_n]             one-body energy
+//   out[2] = Re Tr[rho eps_mf_n]           one-body energy with the mean field
+//   out[3] = 1/2 Im Tr[Sigma * G]^<(t_n, t_n)   correlation energy
+//   out[4] = (out[1] + out[2]) / 2 + out[3]      Galitskii-Migdal total energy
+// [Sigma * G]^<(n,n) from the three parts of Eqs. cles1-cles3 at m = n.
+// One workgroup per problem: thread (element e, group g) sums the terms
+// j = g, g + G, ... of every part; the groups are added in a fixed order.
+__global__ __launch_bounds__(NT2) void k_observables(ProbArg pa, int n, double* out, cplx* rho_out) {
+  int pi = blockIdx.y;
+  const Prob& P = pa.get(pi);
+  if (n > P.nt) return;
+  const KW& W = c_kw[P.k];
+  int d = P.d, dd = d * d, ntau = P.ntau, k = P.k;
+  double h = P.h, ht = P.htau, xi = P.sig;
+  int tid = threadIdx.x, NG = NT2 / dd, e = tid % dd, g = tid / dd;
+  int a = e / d, c = e % d;
+  __shared__ cplx red[NT2];
+  __shared__ cplx cl[64], rh[64];
+  cplx acc = mk(0, 0);
+  if (g < NG) {
+    int jmax = n > k ? n : k;
+    auto wt = [&](int j) { return n > k ? greg(W, n, j) : W.s[n][j]; };
+    // part 1: h w(n,j) Sigma~^R_{n,j} G^<_{j,n}
+    for (int j = g; j <= jmax; j += NG) {
+      cplx t = mk(0, 0);
+      for (int q = 0; q < d; q++)
+        cfma(t, ret_ext_d(P.Sret, n, j, a, q, d), les_any_d(P.Gles, j, n, q, c, d));
+      acc = acc + (h * wt(j)) * t;
+    }
+    // part 2: h w(n,j) Sigma^<_{n,j} G^A_{j,n},  G^A_{j,n}[q][c] = conj(G~^R_{n,j}[c][q])
+    for (int j = g; j <= jmax; j += NG) {
+      cplx t = mk(0, 0);
+      for (int q = 0; q < d; q++)
+        cfma(t, les_any_d(P.Sles, n, j, a, q, d), conj(ret_ext_d(P.Gret, n, j, c, q, d)));
+      acc = acc + (h * wt(j)) * t;
+    }
+    // part 3: -i h_tau w(ntau,j) Sigma^rceil_{n,j} G^lceil_{j,n},
+    //         G^lceil_{j,n}[q][c] = -xi conj(T_{n,ntau-j}[c][q])
+    cplx s3 = mk(0, 0);
+    for (int j = g; j <= ntau; j += NG) {
+      cplx t = mk(0, 0);
+      const cplx* sb = P.Stv + ((size_t)n * (ntau + 1) + j) * dd;
+      const cplx* gb = P.Gtv + ((size_t)n * (ntau + 1) + ntau - j) * dd;
+      for (int q = 0; q < d; q++) cfma(t, sb[a * d + q], -xi * conj(gb[c * d + q]));
+      s3 = s3 + (ht * greg(W, ntau, j)) * t;
+    }
+    acc = acc - mul_i(s3);
+  }
+  red[tid] = acc;
+  __syncthreads();
+  if (tid < dd) {
+    cplx sum = mk(0, 0);
+    for (int gg = 0; gg < NG; gg++) sum = sum + red[gg * dd + tid];
+    cl[tid] = sum;
+    rh[tid] = mul_i(xi * P.Gles[(tri(n) + n) * dd + tid]);
+  }
+  __syncthreads();
+  if (tid == 0) {
+    const cplx* e0 = P.eps0 + (size_t)(n + 1) * dd;
+    const cplx* em = (P.eps_mf ? P.eps_mf : P.eps0) + (size_t)(n + 1) * dd;
+    double N = 0, E1 = 0, Em = 0, Ec = 0;
+    for (int i = 0; i < d; i++) {
+      N += rh[i * d + i].x;
+      Ec += cl[i * d + i].y;
+      for (int q = 0; q < d; q++) {
+        E1 += (rh[i * d + q] * e0[q * d + i]).x;
+        Em += (rh[i * d + q] * em[q * d + i]).x;
+      }
+    }
+    double* o = out + (size_t)pi * 5;
+    o[0] = N;
+    o[1] = E1;
+    o[2] = Em;
+    o[3] = 0.5 * Ec;
+    o[4] = 0.5 * (E1 + Em) + 0.5 * Ec;
+  }
+  if (rho_out && tid < dd) rho_out[(size_t)pi * dd + tid] = rh[tid];
+}
+
+hipError_t launch_observables(const ProbArg& pa, int n, double* out, cplx* rho, hipStream_t s) {
+  dim3 g(1, pa.count);
+  k_observables<<<g, NT2, 0, s>>>(pa, n, out, rho);
+  return hipGetLastError();
+}
+
 hipError_t launch_convolution(const ProbArg& C, const ProbArg& A, const ProbArg& Acc,
                               const ProbArg& B, const ProbArg& Bcc, int n, int d, int nelems,
                               hipStream_t s) {

@@ -137,6 +137,32 @@ def test_timestep_random_history(O, d):
         assert np.array_equal(got["les"][:o], G["les"][:o])
 
 
+@pytest.mark.parametrize("d", [1, 2, 3, 4, 8])
+def test_observables_parity(O, d):
+    """Density matrix, one-body and correlation (Galitskii-Migdal) energies of
+    single slices, random seeded histories, start-up and bulk slices."""
+    require_gpu()
+    g = W.GridSpec(nt=40, ntau=50, d=d, beta=3.0, h=0.05, k=5)
+    r = W.rng(140, d)
+    cG = W.random_contour(r, g, 0.5, decay=0.3)
+    cS = W.random_contour(r, g, 0.4, decay=0.3)
+    e0, emf = rand_eps(r, g), rand_eps(r, g)
+    Go, So = ora(O, g, cG), ora(O, g, cS)
+    Gd, Sd = K.Contour(g, data=cG), K.Contour(g, data=cS)
+    e0d, emd = to_dev(e0), to_dev(emf)
+    for n in (0, 2, 5, 6, 11, 23, g.nt):
+        say(f"observables d={d} n={n}")
+        obs, rho = K.observables(n, [Gd], [Sd], [e0d], [emd])
+        ref, rho_ref = O.observables(n, Go, So, e0, emf)
+        got = obs.cpu().numpy()[0]
+        for i in range(5):
+            assert abs(got[i] - ref[i]) <= TOL * max(1.0, abs(ref[i])), (n, i, got[i], ref[i])
+        assert relerr(rho.cpu().numpy()[0], rho_ref) < TOL
+        obs2, _ = K.observables(n, [Gd], [Sd], [e0d])  # eps_mf absent: eps0 in its place
+        ref2, _ = O.observables(n, Go, So, e0)
+        assert np.allclose(obs2.cpu().numpy()[0], ref2, rtol=TOL, atol=TOL)
+
+
 # -------------------------------------------------- plain solve, config 0
 def test_two_level_embedding_full_solve(O):
     """Plain Dyson solve of the 2x2 level with a bath self-energy at the sizes

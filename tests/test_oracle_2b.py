@@ -151,3 +151,38 @@ def test_2b_half_filled_chain_density(O):
     for n in (-1, 0, 10, 30):
         rho = O.density_matrix(n, G)
         assert np.allclose(np.diag(rho).real, 0.5, atol=1e-10), (n, np.diag(rho))
+
+
+def test_observables_free_closed_forms(O):
+    """Observables of closed-form free propagators (Eq. G0_free).
+    Sigma = 0: rho(t) = f(H) at every time, so N = Tr f(H), the one-body
+    energy is Tr[f(H) H] and the correlation energy vanishes. Scalar levels
+    a, b with Sigma = g_b: the resolvent identity g_b * g_a = (g_b - g_a) /
+    (e_b - e_a) gives E_corr = (f(e_b) - f(e_a)) / (2 (e_b - e_a)), up to the
+    quadrature error of the convolution."""
+    g = W.GridSpec(nt=40, ntau=200, d=2, beta=5.0, h=0.01, k=5)
+    r = W.rng(31)
+    H = W.random_hermitian(r, 2, 1.0)
+    G = hm(O, g, W.free_gf(H, g))
+    S = hm(O, g)
+    x, V = np.linalg.eigh(H)
+    f = 1.0 / (np.exp(g.beta * x) + 1.0)
+    fH = (V * f) @ V.conj().T
+    e0 = np.broadcast_to(H, (g.nt + 2, 2, 2)).copy()
+    for n in (0, 3, 5, 6, 17, g.nt):
+        obs, rho = O.observables(n, G, S, e0)
+        assert np.abs(rho - fH).max() < 1e-13
+        assert abs(obs[0] - f.sum()) < 1e-13
+        assert abs(obs[1] - (f * x).sum()) < 1e-13
+        assert obs[3] == 0.0
+        assert abs(obs[4] - obs[1]) < 1e-13
+    g1 = W.GridSpec(nt=40, ntau=400, d=1, beta=5.0, h=0.01, k=5)
+    ea, eb = -0.4, 0.7
+    Ga = hm(O, g1, W.free_gf(np.array([[ea]], np.complex128), g1))
+    Sb = hm(O, g1, W.free_gf(np.array([[eb]], np.complex128), g1))
+    fa, fb = 1.0 / (np.exp(g1.beta * ea) + 1.0), 1.0 / (np.exp(g1.beta * eb) + 1.0)
+    ref = (fb - fa) / (2.0 * (eb - ea))
+    e1 = np.full((g1.nt + 2, 1, 1), ea, np.complex128)
+    for n in (0, 5, 6, 20, g1.nt):
+        obs, _ = O.observables(n, Ga, Sb, e1)
+        assert abs(obs[3] - ref) < 1e-8, (n, obs[3], ref)
