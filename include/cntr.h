@@ -128,6 +128,19 @@ cntr_status cntr_sigma_2b(int32_t tstp, int32_t count, const cntr_grid* grids, c
                           const double* const* U, const cntr_gf* Sigma, const void* const* eps0,
                           void* const* eps_mf, double nbar, void* stream);
 
+/* ----------------------------------------------------------------- A11 --
+ * Batch-local self-energy on slice tstp (tstp = -1: Matsubara):
+ *   Sigma = lam * (1/count) * sum_i G[i]
+ * on every component, e.g. a lattice self-energy proportional to the local
+ * Green's function G_loc = (1/N_k) sum_k G_k (the per-k Dyson problems of the
+ * parallel k-point scheme, Sec. on MPI parallelisation, coupled only through
+ * a local self-energy). All grids must agree. Sigma is ONE contour function
+ * (the same one is then passed as the self-energy of every instance to
+ * cntr_dyson_step). Reads slice tstp of every G[i]; writes slice tstp of
+ * Sigma. */
+cntr_status cntr_sigma_local(int32_t tstp, int32_t count, const cntr_grid* grids, const cntr_gf* G,
+                             const cntr_gf* Sigma, double lam, void* stream);
+
 /* ----------------------------------------------------------------- A13 --
  * Observables of slice tstp >= 0, per spin (density matrix and Eq.
  * Total_ener, the Galitskii-Migdal energy):

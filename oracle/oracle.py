@@ -248,5 +248,67 @@ def solve_2b(G: HM, S: HM, eps0, U, nbar=0.5, mats_maxit=200, mats_tol=1e-14, ma
                          corr_err_max=stats[5])
 
 
+def sigma_local(n, Gs, S: HM, lam):
+    """Sigma = lam * (1/count) sum_i G_i on slice n (n = -1: Matsubara), every
+    component; sequential sum over i."""
+    w = lam / len(Gs)
+
+    def acc(get):
+        s = np.zeros_like(get(Gs[0]))
+        for G in Gs:
+            s = s + get(G)
+        return w * s
+
+    if n == -1:
+        S.mat[...] = acc(lambda G: G.mat)
+        return
+    o, nt1 = n * (n + 1) // 2, S.g.ntau + 1
+    S.ret[o:o + n + 1] = acc(lambda G: G.ret[o:o + n + 1])
+    S.les[o:o + n + 1] = acc(lambda G: G.les[o:o + n + 1])
+    S.tv[n * nt1:(n + 1) * nt1] = acc(lambda G: G.tv[n * nt1:(n + 1) * nt1])
+
+
+def solve_local(Gs, S: HM, eps, lam, mats_iters=30, boot_iters=8, ncorr=5, nt_stop=None):
+    """Batched lattice problems coupled by a local self-energy Sigma = lam *
+    G_loc, G_loc = (1/count) sum_i G_i (per-k Dyson equations of the parallel
+    k-point scheme). Fixed iteration counts:
+      Matsubara: mats_iters x {Sigma^M from G^M; G_i^M = Dyson(Sigma^M)},
+      bootstrap: boot_iters x {Sigma on slices 0..k; start-up of every G_i},
+      steps    : extrapolation, then ncorr x {Sigma on slice n; time step},
+                 and a last Sigma of slice n.
+    Returns the L1 changes of Sigma^M and of the bootstrap slices in the last
+    iteration (convergence diagnostics)."""
+    g = Gs[0].g
+    k = g.k
+    nt_stop = g.nt if nt_stop is None else nt_stop
+    dm = 0.0
+    for it in range(mats_iters):
+        prev = S.mat.copy()
+        sigma_local(-1, Gs, S, lam)
+        dm = float(np.abs(S.mat - prev).sum())
+        for G, e in zip(Gs, eps):
+            dyson_mat(G, S, e[0])
+    sigma_local(-1, Gs, S, lam)
+    db = 0.0
+    for it in range(boot_iters):
+        prev = S.copy()
+        for n in range(k + 1):
+            sigma_local(n, Gs, S, lam)
+        db = float(np.abs(S.ret - prev.ret).sum() + np.abs(S.les - prev.les).sum() + np.abs(S.tv - prev.tv).sum())
+        for G, e in zip(Gs, eps):
+            dyson_start(G, S, e)
+    for n in range(k + 1):
+        sigma_local(n, Gs, S, lam)
+    for n in range(k + 1, nt_stop + 1):
+        for G in Gs:
+            extrapolate(n - 1, G)
+        for _ in range(ncorr):
+            sigma_local(n, Gs, S, lam)
+            for G, e in zip(Gs, eps):
+                dyson_timestep(n, G, S, e, "B")
+        sigma_local(n, Gs, S, lam)
+    return dict(mats_change=dm, boot_change=db)
+
+
 def num_threads():
     return lib().oracle_num_threads()

@@ -96,6 +96,44 @@ def sigma_2b(tstp: int, G: list, U: list, Sigma: list, eps0=None, eps_mf=None, n
                                nbar, _stream(stream)))
 
 
+def sigma_local(tstp: int, G: list, Sigma, lam: float, stream=None):
+    """Sigma = lam * mean_i G_i on slice tstp (cntr_sigma_local)."""
+    _abi.check(_abi.lib().cntr_sigma_local(tstp, len(G), _grids(G), _gfs(G), _gfs([Sigma]), float(lam),
+                                           _stream(stream)))
+
+
+def solve_local(G: list, Sigma, eps: list, lam: float, mats_iters=30, boot_iters=8, ncorr=5, nt_stop=None,
+                mats_tol=1e-14, stream=None):
+    """Batched problems coupled by a local self-energy Sigma = lam * G_loc,
+    G_loc = (1/count) sum_i G_i (the per-k Dyson equations of a lattice with a
+    local self-energy), every step for all instances in one launch:
+      Matsubara: mats_iters x {Sigma^M from G^M; G_i^M = Dyson(Sigma^M)},
+      bootstrap: boot_iters x {Sigma on slices 0..k; start-up of every G_i},
+      steps    : extrapolation, then ncorr x {Sigma on slice n; time step},
+                 and a last Sigma of slice n.
+    Fixed iteration counts (the same sequence as the reference driver)."""
+    g = G[0].g
+    k = g.k
+    nt_stop = g.nt if nt_stop is None else nt_stop
+    Ss = [Sigma] * len(G)
+    for _ in range(mats_iters):
+        sigma_local(-1, G, Sigma, lam, stream)
+        init_matsubara(G, Ss, eps, tol=mats_tol, stream=stream)
+    sigma_local(-1, G, Sigma, lam, stream)
+    for _ in range(boot_iters):
+        for n in range(k + 1):
+            sigma_local(n, G, Sigma, lam, stream)
+        dyson_step(k, G, Ss, eps, stream)
+    for n in range(k + 1):
+        sigma_local(n, G, Sigma, lam, stream)
+    for n in range(k + 1, nt_stop + 1):
+        extrapolate(n - 1, G, stream)
+        for _ in range(ncorr):
+            sigma_local(n, G, Sigma, lam, stream)
+            dyson_step(n, G, Ss, eps, stream)
+        sigma_local(n, G, Sigma, lam, stream)
+
+
 OBS_NAMES = ("N", "E1", "Emf", "Ecorr", "Etot")
 
 

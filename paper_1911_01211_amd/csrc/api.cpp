@@ -502,6 +502,27 @@ cntr_status cntr_sigma_2b(int32_t tstp, int32_t count, const cntr_grid* grids, c
   return CNTR_OK;
 }
 
+cntr_status cntr_sigma_local(int32_t tstp, int32_t count, const cntr_grid* grids, const cntr_gf* G,
+                             const cntr_gf* Sigma, double lam, void* stream) {
+  cntr_status st = check_batch(count, grids, "cntr_sigma_local");
+  if (st) return st;
+  if (!gf_ok(G, count) || !gf_ok(Sigma, 1)) return fail(CNTR_ESHAPE, "cntr_sigma_local: null pointer");
+  for (int i = 1; i < count; i++)
+    if (grids[i].nt != grids[0].nt || grids[i].ntau != grids[0].ntau)
+      return fail(CNTR_ESHAPE, "cntr_sigma_local: all grids must agree");
+  if (tstp < -1 || tstp > grids[0].nt) return fail(CNTR_EORDER, "cntr_sigma_local: tstp outside -1..nt");
+  hipStream_t s = (hipStream_t)stream;
+  StreamScratch* sc = scratch_for(s);
+  if ((st = grow(s, sc, 256, 5 * (size_t)count, 2))) return st;
+  std::vector<Prob> v(count);
+  for (int i = 0; i < count; i++) v[i] = make_prob(grids[i], &G[i], i == 0 ? Sigma : nullptr, nullptr);
+  ProbArg pa;
+  if ((st = make_arg(s, sc, v, 0, &pa))) return st;
+  hipError_t e = launch_sigma_local(pa, tstp, grids[0].d, (int)slice_elems(grids[0], tstp), lam, s);
+  if (e != hipSuccess) return hip_fail(e, "cntr_sigma_local launch");
+  return CNTR_OK;
+}
+
 cntr_status cntr_observables(int32_t tstp, int32_t count, const cntr_grid* grids, const cntr_gf* G,
                              const cntr_gf* Sigma, const void* const* eps0, const void* const* eps_mf,
                              double* obs, void* rho, void* stream) {

@@ -69,6 +69,7 @@ hipError_t launch_convolution(const ProbArg& C, const ProbArg& A, const ProbArg&
                               hipStream_t s);
 
 hipError_t launch_observables(const ProbArg& pa, int n, double* out, cplx* rho, hipStream_t s);
+hipError_t launch_sigma_local(const ProbArg& pa, int n, int d, int nelems, double lam, hipStream_t s);
 
 // Matsubara pieces (per problem, one problem per call)
 hipError_t launch_free_mat(const Prob& P, cplx* g, hipStream_t s);

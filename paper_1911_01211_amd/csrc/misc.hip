@@ -402,6 +402,41 @@ __global__ __launch_bounds__(NT2) void k_convolution(ProbArg pc, ProbArg pa, Pro
   *slice_ptr(C, s, n, C.Gret, C.Gles, C.Gtv) = acc;
 }
 
+// --------------------------------------------------------- local Sigma
+// Sigma = lam * (1/count) sum_i G_i on slice n of every component (n = -1: the
+// Matsubara component): a self-energy local in the batch index, e.g. the
+// k-point average G_loc of a lattice. Fixed summation order over i.
+// Pointer sources: the batch (pa, count >= 1) supplies the G_i; the output is
+// the Sigma of problem 0.
+__global__ __launch_bounds__(NT2) void k_sigma_local(ProbArg pa, int n, double lam) {
+  const Prob& P0 = pa.get(0);
+  int d = P0.d, dd = d * d, ntau = P0.ntau, cnt = pa.count;
+  long idx = (long)blockIdx.x * NT2 + threadIdx.x;
+  double w = lam / cnt;
+  if (n == -1) {
+    if (idx >= (long)(ntau + 1) * dd) return;
+    cplx s = mk(0, 0);
+    for (int i = 0; i < cnt; i++) s = s + gld(pa.get(i).Gmat + idx);
+    P0.Smat[idx] = w * s;
+    return;
+  }
+  long total = (long)(2 * (n + 1) + ntau + 1) * dd;
+  if (idx >= total) return;
+  SliceIdx sl = slice_idx(idx, n, ntau, d);
+  cplx s = mk(0, 0);
+  for (int i = 0; i < cnt; i++) {
+    const Prob& P = pa.get(i);
+    s = s + gld(slice_ptr(P, sl, n, P.Gret, P.Gles, P.Gtv));
+  }
+  *slice_ptr(P0, sl, n, P0.Sret, P0.Sles, P0.Stv) = w * s;
+}
+
+hipError_t launch_sigma_local(const ProbArg& pa, int n, int d, int nelems, double lam, hipStream_t s) {
+  dim3 g((nelems + NT2 - 1) / NT2, 1);
+  k_sigma_local<<<g, NT2, 0, s>>>(pa, n, lam);
+  return hipGetLastError();
+}
+
 // ------------------------------------------------------------ observables
 // Observables of slice n (per spin; Eq. Total_ener and the density matrix):
 //   rho = i xi G^<(t_n, t_n)
