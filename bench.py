@@ -73,6 +73,44 @@ def run_gpu(args):
     return g, elapsed, prof, stats, dens_dev
 
 
+def run_kpoints(args):
+    """Batched sample: the single-band lattice with 512 k-points, eps_k(t) =
+    -2 cos(k - A(t)) with the pulse A(t), local self-energy Sigma = 0.25 G_loc,
+    beta = 10, ntau = 500, nt = 2000, h = 0.02, k = 5 (full grid allocated,
+    41 GB). Untimed set-up: one Matsubara pass (free G^M, then Sigma^M) and the
+    bootstrap; timed: the predictor-corrector steps k+1..nt_stop for all 512
+    instances in one launch per step (ncorr corrector iterations each)."""
+    import torch
+
+    from paper_1911_01211_amd import contour as K
+    from paper_1911_01211_amd import workloads as W
+
+    g = W.GridSpec(nt=2000, ntau=500, d=1, sig=-1, k=5, beta=10.0, h=0.02, mu=0.0)
+    nk = args.nk
+    eps = [torch.as_tensor(e).to("cuda:0") for e in W.kpoint_band(g, nk)]
+    G = [K.Contour(g, "cuda:0") for _ in range(nk)]
+    S = K.Contour(g, "cuda:0")
+    Ss = [S] * nk
+    lam = 0.25
+    K.solve_local(G, S, eps, lam, mats_iters=1, boot_iters=8, ncorr=args.ncorr, nt_stop=g.k)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for n in range(g.k + 1, args.kp_steps + 1):
+        K.extrapolate(n - 1, G)
+        for _ in range(args.ncorr):
+            K.sigma_local(n, G, S, lam)
+            K.dyson_step(n, G, Ss, eps)
+        K.sigma_local(n, G, S, lam)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    nsteps = (args.kp_steps - g.k) * nk
+    return {"workload": f"{nk} k-points, d=1, local Sigma = 0.25 G_loc, pulse A(t), beta=10, ntau=500, "
+                        f"nt=2000 grid; steps {g.k + 1}..{args.kp_steps} timed",
+            "value": nsteps / el, "unit": "instance time-steps/s", "instances": nk,
+            "ms_per_slice": el / (args.kp_steps - g.k) * 1e3, "corrector_iterations": args.ncorr,
+            "note": "prefix of the run (the per-slice cost grows with n)"}
+
+
 def cpu_baseline(g, ncorr, mats_iter, budget_s):
     """The oracle (OpenMP over the independent loops) on a bounded sample of the
     same workload: one corrector iteration (Sigma_2B + time step) at a few
@@ -136,6 +174,9 @@ def main():
     ap.add_argument("--ncorr", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--nk", type=int, default=512, help="k-points of the batched sample")
+    ap.add_argument("--kp-steps", type=int, default=300, help="last slice of the batched sample")
+    ap.add_argument("--no-kpoints", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -173,6 +214,8 @@ def main():
                      "avg_launch_us": prof["hist_ms"] * 1e3 / max(1, prof["hist_launches"])},
         "check": {"max_density_deviation_at_nt": dens_dev},
     }
+    if not args.no_kpoints:
+        out["batched"] = run_kpoints(args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(g, args.ncorr, stats.mats_iter, args.cpu_budget)
     print(json.dumps(out), flush=True)

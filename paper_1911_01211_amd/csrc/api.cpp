@@ -267,6 +267,20 @@ cntr_status mats_solve(MatsState& st, const Prob& P, bool use_guess, double tol,
   double prev = -1;
   int since_inv = 0;
   for (int it = 0; it < max_iter; it++) {
+    if ((e = launch_matvec(N, d, st.A, P.Gmat, st.g, st.r, s))) return hip_fail(e, "residual");
+    if ((e = hipMemsetAsync(st.norms, 0, 2 * sizeof(double), s))) return hip_fail(e, "norm clear");
+    if ((e = launch_axpy_norm(N * d, P.Gmat, nullptr, st.r, st.g, st.norms, s))) return hip_fail(e, "norm");
+    double nrm[2];
+    if ((e = hipMemcpyAsync(nrm, st.norms, sizeof nrm, hipMemcpyDeviceToHost, s)) ||
+        (e = hipStreamSynchronize(s)))
+      return hip_fail(e, "norm readback");
+    double rel = std::sqrt(nrm[0] / (nrm[1] > 0 ? nrm[1] : 1.0));
+    if (!std::isfinite(rel)) return fail(CNTR_ENONFINITE, "non-finite Matsubara residual");
+    if (iters) *iters = it;
+    if (rel <= tol) return CNTR_OK;
+    // the inverse is formed when first needed, and refreshed when the
+    // refinement stops contracting
+    if (st.have_inv && since_inv >= 2 && prev > 0 && rel > 0.25 * prev) st.have_inv = false;
     if (!st.have_inv) {
       if ((e = hipMemsetAsync(st.status, 0, sizeof(int), s))) return hip_fail(e, "status clear");
       if ((e = hipMemcpyAsync(st.Ainv, st.A, (size_t)N * N * sizeof(cplx), hipMemcpyDeviceToDevice, s)))
@@ -280,22 +294,6 @@ cntr_status mats_solve(MatsState& st, const Prob& P, bool use_guess, double tol,
       st.have_inv = true;
       since_inv = 0;
       prev = -1;
-    }
-    if ((e = launch_matvec(N, d, st.A, P.Gmat, st.g, st.r, s))) return hip_fail(e, "residual");
-    if ((e = hipMemsetAsync(st.norms, 0, 2 * sizeof(double), s))) return hip_fail(e, "norm clear");
-    if ((e = launch_axpy_norm(N * d, P.Gmat, nullptr, st.r, st.g, st.norms, s))) return hip_fail(e, "norm");
-    double nrm[2];
-    if ((e = hipMemcpyAsync(nrm, st.norms, sizeof nrm, hipMemcpyDeviceToHost, s)) ||
-        (e = hipStreamSynchronize(s)))
-      return hip_fail(e, "norm readback");
-    double rel = std::sqrt(nrm[0] / (nrm[1] > 0 ? nrm[1] : 1.0));
-    if (!std::isfinite(rel)) return fail(CNTR_ENONFINITE, "non-finite Matsubara residual");
-    if (iters) *iters = it;
-    if (rel <= tol) return CNTR_OK;
-    // refresh the preconditioner when refinement stops contracting
-    if (since_inv >= 2 && prev > 0 && rel > 0.25 * prev) {
-      st.have_inv = false;
-      continue;
     }
     prev = rel;
     since_inv++;
