@@ -48,7 +48,7 @@ struct ProfState {
 };
 extern ProfState g_prof;
 
-int hist_tj(int d);
+
 int hist_tm(int d);
 HistPlan make_plan(int n, int k, int ntau, int d);
 // scratch bytes (per problem) for the step at the largest n = nt

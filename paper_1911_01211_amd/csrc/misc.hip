@@ -408,34 +408,75 @@ __global__ __launch_bounds__(NT2) void k_convolution(ProbArg pc, ProbArg pa, Pro
 // k-point average G_loc of a lattice. Fixed summation order over i.
 // Pointer sources: the batch (pa, count >= 1) supplies the G_i; the output is
 // the Sigma of problem 0.
+// One workgroup: 64 elements x 4 waves; wave w sums its quarter of the
+// instances (sixteen loads in flight), the quarters are added in order.
 __global__ __launch_bounds__(NT2) void k_sigma_local(ProbArg pa, int n, double lam) {
+  constexpr int NBAT = 256;  // instances whose pointers are staged at once
+  __shared__ const cplx* base[NBAT];
+  __shared__ cplx qs[4][64];
   const Prob& P0 = pa.get(0);
   int d = P0.d, dd = d * d, ntau = P0.ntau, cnt = pa.count;
-  long idx = (long)blockIdx.x * NT2 + threadIdx.x;
+  int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  long idx = (long)blockIdx.x * 64 + lane;
   double w = lam / cnt;
+  // component and offset of this element (identical in every instance)
+  int comp;  // 0 ret, 1 les, 2 tv, 3 mat
+  size_t off;
+  bool valid;
   if (n == -1) {
-    if (idx >= (long)(ntau + 1) * dd) return;
-    cplx s = mk(0, 0);
-    for (int i = 0; i < cnt; i++) s = s + gld(pa.get(i).Gmat + idx);
-    P0.Smat[idx] = w * s;
-    return;
+    comp = 3;
+    off = idx;
+    valid = idx < (long)(ntau + 1) * dd;
+  } else {
+    long total = (long)(2 * (n + 1) + ntau + 1) * dd;
+    valid = idx < total;
+    SliceIdx sl = slice_idx(valid ? idx : 0, n, ntau, d);
+    comp = sl.comp;
+    off = comp == 2 ? ((size_t)n * (ntau + 1) + sl.j) * dd + sl.a * d + sl.c
+                    : (tri(n) + sl.j) * dd + sl.a * d + sl.c;
   }
-  long total = (long)(2 * (n + 1) + ntau + 1) * dd;
-  if (idx >= total) return;
-  SliceIdx sl = slice_idx(idx, n, ntau, d);
   cplx s = mk(0, 0);
-  for (int i = 0; i < cnt; i++) {
-    const Prob& P = pa.get(i);
-    s = s + gld(slice_ptr(P, sl, n, P.Gret, P.Gles, P.Gtv));
+  for (int i0 = 0; i0 < cnt; i0 += NBAT) {
+    int nb = min(NBAT, cnt - i0);
+    int lo = wave * nb / 4, hi = (wave + 1) * nb / 4;
+    for (int c = 0; c < 4; c++) {
+      // stage component c's pointers only if some element of the block needs them
+      bool need = __syncthreads_or(valid && comp == c);
+      if (!need) continue;
+      for (int i = threadIdx.x; i < nb; i += NT2) {
+        const Prob& P = pa.get(i0 + i);
+        base[i] = c == 0 ? P.Gret : c == 1 ? P.Gles : c == 2 ? P.Gtv : P.Gmat;
+      }
+      __syncthreads();
+      if (valid && comp == c) {
+        int i = lo;
+        for (; i + 16 <= hi; i += 16) {
+          cplx v[16];
+#pragma unroll
+          for (int u = 0; u < 16; u++) v[u] = gld(base[i + u] + off);
+#pragma unroll
+          for (int u = 0; u < 16; u++) s = s + v[u];
+        }
+        for (; i < hi; i++) s = s + gld(base[i] + off);
+      }
+    }
   }
-  *slice_ptr(P0, sl, n, P0.Sret, P0.Sles, P0.Stv) = w * s;
+  qs[wave][lane] = s;
+  __syncthreads();
+  if (wave != 0 || !valid) return;
+  cplx r = w * (((qs[0][lane] + qs[1][lane]) + qs[2][lane]) + qs[3][lane]);
+  if (comp == 3) P0.Smat[off] = r;
+  else if (comp == 0) P0.Sret[off] = r;
+  else if (comp == 1) P0.Sles[off] = r;
+  else P0.Stv[off] = r;
 }
 
 hipError_t launch_sigma_local(const ProbArg& pa, int n, int d, int nelems, double lam, hipStream_t s) {
-  dim3 g((nelems + NT2 - 1) / NT2, 1);
+  dim3 g((nelems + 63) / 64, 1);
   k_sigma_local<<<g, NT2, 0, s>>>(pa, n, lam);
   return hipGetLastError();
 }
+
 
 // ------------------------------------------------------------ observables
 // Observables of slice n (per spin; Eq. Total_ener and the density matrix):

@@ -25,8 +25,10 @@ constexpr int NTHR = 256;
 // d <= 4: one output block per lane (64 outputs per workgroup); larger d:
 // one output element per thread
 int hist_tm(int d) { return d <= 4 ? 64 : (NTHR / (d * d) > 0 ? NTHR / (d * d) : 1); }
-int hist_tj(int d) { return d >= 8 ? 32 : 64; }
-static int hist_tjs(int d) { return d <= 4 ? 16 : (d >= 8 ? 16 : 32); }
+// term chunks: d = 1 blocks are single numbers, so long chunks keep the
+// number of workgroups of a (large) batch moderate
+constexpr int hist_tj(int d) { return d == 1 ? 256 : (d >= 8 ? 32 : 64); }
+constexpr int hist_tjs(int d) { return d == 1 ? 512 : (d <= 4 ? 16 : (d >= 8 ? 16 : 32)); }
 // staged path: term chunk of the history jobs and of the tau source
 constexpr int STG_TJ = 32, STG_TJS = 16;
 
@@ -36,7 +38,7 @@ static int cdiv_i(int a, int b) { return (a + b - 1) / b; }
 // history (for the staged path only its part l >= m), 4 source C^<_1,
 // 5 source C^<_3, 6 tau-boundary corrections, 7 lesser history l < m (staged
 // path only).
-bool hist_staged(int d) { return d == 1 || d == 2 || d == 4; }
+constexpr bool hist_staged(int d) { return d == 2 || d == 4; }
 
 HistPlan make_plan(int n, int k, int ntau, int d) {
   HistPlan p{};
@@ -526,6 +528,20 @@ template <int D, class Addr, class Add>
 __device__ inline void term_loop(int jb, int je, Addr addr, Add add) {
   constexpr int DD = D * D;
   if (jb >= je) return;
+  if constexpr (D == 1) {
+    // single-number blocks: sixteen terms loaded together
+    constexpr int U = 16;
+    int jl = je - 1;
+    for (int j = jb; j < je; j += 4 * U) {
+      cplx h[U][1];
+#pragma unroll
+      for (int u = 0; u < U; u++) ld_blk<1>(h[u], addr(min(j + 4 * u, jl)));
+#pragma unroll
+      for (int u = 0; u < U; u++)
+        if (j + 4 * u < je) add(j + 4 * u, h[u]);
+    }
+    return;
+  }
   cplx ha[DD], hb[DD];
   int jl = je - 1;
   ld_blk<DD>(ha, addr(jb));
@@ -1022,8 +1038,10 @@ __global__ __launch_bounds__(NTHR) void k_history(ProbArg pa, Scratch sc, HistPl
   constexpr int LDSA = (2 * TJ * DD) > PREPN ? (2 * TJ * DD) : PREPN;
   constexpr int LDSB = LDSA > TSN ? LDSA : TSN;
   constexpr int LDSR0 = D <= 4 ? 3 * DD * 64 : 0;  // wave sums of the block-per-lane path
-  constexpr int LDSR = (D == 1 || D == 2 || D == 4) ? 4 * Stg<D>::WBUF : LDSR0;  // staged path buffers
-  constexpr bool STG = D == 1 || D == 2 || D == 4;
+  constexpr bool STG = hist_staged(D);
+  constexpr int LDSB1 = hist_tj(D) * DD > 2 * hist_tjs(D) * DD ? hist_tj(D) * DD : 2 * hist_tjs(D) * DD;
+  constexpr int LDSR1 = D <= 4 && LDSB1 > LDSR0 ? LDSB1 : LDSR0;  // operands of the block-per-lane path
+  constexpr int LDSR = STG ? 4 * Stg<D>::WBUF : LDSR1;              // staged path buffers
   constexpr int LDSN = STG ? (PREPN > LDSR ? PREPN : LDSR) : (LDSB > LDSR ? LDSB : LDSR);
   __shared__ cplx lds[LDSN];
   // shared operand of a staged chunk (a separate array: its reads never wait
@@ -1076,7 +1094,7 @@ __global__ __launch_bounds__(NTHR) void k_history(ProbArg pa, Scratch sc, HistPl
     tau_boundary<D>(P, sc, pi, n, pl, lds);
     return;
   }
-  if constexpr (D == 1 || D == 2 || D == 4) {
+  if constexpr (STG) {
     if (job == 2) tau_stg<D>(P, sc, pi, n, pl, mt, ch, lds, shop);
     else hist_stg<D>(P, sc, pi, n, pl, job, mt, ch, lds, shop);
     return;
@@ -1417,11 +1435,15 @@ __global__ __launch_bounds__(NTHR) void k_reduce(ProbArg pa, Scratch sc, HistPla
   int nwg = t0 + t1 + t2;
   int NV = (k + 1) * DD;
   cplx* tpart = sc.part(pi) + pl.tail_off * DD;
-  for (int v = tid; v < NV; v += NTHR) {
+  // G2 thread groups per value split the tile's outputs; the groups' sums
+  // are added in a fixed order
+  int G2 = NV >= NTHR ? 1 : NTHR / NV;
+  for (int vv = tid; vv < G2 * NV; vv += NTHR) {
+    int g2 = vv / NV, v = vv % NV;
     int r = v / DD, ee = v % DD, a2 = ee / D, c2 = ee % D;
     int mr = n - k + r;
     cplx acc = mk(0, 0);
-    for (int mm = mlo; mm <= mhi; mm++) {
+    for (int mm = mlo + g2; mm <= mhi; mm += G2) {
       const cplx* ob = outs + (mm - mlo) * DD;
       const cplx* sb = sigs + (r * nm + mm - mlo) * DD;
       cplx s = mk(0, 0);
@@ -1439,8 +1461,14 @@ __global__ __launch_bounds__(NTHR) void k_reduce(ProbArg pa, Scratch sc, HistPla
         acc = acc + twt[r * nm + mm - mlo] * s;
       }
     }
+    stage[vv] = acc;
+  }
+  __syncthreads();
+  for (int v = tid; v < NV; v += NTHR) {
+    cplx sum = mk(0, 0);
+    for (int g2 = 0; g2 < G2; g2++) sum = sum + stage[g2 * NV + v];
     cplx coef = fam == 1 ? mk(-ht, 0) : mk(0, -h);
-    tpart[(size_t)b * NV + v] = coef * acc;
+    tpart[(size_t)b * NV + v] = coef * sum;
   }
   // completion count; every thread releases its own stores first
   __threadfence();
