@@ -31,6 +31,7 @@ struct HistPlan {
   // reduce tiles of the retarded, mixing and lesser rows; partial sums of
   // the lesser boundary rows, one set per reduce tile
   int red_tiles[3];
+  int walk_tiles;     // one reduce workgroup per problem (large batches)
   long tail_off;      // in blocks
   long total_blocks;  // scratch blocks of the step
 };

@@ -1333,7 +1333,17 @@ __global__ __launch_bounds__(NTHR) void k_reduce(ProbArg pa, Scratch sc, HistPla
   int k = P.k, ntau = P.ntau;
   double h = P.h, ht = P.htau, xi = P.sig;
   int t0 = pl.red_tiles[0], t1 = pl.red_tiles[1], t2 = pl.red_tiles[2];
-  int b = blockIdx.x, fam, mt;
+  int nwg = t0 + t1 + t2;
+  int NV = (k + 1) * DD;
+  cplx* tpart = sc.part(pi) + pl.tail_off * DD;
+  // Large batches: one workgroup per problem walks all its tiles and then
+  // runs the boundary rows itself (no completion count across workgroups).
+  bool walk = pl.walk_tiles;
+  int tid = threadIdx.x;
+  int b_end = walk ? nwg : (int)blockIdx.x + 1;
+  for (int b = walk ? 0 : (int)blockIdx.x; b < b_end; b++) {
+  __syncthreads();  // the LDS buffers of the previous tile are free
+  int fam, mt;
   if (b < t0) {
     fam = 0;
     mt = b;
@@ -1344,7 +1354,6 @@ __global__ __launch_bounds__(NTHR) void k_reduce(ProbArg pa, Scratch sc, HistPla
     fam = 2;
     mt = b - t0 - t1;
   }
-  int tid = threadIdx.x;
   int mo = tid / DD, e = tid % DD, a = e / D, c = e % D;
   int m = mt * TM + mo;
   int mout = fam == 1 ? ntau + 1 : n - k;
@@ -1427,14 +1436,11 @@ __global__ __launch_bounds__(NTHR) void k_reduce(ProbArg pa, Scratch sc, HistPla
       P.Gles[(tri(n) + m) * DD + e] = out;
     }
   }
-  if (n < 2 * k + 1) return;  // the column is finished serially (k_column)
+  if (n >= 2 * k + 1) {  // (else the column is finished serially by k_column)
   __syncthreads();
   if (valid) outs[mo * DD + e] = out;
   __syncthreads();
   // contribution of this tile to the boundary rows
-  int nwg = t0 + t1 + t2;
-  int NV = (k + 1) * DD;
-  cplx* tpart = sc.part(pi) + pl.tail_off * DD;
   // G2 thread groups per value split the tile's outputs; the groups' sums
   // are added in a fixed order
   int G2 = NV >= NTHR ? 1 : NTHR / NV;
@@ -1470,13 +1476,20 @@ __global__ __launch_bounds__(NTHR) void k_reduce(ProbArg pa, Scratch sc, HistPla
     cplx coef = fam == 1 ? mk(-ht, 0) : mk(0, -h);
     tpart[(size_t)b * NV + v] = coef * sum;
   }
-  // completion count; every thread releases its own stores first
-  __threadfence();
-  __syncthreads();
-  if (tid == 0) is_last = atomicAdd(sc.counter(pi), 1) == nwg - 1;
-  __syncthreads();
-  if (!is_last) return;
-  __threadfence();
+  }  // n >= 2k+1
+  }  // tiles
+  if (n < 2 * k + 1) return;
+  if (walk) {
+    __syncthreads();  // this workgroup's own partials
+  } else {
+    // completion count; every thread releases its own stores first
+    __threadfence();
+    __syncthreads();
+    if (tid == 0) is_last = atomicAdd(sc.counter(pi), 1) == nwg - 1;
+    __syncthreads();
+    if (!is_last) return;
+    __threadfence();
+  }
   // last workgroup. The operands of the serial steps are loaded first (into
   // registers), then the partials of all workgroups are summed (G groups per
   // value); the loads of both overlap.
@@ -1876,7 +1889,8 @@ static hipError_t step_d(const ProbArg& pa, const Scratch& sc, int n, hipStream_
     g_prof.rec.push_back({e0, e1, e2, 16.0 * dd * blocks * pa.count,
                           8.0 * dd * D * hist_block_macs(n, k, ntau) * pa.count});
   }
-  dim3 g2(pl.red_tiles[0] + pl.red_tiles[1] + pl.red_tiles[2], pa.count);
+  pl.walk_tiles = pa.count >= 16;
+  dim3 g2(pl.walk_tiles ? 1 : pl.red_tiles[0] + pl.red_tiles[1] + pl.red_tiles[2], pa.count);
   k_reduce<D><<<g2, NTHR, 0, s>>>(pa, sc, pl);
   if (n < 2 * k + 1) {
     dim3 g4(1, pa.count);

@@ -394,12 +394,17 @@ def test_full_size_2b_prefix(O):
 
 
 # ------------------------------------------------------------ batching
-def test_batch_matches_single_instances(O):
+@pytest.mark.parametrize("nb,d", [(3, 2), (20, 2), (20, 4), (18, 1)])
+def test_batch_matches_single_instances(O, nb, d):
+    """Batched step (one launch for all instances, uneven nt: instances with
+    nt < n are skipped) equals the single-instance step bitwise; batches of 16
+    or more use one reduce workgroup per instance."""
     require_gpu()
-    say("batch")
-    base = W.GridSpec(nt=30, ntau=40, d=2, beta=3.0, h=0.04, k=5, mu=0.1)
-    grids = [dataclasses.replace(base, nt=nt) for nt in (30, 22, 27)]
-    r = W.rng(106)
+    say(f"batch nb={nb} d={d}")
+    base = W.GridSpec(nt=30, ntau=40, d=d, beta=3.0, h=0.04, k=5, mu=0.1)
+    nts = [30, 22, 27] + [30 - (i % 4) for i in range(nb - 3)]
+    grids = [dataclasses.replace(base, nt=nt) for nt in nts]
+    r = W.rng(106, nb, d)
     data = [(W.random_contour(r, g, 0.4, decay=0.3), W.random_contour(r, g, 0.3, decay=0.3),
              rand_eps(r, g)) for g in grids]
     n = 25
