@@ -90,17 +90,16 @@ def run_kpoints(args):
     eps = [torch.as_tensor(e).to("cuda:0") for e in W.kpoint_band(g, nk)]
     G = [K.Contour(g, "cuda:0") for _ in range(nk)]
     S = K.Contour(g, "cuda:0")
-    Ss = [S] * nk
     lam = 0.25
-    K.solve_local(G, S, eps, lam, mats_iters=1, boot_iters=8, ncorr=args.ncorr, nt_stop=g.k)
+    B = K.solve_local(G, S, eps, lam, mats_iters=1, boot_iters=8, ncorr=args.ncorr, nt_stop=g.k)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for n in range(g.k + 1, args.kp_steps + 1):
-        K.extrapolate(n - 1, G)
+        B.extrapolate(n - 1)
         for _ in range(args.ncorr):
-            K.sigma_local(n, G, S, lam)
-            K.dyson_step(n, G, Ss, eps)
-        K.sigma_local(n, G, S, lam)
+            B.sigma_local(n, lam)
+            B.step(n)
+        B.sigma_local(n, lam)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     nsteps = (args.kp_steps - g.k) * nk

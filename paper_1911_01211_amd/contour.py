@@ -102,6 +102,36 @@ def sigma_local(tstp: int, G: list, Sigma, lam: float, stream=None):
                                            _stream(stream)))
 
 
+class Batch:
+    """The C-ABI argument arrays of a fixed batch (grids, contour descriptors,
+    self-energies, levels), built once: the per-call marshalling of large
+    batches would otherwise cost more host time than the launches."""
+
+    def __init__(self, G: list, Sigma: list, eps: list):
+        self.count = len(G)
+        self.G = G
+        self.grids = _grids(G)
+        self.gfs = _gfs(G)
+        self.sgfs = _gfs(Sigma)
+        self.eps = _ptrs(eps)
+
+    def step(self, tstp: int, stream=None):
+        _abi.check(_abi.lib().cntr_dyson_step(tstp, self.count, self.grids, self.gfs, self.sgfs, self.eps,
+                                              _stream(stream)))
+
+    def extrapolate(self, tstp: int, stream=None):
+        _abi.check(_abi.lib().cntr_extrapolate(tstp, self.count, self.grids, self.gfs, _stream(stream)))
+
+    def sigma_local(self, tstp: int, lam: float, stream=None):
+        """Sigma_0 = lam * mean_i G_i (the batch's first self-energy)."""
+        _abi.check(_abi.lib().cntr_sigma_local(tstp, self.count, self.grids, self.gfs, self.sgfs, float(lam),
+                                               _stream(stream)))
+
+    def init_matsubara(self, tol=1e-14, max_iter=200, stream=None):
+        _abi.check(_abi.lib().cntr_init_matsubara(self.count, self.grids, self.gfs, self.sgfs, self.eps, tol,
+                                                  max_iter, _stream(stream)))
+
+
 def solve_local(G: list, Sigma, eps: list, lam: float, mats_iters=30, boot_iters=8, ncorr=5, nt_stop=None,
                 mats_tol=1e-14, stream=None):
     """Batched problems coupled by a local self-energy Sigma = lam * G_loc,
@@ -115,23 +145,24 @@ def solve_local(G: list, Sigma, eps: list, lam: float, mats_iters=30, boot_iters
     g = G[0].g
     k = g.k
     nt_stop = g.nt if nt_stop is None else nt_stop
-    Ss = [Sigma] * len(G)
+    B = Batch(G, [Sigma] * len(G), eps)
     for _ in range(mats_iters):
-        sigma_local(-1, G, Sigma, lam, stream)
-        init_matsubara(G, Ss, eps, tol=mats_tol, stream=stream)
-    sigma_local(-1, G, Sigma, lam, stream)
+        B.sigma_local(-1, lam, stream)
+        B.init_matsubara(tol=mats_tol, stream=stream)
+    B.sigma_local(-1, lam, stream)
     for _ in range(boot_iters):
         for n in range(k + 1):
-            sigma_local(n, G, Sigma, lam, stream)
-        dyson_step(k, G, Ss, eps, stream)
+            B.sigma_local(n, lam, stream)
+        B.step(k, stream)
     for n in range(k + 1):
-        sigma_local(n, G, Sigma, lam, stream)
+        B.sigma_local(n, lam, stream)
     for n in range(k + 1, nt_stop + 1):
-        extrapolate(n - 1, G, stream)
+        B.extrapolate(n - 1, stream)
         for _ in range(ncorr):
-            sigma_local(n, G, Sigma, lam, stream)
-            dyson_step(n, G, Ss, eps, stream)
-        sigma_local(n, G, Sigma, lam, stream)
+            B.sigma_local(n, lam, stream)
+            B.step(n, stream)
+        B.sigma_local(n, lam, stream)
+    return B
 
 
 OBS_NAMES = ("N", "E1", "Emf", "Ecorr", "Etot")
