@@ -27,6 +27,28 @@ sys.path.insert(0, ROOT)
 METRIC = "Dyson time-steps/s + FP64 TFLOP/s, batched/adjoint vs plain at <=1e-10 rel err"
 HBM_PEAK_GBS = 8000.0
 
+# HBM traffic of one history-kernel launch at slice n = 1000, from the
+# FETCH_SIZE / WRITE_SIZE counter runs of `bench.py --profile-step 1000`
+# (scaled by the counts of a 1 GiB device copy: FETCH x 2.0, WRITE x 1.0).
+# Valid only for the kernel sources it was taken on (hash below); reported
+# as null once they change.
+TRAFFIC = {"slice": 1000, "bytes": 7.2605e8, "algorithmic_bytes": 3.5891e8,
+           "src_sha256_16": "e4da54bee2736801",
+           "profile": "profiles/k_history_traffic_slice1000_d4.md"}
+TRAFFIC_SRCS = ("paper_1911_01211_amd/csrc/step.hip", "paper_1911_01211_amd/csrc/dev_common.h",
+                "paper_1911_01211_amd/csrc/cntr_internal.h")
+
+
+def traffic_entry():
+    import hashlib
+    h = hashlib.sha256()
+    for f in TRAFFIC_SRCS:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest()[:16] != TRAFFIC["src_sha256_16"]:
+        return None, None
+    return TRAFFIC["bytes"], {k: TRAFFIC[k] for k in ("slice", "algorithmic_bytes", "profile")}
+
 
 def workload_grid():
     from paper_1911_01211_amd import workloads as W
@@ -110,6 +132,34 @@ def run_kpoints(args):
             "note": "prefix of the run (the per-slice cost grows with n)"}
 
 
+def profile_step(args):
+    """Counter runs: the time step at slice args.profile_step of a seeded
+    history with the workload's shape, 5 launches (each recomputes the same
+    slice), then one device copy of 1 GiB (calibration of the HBM byte
+    counters: its algorithmic traffic is 1 GiB read + 1 GiB written)."""
+    import torch
+
+    from paper_1911_01211_amd import contour as K
+    from paper_1911_01211_amd import workloads as W
+
+    g = workload_grid()
+    r = W.rng(900)
+    G = K.Contour(g, "cuda:0", data=W.random_contour(r, g, 0.3, decay=0.2))
+    S = K.Contour(g, "cuda:0", data=W.random_contour(r, g, 0.3, decay=0.2))
+    e0, _ = W.hubbard_ramp(g)
+    e = torch.as_tensor(e0).to("cuda:0")
+    n = args.profile_step
+    for _ in range(5):
+        K.dyson_step(n, [G], [S], [e])
+    torch.cuda.synchronize()
+    src = torch.ones(1 << 27, dtype=torch.float64, device="cuda:0")  # 1 GiB
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"profile_step": n, "algorithmic_bytes_history": 16.0 * g.d ** 2 * (
+        n * (n + 1) + n * (g.ntau + 1)), "copy_bytes": 2 * src.numel() * 8}), flush=True)
+
+
 def cpu_baseline(g, ncorr, mats_iter, budget_s):
     """The oracle (OpenMP over the independent loops) on a bounded sample of the
     same workload: one corrector iteration (Sigma_2B + time step) at a few
@@ -176,7 +226,12 @@ def main():
     ap.add_argument("--nk", type=int, default=512, help="k-points of the batched sample")
     ap.add_argument("--kp-steps", type=int, default=300, help="last slice of the batched sample")
     ap.add_argument("--no-kpoints", action="store_true")
+    ap.add_argument("--profile-step", type=int, default=0,
+                    help="only run the time step at this slice (counter runs), then a 1 GiB copy")
     args = ap.parse_args()
+    if args.profile_step:
+        profile_step(args)
+        return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(the per-GPU share of a sharded run is the single-GPU workload).", file=sys.stderr)
@@ -186,6 +241,7 @@ def main():
     value = nsteps / elapsed
     hist_gbs = prof["hist_bytes"] / (prof["hist_ms"] * 1e-3) / 1e9 if prof["hist_ms"] > 0 else None
     tflops = prof["hist_flops"] / elapsed / 1e12
+    traffic, traffic_at = traffic_entry()
     out = {
         "metric": METRIC,
         "value": value,
@@ -208,7 +264,8 @@ def main():
         "time_step_share": prof["step_ms"] / (elapsed * 1e3),
         "roofline": {"bound": "hbm", "kernel": "k_history<4>", "achieved": hist_gbs,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": (hist_gbs / HBM_PEAK_GBS) if hist_gbs else None, "traffic": None,
+                     "frac": (hist_gbs / HBM_PEAK_GBS) if hist_gbs else None, "traffic": traffic,
+                     "traffic_at": traffic_at,
                      "launches": prof["hist_launches"],
                      "avg_launch_us": prof["hist_ms"] * 1e3 / max(1, prof["hist_launches"])},
         "check": {"max_density_deviation_at_nt": dens_dev},

@@ -216,19 +216,38 @@ hipError_t launch_gj_inverse(int N, cplx* A, cplx* work, int* piv, int* status, 
 
 // ------------------------------------------------------------ matvec
 // y = X v  or  y = b - X v ; one wavefront per row, lanes stride the row.
-__global__ __launch_bounds__(NT3) void k_matvec(int N, int nrhs, const cplx* X, const cplx* v,
-                                                const cplx* b, cplx* y) {
+// One wavefront per row r: y_r = X_r v (or b_r - X_r v); four row elements
+// (and their right-hand sides) are loaded per round.
+template <int NR>
+__global__ __launch_bounds__(NT3) void k_matvec(int N, const cplx* X, const cplx* v, const cplx* b, cplx* y) {
   int lane = threadIdx.x % 64;
   long r = (long)blockIdx.x * (NT3 / 64) + threadIdx.x / 64;
   if (r >= N) return;
-  cplx acc[8];
-  for (int c = 0; c < 8; c++) acc[c] = mk(0, 0);
+  cplx acc[NR];
+#pragma unroll
+  for (int c = 0; c < NR; c++) acc[c] = mk(0, 0);
   const cplx* row = X + r * N;
-  for (int q = lane; q < N; q += 64) {
-    cplx x = row[q];
-    for (int c = 0; c < nrhs; c++) cfma(acc[c], x, v[(long)q * nrhs + c]);
+  int q = lane;
+  for (; q + 192 < N; q += 256) {
+    cplx x[4], w[4][NR];
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+      x[u] = gld(row + q + 64 * u);
+#pragma unroll
+      for (int c = 0; c < NR; c++) w[u][c] = gld(v + (long)(q + 64 * u) * NR + c);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; u++)
+#pragma unroll
+      for (int c = 0; c < NR; c++) cfma(acc[c], x[u], w[u][c]);
   }
-  for (int c = 0; c < nrhs; c++) {
+  for (; q < N; q += 64) {
+    cplx x = gld(row + q);
+#pragma unroll
+    for (int c = 0; c < NR; c++) cfma(acc[c], x, gld(v + (long)q * NR + c));
+  }
+#pragma unroll
+  for (int c = 0; c < NR; c++) {
     double re = acc[c].x, im = acc[c].y;
     for (int off = 32; off > 0; off >>= 1) {
       re += __shfl_xor(re, off);
@@ -236,14 +255,25 @@ __global__ __launch_bounds__(NT3) void k_matvec(int N, int nrhs, const cplx* X, 
     }
     if (lane == 0) {
       cplx o = mk(re, im);
-      y[r * nrhs + c] = b ? b[r * nrhs + c] - o : o;
+      y[r * NR + c] = b ? b[r * NR + c] - o : o;
     }
   }
 }
 
 hipError_t launch_matvec(int N, int nrhs, const cplx* X, const cplx* v, const cplx* b, cplx* y,
                          hipStream_t s) {
-  k_matvec<<<(N + 3) / 4, NT3, 0, s>>>(N, nrhs, X, v, b, y);
+  int g = (N + 3) / 4;
+  switch (nrhs) {
+    case 1: k_matvec<1><<<g, NT3, 0, s>>>(N, X, v, b, y); break;
+    case 2: k_matvec<2><<<g, NT3, 0, s>>>(N, X, v, b, y); break;
+    case 3: k_matvec<3><<<g, NT3, 0, s>>>(N, X, v, b, y); break;
+    case 4: k_matvec<4><<<g, NT3, 0, s>>>(N, X, v, b, y); break;
+    case 5: k_matvec<5><<<g, NT3, 0, s>>>(N, X, v, b, y); break;
+    case 6: k_matvec<6><<<g, NT3, 0, s>>>(N, X, v, b, y); break;
+    case 7: k_matvec<7><<<g, NT3, 0, s>>>(N, X, v, b, y); break;
+    case 8: k_matvec<8><<<g, NT3, 0, s>>>(N, X, v, b, y); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

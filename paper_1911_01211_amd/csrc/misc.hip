@@ -579,18 +579,63 @@ hipError_t launch_convolution(const ProbArg& C, const ProbArg& A, const ProbArg&
 
 namespace cntr {
 
+// Matsubara convolution with the terms of an element split over GM = 16
+// consecutive lanes (term index = lane mod 16), summed with shuffles in a
+// fixed order.
+constexpr int GM = 16;
+__device__ inline cplx mat_conv_part(const Prob& P, const cplx* A, const cplx* B, const cplx* f, int m, int a,
+                                     int c, int g) {
+  const KW& W = c_kw[P.k];
+  int d = P.d, dd = d * d, k = P.k, nt = P.ntau;
+  double ht = P.htau, xi = P.sig;
+  const cplx* fm = fat(f, -1, d);
+  cplx acc = mk(0, 0);
+  auto pr = [&](int ia, int ib) {
+    return triple(d, [&](int x, int y) { return A[(size_t)ia * dd + x * d + y]; }, fm,
+                  [&](int x, int y) { return B[(size_t)ib * dd + x * d + y]; }, a, c);
+  };
+  int K1 = k + 1;
+  if (m <= k) {
+    for (int t = g; t < K1 * K1; t += GM) {
+      int j = t / K1, l = t % K1;
+      acc = acc + (ht * W.R[m][j][l]) * pr(j, l);
+    }
+  } else {
+    for (int l = g; l <= m; l += GM) acc = acc + (ht * greg(W, m, l)) * pr(m - l, l);
+  }
+  if (m >= nt - k) {
+    for (int t = g; t < K1 * K1; t += GM) {
+      int j = t / K1, l = t % K1;
+      acc = acc + (ht * xi * W.R[nt - m][j][l]) * pr(nt - j, nt - l);
+    }
+  } else {
+    for (int l = g; l <= nt - m; l += GM) acc = acc + (ht * xi * greg(W, nt - m, l)) * pr(nt - l, m + l);
+  }
+  return acc;
+}
+
 __global__ __launch_bounds__(NT2) void k_mat_conv(Prob P, const cplx* A, const cplx* B, const cplx* f,
                                                   cplx* out) {
   int d = P.d, dd = d * d;
-  long idx = (long)blockIdx.x * NT2 + threadIdx.x;
-  if (idx >= (long)(P.ntau + 1) * dd) return;
-  int m = idx / dd, e = idx % dd;
-  out[idx] = mat_conv_elem(P, A, B, f, m, e / d, e % d);
+  long gidx = (long)blockIdx.x * NT2 + threadIdx.x;
+  long idx = gidx / GM;
+  int g = (int)(gidx % GM);
+  bool valid = idx < (long)(P.ntau + 1) * dd;
+  cplx acc = mk(0, 0);
+  if (valid) {
+    int m = idx / dd, e = idx % dd;
+    acc = mat_conv_part(P, A, B, f, m, e / d, e % d, g);
+  }
+  for (int off = 1; off < GM; off <<= 1) {
+    acc.x += __shfl_xor(acc.x, off);
+    acc.y += __shfl_xor(acc.y, off);
+  }
+  if (valid && g == 0) out[idx] = acc;
 }
 
 hipError_t launch_mat_conv(const Prob& P, const cplx* A, const cplx* B, const cplx* f, cplx* out,
                            hipStream_t s) {
-  long tot = (long)(P.ntau + 1) * P.d * P.d;
+  long tot = (long)(P.ntau + 1) * P.d * P.d * GM;
   k_mat_conv<<<(unsigned)((tot + NT2 - 1) / NT2), NT2, 0, s>>>(P, A, B, f, out);
   return hipGetLastError();
 }
