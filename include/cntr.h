@@ -199,6 +199,34 @@ cntr_status cntr_solve_2b(const cntr_grid* grid, const cntr_gf* G, const cntr_gf
                           double mats_mix, int32_t boot_maxit, double boot_tol, int32_t ncorr,
                           int32_t nt_stop, double* stats, void* stream);
 
+/* ----------------------------------------------------------------- A12 --
+ * Discrete adjoint (reverse mode) of the Dyson solution for a given
+ * self-energy: the start-up of slices 0..k and the data-parallel time steps
+ * k+1..nt, exactly as cntr_dyson_step computes them (Sec. "Dyson equation:
+ * start-up" and "Time stepping"; the adjoint itself is not in the paper).
+ * With the Matsubara component M and Sigma held fixed, G(eps, Sigma, M) is the
+ * solution of slices 0..nt; for a real objective J(G) the call returns
+ *   dJ/d eps_n   (n = 0..nt),   dJ/d Sigma (slices 0..nt),   dJ/d M.
+ * Convention: for a complex entry z = x + i y the gradient is
+ * dJ/dx + i dJ/dy, so dJ = Re sum conj(grad) dz.
+ *   G        : the converged solution (slices -1..nt) of the same grid, eps and
+ *              Sigma (as written by cntr_dyson_step).
+ *   Gbar     : in: dJ/dG of the objective's explicit dependence on slices
+ *              0..nt (ret, les, tv) and on M (mat); out: mat += the
+ *              contributions of every slice, i.e. the total dJ/dM; ret, les
+ *              and tv are consumed as work space (their values on return are
+ *              the intermediate adjoints of the sweep).
+ *   Sigmabar : NULL, or accumulators (+=) for dJ/dSigma of slices 0..nt
+ *              (ret, les, tv; mat is not touched).
+ *   eps_bar  : accumulators (+=) of (nt+2) blocks, entry n+1 for eps_n
+ *              (entry 0, eps_{-1}, is not touched: it enters only M).
+ * Instances may have different nt (each is swept from its own nt). Every
+ * pointer is a DEVICE pointer, owned by the caller. Synchronizes `stream`;
+ * CNTR_ESINGULAR if a local step or start-up matrix is singular. */
+cntr_status cntr_adjoint_sweep(int32_t count, const cntr_grid* grids, const cntr_gf* G, const cntr_gf* Sigma,
+                               const void* const* eps, const cntr_gf* Gbar, const cntr_gf* Sigmabar,
+                               void* const* eps_bar, void* stream);
+
 /* ------------------------------------------------------------ profiling --
  * Device-time accounting of the time step, measured with HIP events
  * recorded on the stream each kernel is launched on. Between

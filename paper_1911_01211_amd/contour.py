@@ -184,6 +184,17 @@ def observables(tstp: int, G: list, Sigma: list, eps0: list, eps_mf=None, stream
     return obs, rho
 
 
+def adjoint_sweep(G: list, Sigma: list, eps: list, Gbar: list, eps_bar: list, Sigmabar: list | None = None,
+                  stream=None):
+    """Reverse-mode sweep of the Dyson solution for a given self-energy
+    (cntr_adjoint_sweep): Gbar holds dJ/dG on entry (consumed; Gbar.mat
+    returns dJ/dM), eps_bar (+=) receives dJ/deps_n, Sigmabar (+=, optional)
+    dJ/dSigma. Gradients are dJ/dRe + i dJ/dIm of every complex entry."""
+    sb = None if Sigmabar is None else _gfs(Sigmabar)
+    _abi.check(_abi.lib().cntr_adjoint_sweep(len(G), _grids(G), _gfs(G), _gfs(Sigma), _ptrs(eps), _gfs(Gbar),
+                                             sb, _ptrs(eps_bar), _stream(stream)))
+
+
 def extrapolate(tstp: int, G: list, stream=None):
     _abi.check(_abi.lib().cntr_extrapolate(tstp, len(G), _grids(G), _gfs(G), _stream(stream)))
 

@@ -1,0 +1,1242 @@
+// Discrete adjoint of the Dyson time stepper for a given self-energy:
+// reverse mode of the start-up (Sec. "Dyson equation: start-up") and of the
+// data-parallel time step (Sec. "Time stepping": bulk rows of R and G^< by
+// the single steps of Eqs. MBCVSAMx_t / MBCVSAMx_cc_t, k+1 boundary points
+// by the serial forms and the conjugate start-up, Eq. MBCVSAMx_cc_start).
+//
+// The forward step writes slice n as a sequence of block solves
+//   A X = r(earlier blocks)   or   X A = r(earlier blocks),
+// so the adjoint runs the slices backwards, n = nt .. k+1, then the start-up,
+// and for every solve applies the conjugate-transposed solve to the adjoint of
+// X and scatters the result into the adjoints of the blocks r reads.
+// Gradients use one convention throughout: for a real objective J and a
+// complex entry z = x + iy the library accumulates dJ/dx + i dJ/dy. Then
+//   X = A^{-1} r : rbar = A^{-H} Xbar, Abar -= rbar X^H
+//   X = r A^{-1} : rbar = Xbar A^{-H}, Abar -= X^H rbar
+//   Y = c P Q    : Pbar += conj(c) Ybar Q^H, Qbar += conj(c) P^H Ybar
+// and an extended block (the R continuation -[R_{b,a}]^dag, the hermitian
+// partner -[L_{b,a}]^dag, G^lceil = -xi [T]^dag) sends the conjugate
+// transpose of its adjoint to the stored block.
+//
+// Every kernel body is a host-and-device function of (thread index, thread
+// count), so its index arithmetic compiles on the host as well.
+#pragma once
+#include "dev_common.h"
+
+namespace cntr {
+
+#if defined(__HIP_DEVICE_COMPILE__)
+#define ADJ_SYNC() __syncthreads()
+#else
+#define ADJ_SYNC() ((void)0)
+#endif
+
+// One problem of an adjoint sweep. Pointers are device pointers in the
+// canonical layout; the adjoint arrays have the shape of the quantity.
+struct AdjProb {
+  Prob p;                    // G (forward solution), Sigma, eps, grid
+  cplx *aR, *aL, *aT, *aM;   // adjoint of G: seed in, dJ/dM out in aM
+  cplx *sR, *sL, *sT;        // dJ/dSigma (accumulated), null: not formed
+  cplx *ge;                  // dJ/deps_n at index n+1 (accumulated)
+  cplx* scr;                 // scratch of this problem
+  int* stat;                 // set to 1 by a kernel that meets a singular local matrix
+};
+
+constexpr int ADJ_NT = 256;  // threads per workgroup of every adjoint kernel
+
+__host__ __device__ inline size_t oR(int a, int b) { return tri(a) + b; }  // R_{a,b}, a >= b
+__host__ __device__ inline size_t oL(int a, int b) { return tri(b) + a; }  // L_{a,b}, a <= b
+__host__ __device__ inline size_t oT(int n, int m, int ntau) { return (size_t)n * (ntau + 1) + m; }
+
+// Gregory weight w_{N,j} (host-and-device copy of the time stepper's rule).
+__host__ __device__ inline double adj_w(const KW& W, int N, int j) {
+  int k = W.k;
+  if (N <= k) return W.s[N][j];
+  bool left = j <= k, right = N - j <= k;
+  if (left && right) return W.omega[j] + W.omega[N - j] - 1.0;
+  if (left) return W.omega[j];
+  if (right) return W.omega[N - j];
+  return 1.0;
+}
+
+// scratch layout of one problem, in complex units
+struct AdjLayout {
+  size_t mrinv, rhoB, rhoL, rhoT, rhoR, part, binv, psi, pst, total;
+  int cb, npart;
+};
+__host__ __device__ inline int adj_cb(int dd) { return dd >= ADJ_NT ? 1 : ADJ_NT / dd; }
+__host__ __device__ inline AdjLayout adj_layout(int nt, int ntau, int d, int k) {
+  AdjLayout L;
+  size_t dd = (size_t)d * d;
+  L.cb = adj_cb((int)dd);
+  L.npart = 2 * ((nt + 1 + L.cb - 1) / L.cb) + (ntau + 1 + L.cb - 1) / L.cb + 3;
+  size_t o = 0;
+  L.mrinv = o; o += dd;
+  L.rhoB = o; o += (size_t)(2 * k + 2) * dd;
+  L.rhoL = o; o += (size_t)(nt + 1) * dd;
+  L.rhoT = o; o += (size_t)(ntau + 1) * dd;
+  L.rhoR = o; o += (size_t)(nt + 1) * dd;
+  L.part = o; o += (size_t)L.npart * dd;
+  L.binv = o; o += (size_t)k * d * k * d;
+  L.psi = o; o += (size_t)k * (ntau + 1) * dd;
+  L.pst = o; o += (size_t)k * (k + 1) * dd;
+  L.total = o;
+  return L;
+}
+
+// ----------------------------------------------------------- element access
+struct AdjView {
+  const Prob& P;
+  const AdjProb& A;
+  const KW& W;
+  int d, dd, k, nt, ntau;
+  double h, ht, xi;
+  AdjLayout lay;
+  __host__ __device__ AdjView(const AdjProb& a, const KW& w)
+      : P(a.p), A(a), W(w), d(a.p.d), dd(a.p.d * a.p.d), k(a.p.k), nt(a.p.nt), ntau(a.p.ntau),
+        h(a.p.h), ht(a.p.htau), xi((double)a.p.sig), lay(adj_layout(a.p.nt, a.p.ntau, a.p.d, a.p.k)) {}
+  // stored blocks
+  __host__ __device__ const cplx* GR(int a, int b) const { return P.Gret + oR(a, b) * dd; }
+  __host__ __device__ const cplx* GL(int a, int b) const { return P.Gles + oL(a, b) * dd; }
+  __host__ __device__ const cplx* GT(int n, int m) const { return P.Gtv + oT(n, m, ntau) * dd; }
+  __host__ __device__ const cplx* GM(int m) const { return P.Gmat + (size_t)m * dd; }
+  __host__ __device__ const cplx* SR(int a, int b) const { return P.Sret + oR(a, b) * dd; }
+  __host__ __device__ const cplx* SL(int a, int b) const { return P.Sles + oL(a, b) * dd; }
+  __host__ __device__ const cplx* ST(int n, int m) const { return P.Stv + oT(n, m, ntau) * dd; }
+  __host__ __device__ cplx* aR(int a, int b) const { return A.aR + oR(a, b) * dd; }
+  __host__ __device__ cplx* aL(int a, int b) const { return A.aL + oL(a, b) * dd; }
+  __host__ __device__ cplx* aT(int n, int m) const { return A.aT + oT(n, m, ntau) * dd; }
+  __host__ __device__ cplx* aM(int m) const { return A.aM + (size_t)m * dd; }
+  __host__ __device__ cplx* sR(int a, int b) const { return A.sR + oR(a, b) * dd; }
+  __host__ __device__ cplx* sL(int a, int b) const { return A.sL + oL(a, b) * dd; }
+  __host__ __device__ cplx* sT(int n, int m) const { return A.sT + oT(n, m, ntau) * dd; }
+  __host__ __device__ cplx* ge(int n) const { return A.ge + (size_t)(n + 1) * dd; }
+  __host__ __device__ cplx* scr(size_t off) const { return A.scr + off; }
+  // extended elements
+  __host__ __device__ cplx Rt(const cplx* X, int a, int b, int r, int c) const {
+    return a >= b ? X[oR(a, b) * dd + r * d + c] : -conj(X[oR(b, a) * dd + c * d + r]);
+  }
+  __host__ __device__ cplx Lh(const cplx* X, int a, int b, int r, int c) const {
+    return a <= b ? X[oL(a, b) * dd + r * d + c] : -conj(X[oL(b, a) * dd + c * d + r]);
+  }
+  // e_n - mu
+  __host__ __device__ cplx eh(int n, int r, int c) const {
+    cplx v = P.eps[(size_t)(n + 1) * dd + r * d + c];
+    if (r == c) v.x -= P.mu;
+    return v;
+  }
+};
+
+// sum_q a(q) b(q), q = 0..d-1
+template <class FA, class FB>
+__host__ __device__ inline cplx dotq(int d, FA fa, FB fb) {
+  cplx s = mk(0, 0);
+  for (int q = 0; q < d; q++) cfma(s, fa(q), fb(q));
+  return s;
+}
+
+// --------------------------------------------------------------- team algebra
+// Gauss-Jordan inverse in place (n x n, row-major) by a team of `nth`
+// threads; pivot search by thread 0. piv: n + 2 ints. Returns false if
+// singular (uniform over the team).
+__host__ __device__ inline bool team_inverse(int n, cplx* A, int* piv, int tid, int nth) {
+  for (int c = 0; c < n; c++) {
+    if (tid == 0) {
+      int p = c;
+      double best = abs2(A[c * n + c]);
+      for (int r = c + 1; r < n; r++) {
+        double v = abs2(A[r * n + c]);
+        if (v > best) {
+          best = v;
+          p = r;
+        }
+      }
+      piv[c] = p;
+      piv[n] = best > 0.0 ? 1 : 0;
+    }
+    ADJ_SYNC();
+    if (piv[n] == 0) return false;
+    int p = piv[c];
+    if (p != c)
+      for (int q = tid; q < n; q += nth) {
+        cplx t = A[p * n + q];
+        A[p * n + q] = A[c * n + q];
+        A[c * n + q] = t;
+      }
+    ADJ_SYNC();
+    cplx ipv = cdiv(mk(1, 0), A[c * n + c]);
+    for (int idx = tid; idx < n * n; idx += nth) {
+      int r = idx / n, q = idx % n;
+      if (r == c || q == c) continue;
+      A[r * n + q] = A[r * n + q] - A[r * n + c] * (A[c * n + q] * ipv);
+    }
+    ADJ_SYNC();
+    for (int r = tid; r < n; r += nth)
+      if (r != c) A[r * n + c] = -(A[r * n + c] * ipv);
+    ADJ_SYNC();
+    for (int q = tid; q < n; q += nth) A[c * n + q] = (q == c) ? ipv : A[c * n + q] * ipv;
+    ADJ_SYNC();
+  }
+  for (int c = n - 1; c >= 0; c--) {
+    int p = piv[c];
+    if (p != c)
+      for (int r = tid; r < n; r += nth) {
+        cplx t = A[r * n + p];
+        A[r * n + p] = A[r * n + c];
+        A[r * n + c] = t;
+      }
+    ADJ_SYNC();
+  }
+  return true;
+}
+
+// ------------------------------------------------------------ les_source
+// Forward value of the lesser source of row m, column n, element (r, c):
+//   q = -i (C^<_2 + C^<_3)[Sigma, 1, G](m, n),
+//   C^<_2 = sum_{j<=max(n,k)} h w_{n,j} Sigma^<_{m,j} G^A_{j,n},
+//   C^<_3 = -i h_tau sum_j w_{ntau,j} Sigma^rceil_{m,j} G^lceil(tau_j, t_n).
+__host__ __device__ inline cplx les_source_elem(const AdjView& V, int m, int n, int r, int c) {
+  int d = V.d, jmax = n > V.k ? n : V.k;
+  cplx c2 = mk(0, 0), c3 = mk(0, 0);
+  for (int j = 0; j <= jmax; j++) {
+    // G^A_{j,n}[q][c] = conj(Rt(G, n, j)[c][q])
+    cplx t = dotq(d, [&](int q) { return V.Lh(V.P.Sles, m, j, r, q); },
+                  [&](int q) { return conj(V.Rt(V.P.Gret, n, j, c, q)); });
+    c2 = c2 + (V.h * adj_w(V.W, n, j)) * t;
+  }
+  for (int j = 0; j <= V.ntau; j++) {
+    // G^lceil(tau_j, t_n)[q][c] = -xi conj(T_{n, ntau-j}[c][q])
+    const cplx* s = V.ST(m, j);
+    const cplx* g = V.GT(n, V.ntau - j);
+    cplx t = dotq(d, [&](int q) { return s[r * d + q]; }, [&](int q) { return conj(g[c * d + q]); });
+    c3 = c3 + (-V.xi * V.ht * adj_w(V.W, V.ntau, j)) * t;
+  }
+  // -i (c2 + (-i) c3) = -i c2 - c3
+  return mk(c2.y, -c2.x) - c3;
+}
+
+// start_block(p, l)[r][c] = h^-1 D_{p,l} + delta_{pl} i e_p + i h s_{p,l} Sigma~^R_{p,l}
+__host__ __device__ inline cplx start_block_elem(const AdjView& V, int p, int l, int r, int c) {
+  cplx v = V.Rt(V.P.Sret, p, l, r, c);
+  v = mul_i((V.h * V.W.s[p][l]) * v);
+  if (r == c) v.x += V.W.D[p][l] / V.h;
+  if (p == l) v = v + mul_i(V.eh(p, r, c));
+  return v;
+}
+
+// ============================================================== K1a
+// Serial part of the lesser column n (one team per problem):
+//  * n > 2k: boundary rows m = n..n-k (serial steps (A)) in reverse order;
+//  * k < n <= 2k: rows n..k+1 in reverse order, then the start-up rows 1..k;
+//  * n <= k: the start-up rows 1..k of column n.
+// Writes the row adjoints rho_m (gq of the lesser source of row m) to rhoB,
+// the eps and Sigma^R adjoints of the local step matrices, and the adjoint
+// updates among the rows it owns; K1b scatters the rest. Also stores M_R^{-1}
+// of slice n (n > k) for the bulk kernels.
+// lds: >= (2k+2) dd + 4 dd + 5 (k d)^2-sized... see adj_lcol_lds().
+__host__ __device__ inline int adj_lcol_lds(int d, int k) {
+  int dd = d * d, kd = k * d;
+  return (2 * k + 2) * dd + 3 * dd + kd * kd + 4 * kd * d;
+}
+
+__host__ __device__ inline bool adj_lcol_team(const AdjProb& Ap, const KW& W, int n, int tid, int nth,
+                                              cplx* lds, int* piv) {
+  AdjView V(Ap, W);
+  int d = V.d, dd = V.dd, k = V.k;
+  double h = V.h;
+  bool ok = true;
+  cplx* acc = lds;                      // (2k+2) blocks: adjoints of rows r0..n
+  cplx* Am = acc + (2 * k + 2) * dd;    // d x d
+  cplx* rho = Am + dd;                  // d x d
+  cplx* tmp = rho + dd;                 // d x d
+  cplx* Bb = tmp + dd;                  // (k d)^2
+  cplx* yv = Bb + k * d * k * d;        // k d x d
+  cplx* lam = yv + k * d * d;
+  cplx* psi = lam + k * d * d;
+  cplx* rr = psi + k * d * d;
+  cplx* rhoB = V.scr(V.lay.rhoB);
+  bool bulk = n > 2 * k;
+  int r0 = bulk ? n - k : 0;  // first row held in acc
+  // M_R^{-1} of slice n for the bulk kernels
+  if (n > k) {
+    for (int e = tid; e < dd; e += nth) {
+      int r = e / d, c = e % d;
+      cplx v = mul_i((h * adj_w(W, n, n)) * V.SR(n, n)[e]) + mul_i(V.eh(n, r, c));
+      if (r == c) v.x += W.a[0] / h;
+      Am[e] = v;
+    }
+    ADJ_SYNC();
+    ok = team_inverse(d, Am, piv, tid, nth) && ok;
+    for (int e = tid; e < dd; e += nth) V.scr(V.lay.mrinv)[e] = Am[e];
+    ADJ_SYNC();
+  }
+  for (int e = tid; e < (n - r0 + 1) * dd; e += nth) acc[e] = V.aL(r0 + e / dd, n)[e % dd];
+  ADJ_SYNC();
+  // serial steps (A), rows m = n .. mlo in reverse order
+  int mlo = bulk ? n - k : k + 1;
+  for (int m = n; m >= mlo && n > k; m--) {
+    // A_m = h^-1 a_0 + i e_m + i h w_{m,m} Sigma^R_{m,m}; rho = A_m^{-H} lambda_m
+    for (int e = tid; e < dd; e += nth) {
+      int r = e / d, c = e % d;
+      cplx v = mul_i((h * adj_w(W, m, m)) * V.SR(m, m)[e]) + mul_i(V.eh(m, r, c));
+      if (r == c) v.x += W.a[0] / h;
+      Am[e] = v;
+    }
+    ADJ_SYNC();
+    ok = team_inverse(d, Am, piv, tid, nth) && ok;
+    const cplx* lm = acc + (m - r0) * dd;
+    for (int e = tid; e < dd; e += nth) {
+      int r = e / d, c = e % d;
+      rho[e] = dotq(d, [&](int q) { return conj(Am[q * d + r]); }, [&](int q) { return lm[q * d + c]; });
+    }
+    ADJ_SYNC();
+    int slot = bulk ? m - (n - k) : m - 1;
+    for (int e = tid; e < dd; e += nth) rhoB[slot * dd + e] = rho[e];
+    // eps_m and Sigma^R_{m,m}: Abar = -rho L_{m,n}^H
+    const cplx* Lmn = V.GL(m, n);
+    for (int e = tid; e < dd; e += nth) {
+      int r = e / d, c = e % d;
+      cplx t = dotq(d, [&](int q) { return rho[r * d + q]; }, [&](int q) { return conj(Lmn[c * d + q]); });
+      V.ge(m)[e] = V.ge(m)[e] + mul_i(t);
+      if (V.A.sR) V.sR(m, m)[e] = V.sR(m, m)[e] + mul_i((h * adj_w(W, m, m)) * t);
+    }
+    // rows j in [r0, m): history term and BDF
+    for (int e = tid; e < (m - r0) * dd; e += nth) {
+      int j = r0 + e / dd, r = (e % dd) / d, c = e % d;
+      const cplx* s = V.SR(m, j);
+      cplx t = dotq(d, [&](int q) { return conj(s[q * d + r]); }, [&](int q) { return rho[q * d + c]; });
+      cplx v = mul_i((h * adj_w(W, m, j)) * t);
+      int l = m - j;
+      if (l <= k) v = v - (W.a[l] / h) * rho[r * d + c];
+      acc[(j - r0) * dd + r * d + c] = acc[(j - r0) * dd + r * d + c] + v;
+      if (V.A.sR) {
+        const cplx* Lj = V.GL(j, n);
+        cplx u = dotq(d, [&](int q) { return rho[r * d + q]; }, [&](int q) { return conj(Lj[c * d + q]); });
+        V.sR(m, j)[r * d + c] = V.sR(m, j)[r * d + c] + mul_i((h * adj_w(W, m, j)) * u);
+      }
+    }
+    ADJ_SYNC();
+  }
+  if (!bulk) {
+    // start-up rows 1..k of column n (Eq. vdiff_start, y_0 = -[T_{n,0}]^dag)
+    int kd = k * d;
+    for (int e = tid; e < kd * kd; e += nth) {
+      int R = e / kd, C = e % kd;
+      Bb[e] = start_block_elem(V, 1 + R / d, 1 + C / d, R % d, C % d);
+    }
+    // r_p = q_p - B_{p,0} y_0
+    for (int e = tid; e < kd * d; e += nth) {
+      int p = 1 + e / dd, r = (e % dd) / d, c = e % d;
+      cplx v = les_source_elem(V, p, n, r, c);
+      const cplx* T0 = V.GT(n, 0);
+      // y0[q][c] = -conj(T0[c][q])
+      cplx t = dotq(d, [&](int q) { return start_block_elem(V, p, 0, r, q); },
+                    [&](int q) { return -conj(T0[c * d + q]); });
+      rr[e] = v - t;
+      lam[e] = (p <= n) ? acc[p * dd + r * d + c] : mk(0, 0);
+    }
+    ADJ_SYNC();
+    ok = team_inverse(kd, Bb, piv, tid, nth) && ok;
+    for (int e = tid; e < kd * d; e += nth) {
+      int R = e / d, c = e % d;
+      cplx y = mk(0, 0), s = mk(0, 0);
+      for (int q = 0; q < kd; q++) {
+        cfma(y, Bb[R * kd + q], rr[q * d + c]);
+        cfma(s, conj(Bb[q * kd + R]), lam[q * d + c]);
+      }
+      yv[e] = y;
+      psi[e] = s;
+    }
+    ADJ_SYNC();
+    for (int e = tid; e < kd * d; e += nth) rhoB[e] = psi[e];  // rows 1..k at slots 0..k-1
+    // eps_p += i psi_p y_p^H
+    for (int e = tid; e < kd * d; e += nth) {
+      int p = 1 + e / dd, r = (e % dd) / d, c = e % d;
+      const cplx* ps = psi + (p - 1) * dd;
+      const cplx* yp = yv + (p - 1) * dd;
+      cplx t = dotq(d, [&](int q) { return ps[r * d + q]; }, [&](int q) { return conj(yp[c * d + q]); });
+      V.ge(p)[r * d + c] = V.ge(p)[r * d + c] + mul_i(t);
+    }
+    // y_0 = -[T_{n,0}]^dag: gy0 = lambda_0 - sum_p B_{p,0}^H psi_p ; Tbar_{n,0} -= gy0^H
+    for (int e = tid; e < dd; e += nth) {
+      int r = e / d, c = e % d;
+      // (gy0^H)[r][c] = conj(gy0[c][r])
+      cplx g = acc[0 * dd + c * d + r];
+      for (int p = 1; p <= k; p++) {
+        const cplx* ps = psi + (p - 1) * dd;
+        g = g - dotq(d, [&](int q) { return conj(start_block_elem(V, p, 0, q, c)); },
+                     [&](int q) { return ps[q * d + r]; });
+      }
+      V.aT(n, 0)[e] = V.aT(n, 0)[e] - conj(g);
+    }
+    // Sigma~^R_{p,l} += i h s_{p,l} psi_p y_l^H, p = 1..k, l = 0..k, on stored
+    // targets (a, b), a >= b: direct from (p,l) = (a,b), continuation from (b,a).
+    if (V.A.sR) {
+      int nb = (k + 1) * (k + 2) / 2;
+      for (int e = tid; e < nb * dd; e += nth) {
+        int t = e / dd, r = (e % dd) / d, c = e % d;
+        int a = 0;
+        while ((a + 1) * (a + 2) / 2 <= t) a++;
+        int b = t - a * (a + 1) / 2;
+        auto yl = [&](int l, int rr_, int q) -> cplx {  // y_l[c'][q] element
+          if (l == 0) return -conj(V.GT(n, 0)[q * d + rr_]);
+          return yv[(l - 1) * dd + rr_ * d + q];
+        };
+        cplx v = mk(0, 0);
+        if (a >= 1) {
+          const cplx* ps = psi + (a - 1) * dd;
+          cplx u = dotq(d, [&](int q) { return ps[r * d + q]; }, [&](int q) { return conj(yl(b, c, q)); });
+          v = v + mul_i((h * W.s[a][b]) * u);
+        }
+        if (b >= 1 && a > b) {
+          // -(i h s_{b,a} psi_b y_a^H)^H = i h s_{b,a} y_a psi_b^H
+          const cplx* ps = psi + (b - 1) * dd;
+          cplx u = dotq(d, [&](int q) { return yl(a, r, q); }, [&](int q) { return conj(ps[c * d + q]); });
+          v = v + mul_i((h * W.s[b][a]) * u);
+        }
+        V.sR(a, b)[r * d + c] = V.sR(a, b)[r * d + c] + v;
+      }
+    }
+    ADJ_SYNC();
+  }
+  return ok;
+}
+
+// ============================================================== K1b
+// Parallel part of the lesser column: the reverse of the sources of rows
+// r0..r1 (row adjoints in rhoB) and, for n > 2k, the boundary rows' history
+// terms on the bulk rows j < n-k.
+struct LcolGeom {
+  int r0, r1, jmax, bs0;
+  size_t o1, o1x, o2, o3, o4, o5, o6, total;  // element offsets of the output groups
+};
+__host__ __device__ inline LcolGeom lcol_geom(int n, int k, int ntau, int dd, bool sig) {
+  LcolGeom G;
+  bool bulk = n > 2 * k;
+  G.r0 = bulk ? n - k : 1;
+  G.r1 = bulk ? n : (n > k ? n : k);
+  G.jmax = n > k ? n : k;
+  G.bs0 = G.r0;
+  size_t o = 0;
+  G.o1 = o; o += (size_t)(n + 1) * dd;                                  // aR(n, j), j <= n
+  G.o1x = o; o += (size_t)(n < k ? k - n : 0) * dd;                      // aR(j, n), n < j <= k
+  G.o2 = o; o += (size_t)(ntau + 1) * dd;                               // aT(n, tau)
+  G.o3 = o; o += sig ? (size_t)(G.r1 - G.r0 + 1) * (ntau + 1) * dd : 0;  // sT(m, j)
+  G.o4 = o; o += sig ? (tri(G.jmax + 1) - tri(G.bs0)) * dd : 0;          // sL slices bs0..jmax
+  G.o5 = o; o += bulk ? (size_t)(n - k) * dd : 0;                       // aL(j, n), j < n-k
+  G.o6 = o; o += (bulk && sig) ? (size_t)(k + 1) * (n - k) * dd : 0;     // sR(m, j)
+  G.total = o;
+  return G;
+}
+
+__host__ __device__ inline void adj_lcol_elem(const AdjProb& Ap, const KW& W, int n, size_t idx) {
+  AdjView V(Ap, W);
+  int d = V.d, dd = V.dd, k = V.k, ntau = V.ntau;
+  double h = V.h, ht = V.ht, xi = V.xi;
+  bool sig = Ap.sR != nullptr;
+  LcolGeom G = lcol_geom(n, k, ntau, dd, sig);
+  if (idx >= G.total) return;
+  const cplx* rhoB = V.scr(V.lay.rhoB);
+  bool bulk = n > 2 * k;
+  auto gq = [&](int m) { return rhoB + (size_t)(bulk ? m - (n - k) : m - 1) * dd; };
+  int e = (int)(idx % dd), r = e / d, c = e % d;
+  if (idx < G.o1x) {
+    // aR(n, j) += sum_m -i h w_{n,j} gq_m^H Lh(S, m, j)
+    int j = (int)((idx - G.o1) / dd);
+    cplx acc = mk(0, 0);
+    for (int m = G.r0; m <= G.r1; m++) {
+      const cplx* g = gq(m);
+      acc = acc + dotq(d, [&](int q) { return conj(g[q * d + r]); },
+                       [&](int q) { return V.Lh(V.P.Sles, m, j, q, c); });
+    }
+    cplx v = mul_i(-(h * adj_w(W, n, j)) * acc);
+    V.aR(n, j)[e] = V.aR(n, j)[e] + v;
+  } else if (idx < G.o2) {
+    // j > n (start-up columns): aR(j, n) += sum_m -i h w_{n,j} Lh(S, m, j)^H gq_m
+    int j = n + 1 + (int)((idx - G.o1x) / dd);
+    cplx acc = mk(0, 0);
+    for (int m = G.r0; m <= G.r1; m++) {
+      const cplx* g = gq(m);
+      acc = acc + dotq(d, [&](int q) { return conj(V.Lh(V.P.Sles, m, j, q, r)); },
+                       [&](int q) { return g[q * d + c]; });
+    }
+    cplx v = mul_i(-(h * adj_w(W, n, j)) * acc);
+    V.aR(j, n)[e] = V.aR(j, n)[e] + v;
+  } else if (idx < G.o3) {
+    // aT(n, tau) += sum_m xi ht w_{ntau, ntau-tau} gq_m^H Sigma^rceil_{m, ntau-tau}
+    int tau = (int)((idx - G.o2) / dd), j = ntau - tau;
+    cplx acc = mk(0, 0);
+    for (int m = G.r0; m <= G.r1; m++) {
+      const cplx* g = gq(m);
+      const cplx* s = V.ST(m, j);
+      acc = acc + dotq(d, [&](int q) { return conj(g[q * d + r]); }, [&](int q) { return s[q * d + c]; });
+    }
+    V.aT(n, tau)[e] = V.aT(n, tau)[e] + (xi * ht * adj_w(W, ntau, j)) * acc;
+  } else if (idx < G.o4) {
+    // sT(m, j) += xi ht w_{ntau,j} gq_m T_{n, ntau-j}
+    size_t t = (idx - G.o3) / dd;
+    int m = G.r0 + (int)(t / (ntau + 1)), j = (int)(t % (ntau + 1));
+    const cplx* g = gq(m);
+    const cplx* T = V.GT(n, ntau - j);
+    cplx u = dotq(d, [&](int q) { return g[r * d + q]; }, [&](int q) { return T[q * d + c]; });
+    V.sT(m, j)[e] = V.sT(m, j)[e] + (xi * ht * adj_w(W, ntau, j)) * u;
+  } else if (idx < G.o5) {
+    // sL(a, b), slices b in [bs0, jmax], a <= b:
+    //   a in rows:         i h w_{n,b} gq_a Rt(G, n, b)
+    //   b in rows, a < b:  i h w_{n,a} Rt(G, n, a)^H gq_b^H
+    size_t t = tri(G.bs0) + (idx - G.o4) / dd;
+    int b = 0;
+    while (tri(b + 1) <= t) b++;
+    int a = (int)(t - tri(b));
+    cplx v = mk(0, 0);
+    if (a >= G.r0 && a <= G.r1) {
+      const cplx* g = gq(a);
+      cplx u = dotq(d, [&](int q) { return g[r * d + q]; }, [&](int q) { return V.Rt(V.P.Gret, n, b, q, c); });
+      v = v + mul_i((h * adj_w(W, n, b)) * u);
+    }
+    if (b >= G.r0 && b <= G.r1 && a < b) {
+      const cplx* g = gq(b);
+      cplx u = dotq(d, [&](int q) { return conj(V.Rt(V.P.Gret, n, a, q, r)); },
+                    [&](int q) { return conj(g[c * d + q]); });
+      v = v + mul_i((h * adj_w(W, n, a)) * u);
+    }
+    V.sL(a, b)[e] = V.sL(a, b)[e] + v;
+  } else if (idx < G.o6) {
+    // aL(j, n), j < n-k: sum_m i h w_{m,j} S^R_{m,j}^H rho_m - sum_{m=j+l} a_l/h rho_m
+    int j = (int)((idx - G.o5) / dd);
+    cplx v = mk(0, 0);
+    for (int m = n - k; m <= n; m++) {
+      const cplx* g = gq(m);
+      const cplx* s = V.SR(m, j);
+      cplx u = dotq(d, [&](int q) { return conj(s[q * d + r]); }, [&](int q) { return g[q * d + c]; });
+      v = v + mul_i((h * adj_w(W, m, j)) * u);
+      int l = m - j;
+      if (l >= 1 && l <= k) v = v - (W.a[l] / h) * g[e];
+    }
+    V.aL(j, n)[e] = V.aL(j, n)[e] + v;
+  } else {
+    // sR(m, j), m in [n-k, n], j < n-k: i h w_{m,j} rho_m L_{j,n}^H
+    size_t t = (idx - G.o6) / dd;
+    int m = n - k + (int)(t / (n - k)), j = (int)(t % (n - k));
+    const cplx* g = gq(m);
+    const cplx* L = V.GL(j, n);
+    cplx u = dotq(d, [&](int q) { return g[r * d + q]; }, [&](int q) { return conj(L[c * d + q]); });
+    V.sR(m, j)[e] = V.sR(m, j)[e] + mul_i((h * adj_w(W, m, j)) * u);
+  }
+}
+
+// ============================================================== Krho
+// Row adjoints of the bulk solves of slice n > k:
+//   lesser (n > 2k):  rhoL_m = Lbar_{m,n} M_R^{-1}           (m < n-k)
+//   mixing:           rhoT_t = M_R^{-H} Tbar_{n,t}            (t = 0..ntau)
+//   retarded:         rhoR_m = M_R^{-H} Rbar_{n,m}            (m < n-k)
+// and per-workgroup partial sums of M_Rbar = -sum rhoL^H L - sum rhoT T^H - sum rhoR R^H.
+struct RhoGeom {
+  int SL, ST, SR, wl, wt, wr;
+};
+__host__ __device__ inline RhoGeom rho_geom(int n, int k, int ntau, int cb) {
+  RhoGeom g;
+  g.SL = n > 2 * k ? n - k : 0;
+  g.ST = ntau + 1;
+  g.SR = n - k;
+  g.wl = (g.SL + cb - 1) / cb;
+  g.wt = (g.ST + cb - 1) / cb;
+  g.wr = (g.SR + cb - 1) / cb;
+  return g;
+}
+
+// element e of block b (global block index within the segment seg)
+__host__ __device__ inline cplx rho_elem(const AdjView& V, int n, int seg, int b, int r, int c) {
+  int d = V.d;
+  const cplx* Mi = V.scr(V.lay.mrinv);
+  if (seg == 0) {
+    const cplx* l = V.aL(b, n);
+    return dotq(d, [&](int q) { return l[r * d + q]; }, [&](int q) { return Mi[q * d + c]; });
+  }
+  const cplx* l = seg == 1 ? V.aT(n, b) : V.aR(n, b);
+  return dotq(d, [&](int q) { return conj(Mi[q * d + r]); }, [&](int q) { return l[q * d + c]; });
+}
+// contribution of block b to M_Rbar[r][c] given its rho (full block)
+__host__ __device__ inline cplx mr_term(const AdjView& V, int n, int seg, int b, const cplx* rho, int r, int c) {
+  int d = V.d;
+  if (seg == 0) {  // -rho^H L_{b,n}
+    const cplx* L = V.GL(b, n);
+    return -dotq(d, [&](int q) { return conj(rho[q * d + r]); }, [&](int q) { return L[q * d + c]; });
+  }
+  const cplx* X = seg == 1 ? V.GT(n, b) : V.GR(n, b);  // -rho X^H
+  return -dotq(d, [&](int q) { return rho[r * d + q]; }, [&](int q) { return conj(X[c * d + q]); });
+}
+
+// ============================================================== Kscatter
+// Adjoints of the history blocks of slices < n, one element per thread:
+//   L(a, b), a <= b < n:  lesser bulk rows (n > 2k)
+//   R(a, b), b <= a < n:  lesser C^<_1 rows and retarded bulk columns
+//   T(a, t), a < n:       lesser C^<_3 rows and mixing columns
+struct HistGeom {
+  size_t oL, oR, oT, total;
+};
+__host__ __device__ inline HistGeom hist_geom(int n, int k, int ntau, int dd) {
+  HistGeom g;
+  size_t o = 0;
+  g.oL = o; o += n > 2 * k ? tri(n) * dd : 0;
+  g.oR = o; o += tri(n) * dd;
+  g.oT = o; o += (size_t)n * (ntau + 1) * dd;
+  g.total = o;
+  return g;
+}
+
+__host__ __device__ inline void adj_hist_elem(const AdjProb& Ap, const KW& W, int n, size_t idx) {
+  AdjView V(Ap, W);
+  int d = V.d, dd = V.dd, k = V.k, ntau = V.ntau;
+  double h = V.h, ht = V.ht, xi = V.xi;
+  HistGeom G = hist_geom(n, k, ntau, dd);
+  if (idx >= G.total) return;
+  const cplx* rL = V.scr(V.lay.rhoL);
+  const cplx* rT = V.scr(V.lay.rhoT);
+  const cplx* rR = V.scr(V.lay.rhoR);
+  int e = (int)(idx % dd), r = e / d, c = e % d;
+  int nb = n - k;  // bulk rows / columns are < nb
+  bool lb = n > 2 * k;
+  if (idx < G.oR) {
+    size_t t = (idx - G.oL) / dd;
+    int b = 0;
+    while (tri(b + 1) <= t) b++;
+    int a = (int)(t - tri(b));
+    cplx v = mk(0, 0);
+    if (a < nb) {
+      // row m = a, l = b >= a: -i h w_{n,b} rhoL_a S^R_{n,b} (+ BDF for b >= n-k)
+      const cplx* g = rL + (size_t)a * dd;
+      const cplx* s = V.SR(n, b);
+      cplx u = dotq(d, [&](int q) { return g[r * d + q]; }, [&](int q) { return s[q * d + c]; });
+      v = v + mul_i(-(h * adj_w(W, n, b)) * u);
+      int l = n - b;
+      if (l >= 1 && l <= k) v = v - (W.a[l] / h) * g[e];
+    }
+    if (b < nb && a < b) {
+      // row m = b, l = a < b (hermitian partner): -i h w_{n,a} S^R_{n,a}^H rhoL_b^H
+      const cplx* g = rL + (size_t)b * dd;
+      const cplx* s = V.SR(n, a);
+      cplx u = dotq(d, [&](int q) { return conj(s[q * d + r]); }, [&](int q) { return conj(g[c * d + q]); });
+      v = v + mul_i(-(h * adj_w(W, n, a)) * u);
+    }
+    V.aL(a, b)[e] = V.aL(a, b)[e] + v;
+  } else if (idx < G.oT) {
+    size_t t = (idx - G.oR) / dd;
+    int a = 0;
+    while (tri(a + 1) <= t) a++;
+    int b = (int)(t - tri(a));
+    cplx v = mk(0, 0);
+    if (lb && a < nb) {
+      // lesser row m = a, C^<_1 term j = b: -i h w rhoL_a S^<_{b,n}^H (w = s_{a,b} for a <= k)
+      double wt = a > k ? adj_w(W, a, b) : W.s[a][b];
+      const cplx* g = rL + (size_t)a * dd;
+      const cplx* s = V.SL(b, n);
+      cplx u = dotq(d, [&](int q) { return g[r * d + q]; }, [&](int q) { return conj(s[c * d + q]); });
+      v = v + mul_i(-(h * wt) * u);
+    }
+    if (lb && b < nb && b <= k && a <= k && a > b) {
+      // lesser row m = b <= k, continuation Rt(G, b, a): -i h s_{b,a} S^<_{a,n} rhoL_b^H
+      const cplx* g = rL + (size_t)b * dd;
+      const cplx* s = V.SL(a, n);
+      cplx u = dotq(d, [&](int q) { return s[r * d + q]; }, [&](int q) { return conj(g[c * d + q]); });
+      v = v + mul_i(-(h * W.s[b][a]) * u);
+    }
+    if (b < nb) {
+      // retarded column m = b: i h w_{n-b, a-b} S^R_{n,a}^H rhoR_b (+ BDF for a >= n-k)
+      const cplx* g = rR + (size_t)b * dd;
+      const cplx* s = V.SR(n, a);
+      cplx u = dotq(d, [&](int q) { return conj(s[q * d + r]); }, [&](int q) { return g[q * d + c]; });
+      v = v + mul_i((h * adj_w(W, n - b, a - b)) * u);
+      int l = n - a;
+      if (l >= 1 && l <= k) v = v - (W.a[l] / h) * g[e];
+    }
+    V.aR(a, b)[e] = V.aR(a, b)[e] + v;
+  } else {
+    size_t t = (idx - G.oT) / dd;
+    int a = (int)(t / (ntau + 1)), tau = (int)(t % (ntau + 1));
+    cplx v = mk(0, 0);
+    if (lb && a < nb) {
+      // lesser row m = a, C^<_3: -xi ht w_{ntau,tau} rhoL_a S^rceil_{n, ntau-tau}
+      const cplx* g = rL + (size_t)a * dd;
+      const cplx* s = V.ST(n, ntau - tau);
+      cplx u = dotq(d, [&](int q) { return g[r * d + q]; }, [&](int q) { return s[q * d + c]; });
+      v = v + (-xi * ht * adj_w(W, ntau, tau)) * u;
+    }
+    {
+      // mixing column tau: i h w_{n,a} S^R_{n,a}^H rhoT_tau (+ BDF for a >= n-k)
+      const cplx* g = rT + (size_t)tau * dd;
+      const cplx* s = V.SR(n, a);
+      cplx u = dotq(d, [&](int q) { return conj(s[q * d + r]); }, [&](int q) { return g[q * d + c]; });
+      v = v + mul_i((h * adj_w(W, n, a)) * u);
+      int l = n - a;
+      if (l >= 1 && l <= k) v = v - (W.a[l] / h) * g[e];
+    }
+    V.aT(a, tau)[e] = V.aT(a, tau)[e] + v;
+  }
+}
+
+// ============================================================== KsigS
+// Self-energy adjoints of slice n from the bulk row adjoints (reductions):
+//   sR(n, j), j < n:   sum_{m<=j, m<n-k} i h w_{n-m,j-m} rhoR_m R_{j,m}^H
+//                    + sum_t i h w_{n,j} rhoT_t T_{j,t}^H
+//                    + sum_{m<n-k} i h w_{n,j} rhoL_m^H Lh(G, m, j)          (n > 2k)
+//   sL(j, n), j <= n:  sum_m h w rhoL-terms of C^<_1                          (n > 2k)
+//   sT(n, t):          sum_m -xi ht w_{ntau,ntau-t} rhoL_m^H T_{m, ntau-t}   (n > 2k)
+// One output block per workgroup; term index split over lane groups.
+struct SigGeom {
+  int nR, nL, nT, total;
+};
+__host__ __device__ inline SigGeom sig_geom(int n, int k, int ntau) {
+  SigGeom g;
+  g.nR = n;
+  g.nL = n > 2 * k ? n + 1 : 0;
+  g.nT = n > 2 * k ? ntau + 1 : 0;
+  g.total = g.nR + g.nL + g.nT;
+  return g;
+}
+// number of reduction terms of output block ob
+__host__ __device__ inline int sig_nterms(const AdjView& V, int n, int ob) {
+  SigGeom G = sig_geom(n, V.k, V.ntau);
+  int nb = n - V.k;
+  if (ob < G.nR) return (nb) + (V.ntau + 1) + (n > 2 * V.k ? nb : 0);
+  if (ob < G.nR + G.nL) return nb;
+  return nb;
+}
+__host__ __device__ inline cplx sig_term(const AdjView& V, int n, int ob, int t, int r, int c) {
+  SigGeom G = sig_geom(n, V.k, V.ntau);
+  int d = V.d, k = V.k, ntau = V.ntau, nb = n - k;
+  double h = V.h;
+  const cplx* rL = V.scr(V.lay.rhoL);
+  const cplx* rT = V.scr(V.lay.rhoT);
+  const cplx* rR = V.scr(V.lay.rhoR);
+  if (ob < G.nR) {
+    int j = ob;
+    if (t < nb) {
+      int m = t;
+      if (m > j) return mk(0, 0);
+      const cplx* g = rR + (size_t)m * V.dd;
+      const cplx* R = V.GR(j, m);
+      cplx u = dotq(d, [&](int q) { return g[r * d + q]; }, [&](int q) { return conj(R[c * d + q]); });
+      return mul_i((h * adj_w(V.W, n - m, j - m)) * u);
+    }
+    t -= nb;
+    if (t <= ntau) {
+      const cplx* g = rT + (size_t)t * V.dd;
+      const cplx* T = V.GT(j, t);
+      cplx u = dotq(d, [&](int q) { return g[r * d + q]; }, [&](int q) { return conj(T[c * d + q]); });
+      return mul_i((h * adj_w(V.W, n, j)) * u);
+    }
+    int m = t - (ntau + 1);
+    const cplx* g = rL + (size_t)m * V.dd;
+    cplx u = dotq(d, [&](int q) { return conj(g[q * d + r]); },
+                  [&](int q) { return V.Lh(V.P.Gles, m, j, q, c); });
+    return mul_i((h * adj_w(V.W, n, j)) * u);
+  }
+  if (ob < G.nR + G.nL) {
+    int j = ob - G.nR, m = t;
+    const cplx* g = rL + (size_t)m * V.dd;
+    double wt;
+    if (m > k) {
+      if (j > m) return mk(0, 0);
+      wt = adj_w(V.W, m, j);
+    } else {
+      if (j > k) return mk(0, 0);
+      wt = V.W.s[m][j];
+    }
+    // h w Rt(G, m, j)^H (-i rhoL_m)
+    cplx u = dotq(d, [&](int q) { return conj(V.Rt(V.P.Gret, m, j, q, r)); }, [&](int q) { return g[q * d + c]; });
+    return mul_i(-(h * wt) * u);
+  }
+  int tau = ob - G.nR - G.nL, m = t, j = ntau - tau;
+  const cplx* g = rL + (size_t)m * V.dd;
+  const cplx* T = V.GT(m, j);
+  cplx u = dotq(d, [&](int q) { return conj(g[q * d + r]); }, [&](int q) { return T[q * d + c]; });
+  return (-V.xi * V.ht * adj_w(V.W, ntau, j)) * u;
+}
+__host__ __device__ inline cplx* sig_out(const AdjView& V, int n, int ob) {
+  SigGeom G = sig_geom(n, V.k, V.ntau);
+  if (ob < G.nR) return V.sR(n, ob);
+  if (ob < G.nR + G.nL) return V.sL(ob - G.nR, n);
+  return V.sT(n, ob - G.nR - G.nL);
+}
+
+// ============================================================== Ktau
+// Reverse of the tau source C^rceil_2 + C^rceil_3 [Sigma, 1, G](p, m) of
+// row p (Eqs. ctv2, ctv3) for the column adjoints gc_m = i * src_m:
+//   sT(p, a) += sum coef gc_m M_b^H,   aM(b) += sum coef Sigma^rceil_{p,a}^H gc_m
+// over the terms (m, a, b, coef) of the forward rule. Outputs: ntau+1 blocks
+// of sT (if formed) then ntau+1 blocks of aM.
+__host__ __device__ inline void adj_tau_elem(const AdjProb& Ap, const KW& W, int p, const cplx* src,
+                                             size_t idx) {
+  AdjView V(Ap, W);
+  int d = V.d, dd = V.dd, k = V.k, nt = V.ntau;
+  double ht = V.ht, xi = V.xi;
+  bool sig = Ap.sT != nullptr;
+  size_t nout = (size_t)(sig ? 2 : 1) * (nt + 1) * dd;
+  if (idx >= nout) return;
+  int e = (int)(idx % dd), r = e / d, c = e % d;
+  int ob = (int)(idx / dd);
+  bool isM = !sig || ob > nt;
+  int x = isM ? (sig ? ob - nt - 1 : ob) : ob;
+  // gc_m = i src_m
+  auto gc = [&](int m, int rr, int cc) { return mul_i(src[(size_t)m * dd + rr * d + cc]); };
+  cplx v = mk(0, 0);
+  if (!isM) {
+    int a = x;
+    // term contribution coef * gc_m M_b^H
+    auto add = [&](int m, int b, double coef) {
+      const cplx* M = V.GM(b);
+      cplx u = dotq(d, [&](int q) { return gc(m, r, q); }, [&](int q) { return conj(M[c * d + q]); });
+      v = v + coef * u;
+    };
+    if (a <= k)
+      for (int m = 0; m <= k; m++)
+        for (int j = 0; j <= k; j++) add(m, nt - j, ht * xi * W.R[m][j][a]);
+    for (int m = (a > k + 1 ? a : k + 1); m <= nt; m++) add(m, nt - m + a, ht * xi * adj_w(W, m, m - a));
+    if (a >= nt - k)
+      for (int m = nt - k; m <= nt; m++)
+        for (int j = 0; j <= k; j++) add(m, j, ht * W.R[nt - m][j][nt - a]);
+    for (int m = 0; m <= (a < nt - k - 1 ? a : nt - k - 1); m++) add(m, a - m, ht * adj_w(W, nt - m, a - m));
+    V.sT(p, a)[e] = V.sT(p, a)[e] + v;
+  } else {
+    int b = x;
+    // term contribution coef * Sigma^rceil_{p,a}^H gc_m
+    auto add = [&](int m, int a, double coef) {
+      const cplx* S = V.ST(p, a);
+      cplx u = dotq(d, [&](int q) { return conj(S[q * d + r]); }, [&](int q) { return gc(m, q, c); });
+      v = v + coef * u;
+    };
+    if (b >= nt - k)
+      for (int m = 0; m <= k; m++)
+        for (int l = 0; l <= k; l++) add(m, l, ht * xi * W.R[m][nt - b][l]);
+    for (int m = (nt - b > k + 1 ? nt - b : k + 1); m <= nt; m++) add(m, m - nt + b, ht * xi * adj_w(W, m, nt - b));
+    if (b <= k)
+      for (int m = nt - k; m <= nt; m++)
+        for (int l = 0; l <= k; l++) add(m, nt - l, ht * W.R[nt - m][b][l]);
+    for (int m = 0; m <= (nt - b < nt - k - 1 ? nt - b : nt - k - 1); m++) add(m, m + b, ht * adj_w(W, nt - m, b));
+    V.aM(b)[e] = V.aM(b)[e] + v;
+  }
+}
+
+// ============================================================== K3
+// Retarded boundary of slice n (conjugate start-up, Eq. MBCVSAMx_cc_start)
+// and the eps_n / Sigma^R_{n,n} adjoints from the summed M_Rbar partials.
+//   Y C = -Y_0 C_0  with Y_l = R_{n,n-l},  C(l,p) = h^-1 D_{p,l} + delta_{pl} i e_{n-p}
+//                                                 + i h s_{p,l} Sigma~^R_{n-l,n-p}
+//   Psi = Ybar C^{-H}: C Psi^H = Ybar^H ;  Cbar(l,p) = -Y_l^H Psi_p
+__host__ __device__ inline int adj_rb_lds(int d, int k) { return k * d * k * d + 3 * k * d * d + d * d; }
+
+__host__ __device__ inline bool adj_rbound_team(const AdjProb& Ap, const KW& W, int n, int nparts, int tid,
+                                                int nth, cplx* lds, int* piv) {
+  AdjView V(Ap, W);
+  int d = V.d, dd = V.dd, k = V.k, kd = k * d;
+  double h = V.h;
+  cplx* Cb = lds;
+  cplx* X = Cb + kd * kd;  // kd x d: Psi^H blocks
+  cplx* gm = X + kd * d;   // d x d
+  bool ok = true;
+  // M_Rbar
+  const cplx* part = V.scr(V.lay.part);
+  for (int e = tid; e < dd; e += nth) {
+    cplx s = mk(0, 0);
+    for (int w = 0; w < nparts; w++) s = s + part[(size_t)w * dd + e];
+    gm[e] = s;
+  }
+  ADJ_SYNC();
+  for (int e = tid; e < dd; e += nth) {
+    // eps_n += -i M_Rbar ; Sigma^R_{n,n} += -i h w_{n,n} M_Rbar
+    V.ge(n)[e] = V.ge(n)[e] + mul_i(-1.0 * gm[e]);
+    if (V.A.sR) V.sR(n, n)[e] = V.sR(n, n)[e] + mul_i(-(h * adj_w(W, n, n)) * gm[e]);
+  }
+  for (int e = tid; e < kd * kd; e += nth) {
+    int R = e / kd, C = e % kd;
+    int l = 1 + R / d, p = 1 + C / d, r = R % d, c = C % d;
+    cplx v = mul_i((h * W.s[p][l]) * V.Rt(V.P.Sret, n - l, n - p, r, c));
+    if (r == c) v.x += W.D[p][l] / h;
+    if (p == l) v = v + mul_i(V.eh(n - p, r, c));
+    Cb[e] = v;
+  }
+  ADJ_SYNC();
+  ok = team_inverse(kd, Cb, piv, tid, nth) && ok;
+  // X = C^{-1} Ybar^H, Ybar^H block l = aR(n, n-l)^H
+  for (int e = tid; e < kd * d; e += nth) {
+    int R = e / d, c = e % d;
+    cplx s = mk(0, 0);
+    for (int q = 0; q < kd; q++) {
+      int l = 1 + q / d, qq = q % d;
+      cfma(s, Cb[R * kd + q], conj(V.aR(n, n - l)[c * d + qq]));
+    }
+    X[e] = s;
+  }
+  ADJ_SYNC();
+  // Psi_p[r][c] = conj(X[(p-1)d + c][r])
+  auto Psi = [&](int p, int rr, int cc) { return conj(X[((p - 1) * d + cc) * d + rr]); };
+  auto Y = [&](int l, int rr, int cc) -> cplx {
+    if (l == 0) return rr == cc ? mk(0, -1) : mk(0, 0);
+    return V.GR(n, n - l)[rr * d + cc];
+  };
+  for (int e = tid; e < kd * d; e += nth) {
+    int p = 1 + e / dd, r = (e % dd) / d, c = e % d;
+    // eps_{n-p} += i Y_p^H Psi_p
+    cplx u = dotq(d, [&](int q) { return conj(Y(p, q, r)); }, [&](int q) { return Psi(p, q, c); });
+    V.ge(n - p)[r * d + c] = V.ge(n - p)[r * d + c] + mul_i(u);
+  }
+  ADJ_SYNC();
+  if (V.A.sR) {
+    // targets (n-l, n-p), 0 <= l <= p <= k, p >= 1:
+    //   V(l,p) = i h s_{p,l} Y_l^H Psi_p  and, for 1 <= l < p, -V(p,l)^H = i h s_{l,p} Psi_l^H Y_p
+    int nb = k * (k + 3) / 2;  // pairs with p >= 1, 0 <= l <= p
+    for (int e = tid; e < nb * dd; e += nth) {
+      int t = e / dd, r = (e % dd) / d, c = e % d;
+      int p = 1;
+      while (t >= p + 1) {
+        t -= p + 1;
+        p++;
+      }
+      int l = t;
+      cplx u = dotq(d, [&](int q) { return conj(Y(l, q, r)); }, [&](int q) { return Psi(p, q, c); });
+      cplx v = mul_i((h * W.s[p][l]) * u);
+      if (l >= 1 && l < p) {
+        cplx u2 = dotq(d, [&](int q) { return conj(Psi(l, q, r)); }, [&](int q) { return Y(p, q, c); });
+        v = v + mul_i((h * W.s[l][p]) * u2);
+      }
+      V.sR(n - l, n - p)[r * d + c] = V.sR(n - l, n - p)[r * d + c] + v;
+    }
+  }
+  ADJ_SYNC();
+  return ok;
+}
+
+// ============================================================== start-up, mixing
+// B = [start_block(p, l)]_{p,l=1..k} is shared by every tau index; psi(m) =
+// B^{-H} [Tbar_{p,m}]_p. tstart_inv inverts B into scratch.
+__host__ __device__ inline bool adj_tinv_team(const AdjProb& Ap, const KW& W, int tid, int nth, cplx* lds,
+                                              int* piv) {
+  AdjView V(Ap, W);
+  int d = V.d, k = V.k, kd = k * d;
+  for (int e = tid; e < kd * kd; e += nth) {
+    int R = e / kd, C = e % kd;
+    lds[e] = start_block_elem(V, 1 + R / d, 1 + C / d, R % d, C % d);
+  }
+  ADJ_SYNC();
+  bool ok = team_inverse(kd, lds, piv, tid, nth);
+  for (int e = tid; e < kd * kd; e += nth) V.scr(V.lay.binv)[e] = lds[e];
+  ADJ_SYNC();
+  return ok;
+}
+// psi_p(m)[r][c] = sum_q conj(Binv[q][(p-1)d + r]) lambda(m)[q][c]; stored at psi + ((p-1)(ntau+1) + m) dd
+__host__ __device__ inline void adj_tpsi_elem(const AdjProb& Ap, const KW& W, size_t idx) {
+  AdjView V(Ap, W);
+  int d = V.d, dd = V.dd, k = V.k, kd = k * d, nt1 = V.ntau + 1;
+  if (idx >= (size_t)k * nt1 * dd) return;
+  int e = (int)(idx % dd), r = e / d, c = e % d;
+  int t = (int)(idx / dd), p = 1 + t / nt1, m = t % nt1;
+  const cplx* Bi = V.scr(V.lay.binv);
+  cplx s = mk(0, 0);
+  for (int q = 0; q < kd; q++) cfma(s, conj(Bi[q * kd + (p - 1) * d + r]), V.aT(1 + q / d, m)[(q % d) * d + c]);
+  V.scr(V.lay.psi)[((size_t)(p - 1) * nt1 + m) * dd + e] = s;
+}
+// y_0 = T_{0,m} = i xi M_{ntau-m}: gy0 = Tbar_{0,m} - sum_p B_{p,0}^H psi_p(m); aM(ntau-m) += -i xi gy0
+__host__ __device__ inline void adj_ty0_elem(const AdjProb& Ap, const KW& W, size_t idx) {
+  AdjView V(Ap, W);
+  int d = V.d, dd = V.dd, k = V.k, nt1 = V.ntau + 1;
+  if (idx >= (size_t)nt1 * dd) return;
+  int e = (int)(idx % dd), r = e / d, c = e % d, m = (int)(idx / dd);
+  cplx g = V.aT(0, m)[e];
+  for (int p = 1; p <= k; p++) {
+    const cplx* ps = V.scr(V.lay.psi) + ((size_t)(p - 1) * nt1 + m) * dd;
+    g = g - dotq(d, [&](int q) { return conj(start_block_elem(V, p, 0, q, r)); }, [&](int q) { return ps[q * d + c]; });
+  }
+  V.aM(V.ntau - m)[e] = V.aM(V.ntau - m)[e] + mul_i(-V.xi * g);
+}
+// P(p, l) = sum_m psi_p(m) T_{l,m}^H, p = 1..k, l = 0..k: reduction terms
+__host__ __device__ inline cplx adj_tp_term(const AdjView& V, int ob, int m, int r, int c) {
+  int d = V.d, k = V.k, nt1 = V.ntau + 1;
+  int p = 1 + ob / (k + 1), l = ob % (k + 1);
+  const cplx* ps = V.scr(V.lay.psi) + ((size_t)(p - 1) * nt1 + m) * V.dd;
+  const cplx* T = V.GT(l, m);
+  return dotq(d, [&](int q) { return ps[r * d + q]; }, [&](int q) { return conj(T[c * d + q]); });
+}
+
+// ============================================================== start-up, retarded
+// Finalises the mixing start-up sums (eps_p += i P(p,p); Sigma~^R_{p,l} +=
+// i h s_{p,l} P(p,l)) and reverses the retarded start-up columns m = k-1..0:
+//   A(p,l) = i h^-1 D_{p,l} - delta_{pl} e_p - h I_{m,p,l} Sigma~^R_{p,l},
+//   sum_l A(p,l) y_l = 0 (p = m+1..k), y_l = -[R_{m,l}]^dag (l < m), y_m = -i.
+__host__ __device__ inline int adj_rs_lds(int d, int k) { return k * d * k * d + 2 * k * d * d; }
+
+__host__ __device__ inline bool adj_rstart_team(const AdjProb& Ap, const KW& W, int tid, int nth, cplx* lds,
+                                                int* piv) {
+  AdjView V(Ap, W);
+  int d = V.d, dd = V.dd, k = V.k;
+  double h = V.h;
+  bool ok = true;
+  const cplx* P = V.scr(V.lay.pst);
+  auto Pb = [&](int p, int l) { return P + (size_t)((p - 1) * (k + 1) + l) * dd; };
+  for (int e = tid; e < k * dd; e += nth) {
+    int p = 1 + e / dd, ee = e % dd;
+    V.ge(p)[ee] = V.ge(p)[ee] + mul_i(Pb(p, p)[ee]);
+  }
+  if (V.A.sR) {
+    int nb = (k + 1) * (k + 2) / 2;
+    for (int e = tid; e < nb * dd; e += nth) {
+      int t = e / dd, r = (e % dd) / d, c = e % d;
+      int a = 0;
+      while ((a + 1) * (a + 2) / 2 <= t) a++;
+      int b = t - a * (a + 1) / 2;
+      cplx v = mk(0, 0);
+      if (a >= 1) v = v + mul_i((h * W.s[a][b]) * Pb(a, b)[r * d + c]);
+      if (b >= 1 && a > b) v = v + mul_i((h * W.s[b][a]) * conj(Pb(b, a)[c * d + r]));
+      V.sR(a, b)[r * d + c] = V.sR(a, b)[r * d + c] + v;
+    }
+  }
+  ADJ_SYNC();
+  cplx* A = lds;
+  cplx* lam = A + k * d * k * d;
+  cplx* psi = lam + k * d * d;
+  for (int m = k - 1; m >= 0; m--) {
+    int nu = k - m, N = nu * d;
+    auto yl = [&](int l, int rr, int cc) -> cplx {
+      if (l < m) return -conj(V.GR(m, l)[cc * d + rr]);
+      if (l == m) return rr == cc ? mk(0, -1) : mk(0, 0);
+      return V.GR(l, m)[rr * d + cc];
+    };
+    auto Ael = [&](int p, int l, int rr, int cc) -> cplx {
+      cplx v = (-(h * W.I[m][p][l])) * V.Rt(V.P.Sret, p, l, rr, cc);
+      if (rr == cc) v = v + mk(0, W.D[p][l] / h);
+      if (p == l) v = v - V.eh(p, rr, cc);
+      return v;
+    };
+    // A^H in LDS: (A^H)[(p'..)][(l'..)] = conj(A[l'][p'])
+    for (int e = tid; e < N * N; e += nth) {
+      int R = e / N, C = e % N;
+      A[e] = conj(Ael(m + 1 + C / d, m + 1 + R / d, C % d, R % d));
+    }
+    for (int e = tid; e < N * d; e += nth) {
+      int p = m + 1 + e / dd, ee = e % dd;
+      lam[e] = V.aR(p, m)[ee];
+    }
+    ADJ_SYNC();
+    ok = team_inverse(N, A, piv, tid, nth) && ok;
+    for (int e = tid; e < N * d; e += nth) {
+      int R = e / d, c = e % d;
+      cplx s = mk(0, 0);
+      for (int q = 0; q < N; q++) cfma(s, A[R * N + q], lam[q * d + c]);
+      psi[e] = s;
+    }
+    ADJ_SYNC();
+    auto ps = [&](int p, int rr, int cc) { return psi[(p - m - 1) * dd + rr * d + cc]; };
+    for (int e = tid; e < N * d; e += nth) {
+      int p = m + 1 + e / dd, r = (e % dd) / d, c = e % d;
+      // eps_p += psi_p y_p^H
+      cplx u = dotq(d, [&](int q) { return ps(p, r, q); }, [&](int q) { return conj(yl(p, c, q)); });
+      V.ge(p)[r * d + c] = V.ge(p)[r * d + c] + u;
+    }
+    // R_{m,l} (l < m) += sum_p psi_p^H A(p,l)
+    for (int e = tid; e < m * dd; e += nth) {
+      int l = e / dd, r = (e % dd) / d, c = e % d;
+      cplx s = mk(0, 0);
+      for (int p = m + 1; p <= k; p++)
+        s = s + dotq(d, [&](int q) { return conj(ps(p, q, r)); }, [&](int q) { return Ael(p, l, q, c); });
+      V.aR(m, l)[r * d + c] = V.aR(m, l)[r * d + c] + s;
+    }
+    if (V.A.sR) {
+      // Sigma~^R_{p,l} += h I_{m,p,l} psi_p y_l^H, stored targets (a, b), a >= b
+      int nb = (k + 1) * (k + 2) / 2;
+      for (int e = tid; e < nb * dd; e += nth) {
+        int t = e / dd, r = (e % dd) / d, c = e % d;
+        int a = 0;
+        while ((a + 1) * (a + 2) / 2 <= t) a++;
+        int b = t - a * (a + 1) / 2;
+        cplx v = mk(0, 0);
+        if (a > m) {
+          cplx u = dotq(d, [&](int q) { return ps(a, r, q); }, [&](int q) { return conj(yl(b, c, q)); });
+          v = v + (h * W.I[m][a][b]) * u;
+        }
+        if (b > m && a > b) {
+          // -(h I_{m,b,a} psi_b y_a^H)^H = -h I_{m,b,a} y_a psi_b^H
+          cplx u = dotq(d, [&](int q) { return yl(a, r, q); }, [&](int q) { return conj(ps(b, c, q)); });
+          v = v - (h * W.I[m][b][a]) * u;
+        }
+        V.sR(a, b)[r * d + c] = V.sR(a, b)[r * d + c] + v;
+      }
+    }
+    ADJ_SYNC();
+  }
+  return ok;
+}
+
+// ============================================================== device kernels
+constexpr int ADJ_LDS = 4000;  // complex entries of the team kernels' LDS (64000 B)
+
+__device__ inline void adj_fail(const AdjProb& A) { *A.stat = 1; }
+
+__global__ void __launch_bounds__(ADJ_NT) k_adj_lcol(const AdjProb* ap, int n) {
+  __shared__ cplx lds[ADJ_LDS];
+  __shared__ int piv[72];
+  const AdjProb& A = ap[blockIdx.y];
+  if (n > A.p.nt) return;
+  if (!adj_lcol_team(A, c_kw[A.p.k], n, threadIdx.x, blockDim.x, lds, piv) && threadIdx.x == 0) adj_fail(A);
+}
+__global__ void __launch_bounds__(ADJ_NT) k_adj_lcol_scatter(const AdjProb* ap, int n) {
+  const AdjProb& A = ap[blockIdx.y];
+  if (n > A.p.nt) return;
+  adj_lcol_elem(A, c_kw[A.p.k], n, (size_t)blockIdx.x * blockDim.x + threadIdx.x);
+}
+__global__ void __launch_bounds__(ADJ_NT) k_adj_rho(const AdjProb* ap, int n) {
+  __shared__ cplx rho[ADJ_NT];
+  const AdjProb& A = ap[blockIdx.y];
+  if (n > A.p.nt) return;
+  AdjView V(A, c_kw[A.p.k]);
+  int dd = V.dd, cb = V.lay.cb;
+  RhoGeom g = rho_geom(n, V.k, V.ntau, cb);
+  int w = blockIdx.x;
+  if (w >= g.wl + g.wt + g.wr) return;
+  int seg = w < g.wl ? 0 : (w < g.wl + g.wt ? 1 : 2);
+  int wb = seg == 0 ? w : (seg == 1 ? w - g.wl : w - g.wl - g.wt);
+  int cnt = seg == 0 ? g.SL : (seg == 1 ? g.ST : g.SR);
+  int b0 = wb * cb, nbk = cnt - b0 < cb ? cnt - b0 : cb;
+  cplx* dst = V.scr(seg == 0 ? V.lay.rhoL : (seg == 1 ? V.lay.rhoT : V.lay.rhoR));
+  int t = threadIdx.x;
+  if (t < nbk * dd) {
+    int b = b0 + t / dd, e = t % dd;
+    cplx v = rho_elem(V, n, seg, b, e / V.d, e % V.d);
+    rho[t] = v;
+    dst[(size_t)b * dd + e] = v;
+  }
+  __syncthreads();
+  if (t < dd) {
+    cplx s = mk(0, 0);
+    for (int bb = 0; bb < nbk; bb++) s = s + mr_term(V, n, seg, b0 + bb, rho + bb * dd, t / V.d, t % V.d);
+    V.scr(V.lay.part)[(size_t)w * dd + t] = s;
+  }
+}
+__global__ void __launch_bounds__(ADJ_NT) k_adj_hist(const AdjProb* ap, int n) {
+  const AdjProb& A = ap[blockIdx.y];
+  if (n > A.p.nt) return;
+  adj_hist_elem(A, c_kw[A.p.k], n, (size_t)blockIdx.x * blockDim.x + threadIdx.x);
+}
+// one output block per workgroup: dd element rows x (ADJ_NT / dd) term lanes
+template <class NT, class TERM, class OUT>
+__device__ inline void team_reduce_block(int dd, NT nterms, TERM term, OUT out) {
+  __shared__ cplx red[ADJ_NT];
+  int lanes = dd >= ADJ_NT ? 1 : ADJ_NT / dd;
+  int t = threadIdx.x, e = t % dd, lane = t / dd;
+  cplx s = mk(0, 0);
+  if (lane < lanes && t < lanes * dd) {
+    int nt = nterms();
+    for (int i = lane; i < nt; i += lanes) s = s + term(i, e);
+  }
+  red[t] = s;
+  __syncthreads();
+  if (t < dd) {
+    cplx acc = mk(0, 0);
+    for (int l = 0; l < lanes; l++) acc = acc + red[l * dd + t];
+    out(e, acc);
+  }
+}
+__global__ void __launch_bounds__(ADJ_NT) k_adj_sigma(const AdjProb* ap, int n) {
+  const AdjProb& A = ap[blockIdx.y];
+  if (n > A.p.nt) return;
+  AdjView V(A, c_kw[A.p.k]);
+  int ob = blockIdx.x;
+  if (ob >= sig_geom(n, V.k, V.ntau).total) return;
+  int d = V.d;
+  team_reduce_block(
+      V.dd, [&]() { return sig_nterms(V, n, ob); },
+      [&](int i, int e) { return sig_term(V, n, ob, i, e / d, e % d); },
+      [&](int e, cplx v) {
+        cplx* o = sig_out(V, n, ob);
+        o[e] = o[e] + v;
+      });
+}
+__global__ void __launch_bounds__(ADJ_NT) k_adj_tau(const AdjProb* ap, int p, int srcsel) {
+  const AdjProb& A = ap[blockIdx.y];
+  if (p > A.p.nt) return;
+  AdjView V(A, c_kw[A.p.k]);
+  const cplx* src = srcsel == 0 ? V.scr(V.lay.rhoT) : V.scr(V.lay.psi) + (size_t)(p - 1) * (V.ntau + 1) * V.dd;
+  adj_tau_elem(A, c_kw[A.p.k], p, src, (size_t)blockIdx.x * blockDim.x + threadIdx.x);
+}
+__global__ void __launch_bounds__(ADJ_NT) k_adj_rbound(const AdjProb* ap, int n) {
+  __shared__ cplx lds[ADJ_LDS];
+  __shared__ int piv[72];
+  const AdjProb& A = ap[blockIdx.y];
+  if (n > A.p.nt) return;
+  AdjView V(A, c_kw[A.p.k]);
+  RhoGeom g = rho_geom(n, V.k, V.ntau, V.lay.cb);
+  if (!adj_rbound_team(A, c_kw[A.p.k], n, g.wl + g.wt + g.wr, threadIdx.x, blockDim.x, lds, piv) &&
+      threadIdx.x == 0)
+    adj_fail(A);
+}
+__global__ void __launch_bounds__(ADJ_NT) k_adj_tinv(const AdjProb* ap) {
+  __shared__ cplx lds[ADJ_LDS];
+  __shared__ int piv[72];
+  const AdjProb& A = ap[blockIdx.y];
+  if (!adj_tinv_team(A, c_kw[A.p.k], threadIdx.x, blockDim.x, lds, piv) && threadIdx.x == 0) adj_fail(A);
+}
+__global__ void __launch_bounds__(ADJ_NT) k_adj_tpsi(const AdjProb* ap) {
+  const AdjProb& A = ap[blockIdx.y];
+  adj_tpsi_elem(A, c_kw[A.p.k], (size_t)blockIdx.x * blockDim.x + threadIdx.x);
+}
+__global__ void __launch_bounds__(ADJ_NT) k_adj_ty0(const AdjProb* ap) {
+  const AdjProb& A = ap[blockIdx.y];
+  adj_ty0_elem(A, c_kw[A.p.k], (size_t)blockIdx.x * blockDim.x + threadIdx.x);
+}
+__global__ void __launch_bounds__(ADJ_NT) k_adj_tp(const AdjProb* ap) {
+  const AdjProb& A = ap[blockIdx.y];
+  AdjView V(A, c_kw[A.p.k]);
+  int ob = blockIdx.x;
+  if (ob >= V.k * (V.k + 1)) return;
+  int d = V.d;
+  team_reduce_block(
+      V.dd, [&]() { return V.ntau + 1; }, [&](int i, int e) { return adj_tp_term(V, ob, i, e / d, e % d); },
+      [&](int e, cplx v) { V.scr(V.lay.pst)[(size_t)ob * V.dd + e] = v; });
+}
+__global__ void __launch_bounds__(ADJ_NT) k_adj_rstart(const AdjProb* ap) {
+  __shared__ cplx lds[ADJ_LDS];
+  __shared__ int piv[72];
+  const AdjProb& A = ap[blockIdx.y];
+  if (!adj_rstart_team(A, c_kw[A.p.k], threadIdx.x, blockDim.x, lds, piv) && threadIdx.x == 0) adj_fail(A);
+}
+
+// ============================================================== host sequencing
+// Launches the whole backward sweep for the problems in dA (host copies in hA,
+// which share d, k and ntau): slices ntmax .. k+1, then the start-up.
+inline unsigned adj_blocks(size_t elems) { return (unsigned)((elems + ADJ_NT - 1) / ADJ_NT); }
+
+hipError_t launch_adjoint_sweep(const AdjProb* dA, const AdjProb* hA, int count, hipStream_t s) {
+  int k = hA[0].p.k, d = hA[0].p.d, ntau = hA[0].p.ntau, dd = d * d, ntmax = 0;
+  bool sig = hA[0].sR != nullptr;
+  for (int i = 0; i < count; i++) ntmax = hA[i].p.nt > ntmax ? hA[i].p.nt : ntmax;
+  dim3 blk(ADJ_NT);
+  int cb = adj_cb(dd);
+  for (int n = ntmax; n > k; n--) {
+    LcolGeom lg = lcol_geom(n, k, ntau, dd, sig);
+    RhoGeom rg = rho_geom(n, k, ntau, cb);
+    HistGeom hg = hist_geom(n, k, ntau, dd);
+    hipLaunchKernelGGL(k_adj_lcol, dim3(1, count), blk, 0, s, dA, n);
+    hipLaunchKernelGGL(k_adj_lcol_scatter, dim3(adj_blocks(lg.total), count), blk, 0, s, dA, n);
+    hipLaunchKernelGGL(k_adj_rho, dim3(rg.wl + rg.wt + rg.wr, count), blk, 0, s, dA, n);
+    hipLaunchKernelGGL(k_adj_hist, dim3(adj_blocks(hg.total), count), blk, 0, s, dA, n);
+    if (sig) hipLaunchKernelGGL(k_adj_sigma, dim3(sig_geom(n, k, ntau).total, count), blk, 0, s, dA, n);
+    hipLaunchKernelGGL(k_adj_tau, dim3(adj_blocks((size_t)(sig ? 2 : 1) * (ntau + 1) * dd), count), blk, 0, s,
+                       dA, n, 0);
+    hipLaunchKernelGGL(k_adj_rbound, dim3(1, count), blk, 0, s, dA, n);
+  }
+  for (int n = k; n >= 0; n--) {
+    LcolGeom lg = lcol_geom(n, k, ntau, dd, sig);
+    hipLaunchKernelGGL(k_adj_lcol, dim3(1, count), blk, 0, s, dA, n);
+    hipLaunchKernelGGL(k_adj_lcol_scatter, dim3(adj_blocks(lg.total), count), blk, 0, s, dA, n);
+  }
+  hipLaunchKernelGGL(k_adj_tinv, dim3(1, count), blk, 0, s, dA);
+  hipLaunchKernelGGL(k_adj_tpsi, dim3(adj_blocks((size_t)k * (ntau + 1) * dd), count), blk, 0, s, dA);
+  hipLaunchKernelGGL(k_adj_ty0, dim3(adj_blocks((size_t)(ntau + 1) * dd), count), blk, 0, s, dA);
+  hipLaunchKernelGGL(k_adj_tp, dim3(k * (k + 1), count), blk, 0, s, dA);
+  for (int p = 1; p <= k; p++)
+    hipLaunchKernelGGL(k_adj_tau, dim3(adj_blocks((size_t)(sig ? 2 : 1) * (ntau + 1) * dd), count), blk, 0, s,
+                       dA, p, 1);
+  hipLaunchKernelGGL(k_adj_rstart, dim3(1, count), blk, 0, s, dA);
+  return hipGetLastError();
+}
+
+}  // namespace cntr

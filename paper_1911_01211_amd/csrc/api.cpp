@@ -551,6 +551,57 @@ cntr_status cntr_observables(int32_t tstp, int32_t count, const cntr_grid* grids
   return CNTR_OK;
 }
 
+cntr_status cntr_adjoint_sweep(int32_t count, const cntr_grid* grids, const cntr_gf* G, const cntr_gf* Sigma,
+                               const void* const* eps, const cntr_gf* Gbar, const cntr_gf* Sigmabar,
+                               void* const* eps_bar, void* stream) {
+  cntr_status st = check_batch(count, grids, "cntr_adjoint_sweep");
+  if (st) return st;
+  if (!gf_ok(G, count) || !gf_ok(Sigma, count) || !gf_ok(Gbar, count) || !eps || !eps_bar)
+    return fail(CNTR_ESHAPE, "cntr_adjoint_sweep: null pointer");
+  for (int i = 0; i < count; i++) {
+    if (!eps[i] || !eps_bar[i]) return fail(CNTR_ESHAPE, "cntr_adjoint_sweep: null eps or eps_bar");
+    if (Sigmabar && (!Sigmabar[i].ret || !Sigmabar[i].les || !Sigmabar[i].tv))
+      return fail(CNTR_ESHAPE, "cntr_adjoint_sweep: Sigmabar needs ret, les and tv");
+  }
+  if ((st = ensure_weights())) return st;
+  hipStream_t s = (hipStream_t)stream;
+  StreamScratch* sc = scratch_for(s);
+  int ntmax = 0;
+  for (int i = 0; i < count; i++) ntmax = grids[i].nt > ntmax ? grids[i].nt : ntmax;
+  AdjLayout lay = adj_layout(ntmax, grids[0].ntau, grids[0].d, grids[0].k);
+  size_t per = round256(lay.total * sizeof(cplx));
+  size_t head = round256(count * sizeof(int)) + round256(count * sizeof(AdjProb));
+  if ((st = grow(s, sc, head + per * count, 5, 2))) return st;
+  int* dstat = (int*)sc->buf;
+  AdjProb* dA = (AdjProb*)(sc->buf + round256(count * sizeof(int)));
+  std::vector<AdjProb> hA(count);
+  for (int i = 0; i < count; i++) {
+    AdjProb& a = hA[i];
+    a.p = make_prob(grids[i], &G[i], &Sigma[i], eps[i]);
+    a.aR = (cplx*)Gbar[i].ret;
+    a.aL = (cplx*)Gbar[i].les;
+    a.aT = (cplx*)Gbar[i].tv;
+    a.aM = (cplx*)Gbar[i].mat;
+    a.sR = Sigmabar ? (cplx*)Sigmabar[i].ret : nullptr;
+    a.sL = Sigmabar ? (cplx*)Sigmabar[i].les : nullptr;
+    a.sT = Sigmabar ? (cplx*)Sigmabar[i].tv : nullptr;
+    a.ge = (cplx*)eps_bar[i];
+    // every problem's scratch is laid out for its own nt (offsets depend on nt)
+    a.scr = (cplx*)(sc->buf + head + per * i);
+    a.stat = dstat + i;
+  }
+  hipError_t e = hipMemsetAsync(dstat, 0, count * sizeof(int), s);
+  if (e == hipSuccess) e = hipMemcpyAsync(dA, hA.data(), count * sizeof(AdjProb), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = launch_adjoint_sweep(dA, hA.data(), count, s);
+  std::vector<int> hs(count, 0);
+  if (e == hipSuccess) e = hipMemcpyAsync(hs.data(), dstat, count * sizeof(int), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "cntr_adjoint_sweep");
+  for (int i = 0; i < count; i++)
+    if (hs[i]) return fail(CNTR_ESINGULAR, "cntr_adjoint_sweep: singular local matrix in problem " + std::to_string(i));
+  return CNTR_OK;
+}
+
 cntr_status cntr_extrapolate(int32_t tstp, int32_t count, const cntr_grid* grids, const cntr_gf* G,
                              void* stream) {
   cntr_status st = check_batch(count, grids, "cntr_extrapolate");

@@ -4,4 +4,5 @@
 #include "step.hip"
 #include "misc.hip"
 #include "mats.hip"
+#include "adjoint.hip"
 #include "api.cpp"
