@@ -92,7 +92,42 @@ def run_gpu(args):
     # physical sanity of the last run: half filling on every site at t_nt
     L = G.les[-1].cpu().numpy()
     dens_dev = float(abs((L.diagonal().imag) - 0.5).max())
-    return g, elapsed, prof, stats, dens_dev
+    state = dict(G=G, S=S, emf=emf, e0=e0np, U=U)
+    return g, elapsed, prof, stats, dens_dev, state
+
+
+def run_adjoint(g, state, args):
+    """Adjoint sample: gradient of the kinetic energy at the last time,
+    J = 2 Re Tr[eps_kin rho(t_nt)] with rho = -i G^<(t_nt, t_nt) (both spins),
+    with respect to every eps0_n and U_n of the 2B chain run just timed
+    (second-Born mode of cntr_adjoint_sweep on its converged solution,
+    `niter` fixed-point iterations per slice)."""
+    import numpy as np
+    import torch
+
+    from paper_1911_01211_amd import contour as K
+
+    dev = "cuda:0"
+    G, S, emf, U = state["G"], state["S"], state["emf"], state["U"]
+    d, nt = g.d, g.nt
+    ekin = state["e0"][nt + 1] * (1 - np.eye(d))  # hopping part of eps0(t_nt)
+    Gb, Sb = K.Contour(g, dev), K.Contour(g, dev)
+    eb = torch.zeros_like(emf)
+    ub = torch.zeros_like(U)
+    # J = Re(-2i sum_ab eps_ba L_ab)  ->  dJ/dL_ab = conj(-2i eps_ba)
+    Gb.les[-1] = torch.as_tensor(np.conj(-2j * ekin.T)).to(dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    conv = K.adjoint_sweep([G], [S], [emf], [Gb], [eb], [Sb], U=[U], U_bar=[ub], niter=args.adj_niter)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ubh = ub.cpu().numpy()
+    return {"workload": "gradient of the kinetic energy at t_nt w.r.t. eps0_n and U_n (n = 0..nt) of the "
+                        "same 2B chain solution (second-Born adjoint sweep, Matsubara held fixed)",
+            "value": (nt - g.k) / el, "unit": "adjoint time-steps/s", "seconds": el,
+            "fixed_point_iterations": args.adj_niter, "fixed_point_last_change": conv,
+            "forward_equivalent": "one forward time step = 5 corrector iterations",
+            "dJ_dU_sum": float(ubh.sum())}
 
 
 def run_kpoints(args):
@@ -226,6 +261,8 @@ def main():
     ap.add_argument("--nk", type=int, default=512, help="k-points of the batched sample")
     ap.add_argument("--kp-steps", type=int, default=300, help="last slice of the batched sample")
     ap.add_argument("--no-kpoints", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--adj-niter", type=int, default=16, help="adjoint fixed-point iterations per slice")
     ap.add_argument("--profile-step", type=int, default=0,
                     help="only run the time step at this slice (counter runs), then a 1 GiB copy")
     args = ap.parse_args()
@@ -236,7 +273,7 @@ def main():
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(the per-GPU share of a sharded run is the single-GPU workload).", file=sys.stderr)
         sys.exit(2)
-    g, elapsed, prof, stats, dens_dev = run_gpu(args)
+    g, elapsed, prof, stats, dens_dev, state = run_gpu(args)
     nsteps = (g.nt - g.k) * args.steps
     value = nsteps / elapsed
     hist_gbs = prof["hist_bytes"] / (prof["hist_ms"] * 1e-3) / 1e9 if prof["hist_ms"] > 0 else None
@@ -270,6 +307,9 @@ def main():
                      "avg_launch_us": prof["hist_ms"] * 1e3 / max(1, prof["hist_launches"])},
         "check": {"max_density_deviation_at_nt": dens_dev},
     }
+    if not args.no_adjoint:
+        out["adjoint"] = run_adjoint(g, state, args)
+    del state
     if not args.no_kpoints:
         out["batched"] = run_kpoints(args)
     if not args.no_cpu_baseline:

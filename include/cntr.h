@@ -200,32 +200,50 @@ cntr_status cntr_solve_2b(const cntr_grid* grid, const cntr_gf* G, const cntr_gf
                           int32_t nt_stop, double* stats, void* stream);
 
 /* ----------------------------------------------------------------- A12 --
- * Discrete adjoint (reverse mode) of the Dyson solution for a given
- * self-energy: the start-up of slices 0..k and the data-parallel time steps
- * k+1..nt, exactly as cntr_dyson_step computes them (Sec. "Dyson equation:
- * start-up" and "Time stepping"; the adjoint itself is not in the paper).
- * With the Matsubara component M and Sigma held fixed, G(eps, Sigma, M) is the
- * solution of slices 0..nt; for a real objective J(G) the call returns
- *   dJ/d eps_n   (n = 0..nt),   dJ/d Sigma (slices 0..nt),   dJ/d M.
- * Convention: for a complex entry z = x + i y the gradient is
- * dJ/dx + i dJ/dy, so dJ = Re sum conj(grad) dz.
- *   G        : the converged solution (slices -1..nt) of the same grid, eps and
- *              Sigma (as written by cntr_dyson_step).
+ * Discrete adjoint (reverse mode) of the Dyson solution: the start-up of
+ * slices 0..k and the data-parallel time steps k+1..nt, exactly as
+ * cntr_dyson_step computes them (Sec. "Dyson equation: start-up" and "Time
+ * stepping"; the adjoint itself is not in the paper). The Matsubara
+ * component M is held fixed; for a real objective J(G) the call returns the
+ * gradients of J, with the convention dJ/dx + i dJ/dy for a complex entry
+ * z = x + i y (so dJ = Re sum conj(grad) dz).
+ *
+ * Given self-energy (U == NULL): G(eps, Sigma, M) solves slices 0..nt;
+ *   eps_bar += dJ/deps_n, Sigmabar += dJ/dSigma (if not NULL), Gbar.mat += dJ/dM.
+ * Second-Born mode (U != NULL): Sigma = Sigma_2B[G; U] (as cntr_sigma_2b) and
+ *   eps = eps0 + Hartree[G; U, nbar] on every slice 0..nt; G, Sigma and eps
+ *   are the converged self-consistent solution (cntr_solve_2b; eps is its
+ *   eps_mf). Each slice's adjoint is the fixed point of the reverse step
+ *   composed with the adjoints of Sigma_2B and Hartree, iterated `niter`
+ *   times per slice (the start-up block of slices 0..k together);
+ *   eps_bar += dJ/deps0_n (n = 0..nt), U_bar += dJ/dU_n for n = 0..nt and
+ *   the part of dJ/dU_{-1} that enters through Sigma^rceil (the Matsubara
+ *   part enters through M: Gbar.mat returns dJ/dM). Sigmabar is required
+ *   (work space; returns the total dJ/dSigma), U_bar is required.
+ *
+ *   G        : the converged solution (slices -1..nt) of the same grid.
+ *   Sigma    : the self-energy the solution was computed with.
+ *   eps      : the levels of the solution (eps_mf in the second-Born mode).
+ *   U, nbar  : per problem DEVICE array of nt+2 doubles (as cntr_sigma_2b),
+ *              and the Hartree shift, or U = NULL.
  *   Gbar     : in: dJ/dG of the objective's explicit dependence on slices
- *              0..nt (ret, les, tv) and on M (mat); out: mat += the
- *              contributions of every slice, i.e. the total dJ/dM; ret, les
- *              and tv are consumed as work space (their values on return are
- *              the intermediate adjoints of the sweep).
- *   Sigmabar : NULL, or accumulators (+=) for dJ/dSigma of slices 0..nt
- *              (ret, les, tv; mat is not touched).
- *   eps_bar  : accumulators (+=) of (nt+2) blocks, entry n+1 for eps_n
- *              (entry 0, eps_{-1}, is not touched: it enters only M).
+ *              0..nt (ret, les, tv) and on M (mat); out: mat += every
+ *              slice's contribution (the total dJ/dM); ret, les and tv are
+ *              consumed as work space (on return: intermediate adjoints).
+ *   Sigmabar : accumulators (+=) of dJ/dSigma, slices 0..nt (mat untouched).
+ *   eps_bar  : accumulators (+=) of (nt+2) blocks, entry n+1 for time n
+ *              (entry 0 is not touched).
+ *   U_bar    : per problem DEVICE array of nt+2 doubles (+=), index n+1.
+ *   niter    : fixed-point iterations per slice (<= 0: 16).
+ *   conv     : HOST double or NULL: largest relative change of a slice
+ *              adjoint in its last iteration (second-Born mode).
  * Instances may have different nt (each is swept from its own nt). Every
- * pointer is a DEVICE pointer, owned by the caller. Synchronizes `stream`;
- * CNTR_ESINGULAR if a local step or start-up matrix is singular. */
+ * pointer except conv is a DEVICE pointer, owned by the caller. Synchronizes
+ * `stream`; CNTR_ESINGULAR if a local step or start-up matrix is singular. */
 cntr_status cntr_adjoint_sweep(int32_t count, const cntr_grid* grids, const cntr_gf* G, const cntr_gf* Sigma,
-                               const void* const* eps, const cntr_gf* Gbar, const cntr_gf* Sigmabar,
-                               void* const* eps_bar, void* stream);
+                               const void* const* eps, const double* const* U, double nbar,
+                               const cntr_gf* Gbar, const cntr_gf* Sigmabar, void* const* eps_bar,
+                               double* const* U_bar, int32_t niter, double* conv, void* stream);
 
 /* ------------------------------------------------------------ profiling --
  * Device-time accounting of the time step, measured with HIP events

@@ -63,7 +63,8 @@ def lib():
                                     i32, dbl, i32, i32, P(dbl), vp]
         L.cntr_observables.argtypes = [i32, i32, P(Grid), P(GF), P(GF), P(vp), P(vp), vp, vp, vp]
         L.cntr_sigma_local.argtypes = [i32, i32, P(Grid), P(GF), P(GF), dbl, vp]
-        L.cntr_adjoint_sweep.argtypes = [i32, P(Grid), P(GF), P(GF), P(vp), P(GF), P(GF), P(vp), vp]
+        L.cntr_adjoint_sweep.argtypes = [i32, P(Grid), P(GF), P(GF), P(vp), P(vp), dbl, P(GF), P(GF), P(vp),
+                                         P(vp), i32, P(dbl), vp]
         L.cntr_sync.argtypes = [vp]
         L.cntr_profile_begin.argtypes = []
         L.cntr_profile_end.argtypes = [P(Profile)]

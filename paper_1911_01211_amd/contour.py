@@ -185,14 +185,22 @@ def observables(tstp: int, G: list, Sigma: list, eps0: list, eps_mf=None, stream
 
 
 def adjoint_sweep(G: list, Sigma: list, eps: list, Gbar: list, eps_bar: list, Sigmabar: list | None = None,
-                  stream=None):
-    """Reverse-mode sweep of the Dyson solution for a given self-energy
-    (cntr_adjoint_sweep): Gbar holds dJ/dG on entry (consumed; Gbar.mat
-    returns dJ/dM), eps_bar (+=) receives dJ/deps_n, Sigmabar (+=, optional)
-    dJ/dSigma. Gradients are dJ/dRe + i dJ/dIm of every complex entry."""
+                  U: list | None = None, U_bar: list | None = None, nbar=0.5, niter=16, stream=None):
+    """Reverse-mode sweep of the Dyson solution (cntr_adjoint_sweep). Gbar
+    holds dJ/dG on entry (consumed; Gbar.mat returns dJ/dM), eps_bar (+=)
+    receives dJ/deps_n, Sigmabar (+=) dJ/dSigma. With U (second-Born mode:
+    G, Sigma, eps the converged solution with eps = eps_mf) eps_bar receives
+    dJ/deps0_n and U_bar (+=) dJ/dU_n. Returns the largest relative change of
+    a slice adjoint in its last fixed-point iteration (0 for a given Sigma).
+    Gradients are dJ/dRe + i dJ/dIm of every complex entry."""
     sb = None if Sigmabar is None else _gfs(Sigmabar)
-    _abi.check(_abi.lib().cntr_adjoint_sweep(len(G), _grids(G), _gfs(G), _gfs(Sigma), _ptrs(eps), _gfs(Gbar),
-                                             sb, _ptrs(eps_bar), _stream(stream)))
+    conv = C.c_double(0.0)
+    up = None if U is None else _ptrs(U)
+    ub = None if U_bar is None else _ptrs(U_bar)
+    _abi.check(_abi.lib().cntr_adjoint_sweep(len(G), _grids(G), _gfs(G), _gfs(Sigma), _ptrs(eps), up, float(nbar),
+                                             _gfs(Gbar), sb, _ptrs(eps_bar), ub, int(niter), C.byref(conv),
+                                             _stream(stream)))
+    return conv.value
 
 
 def extrapolate(tstp: int, G: list, stream=None):

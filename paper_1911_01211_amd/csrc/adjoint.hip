@@ -31,8 +31,17 @@ namespace cntr {
 #define ADJ_SYNC() ((void)0)
 #endif
 
+// Slices lo..hi of a contour function held contiguously: the R rows, the
+// L columns and the T rows of those slices; (oR, oL, oT) are the block
+// offsets of slice lo's first block in the full arrays.
+struct AdjWin {
+  cplx *R, *L, *T;
+  size_t oR, oL, oT;
+};
+
 // One problem of an adjoint sweep. Pointers are device pointers in the
-// canonical layout; the adjoint arrays have the shape of the quantity.
+// canonical layout; the adjoint arrays have the shape of the quantity, or
+// are windows of it whose first block sits at the given block origin.
 struct AdjProb {
   Prob p;                    // G (forward solution), Sigma, eps, grid
   cplx *aR, *aL, *aT, *aM;   // adjoint of G: seed in, dJ/dM out in aM
@@ -40,6 +49,15 @@ struct AdjProb {
   cplx *ge;                  // dJ/deps_n at index n+1 (accumulated)
   cplx* scr;                 // scratch of this problem
   int* stat;                 // set to 1 by a kernel that meets a singular local matrix
+  size_t aoR, aoL, aoT;      // block origins of aR, aL, aT (0: whole arrays)
+  size_t soR, soL, soT;      // block origins of sR, sL, sT
+  // second-Born mode (Sigma = Sigma_2B[G], eps = eps0 + Hartree[G])
+  const double* U;           // (nt+2), index n+1
+  double nbar;
+  double* ub;                // dJ/dU (accumulated), (nt+2)
+  AdjWin g0, s0, nu[2], gdry, sdry;
+  cplx *e0, *gedry, *mdummy;
+  double* conv;              // per slice: max |change| and max |value| of the last iterate
 };
 
 constexpr int ADJ_NT = 256;  // threads per workgroup of every adjoint kernel
@@ -103,13 +121,17 @@ struct AdjView {
   __host__ __device__ const cplx* SR(int a, int b) const { return P.Sret + oR(a, b) * dd; }
   __host__ __device__ const cplx* SL(int a, int b) const { return P.Sles + oL(a, b) * dd; }
   __host__ __device__ const cplx* ST(int n, int m) const { return P.Stv + oT(n, m, ntau) * dd; }
-  __host__ __device__ cplx* aR(int a, int b) const { return A.aR + oR(a, b) * dd; }
-  __host__ __device__ cplx* aL(int a, int b) const { return A.aL + oL(a, b) * dd; }
-  __host__ __device__ cplx* aT(int n, int m) const { return A.aT + oT(n, m, ntau) * dd; }
+  __host__ __device__ cplx* aR(int a, int b) const { return A.aR + (oR(a, b) - A.aoR) * dd; }
+  __host__ __device__ cplx* aL(int a, int b) const { return A.aL + (oL(a, b) - A.aoL) * dd; }
+  __host__ __device__ cplx* aT(int n, int m) const { return A.aT + (oT(n, m, ntau) - A.aoT) * dd; }
   __host__ __device__ cplx* aM(int m) const { return A.aM + (size_t)m * dd; }
-  __host__ __device__ cplx* sR(int a, int b) const { return A.sR + oR(a, b) * dd; }
-  __host__ __device__ cplx* sL(int a, int b) const { return A.sL + oL(a, b) * dd; }
-  __host__ __device__ cplx* sT(int n, int m) const { return A.sT + oT(n, m, ntau) * dd; }
+  __host__ __device__ cplx* sR(int a, int b) const { return A.sR + (oR(a, b) - A.soR) * dd; }
+  __host__ __device__ cplx* sL(int a, int b) const { return A.sL + (oL(a, b) - A.soL) * dd; }
+  __host__ __device__ cplx* sT(int n, int m) const { return A.sT + (oT(n, m, ntau) - A.soT) * dd; }
+  // windows
+  __host__ __device__ cplx* wR(const AdjWin& w, int a, int b) const { return w.R + (oR(a, b) - w.oR) * dd; }
+  __host__ __device__ cplx* wL(const AdjWin& w, int a, int b) const { return w.L + (oL(a, b) - w.oL) * dd; }
+  __host__ __device__ cplx* wT(const AdjWin& w, int n, int m) const { return w.T + (oT(n, m, ntau) - w.oT) * dd; }
   __host__ __device__ cplx* ge(int n) const { return A.ge + (size_t)(n + 1) * dd; }
   __host__ __device__ cplx* scr(size_t off) const { return A.scr + off; }
   // extended elements
@@ -1066,6 +1088,216 @@ __host__ __device__ inline bool adj_rstart_team(const AdjProb& Ap, const KW& W, 
   return ok;
 }
 
+// ============================================================== second-Born chain
+// With Sigma = Sigma_2B[G] (elementwise in the orbital indices, per slice)
+// and eps = eps0 + Hartree[G], slice s of G is a fixed point of the step that
+// produces it. Its adjoint nu_s solves
+//   nu_s = gbar_s + Sigma_2B'(G_s)^* (sbar_s + S_s(nu_s)) + Hartree'(G_s)^* (ebar_s + E_s(nu_s)),
+// where gbar_s, sbar_s, ebar_s collect the later slices' contributions and
+// S_s, E_s are the Sigma / eps adjoints that the reverse step of slice s
+// itself returns for the input nu_s. The sweep iterates this map per slice
+// (per start-up block of slices 0..k) on windows, then applies the reverse
+// step once more, for good, with the final nu.
+
+// element counts of slices lo..hi (R row, L column, T row per slice)
+__host__ __device__ inline size_t win_elems(int lo, int hi, int ntau, int dd) {
+  return (2 * (tri(hi + 1) - tri(lo)) + (size_t)(hi - lo + 1) * (ntau + 1)) * dd;
+}
+// decode a window element index: slice s, component (0 R, 1 L, 2 T), block j, element e
+__host__ __device__ inline void win_decode(size_t idx, int lo, int hi, int ntau, int dd, int& s, int& comp,
+                                           int& j, int& e) {
+  s = lo;
+  size_t t = idx / dd;
+  e = (int)(idx % dd);
+  while (s < hi) {
+    size_t c = (size_t)2 * (s + 1) + ntau + 1;
+    if (t < c) break;
+    t -= c;
+    s++;
+  }
+  if (t < (size_t)(s + 1)) {
+    comp = 0;
+    j = (int)t;
+  } else if (t < (size_t)2 * (s + 1)) {
+    comp = 1;
+    j = (int)(t - (s + 1));
+  } else {
+    comp = 2;
+    j = (int)(t - 2 * (s + 1));
+  }
+}
+__host__ __device__ inline cplx* win_at(const AdjView& V, const AdjWin& w, int comp, int s, int j) {
+  return comp == 0 ? V.wR(w, s, j) : (comp == 1 ? V.wL(w, j, s) : V.wT(w, s, j));
+}
+
+// Window copies of slices lo..hi:
+//   mode 0: g0 <- Gbar, s0 <- Sigmabar, e0 <- eps_bar         (before the iteration)
+//   mode 1: gdry <- nu[b], sdry <- s0, gedry <- e0             (before a trial step)
+//   mode 2: Gbar <- nu[b]                                       (commit)
+__host__ __device__ inline void adj_wcopy_elem(const AdjProb& Ap, const KW& W, int mode, int lo, int hi, int b,
+                                               size_t idx) {
+  AdjView V(Ap, W);
+  int dd = V.dd;
+  size_t nw = win_elems(lo, hi, V.ntau, dd);
+  if (idx < nw) {
+    int s, comp, j, e;
+    win_decode(idx, lo, hi, V.ntau, dd, s, comp, j, e);
+    if (mode == 0) {
+      cplx* g = comp == 0 ? V.aR(s, j) : (comp == 1 ? V.aL(j, s) : V.aT(s, j));
+      cplx* x = comp == 0 ? V.sR(s, j) : (comp == 1 ? V.sL(j, s) : V.sT(s, j));
+      win_at(V, Ap.g0, comp, s, j)[e] = g[e];
+      win_at(V, Ap.s0, comp, s, j)[e] = x[e];
+    } else if (mode == 1) {
+      win_at(V, Ap.gdry, comp, s, j)[e] = win_at(V, Ap.nu[b], comp, s, j)[e];
+      win_at(V, Ap.sdry, comp, s, j)[e] = win_at(V, Ap.s0, comp, s, j)[e];
+    } else {
+      cplx* g = comp == 0 ? V.aR(s, j) : (comp == 1 ? V.aL(j, s) : V.aT(s, j));
+      g[e] = win_at(V, Ap.nu[b], comp, s, j)[e];
+    }
+    return;
+  }
+  idx -= nw;
+  if (mode == 2 || idx >= (size_t)(hi - lo + 1) * dd) return;
+  int s = lo + (int)(idx / dd), e = (int)(idx % dd);
+  if (mode == 0)
+    Ap.e0[(size_t)(s - lo) * dd + e] = V.ge(s)[e];
+  else
+    Ap.gedry[(size_t)(s + 1) * dd + e] = Ap.e0[(size_t)(s - lo) * dd + e];
+}
+
+// nu[b] = g0 + Sigma_2B'^*(sbar) + Hartree'^*(ebar) on slices lo..hi, with
+// (sbar, ebar) = (s0, e0) for src 0 and the trial step's (sdry, gedry) for src 1.
+//   Sigma^<_ab(j,s) = u L_ab^2 (R_ba - conj L_ab),
+//   Sigma^R_ab(s,j) = u [(R_ab - conj L_ba)^2 L_ba - conj(L_ba)^2 (L_ba - conj R_ab)],  u = U_s U_j,
+//   Sigma^rceil_ab(s,m) = U_s U_{-1} T_ab(s,m)^2 (-xi conj T_ab(s, ntau-m)),
+//   eps_ii(s) += U_s (Re(i xi L_ii(s,s)) - nbar).
+// For w = f(z, conj z): zbar += conj(df/dz) wbar + (df/dconj z) conj(wbar).
+__host__ __device__ inline void adj_sig2b_elem(const AdjProb& Ap, const KW& W, int lo, int hi, int src, int b,
+                                               size_t idx) {
+  AdjView V(Ap, W);
+  int d = V.d, dd = V.dd, ntau = V.ntau;
+  double xi = V.xi;
+  if (idx >= win_elems(lo, hi, ntau, dd)) return;
+  int s, comp, j, e;
+  win_decode(idx, lo, hi, ntau, dd, s, comp, j, e);
+  int p = e / d, q = e % d;
+  const AdjWin& S = src == 0 ? Ap.s0 : Ap.sdry;
+  auto u = [&](int t) { return Ap.U[t + 1]; };
+  cplx v = win_at(V, Ap.g0, comp, s, j)[e];
+  if (comp == 0) {
+    double uu = u(s) * u(j);
+    cplx Lqp = V.GL(j, s)[q * d + p], Rpq = V.GR(s, j)[p * d + q];
+    cplx wL = V.wL(S, j, s)[q * d + p], wR = V.wR(S, s, j)[p * d + q];
+    v = v + conj(uu * (Lqp * Lqp)) * wL;
+    cplx A = Rpq - conj(Lqp);
+    cplx fR = (2.0 * uu) * (A * Lqp), fRc = uu * (conj(Lqp) * conj(Lqp));
+    v = v + conj(fR) * wR + fRc * conj(wR);
+  } else if (comp == 1) {
+    double uu = u(s) * u(j);
+    cplx Lpq = V.GL(j, s)[p * d + q], Rqp = V.GR(s, j)[q * d + p];
+    cplx wL = V.wL(S, j, s)[p * d + q], wR = V.wR(S, s, j)[q * d + p];
+    cplx fl = (2.0 * uu) * (Lpq * (Rqp - conj(Lpq))), flc = -uu * (Lpq * Lpq);
+    v = v + conj(fl) * wL + flc * conj(wL);
+    cplx A = Rqp - conj(Lpq);
+    cplx fL = uu * (A * A - conj(Lpq) * conj(Lpq));
+    cplx fLc = uu * ((-2.0) * (A * Lpq) - 2.0 * (conj(Lpq) * Lpq) + 2.0 * (conj(Lpq) * conj(Rqp)));
+    v = v + conj(fL) * wR + fLc * conj(wR);
+    if (j == s && p == q) {
+      const cplx* eb = src == 0 ? Ap.e0 + (size_t)(s - lo) * dd : Ap.gedry + (size_t)(s + 1) * dd;
+      v = v + mk(0, -xi * u(s) * eb[p * d + p].x);
+    }
+  } else {
+    int m = j;
+    double uT = u(s) * u(-1);
+    cplx x = V.GT(s, m)[e], y = V.GT(s, ntau - m)[e];
+    cplx vt = -xi * conj(y);
+    cplx w = V.wT(S, s, m)[e], w2 = V.wT(S, s, ntau - m)[e];
+    v = v + conj((2.0 * uT) * (x * vt)) * w + (-xi * uT) * (y * y) * conj(w2);
+  }
+  win_at(V, Ap.nu[b], comp, s, j)[e] = v;
+}
+
+// max |nu[0] - nu[1]| and max |nu[1]| over slices lo..hi (team), to conv[2 slot]
+__host__ __device__ inline void adj_conv_team(const AdjProb& Ap, const KW& W, int lo, int hi, int slot, int tid,
+                                              int nth, double* red) {
+  AdjView V(Ap, W);
+  size_t nw = win_elems(lo, hi, V.ntau, V.dd);
+  double dm = 0.0, vm = 0.0;
+  for (size_t i = tid; i < nw; i += nth) {
+    int s, comp, j, e;
+    win_decode(i, lo, hi, V.ntau, V.dd, s, comp, j, e);
+    if (comp == 0 && j == s) continue;  // R_{s,s} is fixed
+    cplx a = win_at(V, Ap.nu[0], comp, s, j)[e], c = win_at(V, Ap.nu[1], comp, s, j)[e];
+    double x = sqrt(abs2(a - c)), y = sqrt(abs2(c));
+    dm = x > dm ? x : dm;
+    vm = y > vm ? y : vm;
+  }
+  red[2 * tid] = dm;
+  red[2 * tid + 1] = vm;
+  ADJ_SYNC();
+  if (tid == 0) {
+    for (int t = 1; t < nth; t++) {
+      dm = red[2 * t] > dm ? red[2 * t] : dm;
+      vm = red[2 * t + 1] > vm ? red[2 * t + 1] : vm;
+    }
+    Ap.conv[2 * slot] = dm;
+    Ap.conv[2 * slot + 1] = vm;
+  }
+  ADJ_SYNC();
+}
+
+// dJ/dU from the final Sigma and eps adjoints of slice s (team):
+//   Ubar_j += U_s c_j, Ubar_s += U_j c_j (c_j: column j of R and L),
+//   Ubar_s += U_{-1} c_T + c_H, Ubar_{-1} += U_s c_T.
+__host__ __device__ inline void adj_ugrad_team(const AdjProb& Ap, const KW& W, int s, int tid, int nth,
+                                               double* red) {
+  AdjView V(Ap, W);
+  int d = V.d, dd = V.dd, ntau = V.ntau;
+  double xi = V.xi;
+  auto u = [&](int t) { return Ap.U[t + 1]; };
+  double accS = 0.0, accT = 0.0;
+  for (int j = tid; j <= s; j += nth) {
+    double c = 0.0;
+    for (int e = 0; e < dd; e++) {
+      int a = e / d, b = e % d;
+      cplx Lab = V.GL(j, s)[a * d + b], Lba = V.GL(j, s)[b * d + a];
+      cplx Rab = V.GR(s, j)[a * d + b], Rba = V.GR(s, j)[b * d + a];
+      cplx wL = V.sL(j, s)[e], wR = V.sR(s, j)[e];
+      cplx pl = (Lab * Lab) * (Rba - conj(Lab));
+      cplx A = Rab - conj(Lba);
+      cplx pr = (A * A) * Lba - (conj(Lba) * conj(Lba)) * (Lba - conj(Rab));
+      c += (conj(wL) * pl).x + (conj(wR) * pr).x;
+    }
+    if (j < s) Ap.ub[j + 1] += u(s) * c;
+    accS += u(j) * c + (j == s ? u(s) * c : 0.0);
+  }
+  for (int m = tid; m <= ntau; m += nth)
+    for (int e = 0; e < dd; e++) {
+      cplx x = V.GT(s, m)[e], y = V.GT(s, ntau - m)[e];
+      cplx w = V.sT(s, m)[e];
+      accT += (conj(w) * ((x * x) * (-xi * conj(y)))).x;
+    }
+  red[2 * tid] = accS;
+  red[2 * tid + 1] = accT;
+  ADJ_SYNC();
+  if (tid == 0) {
+    double cs = 0.0, ct = 0.0;
+    for (int t = 0; t < nth; t++) {
+      cs += red[2 * t];
+      ct += red[2 * t + 1];
+    }
+    double ch = 0.0;
+    for (int i = 0; i < d; i++) {
+      cplx L = V.GL(s, s)[i * d + i];
+      double rho = -xi * L.y;  // Re(i xi L)
+      ch += V.ge(s)[i * d + i].x * (rho - Ap.nbar);
+    }
+    Ap.ub[s + 1] += cs + u(-1) * ct + ch;
+    Ap.ub[0] += u(s) * ct;
+  }
+  ADJ_SYNC();
+}
+
 // ============================================================== device kernels
 constexpr int ADJ_LDS = 4000;  // complex entries of the team kernels' LDS (64000 B)
 
@@ -1199,43 +1431,163 @@ __global__ void __launch_bounds__(ADJ_NT) k_adj_rstart(const AdjProb* ap) {
   if (!adj_rstart_team(A, c_kw[A.p.k], threadIdx.x, blockDim.x, lds, piv) && threadIdx.x == 0) adj_fail(A);
 }
 
+// Start of a block of slices lo..hi: window origins of every problem, and its
+// trial copy with the adjoint arrays redirected to the windows (Sigma window
+// from slice wlo, the first slice the trial step's boundary terms reach).
+__global__ void k_adj_setdry(AdjProb* dry, AdjProb* ap, int lo, int wlo) {
+  if (threadIdx.x != 0) return;
+  int i = blockIdx.y;
+  int ntau = ap[i].p.ntau;
+  AdjWin* ws[5] = {&ap[i].g0, &ap[i].s0, &ap[i].nu[0], &ap[i].nu[1], &ap[i].gdry};
+  for (int w = 0; w < 5; w++) {
+    ws[w]->oR = tri(lo);
+    ws[w]->oL = tri(lo);
+    ws[w]->oT = (size_t)lo * (ntau + 1);
+  }
+  ap[i].sdry.oR = tri(wlo);
+  ap[i].sdry.oL = tri(wlo);
+  ap[i].sdry.oT = (size_t)wlo * (ntau + 1);
+  AdjProb a = ap[i];
+  a.aR = a.gdry.R;
+  a.aL = a.gdry.L;
+  a.aT = a.gdry.T;
+  a.aoR = tri(lo);
+  a.aoL = tri(lo);
+  a.aoT = (size_t)lo * (ntau + 1);
+  a.sR = a.sdry.R;
+  a.sL = a.sdry.L;
+  a.sT = a.sdry.T;
+  a.soR = tri(wlo);
+  a.soL = tri(wlo);
+  a.soT = (size_t)wlo * (ntau + 1);
+  a.ge = a.gedry;
+  a.aM = a.mdummy;
+  dry[i] = a;
+}
+__global__ void __launch_bounds__(ADJ_NT) k_adj_wcopy(const AdjProb* ap, int mode, int lo, int hi, int b) {
+  const AdjProb& A = ap[blockIdx.y];
+  if (hi > A.p.nt) return;
+  adj_wcopy_elem(A, c_kw[A.p.k], mode, lo, hi, b, (size_t)blockIdx.x * blockDim.x + threadIdx.x);
+}
+__global__ void __launch_bounds__(ADJ_NT) k_adj_sig2b(const AdjProb* ap, int lo, int hi, int src, int b) {
+  const AdjProb& A = ap[blockIdx.y];
+  if (hi > A.p.nt) return;
+  adj_sig2b_elem(A, c_kw[A.p.k], lo, hi, src, b, (size_t)blockIdx.x * blockDim.x + threadIdx.x);
+}
+__global__ void __launch_bounds__(ADJ_NT) k_adj_conv(const AdjProb* ap, int lo, int hi, int slot) {
+  __shared__ double red[2 * ADJ_NT];
+  const AdjProb& A = ap[blockIdx.y];
+  if (hi > A.p.nt) return;
+  adj_conv_team(A, c_kw[A.p.k], lo, hi, slot, threadIdx.x, blockDim.x, red);
+}
+__global__ void __launch_bounds__(ADJ_NT) k_adj_ugrad(const AdjProb* ap, int s) {
+  __shared__ double red[2 * ADJ_NT];
+  const AdjProb& A = ap[blockIdx.y];
+  if (s > A.p.nt) return;
+  adj_ugrad_team(A, c_kw[A.p.k], s, threadIdx.x, blockDim.x, red);
+}
+
 // ============================================================== host sequencing
 // Launches the whole backward sweep for the problems in dA (host copies in hA,
 // which share d, k and ntau): slices ntmax .. k+1, then the start-up.
 inline unsigned adj_blocks(size_t elems) { return (unsigned)((elems + ADJ_NT - 1) / ADJ_NT); }
 
-hipError_t launch_adjoint_sweep(const AdjProb* dA, const AdjProb* hA, int count, hipStream_t s) {
-  int k = hA[0].p.k, d = hA[0].p.d, ntau = hA[0].p.ntau, dd = d * d, ntmax = 0;
-  bool sig = hA[0].sR != nullptr;
-  for (int i = 0; i < count; i++) ntmax = hA[i].p.nt > ntmax ? hA[i].p.nt : ntmax;
+struct AdjShape {
+  int count, k, d, ntau, dd, ntmax;
+  bool sig;
+};
+
+// reverse step of slice n > k (hist: also scatter into the history of slices < n)
+void adj_step_launch(const AdjProb* dA, const AdjShape& S, int n, bool hist, hipStream_t s) {
+  int k = S.k, ntau = S.ntau, dd = S.dd;
   dim3 blk(ADJ_NT);
-  int cb = adj_cb(dd);
-  for (int n = ntmax; n > k; n--) {
-    LcolGeom lg = lcol_geom(n, k, ntau, dd, sig);
-    RhoGeom rg = rho_geom(n, k, ntau, cb);
+  LcolGeom lg = lcol_geom(n, k, ntau, dd, S.sig);
+  RhoGeom rg = rho_geom(n, k, ntau, adj_cb(dd));
+  hipLaunchKernelGGL(k_adj_lcol, dim3(1, S.count), blk, 0, s, dA, n);
+  hipLaunchKernelGGL(k_adj_lcol_scatter, dim3(adj_blocks(lg.total), S.count), blk, 0, s, dA, n);
+  hipLaunchKernelGGL(k_adj_rho, dim3(rg.wl + rg.wt + rg.wr, S.count), blk, 0, s, dA, n);
+  if (hist) {
     HistGeom hg = hist_geom(n, k, ntau, dd);
-    hipLaunchKernelGGL(k_adj_lcol, dim3(1, count), blk, 0, s, dA, n);
-    hipLaunchKernelGGL(k_adj_lcol_scatter, dim3(adj_blocks(lg.total), count), blk, 0, s, dA, n);
-    hipLaunchKernelGGL(k_adj_rho, dim3(rg.wl + rg.wt + rg.wr, count), blk, 0, s, dA, n);
-    hipLaunchKernelGGL(k_adj_hist, dim3(adj_blocks(hg.total), count), blk, 0, s, dA, n);
-    if (sig) hipLaunchKernelGGL(k_adj_sigma, dim3(sig_geom(n, k, ntau).total, count), blk, 0, s, dA, n);
-    hipLaunchKernelGGL(k_adj_tau, dim3(adj_blocks((size_t)(sig ? 2 : 1) * (ntau + 1) * dd), count), blk, 0, s,
-                       dA, n, 0);
-    hipLaunchKernelGGL(k_adj_rbound, dim3(1, count), blk, 0, s, dA, n);
+    hipLaunchKernelGGL(k_adj_hist, dim3(adj_blocks(hg.total), S.count), blk, 0, s, dA, n);
   }
+  if (S.sig) hipLaunchKernelGGL(k_adj_sigma, dim3(sig_geom(n, k, ntau).total, S.count), blk, 0, s, dA, n);
+  hipLaunchKernelGGL(k_adj_tau, dim3(adj_blocks((size_t)(S.sig ? 2 : 1) * (ntau + 1) * dd), S.count), blk, 0, s,
+                     dA, n, 0);
+  hipLaunchKernelGGL(k_adj_rbound, dim3(1, S.count), blk, 0, s, dA, n);
+}
+
+// reverse of the start-up (slices 0..k)
+void adj_start_launch(const AdjProb* dA, const AdjShape& S, hipStream_t s) {
+  int k = S.k, ntau = S.ntau, dd = S.dd;
+  dim3 blk(ADJ_NT);
   for (int n = k; n >= 0; n--) {
-    LcolGeom lg = lcol_geom(n, k, ntau, dd, sig);
-    hipLaunchKernelGGL(k_adj_lcol, dim3(1, count), blk, 0, s, dA, n);
-    hipLaunchKernelGGL(k_adj_lcol_scatter, dim3(adj_blocks(lg.total), count), blk, 0, s, dA, n);
+    LcolGeom lg = lcol_geom(n, k, ntau, dd, S.sig);
+    hipLaunchKernelGGL(k_adj_lcol, dim3(1, S.count), blk, 0, s, dA, n);
+    hipLaunchKernelGGL(k_adj_lcol_scatter, dim3(adj_blocks(lg.total), S.count), blk, 0, s, dA, n);
   }
-  hipLaunchKernelGGL(k_adj_tinv, dim3(1, count), blk, 0, s, dA);
-  hipLaunchKernelGGL(k_adj_tpsi, dim3(adj_blocks((size_t)k * (ntau + 1) * dd), count), blk, 0, s, dA);
-  hipLaunchKernelGGL(k_adj_ty0, dim3(adj_blocks((size_t)(ntau + 1) * dd), count), blk, 0, s, dA);
-  hipLaunchKernelGGL(k_adj_tp, dim3(k * (k + 1), count), blk, 0, s, dA);
+  hipLaunchKernelGGL(k_adj_tinv, dim3(1, S.count), blk, 0, s, dA);
+  hipLaunchKernelGGL(k_adj_tpsi, dim3(adj_blocks((size_t)k * (ntau + 1) * dd), S.count), blk, 0, s, dA);
+  hipLaunchKernelGGL(k_adj_ty0, dim3(adj_blocks((size_t)(ntau + 1) * dd), S.count), blk, 0, s, dA);
+  hipLaunchKernelGGL(k_adj_tp, dim3(k * (k + 1), S.count), blk, 0, s, dA);
   for (int p = 1; p <= k; p++)
-    hipLaunchKernelGGL(k_adj_tau, dim3(adj_blocks((size_t)(sig ? 2 : 1) * (ntau + 1) * dd), count), blk, 0, s,
-                       dA, p, 1);
-  hipLaunchKernelGGL(k_adj_rstart, dim3(1, count), blk, 0, s, dA);
+    hipLaunchKernelGGL(k_adj_tau, dim3(adj_blocks((size_t)(S.sig ? 2 : 1) * (ntau + 1) * dd), S.count), blk, 0,
+                       s, dA, p, 1);
+  hipLaunchKernelGGL(k_adj_rstart, dim3(1, S.count), blk, 0, s, dA);
+}
+
+AdjShape adj_shape(const AdjProb* hA, int count) {
+  AdjShape S;
+  S.count = count;
+  S.k = hA[0].p.k;
+  S.d = hA[0].p.d;
+  S.ntau = hA[0].p.ntau;
+  S.dd = S.d * S.d;
+  S.sig = hA[0].sR != nullptr;
+  S.ntmax = 0;
+  for (int i = 0; i < count; i++) S.ntmax = hA[i].p.nt > S.ntmax ? hA[i].p.nt : S.ntmax;
+  return S;
+}
+
+// Whole backward sweep for a given self-energy: slices ntmax .. k+1, then the
+// start-up (problems share d, k and ntau).
+hipError_t launch_adjoint_sweep(const AdjProb* dA, const AdjProb* hA, int count, hipStream_t s) {
+  AdjShape S = adj_shape(hA, count);
+  for (int n = S.ntmax; n > S.k; n--) adj_step_launch(dA, S, n, true, s);
+  adj_start_launch(dA, S, s);
+  return hipGetLastError();
+}
+
+// Second-Born chain: per slice (and for the start-up block 0..k) `niter`
+// trial steps of the adjoint fixed point on windows, then the final step.
+hipError_t launch_adjoint_2b(AdjProb* dA, AdjProb* dDry, const AdjProb* hA, int count, int niter,
+                             hipStream_t s) {
+  AdjShape S = adj_shape(hA, count);
+  int k = S.k, ntau = S.ntau, dd = S.dd;
+  dim3 blk(ADJ_NT);
+  auto block = [&](int lo, int hi, int wlo, bool start) {
+    unsigned wb = adj_blocks(win_elems(lo, hi, ntau, dd) + (size_t)(hi - lo + 1) * dd);
+    unsigned sb = adj_blocks(win_elems(lo, hi, ntau, dd));
+    hipLaunchKernelGGL(k_adj_setdry, dim3(1, count), dim3(64), 0, s, dDry, dA, lo, wlo);
+    hipLaunchKernelGGL(k_adj_wcopy, dim3(wb, count), blk, 0, s, dA, 0, lo, hi, 0);
+    hipLaunchKernelGGL(k_adj_sig2b, dim3(sb, count), blk, 0, s, dA, lo, hi, 0, 0);
+    for (int it = 0; it < niter; it++) {
+      hipLaunchKernelGGL(k_adj_wcopy, dim3(wb, count), blk, 0, s, dA, 1, lo, hi, it % 2);
+      if (start)
+        adj_start_launch(dDry, S, s);
+      else
+        adj_step_launch(dDry, S, hi, false, s);
+      hipLaunchKernelGGL(k_adj_sig2b, dim3(sb, count), blk, 0, s, dA, lo, hi, 1, (it + 1) % 2);
+    }
+    hipLaunchKernelGGL(k_adj_conv, dim3(1, count), blk, 0, s, dA, lo, hi, hi);
+    hipLaunchKernelGGL(k_adj_wcopy, dim3(wb, count), blk, 0, s, dA, 2, lo, hi, niter % 2);
+    if (start)
+      adj_start_launch(dA, S, s);
+    else
+      adj_step_launch(dA, S, hi, true, s);
+    for (int t = lo; t <= hi; t++) hipLaunchKernelGGL(k_adj_ugrad, dim3(1, count), blk, 0, s, dA, t);
+  };
+  for (int n = S.ntmax; n > k; n--) block(n, n, n > 2 * k ? n - k : 0, false);
+  block(0, k, 0, true);
   return hipGetLastError();
 }
 

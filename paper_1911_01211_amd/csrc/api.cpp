@@ -1,6 +1,7 @@
 // C ABI of the HIP Dyson time stepper: argument validation, library state
 // (weight tables, per-stream scratch), and the host-side sequencing of the
 // Matsubara solve and the self-consistent second-Born propagation.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -552,31 +553,49 @@ cntr_status cntr_observables(int32_t tstp, int32_t count, const cntr_grid* grids
 }
 
 cntr_status cntr_adjoint_sweep(int32_t count, const cntr_grid* grids, const cntr_gf* G, const cntr_gf* Sigma,
-                               const void* const* eps, const cntr_gf* Gbar, const cntr_gf* Sigmabar,
-                               void* const* eps_bar, void* stream) {
+                               const void* const* eps, const double* const* U, double nbar,
+                               const cntr_gf* Gbar, const cntr_gf* Sigmabar, void* const* eps_bar,
+                               double* const* U_bar, int32_t niter, double* conv, void* stream) {
   cntr_status st = check_batch(count, grids, "cntr_adjoint_sweep");
   if (st) return st;
+  if (count > 65535) return fail(CNTR_ESHAPE, "cntr_adjoint_sweep: at most 65535 problems per call");
   if (!gf_ok(G, count) || !gf_ok(Sigma, count) || !gf_ok(Gbar, count) || !eps || !eps_bar)
     return fail(CNTR_ESHAPE, "cntr_adjoint_sweep: null pointer");
+  bool twob = U != nullptr;
+  if (twob && (!Sigmabar || !U_bar))
+    return fail(CNTR_ESHAPE, "cntr_adjoint_sweep: the second-Born mode needs Sigmabar and U_bar");
   for (int i = 0; i < count; i++) {
     if (!eps[i] || !eps_bar[i]) return fail(CNTR_ESHAPE, "cntr_adjoint_sweep: null eps or eps_bar");
     if (Sigmabar && (!Sigmabar[i].ret || !Sigmabar[i].les || !Sigmabar[i].tv))
       return fail(CNTR_ESHAPE, "cntr_adjoint_sweep: Sigmabar needs ret, les and tv");
+    if (twob && (!U[i] || !U_bar[i])) return fail(CNTR_ESHAPE, "cntr_adjoint_sweep: null U or U_bar");
   }
+  if (niter <= 0) niter = 16;
   if ((st = ensure_weights())) return st;
   hipStream_t s = (hipStream_t)stream;
   StreamScratch* sc = scratch_for(s);
-  int ntmax = 0;
+  int ntmax = 0, k = grids[0].k, d = grids[0].d, ntau = grids[0].ntau;
   for (int i = 0; i < count; i++) ntmax = grids[i].nt > ntmax ? grids[i].nt : ntmax;
-  AdjLayout lay = adj_layout(ntmax, grids[0].ntau, grids[0].d, grids[0].k);
-  size_t per = round256(lay.total * sizeof(cplx));
-  size_t head = round256(count * sizeof(int)) + round256(count * sizeof(AdjProb));
+  size_t dd = (size_t)d * d;
+  AdjLayout lay = adj_layout(ntmax, ntau, d, k);
+  // second-Born work windows (blocks): slice windows of slices [n, n] or [0, k],
+  // Sigma windows of slices [n-k, n] or [0, n <= 2k]
+  size_t wr = std::max<size_t>(ntmax + 1, tri(k + 1)), wt = (size_t)(k + 1) * (ntau + 1);
+  size_t sr = std::max<size_t>((size_t)(k + 1) * (ntmax + 1), tri(2 * k + 1)), stt = (size_t)(2 * k + 1) * (ntau + 1);
+  size_t wblk = 2 * wr + wt, sblk = 2 * sr + stt;
+  size_t work = twob ? round256((5 * wblk + sblk + (k + 1) + (ntmax + 2) + (ntau + 1)) * dd * sizeof(cplx)) +
+                           round256(2 * (ntmax + 2) * sizeof(double))
+                     : 0;
+  size_t per = round256(lay.total * sizeof(cplx)) + work;
+  size_t head = round256(count * sizeof(int)) + 2 * round256(count * sizeof(AdjProb));
   if ((st = grow(s, sc, head + per * count, 5, 2))) return st;
   int* dstat = (int*)sc->buf;
   AdjProb* dA = (AdjProb*)(sc->buf + round256(count * sizeof(int)));
+  AdjProb* dDry = (AdjProb*)((char*)dA + round256(count * sizeof(AdjProb)));
   std::vector<AdjProb> hA(count);
   for (int i = 0; i < count; i++) {
     AdjProb& a = hA[i];
+    a = AdjProb{};
     a.p = make_prob(grids[i], &G[i], &Sigma[i], eps[i]);
     a.aR = (cplx*)Gbar[i].ret;
     a.aL = (cplx*)Gbar[i].les;
@@ -586,19 +605,63 @@ cntr_status cntr_adjoint_sweep(int32_t count, const cntr_grid* grids, const cntr
     a.sL = Sigmabar ? (cplx*)Sigmabar[i].les : nullptr;
     a.sT = Sigmabar ? (cplx*)Sigmabar[i].tv : nullptr;
     a.ge = (cplx*)eps_bar[i];
-    // every problem's scratch is laid out for its own nt (offsets depend on nt)
-    a.scr = (cplx*)(sc->buf + head + per * i);
+    char* base = sc->buf + head + per * i;
+    a.scr = (cplx*)base;
     a.stat = dstat + i;
+    if (twob) {
+      a.U = U[i];
+      a.nbar = nbar;
+      a.ub = U_bar[i];
+      cplx* w = (cplx*)(base + round256(lay.total * sizeof(cplx)));
+      auto win = [&](AdjWin& x, size_t r, size_t t) {
+        x.R = w;
+        x.L = w + r * dd;
+        x.T = w + 2 * r * dd;
+        w += (2 * r + t) * dd;
+      };
+      win(a.g0, wr, wt);
+      win(a.s0, wr, wt);
+      win(a.nu[0], wr, wt);
+      win(a.nu[1], wr, wt);
+      win(a.gdry, wr, wt);
+      win(a.sdry, sr, stt);
+      a.e0 = w;
+      w += (k + 1) * dd;
+      a.gedry = w;
+      w += (ntmax + 2) * dd;
+      a.mdummy = w;
+      w += (ntau + 1) * dd;
+      a.conv = (double*)((char*)a.scr + round256(lay.total * sizeof(cplx)) +
+                         round256((5 * wblk + sblk + (k + 1) + (ntmax + 2) + (ntau + 1)) * dd * sizeof(cplx)));
+    }
   }
   hipError_t e = hipMemsetAsync(dstat, 0, count * sizeof(int), s);
   if (e == hipSuccess) e = hipMemcpyAsync(dA, hA.data(), count * sizeof(AdjProb), hipMemcpyHostToDevice, s);
-  if (e == hipSuccess) e = launch_adjoint_sweep(dA, hA.data(), count, s);
+  if (e == hipSuccess)
+    e = twob ? launch_adjoint_2b(dA, dDry, hA.data(), count, niter, s) : launch_adjoint_sweep(dA, hA.data(), count, s);
   std::vector<int> hs(count, 0);
+  std::vector<std::vector<double>> hc;
   if (e == hipSuccess) e = hipMemcpyAsync(hs.data(), dstat, count * sizeof(int), hipMemcpyDeviceToHost, s);
+  if (twob && conv)
+    for (int i = 0; i < count && e == hipSuccess; i++) {
+      hc.emplace_back(2 * (grids[i].nt + 2));
+      e = hipMemcpyAsync(hc.back().data(), hA[i].conv, hc.back().size() * sizeof(double), hipMemcpyDeviceToHost, s);
+    }
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return hip_fail(e, "cntr_adjoint_sweep");
   for (int i = 0; i < count; i++)
     if (hs[i]) return fail(CNTR_ESINGULAR, "cntr_adjoint_sweep: singular local matrix in problem " + std::to_string(i));
+  if (twob && conv) {
+    // slots: slice n for the steps (n > k), slot k for the start-up block
+    double worst = 0.0;
+    for (int i = 0; i < count; i++)
+      for (int n = k; n <= grids[i].nt; n++) {
+        double ch = hc[i][2 * n], v = hc[i][2 * n + 1];
+        double r = v > 0 ? ch / v : ch;
+        worst = r > worst ? r : worst;
+      }
+    *conv = worst;
+  }
   return CNTR_OK;
 }
 
