@@ -211,15 +211,19 @@ cntr_status cntr_solve_2b(const cntr_grid* grid, const cntr_gf* G, const cntr_gf
  * Given self-energy (U == NULL): G(eps, Sigma, M) solves slices 0..nt;
  *   eps_bar += dJ/deps_n, Sigmabar += dJ/dSigma (if not NULL), Gbar.mat += dJ/dM.
  * Second-Born mode (U != NULL): Sigma = Sigma_2B[G; U] (as cntr_sigma_2b) and
- *   eps = eps0 + Hartree[G; U, nbar] on every slice 0..nt; G, Sigma and eps
+ *   eps = eps0 + Hartree[G; U, nbar] on every slice -1..nt; G, Sigma and eps
  *   are the converged self-consistent solution (cntr_solve_2b; eps is its
- *   eps_mf). Each slice's adjoint is the fixed point of the reverse step
- *   composed with the adjoints of Sigma_2B and Hartree, iterated `niter`
- *   times per slice (the start-up block of slices 0..k together);
- *   eps_bar += dJ/deps0_n (n = 0..nt), U_bar += dJ/dU_n for n = 0..nt and
- *   the part of dJ/dU_{-1} that enters through Sigma^rceil (the Matsubara
- *   part enters through M: Gbar.mat returns dJ/dM). Sigmabar is required
- *   (work space; returns the total dJ/dSigma), U_bar is required.
+ *   eps_mf), including the Matsubara component. Each slice's adjoint is the
+ *   fixed point of the reverse step composed with the adjoints of Sigma_2B
+ *   and Hartree, iterated `niter` times per slice (the start-up block of
+ *   slices 0..k together); the Matsubara solve (Eq. Gmat_dyson_integ, its
+ *   operator rebuilt and inverted at the converged Sigma^M) is reversed
+ *   likewise, with 200 damped iterations (weight 1/2, as the forward loop).
+ *   eps_bar += dJ/deps0_n and U_bar += dJ/dU_n for n = -1..nt (eps0_{-1}
+ *   through a hermitian eigen-decomposition: its gradient is exact along
+ *   hermitian directions). Gbar.mat returns dJ/dM with M held fixed (the
+ *   seed of the equilibrium part). Sigmabar is required (work space; returns
+ *   the total dJ/dSigma of slices 0..nt), U_bar is required.
  *
  *   G        : the converged solution (slices -1..nt) of the same grid.
  *   Sigma    : the self-energy the solution was computed with.
@@ -232,11 +236,11 @@ cntr_status cntr_solve_2b(const cntr_grid* grid, const cntr_gf* G, const cntr_gf
  *              consumed as work space (on return: intermediate adjoints).
  *   Sigmabar : accumulators (+=) of dJ/dSigma, slices 0..nt (mat untouched).
  *   eps_bar  : accumulators (+=) of (nt+2) blocks, entry n+1 for time n
- *              (entry 0 is not touched).
+ *              (entry 0, time -1, only in the second-Born mode).
  *   U_bar    : per problem DEVICE array of nt+2 doubles (+=), index n+1.
  *   niter    : fixed-point iterations per slice (<= 0: 16).
  *   conv     : HOST double or NULL: largest relative change of a slice
- *              adjoint in its last iteration (second-Born mode).
+ *              (or Matsubara) adjoint in its last iteration (second-Born mode).
  * Instances may have different nt (each is swept from its own nt). Every
  * pointer except conv is a DEVICE pointer, owned by the caller. Synchronizes
  * `stream`; CNTR_ESINGULAR if a local step or start-up matrix is singular. */

@@ -22,6 +22,7 @@
 // count), so its index arithmetic compiles on the host as well.
 #pragma once
 #include "dev_common.h"
+#include "launch.h"
 
 namespace cntr {
 
@@ -1298,6 +1299,230 @@ __host__ __device__ inline void adj_ugrad_team(const AdjProb& Ap, const KW& W, i
   ADJ_SYNC();
 }
 
+// ============================================================== Matsubara
+// Reverse of the self-consistent Matsubara solve of the second-Born run
+// (Eq. Gmat_dyson_integ: A M = g with A = 1 - B[K], K = [g * Sigma^M]^M by
+// Eqs. cm1, cm2, g the free function of eps_{-1}; Sigma^M = Sigma_2B[M],
+// eps_{-1} = eps0_{-1} + Hartree[M]). Its adjoint nu solves
+//   nu = Mbar + Sigma_2B'^*(Sigmabar^M(nu)) + Hartree'^*(epsbar(nu)),
+//   gA = A^{-H} nu,  Kbar_J = sum c gA_m M_l^H over the terms c K_J of B_{m,l},
+//   gbar = gA + cm-reverse (Kbar, Sigma^M),  Sigmabar^M = cm-reverse (g, Kbar),
+//   epsbar = sum_m V (Gamma_m o (V^H gbar_m V)) V^H   (Daleckii-Krein, g_m = V f_m(x) V^H),
+// iterated with the damping of the forward loop.
+struct MadjBuf {
+  cplx *Ainv, *g, *gA, *Kb, *gb, *Sb, *nu, *nun, *eb, *V;
+  double *x, *red;
+};
+
+// gA = Ainv^H nu ; N x d
+__host__ __device__ inline void madj_ga_elem(int N, int d, const cplx* Ainv, const cplx* nu, cplx* gA, size_t idx) {
+  if (idx >= (size_t)N * d) return;
+  int r = (int)(idx / d), c = (int)(idx % d);
+  cplx s = mk(0, 0);
+  for (int q = 0; q < N; q++) cfma(s, conj(Ainv[(size_t)q * N + r]), nu[(size_t)q * d + c]);
+  gA[idx] = s;
+}
+
+// Kbar_J[p][q] = sum c (gA_m M_col^H)[p][q] over the terms c K_J of B_{m,col}
+__host__ __device__ inline void madj_kbar_elem(const Prob& P, const KW& W, const cplx* gA, cplx* Kb, size_t idx) {
+  int d = P.d, dd = d * d, nt = P.ntau, k = P.k;
+  if (idx >= (size_t)(nt + 1) * dd) return;
+  int J = (int)(idx / dd), e = (int)(idx % dd), p = e / d, q = e % d;
+  double ht = P.htau, xi = P.sig;
+  cplx v = mk(0, 0);
+  auto add = [&](int m, int col, double c) {
+    const cplx* g = gA + (size_t)m * dd;
+    const cplx* M = P.Gmat + (size_t)col * dd;
+    v = v + c * dotq(d, [&](int t) { return g[p * d + t]; }, [&](int t) { return conj(M[q * d + t]); });
+  };
+  if (J <= k)
+    for (int m = 0; m <= k; m++)
+      for (int l = 0; l <= k; l++) add(m, l, ht * W.R[m][J][l]);
+  for (int m = J > k + 1 ? J : k + 1; m <= nt; m++) add(m, m - J, ht * adj_w(W, m, m - J));
+  if (J >= nt - k)
+    for (int m = nt - k; m <= nt; m++)
+      for (int l = 0; l <= k; l++) add(m, nt - l, ht * xi * W.R[nt - m][nt - J][l]);
+  for (int m = 0; m <= (J < nt - k - 1 ? J : nt - k - 1); m++) add(m, m + nt - J, ht * xi * adj_w(W, nt - m, nt - J));
+  Kb[idx] = v;
+}
+
+// gbar_a = gA_a + sum c Kbar_m Sigma^M_b^H, Sigmabar^M_b = sum c g_a^H Kbar_m over the
+// terms c g_a Sigma^M_b of K_m (Eqs. cm1, cm2)
+__host__ __device__ inline void madj_conv_elem(const Prob& P, const KW& W, const MadjBuf& B, size_t idx) {
+  int d = P.d, dd = d * d, nt = P.ntau, k = P.k;
+  size_t nb = (size_t)(nt + 1) * dd;
+  if (idx >= 2 * nb) return;
+  bool sig = idx >= nb;
+  size_t i2 = sig ? idx - nb : idx;
+  int X = (int)(i2 / dd), e = (int)(i2 % dd), p = e / d, q = e % d;
+  double ht = P.htau, xi = P.sig;
+  cplx v = sig ? mk(0, 0) : B.gA[i2];
+  if (!sig) {
+    int a = X;
+    auto add = [&](int m, int b, double c) {
+      const cplx* K = B.Kb + (size_t)m * dd;
+      const cplx* S = P.Smat + (size_t)b * dd;
+      v = v + c * dotq(d, [&](int t) { return K[p * d + t]; }, [&](int t) { return conj(S[q * d + t]); });
+    };
+    if (a <= k)
+      for (int m = 0; m <= k; m++)
+        for (int l = 0; l <= k; l++) add(m, l, ht * W.R[m][a][l]);
+    for (int m = a > k + 1 ? a : k + 1; m <= nt; m++) add(m, m - a, ht * adj_w(W, m, m - a));
+    if (a >= nt - k)
+      for (int m = nt - k; m <= nt; m++)
+        for (int l = 0; l <= k; l++) add(m, nt - l, ht * xi * W.R[nt - m][nt - a][l]);
+    for (int m = 0; m <= (a < nt - k - 1 ? a : nt - k - 1); m++) add(m, m + nt - a, ht * xi * adj_w(W, nt - m, nt - a));
+    B.gb[i2] = v;
+  } else {
+    int b = X;
+    auto add = [&](int m, int a, double c) {
+      const cplx* K = B.Kb + (size_t)m * dd;
+      const cplx* g = B.g + (size_t)a * dd;
+      v = v + c * dotq(d, [&](int t) { return conj(g[t * d + p]); }, [&](int t) { return K[t * d + q]; });
+    };
+    if (b <= k)
+      for (int m = 0; m <= k; m++)
+        for (int j = 0; j <= k; j++) add(m, j, ht * W.R[m][j][b]);
+    for (int m = b > k + 1 ? b : k + 1; m <= nt; m++) add(m, m - b, ht * adj_w(W, m, b));
+    if (b >= nt - k)
+      for (int m = nt - k; m <= nt; m++)
+        for (int j = 0; j <= k; j++) add(m, nt - j, ht * xi * W.R[nt - m][j][nt - b]);
+    for (int m = 0; m <= (b < nt - k - 1 ? b : nt - k - 1); m++) add(m, nt - b + m, ht * xi * adj_w(W, nt - m, b - m));
+    B.Sb[i2] = v;
+  }
+}
+
+// f(x, tau) of the free function and its x-derivative (overflow-free forms)
+__host__ __device__ inline double madj_f(double x, double tau, double beta, double xi) {
+  if (x >= 0 || xi > 0) return -exp(-x * tau) / (1 - xi * exp(-beta * x));
+  return -exp(x * (beta - tau)) / (exp(beta * x) - xi);
+}
+__host__ __device__ inline double madj_fp(double x, double tau, double beta, double xi) {
+  double f = madj_f(x, tau, beta, xi);
+  double q = x >= 0 ? xi * exp(-beta * x) / (1 - xi * exp(-beta * x)) : xi / (exp(beta * x) - xi);
+  return f * (-tau - beta * q);
+}
+
+// eigen-decomposition of eps_{-1} - mu (thread 0 of the team)
+__host__ __device__ inline void madj_eig_team(const Prob& P, const MadjBuf& B, int tid, cplx* A) {
+  if (tid != 0) return;
+  int d = P.d;
+  for (int e = 0; e < d * d; e++) {
+    A[e] = P.eps[e];
+    if (e / d == e % d) A[e].x -= P.mu;
+  }
+  herm_jacobi(d, A, B.V, B.x);
+}
+
+// epsbar = sum_m V (Gamma_m o (V^H gbar_m V)) V^H (team; red: >= max(nth, dd) + dd complex)
+__host__ __device__ inline void madj_eps_team(const Prob& P, const MadjBuf& B, int tid, int nth, cplx* red) {
+  int d = P.d, dd = d * d, nt = P.ntau;
+  double beta = P.beta, xi = P.sig;
+  int lanes = dd >= nth ? 1 : nth / dd, slots = lanes * dd;
+  for (int t = tid; t < slots; t += nth) {
+    int e = t % dd, lane = t / dd, a = e / d, b = e % d;
+    double xa = B.x[a], xb = B.x[b];
+    bool deg = fabs(xa - xb) <= 1e-9 * (1 + fabs(xa));
+    cplx y = mk(0, 0);
+    for (int m = lane; m <= nt; m += lanes) {
+      double tau = m * P.htau;
+      double gm = deg ? madj_fp(xa, tau, beta, xi)
+                      : (madj_f(xa, tau, beta, xi) - madj_f(xb, tau, beta, xi)) / (xa - xb);
+      const cplx* G = B.gb + (size_t)m * dd;
+      cplx u = mk(0, 0);
+      for (int i = 0; i < d; i++)
+        for (int j = 0; j < d; j++) cfma(u, conj(B.V[i * d + a]), G[i * d + j] * B.V[j * d + b]);
+      y = y + gm * u;
+    }
+    red[t] = y;
+  }
+  ADJ_SYNC();
+  cplx* Y = red + slots;
+  for (int e = tid; e < dd; e += nth) {
+    cplx s = mk(0, 0);
+    for (int l = 0; l < lanes; l++) s = s + red[l * dd + e];
+    Y[e] = s;
+  }
+  ADJ_SYNC();
+  for (int e = tid; e < dd; e += nth) {
+    int pp = e / d, qq = e % d;
+    cplx s = mk(0, 0);
+    for (int i = 0; i < d; i++)
+      for (int j = 0; j < d; j++) cfma(s, B.V[pp * d + i], Y[i * d + j] * conj(B.V[qq * d + j]));
+    B.eb[e] = s;
+  }
+  ADJ_SYNC();
+}
+
+// nun = Mbar + Sigma_2B'^*(Sigmabar^M) + Hartree'^*(epsbar):
+//   Sigma^M_ab(m) = -xi U^2 M_ab(m)^2 M_ba(nt-m),  eps_ii += U (Re(-M_ii(nt)) - nbar)
+__host__ __device__ inline void madj_nu_elem(const Prob& P, const MadjBuf& B, const cplx* Mbar, double u, size_t idx) {
+  int d = P.d, dd = d * d, nt = P.ntau;
+  if (idx >= (size_t)(nt + 1) * dd) return;
+  int m = (int)(idx / dd), e = (int)(idx % dd), a = e / d, b = e % d;
+  double xi = P.sig, c2 = -xi * u * u;
+  const cplx* M = P.Gmat;
+  cplx x = M[(size_t)m * dd + a * d + b], y = M[(size_t)(nt - m) * dd + b * d + a];
+  cplx v = Mbar[idx];
+  v = v + conj((2.0 * c2) * (x * y)) * B.Sb[idx];
+  v = v + conj(c2 * (y * y)) * B.Sb[(size_t)(nt - m) * dd + b * d + a];
+  if (m == nt && a == b) v.x += -u * B.eb[a * d + a].x;
+  B.nun[idx] = v;
+}
+
+// nu <- mix nun + (1 - mix) nu
+__host__ __device__ inline void madj_mix_elem(const Prob& P, const MadjBuf& B, double mix, size_t idx) {
+  if (idx >= (size_t)(P.ntau + 1) * P.d * P.d) return;
+  B.nu[idx] = mix * B.nun[idx] + (1 - mix) * B.nu[idx];
+}
+
+// max |nun - nu| and max |nun| (team) into red[0], red[1]
+__host__ __device__ inline void madj_change_team(const Prob& P, const MadjBuf& B, int tid, int nth) {
+  size_t n = (size_t)(P.ntau + 1) * P.d * P.d;
+  double dm = 0, vm = 0;
+  for (size_t i = tid; i < n; i += nth) {
+    double x = sqrt(abs2(B.nun[i] - B.nu[i])), y = sqrt(abs2(B.nun[i]));
+    dm = x > dm ? x : dm;
+    vm = y > vm ? y : vm;
+  }
+  B.red[2 + 2 * tid] = dm;
+  B.red[3 + 2 * tid] = vm;
+  ADJ_SYNC();
+  if (tid == 0) {
+    for (int t = 0; t < nth; t++) {
+      dm = B.red[2 + 2 * t] > dm ? B.red[2 + 2 * t] : dm;
+      vm = B.red[3 + 2 * t] > vm ? B.red[3 + 2 * t] : vm;
+    }
+    B.red[0] = dm;
+    B.red[1] = vm;
+  }
+  ADJ_SYNC();
+}
+
+// dJ/dU_{-1} += sum Re(conj(Sigmabar^M) dSigma^M/dU) + Hartree part ; epsbar_{-1} += epsbar (team)
+__host__ __device__ inline void madj_final_team(const Prob& P, const MadjBuf& B, double u, double nbar, double* ub,
+                                                cplx* ge0, int tid, int nth) {
+  int d = P.d, dd = d * d, nt = P.ntau;
+  double xi = P.sig;
+  const cplx* M = P.Gmat;
+  double acc = 0;
+  for (size_t i = tid; i < (size_t)(nt + 1) * dd; i += nth) {
+    int m = (int)(i / dd), e = (int)(i % dd), a = e / d, b = e % d;
+    cplx x = M[i], y = M[(size_t)(nt - m) * dd + b * d + a];
+    acc += (conj(B.Sb[i]) * ((-2.0 * xi * u) * (x * x * y))).x;
+  }
+  B.red[2 + tid] = acc;
+  ADJ_SYNC();
+  if (tid == 0) {
+    double s = 0;
+    for (int t = 0; t < nth; t++) s += B.red[2 + t];
+    for (int i = 0; i < d; i++) s += B.eb[i * d + i].x * (-M[(size_t)nt * dd + i * d + i].x - nbar);
+    ub[0] += s;
+    for (int e = 0; e < dd; e++) ge0[e] = ge0[e] + B.eb[e];
+  }
+  ADJ_SYNC();
+}
+
 // ============================================================== device kernels
 constexpr int ADJ_LDS = 4000;  // complex entries of the team kernels' LDS (64000 B)
 
@@ -1487,6 +1712,37 @@ __global__ void __launch_bounds__(ADJ_NT) k_adj_ugrad(const AdjProb* ap, int s) 
   adj_ugrad_team(A, c_kw[A.p.k], s, threadIdx.x, blockDim.x, red);
 }
 
+__global__ void __launch_bounds__(ADJ_NT) k_madj_ga(int N, int d, const cplx* Ainv, const cplx* nu, cplx* gA) {
+  madj_ga_elem(N, d, Ainv, nu, gA, (size_t)blockIdx.x * blockDim.x + threadIdx.x);
+}
+__global__ void __launch_bounds__(ADJ_NT) k_madj_kbar(Prob P, const cplx* gA, cplx* Kb) {
+  madj_kbar_elem(P, c_kw[P.k], gA, Kb, (size_t)blockIdx.x * blockDim.x + threadIdx.x);
+}
+__global__ void __launch_bounds__(ADJ_NT) k_madj_conv(Prob P, MadjBuf B) {
+  madj_conv_elem(P, c_kw[P.k], B, (size_t)blockIdx.x * blockDim.x + threadIdx.x);
+}
+__global__ void __launch_bounds__(ADJ_NT) k_madj_eig(Prob P, MadjBuf B) {
+  __shared__ cplx A[64];
+  madj_eig_team(P, B, threadIdx.x, A);
+}
+__global__ void __launch_bounds__(ADJ_NT) k_madj_eps(Prob P, MadjBuf B) {
+  __shared__ cplx red[ADJ_NT + 64];
+  madj_eps_team(P, B, threadIdx.x, blockDim.x, red);
+}
+__global__ void __launch_bounds__(ADJ_NT) k_madj_nu(Prob P, MadjBuf B, const cplx* Mbar, double u) {
+  madj_nu_elem(P, B, Mbar, u, (size_t)blockIdx.x * blockDim.x + threadIdx.x);
+}
+__global__ void __launch_bounds__(ADJ_NT) k_madj_mix(Prob P, MadjBuf B, double mix) {
+  madj_mix_elem(P, B, mix, (size_t)blockIdx.x * blockDim.x + threadIdx.x);
+}
+__global__ void __launch_bounds__(ADJ_NT) k_madj_change(Prob P, MadjBuf B) {
+  madj_change_team(P, B, threadIdx.x, blockDim.x);
+}
+__global__ void __launch_bounds__(ADJ_NT) k_madj_final(Prob P, MadjBuf B, double u, double nbar, double* ub,
+                                                       cplx* ge0) {
+  madj_final_team(P, B, u, nbar, ub, ge0, threadIdx.x, blockDim.x);
+}
+
 // ============================================================== host sequencing
 // Launches the whole backward sweep for the problems in dA (host copies in hA,
 // which share d, k and ntau): slices ntmax .. k+1, then the start-up.
@@ -1588,6 +1844,41 @@ hipError_t launch_adjoint_2b(AdjProb* dA, AdjProb* dDry, const AdjProb* hA, int 
   };
   for (int n = S.ntmax; n > k; n--) block(n, n, n > 2 * k ? n - k : 0, false);
   block(0, k, 0, true);
+  return hipGetLastError();
+}
+
+// Matsubara part of the second-Born adjoint for one problem: A is rebuilt at
+// the converged Sigma^M and inverted (Ainv, work, piv, status as for the
+// forward solve); `nit` damped iterations of the adjoint fixed point, the
+// last change written to B.red[0..1]; then dJ/dU_{-1} and dJ/deps0_{-1}.
+hipError_t launch_adjoint_mats(const Prob& P, const MadjBuf& B, cplx* K, cplx* work, int* piv, int* status,
+                               const cplx* Mbar, double u, double nbar, double* ub, cplx* ge0, int nit,
+                               double mix, hipStream_t s) {
+  int d = P.d, N = (P.ntau + 1) * d;
+  size_t nb = (size_t)(P.ntau + 1) * d * d;
+  hipError_t e;
+  if ((e = launch_free_mat(P, B.g, s))) return e;
+  if ((e = launch_mat_conv(P, B.g, P.Smat, nullptr, K, s))) return e;
+  if ((e = launch_mat_build(P, K, B.Ainv, s))) return e;
+  if ((e = launch_gj_inverse(N, B.Ainv, work, piv, status, s))) return e;
+  dim3 blk(ADJ_NT);
+  hipLaunchKernelGGL(k_madj_eig, dim3(1), blk, 0, s, P, B);
+  if ((e = hipMemcpyAsync(B.nu, Mbar, nb * sizeof(cplx), hipMemcpyDeviceToDevice, s))) return e;
+  auto rev = [&]() {
+    hipLaunchKernelGGL(k_madj_ga, dim3(adj_blocks((size_t)N * d)), blk, 0, s, N, d, (const cplx*)B.Ainv,
+                       (const cplx*)B.nu, B.gA);
+    hipLaunchKernelGGL(k_madj_kbar, dim3(adj_blocks(nb)), blk, 0, s, P, (const cplx*)B.gA, B.Kb);
+    hipLaunchKernelGGL(k_madj_conv, dim3(adj_blocks(2 * nb)), blk, 0, s, P, B);
+    hipLaunchKernelGGL(k_madj_eps, dim3(1), blk, 0, s, P, B);
+  };
+  for (int it = 0; it < nit; it++) {
+    rev();
+    hipLaunchKernelGGL(k_madj_nu, dim3(adj_blocks(nb)), blk, 0, s, P, B, Mbar, u);
+    if (it == nit - 1) hipLaunchKernelGGL(k_madj_change, dim3(1), blk, 0, s, P, B);
+    hipLaunchKernelGGL(k_madj_mix, dim3(adj_blocks(nb)), blk, 0, s, P, B, mix);
+  }
+  rev();
+  hipLaunchKernelGGL(k_madj_final, dim3(1), blk, 0, s, P, B, u, nbar, ub, ge0);
   return hipGetLastError();
 }
 

@@ -13,6 +13,48 @@ namespace cntr {
 constexpr int NT3 = 256;
 
 // ------------------------------------------------------------ free g^M
+// Cyclic Jacobi rotations on the hermitian d x d matrix A (destroyed):
+// A = V diag(x) V^dag, V unitary (one thread).
+__host__ __device__ inline void herm_jacobi(int d, cplx* A, cplx* V, double* x) {
+  for (int e = 0; e < d * d; e++) V[e] = (e / d == e % d) ? mk(1, 0) : mk(0, 0);
+  for (int sweep = 0; sweep < 60; sweep++) {
+    double off = 0, tot = 0;
+    for (int i = 0; i < d; i++)
+      for (int j = 0; j < d; j++) {
+        double v = abs2(A[i * d + j]);
+        tot += v;
+        if (i != j) off += v;
+      }
+    if (off <= 1e-32 * tot) break;
+    for (int p = 0; p < d; p++)
+      for (int q = p + 1; q < d; q++) {
+        cplx apq = A[p * d + q];
+        double gabs = sqrt(abs2(apq));
+        if (gabs == 0) continue;
+        cplx ph = mk(apq.x / gabs, apq.y / gabs);
+        double th = (A[q * d + q].x - A[p * d + p].x) / (2 * gabs);
+        double t = (th >= 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(1 + th * th));
+        double cs = 1 / sqrt(1 + t * t), sn = t * cs;
+        for (int i = 0; i < d; i++) {
+          cplx aip = A[i * d + p], aiq = A[i * d + q];
+          A[i * d + p] = cs * aip - sn * (conj(ph) * aiq);
+          A[i * d + q] = sn * (ph * aip) + cs * aiq;
+        }
+        for (int j = 0; j < d; j++) {
+          cplx apj = A[p * d + j], aqj = A[q * d + j];
+          A[p * d + j] = cs * apj - sn * (ph * aqj);
+          A[q * d + j] = sn * (conj(ph) * apj) + cs * aqj;
+        }
+        for (int i = 0; i < d; i++) {
+          cplx vip = V[i * d + p], viq = V[i * d + q];
+          V[i * d + p] = cs * vip - sn * (conj(ph) * viq);
+          V[i * d + q] = sn * (ph * vip) + cs * viq;
+        }
+      }
+  }
+  for (int i = 0; i < d; i++) x[i] = A[i * d + i].x;
+}
+
 // g(tau) = -V diag( e^{-x tau} / (1 - xi e^{-beta x}) ) V^dag for
 // eps_{-1} - mu = V diag(x) V^dag, evaluated in the overflow-free form.
 __global__ __launch_bounds__(NT3) void k_free_mat(Prob P, cplx* g) {
@@ -23,45 +65,8 @@ __global__ __launch_bounds__(NT3) void k_free_mat(Prob P, cplx* g) {
     for (int e = 0; e < dd; e++) {
       A[e] = P.eps[e];
       if (e / d == e % d) A[e].x -= P.mu;
-      V[e] = (e / d == e % d) ? mk(1, 0) : mk(0, 0);
     }
-    // cyclic Jacobi rotations on the hermitian matrix
-    for (int sweep = 0; sweep < 60; sweep++) {
-      double off = 0, tot = 0;
-      for (int i = 0; i < d; i++)
-        for (int j = 0; j < d; j++) {
-          double v = abs2(A[i * d + j]);
-          tot += v;
-          if (i != j) off += v;
-        }
-      if (off <= 1e-32 * tot) break;
-      for (int p = 0; p < d; p++)
-        for (int q = p + 1; q < d; q++) {
-          cplx apq = A[p * d + q];
-          double gabs = sqrt(abs2(apq));
-          if (gabs == 0) continue;
-          cplx ph = mk(apq.x / gabs, apq.y / gabs);
-          double th = (A[q * d + q].x - A[p * d + p].x) / (2 * gabs);
-          double t = (th >= 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(1 + th * th));
-          double cs = 1 / sqrt(1 + t * t), sn = t * cs;
-          for (int i = 0; i < d; i++) {
-            cplx aip = A[i * d + p], aiq = A[i * d + q];
-            A[i * d + p] = cs * aip - sn * (conj(ph) * aiq);
-            A[i * d + q] = sn * (ph * aip) + cs * aiq;
-          }
-          for (int j = 0; j < d; j++) {
-            cplx apj = A[p * d + j], aqj = A[q * d + j];
-            A[p * d + j] = cs * apj - sn * (ph * aqj);
-            A[q * d + j] = sn * (conj(ph) * apj) + cs * aqj;
-          }
-          for (int i = 0; i < d; i++) {
-            cplx vip = V[i * d + p], viq = V[i * d + q];
-            V[i * d + p] = cs * vip - sn * (conj(ph) * viq);
-            V[i * d + q] = sn * (ph * vip) + cs * viq;
-          }
-        }
-    }
-    for (int i = 0; i < d; i++) x[i] = A[i * d + i].x;
+    herm_jacobi(d, A, V, x);
   }
   __syncthreads();
   double xi = P.sig, beta = P.beta;

@@ -198,7 +198,8 @@ def gpu_gradients_2b(g, e0, U, C, niter=16):
 @pytest.mark.parametrize("d,nt,ntau", [(2, 14, 12), (1, 17, 13), (3, 12, 12)])
 def test_adjoint_2b_matches_oracle_differences(O, d, nt, ntau):
     """Gradients of J = Re <C, G> of the self-consistent 2B + Hartree solution
-    with respect to eps0_n and U_n (n >= 0; M does not depend on them)."""
+    with respect to eps0_n and U_n, n = -1..nt (n = -1 enters through the
+    Matsubara solve; eps0 directions hermitian, as the solution assumes)."""
     say(f"adjoint 2B d={d} nt={nt} ntau={ntau}")
     g, r, e0, U, C = setup_2b(O, d, nt, ntau, 1)
     ge, ub, conv = gpu_gradients_2b(g, e0, U, C)
@@ -211,6 +212,14 @@ def test_adjoint_2b_matches_oracle_differences(O, d, nt, ntau):
     dU = r.normal(size=U.shape)
     dU[0] = 0.0
     cases["U"] = (np.zeros_like(e0), dU)
+    x = np.zeros_like(U)
+    x[0] = 1.0
+    cases["U[-1]"] = (np.zeros_like(e0), x)
+    y = np.zeros_like(e0)
+    y[0] = W.random_hermitian(r, d, 1.0)
+    cases["eps0[-1]"] = (y, np.zeros_like(U))
+    y = np.array([W.random_hermitian(r, d, 1.0) for _ in range(nt + 2)])
+    cases["all"] = (y, r.normal(size=U.shape))
     for n in (g.k, nt):
         x = np.zeros_like(U)
         x[n + 1] = 1.0
