@@ -61,3 +61,29 @@ def test_shape_and_order_errors():
     assert L.cntr_dyson_step(6, 2, g2, gf2, gf2, eps2, None) == -2
     assert L.cntr_convolution(-2, 1, g, gf, gf, gf, gf, gf, None, None) == -3
     assert L.cntr_extrapolate(2, 1, g, gf, None) == -3
+
+
+def test_adjoint_sweep_validation():
+    """cntr_adjoint_sweep rejects bad arguments on the host, before any
+    device work: null contour pointers, missing eps_bar, and the second-Born
+    mode without its Sigmabar / U_bar accumulators."""
+    L = _abi.lib()
+    g = (_abi.Grid * 1)(_grid())
+    gf = (_abi.GF * 1)(_abi.GF(1, 1, 1, 1))
+    nul = (_abi.GF * 1)(_abi.GF(1, None, 1, 1))
+    p1 = (C.c_void_p * 1)(1)
+    pn = (C.c_void_p * 1)(None)
+    conv = C.c_double(0.0)
+    args = lambda G=gf, S=gf, Gb=gf, Sb=None, U=None, Ub=None, eb=p1, n=1, gr=g: (
+        n, gr, G, S, p1, U, 0.5, Gb, Sb, eb, Ub, 4, C.byref(conv), None)
+    assert L.cntr_adjoint_sweep(*args(G=nul)) == -2
+    assert L.cntr_adjoint_sweep(*args(Gb=nul)) == -2
+    assert L.cntr_adjoint_sweep(*args(eb=pn)) == -2
+    assert "eps_bar" in L.cntr_last_error().decode()
+    assert L.cntr_adjoint_sweep(*args(U=p1)) == -2           # second-Born mode needs Sigmabar, U_bar
+    assert "second-Born" in L.cntr_last_error().decode()
+    assert L.cntr_adjoint_sweep(*args(U=p1, Sb=gf)) == -2
+    assert L.cntr_adjoint_sweep(*args(U=p1, Sb=nul, Ub=p1)) == -2
+    assert L.cntr_adjoint_sweep(*args(n=0)) == -2
+    bad = (_abi.Grid * 1)(_grid(k=7))
+    assert L.cntr_adjoint_sweep(*args(gr=bad)) == -1
