@@ -218,7 +218,7 @@ cntr_status cntr_solve_2b(const cntr_grid* grid, const cntr_gf* G, const cntr_gf
  *   and Hartree, iterated `niter` times per slice (the start-up block of
  *   slices 0..k together); the Matsubara solve (Eq. Gmat_dyson_integ, its
  *   operator rebuilt and inverted at the converged Sigma^M) is reversed
- *   likewise, with 200 damped iterations (weight 1/2, as the forward loop).
+ *   likewise, with 150 damped iterations (weight 1/2, as the forward loop).
  *   eps_bar += dJ/deps0_n and U_bar += dJ/dU_n for n = -1..nt (eps0_{-1}
  *   through a hermitian eigen-decomposition: its gradient is exact along
  *   hermitian directions). Gbar.mat returns dJ/dM with M held fixed (the

@@ -63,6 +63,15 @@ struct AdjProb {
 
 constexpr int ADJ_NT = 256;  // threads per workgroup of every adjoint kernel
 
+// row s of the triangle index t = tri(s) + j, 0 <= j <= s (closed form, then
+// corrected for the rounding of the square root)
+__host__ __device__ inline int tri_row(size_t t) {
+  int s = (int)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+  while (tri(s) > t) s--;
+  while (tri(s + 1) <= t) s++;
+  return s;
+}
+
 __host__ __device__ inline size_t oR(int a, int b) { return tri(a) + b; }  // R_{a,b}, a >= b
 __host__ __device__ inline size_t oL(int a, int b) { return tri(b) + a; }  // L_{a,b}, a <= b
 __host__ __device__ inline size_t oT(int n, int m, int ntau) { return (size_t)n * (ntau + 1) + m; }
@@ -508,8 +517,7 @@ __host__ __device__ inline void adj_lcol_elem(const AdjProb& Ap, const KW& W, in
     //   a in rows:         i h w_{n,b} gq_a Rt(G, n, b)
     //   b in rows, a < b:  i h w_{n,a} Rt(G, n, a)^H gq_b^H
     size_t t = tri(G.bs0) + (idx - G.o4) / dd;
-    int b = 0;
-    while (tri(b + 1) <= t) b++;
+    int b = tri_row(t);
     int a = (int)(t - tri(b));
     cplx v = mk(0, 0);
     if (a >= G.r0 && a <= G.r1) {
@@ -622,8 +630,7 @@ __host__ __device__ inline void adj_hist_elem(const AdjProb& Ap, const KW& W, in
   bool lb = n > 2 * k;
   if (idx < G.oR) {
     size_t t = (idx - G.oL) / dd;
-    int b = 0;
-    while (tri(b + 1) <= t) b++;
+    int b = tri_row(t);
     int a = (int)(t - tri(b));
     cplx v = mk(0, 0);
     if (a < nb) {
@@ -645,8 +652,7 @@ __host__ __device__ inline void adj_hist_elem(const AdjProb& Ap, const KW& W, in
     V.aL(a, b)[e] = V.aL(a, b)[e] + v;
   } else if (idx < G.oT) {
     size_t t = (idx - G.oR) / dd;
-    int a = 0;
-    while (tri(a + 1) <= t) a++;
+    int a = tri_row(t);
     int b = (int)(t - tri(a));
     cplx v = mk(0, 0);
     if (lb && a < nb) {
@@ -789,13 +795,14 @@ __host__ __device__ inline cplx* sig_out(const AdjView& V, int n, int ob) {
 //   sT(p, a) += sum coef gc_m M_b^H,   aM(b) += sum coef Sigma^rceil_{p,a}^H gc_m
 // over the terms (m, a, b, coef) of the forward rule. Outputs: ntau+1 blocks
 // of sT (if formed) then ntau+1 blocks of aM.
+// (with_m = false: the Sigma^rceil part only, for trial steps)
 __host__ __device__ inline void adj_tau_elem(const AdjProb& Ap, const KW& W, int p, const cplx* src,
-                                             size_t idx) {
+                                             size_t idx, bool with_m = true) {
   AdjView V(Ap, W);
   int d = V.d, dd = V.dd, k = V.k, nt = V.ntau;
   double ht = V.ht, xi = V.xi;
   bool sig = Ap.sT != nullptr;
-  size_t nout = (size_t)(sig ? 2 : 1) * (nt + 1) * dd;
+  size_t nout = (size_t)((sig ? 1 : 0) + (with_m ? 1 : 0)) * (nt + 1) * dd;
   if (idx >= nout) return;
   int e = (int)(idx % dd), r = e / d, c = e % d;
   int ob = (int)(idx / dd);
@@ -1607,12 +1614,12 @@ __global__ void __launch_bounds__(ADJ_NT) k_adj_sigma(const AdjProb* ap, int n) 
         o[e] = o[e] + v;
       });
 }
-__global__ void __launch_bounds__(ADJ_NT) k_adj_tau(const AdjProb* ap, int p, int srcsel) {
+__global__ void __launch_bounds__(ADJ_NT) k_adj_tau(const AdjProb* ap, int p, int srcsel, int with_m) {
   const AdjProb& A = ap[blockIdx.y];
   if (p > A.p.nt) return;
   AdjView V(A, c_kw[A.p.k]);
   const cplx* src = srcsel == 0 ? V.scr(V.lay.rhoT) : V.scr(V.lay.psi) + (size_t)(p - 1) * (V.ntau + 1) * V.dd;
-  adj_tau_elem(A, c_kw[A.p.k], p, src, (size_t)blockIdx.x * blockDim.x + threadIdx.x);
+  adj_tau_elem(A, c_kw[A.p.k], p, src, (size_t)blockIdx.x * blockDim.x + threadIdx.x, with_m != 0);
 }
 __global__ void __launch_bounds__(ADJ_NT) k_adj_rbound(const AdjProb* ap, int n) {
   __shared__ cplx lds[ADJ_LDS];
@@ -1767,8 +1774,11 @@ void adj_step_launch(const AdjProb* dA, const AdjShape& S, int n, bool hist, hip
     hipLaunchKernelGGL(k_adj_hist, dim3(adj_blocks(hg.total), S.count), blk, 0, s, dA, n);
   }
   if (S.sig) hipLaunchKernelGGL(k_adj_sigma, dim3(sig_geom(n, k, ntau).total, S.count), blk, 0, s, dA, n);
-  hipLaunchKernelGGL(k_adj_tau, dim3(adj_blocks((size_t)(S.sig ? 2 : 1) * (ntau + 1) * dd), S.count), blk, 0, s,
-                     dA, n, 0);
+  // (a trial step, hist = false, needs no M adjoint)
+  int nto = (S.sig ? 1 : 0) + (hist ? 1 : 0);
+  if (nto)
+    hipLaunchKernelGGL(k_adj_tau, dim3(adj_blocks((size_t)nto * (ntau + 1) * dd), S.count), blk, 0, s, dA, n, 0,
+                       hist ? 1 : 0);
   hipLaunchKernelGGL(k_adj_rbound, dim3(1, S.count), blk, 0, s, dA, n);
 }
 
@@ -1787,7 +1797,7 @@ void adj_start_launch(const AdjProb* dA, const AdjShape& S, hipStream_t s) {
   hipLaunchKernelGGL(k_adj_tp, dim3(k * (k + 1), S.count), blk, 0, s, dA);
   for (int p = 1; p <= k; p++)
     hipLaunchKernelGGL(k_adj_tau, dim3(adj_blocks((size_t)(S.sig ? 2 : 1) * (ntau + 1) * dd), S.count), blk, 0,
-                       s, dA, p, 1);
+                       s, dA, p, 1, 1);
   hipLaunchKernelGGL(k_adj_rstart, dim3(1, S.count), blk, 0, s, dA);
 }
 

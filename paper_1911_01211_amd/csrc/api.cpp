@@ -675,7 +675,7 @@ cntr_status cntr_adjoint_sweep(int32_t count, const cntr_grid* grids, const cntr
       if (e == hipSuccess) e = hipStreamSynchronize(s);
       if (e == hipSuccess)
         e = launch_adjoint_mats(hA[i].p, B, ms.K, ms.work, ms.piv, ms.status, (const cplx*)Gbar[i].mat, u, nbar,
-                                U_bar[i], (cplx*)eps_bar[i], 200, 0.5, s);
+                                U_bar[i], (cplx*)eps_bar[i], 150, 0.5, s);
       if (e == hipSuccess) e = hipMemcpyAsync(red, B.red, sizeof red, hipMemcpyDeviceToHost, s);
       if (e == hipSuccess) e = hipMemcpyAsync(&stat, ms.status, sizeof(int), hipMemcpyDeviceToHost, s);
       if (e == hipSuccess) e = hipStreamSynchronize(s);
