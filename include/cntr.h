@@ -249,6 +249,23 @@ cntr_status cntr_adjoint_sweep(int32_t count, const cntr_grid* grids, const cntr
                                const cntr_gf* Gbar, const cntr_gf* Sigmabar, void* const* eps_bar,
                                double* const* U_bar, int32_t niter, double* conv, void* stream);
 
+/* ----------------------------------------------------------------- A11 --
+ * The same self-consistent second-Born + Hartree propagation for `count`
+ * independent problems that share d, k and ntau (nt, beta, h, mu, eps0 and U
+ * may differ): each problem's Matsubara loop runs on its own (it has its own
+ * dense solve); the bootstrap and the time steps advance every problem in one
+ * launch per kernel, each problem up to its own nt (problems whose nt is
+ * reached drop out of the later launches). Loop controls as cntr_solve_2b;
+ * the bootstrap tolerance applies to the largest relative distance of the
+ * batch. Arrays of `count` descriptors / DEVICE pointers; stats (HOST, may be
+ * NULL): largest Matsubara iteration count, bootstrap iterations, largest
+ * last Matsubara error, last bootstrap error. Synchronizes `stream`. */
+cntr_status cntr_solve_2b_batch(int32_t count, const cntr_grid* grids, const cntr_gf* G, const cntr_gf* Sigma,
+                                const cntr_gf* Gscratch, const void* const* eps0, const double* const* U,
+                                void* const* eps_mf, double nbar, int32_t mats_maxit, double mats_tol,
+                                double mats_mix, int32_t boot_maxit, double boot_tol, int32_t ncorr,
+                                double* stats, void* stream);
+
 /* ------------------------------------------------------------ profiling --
  * Device-time accounting of the time step, measured with HIP events
  * recorded on the stream each kernel is launched on. Between

@@ -18,7 +18,8 @@ STATUS = {0: "CNTR_OK", -1: "CNTR_EINVAL", -2: "CNTR_ESHAPE", -3: "CNTR_EORDER",
 SYMBOLS = ["cntr_init_matsubara", "cntr_dyson_step", "cntr_convolution", "cntr_sigma_2b",
            "cntr_extrapolate", "cntr_distance", "cntr_copy_slice", "cntr_solve_2b", "cntr_sync",
            "cntr_last_error", "cntr_finalize", "cntr_version", "cntr_profile_begin",
-           "cntr_profile_end", "cntr_observables", "cntr_sigma_local", "cntr_adjoint_sweep"]
+           "cntr_profile_end", "cntr_observables", "cntr_sigma_local", "cntr_adjoint_sweep",
+           "cntr_solve_2b_batch"]
 
 
 class CntrError(RuntimeError):
@@ -65,6 +66,8 @@ def lib():
         L.cntr_sigma_local.argtypes = [i32, i32, P(Grid), P(GF), P(GF), dbl, vp]
         L.cntr_adjoint_sweep.argtypes = [i32, P(Grid), P(GF), P(GF), P(vp), P(vp), dbl, P(GF), P(GF), P(vp),
                                          P(vp), i32, P(dbl), vp]
+        L.cntr_solve_2b_batch.argtypes = [i32, P(Grid), P(GF), P(GF), P(GF), P(vp), P(vp), P(vp), dbl, i32, dbl,
+                                          dbl, i32, dbl, i32, P(dbl), vp]
         L.cntr_sync.argtypes = [vp]
         L.cntr_profile_begin.argtypes = []
         L.cntr_profile_end.argtypes = [P(Profile)]

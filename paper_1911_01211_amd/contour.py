@@ -254,3 +254,29 @@ def solve_2b(G: Contour, Sigma: Contour, Gscratch: Contour, eps0: torch.Tensor, 
                                         boot_maxit,
                                         boot_tol, ncorr, nt_stop, st, _stream(stream)))
     return Solve2BStats(int(st[0]), int(st[1]), st[2], st[3])
+
+
+def solve_2b_batch(G: list, Sigma: list, Gscratch: list, eps0: list, U: list, eps_mf: list, nbar=0.5,
+                   mats_maxit=200, mats_tol=1e-14, mats_mix=0.5, boot_maxit=100, boot_tol=1e-14, ncorr=6,
+                   stream=None) -> Solve2BStats:
+    """Self-consistent 2B + Hartree for problems sharing d, k and ntau
+    (cntr_solve_2b_batch): one launch per kernel and step for the batch."""
+    st = (C.c_double * 4)()
+    _abi.check(_abi.lib().cntr_solve_2b_batch(len(G), _grids(G), _gfs(G), _gfs(Sigma), _gfs(Gscratch), _ptrs(eps0),
+                                              _ptrs(U), _ptrs(eps_mf), nbar, mats_maxit, mats_tol, mats_mix,
+                                              boot_maxit, boot_tol, ncorr, st, _stream(stream)))
+    return Solve2BStats(int(st[0]), int(st[1]), st[2], st[3])
+
+
+def solve_uneven(problems: list, **kw) -> dict:
+    """An uneven set of second-Born problems (dicts with G, Sigma, Gscratch,
+    eps0, U, eps_mf; any d and nt): one batched solve per orbital count d.
+    Returns the stats per d."""
+    by_d = {}
+    for p in problems:
+        by_d.setdefault(p["G"].g.d, []).append(p)
+    out = {}
+    for d, ps in sorted(by_d.items()):
+        out[d] = solve_2b_batch([p["G"] for p in ps], [p["Sigma"] for p in ps], [p["Gscratch"] for p in ps],
+                                [p["eps0"] for p in ps], [p["U"] for p in ps], [p["eps_mf"] for p in ps], **kw)
+    return out

@@ -305,6 +305,58 @@ cntr_status mats_solve(MatsState& st, const Prob& P, bool use_guess, double tol,
   return fail(CNTR_ENOCONV, "Matsubara refinement did not reach its tolerance");
 }
 
+// Matsubara loop of the second-Born run of one problem (P, with its scratch
+// copy in po): {Hartree + Sigma_2B on slice -1, mixing of that input with the
+// previous one, Matsubara solve} until the relative distance of G^M is below
+// tol (at most maxit). G^M starts as the free function of eps0_{-1}.
+cntr_status mats_loop_2b(const cntr_grid& g, const Prob& P, const ProbArg& pa, const ProbArg& po,
+                         StreamScratch* sc, double nbar, int maxit, double tol, double mix, hipStream_t s,
+                         int* iters, double* err_out) {
+  int d = g.d;
+  hipError_t e;
+  cntr_status st;
+  MatsState ms;
+  if ((st = ms.alloc(g.ntau, d))) return st;
+  Prob P0 = P;
+  P0.eps = P.eps0;
+  int it = 0;
+  double err = 0, dist[2];
+  if ((e = launch_free_mat(P0, P.Gmat, s))) {
+    ms.release();
+    return hip_fail(e, "initial G^M");
+  }
+  for (it = 0; it < maxit; it++) {
+    if ((e = launch_sigma2b(pa, -1, d, (int)slice_elems(g, -1), nbar, s)) ||
+        (e = launch_mix((g.ntau + 1) * d * d, P.Smat, ms.smix, mix, it == 0, s)) ||
+        (e = launch_mix(d * d, P.eps_mf, ms.emix, mix, it == 0, s)) ||
+        (e = launch_copy(po, pa, -1, d, (int)slice_elems(g, -1), s))) {
+      ms.release();
+      return hip_fail(e, "Matsubara loop");
+    }
+    if ((st = mats_solve(ms, P, true, 1e-15, 200, s, nullptr))) {
+      ms.release();
+      return st;
+    }
+    e = hipMemsetAsync(sc->red, 0, 2 * sizeof(double), s);
+    if (!e) e = launch_distance(pa, po, -1, d, (int)slice_elems(g, -1), sc->red, s);
+    if (!e) e = hipMemcpyAsync(dist, sc->red, 2 * sizeof(double), hipMemcpyDeviceToHost, s);
+    if (!e) e = hipStreamSynchronize(s);
+    if (e) {
+      ms.release();
+      return hip_fail(e, "distance");
+    }
+    err = dist[0] / dist[1];
+    if (err < tol) {
+      it++;
+      break;
+    }
+  }
+  ms.release();
+  *iters = it;
+  *err_out = err;
+  return CNTR_OK;
+}
+
 }  // namespace
 }  // namespace cntr
 
@@ -821,34 +873,14 @@ cntr_status cntr_solve_2b(const cntr_grid* grid, const cntr_gf* G, const cntr_gf
     return ee ? hip_fail(ee, "distance") : CNTR_OK;
   };
   // Matsubara self-consistency. Initial G^M: free function of eps0_{-1}.
-  MatsState ms;
-  if ((st = ms.alloc(g.ntau, d))) return st;
-  Prob P0 = P;
-  P0.eps = (const cplx*)eps0;
-  if ((e = launch_free_mat(P0, P.Gmat, s))) return hip_fail(e, "initial G^M");
+  if (!(mats_mix > 0 && mats_mix <= 1)) return fail(CNTR_EINVAL, "cntr_solve_2b: mats_mix outside (0,1]");
   int it = 0;
   double err = 0;
-  if (!(mats_mix > 0 && mats_mix <= 1)) return fail(CNTR_EINVAL, "cntr_solve_2b: mats_mix outside (0,1]");
-  for (it = 0; it < mats_maxit; it++) {
-    if ((e = launch_sigma2b(pa, -1, d, (int)slice_elems(g, -1), nbar, s))) return hip_fail(e, "Sigma^M");
-    // mix the new input (Sigma^M, eps_mf_{-1}) with the previous one
-    if ((e = launch_mix((g.ntau + 1) * d * d, P.Smat, ms.smix, mats_mix, it == 0, s)) ||
-        (e = launch_mix(d * d, (cplx*)eps_mf, ms.emix, mats_mix, it == 0, s)))
-      return hip_fail(e, "mixing");
-    if ((e = launch_copy(po, pa, -1, d, (int)slice_elems(g, -1), s))) return hip_fail(e, "copy");
-    if ((st = mats_solve(ms, P, true, 1e-15, 200, s, nullptr))) return st;
-    if ((st = distance(-1, dist))) return st;
-    err = dist[0] / dist[1];
-    if (err < mats_tol) {
-      it++;
-      break;
-    }
-  }
+  if ((st = mats_loop_2b(g, P, pa, po, sc, nbar, mats_maxit, mats_tol, mats_mix, s, &it, &err))) return st;
   if (stats) {
     stats[0] = it;
     stats[2] = err;
   }
-  ms.release();
   // bootstrap over slices 0..k
   for (it = 0; it < boot_maxit; it++) {
     for (int n = 0; n <= k; n++)
@@ -882,6 +914,101 @@ cntr_status cntr_solve_2b(const cntr_grid* grid, const cntr_gf* G, const cntr_gf
   }
   for (int n = k + 1; n <= nt_stop; n++)
     if ((e = launch_sigma2b(pa, n, d, (int)slice_elems(g, n), nbar, s))) return hip_fail(e, "Sigma");
+  return CNTR_OK;
+}
+
+cntr_status cntr_solve_2b_batch(int32_t count, const cntr_grid* grids, const cntr_gf* G, const cntr_gf* Sigma,
+                                const cntr_gf* Gscratch, const void* const* eps0, const double* const* U,
+                                void* const* eps_mf, double nbar, int32_t mats_maxit, double mats_tol,
+                                double mats_mix, int32_t boot_maxit, double boot_tol, int32_t ncorr,
+                                double* stats, void* stream) {
+  cntr_status st = check_batch(count, grids, "cntr_solve_2b_batch");
+  if (st) return st;
+  if (!gf_ok(G, count) || !gf_ok(Sigma, count) || !gf_ok(Gscratch, count) || !eps0 || !U || !eps_mf)
+    return fail(CNTR_ESHAPE, "cntr_solve_2b_batch: null pointer");
+  for (int i = 0; i < count; i++)
+    if (!eps0[i] || !U[i] || !eps_mf[i]) return fail(CNTR_ESHAPE, "cntr_solve_2b_batch: null eps0, U or eps_mf");
+  if (!(mats_mix > 0 && mats_mix <= 1)) return fail(CNTR_EINVAL, "cntr_solve_2b_batch: mats_mix outside (0,1]");
+  if ((st = ensure_weights())) return st;
+  hipStream_t s = (hipStream_t)stream;
+  int k = grids[0].k, d = grids[0].d, ntmax = 0;
+  for (int i = 0; i < count; i++) ntmax = grids[i].nt > ntmax ? grids[i].nt : ntmax;
+  cntr_grid gmax = grids[0];
+  gmax.nt = ntmax < k + 1 ? k + 1 : ntmax;
+  StreamScratch* sc = scratch_for(s);
+  StepScratch lay = step_layout(gmax);
+  if ((st = grow(s, sc, lay.per * count, 5 * (size_t)count, 2 * (size_t)count))) return st;
+  Scratch scr = lay.sc;
+  scr.base = sc->buf;
+  std::vector<Prob> v(count), vo(count);
+  for (int i = 0; i < count; i++) {
+    v[i] = make_prob(grids[i], &G[i], &Sigma[i], eps_mf[i]);
+    v[i].U = U[i];
+    v[i].eps0 = (const cplx*)eps0[i];
+    v[i].eps_mf = (cplx*)eps_mf[i];
+    vo[i] = make_prob(grids[i], &Gscratch[i], nullptr, nullptr);
+  }
+  // Matsubara loops one problem at a time (each has its own dense solve)
+  int itmax = 0;
+  double errmax = 0;
+  for (int i = 0; i < count; i++) {
+    ProbArg p1{v[i], nullptr, 1}, o1{vo[i], nullptr, 1};
+    int it = 0;
+    double err = 0;
+    if ((st = mats_loop_2b(grids[i], v[i], p1, o1, sc, nbar, mats_maxit, mats_tol, mats_mix, s, &it, &err)))
+      return st;
+    itmax = it > itmax ? it : itmax;
+    errmax = err > errmax ? err : errmax;
+  }
+  if (stats) {
+    stats[0] = itmax;
+    stats[2] = errmax;
+  }
+  // bootstrap and time steps: one launch per kernel for the whole batch
+  ProbArg pa, po;
+  if ((st = make_arg(s, sc, v, 0, &pa)) || (st = make_arg(s, sc, vo, 1, &po))) return st;
+  hipError_t e;
+  std::vector<double> dist(2 * (size_t)count);
+  int it;
+  double err = 0;
+  for (it = 0; it < boot_maxit; it++) {
+    for (int n = 0; n <= k; n++)
+      if ((e = launch_sigma2b(pa, n, d, (int)slice_elems(gmax, n), nbar, s))) return hip_fail(e, "Sigma start");
+    for (int n = 0; n <= k; n++)
+      if ((e = launch_copy(po, pa, n, d, (int)slice_elems(gmax, n), s))) return hip_fail(e, "copy");
+    if ((e = launch_start(pa, scr, d, gmax.ntau, s))) return hip_fail(e, "start-up");
+    std::vector<double> num(count, 0.0), den(count, 0.0);
+    for (int n = 0; n <= k; n++) {
+      e = hipMemsetAsync(sc->red, 0, 2 * (size_t)count * sizeof(double), s);
+      if (!e) e = launch_distance(pa, po, n, d, (int)slice_elems(gmax, n), sc->red, s);
+      if (!e) e = hipMemcpyAsync(dist.data(), sc->red, 2 * (size_t)count * sizeof(double), hipMemcpyDeviceToHost, s);
+      if (!e) e = hipStreamSynchronize(s);
+      if (e) return hip_fail(e, "distance");
+      for (int i = 0; i < count; i++) {
+        num[i] += dist[2 * i];
+        den[i] += dist[2 * i + 1];
+      }
+    }
+    err = 0;
+    for (int i = 0; i < count; i++) err = std::max(err, num[i] / den[i]);
+    if (err < boot_tol && it > 2) {
+      it++;
+      break;
+    }
+  }
+  if (stats) {
+    stats[1] = it;
+    stats[3] = err;
+  }
+  for (int n = k + 1; n <= ntmax; n++) {
+    if ((e = launch_extrapolate(pa, n - 1, d, (int)slice_elems(gmax, n), s))) return hip_fail(e, "extrapolate");
+    for (int c = 0; c < ncorr; c++) {
+      if ((e = launch_sigma2b(pa, n, d, (int)slice_elems(gmax, n), nbar, s))) return hip_fail(e, "Sigma");
+      if ((e = launch_step(pa, scr, n, d, s))) return hip_fail(e, "step");
+    }
+  }
+  for (int n = k + 1; n <= ntmax; n++)
+    if ((e = launch_sigma2b(pa, n, d, (int)slice_elems(gmax, n), nbar, s))) return hip_fail(e, "Sigma");
   return CNTR_OK;
 }
 

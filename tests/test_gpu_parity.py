@@ -421,3 +421,34 @@ def test_batch_matches_single_instances(O, nb, d):
         K.sync()
         for key in K.KEYS:
             assert np.array_equal(G.numpy()[key], Gs.numpy()[key]), key
+
+
+def test_uneven_2b_batch(O):
+    """Uneven batch (cntr_solve_2b_batch through contour.solve_uneven):
+    second-Born problems with d in {1, 2, 4} and different nt, a random
+    hermitian H with spectrum in [-2, 2] and a constant U in [0.5, 2] each;
+    every problem of the batch equals its own oracle solve."""
+    require_gpu()
+    specs = [(2, 20), (2, 14), (1, 24), (4, 16), (2, 17), (1, 13), (4, 12)]
+    problems, refs = [], []
+    for i, (d, nt) in enumerate(specs):
+        say(f"uneven batch problem {i}: d={d} nt={nt}")
+        g = W.GridSpec(nt=nt, ntau=24, d=d, beta=3.0, h=0.04, k=5)
+        r = W.rng(500, i)
+        H = W.haar_hermitian(r, d)
+        e0 = np.broadcast_to(H, (nt + 2, d, d)).copy()
+        U = np.full(nt + 2, r.uniform(0.5, 2.0))
+        Go, So = ora(O, g, None), ora(O, g, None)
+        rc, _, _ = O.solve_2b(Go, So, e0, U, ncorr=6, mats_tol=1e-14, boot_tol=1e-14)
+        assert rc == 0
+        refs.append((g, Go))
+        e0d = to_dev(e0)
+        problems.append(dict(G=K.Contour(g), Sigma=K.Contour(g), Gscratch=K.Contour(g), eps0=e0d,
+                             U=to_dev(U), eps_mf=torch.zeros_like(e0d)))
+    say("uneven batch: solve")
+    K.solve_uneven(problems, ncorr=6, mats_tol=1e-14, boot_tol=1e-14)
+    K.sync()
+    for (g, Go), p in zip(refs, problems):
+        got = p["G"].numpy()
+        ref = {key: getattr(Go, key) for key in K.KEYS}
+        assert_slices(g, got, ref, range(-1, g.nt + 1), what=f"uneven d={g.d} nt={g.nt}")
