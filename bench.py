@@ -130,6 +130,55 @@ def run_adjoint(g, state, args):
             "dJ_dU_sum": float(ubh.sum())}
 
 
+def run_uneven(args):
+    """Uneven batch sample: 8 second-Born problems, two each of d = 1, 2, 4, 8
+    orbitals, nt uniform in [300, 500], ntau = 300, beta = 10, h = 0.02, k = 5,
+    a random hermitian H with spectrum in [-2, 2] and a constant U uniform in
+    [0.5, 2] per problem (seeded). Timed twice on the same problems: batched
+    (one cntr_solve_2b_batch per orbital count: every problem of a group
+    advances in one launch per kernel and step) and the per-instance loop
+    (cntr_solve_2b per problem). Both include the Matsubara loops and the
+    bootstrap."""
+    import numpy as np
+    import torch
+
+    from paper_1911_01211_amd import contour as K
+    from paper_1911_01211_amd import workloads as W
+
+    dev = "cuda:0"
+    problems = []
+    for i, d in enumerate([1, 1, 2, 2, 4, 4, 8, 8]):
+        r = W.rng(700, i)
+        nt = int(r.integers(300, 501))
+        g = W.GridSpec(nt=nt, ntau=300, d=d, sig=-1, k=5, beta=10.0, h=0.02, mu=0.0)
+        H = W.haar_hermitian(r, d)
+        e0 = torch.as_tensor(np.broadcast_to(H, (nt + 2, d, d)).copy()).to(dev)
+        U = torch.full((nt + 2,), float(r.uniform(0.5, 2.0)), dtype=torch.float64, device=dev)
+        problems.append(dict(G=K.Contour(g, dev), Sigma=K.Contour(g, dev), Gscratch=K.Contour(g, dev), eps0=e0,
+                             U=U, eps_mf=torch.zeros_like(e0)))
+    slices = sum(p["G"].g.nt - p["G"].g.k for p in problems)
+    opts = dict(ncorr=args.ncorr, mats_tol=1e-14, boot_tol=1e-14)
+    times = {}
+    for mode in ("batched", "loop"):
+        for p in problems:
+            p["G"].zero_()
+            p["Sigma"].zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        if mode == "batched":
+            K.solve_uneven(problems, **opts)
+        else:
+            for p in problems:
+                K.solve_2b(p["G"], p["Sigma"], p["Gscratch"], p["eps0"], p["U"], p["eps_mf"], **opts)
+        torch.cuda.synchronize()
+        times[mode] = time.perf_counter() - t0
+    return {"workload": "8 second-Born problems, d = 1, 1, 2, 2, 4, 4, 8, 8, nt in [300, 500], ntau = 300, "
+                        "beta = 10, random H (spectrum [-2, 2]), U in [0.5, 2]; whole solves",
+            "value": slices / times["batched"], "unit": "instance time-steps/s",
+            "per_instance_loop": slices / times["loop"], "speedup_vs_loop": times["loop"] / times["batched"],
+            "seconds": times, "corrector_iterations": args.ncorr}
+
+
 def run_kpoints(args):
     """Batched sample: the single-band lattice with 512 k-points, eps_k(t) =
     -2 cos(k - A(t)) with the pulse A(t), local self-energy Sigma = 0.25 G_loc,
@@ -262,6 +311,7 @@ def main():
     ap.add_argument("--kp-steps", type=int, default=300, help="last slice of the batched sample")
     ap.add_argument("--no-kpoints", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-uneven", action="store_true")
     ap.add_argument("--adj-niter", type=int, default=16, help="adjoint fixed-point iterations per slice")
     ap.add_argument("--profile-step", type=int, default=0,
                     help="only run the time step at this slice (counter runs), then a 1 GiB copy")
@@ -310,6 +360,8 @@ def main():
     if not args.no_adjoint:
         out["adjoint"] = run_adjoint(g, state, args)
     del state
+    if not args.no_uneven:
+        out["uneven"] = run_uneven(args)
     if not args.no_kpoints:
         out["batched"] = run_kpoints(args)
     if not args.no_cpu_baseline:
