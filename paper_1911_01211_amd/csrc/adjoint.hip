@@ -89,7 +89,7 @@ __host__ __device__ inline double adj_w(const KW& W, int N, int j) {
 
 // scratch layout of one problem, in complex units
 struct AdjLayout {
-  size_t mrinv, rhoB, rhoL, rhoT, rhoR, part, binv, psi, pst, total;
+  size_t mrinv, rhoB, rhoL, rhoT, rhoR, part, binv, psi, pst, ainv, cbinv, total;
   int cb, npart;
 };
 __host__ __device__ inline int adj_cb(int dd) { return dd >= ADJ_NT ? 1 : ADJ_NT / dd; }
@@ -108,6 +108,8 @@ __host__ __device__ inline AdjLayout adj_layout(int nt, int ntau, int d, int k) 
   L.binv = o; o += (size_t)k * d * k * d;
   L.psi = o; o += (size_t)k * (ntau + 1) * dd;
   L.pst = o; o += (size_t)k * (k + 1) * dd;
+  L.ainv = o; o += (size_t)(k + 1) * dd;
+  L.cbinv = o; o += (size_t)k * d * k * d;
   L.total = o;
   return L;
 }
@@ -289,33 +291,15 @@ __host__ __device__ inline bool adj_lcol_team(const AdjProb& Ap, const KW& W, in
   cplx* rhoB = V.scr(V.lay.rhoB);
   bool bulk = n > 2 * k;
   int r0 = bulk ? n - k : 0;  // first row held in acc
-  // M_R^{-1} of slice n for the bulk kernels
-  if (n > k) {
-    for (int e = tid; e < dd; e += nth) {
-      int r = e / d, c = e % d;
-      cplx v = mul_i((h * adj_w(W, n, n)) * V.SR(n, n)[e]) + mul_i(V.eh(n, r, c));
-      if (r == c) v.x += W.a[0] / h;
-      Am[e] = v;
-    }
-    ADJ_SYNC();
-    ok = team_inverse(d, Am, piv, tid, nth) && ok;
-    for (int e = tid; e < dd; e += nth) V.scr(V.lay.mrinv)[e] = Am[e];
-    ADJ_SYNC();
-  }
   for (int e = tid; e < (n - r0 + 1) * dd; e += nth) acc[e] = V.aL(r0 + e / dd, n)[e % dd];
   ADJ_SYNC();
   // serial steps (A), rows m = n .. mlo in reverse order
   int mlo = bulk ? n - k : k + 1;
   for (int m = n; m >= mlo && n > k; m--) {
-    // A_m = h^-1 a_0 + i e_m + i h w_{m,m} Sigma^R_{m,m}; rho = A_m^{-H} lambda_m
-    for (int e = tid; e < dd; e += nth) {
-      int r = e / d, c = e % d;
-      cplx v = mul_i((h * adj_w(W, m, m)) * V.SR(m, m)[e]) + mul_i(V.eh(m, r, c));
-      if (r == c) v.x += W.a[0] / h;
-      Am[e] = v;
-    }
+    // A_m = h^-1 a_0 + i e_m + i h w_{m,m} Sigma^R_{m,m} (inverse prepared by
+    // adj_prep_team); rho = A_m^{-H} lambda_m
+    for (int e = tid; e < dd; e += nth) Am[e] = V.scr(V.lay.ainv)[(size_t)(m - mlo) * dd + e];
     ADJ_SYNC();
-    ok = team_inverse(d, Am, piv, tid, nth) && ok;
     const cplx* lm = acc + (m - r0) * dd;
     for (int e = tid; e < dd; e += nth) {
       int r = e / d, c = e % d;
@@ -352,10 +336,6 @@ __host__ __device__ inline bool adj_lcol_team(const AdjProb& Ap, const KW& W, in
   if (!bulk) {
     // start-up rows 1..k of column n (Eq. vdiff_start, y_0 = -[T_{n,0}]^dag)
     int kd = k * d;
-    for (int e = tid; e < kd * kd; e += nth) {
-      int R = e / kd, C = e % kd;
-      Bb[e] = start_block_elem(V, 1 + R / d, 1 + C / d, R % d, C % d);
-    }
     // r_p = q_p - B_{p,0} y_0
     for (int e = tid; e < kd * d; e += nth) {
       int p = 1 + e / dd, r = (e % dd) / d, c = e % d;
@@ -367,8 +347,8 @@ __host__ __device__ inline bool adj_lcol_team(const AdjProb& Ap, const KW& W, in
       rr[e] = v - t;
       lam[e] = (p <= n) ? acc[p * dd + r * d + c] : mk(0, 0);
     }
+    for (int e = tid; e < kd * kd; e += nth) Bb[e] = V.scr(V.lay.binv)[e];  // B^{-1}, adj_tinv_team
     ADJ_SYNC();
-    ok = team_inverse(kd, Bb, piv, tid, nth) && ok;
     for (int e = tid; e < kd * d; e += nth) {
       int R = e / d, c = e % d;
       cplx y = mk(0, 0), s = mk(0, 0);
@@ -794,58 +774,151 @@ __host__ __device__ inline cplx* sig_out(const AdjView& V, int n, int ob) {
 // row p (Eqs. ctv2, ctv3) for the column adjoints gc_m = i * src_m:
 //   sT(p, a) += sum coef gc_m M_b^H,   aM(b) += sum coef Sigma^rceil_{p,a}^H gc_m
 // over the terms (m, a, b, coef) of the forward rule. Outputs: ntau+1 blocks
-// of sT (if formed) then ntau+1 blocks of aM.
-// (with_m = false: the Sigma^rceil part only, for trial steps)
+// of sT (if formed) then ntau+1 blocks of aM (with_m = false: the Sigma^rceil
+// part only, for trial steps).
+// Term t of output x (the a of sT(p, a), or the b of aM(b)): sets the column
+// m, the partner block y (b, or a) and coef; false past the last term.
+__host__ __device__ inline int tau_nterms(int k, int nt, bool isM, int x) {
+  int kk = (k + 1) * (k + 1), c;
+  if (!isM) {
+    c = (x <= k ? kk : 0) + (x >= nt - k ? kk : 0);
+    int m0 = x > k + 1 ? x : k + 1;
+    c += nt - m0 + 1 > 0 ? nt - m0 + 1 : 0;
+    int m1 = x < nt - k - 1 ? x : nt - k - 1;
+    c += m1 + 1 > 0 ? m1 + 1 : 0;
+  } else {
+    c = (x >= nt - k ? kk : 0) + (x <= k ? kk : 0);
+    int m0 = nt - x > k + 1 ? nt - x : k + 1;
+    c += nt - m0 + 1 > 0 ? nt - m0 + 1 : 0;
+    int m1 = nt - x < nt - k - 1 ? nt - x : nt - k - 1;
+    c += m1 + 1 > 0 ? m1 + 1 : 0;
+  }
+  return c;
+}
+__host__ __device__ inline bool tau_term(const KW& W, int k, int nt, double ht, double xi, bool isM, int x, int t,
+                                         int& m, int& y, double& coef) {
+  int kk = (k + 1) * (k + 1);
+  if (!isM) {
+    int a = x;
+    if (a <= k) {
+      if (t < kk) {
+        m = t / (k + 1);
+        int j = t % (k + 1);
+        y = nt - j;
+        coef = ht * xi * W.R[m][j][a];
+        return true;
+      }
+      t -= kk;
+    }
+    int m0 = a > k + 1 ? a : k + 1, n2 = nt - m0 + 1 > 0 ? nt - m0 + 1 : 0;
+    if (t < n2) {
+      m = m0 + t;
+      y = nt - m + a;
+      coef = ht * xi * adj_w(W, m, m - a);
+      return true;
+    }
+    t -= n2;
+    if (a >= nt - k) {
+      if (t < kk) {
+        m = nt - k + t / (k + 1);
+        int j = t % (k + 1);
+        y = j;
+        coef = ht * W.R[nt - m][j][nt - a];
+        return true;
+      }
+      t -= kk;
+    }
+    int m1 = a < nt - k - 1 ? a : nt - k - 1;
+    if (t <= m1) {
+      m = t;
+      y = a - m;
+      coef = ht * adj_w(W, nt - m, a - m);
+      return true;
+    }
+    return false;
+  }
+  int b = x;
+  if (b >= nt - k) {
+    if (t < kk) {
+      m = t / (k + 1);
+      int l = t % (k + 1);
+      y = l;
+      coef = ht * xi * W.R[m][nt - b][l];
+      return true;
+    }
+    t -= kk;
+  }
+  int m0 = nt - b > k + 1 ? nt - b : k + 1, n2 = nt - m0 + 1 > 0 ? nt - m0 + 1 : 0;
+  if (t < n2) {
+    m = m0 + t;
+    y = m - nt + b;
+    coef = ht * xi * adj_w(W, m, nt - b);
+    return true;
+  }
+  t -= n2;
+  if (b <= k) {
+    if (t < kk) {
+      m = nt - k + t / (k + 1);
+      int l = t % (k + 1);
+      y = nt - l;
+      coef = ht * W.R[nt - m][b][l];
+      return true;
+    }
+    t -= kk;
+  }
+  int m1 = nt - b < nt - k - 1 ? nt - b : nt - k - 1;
+  if (t <= m1) {
+    m = t;
+    y = m + b;
+    coef = ht * adj_w(W, nt - m, b);
+    return true;
+  }
+  return false;
+}
+// output block ob of a launch (sT blocks first when formed), decoded
+__host__ __device__ inline bool tau_out(const AdjProb& Ap, int nt, int ob, bool with_m, bool& isM, int& x) {
+  bool sig = Ap.sT != nullptr;
+  int nout = ((sig ? 1 : 0) + (with_m ? 1 : 0)) * (nt + 1);
+  if (ob >= nout) return false;
+  isM = !sig || ob > nt;
+  x = isM ? (sig ? ob - nt - 1 : ob) : ob;
+  return true;
+}
+// contribution of term t to element (r, c) of output (isM, x)
+__host__ __device__ inline cplx tau_contrib(const AdjView& V, int p, const cplx* src, bool isM, int x, int t, int r,
+                                            int c) {
+  int m, y;
+  double coef;
+  if (!tau_term(V.W, V.k, V.ntau, V.ht, V.xi, isM, x, t, m, y, coef)) return mk(0, 0);
+  int d = V.d;
+  const cplx* g = src + (size_t)m * V.dd;  // gc_m = i g
+  cplx u;
+  if (!isM) {
+    const cplx* M = V.GM(y);
+    u = dotq(d, [&](int q) { return g[r * d + q]; }, [&](int q) { return conj(M[c * d + q]); });
+  } else {
+    const cplx* S = V.ST(p, y);
+    u = dotq(d, [&](int q) { return conj(S[q * d + r]); }, [&](int q) { return g[q * d + c]; });
+  }
+  return mul_i(coef * u);
+}
+__host__ __device__ inline cplx* tau_dst(const AdjView& V, int p, bool isM, int x) {
+  return isM ? V.aM(x) : V.sT(p, x);
+}
+// element form (one thread per output element, all terms)
 __host__ __device__ inline void adj_tau_elem(const AdjProb& Ap, const KW& W, int p, const cplx* src,
                                              size_t idx, bool with_m = true) {
   AdjView V(Ap, W);
-  int d = V.d, dd = V.dd, k = V.k, nt = V.ntau;
-  double ht = V.ht, xi = V.xi;
-  bool sig = Ap.sT != nullptr;
-  size_t nout = (size_t)((sig ? 1 : 0) + (with_m ? 1 : 0)) * (nt + 1) * dd;
-  if (idx >= nout) return;
-  int e = (int)(idx % dd), r = e / d, c = e % d;
-  int ob = (int)(idx / dd);
-  bool isM = !sig || ob > nt;
-  int x = isM ? (sig ? ob - nt - 1 : ob) : ob;
-  // gc_m = i src_m
-  auto gc = [&](int m, int rr, int cc) { return mul_i(src[(size_t)m * dd + rr * d + cc]); };
+  int dd = V.dd;
+  bool isM;
+  int x;
+  if (!tau_out(Ap, V.ntau, (int)(idx / dd), with_m, isM, x)) return;
+  int e = (int)(idx % dd);
   cplx v = mk(0, 0);
-  if (!isM) {
-    int a = x;
-    // term contribution coef * gc_m M_b^H
-    auto add = [&](int m, int b, double coef) {
-      const cplx* M = V.GM(b);
-      cplx u = dotq(d, [&](int q) { return gc(m, r, q); }, [&](int q) { return conj(M[c * d + q]); });
-      v = v + coef * u;
-    };
-    if (a <= k)
-      for (int m = 0; m <= k; m++)
-        for (int j = 0; j <= k; j++) add(m, nt - j, ht * xi * W.R[m][j][a]);
-    for (int m = (a > k + 1 ? a : k + 1); m <= nt; m++) add(m, nt - m + a, ht * xi * adj_w(W, m, m - a));
-    if (a >= nt - k)
-      for (int m = nt - k; m <= nt; m++)
-        for (int j = 0; j <= k; j++) add(m, j, ht * W.R[nt - m][j][nt - a]);
-    for (int m = 0; m <= (a < nt - k - 1 ? a : nt - k - 1); m++) add(m, a - m, ht * adj_w(W, nt - m, a - m));
-    V.sT(p, a)[e] = V.sT(p, a)[e] + v;
-  } else {
-    int b = x;
-    // term contribution coef * Sigma^rceil_{p,a}^H gc_m
-    auto add = [&](int m, int a, double coef) {
-      const cplx* S = V.ST(p, a);
-      cplx u = dotq(d, [&](int q) { return conj(S[q * d + r]); }, [&](int q) { return gc(m, q, c); });
-      v = v + coef * u;
-    };
-    if (b >= nt - k)
-      for (int m = 0; m <= k; m++)
-        for (int l = 0; l <= k; l++) add(m, l, ht * xi * W.R[m][nt - b][l]);
-    for (int m = (nt - b > k + 1 ? nt - b : k + 1); m <= nt; m++) add(m, m - nt + b, ht * xi * adj_w(W, m, nt - b));
-    if (b <= k)
-      for (int m = nt - k; m <= nt; m++)
-        for (int l = 0; l <= k; l++) add(m, nt - l, ht * W.R[nt - m][b][l]);
-    for (int m = 0; m <= (nt - b < nt - k - 1 ? nt - b : nt - k - 1); m++) add(m, m + b, ht * adj_w(W, nt - m, b));
-    V.aM(b)[e] = V.aM(b)[e] + v;
-  }
+  int nterm = tau_nterms(V.k, V.ntau, isM, x);
+  for (int t = 0; t < nterm; t++) v = v + tau_contrib(V, p, src, isM, x, t, e / V.d, e % V.d);
+  cplx* o = tau_dst(V, p, isM, x);
+  o[e] = o[e] + v;
 }
 
 // ============================================================== K3
@@ -878,16 +951,8 @@ __host__ __device__ inline bool adj_rbound_team(const AdjProb& Ap, const KW& W, 
     V.ge(n)[e] = V.ge(n)[e] + mul_i(-1.0 * gm[e]);
     if (V.A.sR) V.sR(n, n)[e] = V.sR(n, n)[e] + mul_i(-(h * adj_w(W, n, n)) * gm[e]);
   }
-  for (int e = tid; e < kd * kd; e += nth) {
-    int R = e / kd, C = e % kd;
-    int l = 1 + R / d, p = 1 + C / d, r = R % d, c = C % d;
-    cplx v = mul_i((h * W.s[p][l]) * V.Rt(V.P.Sret, n - l, n - p, r, c));
-    if (r == c) v.x += W.D[p][l] / h;
-    if (p == l) v = v + mul_i(V.eh(n - p, r, c));
-    Cb[e] = v;
-  }
+  for (int e = tid; e < kd * kd; e += nth) Cb[e] = V.scr(V.lay.cbinv)[e];  // C^{-1}, adj_prep_team
   ADJ_SYNC();
-  ok = team_inverse(kd, Cb, piv, tid, nth) && ok;
   // X = C^{-1} Ybar^H, Ybar^H block l = aR(n, n-l)^H
   for (int e = tid; e < kd * d; e += nth) {
     int R = e / d, c = e % d;
@@ -933,6 +998,59 @@ __host__ __device__ inline bool adj_rbound_team(const AdjProb& Ap, const KW& W, 
       V.sR(n - l, n - p)[r * d + c] = V.sR(n - l, n - p)[r * d + c] + v;
     }
   }
+  ADJ_SYNC();
+  return ok;
+}
+
+// ============================================================== per-slice set-up
+// Inverses of the local matrices of slice n > k, which depend on Sigma and eps
+// only (fixed during the sweep): M_R (bulk rows), A_m for the serial rows m
+// (n-k..n, or k+1..n for n <= 2k) and the retarded-boundary matrix C.
+__host__ __device__ inline int adj_prep_lds(int d, int k) { return k * d * k * d; }
+
+__host__ __device__ inline bool adj_prep_team(const AdjProb& Ap, const KW& W, int n, int tid, int nth, cplx* lds,
+                                              int* piv) {
+  AdjView V(Ap, W);
+  int d = V.d, dd = V.dd, k = V.k, kd = k * d;
+  double h = V.h;
+  bool ok = true;
+  cplx* A = lds;
+  // M_R = h^-1 a_0 + i e_n + i h w_{n,n} Sigma^R_{n,n}
+  for (int e = tid; e < dd; e += nth) {
+    int r = e / d, c = e % d;
+    cplx v = mul_i((h * adj_w(W, n, n)) * V.SR(n, n)[e]) + mul_i(V.eh(n, r, c));
+    if (r == c) v.x += W.a[0] / h;
+    A[e] = v;
+  }
+  ADJ_SYNC();
+  ok = team_inverse(d, A, piv, tid, nth) && ok;
+  for (int e = tid; e < dd; e += nth) V.scr(V.lay.mrinv)[e] = A[e];
+  ADJ_SYNC();
+  int mlo = n > 2 * k ? n - k : k + 1;
+  for (int m = mlo; m <= n; m++) {
+    for (int e = tid; e < dd; e += nth) {
+      int r = e / d, c = e % d;
+      cplx v = mul_i((h * adj_w(W, m, m)) * V.SR(m, m)[e]) + mul_i(V.eh(m, r, c));
+      if (r == c) v.x += W.a[0] / h;
+      A[e] = v;
+    }
+    ADJ_SYNC();
+    ok = team_inverse(d, A, piv, tid, nth) && ok;
+    for (int e = tid; e < dd; e += nth) V.scr(V.lay.ainv)[(size_t)(m - mlo) * dd + e] = A[e];
+    ADJ_SYNC();
+  }
+  // C(l,p) = h^-1 D_{p,l} + delta_{pl} i e_{n-p} + i h s_{p,l} Sigma~^R_{n-l,n-p}, l, p = 1..k
+  for (int e = tid; e < kd * kd; e += nth) {
+    int R = e / kd, C = e % kd;
+    int l = 1 + R / d, p = 1 + C / d, r = R % d, c = C % d;
+    cplx v = mul_i((h * W.s[p][l]) * V.Rt(V.P.Sret, n - l, n - p, r, c));
+    if (r == c) v.x += W.D[p][l] / h;
+    if (p == l) v = v + mul_i(V.eh(n - p, r, c));
+    A[e] = v;
+  }
+  ADJ_SYNC();
+  ok = team_inverse(kd, A, piv, tid, nth) && ok;
+  for (int e = tid; e < kd * kd; e += nth) V.scr(V.lay.cbinv)[e] = A[e];
   ADJ_SYNC();
   return ok;
 }
@@ -1589,7 +1707,13 @@ __device__ inline void team_reduce_block(int dd, NT nterms, TERM term, OUT out) 
   cplx s = mk(0, 0);
   if (lane < lanes && t < lanes * dd) {
     int nt = nterms();
-    for (int i = lane; i < nt; i += lanes) s = s + term(i, e);
+    int i = lane;
+    // four independent terms per round keep their loads in flight together
+    for (; i + 3 * lanes < nt; i += 4 * lanes) {
+      cplx a0 = term(i, e), a1 = term(i + lanes, e), a2 = term(i + 2 * lanes, e), a3 = term(i + 3 * lanes, e);
+      s = s + ((a0 + a1) + (a2 + a3));
+    }
+    for (; i < nt; i += lanes) s = s + term(i, e);
   }
   red[t] = s;
   __syncthreads();
@@ -1614,12 +1738,30 @@ __global__ void __launch_bounds__(ADJ_NT) k_adj_sigma(const AdjProb* ap, int n) 
         o[e] = o[e] + v;
       });
 }
+// one output block per workgroup, the terms split over lane groups
 __global__ void __launch_bounds__(ADJ_NT) k_adj_tau(const AdjProb* ap, int p, int srcsel, int with_m) {
   const AdjProb& A = ap[blockIdx.y];
   if (p > A.p.nt) return;
   AdjView V(A, c_kw[A.p.k]);
+  bool isM;
+  int x;
+  if (!tau_out(A, V.ntau, blockIdx.x, with_m != 0, isM, x)) return;
   const cplx* src = srcsel == 0 ? V.scr(V.lay.rhoT) : V.scr(V.lay.psi) + (size_t)(p - 1) * (V.ntau + 1) * V.dd;
-  adj_tau_elem(A, c_kw[A.p.k], p, src, (size_t)blockIdx.x * blockDim.x + threadIdx.x, with_m != 0);
+  int d = V.d;
+  team_reduce_block(
+      V.dd, [&]() { return tau_nterms(V.k, V.ntau, isM, x); },
+      [&](int t, int e) { return tau_contrib(V, p, src, isM, x, t, e / d, e % d); },
+      [&](int e, cplx v) {
+        cplx* o = tau_dst(V, p, isM, x);
+        o[e] = o[e] + v;
+      });
+}
+__global__ void __launch_bounds__(ADJ_NT) k_adj_prep(const AdjProb* ap, int n) {
+  __shared__ cplx lds[ADJ_LDS];
+  __shared__ int piv[72];
+  const AdjProb& A = ap[blockIdx.y];
+  if (n > A.p.nt) return;
+  if (!adj_prep_team(A, c_kw[A.p.k], n, threadIdx.x, blockDim.x, lds, piv) && threadIdx.x == 0) adj_fail(A);
 }
 __global__ void __launch_bounds__(ADJ_NT) k_adj_rbound(const AdjProb* ap, int n) {
   __shared__ cplx lds[ADJ_LDS];
@@ -1760,6 +1902,11 @@ struct AdjShape {
   bool sig;
 };
 
+// set-up of slice n > k (inverses of the local matrices; once per slice)
+void adj_prep_launch(const AdjProb* dA, const AdjShape& S, int n, hipStream_t s) {
+  hipLaunchKernelGGL(k_adj_prep, dim3(1, S.count), dim3(ADJ_NT), 0, s, dA, n);
+}
+
 // reverse step of slice n > k (hist: also scatter into the history of slices < n)
 void adj_step_launch(const AdjProb* dA, const AdjShape& S, int n, bool hist, hipStream_t s) {
   int k = S.k, ntau = S.ntau, dd = S.dd;
@@ -1776,9 +1923,7 @@ void adj_step_launch(const AdjProb* dA, const AdjShape& S, int n, bool hist, hip
   if (S.sig) hipLaunchKernelGGL(k_adj_sigma, dim3(sig_geom(n, k, ntau).total, S.count), blk, 0, s, dA, n);
   // (a trial step, hist = false, needs no M adjoint)
   int nto = (S.sig ? 1 : 0) + (hist ? 1 : 0);
-  if (nto)
-    hipLaunchKernelGGL(k_adj_tau, dim3(adj_blocks((size_t)nto * (ntau + 1) * dd), S.count), blk, 0, s, dA, n, 0,
-                       hist ? 1 : 0);
+  if (nto) hipLaunchKernelGGL(k_adj_tau, dim3(nto * (ntau + 1), S.count), blk, 0, s, dA, n, 0, hist ? 1 : 0);
   hipLaunchKernelGGL(k_adj_rbound, dim3(1, S.count), blk, 0, s, dA, n);
 }
 
@@ -1791,13 +1936,11 @@ void adj_start_launch(const AdjProb* dA, const AdjShape& S, hipStream_t s) {
     hipLaunchKernelGGL(k_adj_lcol, dim3(1, S.count), blk, 0, s, dA, n);
     hipLaunchKernelGGL(k_adj_lcol_scatter, dim3(adj_blocks(lg.total), S.count), blk, 0, s, dA, n);
   }
-  hipLaunchKernelGGL(k_adj_tinv, dim3(1, S.count), blk, 0, s, dA);
   hipLaunchKernelGGL(k_adj_tpsi, dim3(adj_blocks((size_t)k * (ntau + 1) * dd), S.count), blk, 0, s, dA);
   hipLaunchKernelGGL(k_adj_ty0, dim3(adj_blocks((size_t)(ntau + 1) * dd), S.count), blk, 0, s, dA);
   hipLaunchKernelGGL(k_adj_tp, dim3(k * (k + 1), S.count), blk, 0, s, dA);
   for (int p = 1; p <= k; p++)
-    hipLaunchKernelGGL(k_adj_tau, dim3(adj_blocks((size_t)(S.sig ? 2 : 1) * (ntau + 1) * dd), S.count), blk, 0,
-                       s, dA, p, 1, 1);
+    hipLaunchKernelGGL(k_adj_tau, dim3((S.sig ? 2 : 1) * (ntau + 1), S.count), blk, 0, s, dA, p, 1, 1);
   hipLaunchKernelGGL(k_adj_rstart, dim3(1, S.count), blk, 0, s, dA);
 }
 
@@ -1818,7 +1961,12 @@ AdjShape adj_shape(const AdjProb* hA, int count) {
 // start-up (problems share d, k and ntau).
 hipError_t launch_adjoint_sweep(const AdjProb* dA, const AdjProb* hA, int count, hipStream_t s) {
   AdjShape S = adj_shape(hA, count);
-  for (int n = S.ntmax; n > S.k; n--) adj_step_launch(dA, S, n, true, s);
+  // inverse of the start-up matrix (used by the columns n <= 2k and the mixing start-up)
+  hipLaunchKernelGGL(k_adj_tinv, dim3(1, count), dim3(ADJ_NT), 0, s, dA);
+  for (int n = S.ntmax; n > S.k; n--) {
+    adj_prep_launch(dA, S, n, s);
+    adj_step_launch(dA, S, n, true, s);
+  }
   adj_start_launch(dA, S, s);
   return hipGetLastError();
 }
@@ -1830,7 +1978,9 @@ hipError_t launch_adjoint_2b(AdjProb* dA, AdjProb* dDry, const AdjProb* hA, int 
   AdjShape S = adj_shape(hA, count);
   int k = S.k, ntau = S.ntau, dd = S.dd;
   dim3 blk(ADJ_NT);
+  hipLaunchKernelGGL(k_adj_tinv, dim3(1, count), blk, 0, s, dA);
   auto block = [&](int lo, int hi, int wlo, bool start) {
+    if (!start) adj_prep_launch(dA, S, hi, s);
     unsigned wb = adj_blocks(win_elems(lo, hi, ntau, dd) + (size_t)(hi - lo + 1) * dd);
     unsigned sb = adj_blocks(win_elems(lo, hi, ntau, dd));
     hipLaunchKernelGGL(k_adj_setdry, dim3(1, count), dim3(64), 0, s, dDry, dA, lo, wlo);
