@@ -703,12 +703,25 @@ __host__ __device__ inline SigGeom sig_geom(int n, int k, int ntau) {
   g.total = g.nR + g.nL + g.nT;
   return g;
 }
-// number of reduction terms of output block ob
+// Reduction terms of output block ob, over their exact ranges:
+//   sR(n, j): m = 0..min(j, nb-1) (retarded), t = 0..ntau (mixing),
+//             m = 0..nb-1 (lesser, n > 2k);
+//   sL(j, n): m = 0..min(k, nb-1) when j <= k, then m = max(j, k+1)..nb-1;
+//   sT(n, t): m = 0..nb-1.
+// (nb = n - k bulk rows)
 __host__ __device__ inline int sig_nterms(const AdjView& V, int n, int ob) {
   SigGeom G = sig_geom(n, V.k, V.ntau);
-  int nb = n - V.k;
-  if (ob < G.nR) return (nb) + (V.ntau + 1) + (n > 2 * V.k ? nb : 0);
-  if (ob < G.nR + G.nL) return nb;
+  int k = V.k, nb = n - k;
+  if (ob < G.nR) {
+    int j = ob, a = (j < nb - 1 ? j : nb - 1) + 1;
+    return a + (V.ntau + 1) + (n > 2 * k ? nb : 0);
+  }
+  if (ob < G.nR + G.nL) {
+    int j = ob - G.nR;
+    int a = j <= k ? (k < nb - 1 ? k : nb - 1) + 1 : 0;
+    int m0 = j > k + 1 ? j : k + 1;
+    return a + (nb - m0 > 0 ? nb - m0 : 0);
+  }
   return nb;
 }
 __host__ __device__ inline cplx sig_term(const AdjView& V, int n, int ob, int t, int r, int c) {
@@ -719,16 +732,15 @@ __host__ __device__ inline cplx sig_term(const AdjView& V, int n, int ob, int t,
   const cplx* rT = V.scr(V.lay.rhoT);
   const cplx* rR = V.scr(V.lay.rhoR);
   if (ob < G.nR) {
-    int j = ob;
-    if (t < nb) {
+    int j = ob, na = (j < nb - 1 ? j : nb - 1) + 1;
+    if (t < na) {
       int m = t;
-      if (m > j) return mk(0, 0);
       const cplx* g = rR + (size_t)m * V.dd;
       const cplx* R = V.GR(j, m);
       cplx u = dotq(d, [&](int q) { return g[r * d + q]; }, [&](int q) { return conj(R[c * d + q]); });
       return mul_i((h * adj_w(V.W, n - m, j - m)) * u);
     }
-    t -= nb;
+    t -= na;
     if (t <= ntau) {
       const cplx* g = rT + (size_t)t * V.dd;
       const cplx* T = V.GT(j, t);
@@ -742,16 +754,18 @@ __host__ __device__ inline cplx sig_term(const AdjView& V, int n, int ob, int t,
     return mul_i((h * adj_w(V.W, n, j)) * u);
   }
   if (ob < G.nR + G.nL) {
-    int j = ob - G.nR, m = t;
-    const cplx* g = rL + (size_t)m * V.dd;
+    int j = ob - G.nR;
+    int na = j <= k ? (k < nb - 1 ? k : nb - 1) + 1 : 0;
+    int m;
     double wt;
-    if (m > k) {
-      if (j > m) return mk(0, 0);
-      wt = adj_w(V.W, m, j);
+    if (t < na) {
+      m = t;
+      wt = V.W.s[m][j];  // m <= k: start weights, Rt continuation for j > m
     } else {
-      if (j > k) return mk(0, 0);
-      wt = V.W.s[m][j];
+      m = (j > k + 1 ? j : k + 1) + (t - na);
+      wt = adj_w(V.W, m, j);  // m > k, j <= m
     }
+    const cplx* g = rL + (size_t)m * V.dd;
     // h w Rt(G, m, j)^H (-i rhoL_m)
     cplx u = dotq(d, [&](int q) { return conj(V.Rt(V.P.Gret, m, j, q, r)); }, [&](int q) { return g[q * d + c]; });
     return mul_i(-(h * wt) * u);
@@ -927,7 +941,7 @@ __host__ __device__ inline void adj_tau_elem(const AdjProb& Ap, const KW& W, int
 //   Y C = -Y_0 C_0  with Y_l = R_{n,n-l},  C(l,p) = h^-1 D_{p,l} + delta_{pl} i e_{n-p}
 //                                                 + i h s_{p,l} Sigma~^R_{n-l,n-p}
 //   Psi = Ybar C^{-H}: C Psi^H = Ybar^H ;  Cbar(l,p) = -Y_l^H Psi_p
-__host__ __device__ inline int adj_rb_lds(int d, int k) { return k * d * k * d + 3 * k * d * d + d * d; }
+__host__ __device__ inline int adj_rb_lds(int d, int k) { return k * d * k * d + 3 * k * d * d + d * d + ADJ_NT; }
 
 __host__ __device__ inline bool adj_rbound_team(const AdjProb& Ap, const KW& W, int n, int nparts, int tid,
                                                 int nth, cplx* lds, int* piv) {
@@ -938,11 +952,20 @@ __host__ __device__ inline bool adj_rbound_team(const AdjProb& Ap, const KW& W, 
   cplx* X = Cb + kd * kd;  // kd x d: Psi^H blocks
   cplx* gm = X + kd * d;   // d x d
   bool ok = true;
-  // M_Rbar
+  // M_Rbar: the workgroup partials, split over thread groups (fixed order)
   const cplx* part = V.scr(V.lay.part);
+  int grp = dd >= nth ? 1 : nth / dd;
+  cplx* gs = gm + dd;  // grp x dd
+  for (int t = tid; t < grp * dd; t += nth) {
+    int gg = t / dd, e = t % dd;
+    cplx s = mk(0, 0);
+    for (int w = gg; w < nparts; w += grp) s = s + part[(size_t)w * dd + e];
+    gs[t] = s;
+  }
+  ADJ_SYNC();
   for (int e = tid; e < dd; e += nth) {
     cplx s = mk(0, 0);
-    for (int w = 0; w < nparts; w++) s = s + part[(size_t)w * dd + e];
+    for (int gg = 0; gg < grp; gg++) s = s + gs[gg * dd + e];
     gm[e] = s;
   }
   ADJ_SYNC();
