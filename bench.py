@@ -312,7 +312,7 @@ def main():
     ap.add_argument("--no-kpoints", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-uneven", action="store_true")
-    ap.add_argument("--adj-niter", type=int, default=16, help="adjoint fixed-point iterations per slice")
+    ap.add_argument("--adj-niter", type=int, default=10, help="adjoint fixed-point iterations per slice")
     ap.add_argument("--profile-step", type=int, default=0,
                     help="only run the time step at this slice (counter runs), then a 1 GiB copy")
     args = ap.parse_args()

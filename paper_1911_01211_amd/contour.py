@@ -185,7 +185,7 @@ def observables(tstp: int, G: list, Sigma: list, eps0: list, eps_mf=None, stream
 
 
 def adjoint_sweep(G: list, Sigma: list, eps: list, Gbar: list, eps_bar: list, Sigmabar: list | None = None,
-                  U: list | None = None, U_bar: list | None = None, nbar=0.5, niter=16, stream=None):
+                  U: list | None = None, U_bar: list | None = None, nbar=0.5, niter=10, stream=None):
     """Reverse-mode sweep of the Dyson solution (cntr_adjoint_sweep). Gbar
     holds dJ/dG on entry (consumed; Gbar.mat returns dJ/dM), eps_bar (+=)
     receives dJ/deps_n, Sigmabar (+=) dJ/dSigma. With U (second-Born mode:

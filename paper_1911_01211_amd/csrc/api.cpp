@@ -622,7 +622,7 @@ cntr_status cntr_adjoint_sweep(int32_t count, const cntr_grid* grids, const cntr
       return fail(CNTR_ESHAPE, "cntr_adjoint_sweep: Sigmabar needs ret, les and tv");
     if (twob && (!U[i] || !U_bar[i])) return fail(CNTR_ESHAPE, "cntr_adjoint_sweep: null U or U_bar");
   }
-  if (niter <= 0) niter = 16;
+  if (niter <= 0) niter = 10;
   if ((st = ensure_weights())) return st;
   hipStream_t s = (hipStream_t)stream;
   StreamScratch* sc = scratch_for(s);

@@ -178,7 +178,7 @@ def setup_2b(O, d, nt, ntau, seed):
     return g, r, e0, U, C
 
 
-def gpu_gradients_2b(g, e0, U, C, niter=16):
+def gpu_gradients_2b(g, e0, U, C, niter=10):
     """GPU forward (cntr_solve_2b) then the second-Born adjoint sweep."""
     G, S, Gs = K.Contour(g), K.Contour(g), K.Contour(g)
     e0d = torch.as_tensor(e0).to(DEV)
