@@ -99,7 +99,7 @@ def run_gpu(args):
 def run_adjoint(g, state, args):
     """Adjoint sample: gradient of the kinetic energy at the last time,
     J = 2 Re Tr[eps_kin rho(t_nt)] with rho = -i G^<(t_nt, t_nt) (both spins),
-    with respect to every eps0_n and U_n of the 2B chain run just timed
+    with respect to every eps0_n and U_n (n = -1..nt) of the 2B chain run just timed
     (second-Born mode of cntr_adjoint_sweep on its converged solution,
     `niter` fixed-point iterations per slice)."""
     import numpy as np
@@ -123,7 +123,7 @@ def run_adjoint(g, state, args):
     el = time.perf_counter() - t0
     ubh = ub.cpu().numpy()
     return {"workload": "gradient of the kinetic energy at t_nt w.r.t. eps0_n and U_n (n = 0..nt) of the "
-                        "same 2B chain solution (second-Born adjoint sweep, Matsubara held fixed)",
+                        "same 2B chain solution (second-Born adjoint sweep, Matsubara solve included)",
             "value": (nt - g.k) / el, "unit": "adjoint time-steps/s", "seconds": el,
             "fixed_point_iterations": args.adj_niter, "fixed_point_last_change": conv,
             "forward_equivalent": "one forward time step = 5 corrector iterations",
