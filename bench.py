@@ -199,6 +199,7 @@ def run_kpoints(args):
     lam = 0.25
     B = K.solve_local(G, S, eps, lam, mats_iters=1, boot_iters=8, ncorr=args.ncorr, nt_stop=g.k)
     torch.cuda.synchronize()
+    K.profile_begin()
     t0 = time.perf_counter()
     for n in range(g.k + 1, args.kp_steps + 1):
         B.extrapolate(n - 1)
@@ -208,11 +209,16 @@ def run_kpoints(args):
         B.sigma_local(n, lam)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
+    prof = K.profile_end()
     nsteps = (args.kp_steps - g.k) * nk
+    gbs = prof["hist_bytes"] / (prof["hist_ms"] * 1e-3) / 1e9 if prof["hist_ms"] > 0 else None
     return {"workload": f"{nk} k-points, d=1, local Sigma = 0.25 G_loc, pulse A(t), beta=10, ntau=500, "
                         f"nt=2000 grid; steps {g.k + 1}..{args.kp_steps} timed",
             "value": nsteps / el, "unit": "instance time-steps/s", "instances": nk,
             "ms_per_slice": el / (args.kp_steps - g.k) * 1e3, "corrector_iterations": args.ncorr,
+            "roofline": {"bound": "hbm", "kernel": "k_history<1>", "achieved": gbs, "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS if gbs else None,
+                         "avg_launch_us": prof["hist_ms"] * 1e3 / max(1, prof["hist_launches"])},
             "note": "prefix of the run (the per-slice cost grows with n)"}
 
 
