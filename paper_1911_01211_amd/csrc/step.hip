@@ -1259,37 +1259,52 @@ __global__ __launch_bounds__(NTHR) void k_history(ProbArg pa, Scratch sc, HistPl
 // and the last workgroup to finish (completion counter, no waiting) sums the
 // per-workgroup partials, adds the terms of the boundary rows themselves and
 // runs the k+1 serial steps with the inverses prepared by the step set-up.
-// Sum of cnt values p[i * stride] (in a fixed order), eight loads in flight.
-__device__ inline cplx psum(const cplx* p, long stride, int cnt) {
-  cplx s[8];
+// Sum of cnt values p[i * stride] (in a fixed order), B loads in flight.
+template <int B>
+__device__ inline cplx psum_b(const cplx* p, long stride, int cnt) {
+  cplx s[B];
 #pragma unroll
-  for (int u = 0; u < 8; u++) s[u] = mk(0, 0);
+  for (int u = 0; u < B; u++) s[u] = mk(0, 0);
   int i = 0;
-  for (; i + 8 <= cnt; i += 8) {
-    cplx v[8];
+  for (; i + B <= cnt; i += B) {
+    cplx v[B];
 #pragma unroll
-    for (int u = 0; u < 8; u++) v[u] = gld(p + (long)(i + u) * stride);
+    for (int u = 0; u < B; u++) v[u] = gld(p + (long)(i + u) * stride);
 #pragma unroll
-    for (int u = 0; u < 8; u++) s[u] = s[u] + v[u];
+    for (int u = 0; u < B; u++) s[u] = s[u] + v[u];
   }
-  for (; i < cnt; i++) s[0] = s[0] + gld(p + (long)i * stride);
-  return ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
+  {
+    cplx v[B];
+#pragma unroll
+    for (int u = 0; u < B; u++) v[u] = i + u < cnt ? gld(p + (long)(i + u) * stride) : mk(0, 0);
+#pragma unroll
+    for (int u = 0; u < B; u++) s[u] = s[u] + v[u];
+  }
+#pragma unroll
+  for (int w = B / 2; w >= 1; w /= 2)
+#pragma unroll
+    for (int u = 0; u < w; u++) s[u] = s[u] + s[u + w];
+  return s[0];
 }
 
-// Sums of NS sequences p[s][i * stride], i < cnt[s]: the first eight terms of
+// Sums of NS sequences p[s][i * stride], i < cnt[s]: the first B terms of
 // every sequence are loaded together (one memory round when all counts are
-// <= 8), longer tails follow with psum. Fixed summation order.
-template <int NS>
+// <= B), longer tails follow with psum_b. Fixed summation order.
+template <int NS, int B>
 __device__ inline void msum(const cplx* const (&p)[NS], const int (&cnt)[NS], long stride, cplx (&out)[NS]) {
-  cplx v[NS][8];
+  cplx v[NS][B];
 #pragma unroll
   for (int q = 0; q < NS; q++)
 #pragma unroll
-    for (int u = 0; u < 8; u++) v[q][u] = u < cnt[q] ? gld(p[q] + (long)u * stride) : mk(0, 0);
+    for (int u = 0; u < B; u++) v[q][u] = u < cnt[q] ? gld(p[q] + (long)u * stride) : mk(0, 0);
 #pragma unroll
   for (int q = 0; q < NS; q++) {
-    out[q] = ((v[q][0] + v[q][1]) + (v[q][2] + v[q][3])) + ((v[q][4] + v[q][5]) + (v[q][6] + v[q][7]));
-    if (cnt[q] > 8) out[q] = out[q] + psum(p[q] + 8 * stride, stride, cnt[q] - 8);
+#pragma unroll
+    for (int w = B / 2; w >= 1; w /= 2)
+#pragma unroll
+      for (int u = 0; u < w; u++) v[q][u] = v[q][u] + v[q][u + w];
+    out[q] = v[q][0];
+    if (cnt[q] > B) out[q] = out[q] + psum_b<B>(p[q] + B * stride, stride, cnt[q] - B);
   }
 }
 
@@ -1316,6 +1331,9 @@ __global__ __launch_bounds__(NTHR) void k_reduce(ProbArg pa, Scratch sc, HistPla
   constexpr int TM = NTHR / DD > 0 ? NTHR / DD : 1;
   constexpr int NVMAX = (KMAX + 1) * DD;
   constexpr int NSTAGE = NVMAX > NTHR ? NVMAX : NTHR;
+  // partial sums loaded per sequence in one round (one workgroup per compute
+  // unit for d >= 2, so registers are plentiful)
+  constexpr int MSB = D >= 2 ? 16 : 8;
   __shared__ cplx outs[TM * DD];
   __shared__ cplx minv[DD];
   __shared__ cplx pre[NVMAX];
@@ -1324,6 +1342,9 @@ __global__ __launch_bounds__(NTHR) void k_reduce(ProbArg pa, Scratch sc, HistPla
   __shared__ cplx sigs[(KMAX + 1) * TM * DD];
   __shared__ double twt[(KMAX + 1) * TM];  // quadrature weights of the tile terms
   __shared__ cplx ser[(KMAX * (KMAX + 1) / 2 + 2 * KMAX + 1) * DD];
+  __shared__ double s_om[KMAX + 1], s_ss[(KMAX + 1) * (KMAX + 1)];  // Gregory end weights
+  __shared__ double s_ah[KMAX + 1];                                // a_l / h (BDF)
+  __shared__ double s_gw[(KMAX + 1) * (KMAX + 1)];                 // weights of the serial rows
   __shared__ int is_last;
   int pi = blockIdx.y;
   const Prob& P = pa.get(pi);
@@ -1340,6 +1361,26 @@ __global__ __launch_bounds__(NTHR) void k_reduce(ProbArg pa, Scratch sc, HistPla
   // runs the boundary rows itself (no completion count across workgroups).
   bool walk = pl.walk_tiles;
   int tid = threadIdx.x;
+  constexpr int K1M = KMAX + 1;
+  if (tid <= KMAX) s_om[tid] = W.omega[tid];
+  if (tid >= 1 && tid <= k) s_ah[tid] = W.a[tid] / h;
+  if (tid < K1M * K1M) s_ss[tid] = W.s[tid / K1M][tid % K1M];
+  // Gregory weight w(N, j) from the LDS tables (per-lane indices)
+  auto gw = [&](int N, int j) -> double {
+    if (N <= k) return s_ss[N * K1M + j];
+    bool left = j <= k, right = N - j <= k;
+    if (left && right) return s_om[j] + s_om[N - j] - 1.0;
+    if (left) return s_om[j];
+    if (right) return s_om[N - j];
+    return 1.0;
+  };
+  auto bdf = [&](const cplx(&v)[KMAX]) {
+    cplx r = mk(0, 0);
+#pragma unroll
+    for (int l = 1; l <= KMAX; l++)
+      if (l <= k) r = r - s_ah[l] * v[l - 1];
+    return r;
+  };
   int b_end = walk ? nwg : (int)blockIdx.x + 1;
   for (int b = walk ? 0 : (int)blockIdx.x; b < b_end; b++) {
   __syncthreads();  // the LDS buffers of the previous tile are free
@@ -1361,26 +1402,22 @@ __global__ __launch_bounds__(NTHR) void k_reduce(ProbArg pa, Scratch sc, HistPla
   if (tid < DD) minv[tid] = sc.minv(pi)[tid];
   const cplx* part = sc.part(pi);
   int mlo = mt * TM, mhi = min(mlo + TM, mout) - 1, nm = mhi - mlo + 1;
-  if (n >= 2 * k + 1) {
-    // self-energy blocks of the boundary rows paired with this tile (used
-    // after the outputs are formed; loaded now, in the same memory round)
-#pragma unroll 8
-    for (int idx = tid; idx < (k + 1) * nm * DD; idx += NTHR) {
+  // self-energy blocks of the boundary rows paired with this tile (used after
+  // the outputs are formed; loaded now into registers, in the same memory
+  // round as the partial sums, and stored to LDS afterwards)
+  constexpr int NSG = KMAX + 1;  // (k+1) nm d^2 <= (KMAX+1) NTHR
+  cplx sgv[NSG];
+  bool bnd = n >= 2 * k + 1;
+#pragma unroll
+  for (int u = 0; u < NSG; u++) {
+    int idx = tid + u * NTHR;
+    sgv[u] = mk(0, 0);
+    if (bnd && idx < (k + 1) * nm * DD) {
       int r = idx / (nm * DD), rem = idx % (nm * DD), mm = mlo + rem / DD, ee = rem % DD;
       int mr = n - k + r;
-      cplx v;
-      if (fam == 0) v = gld(P.Sles + (tri(mr) + mm) * DD + ee);  // Sigma^<_{mm,mr}, mm < mr
-      else if (fam == 1) v = gld(P.Stv + ((size_t)mr * (ntau + 1) + ntau - mm) * DD + ee);
-      else v = gld(P.Sret + (tri(mr) + mm) * DD + ee);
-      sigs[idx] = v;
-    }
-    for (int idx = tid; idx < (k + 1) * nm; idx += NTHR) {
-      int r = idx / nm, mm = mlo + idx % nm;
-      double w;
-      if (fam == 0) w = greg(W, n, mm);
-      else if (fam == 1) w = -xi * greg(W, ntau, ntau - mm);
-      else w = greg(W, n - k + r, mm);
-      twt[idx] = w;
+      if (fam == 0) sgv[u] = gld(P.Sles + (tri(mr) + mm) * DD + ee);  // Sigma^<_{mm,mr}, mm < mr
+      else if (fam == 1) sgv[u] = gld(P.Stv + ((size_t)mr * (ntau + 1) + ntau - mm) * DD + ee);
+      else sgv[u] = gld(P.Sret + (tri(mr) + mm) * DD + ee);
     }
   }
   if (valid) {
@@ -1395,8 +1432,8 @@ __global__ __launch_bounds__(NTHR) void k_reduce(ProbArg pa, Scratch sc, HistPla
       const cplx* ps[1] = {pp(0, c0)};
       int cn[1] = {pl.nch[0] - c0};
       cplx sm[1];
-      msum<1>(ps, cn, cs, sm);
-      r = bdf_add(W, k, h, bv) - h * mul_i(sm[0]);
+      msum<1, MSB>(ps, cn, cs, sm);
+      r = bdf(bv) - h * mul_i(sm[0]);
     } else if (fam == 1) {
       cplx bv[KMAX];
       bdf_load(k, [&](int l) { return P.Gtv + ((size_t)(n - l) * (ntau + 1) + m) * DD + e; }, bv);
@@ -1404,9 +1441,9 @@ __global__ __launch_bounds__(NTHR) void k_reduce(ProbArg pa, Scratch sc, HistPla
       const cplx* ps[2] = {pp(2, 0), pp(1, 0)};
       int cn[2] = {pl.nch[2], pl.nch[1]};
       cplx sm[2];
-      msum<2>(ps, cn, cs, sm);
+      msum<2, MSB>(ps, cn, cs, sm);
       cplx ts = ht * (sm[0] + tb);
-      r = bdf_add(W, k, h, bv) - mul_i(ts) - h * mul_i(sm[1]);
+      r = bdf(bv) - mul_i(ts) - h * mul_i(sm[1]);
     } else {
       int jmax = m > k ? m : k;
       cplx bv[KMAX];
@@ -1417,11 +1454,24 @@ __global__ __launch_bounds__(NTHR) void k_reduce(ProbArg pa, Scratch sc, HistPla
       const cplx* ps[4] = {pp(3, c3), pl.staged ? pp(7, 0) : part, pp(4, 0), pp(5, 0)};
       int cn[4] = {pl.nch[3] - c3, n7, jmax / pl.tj[4] + 1, pl.nch[5]};
       cplx sm[4];
-      msum<4>(ps, cn, cs, sm);
+      msum<4, MSB>(ps, cn, cs, sm);
       cplx s3 = sm[0] + sm[1];
-      r = bdf_add(W, k, h, bv) + h * mul_i(sm[2]) + ht * sm[3] + h * mul_i(s3);
+      r = bdf(bv) + h * mul_i(sm[2]) + ht * sm[3] + h * mul_i(s3);
     }
     outs[mo * DD + e] = r;
+  }
+  if (bnd) {
+#pragma unroll
+    for (int u = 0; u < NSG; u++)
+      if (tid + u * NTHR < (k + 1) * nm * DD) sigs[tid + u * NTHR] = sgv[u];
+    for (int idx = tid; idx < (k + 1) * nm; idx += NTHR) {
+      int r = idx / nm, mm = mlo + idx % nm;
+      double w;
+      if (fam == 0) w = gw(n, mm);
+      else if (fam == 1) w = -xi * gw(ntau, ntau - mm);
+      else w = gw(n - k + r, mm);
+      twt[idx] = w;
+    }
   }
   __syncthreads();
   cplx out = mk(0, 0);
@@ -1521,11 +1571,16 @@ __global__ __launch_bounds__(NTHR) void k_reduce(ProbArg pa, Scratch sc, HistPla
     int idx = tid + u * NTHR;
     if (idx < (k + 1) * DD) vb[u] = gld(sc.minv(pi) + DD + idx);
   }
+  // Gregory weights of the serial rows, w(m_r, n-k+jj), jj < r
+  for (int v = tid; v < (k + 1) * (k + 1); v += NTHR) {
+    int r = v / (k + 1), jj = v % (k + 1);
+    s_gw[r * K1M + jj] = jj < r ? gw(n - k + r, n - k + jj) : 0.0;
+  }
   int G = NV >= NTHR ? 1 : NTHR / NV;
   for (int vv = tid; vv < G * NV; vv += NTHR) {
     int g = vv / NV, v = vv % NV;
     // workgroups g, g+G, g+2G, ... of value v
-    stage[vv] = psum(tpart + (size_t)g * NV + v, (long)G * NV, g < nwg ? (nwg - g + G - 1) / G : 0);
+    stage[vv] = psum_b<16>(tpart + (size_t)g * NV + v, (long)G * NV, g < nwg ? (nwg - g + G - 1) / G : 0);
   }
 #pragma unroll
   for (int u = 0; u < NSR; u++)
@@ -1571,14 +1626,14 @@ __global__ __launch_bounds__(NTHR) void k_reduce(ProbArg pa, Scratch sc, HistPla
       for (int l = 1; l <= k; l++) {
         int row = mr - l;
         cplx y = row >= n - k ? lrow[(row - (n - k)) * DD + tid] : s_l[(row - (n - 2 * k)) * DD + tid];
-        v = v - (W.a[l] / h) * y;
+        v = v - s_ah[l] * y;
       }
       cplx hs = mk(0, 0);
       for (int jj = 0; jj < r; jj++) {
         const cplx* sb = s_r + (r * (r - 1) / 2 + jj) * DD + a2 * D;
         cplx s = mk(0, 0);
         for (int q = 0; q < D; q++) cfma(s, sb[q], lrow[jj * DD + q * D + c2]);
-        hs = hs + greg(W, mr, n - k + jj) * s;
+        hs = hs + s_gw[r * K1M + jj] * s;
       }
       stage[tid] = v - h * mul_i(hs);
     }

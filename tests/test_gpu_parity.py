@@ -108,6 +108,29 @@ def test_startup_parity(O, d):
 
 
 # ------------------------------------------------------- single time steps
+@pytest.mark.parametrize("d,slices", [(2, (640, 700)), (4, (641, 700))])
+def test_timestep_long_history(O, d, slices):
+    """Slices from 640 on (history chunks of two operand pieces on the staged
+    path); 700 = 10 * 64 + 60 leaves a ragged last chunk."""
+    require_gpu()
+    g = W.GridSpec(nt=700, ntau=20, d=d, beta=2.0, h=0.01, k=5, mu=-0.2)
+    r = W.rng(109, d)
+    G = W.random_contour(r, g, 0.3, decay=0.2)
+    S = W.random_contour(r, g, 0.3, decay=0.2)
+    eps = rand_eps(r, g)
+    Sd, e = K.Contour(g, data=S), to_dev(eps)
+    for n in slices:
+        say(f"long-history step d={d} n={n}")
+        Go = ora(O, g, G)
+        assert O.dyson_timestep(n, Go, ora(O, g, S), eps, "B") == 0
+        Gd = K.Contour(g, data=G)
+        K.dyson_step(n, [Gd], [Sd], [e])
+        K.sync()
+        got = Gd.numpy()
+        ref = {key: getattr(Go, key) for key in K.KEYS}
+        assert_slices(g, got, ref, [n], what=f"long-history step d={d}")
+
+
 @pytest.mark.parametrize("d", [1, 2, 3, 4, 8])
 def test_timestep_random_history(O, d):
     require_gpu()
