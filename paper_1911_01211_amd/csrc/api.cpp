@@ -231,7 +231,7 @@ struct MatsState {
     size_t nn = (size_t)N * N * sizeof(cplx);
     size_t vec = (size_t)N * dd * sizeof(cplx);
     if (hipMalloc(&g, bs) || hipMalloc(&K, bs) || hipMalloc(&A, nn) || hipMalloc(&Ainv, nn) ||
-        hipMalloc(&r, vec) || hipMalloc(&dx, vec) || hipMalloc(&work, 2 * (size_t)N * sizeof(cplx)) ||
+        hipMalloc(&r, vec) || hipMalloc(&dx, vec) || hipMalloc(&work, gj_work_elems(N) * sizeof(cplx)) ||
         hipMalloc(&piv, N * sizeof(int)) || hipMalloc(&status, sizeof(int)) ||
         hipMalloc(&norms, 2 * sizeof(double)) || hipMalloc(&smix, bs) ||
         hipMalloc(&emix, (size_t)dd * dd * sizeof(cplx))) {

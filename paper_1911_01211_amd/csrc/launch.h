@@ -79,6 +79,8 @@ hipError_t launch_mat_conv(const Prob& P, const cplx* A, const cplx* B, const cp
 hipError_t launch_mat_build(const Prob& P, const cplx* K, cplx* Amat, hipStream_t s);
 hipError_t launch_gj_inverse(int N, cplx* Amat, cplx* work, int* piv, int* status,
                              hipStream_t s);
+// complex elements of the work buffer of launch_gj_inverse
+size_t gj_work_elems(int N);
 // y = X v  (X: N x N, v, y: N x nrhs); y = b - X v when b != nullptr
 hipError_t launch_matvec(int N, int nrhs, const cplx* X, const cplx* v, const cplx* b, cplx* y,
                          hipStream_t s);

@@ -206,14 +206,239 @@ __global__ __launch_bounds__(NT3) void k_gj_unpivot(int N, cplx* A, const int* p
   }
 }
 
+// ------------------------------------ blocked Gauss-Jordan (N <= 2 NGJ)
+// Panels of GJB columns. For the panel columns c0..c0+nb-1 the GJ steps run
+// in one workgroup with the panel in registers (thread t holds rows t and
+// t + NGJ): pivot search over the rows r >= c, row interchange, and the
+// in-place update of the panel (column c becomes column c of the inverse
+// form). The row interchanges of the other columns are applied once per
+// panel, and their pivot rows (after the interchanges) go to prbuf. The other
+// columns then take the whole panel as one rank-nb update (block identity of
+// the in-place elimination): block rows  A_1j := A11' A_1j,  other rows
+// A_ij += A_i1' A_1j, with the panel ' after its steps and A_1j the pivot rows
+// before them.
+constexpr int GJB = 8;
+
+__device__ inline void gj_argmax(double& v, int& i) {
+  // ties: smaller index
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    double ov = __shfl_xor(v, off);
+    int oi = __shfl_xor(i, off);
+    if (ov > v || (ov == v && oi < i)) {
+      v = ov;
+      i = oi;
+    }
+  }
+}
+
+__global__ __launch_bounds__(NGJ) void k_gjb_panel(int N, int c0, int nb, cplx* A, cplx* prbuf, int* piv,
+                                                   int* status) {
+  __shared__ double wv[NGJ / 64];
+  __shared__ int wi[NGJ / 64];
+  __shared__ cplx xr[2][GJB];  // rows being interchanged
+  __shared__ cplx pr[GJB];     // pivot row of the step
+  __shared__ int s_p, s_ok;
+  __shared__ int dst[2 * GJB], src[2 * GJB], s_m;
+  int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  cplx L[2][GJB];
+#pragma unroll
+  for (int h = 0; h < 2; h++) {
+    int r = t + h * NGJ;
+#pragma unroll
+    for (int j = 0; j < GJB; j++) L[h][j] = (r < N && j < nb) ? A[(long)r * N + c0 + j] : mk(0, 0);
+  }
+  for (int b = 0; b < nb; b++) {
+    int c = c0 + b;
+    // pivot: largest |a_rc|^2 over the rows r >= c
+    double best = -1;
+    int bi = c;
+#pragma unroll
+    for (int h = 0; h < 2; h++) {
+      int r = t + h * NGJ;
+      double v = -1;
+#pragma unroll
+      for (int j = 0; j < GJB; j++)
+        if (j == b) v = abs2(L[h][j]);
+      if (r >= c && r < N && v > best) {
+        best = v;
+        bi = r;
+      }
+    }
+    gj_argmax(best, bi);
+    if (lane == 0) {
+      wv[wave] = best;
+      wi[wave] = bi;
+    }
+    __syncthreads();
+    if (t == 0) {
+      double bb = wv[0];
+      int ii = wi[0];
+      for (int w = 1; w < NGJ / 64; w++)
+        if (wv[w] > bb || (wv[w] == bb && wi[w] < ii)) {
+          bb = wv[w];
+          ii = wi[w];
+        }
+      s_ok = bb > 0.0;
+      if (!s_ok) {
+        *status = CNTR_ESINGULAR;
+        ii = c;
+      }
+      s_p = ii;
+      piv[c] = ii;
+    }
+    __syncthreads();
+    int p = s_p;
+    // interchange rows c and p of the panel
+    if (p != c) {
+#pragma unroll
+      for (int h = 0; h < 2; h++) {
+        int r = t + h * NGJ;
+        if (r == c || r == p)
+#pragma unroll
+          for (int j = 0; j < GJB; j++) xr[r == c ? 0 : 1][j] = L[h][j];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int h = 0; h < 2; h++) {
+        int r = t + h * NGJ;
+        if (r == c || r == p)
+#pragma unroll
+          for (int j = 0; j < GJB; j++) L[h][j] = xr[r == c ? 1 : 0][j];
+      }
+    }
+    // pivot row
+#pragma unroll
+    for (int h = 0; h < 2; h++)
+      if (t + h * NGJ == c)
+#pragma unroll
+        for (int j = 0; j < GJB; j++) pr[j] = L[h][j];
+    __syncthreads();
+    cplx pv = mk(0, 0);
+#pragma unroll
+    for (int j = 0; j < GJB; j++)
+      if (j == b) pv = pr[j];
+    cplx ipv = s_ok ? cdiv(mk(1, 0), pv) : mk(0, 0);
+#pragma unroll
+    for (int h = 0; h < 2; h++) {
+      int r = t + h * NGJ;
+      if (r >= N) continue;
+      if (r == c) {
+#pragma unroll
+        for (int j = 0; j < GJB; j++) L[h][j] = j == b ? ipv : pr[j] * ipv;
+      } else {
+        cplx f = mk(0, 0);
+#pragma unroll
+        for (int j = 0; j < GJB; j++)
+          if (j == b) f = L[h][j];
+#pragma unroll
+        for (int j = 0; j < GJB; j++) L[h][j] = j == b ? -(f * ipv) : L[h][j] - f * (pr[j] * ipv);
+      }
+    }
+    __syncthreads();  // pr and xr are free
+  }
+#pragma unroll
+  for (int h = 0; h < 2; h++) {
+    int r = t + h * NGJ;
+    if (r < N)
+#pragma unroll
+      for (int j = 0; j < GJB; j++)
+        if (j < nb) A[(long)r * N + c0 + j] = L[h][j];
+  }
+  // the panel's interchanges as one permutation of the rows involved:
+  // row dst[i] receives the old row src[i]
+  if (t == 0) {
+    int m = 0;
+    for (int b = 0; b < nb; b++) {
+      int rr[2] = {c0 + b, piv[c0 + b]};
+      for (int u = 0; u < 2; u++) {
+        bool seen = false;
+        for (int i = 0; i < m; i++) seen = seen || dst[i] == rr[u];
+        if (!seen) {
+          dst[m] = rr[u];
+          src[m] = rr[u];
+          m++;
+        }
+      }
+    }
+    for (int b = 0; b < nb; b++) {
+      int c = c0 + b, p = piv[c];
+      if (p == c) continue;
+      int ic = 0, ip = 0;
+      for (int i = 0; i < m; i++) {
+        if (dst[i] == c) ic = i;
+        if (dst[i] == p) ip = i;
+      }
+      int tmp = src[ic];
+      src[ic] = src[ip];
+      src[ip] = tmp;
+    }
+    s_m = m;
+  }
+  __syncthreads();
+  int m = s_m;
+  for (int q = t; q < N; q += NGJ) {
+    if (q >= c0 && q < c0 + nb) continue;
+    cplx v[2 * GJB];
+#pragma unroll
+    for (int i = 0; i < 2 * GJB; i++)
+      if (i < m) v[i] = A[(long)src[i] * N + q];
+#pragma unroll
+    for (int i = 0; i < 2 * GJB; i++)
+      if (i < m) A[(long)dst[i] * N + q] = v[i];
+    // pivot rows after the interchanges (block rows c0..c0+nb-1)
+#pragma unroll
+    for (int i = 0; i < 2 * GJB; i++)
+      if (i < m && dst[i] >= c0 && dst[i] < c0 + nb) prbuf[(long)(dst[i] - c0) * N + q] = v[i];
+  }
+}
+
+// Rank-nb update of the columns outside the panel; a workgroup covers NT3
+// consecutive columns and GJR rows.
+constexpr int GJR = 16;
+__global__ __launch_bounds__(NT3) void k_gjb_update(int N, int c0, int nb, cplx* A, const cplx* prbuf) {
+  __shared__ cplx ps[GJR][GJB];
+  int t = threadIdx.x;
+  int q = blockIdx.x * NT3 + t, r0 = blockIdx.y * GJR;
+  for (int i = t; i < GJR * GJB; i += NT3) {
+    int rr = r0 + i / GJB, j = i % GJB;
+    ps[i / GJB][j] = (rr < N && j < nb) ? A[(long)rr * N + c0 + j] : mk(0, 0);
+  }
+  __syncthreads();
+  if (q >= N || (q >= c0 && q < c0 + nb)) return;
+  cplx y[GJB];
+#pragma unroll
+  for (int j = 0; j < GJB; j++) y[j] = j < nb ? prbuf[(long)j * N + q] : mk(0, 0);
+  for (int i = 0; i < GJR; i++) {
+    int r = r0 + i;
+    if (r >= N) break;
+    bool blk = r >= c0 && r < c0 + nb;
+    cplx v = blk ? mk(0, 0) : A[(long)r * N + q];
+#pragma unroll
+    for (int j = 0; j < GJB; j++) v = v + ps[i][j] * y[j];
+    A[(long)r * N + q] = v;
+  }
+}
+
+size_t gj_work_elems(int N) { return (size_t)(GJB > 2 ? GJB : 2) * N; }
+
 hipError_t launch_gj_inverse(int N, cplx* A, cplx* work, int* piv, int* status, hipStream_t s) {
-  cplx* col = work;
-  cplx* prow = work + N;
-  long tot = (long)N * N;
-  unsigned nb = (unsigned)((tot + NT3 - 1) / NT3);
-  for (int c = 0; c < N; c++) {
-    k_gj_pivot<<<1, NGJ, 0, s>>>(N, c, A, col, prow, piv, status);
-    k_gj_update<<<nb, NT3, 0, s>>>(N, c, A, col, prow);
+  if (N <= 2 * NGJ) {
+    dim3 gu((N + NT3 - 1) / NT3, (N + GJR - 1) / GJR);
+    for (int c0 = 0; c0 < N; c0 += GJB) {
+      int nb = N - c0 < GJB ? N - c0 : GJB;
+      k_gjb_panel<<<1, NGJ, 0, s>>>(N, c0, nb, A, work, piv, status);
+      k_gjb_update<<<gu, NT3, 0, s>>>(N, c0, nb, A, work);
+    }
+  } else {
+    cplx* col = work;
+    cplx* prow = work + N;
+    long tot = (long)N * N;
+    unsigned nbk = (unsigned)((tot + NT3 - 1) / NT3);
+    for (int c = 0; c < N; c++) {
+      k_gj_pivot<<<1, NGJ, 0, s>>>(N, c, A, col, prow, piv, status);
+      k_gj_update<<<nbk, NT3, 0, s>>>(N, c, A, col, prow);
+    }
   }
   k_gj_unpivot<<<(N + NT3 - 1) / NT3, NT3, 0, s>>>(N, A, piv);
   return hipGetLastError();
