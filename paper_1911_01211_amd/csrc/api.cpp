@@ -333,7 +333,11 @@ cntr_status mats_loop_2b(const cntr_grid& g, const Prob& P, const ProbArg& pa, c
       ms.release();
       return hip_fail(e, "Matsubara loop");
     }
-    if ((st = mats_solve(ms, P, true, 1e-15, 200, s, nullptr))) {
+    // inexact inner solves: the refinement stops three orders of magnitude
+    // below the last outer distance (at most 1e-8, at least 1e-15); the
+    // fixpoint and the final accuracy are those of exact inner solves
+    double itol = std::min(1e-8, std::max(1e-15, 1e-3 * (it == 0 ? 1.0 : err)));
+    if ((st = mats_solve(ms, P, true, itol, 200, s, nullptr))) {
       ms.release();
       return st;
     }
