@@ -268,8 +268,7 @@ cntr_status mats_solve(MatsState& st, const Prob& P, bool use_guess, double tol,
   double prev = -1;
   int since_inv = 0;
   for (int it = 0; it < max_iter; it++) {
-    if ((e = launch_matvec(N, d, st.A, P.Gmat, st.g, st.r, s))) return hip_fail(e, "residual");
-    if ((e = hipMemsetAsync(st.norms, 0, 2 * sizeof(double), s))) return hip_fail(e, "norm clear");
+    if ((e = launch_matvec(N, d, st.A, P.Gmat, st.g, st.r, s, st.norms))) return hip_fail(e, "residual");
     if ((e = launch_axpy_norm(N * d, P.Gmat, nullptr, st.r, st.g, st.norms, s))) return hip_fail(e, "norm");
     double nrm[2];
     if ((e = hipMemcpyAsync(nrm, st.norms, sizeof nrm, hipMemcpyDeviceToHost, s)) ||
@@ -298,8 +297,7 @@ cntr_status mats_solve(MatsState& st, const Prob& P, bool use_guess, double tol,
     }
     prev = rel;
     since_inv++;
-    if ((e = launch_matvec(N, d, st.Ainv, st.r, nullptr, st.dx, s))) return hip_fail(e, "correction");
-    if ((e = hipMemsetAsync(st.norms, 0, 2 * sizeof(double), s))) return hip_fail(e, "norm clear");
+    if ((e = launch_matvec(N, d, st.Ainv, st.r, nullptr, st.dx, s, st.norms))) return hip_fail(e, "correction");
     if ((e = launch_axpy_norm(N * d, P.Gmat, st.dx, st.r, st.g, st.norms, s))) return hip_fail(e, "update");
   }
   return fail(CNTR_ENOCONV, "Matsubara refinement did not reach its tolerance");

@@ -81,9 +81,10 @@ hipError_t launch_gj_inverse(int N, cplx* Amat, cplx* work, int* piv, int* statu
                              hipStream_t s);
 // complex elements of the work buffer of launch_gj_inverse
 size_t gj_work_elems(int N);
-// y = X v  (X: N x N, v, y: N x nrhs); y = b - X v when b != nullptr
+// y = X v  (X: N x N, v, y: N x nrhs); y = b - X v when b != nullptr;
+// zero2[0..1] = 0 when zero2 != nullptr (accumulators of a following norm)
 hipError_t launch_matvec(int N, int nrhs, const cplx* X, const cplx* v, const cplx* b, cplx* y,
-                         hipStream_t s);
+                         hipStream_t s, double* zero2 = nullptr);
 hipError_t launch_mix(int len, cplx* x, cplx* keep, double a, bool first, hipStream_t s);
 hipError_t launch_axpy_norm(int len, cplx* x, const cplx* dx, const cplx* r, const cplx* g,
                             double* norms, hipStream_t s);

@@ -206,18 +206,18 @@ __global__ __launch_bounds__(NT3) void k_gj_unpivot(int N, cplx* A, const int* p
   }
 }
 
-// ------------------------------------ blocked Gauss-Jordan (N <= 2 NGJ)
+// ----------------------------------- blocked Gauss-Jordan (N <= GJT GJH)
 // Panels of GJB columns. For the panel columns c0..c0+nb-1 the GJ steps run
-// in one workgroup with the panel in registers (thread t holds rows t and
-// t + NGJ): pivot search over the rows r >= c, row interchange, and the
-// in-place update of the panel (column c becomes column c of the inverse
-// form). The row interchanges of the other columns are applied once per
-// panel, and their pivot rows (after the interchanges) go to prbuf. The other
-// columns then take the whole panel as one rank-nb update (block identity of
-// the in-place elimination): block rows  A_1j := A11' A_1j,  other rows
-// A_ij += A_i1' A_1j, with the panel ' after its steps and A_1j the pivot rows
-// before them.
+// in one workgroup with the panel in registers (thread t holds the rows
+// t + h GJT, h < GJH): pivot search over the rows r >= c, row interchange,
+// and the in-place update of the panel (column c becomes column c of the
+// inverse form). The rows that the panel's interchanges move are copied,
+// interchanged, to ob. The other columns then take the whole panel as one
+// rank-nb update (block identity of the in-place elimination): block rows
+// A_1j := A11' A_1j, other rows A_ij += A_i1' A_1j, with the panel ' after
+// its steps and A_1j the pivot rows before them.
 constexpr int GJB = 8;
+constexpr int GJT = 512, GJH = 4;  // panel workgroup: GJT threads, GJH rows each (N <= GJT GJH)
 
 __device__ inline void gj_argmax(double& v, int& i) {
   // ties: smaller index
@@ -232,19 +232,19 @@ __device__ inline void gj_argmax(double& v, int& i) {
   }
 }
 
-__global__ __launch_bounds__(NGJ) void k_gjb_panel(int N, int c0, int nb, cplx* A, cplx* prbuf, int* piv,
-                                                   int* status) {
-  __shared__ double wv[NGJ / 64];
-  __shared__ int wi[NGJ / 64];
+__global__ __launch_bounds__(GJT) void k_gjb_panel(int N, int c0, int nb, cplx* A, cplx* ob, int* rlist,
+                                                   int* piv, int* status) {
+  __shared__ double wv[GJT / 64];
+  __shared__ int wi[GJT / 64];
   __shared__ cplx xr[2][GJB];  // rows being interchanged
   __shared__ cplx pr[GJB];     // pivot row of the step
   __shared__ int s_p, s_ok;
   __shared__ int dst[2 * GJB], src[2 * GJB], s_m;
   int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  cplx L[2][GJB];
+  cplx L[GJH][GJB];
 #pragma unroll
-  for (int h = 0; h < 2; h++) {
-    int r = t + h * NGJ;
+  for (int h = 0; h < GJH; h++) {
+    int r = t + h * GJT;
 #pragma unroll
     for (int j = 0; j < GJB; j++) L[h][j] = (r < N && j < nb) ? A[(long)r * N + c0 + j] : mk(0, 0);
   }
@@ -254,8 +254,8 @@ __global__ __launch_bounds__(NGJ) void k_gjb_panel(int N, int c0, int nb, cplx* 
     double best = -1;
     int bi = c;
 #pragma unroll
-    for (int h = 0; h < 2; h++) {
-      int r = t + h * NGJ;
+    for (int h = 0; h < GJH; h++) {
+      int r = t + h * GJT;
       double v = -1;
 #pragma unroll
       for (int j = 0; j < GJB; j++)
@@ -274,7 +274,7 @@ __global__ __launch_bounds__(NGJ) void k_gjb_panel(int N, int c0, int nb, cplx* 
     if (t == 0) {
       double bb = wv[0];
       int ii = wi[0];
-      for (int w = 1; w < NGJ / 64; w++)
+      for (int w = 1; w < GJT / 64; w++)
         if (wv[w] > bb || (wv[w] == bb && wi[w] < ii)) {
           bb = wv[w];
           ii = wi[w];
@@ -292,16 +292,16 @@ __global__ __launch_bounds__(NGJ) void k_gjb_panel(int N, int c0, int nb, cplx* 
     // interchange rows c and p of the panel
     if (p != c) {
 #pragma unroll
-      for (int h = 0; h < 2; h++) {
-        int r = t + h * NGJ;
+      for (int h = 0; h < GJH; h++) {
+        int r = t + h * GJT;
         if (r == c || r == p)
 #pragma unroll
           for (int j = 0; j < GJB; j++) xr[r == c ? 0 : 1][j] = L[h][j];
       }
       __syncthreads();
 #pragma unroll
-      for (int h = 0; h < 2; h++) {
-        int r = t + h * NGJ;
+      for (int h = 0; h < GJH; h++) {
+        int r = t + h * GJT;
         if (r == c || r == p)
 #pragma unroll
           for (int j = 0; j < GJB; j++) L[h][j] = xr[r == c ? 1 : 0][j];
@@ -309,8 +309,8 @@ __global__ __launch_bounds__(NGJ) void k_gjb_panel(int N, int c0, int nb, cplx* 
     }
     // pivot row
 #pragma unroll
-    for (int h = 0; h < 2; h++)
-      if (t + h * NGJ == c)
+    for (int h = 0; h < GJH; h++)
+      if (t + h * GJT == c)
 #pragma unroll
         for (int j = 0; j < GJB; j++) pr[j] = L[h][j];
     __syncthreads();
@@ -320,8 +320,8 @@ __global__ __launch_bounds__(NGJ) void k_gjb_panel(int N, int c0, int nb, cplx* 
       if (j == b) pv = pr[j];
     cplx ipv = s_ok ? cdiv(mk(1, 0), pv) : mk(0, 0);
 #pragma unroll
-    for (int h = 0; h < 2; h++) {
-      int r = t + h * NGJ;
+    for (int h = 0; h < GJH; h++) {
+      int r = t + h * GJT;
       if (r >= N) continue;
       if (r == c) {
 #pragma unroll
@@ -338,8 +338,8 @@ __global__ __launch_bounds__(NGJ) void k_gjb_panel(int N, int c0, int nb, cplx* 
     __syncthreads();  // pr and xr are free
   }
 #pragma unroll
-  for (int h = 0; h < 2; h++) {
-    int r = t + h * NGJ;
+  for (int h = 0; h < GJH; h++) {
+    int r = t + h * GJT;
     if (r < N)
 #pragma unroll
       for (int j = 0; j < GJB; j++)
@@ -374,61 +374,76 @@ __global__ __launch_bounds__(NGJ) void k_gjb_panel(int N, int c0, int nb, cplx* 
       src[ip] = tmp;
     }
     s_m = m;
+    rlist[0] = m;
+    for (int i = 0; i < m; i++) rlist[1 + i] = dst[i];
   }
   __syncthreads();
+  // rows dst[i] after the interchanges, columns outside the panel, to ob[i]
+  // (the update reads them from there; A itself is rewritten by the update)
   int m = s_m;
-  for (int q = t; q < N; q += NGJ) {
-    if (q >= c0 && q < c0 + nb) continue;
-    cplx v[2 * GJB];
-#pragma unroll
-    for (int i = 0; i < 2 * GJB; i++)
-      if (i < m) v[i] = A[(long)src[i] * N + q];
-#pragma unroll
-    for (int i = 0; i < 2 * GJB; i++)
-      if (i < m) A[(long)dst[i] * N + q] = v[i];
-    // pivot rows after the interchanges (block rows c0..c0+nb-1)
-#pragma unroll
-    for (int i = 0; i < 2 * GJB; i++)
-      if (i < m && dst[i] >= c0 && dst[i] < c0 + nb) prbuf[(long)(dst[i] - c0) * N + q] = v[i];
+  for (int i = 0; i < m; i++) {
+    const cplx* from = A + (long)src[i] * N;
+    cplx* to = ob + (long)i * N;
+    for (int q = t; q < N; q += GJT)
+      if (q < c0 || q >= c0 + nb) to[q] = from[q];
   }
 }
 
 // Rank-nb update of the columns outside the panel; a workgroup covers NT3
-// consecutive columns and GJR rows.
+// consecutive columns and GJR rows. Rows involved in the panel's
+// interchanges take their (interchanged) old values from ob.
 constexpr int GJR = 16;
-__global__ __launch_bounds__(NT3) void k_gjb_update(int N, int c0, int nb, cplx* A, const cplx* prbuf) {
+__global__ __launch_bounds__(NT3) void k_gjb_update(int N, int c0, int nb, cplx* A, const cplx* ob,
+                                                    const int* rlist) {
   __shared__ cplx ps[GJR][GJB];
+  __shared__ int rl[2 * GJB + 1];
   int t = threadIdx.x;
   int q = blockIdx.x * NT3 + t, r0 = blockIdx.y * GJR;
   for (int i = t; i < GJR * GJB; i += NT3) {
     int rr = r0 + i / GJB, j = i % GJB;
     ps[i / GJB][j] = (rr < N && j < nb) ? A[(long)rr * N + c0 + j] : mk(0, 0);
   }
+  if (t <= 2 * GJB) rl[t] = rlist[t];
   __syncthreads();
   if (q >= N || (q >= c0 && q < c0 + nb)) return;
+  int m = rl[0];
+  // pivot rows (block rows c0 + j) after the interchanges
   cplx y[GJB];
 #pragma unroll
-  for (int j = 0; j < GJB; j++) y[j] = j < nb ? prbuf[(long)j * N + q] : mk(0, 0);
+  for (int j = 0; j < GJB; j++) {
+    int ij = 0;
+    for (int i = 0; i < m; i++)
+      if (rl[1 + i] == c0 + j) ij = i;
+    y[j] = j < nb ? ob[(long)ij * N + q] : mk(0, 0);
+  }
   for (int i = 0; i < GJR; i++) {
     int r = r0 + i;
     if (r >= N) break;
     bool blk = r >= c0 && r < c0 + nb;
-    cplx v = blk ? mk(0, 0) : A[(long)r * N + q];
+    cplx v = mk(0, 0);
+    if (!blk) {
+      int ir = -1;
+      for (int u = 0; u < m; u++)
+        if (rl[1 + u] == r) ir = u;
+      v = ir >= 0 ? ob[(long)ir * N + q] : A[(long)r * N + q];
+    }
 #pragma unroll
     for (int j = 0; j < GJB; j++) v = v + ps[i][j] * y[j];
     A[(long)r * N + q] = v;
   }
 }
 
-size_t gj_work_elems(int N) { return (size_t)(GJB > 2 ? GJB : 2) * N; }
+// ob (2 GJB rows of N) and the list of the rows involved (2 GJB + 1 ints)
+size_t gj_work_elems(int N) { return (size_t)(2 * GJB) * N + 4 * GJB; }
 
 hipError_t launch_gj_inverse(int N, cplx* A, cplx* work, int* piv, int* status, hipStream_t s) {
-  if (N <= 2 * NGJ) {
+  if (N <= GJT * GJH) {
     dim3 gu((N + NT3 - 1) / NT3, (N + GJR - 1) / GJR);
     for (int c0 = 0; c0 < N; c0 += GJB) {
       int nb = N - c0 < GJB ? N - c0 : GJB;
-      k_gjb_panel<<<1, NGJ, 0, s>>>(N, c0, nb, A, work, piv, status);
-      k_gjb_update<<<gu, NT3, 0, s>>>(N, c0, nb, A, work);
+      int* rlist = (int*)(work + (size_t)(2 * GJB) * N);
+      k_gjb_panel<<<1, GJT, 0, s>>>(N, c0, nb, A, work, rlist, piv, status);
+      k_gjb_update<<<gu, NT3, 0, s>>>(N, c0, nb, A, work, rlist);
     }
   } else {
     cplx* col = work;
@@ -449,7 +464,9 @@ hipError_t launch_gj_inverse(int N, cplx* A, cplx* work, int* piv, int* status, 
 // One wavefront per row r: y_r = X_r v (or b_r - X_r v); four row elements
 // (and their right-hand sides) are loaded per round.
 template <int NR>
-__global__ __launch_bounds__(NT3) void k_matvec(int N, const cplx* X, const cplx* v, const cplx* b, cplx* y) {
+__global__ __launch_bounds__(NT3) void k_matvec(int N, const cplx* X, const cplx* v, const cplx* b, cplx* y,
+                                                double* zero2) {
+  if (zero2 && blockIdx.x == 0 && threadIdx.x < 2) zero2[threadIdx.x] = 0.0;
   int lane = threadIdx.x % 64;
   long r = (long)blockIdx.x * (NT3 / 64) + threadIdx.x / 64;
   if (r >= N) return;
@@ -491,17 +508,17 @@ __global__ __launch_bounds__(NT3) void k_matvec(int N, const cplx* X, const cplx
 }
 
 hipError_t launch_matvec(int N, int nrhs, const cplx* X, const cplx* v, const cplx* b, cplx* y,
-                         hipStream_t s) {
+                         hipStream_t s, double* zero2) {
   int g = (N + 3) / 4;
   switch (nrhs) {
-    case 1: k_matvec<1><<<g, NT3, 0, s>>>(N, X, v, b, y); break;
-    case 2: k_matvec<2><<<g, NT3, 0, s>>>(N, X, v, b, y); break;
-    case 3: k_matvec<3><<<g, NT3, 0, s>>>(N, X, v, b, y); break;
-    case 4: k_matvec<4><<<g, NT3, 0, s>>>(N, X, v, b, y); break;
-    case 5: k_matvec<5><<<g, NT3, 0, s>>>(N, X, v, b, y); break;
-    case 6: k_matvec<6><<<g, NT3, 0, s>>>(N, X, v, b, y); break;
-    case 7: k_matvec<7><<<g, NT3, 0, s>>>(N, X, v, b, y); break;
-    case 8: k_matvec<8><<<g, NT3, 0, s>>>(N, X, v, b, y); break;
+    case 1: k_matvec<1><<<g, NT3, 0, s>>>(N, X, v, b, y, zero2); break;
+    case 2: k_matvec<2><<<g, NT3, 0, s>>>(N, X, v, b, y, zero2); break;
+    case 3: k_matvec<3><<<g, NT3, 0, s>>>(N, X, v, b, y, zero2); break;
+    case 4: k_matvec<4><<<g, NT3, 0, s>>>(N, X, v, b, y, zero2); break;
+    case 5: k_matvec<5><<<g, NT3, 0, s>>>(N, X, v, b, y, zero2); break;
+    case 6: k_matvec<6><<<g, NT3, 0, s>>>(N, X, v, b, y, zero2); break;
+    case 7: k_matvec<7><<<g, NT3, 0, s>>>(N, X, v, b, y, zero2); break;
+    case 8: k_matvec<8><<<g, NT3, 0, s>>>(N, X, v, b, y, zero2); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
