@@ -234,11 +234,13 @@ __device__ inline void gj_argmax(double& v, int& i) {
 
 __global__ __launch_bounds__(GJT) void k_gjb_panel(int N, int c0, int nb, cplx* A, cplx* ob, int* rlist,
                                                    int* piv, int* status) {
-  __shared__ double wv[GJT / 64];
-  __shared__ int wi[GJT / 64];
-  __shared__ cplx xr[2][GJB];  // rows being interchanged
-  __shared__ cplx pr[GJB];     // pivot row of the step
-  __shared__ int s_p, s_ok;
+  // per-step LDS, double-buffered by the parity of the step (one barrier
+  // fewer per step)
+  __shared__ double wv[2][GJT / 64];
+  __shared__ int wi[2][GJT / 64];
+  __shared__ cplx xr[2][2][GJB];  // rows being interchanged
+  __shared__ cplx pr[2][GJB];     // pivot row of the step
+  __shared__ int s_piv[GJB];
   __shared__ int dst[2 * GJB], src[2 * GJB], s_m;
   int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   cplx L[GJH][GJB];
@@ -249,8 +251,8 @@ __global__ __launch_bounds__(GJT) void k_gjb_panel(int N, int c0, int nb, cplx* 
     for (int j = 0; j < GJB; j++) L[h][j] = (r < N && j < nb) ? A[(long)r * N + c0 + j] : mk(0, 0);
   }
   for (int b = 0; b < nb; b++) {
-    int c = c0 + b;
-    // pivot: largest |a_rc|^2 over the rows r >= c
+    int c = c0 + b, sb = b & 1;
+    // pivot: largest |a_rc|^2 over the rows r >= c (ties: smallest row)
     double best = -1;
     int bi = c;
 #pragma unroll
@@ -267,36 +269,34 @@ __global__ __launch_bounds__(GJT) void k_gjb_panel(int N, int c0, int nb, cplx* 
     }
     gj_argmax(best, bi);
     if (lane == 0) {
-      wv[wave] = best;
-      wi[wave] = bi;
+      wv[sb][wave] = best;
+      wi[sb][wave] = bi;
     }
     __syncthreads();
-    if (t == 0) {
-      double bb = wv[0];
-      int ii = wi[0];
-      for (int w = 1; w < GJT / 64; w++)
-        if (wv[w] > bb || (wv[w] == bb && wi[w] < ii)) {
-          bb = wv[w];
-          ii = wi[w];
-        }
-      s_ok = bb > 0.0;
-      if (!s_ok) {
-        *status = CNTR_ESINGULAR;
-        ii = c;
+    // every thread combines the wave results (same order, same answer)
+    double bb = wv[sb][0];
+    int p = wi[sb][0];
+#pragma unroll
+    for (int w = 1; w < GJT / 64; w++)
+      if (wv[sb][w] > bb || (wv[sb][w] == bb && wi[sb][w] < p)) {
+        bb = wv[sb][w];
+        p = wi[sb][w];
       }
-      s_p = ii;
-      piv[c] = ii;
+    bool ok = bb > 0.0;
+    if (!ok) p = c;
+    if (t == 0) {
+      if (!ok) *status = CNTR_ESINGULAR;
+      s_piv[b] = p;
+      piv[c] = p;
     }
-    __syncthreads();
-    int p = s_p;
-    // interchange rows c and p of the panel
+    // interchange rows c and p of the panel; the pivot row
     if (p != c) {
 #pragma unroll
       for (int h = 0; h < GJH; h++) {
         int r = t + h * GJT;
         if (r == c || r == p)
 #pragma unroll
-          for (int j = 0; j < GJB; j++) xr[r == c ? 0 : 1][j] = L[h][j];
+          for (int j = 0; j < GJB; j++) xr[sb][r == c ? 0 : 1][j] = L[h][j];
       }
       __syncthreads();
 #pragma unroll
@@ -304,38 +304,39 @@ __global__ __launch_bounds__(GJT) void k_gjb_panel(int N, int c0, int nb, cplx* 
         int r = t + h * GJT;
         if (r == c || r == p)
 #pragma unroll
-          for (int j = 0; j < GJB; j++) L[h][j] = xr[r == c ? 1 : 0][j];
+          for (int j = 0; j < GJB; j++) L[h][j] = xr[sb][r == c ? 1 : 0][j];
       }
     }
-    // pivot row
 #pragma unroll
     for (int h = 0; h < GJH; h++)
       if (t + h * GJT == c)
 #pragma unroll
-        for (int j = 0; j < GJB; j++) pr[j] = L[h][j];
+        for (int j = 0; j < GJB; j++) pr[sb][j] = L[h][j];
     __syncthreads();
     cplx pv = mk(0, 0);
 #pragma unroll
     for (int j = 0; j < GJB; j++)
-      if (j == b) pv = pr[j];
-    cplx ipv = s_ok ? cdiv(mk(1, 0), pv) : mk(0, 0);
+      if (j == b) pv = pr[sb][j];
+    cplx ipv = ok ? cdiv(mk(1, 0), pv) : mk(0, 0);
+    cplx ps[GJB];  // pivot row times 1 / pivot
+#pragma unroll
+    for (int j = 0; j < GJB; j++) ps[j] = j == b ? ipv : pr[sb][j] * ipv;
 #pragma unroll
     for (int h = 0; h < GJH; h++) {
       int r = t + h * GJT;
       if (r >= N) continue;
       if (r == c) {
 #pragma unroll
-        for (int j = 0; j < GJB; j++) L[h][j] = j == b ? ipv : pr[j] * ipv;
+        for (int j = 0; j < GJB; j++) L[h][j] = ps[j];
       } else {
         cplx f = mk(0, 0);
 #pragma unroll
         for (int j = 0; j < GJB; j++)
           if (j == b) f = L[h][j];
 #pragma unroll
-        for (int j = 0; j < GJB; j++) L[h][j] = j == b ? -(f * ipv) : L[h][j] - f * (pr[j] * ipv);
+        for (int j = 0; j < GJB; j++) L[h][j] = j == b ? -(f * ipv) : L[h][j] - f * ps[j];
       }
     }
-    __syncthreads();  // pr and xr are free
   }
 #pragma unroll
   for (int h = 0; h < GJH; h++) {
@@ -345,47 +346,75 @@ __global__ __launch_bounds__(GJT) void k_gjb_panel(int N, int c0, int nb, cplx* 
       for (int j = 0; j < GJB; j++)
         if (j < nb) A[(long)r * N + c0 + j] = L[h][j];
   }
-  // the panel's interchanges as one permutation of the rows involved:
-  // row dst[i] receives the old row src[i]
+  // the panel's interchanges as one permutation of the rows involved (row
+  // dst[i] receives the old row src[i]), built in registers: slots 0..nb-1
+  // are the block rows, slot GJB + b the pivot row of step b when it lies
+  // outside the block and is new (else empty)
+  __syncthreads();  // s_piv
   if (t == 0) {
-    int m = 0;
-    for (int b = 0; b < nb; b++) {
-      int rr[2] = {c0 + b, piv[c0 + b]};
-      for (int u = 0; u < 2; u++) {
-        bool seen = false;
-        for (int i = 0; i < m; i++) seen = seen || dst[i] == rr[u];
-        if (!seen) {
-          dst[m] = rr[u];
-          src[m] = rr[u];
-          m++;
+    int dl[2 * GJB], sl[2 * GJB];
+#pragma unroll
+    for (int i = 0; i < GJB; i++) dl[i] = i < nb ? c0 + i : -1;
+#pragma unroll
+    for (int b = 0; b < GJB; b++) {
+      int pb = b < nb ? s_piv[b] : -1;
+      bool keep = pb >= c0 + nb;
+#pragma unroll
+      for (int b2 = 0; b2 < GJB; b2++)
+        if (b2 < b) keep = keep && dl[GJB + b2] != pb;
+      dl[GJB + b] = keep ? pb : -1;
+    }
+#pragma unroll
+    for (int i = 0; i < 2 * GJB; i++) sl[i] = dl[i];
+#pragma unroll
+    for (int b = 0; b < GJB; b++) {
+      int c = c0 + b, pb = b < nb ? s_piv[b] : c;
+      if (pb != c) {
+        int vc = -1, vp = -1;
+#pragma unroll
+        for (int i = 0; i < 2 * GJB; i++) {
+          if (dl[i] == c) vc = sl[i];
+          if (dl[i] == pb) vp = sl[i];
+        }
+#pragma unroll
+        for (int i = 0; i < 2 * GJB; i++) {
+          if (dl[i] == c) sl[i] = vp;
+          else if (dl[i] == pb) sl[i] = vc;
         }
       }
     }
-    for (int b = 0; b < nb; b++) {
-      int c = c0 + b, p = piv[c];
-      if (p == c) continue;
-      int ic = 0, ip = 0;
-      for (int i = 0; i < m; i++) {
-        if (dst[i] == c) ic = i;
-        if (dst[i] == p) ip = i;
+    int m = 0;
+#pragma unroll
+    for (int i = 0; i < 2 * GJB; i++)
+      if (dl[i] >= 0) {
+        dst[m] = dl[i];
+        src[m] = sl[i];
+        rlist[1 + m] = dl[i];
+        m++;
       }
-      int tmp = src[ic];
-      src[ic] = src[ip];
-      src[ip] = tmp;
-    }
     s_m = m;
     rlist[0] = m;
-    for (int i = 0; i < m; i++) rlist[1 + i] = dst[i];
   }
   __syncthreads();
   // rows dst[i] after the interchanges, columns outside the panel, to ob[i]
   // (the update reads them from there; A itself is rewritten by the update)
   int m = s_m;
-  for (int i = 0; i < m; i++) {
-    const cplx* from = A + (long)src[i] * N;
-    cplx* to = ob + (long)i * N;
-    for (int q = t; q < N; q += GJT)
-      if (q < c0 || q >= c0 + nb) to[q] = from[q];
+  for (int i0 = 0; i0 < m; i0 += 8) {
+    cplx v[8][GJH];  // 8 GJH loads in flight
+#pragma unroll
+    for (int u = 0; u < 8; u++)
+#pragma unroll
+      for (int h = 0; h < GJH; h++) {
+        int i = i0 + u, q = t + h * GJT;
+        v[u][h] = (i < m && q < N) ? A[(long)src[i] * N + q] : mk(0, 0);
+      }
+#pragma unroll
+    for (int u = 0; u < 8; u++)
+#pragma unroll
+      for (int h = 0; h < GJH; h++) {
+        int i = i0 + u, q = t + h * GJT;
+        if (i < m && q < N && (q < c0 || q >= c0 + nb)) ob[(long)i * N + q] = v[u][h];
+      }
   }
 }
 
