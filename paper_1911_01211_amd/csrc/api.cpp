@@ -461,7 +461,10 @@ cntr_status cntr_dyson_step(int32_t tstp, int32_t count, const cntr_grid* grids,
   if ((st = make_arg(s, sc, v, 0, &pa))) return st;
   Scratch scr = lay.sc;
   scr.base = sc->buf;
-  hipError_t e = tstp <= k ? launch_start(pa, scr, d, ntau, s) : launch_step(pa, scr, tstp, d, s);
+  bool shared = true;  // one Sigma (statistics, grid) for every problem
+  for (int i = 1; i < count; i++)
+    shared = shared && v[i].Stv == v[0].Stv && v[i].sig == v[0].sig && grids[i].nt == grids[0].nt;
+  hipError_t e = tstp <= k ? launch_start(pa, scr, d, ntau, s) : launch_step(pa, scr, tstp, d, s, shared);
   if (e != hipSuccess) return hip_fail(e, "cntr_dyson_step launch");
   return CNTR_OK;
 }

@@ -32,6 +32,7 @@ struct HistPlan {
   // the lesser boundary rows, one set per reduce tile
   int red_tiles[3];
   int walk_tiles;     // one reduce workgroup per problem (large batches)
+  int tau_shared;     // d = 1 batch sharing Sigma: tau source by k_tau_shared
   long tail_off;      // in blocks
   long total_blocks;  // scratch blocks of the step
 };
@@ -55,7 +56,11 @@ HistPlan make_plan(int n, int k, int ntau, int d);
 // scratch bytes (per problem) for the step at the largest n = nt
 size_t step_scratch_bytes(int nt, int k, int ntau, int d);
 
-hipError_t launch_step(const ProbArg& pa, const Scratch& sc, int n, int d, hipStream_t s);
+// shared_sigma: every problem of the call has the same Sigma (pointer) and
+// statistics; for d = 1 batches the tau source is then one product of the
+// shared (Nτ+1) x (Nτ+1) operator with the problems' G^M
+hipError_t launch_step(const ProbArg& pa, const Scratch& sc, int n, int d, hipStream_t s,
+                       bool shared_sigma = false);
 hipError_t launch_start(const ProbArg& pa, const Scratch& sc, int d, int ntau, hipStream_t s);
 hipError_t launch_sigma2b(const ProbArg& pa, int n, int d, int nmax_elems, double nbar,
                           hipStream_t s);

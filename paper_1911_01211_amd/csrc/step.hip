@@ -1099,8 +1099,11 @@ __global__ __launch_bounds__(NTHR) void k_history(ProbArg pa, Scratch sc, HistPl
     else hist_stg<D>(P, sc, pi, n, pl, job, mt, ch, lds, shop);
     return;
   } else if constexpr (D <= 4) {
-    if (job == 2) tau_blk<D>(P, sc, pi, n, pl, mt, ch, lds);
-    else hist_blk<D>(P, sc, pi, n, pl, job, mt, ch, lds);
+    if (job == 2) {
+      if (!pl.tau_shared) tau_blk<D>(P, sc, pi, n, pl, mt, ch, lds);  // else k_tau_shared
+    } else {
+      hist_blk<D>(P, sc, pi, n, pl, job, mt, ch, lds);
+    }
     return;
   }
   if (job == 2) {
@@ -1922,12 +1925,102 @@ static double hist_block_macs(int n, int k, int ntau) {
   return macs;
 }
 
+// ----------------------------------- TAU SOURCE OF A SHARED SIGMA (d = 1)
+// Batches whose problems share Sigma (k-points with a local self-energy):
+// the tau source of every problem at once, out[m][p] = sum_v A[m][v]
+// G^M_p[v], with one operator built from the slice's Sigma^rceil_{n,.}:
+//   A[m][v] = xi w(m, ntau-v) Sigma^rceil_{n,m-ntau+v}   (m > k, ntau-v <= m)
+//           + w(ntau-m, v) Sigma^rceil_{n,m+v}            (m < ntau-k, m+v <= ntau),
+// the Gregory parts of Eqs. ctv2 and ctv3 with J = ntau - v and J = m + v.
+// A workgroup computes 32 outputs m x 32 problems (2 x 2 per thread) over
+// chunks of 32 v in LDS (the next chunk of G^M in flight while one is
+// multiplied); the sums are chunk 0 of the tau-source partials.
+constexpr int TSM = 32, TSP = 32, TSV = 32, TS_NTAU = 512;
+__global__ __launch_bounds__(NTHR) void k_tau_shared(ProbArg pa, Scratch sc, HistPlan pl) {
+  __shared__ cplx s_row[TS_NTAU];
+  __shared__ cplx sa[TSM][TSV + 1];
+  __shared__ cplx sx[TSV][TSP + 1];
+  __shared__ double s_om[KMAX + 1];
+  __shared__ const cplx* s_gm[TSP];
+  const Prob& P0 = pa.get(0);
+  int n = pl.n, ntau = P0.ntau, k = P0.k, tid = threadIdx.x;
+  int m0 = blockIdx.x * TSM, p0 = blockIdx.y * TSP;
+  const KW& W = c_kw[k];
+  WReg wr;
+  wr.load(W, s_om);
+  double xi = P0.sig;
+  const cplx* Srow = P0.Stv + (size_t)n * (ntau + 1);
+  for (int j = tid; j <= ntau; j += NTHR) s_row[j] = gld(Srow + j);
+  if (tid < TSP) s_gm[tid] = pa.get(min(p0 + tid, pa.count - 1)).Gmat;
+  __syncthreads();
+  int tm = tid / 16, tp = tid % 16;
+  cplx acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; i++)
+#pragma unroll
+    for (int j = 0; j < 2; j++) acc[i][j] = mk(0, 0);
+  constexpr int NX = TSV * TSP / NTHR;  // G^M values per thread and chunk
+  cplx xn[NX];
+  auto load_x = [&](int v0) {
+#pragma unroll
+    for (int u = 0; u < NX; u++) {
+      int i = tid + u * NTHR, vv = i / TSP, pp = i % TSP, v = v0 + vv;
+      xn[u] = v <= ntau ? gld(s_gm[pp] + v) : mk(0, 0);
+    }
+  };
+  load_x(0);
+  for (int v0 = 0; v0 <= ntau; v0 += TSV) {
+    // operator tile A[m0 .. m0+31][v0 .. v0+31]
+    for (int i = tid; i < TSM * TSV; i += NTHR) {
+      int mm = i / TSV, vv = i % TSV, m = m0 + mm, v = v0 + vv;
+      cplx a = mk(0, 0);
+      if (m <= ntau && v <= ntau) {
+        int J = ntau - v;
+        if (m > k && J <= m) a = a + (xi * wr.w(m, J)) * s_row[m - J];
+        if (m < ntau - k && m + v <= ntau) a = a + wr.w(ntau - m, v) * s_row[m + v];
+      }
+      sa[mm][vv] = a;
+    }
+#pragma unroll
+    for (int u = 0; u < NX; u++) {
+      int i = tid + u * NTHR;
+      sx[i / TSP][i % TSP] = xn[u];
+    }
+    __syncthreads();
+    if (v0 + TSV <= ntau) load_x(v0 + TSV);
+#pragma unroll 8
+    for (int vv = 0; vv < TSV; vv++) {
+      cplx a0 = sa[2 * tm][vv], a1 = sa[2 * tm + 1][vv];
+      cplx x0 = sx[vv][2 * tp], x1 = sx[vv][2 * tp + 1];
+      cfma(acc[0][0], a0, x0);
+      cfma(acc[0][1], a0, x1);
+      cfma(acc[1][0], a1, x0);
+      cfma(acc[1][1], a1, x1);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 2; i++)
+#pragma unroll
+    for (int j = 0; j < 2; j++) {
+      int m = m0 + 2 * tm + i, p = p0 + 2 * tp + j;
+      if (m <= ntau && p < pa.count && n <= pa.get(p).nt) gst(sc.part(p) + pl.part_off[2] + m, acc[i][j]);
+    }
+}
+
 // ------------------------------------------------------------ launches
 template <int D>
-static hipError_t step_d(const ProbArg& pa, const Scratch& sc, int n, hipStream_t s) {
+static hipError_t step_d(const ProbArg& pa, const Scratch& sc, int n, hipStream_t s, bool shared_sigma) {
   const Prob& P0 = pa.one;  // d, k and ntau are uniform within a call
   int k = P0.k, ntau = P0.ntau;
   HistPlan pl = make_plan(n, k, ntau, D);
+  // one operator for the whole batch: d = 1, Sigma shared, the tau source in
+  // one chunk, enough problems for the product to pay
+  pl.tau_shared = D == 1 && shared_sigma && pa.count >= TSP && pl.nch[2] == 1 && ntau + 1 <= TS_NTAU;
+  if (pl.tau_shared) {
+    dim3 gt((ntau + TSM) / TSM, (pa.count + TSP - 1) / TSP);
+    k_tau_shared<<<gt, NTHR, 0, s>>>(pa, sc, pl);
+  }
   dim3 g1(pl.grid + 1, pa.count);
   hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr;
   if (g_prof.on) {
@@ -1955,16 +2048,16 @@ static hipError_t step_d(const ProbArg& pa, const Scratch& sc, int n, hipStream_
   return hipGetLastError();
 }
 
-hipError_t launch_step(const ProbArg& pa, const Scratch& sc, int n, int d, hipStream_t s) {
+hipError_t launch_step(const ProbArg& pa, const Scratch& sc, int n, int d, hipStream_t s, bool shared_sigma) {
   switch (d) {
-    case 1: return step_d<1>(pa, sc, n, s);
-    case 2: return step_d<2>(pa, sc, n, s);
-    case 3: return step_d<3>(pa, sc, n, s);
-    case 4: return step_d<4>(pa, sc, n, s);
-    case 5: return step_d<5>(pa, sc, n, s);
-    case 6: return step_d<6>(pa, sc, n, s);
-    case 7: return step_d<7>(pa, sc, n, s);
-    case 8: return step_d<8>(pa, sc, n, s);
+    case 1: return step_d<1>(pa, sc, n, s, shared_sigma);
+    case 2: return step_d<2>(pa, sc, n, s, shared_sigma);
+    case 3: return step_d<3>(pa, sc, n, s, shared_sigma);
+    case 4: return step_d<4>(pa, sc, n, s, shared_sigma);
+    case 5: return step_d<5>(pa, sc, n, s, shared_sigma);
+    case 6: return step_d<6>(pa, sc, n, s, shared_sigma);
+    case 7: return step_d<7>(pa, sc, n, s, shared_sigma);
+    case 8: return step_d<8>(pa, sc, n, s, shared_sigma);
   }
   return hipErrorInvalidValue;
 }

@@ -203,17 +203,22 @@ def test_sigma_local_parity(O):
     assert_slices(g, got, {key: getattr(So, key) for key in K.KEYS}, [-1, 0, 4, 11, g.nt], what="sigma_local")
 
 
-@pytest.mark.parametrize("case", ["kpoints", "bands"])
+@pytest.mark.parametrize("case", ["kpoints", "kpoints70", "bands"])
 def test_local_sigma_batch_solve(O, case):
     """Batched k-point propagation (one launch per step for all instances)
     with the local self-energy Sigma = 0.25 G_loc: Matsubara, bootstrap and
     predictor-corrector steps against the reference driver. kpoints: the
     single-band lattice eps_k(t) = -2 cos(k - A(t)) with the pulse A(t);
-    bands: two-orbital instances with seeded random Hermitian levels."""
+    kpoints70: 70 k-points, enough for the tau source of the shared Sigma as
+    one operator product (three problem tiles, the last ragged); bands:
+    two-orbital instances with seeded random Hermitian levels."""
     require_gpu()
     if case == "kpoints":
         g = W.GridSpec(nt=40, ntau=60, d=1, beta=10.0, h=0.02, k=5)
         eps = list(W.kpoint_band(g, 8))
+    elif case == "kpoints70":
+        g = W.GridSpec(nt=24, ntau=70, d=1, beta=10.0, h=0.02, k=5)
+        eps = list(W.kpoint_band(g, 70))
     else:
         g = W.GridSpec(nt=30, ntau=40, d=2, beta=5.0, h=0.03, k=5)
         r = W.rng(151)
