@@ -52,7 +52,9 @@ extern ProfState g_prof;
 
 
 int hist_tm(int d);
-HistPlan make_plan(int n, int k, int ntau, int d);
+// tau_split > 0: the tau source comes from k_tau_shared in tau_split chunks
+// (no history workgroups for it)
+HistPlan make_plan(int n, int k, int ntau, int d, int tau_split = 0);
 // scratch bytes (per problem) for the step at the largest n = nt
 size_t step_scratch_bytes(int nt, int k, int ntau, int d);
 

@@ -34,13 +34,17 @@ constexpr int STG_TJ = 32, STG_TJS = 16;
 
 static int cdiv_i(int a, int b) { return (a + b - 1) / b; }
 
+// k_tau_shared: tiles of TSM outputs x TSP problems, chunks of TSV terms;
+// the terms are split over TS_SPLIT workgroups (partial-sum chunks)
+constexpr int TSM = 32, TSP = 32, TSV = 32, TS_NTAU = 512, TS_SPLIT = 4;
+
 // Jobs: 0 retarded bulk, 1 left-mixing history, 2 tau source, 3 lesser
 // history (for the staged path only its part l >= m), 4 source C^<_1,
 // 5 source C^<_3, 6 tau-boundary corrections, 7 lesser history l < m (staged
 // path only).
 constexpr bool hist_staged(int d) { return d == 2 || d == 4; }
 
-HistPlan make_plan(int n, int k, int ntau, int d) {
+HistPlan make_plan(int n, int k, int ntau, int d, int tau_split) {
   HistPlan p{};
   p.n = n;
   p.staged = hist_staged(d);
@@ -72,7 +76,8 @@ HistPlan make_plan(int n, int k, int ntau, int d) {
     p.nch[j] = mout[j] > 0 ? cdiv_i(span[j], p.tj[j]) : 0;
     p.mtiles[j] = mout[j] > 0 ? cdiv_i(mout[j], p.tm[j]) : 0;
     if (j == 6) p.nch[j] = p.mtiles[j] = 1;  // one workgroup: both tau ends
-    p.wg_off[j + 1] = p.wg_off[j] + p.nch[j] * p.mtiles[j];
+    if (j == 2 && tau_split > 0) p.nch[j] = tau_split;
+    p.wg_off[j + 1] = p.wg_off[j] + ((j == 2 && tau_split > 0) ? 0 : p.nch[j] * p.mtiles[j]);
     p.part_off[j] = off;
     off += (long)p.nch[j] * mout[j];
   }
@@ -110,11 +115,12 @@ HistPlan make_plan(int n, int k, int ntau, int d) {
 size_t step_scratch_bytes(int nt, int k, int ntau, int d) {
   size_t mx = 0;
   // partial storage grows with n; check the largest few n (monotone)
-  for (int n = nt; n >= nt - 1 && n > k; n--) {
-    HistPlan p = make_plan(n, k, ntau, d);
-    size_t blocks = (size_t)p.total_blocks;
-    if (blocks > mx) mx = blocks;
-  }
+  for (int n = nt; n >= nt - 1 && n > k; n--)
+    for (int ts : {0, TS_SPLIT}) {
+      HistPlan p = make_plan(n, k, ntau, d, d == 1 ? ts : 0);
+      size_t blocks = (size_t)p.total_blocks;
+      if (blocks > mx) mx = blocks;
+    }
   return mx * d * d * sizeof(cplx);
 }
 
@@ -1934,8 +1940,8 @@ static double hist_block_macs(int n, int k, int ntau) {
 // the Gregory parts of Eqs. ctv2 and ctv3 with J = ntau - v and J = m + v.
 // A workgroup computes 32 outputs m x 32 problems (2 x 2 per thread) over
 // chunks of 32 v in LDS (the next chunk of G^M in flight while one is
-// multiplied); the sums are chunk 0 of the tau-source partials.
-constexpr int TSM = 32, TSP = 32, TSV = 32, TS_NTAU = 512;
+// multiplied). The terms are split over TS_SPLIT workgroups; split z writes
+// chunk z of the tau-source partials.
 __global__ __launch_bounds__(NTHR) void k_tau_shared(ProbArg pa, Scratch sc, HistPlan pl) {
   __shared__ cplx s_row[TS_NTAU];
   __shared__ cplx sa[TSM][TSV + 1];
@@ -1945,6 +1951,9 @@ __global__ __launch_bounds__(NTHR) void k_tau_shared(ProbArg pa, Scratch sc, His
   const Prob& P0 = pa.get(0);
   int n = pl.n, ntau = P0.ntau, k = P0.k, tid = threadIdx.x;
   int m0 = blockIdx.x * TSM, p0 = blockIdx.y * TSP;
+  // this workgroup's share of the terms v (whole chunks of TSV)
+  int nchunk = (ntau + TSV) / TSV, per = (nchunk + TS_SPLIT - 1) / TS_SPLIT;
+  int vbeg = blockIdx.z * per * TSV, vend = min(ntau + 1, (int)(blockIdx.z + 1) * per * TSV);
   const KW& W = c_kw[k];
   WReg wr;
   wr.load(W, s_om);
@@ -1968,8 +1977,8 @@ __global__ __launch_bounds__(NTHR) void k_tau_shared(ProbArg pa, Scratch sc, His
       xn[u] = v <= ntau ? gld(s_gm[pp] + v) : mk(0, 0);
     }
   };
-  load_x(0);
-  for (int v0 = 0; v0 <= ntau; v0 += TSV) {
+  if (vbeg < vend) load_x(vbeg);
+  for (int v0 = vbeg; v0 < vend; v0 += TSV) {
     // operator tile A[m0 .. m0+31][v0 .. v0+31]
     for (int i = tid; i < TSM * TSV; i += NTHR) {
       int mm = i / TSV, vv = i % TSV, m = m0 + mm, v = v0 + vv;
@@ -1987,7 +1996,7 @@ __global__ __launch_bounds__(NTHR) void k_tau_shared(ProbArg pa, Scratch sc, His
       sx[i / TSP][i % TSP] = xn[u];
     }
     __syncthreads();
-    if (v0 + TSV <= ntau) load_x(v0 + TSV);
+    if (v0 + TSV < vend) load_x(v0 + TSV);
 #pragma unroll 8
     for (int vv = 0; vv < TSV; vv++) {
       cplx a0 = sa[2 * tm][vv], a1 = sa[2 * tm + 1][vv];
@@ -2004,7 +2013,8 @@ __global__ __launch_bounds__(NTHR) void k_tau_shared(ProbArg pa, Scratch sc, His
 #pragma unroll
     for (int j = 0; j < 2; j++) {
       int m = m0 + 2 * tm + i, p = p0 + 2 * tp + j;
-      if (m <= ntau && p < pa.count && n <= pa.get(p).nt) gst(sc.part(p) + pl.part_off[2] + m, acc[i][j]);
+      if (m <= ntau && p < pa.count && n <= pa.get(p).nt)
+        gst(sc.part(p) + pl.part_off[2] + (size_t)blockIdx.z * (ntau + 1) + m, acc[i][j]);
     }
 }
 
@@ -2014,11 +2024,12 @@ static hipError_t step_d(const ProbArg& pa, const Scratch& sc, int n, hipStream_
   const Prob& P0 = pa.one;  // d, k and ntau are uniform within a call
   int k = P0.k, ntau = P0.ntau;
   HistPlan pl = make_plan(n, k, ntau, D);
-  // one operator for the whole batch: d = 1, Sigma shared, the tau source in
-  // one chunk, enough problems for the product to pay
-  pl.tau_shared = D == 1 && shared_sigma && pa.count >= TSP && pl.nch[2] == 1 && ntau + 1 <= TS_NTAU;
-  if (pl.tau_shared) {
-    dim3 gt((ntau + TSM) / TSM, (pa.count + TSP - 1) / TSP);
+  // one operator for the whole batch: d = 1, Sigma shared, enough problems
+  // for the product to pay
+  if (D == 1 && shared_sigma && pa.count >= TSP && ntau + 1 <= TS_NTAU) {
+    pl = make_plan(n, k, ntau, D, TS_SPLIT);
+    pl.tau_shared = 1;
+    dim3 gt((ntau + TSM) / TSM, (pa.count + TSP - 1) / TSP, TS_SPLIT);
     k_tau_shared<<<gt, NTHR, 0, s>>>(pa, sc, pl);
   }
   dim3 g1(pl.grid + 1, pa.count);
