@@ -87,6 +87,24 @@ def test_matsubara_parity(O, d, sig):
     assert relerr(Gd.mat.cpu().numpy(), Go.mat) < TOL
 
 
+@pytest.mark.parametrize("d,ntau", [(4, 511), (8, 260)])
+def test_matsubara_parity_large_system(O, d, ntau):
+    """Matsubara systems of (ntau+1) d = 2048 unknowns (the largest for the
+    blocked inverse, 256 panels) and 2088 (above it: one column per step)."""
+    require_gpu()
+    say(f"matsubara large d={d} ntau={ntau}")
+    g = W.GridSpec(nt=6, ntau=ntau, d=d, sig=-1, beta=8.0, h=0.05, k=5, mu=0.1)
+    r = W.rng(104, d)
+    S = W.random_contour(r, g, 0.15)
+    eps = rand_eps(r, g)
+    Go, So = ora(O, g, None), ora(O, g, S)
+    O.dyson_mat(Go, So, eps[0])
+    Gd, Sd = K.Contour(g), K.Contour(g, data=S)
+    K.init_matsubara([Gd], [Sd], [to_dev(eps)])
+    torch.cuda.synchronize()
+    assert relerr(Gd.mat.cpu().numpy(), Go.mat) < TOL
+
+
 # ------------------------------------------------------------------ start-up
 @pytest.mark.parametrize("d", [1, 2, 4, 8])
 def test_startup_parity(O, d):
