@@ -92,7 +92,15 @@ def run_gpu(args):
     # physical sanity of the last run: half filling on every site at t_nt
     L = G.les[-1].cpu().numpy()
     dens_dev = float(abs((L.diagonal().imag) - 0.5).max())
-    state = dict(G=G, S=S, emf=emf, e0=e0np, U=U)
+    # one slice at n = nt on the converged state: ncorr x (Sigma_2B + step)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(args.ncorr):
+        K.sigma_2b(g.nt, [G], [U], [S], eps0=[e0], eps_mf=[emf], nbar=0.5)
+        K.dyson_step(g.nt, [G], [S], [emf])
+    ev1.record()
+    torch.cuda.synchronize()
+    state = dict(G=G, S=S, emf=emf, e0=e0np, U=U, last_slice_ms=ev0.elapsed_time(ev1))
     return g, elapsed, prof, stats, dens_dev, state
 
 
@@ -212,14 +220,52 @@ def run_kpoints(args):
     prof = K.profile_end()
     nsteps = (args.kp_steps - g.k) * nk
     gbs = prof["hist_bytes"] / (prof["hist_ms"] * 1e-3) / 1e9 if prof["hist_ms"] > 0 else None
+
+    # the plain per-instance loop at the last timed slice: one step of 16
+    # instances, one call each, scaled to all instances, against the batched step
+    def timed(f):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        f()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1)
+
+    n_last, nloop = args.kp_steps, min(16, nk)
+    t_batch = min(timed(lambda: B.step(n_last)) for _ in range(3))
+    t_loop = min(timed(lambda: [K.dyson_step(n_last, [G[i]], [S], [eps[i]]) for i in range(nloop)])
+                 for _ in range(2)) * nk / nloop
     return {"workload": f"{nk} k-points, d=1, local Sigma = 0.25 G_loc, pulse A(t), beta=10, ntau=500, "
                         f"nt=2000 grid; steps {g.k + 1}..{args.kp_steps} timed",
             "value": nsteps / el, "unit": "instance time-steps/s", "instances": nk,
             "ms_per_slice": el / (args.kp_steps - g.k) * 1e3, "corrector_iterations": args.ncorr,
+            "loop_vs_batched_at_last_slice": {"slice": n_last, "batched_step_ms": t_batch,
+                                              "per_instance_loop_ms": t_loop, "speedup": t_loop / t_batch,
+                                              "loop_sample": f"{nloop} instances, scaled to {nk}"},
             "roofline": {"bound": "hbm", "kernel": "k_history<1>", "achieved": gbs, "peak": HBM_PEAK_GBS,
                          "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS if gbs else None,
                          "avg_launch_us": prof["hist_ms"] * 1e3 / max(1, prof["hist_launches"])},
             "note": "prefix of the run (the per-slice cost grows with n)"}
+
+
+def stream_bandwidth():
+    """Device copy of 1 GiB (1 GiB read + 1 GiB written), best of 5, in GB/s:
+    the attainable HBM rate that the roofline is also quoted against."""
+    import torch
+
+    src = torch.ones(1 << 27, dtype=torch.float64, device="cuda:0")
+    dst = torch.empty_like(src)
+    best = None
+    for _ in range(5):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        best = ms if best is None else min(best, ms)
+    del src, dst
+    return 2 * (1 << 30) / (best * 1e-3) / 1e9
 
 
 def profile_step(args):
@@ -335,6 +381,7 @@ def main():
               "(the per-GPU share of a sharded run is the single-GPU workload).", file=sys.stderr)
         sys.exit(2)
     g, elapsed, prof, stats, dens_dev, state = run_gpu(args)
+    stream_gbs = stream_bandwidth()
     nsteps = (g.nt - g.k) * args.steps
     value = nsteps / elapsed
     hist_gbs = prof["hist_bytes"] / (prof["hist_ms"] * 1e-3) / 1e9 if prof["hist_ms"] > 0 else None
@@ -359,10 +406,15 @@ def main():
                    "corrector_iterations": args.ncorr, "mats_iterations": stats.mats_iter,
                    "boot_iterations": stats.boot_iter},
         "fp64_tflops": tflops,
+        "sweeps_per_s": args.ncorr * args.steps / elapsed,
+        "last_slice_ms": state["last_slice_ms"],
         "time_step_share": prof["step_ms"] / (elapsed * 1e3),
         "roofline": {"bound": "hbm", "kernel": "k_history<4>", "achieved": hist_gbs,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": (hist_gbs / HBM_PEAK_GBS) if hist_gbs else None, "traffic": traffic,
+                     "frac": (hist_gbs / HBM_PEAK_GBS) if hist_gbs else None,
+                     "stream_gbs": stream_gbs,
+                     "frac_vs_stream": (hist_gbs / stream_gbs) if hist_gbs and stream_gbs else None,
+                     "traffic": traffic,
                      "traffic_at": traffic_at,
                      "launches": prof["hist_launches"],
                      "avg_launch_us": prof["hist_ms"] * 1e3 / max(1, prof["hist_launches"])},
