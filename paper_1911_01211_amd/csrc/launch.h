@@ -33,6 +33,7 @@ struct HistPlan {
   int red_tiles[3];
   int walk_tiles;     // one reduce workgroup per problem (large batches)
   int tau_shared;     // d = 1 batch sharing Sigma: tau source by k_tau_shared
+  int fuse_t;         // d = 1: job 1 also forms the job-5 row sums (no job-5 workgroups)
   long tail_off;      // in blocks
   long total_blocks;  // scratch blocks of the step
 };

@@ -69,6 +69,10 @@ HistPlan make_plan(int n, int k, int ntau, int d, int tau_split) {
       p.tj[j] = j == 2 ? p.TJS : p.TJ;
     }
   }
+  // d = 1: the mixing panel is read once for both of its consumers (job 1
+  // forms the job-5 row sums of each 64-column tile)
+  p.fuse_t = d == 1;
+  if (p.fuse_t) p.tj[5] = p.TM;
   long off = 0;
   p.wg_off[0] = 0;
   for (int j = 0; j < NJOB; j++) {
@@ -77,7 +81,8 @@ HistPlan make_plan(int n, int k, int ntau, int d, int tau_split) {
     p.mtiles[j] = mout[j] > 0 ? cdiv_i(mout[j], p.tm[j]) : 0;
     if (j == 6) p.nch[j] = p.mtiles[j] = 1;  // one workgroup: both tau ends
     if (j == 2 && tau_split > 0) p.nch[j] = tau_split;
-    p.wg_off[j + 1] = p.wg_off[j] + ((j == 2 && tau_split > 0) ? 0 : p.nch[j] * p.mtiles[j]);
+    bool none = (j == 2 && tau_split > 0) || (j == 5 && p.fuse_t);  // formed elsewhere
+    p.wg_off[j + 1] = p.wg_off[j] + (none ? 0 : p.nch[j] * p.mtiles[j]);
     p.part_off[j] = off;
     off += (long)p.nch[j] * mout[j];
   }
@@ -577,6 +582,59 @@ __device__ inline void wave_sum_store(cplx (&acc)[D * D], cplx* red, bool valid,
       gst(dst + e, ((acc[e] + red[e * 64 + lane]) + red[(DD + e) * 64 + lane]) + red[(2 * DD + e) * 64 + lane]);
 }
 
+// d = 1: both consumers of the mixing panel T in one pass. Each wave step
+// loads one row j of T for the 64 outputs m of the tile (column sums of
+// A5: sum_j w(n,j) S^R_{n,j} T_{j,m}, lane-local as in the plain job) and
+// also forms the row sums of C^<_3 without -i (job 5): sum_m (-xi) w(ntau,m)
+// T_{j,m} (S^rceil_{n,ntau-m})^*, over the tile's 64 columns. Sixteen rows
+// are summed over the lanes at once (transposed butterfly: at exchange step
+// t the lanes with bit t set keep the upper half of the live registers, so
+// lane L < 16 ends with row bitrev4(L)); the sums are the job-5 partials of
+// column tile mt.
+__device__ inline cplx shx1(cplx v, int m) { return mk(__shfl_xor(v.x, m), __shfl_xor(v.y, m)); }
+__device__ void t_rows_fused(const Prob& P, const Scratch& sc, int pi, int n, const HistPlan& pl, int mt,
+                             bool valid, int mc, int jb, int je, int j0, const cplx* sh, const WReg& wr,
+                             cplx (&acc)[1]) {
+  constexpr int U = 16;
+  int lane = threadIdx.x & 63, ntau = P.ntau, nro = pl.mout[5];
+  size_t NT1 = ntau + 1;
+  gcp Gtv = G(P.Gtv);
+  // per-lane factor of the row sums
+  cplx cst = mk(0, 0);
+  if (valid && nro > 0) cst = (-P.sig * wr.w(ntau, mc)) * conj(gld(P.Stv + (size_t)n * NT1 + ntau - mc));
+  cplx* dst = sc.part(pi) + pl.part_off[5] + (long)mt * nro;
+  int jl = je - 1;
+  for (int j = jb; j < je; j += 4 * U) {
+    cplx h[U];
+#pragma unroll
+    for (int u = 0; u < U; u++) h[u] = Gtv[(size_t)min(j + 4 * u, jl) * NT1 + mc];
+#pragma unroll
+    for (int u = 0; u < U; u++)
+      if (j + 4 * u < je) cfma(acc[0], (valid ? wr.w(n, j + 4 * u) : 0.0) * sh[j + 4 * u - j0], h[u]);
+    if (j < nro) {  // (uniform) some row of this batch has a row output
+      cplx q[U];
+#pragma unroll
+      for (int u = 0; u < U; u++) q[u] = (j + 4 * u < je && j + 4 * u < nro) ? h[u] * cst : mk(0, 0);
+#pragma unroll
+      for (int t = 0, w = U / 2; w >= 1; t++, w /= 2) {
+        bool up = (lane >> t) & 1;
+#pragma unroll
+        for (int i = 0; i < w; i++) {
+          cplx keep = up ? q[i + w] : q[i], send = up ? q[i] : q[i + w];
+          q[i] = keep + shx1(send, 1 << t);
+        }
+      }
+      q[0] = q[0] + shx1(q[0], 16);
+      q[0] = q[0] + shx1(q[0], 32);
+      if (lane < U) {
+        int b = lane, r = ((b & 1) << 3) | ((b & 2) << 1) | ((b & 4) >> 1) | ((b & 8) >> 3);  // bitrev4
+        int row = j + 4 * r;
+        if (row < je && row < nro) gst(dst + row, q[0]);
+      }
+    }
+  }
+}
+
 template <int D>
 __device__ void hist_blk(const Prob& P, const Scratch& sc, int pi, int n, const HistPlan& pl, int job,
                          int mt, int ch, cplx* lds) {
@@ -638,6 +696,12 @@ __device__ void hist_blk(const Prob& P, const Scratch& sc, int pi, int n, const 
     } break;
     case 1: {  // left-mixing history: sum_j w(n,j) S^R_{n,j} T_{j,m}
       int je = min(n, j0 + TJ);
+      if constexpr (D == 1) {
+        if (pl.fuse_t) {
+          t_rows_fused(P, sc, pi, n, pl, mt, valid, mc, jb, je, j0, sh, wr, acc);
+          break;
+        }
+      }
       term_loop<D>(
           jb, je, [&](int j) { return Gtv + ((size_t)j * NT1 + mc) * DD; },
           [&](int j, const cplx(&H)[DD]) { f_left<D>(acc, valid ? wr.w(n, j) : 0.0, sh + (j - j0) * DD, H); });
