@@ -39,9 +39,11 @@ static int cdiv_i(int a, int b) { return (a + b - 1) / b; }
 constexpr int TSM = 32, TSP = 32, TSV = 32, TS_NTAU = 512, TS_SPLIT = 4;
 
 // Jobs: 0 retarded bulk, 1 left-mixing history, 2 tau source, 3 lesser
-// history (for the staged path only its part l >= m), 4 source C^<_1,
-// 5 source C^<_3, 6 tau-boundary corrections, 7 lesser history l < m (staged
-// path only).
+// history (for the staged path and d = 1 only its part l >= m), 4 source
+// C^<_1, 5 source C^<_3, 6 tau-boundary corrections, 7 lesser history l < m
+// (staged path and d = 1). For d = 1 the jobs 4, 5 and 7 have no workgroups
+// of their own: jobs 0, 1 and 3 form them in the same pass over each stored
+// panel.
 constexpr bool hist_staged(int d) { return d == 2 || d == 4; }
 
 HistPlan make_plan(int n, int k, int ntau, int d, int tau_split) {
@@ -55,7 +57,7 @@ HistPlan make_plan(int n, int k, int ntau, int d, int tau_split) {
   bool les_bulk = n >= 2 * k + 1;
   p.njob = NJOB;
   int mout[NJOB] = {nb, ntau + 1, ntau + 1, les_bulk ? nb : 0, les_bulk ? nb : 0, les_bulk ? nb : 0,
-                    ntau + 1, (les_bulk && p.staged) ? nb : 0};
+                    ntau + 1, (les_bulk && (p.staged || d == 1)) ? nb : 0};
   int span[NJOB] = {n, n, ntau + 1, n, nb > k + 1 ? nb : k + 1, ntau + 1, 1, nb};
   for (int j = 0; j < NJOB; j++) {
     if (p.staged) {
@@ -72,7 +74,7 @@ HistPlan make_plan(int n, int k, int ntau, int d, int tau_split) {
   // d = 1: the mixing panel is read once for both of its consumers (job 1
   // forms the job-5 row sums of each 64-column tile)
   p.fuse_t = d == 1;
-  if (p.fuse_t) p.tj[5] = p.TM;
+  if (p.fuse_t) p.tj[5] = p.tj[4] = p.tj[7] = p.TM;
   long off = 0;
   p.wg_off[0] = 0;
   for (int j = 0; j < NJOB; j++) {
@@ -81,7 +83,7 @@ HistPlan make_plan(int n, int k, int ntau, int d, int tau_split) {
     p.mtiles[j] = mout[j] > 0 ? cdiv_i(mout[j], p.tm[j]) : 0;
     if (j == 6) p.nch[j] = p.mtiles[j] = 1;  // one workgroup: both tau ends
     if (j == 2 && tau_split > 0) p.nch[j] = tau_split;
-    bool none = (j == 2 && tau_split > 0) || (j == 5 && p.fuse_t);  // formed elsewhere
+    bool none = (j == 2 && tau_split > 0) || ((j == 4 || j == 5 || j == 7) && p.fuse_t);  // formed elsewhere
     p.wg_off[j + 1] = p.wg_off[j] + (none ? 0 : p.nch[j] * p.mtiles[j]);
     p.part_off[j] = off;
     off += (long)p.nch[j] * mout[j];
@@ -582,52 +584,58 @@ __device__ inline void wave_sum_store(cplx (&acc)[D * D], cplx* red, bool valid,
       gst(dst + e, ((acc[e] + red[e * 64 + lane]) + red[(DD + e) * 64 + lane]) + red[(2 * DD + e) * 64 + lane]);
 }
 
-// d = 1: both consumers of the mixing panel T in one pass. Each wave step
-// loads one row j of T for the 64 outputs m of the tile (column sums of
-// A5: sum_j w(n,j) S^R_{n,j} T_{j,m}, lane-local as in the plain job) and
-// also forms the row sums of C^<_3 without -i (job 5): sum_m (-xi) w(ntau,m)
-// T_{j,m} (S^rceil_{n,ntau-m})^*, over the tile's 64 columns. Sixteen rows
-// are summed over the lanes at once (transposed butterfly: at exchange step
-// t the lanes with bit t set keep the upper half of the live registers, so
-// lane L < 16 ends with row bitrev4(L)); the sums are the job-5 partials of
-// column tile mt.
+// d = 1: both consumers of a stored panel in one pass. Each wave step loads
+// one stored row j for the 64 outputs m of the tile; colf(j) is the lane's
+// factor of its column sum (weight times the staged S^R_{n,j} or its
+// conjugate), and rowq(j, h) gives the lane's term of the row sum of row j
+// (zero where it does not apply):
+//   mixing panel T (job 1 + job 5): row sums of C^<_3 without -i,
+//     sum_m (-xi) w(ntau,m) T_{j,m} (S^rceil_{n,ntau-m})^*;
+//   retarded panel R (job 0 + job 4): row sums of C^<_1[G,1,Sigma](j,n),
+//     sum_{m<=j} w(j,m) R_{j,m} S^<_{m,n} (its terms m in (j, k] of the first
+//     rows use -R_{m,j}^* and are added by k_reduce);
+//   lesser panel L (job 3, stored L_{m,j}, m <= j): column sums over l >= m,
+//     sum_j w(n,j) L_{m,j} (S^R_{n,j})^*; row sums over l < j (job-7
+//     partials), sum_{m<j} w(n,m) (-L_{m,j}^*) (S^R_{n,m})^*.
+// Eight rows are summed over the lanes at once (transposed butterfly: at
+// exchange step t the lanes with bit t set keep the upper half of the live
+// registers, so lane L < 8 ends with row bitrev3(L)); the sums are the
+// row-job partials of column tile mt.
 __device__ inline cplx shx1(cplx v, int m) { return mk(__shfl_xor(v.x, m), __shfl_xor(v.y, m)); }
-__device__ void t_rows_fused(const Prob& P, const Scratch& sc, int pi, int n, const HistPlan& pl, int mt,
-                             bool valid, int mc, int jb, int je, int j0, const cplx* sh, const WReg& wr,
-                             cplx (&acc)[1]) {
-  constexpr int U = 16;
-  int lane = threadIdx.x & 63, ntau = P.ntau, nro = pl.mout[5];
-  size_t NT1 = ntau + 1;
-  gcp Gtv = G(P.Gtv);
-  // per-lane factor of the row sums
-  cplx cst = mk(0, 0);
-  if (valid && nro > 0) cst = (-P.sig * wr.w(ntau, mc)) * conj(gld(P.Stv + (size_t)n * NT1 + ntau - mc));
-  cplx* dst = sc.part(pi) + pl.part_off[5] + (long)mt * nro;
+// exchange step T of the transposed butterfly over W live registers pairs
+template <int W, int T, int N>
+__device__ inline void bfly(cplx (&q)[N], int lane) {
+  bool up = (lane >> T) & 1;
+#pragma unroll
+  for (int i = 0; i < W; i++) {
+    cplx keep = up ? q[i + W] : q[i], send = up ? q[i] : q[i + W];
+    q[i] = keep + shx1(send, 1 << T);
+  }
+  if constexpr (W > 1) bfly<W / 2, T + 1>(q, lane);
+}
+template <class Addr, class ColF, class RowQ>
+__device__ __forceinline__ void rows_fused(int jb, int je, int j0, int nro, cplx* dst, Addr addr, ColF colf, RowQ rowq,
+                           cplx (&acc)[1]) {
+  constexpr int U = 8;
+  int lane = threadIdx.x & 63;
   int jl = je - 1;
   for (int j = jb; j < je; j += 4 * U) {
     cplx h[U];
 #pragma unroll
-    for (int u = 0; u < U; u++) h[u] = Gtv[(size_t)min(j + 4 * u, jl) * NT1 + mc];
+    for (int u = 0; u < U; u++) h[u] = *addr(min(j + 4 * u, jl));
 #pragma unroll
     for (int u = 0; u < U; u++)
-      if (j + 4 * u < je) cfma(acc[0], (valid ? wr.w(n, j + 4 * u) : 0.0) * sh[j + 4 * u - j0], h[u]);
+      if (j + 4 * u < je) cfma(acc[0], colf(j + 4 * u), h[u]);
     if (j < nro) {  // (uniform) some row of this batch has a row output
       cplx q[U];
 #pragma unroll
-      for (int u = 0; u < U; u++) q[u] = (j + 4 * u < je && j + 4 * u < nro) ? h[u] * cst : mk(0, 0);
-#pragma unroll
-      for (int t = 0, w = U / 2; w >= 1; t++, w /= 2) {
-        bool up = (lane >> t) & 1;
-#pragma unroll
-        for (int i = 0; i < w; i++) {
-          cplx keep = up ? q[i + w] : q[i], send = up ? q[i] : q[i + w];
-          q[i] = keep + shx1(send, 1 << t);
-        }
-      }
+      for (int u = 0; u < U; u++) q[u] = (j + 4 * u < je && j + 4 * u < nro) ? rowq(j + 4 * u, h[u]) : mk(0, 0);
+      bfly<U / 2, 0>(q, lane);
+      q[0] = q[0] + shx1(q[0], 8);
       q[0] = q[0] + shx1(q[0], 16);
       q[0] = q[0] + shx1(q[0], 32);
       if (lane < U) {
-        int b = lane, r = ((b & 1) << 3) | ((b & 2) << 1) | ((b & 4) >> 1) | ((b & 8) >> 3);  // bitrev4
+        int b = lane, r = ((b & 1) << 2) | (b & 2) | ((b & 4) >> 2);  // bitrev3
         int row = j + 4 * r;
         if (row < je && row < nro) gst(dst + row, q[0]);
       }
@@ -655,6 +663,7 @@ __device__ void hist_blk(const Prob& P, const Scratch& sc, int pi, int n, const 
   int mc = valid ? m : mhi;  // in-range output index for address arithmetic
   int j0 = ch * TJ;
   if (job == 0 && j0 + TJ - 1 < mlo) return;
+  if (job == 3 && D == 1 && pl.fuse_t && j0 + TJ - 1 < mlo) return;  // fused: stored rows l >= m only
   if (job == 4 && j0 > max(mhi, k)) return;
   gcp Gret = G(P.Gret), Gles = G(P.Gles), Gtv = G(P.Gtv);
   cplx* sh = lds;
@@ -687,6 +696,23 @@ __device__ void hist_blk(const Prob& P, const Scratch& sc, int pi, int n, const 
   switch (job) {
     case 0: {  // retarded bulk: sum_j w(n-m, j-m) S^R_{n,j} R_{j,m}, j >= m
       int je = min(n, j0 + TJ);
+      if constexpr (D == 1) {
+        if (pl.fuse_t) {
+          int nro = pl.mout[4];
+          cplx sl = (valid && nro > 0) ? gld(P.Sles + tri(n) + mc) : mk(0, 0);  // S^<_{m,n}
+          rows_fused(
+              jb, je, j0, nro, sc.part(pi) + pl.part_off[4] + (long)mt * nro,
+              [&](int j) { return Gret + (tri(max(j, mc)) + mc); },
+              [&](int j) { return ((valid && j >= m) ? wr.w(n - m, j - m) : 0.0) * sh[j - j0]; },
+              [&](int j, cplx h) {
+                double w = 0.0;
+                if (valid && mc <= j) w = j > k ? wr.w(j, mc) : s_s[j * K1 + mc];
+                return (w * h) * sl;
+              },
+              acc);
+          break;
+        }
+      }
       term_loop<D>(
           jb, je, [&](int j) { return Gret + (tri(max(j, mc)) + mc) * DD; },
           [&](int j, const cplx(&H)[DD]) {
@@ -698,7 +724,14 @@ __device__ void hist_blk(const Prob& P, const Scratch& sc, int pi, int n, const 
       int je = min(n, j0 + TJ);
       if constexpr (D == 1) {
         if (pl.fuse_t) {
-          t_rows_fused(P, sc, pi, n, pl, mt, valid, mc, jb, je, j0, sh, wr, acc);
+          int nro = pl.mout[5];
+          cplx cst = mk(0, 0);  // per-lane factor of the row sums
+          if (valid && nro > 0) cst = (-xi * wr.w(ntau, mc)) * conj(gld(P.Stv + T1 + ntau - mc));
+          rows_fused(
+              jb, je, j0, nro, sc.part(pi) + pl.part_off[5] + (long)mt * nro,
+              [&](int j) { return Gtv + ((size_t)j * NT1 + mc); },
+              [&](int j) { return (valid ? wr.w(n, j) : 0.0) * sh[j - j0]; }, [&](int j, cplx h) { return h * cst; },
+              acc);
           break;
         }
       }
@@ -708,6 +741,19 @@ __device__ void hist_blk(const Prob& P, const Scratch& sc, int pi, int n, const 
     } break;
     case 3: {  // lesser history: sum_l w(n,l) L^_{m,l} (S^R_{n,l})^dag
       int je = min(n, j0 + TJ);
+      if constexpr (D == 1) {
+        if (pl.fuse_t) {
+          int nro = pl.mout[7];
+          // per-lane factor of the row sums: -w(n,m) (S^R_{n,m})^*
+          cplx fr = valid ? -(wr.w(n, mc) * conj(gld(P.Sret + tri(n) + mc))) : mk(0, 0);
+          rows_fused(
+              jb, je, j0, nro, sc.part(pi) + pl.part_off[7] + (long)mt * nro,
+              [&](int l) { return Gles + (tri(max(l, mc)) + mc); },
+              [&](int l) { return ((valid && l >= m) ? wr.w(n, l) : 0.0) * conj(sh[l - j0]); },
+              [&](int l, cplx h) { return mc < l ? conj(h) * fr : mk(0, 0); }, acc);
+          break;
+        }
+      }
       term_loop<D>(
           jb, je,
           [&](int l) { return l >= mc ? Gles + (tri(l) + mc) * DD : Gles + (tri(mc) + l) * DD; },
@@ -1522,12 +1568,25 @@ __global__ __launch_bounds__(NTHR) void k_reduce(ProbArg pa, Scratch sc, HistPla
       cplx bv[KMAX];
       bdf_load(k, [&](int l) { return P.Gles + (tri(n - l) + m) * DD + e; }, bv);
       // lesser history: one job over all l, or (staged) l >= m and l < m
-      int c3 = pl.staged ? m / pl.tj[3] : 0;
-      int n7 = (pl.staged && m > 0) ? (m - 1) / pl.tj[7] + 1 : 0;
-      const cplx* ps[4] = {pp(3, c3), pl.staged ? pp(7, 0) : part, pp(4, 0), pp(5, 0)};
+      bool split3 = pl.staged || pl.fuse_t;  // job 3 only l >= m, job 7 l < m
+      int c3 = split3 ? m / pl.tj[3] : 0;
+      int n7 = (split3 && m > 0) ? (m - 1) / pl.tj[7] + 1 : 0;
+      const cplx* ps[4] = {pp(3, c3), split3 ? pp(7, 0) : part, pp(4, 0), pp(5, 0)};
       int cn[4] = {pl.nch[3] - c3, n7, jmax / pl.tj[4] + 1, pl.nch[5]};
       cplx sm[4];
       msum<4, MSB>(ps, cn, cs, sm);
+      if (pl.fuse_t && m < k) {
+        // terms j in (m, k] of C^<_1 (start-up weights), R~_{m,j} = -(R_{j,m})^dag
+        cplx cr = mk(0, 0);
+        for (int j = m + 1; j <= k; j++) {
+          cplx t = mk(0, 0);
+#pragma unroll
+          for (int q = 0; q < D; q++)
+            cfma_cb(t, gld(P.Sles + (tri(n) + j) * DD + q * D + c), gld(P.Gret + (tri(j) + m) * DD + q * D + a));
+          cr = cr + W.s[m][j] * t;
+        }
+        sm[2] = sm[2] - cr;
+      }
       cplx s3 = sm[0] + sm[1];
       r = bdf(bv) + h * mul_i(sm[2]) + ht * sm[3] + h * mul_i(s3);
     }
