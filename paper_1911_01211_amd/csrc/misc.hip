@@ -408,12 +408,13 @@ __global__ __launch_bounds__(NT2) void k_convolution(ProbArg pc, ProbArg pa, Pro
 // k-point average G_loc of a lattice. Fixed summation order over i.
 // Pointer sources: the batch (pa, count >= 1) supplies the G_i; the output is
 // the Sigma of problem 0.
-// One workgroup: 64 elements x 4 waves; wave w sums its quarter of the
-// instances (sixteen loads in flight), the quarters are added in order.
-__global__ __launch_bounds__(NT2) void k_sigma_local(ProbArg pa, int n, double lam) {
-  constexpr int NBAT = 256;  // instances whose pointers are staged at once
+// One workgroup: 64 elements x 16 waves; wave w sums its sixteenth of the
+// instances (sixteen loads in flight), the sixteenths are added in order.
+constexpr int NSL = 1024, NSLW = NSL / 64;
+__global__ __launch_bounds__(NSL) void k_sigma_local(ProbArg pa, int n, double lam) {
+  constexpr int NBAT = 512;  // instances whose pointers are staged at once
   __shared__ const cplx* base[NBAT];
-  __shared__ cplx qs[4][64];
+  __shared__ cplx qs[NSLW][64];
   const Prob& P0 = pa.get(0);
   int d = P0.d, dd = d * d, ntau = P0.ntau, cnt = pa.count;
   int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -438,12 +439,12 @@ __global__ __launch_bounds__(NT2) void k_sigma_local(ProbArg pa, int n, double l
   cplx s = mk(0, 0);
   for (int i0 = 0; i0 < cnt; i0 += NBAT) {
     int nb = min(NBAT, cnt - i0);
-    int lo = wave * nb / 4, hi = (wave + 1) * nb / 4;
+    int lo = wave * nb / NSLW, hi = (wave + 1) * nb / NSLW;
     for (int c = 0; c < 4; c++) {
       // stage component c's pointers only if some element of the block needs them
       bool need = __syncthreads_or(valid && comp == c);
       if (!need) continue;
-      for (int i = threadIdx.x; i < nb; i += NT2) {
+      for (int i = threadIdx.x; i < nb; i += NSL) {
         const Prob& P = pa.get(i0 + i);
         base[i] = c == 0 ? P.Gret : c == 1 ? P.Gles : c == 2 ? P.Gtv : P.Gmat;
       }
@@ -464,7 +465,9 @@ __global__ __launch_bounds__(NT2) void k_sigma_local(ProbArg pa, int n, double l
   qs[wave][lane] = s;
   __syncthreads();
   if (wave != 0 || !valid) return;
-  cplx r = w * (((qs[0][lane] + qs[1][lane]) + qs[2][lane]) + qs[3][lane]);
+  cplx r = qs[0][lane];
+  for (int q = 1; q < NSLW; q++) r = r + qs[q][lane];
+  r = w * r;
   if (comp == 3) P0.Smat[off] = r;
   else if (comp == 0) P0.Sret[off] = r;
   else if (comp == 1) P0.Sles[off] = r;
@@ -473,7 +476,7 @@ __global__ __launch_bounds__(NT2) void k_sigma_local(ProbArg pa, int n, double l
 
 hipError_t launch_sigma_local(const ProbArg& pa, int n, int d, int nelems, double lam, hipStream_t s) {
   dim3 g((nelems + 63) / 64, 1);
-  k_sigma_local<<<g, NT2, 0, s>>>(pa, n, lam);
+  k_sigma_local<<<g, NSL, 0, s>>>(pa, n, lam);
   return hipGetLastError();
 }
 
