@@ -1761,6 +1761,153 @@ __global__ void __launch_bounds__(ADJ_NT) k_adj_sigma(const AdjProb* ap, int n) 
         o[e] = o[e] + v;
       });
 }
+// The same reductions for d <= 4 with the orbital count known at compile
+// time: a thread forms whole d x d block terms (each block loaded once, the
+// products unrolled), threads t, t + 256, ... take the terms of the output
+// block in turn, and the 256 block sums are added in a fixed order.
+template <int D>
+__device__ inline void blk_ld(cplx (&b)[D * D], const cplx* p) {
+#pragma unroll
+  for (int e = 0; e < D * D; e++) b[e] = p[e];
+}
+// extended blocks: R~_{a,b} (a < b: -(R_{b,a})^dag) and L^_{a,b} (a > b: -(L_{b,a})^dag)
+template <int D>
+__device__ inline void blk_rt(cplx (&b)[D * D], const AdjView& V, int a, int c) {
+  if (a >= c) {
+    blk_ld<D>(b, V.GR(a, c));
+  } else {
+    const cplx* p = V.GR(c, a);
+#pragma unroll
+    for (int x = 0; x < D; x++)
+#pragma unroll
+      for (int y = 0; y < D; y++) b[x * D + y] = -conj(p[y * D + x]);
+  }
+}
+template <int D>
+__device__ inline void blk_lh(cplx (&b)[D * D], const AdjView& V, int a, int c) {
+  if (a <= c) {
+    blk_ld<D>(b, V.GL(a, c));
+  } else {
+    const cplx* p = V.GL(c, a);
+#pragma unroll
+    for (int x = 0; x < D; x++)
+#pragma unroll
+      for (int y = 0; y < D; y++) b[x * D + y] = -conj(p[y * D + x]);
+  }
+}
+// acc += f X Y^H  and  acc += f X^H Y
+template <int D>
+__device__ inline void blk_abh(cplx (&acc)[D * D], cplx f, const cplx (&X)[D * D], const cplx (&Y)[D * D]) {
+#pragma unroll
+  for (int r = 0; r < D; r++)
+#pragma unroll
+    for (int c = 0; c < D; c++) {
+      cplx u = mk(0, 0);
+#pragma unroll
+      for (int q = 0; q < D; q++) cfma(u, X[r * D + q], conj(Y[c * D + q]));
+      acc[r * D + c] = acc[r * D + c] + f * u;
+    }
+}
+template <int D>
+__device__ inline void blk_ahb(cplx (&acc)[D * D], cplx f, const cplx (&X)[D * D], const cplx (&Y)[D * D]) {
+#pragma unroll
+  for (int r = 0; r < D; r++)
+#pragma unroll
+    for (int c = 0; c < D; c++) {
+      cplx u = mk(0, 0);
+#pragma unroll
+      for (int q = 0; q < D; q++) cfma(u, conj(X[q * D + r]), Y[q * D + c]);
+      acc[r * D + c] = acc[r * D + c] + f * u;
+    }
+}
+// term t of output block ob (the terms of sig_term, as whole blocks)
+template <int D>
+__device__ inline void sig_term_blk(const AdjView& V, int n, int ob, int t, cplx (&acc)[D * D]) {
+  constexpr int DD = D * D;
+  SigGeom G = sig_geom(n, V.k, V.ntau);
+  int k = V.k, ntau = V.ntau, nb = n - k;
+  double h = V.h;
+  const cplx* rL = V.scr(V.lay.rhoL);
+  const cplx* rT = V.scr(V.lay.rhoT);
+  const cplx* rR = V.scr(V.lay.rhoR);
+  cplx X[DD], Y[DD];
+  if (ob < G.nR) {
+    int j = ob, na = (j < nb - 1 ? j : nb - 1) + 1;
+    if (t < na) {
+      int m = t;
+      blk_ld<D>(X, rR + (size_t)m * DD);
+      blk_ld<D>(Y, V.GR(j, m));
+      blk_abh<D>(acc, mk(0, h * adj_w(V.W, n - m, j - m)), X, Y);
+      return;
+    }
+    t -= na;
+    if (t <= ntau) {
+      blk_ld<D>(X, rT + (size_t)t * DD);
+      blk_ld<D>(Y, V.GT(j, t));
+      blk_abh<D>(acc, mk(0, h * adj_w(V.W, n, j)), X, Y);
+      return;
+    }
+    int m = t - (ntau + 1);
+    blk_ld<D>(X, rL + (size_t)m * DD);
+    blk_lh<D>(Y, V, m, j);
+    blk_ahb<D>(acc, mk(0, h * adj_w(V.W, n, j)), X, Y);
+    return;
+  }
+  if (ob < G.nR + G.nL) {
+    int j = ob - G.nR;
+    int na = j <= k ? (k < nb - 1 ? k : nb - 1) + 1 : 0;
+    int m;
+    double wt;
+    if (t < na) {
+      m = t;
+      wt = V.W.s[m][j];
+    } else {
+      m = (j > k + 1 ? j : k + 1) + (t - na);
+      wt = adj_w(V.W, m, j);
+    }
+    blk_rt<D>(X, V, m, j);
+    blk_ld<D>(Y, rL + (size_t)m * DD);
+    blk_ahb<D>(acc, mk(0, -(h * wt)), X, Y);
+    return;
+  }
+  int tau = ob - G.nR - G.nL, m = t, j = ntau - tau;
+  blk_ld<D>(X, rL + (size_t)m * DD);
+  blk_ld<D>(Y, V.GT(m, j));
+  blk_ahb<D>(acc, mk(-V.xi * V.ht * adj_w(V.W, ntau, j), 0), X, Y);
+}
+template <int D>
+__global__ void __launch_bounds__(ADJ_NT) k_adj_sigma_blk(const AdjProb* ap, int n) {
+  constexpr int DD = D * D, NG = ADJ_NT / DD;
+  __shared__ cplx red[DD][ADJ_NT];
+  __shared__ cplx red2[NG][DD];
+  const AdjProb& A = ap[blockIdx.y];
+  if (n > A.p.nt) return;
+  AdjView V(A, c_kw[A.p.k]);
+  int ob = blockIdx.x;
+  if (ob >= sig_geom(n, V.k, V.ntau).total) return;
+  int tid = threadIdx.x;
+  cplx acc[DD];
+#pragma unroll
+  for (int e = 0; e < DD; e++) acc[e] = mk(0, 0);
+  int nt = sig_nterms(V, n, ob);
+  for (int t = tid; t < nt; t += ADJ_NT) sig_term_blk<D>(V, n, ob, t, acc);
+#pragma unroll
+  for (int e = 0; e < DD; e++) red[e][tid] = acc[e];
+  __syncthreads();
+  if (tid < NG * DD) {  // group g sums the threads g, g + NG, g + 2 NG, ... element by element
+    int e = tid % DD, g = tid / DD;
+    cplx v = mk(0, 0);
+    for (int i = g; i < ADJ_NT; i += NG) v = v + red[e][i];
+    red2[g][e] = v;
+  }
+  __syncthreads();
+  if (tid < DD) {
+    cplx v = mk(0, 0);
+    for (int g = 0; g < NG; g++) v = v + red2[g][tid];
+    cplx* o = sig_out(V, n, ob);
+    o[tid] = o[tid] + v;
+  }
+}
 // one output block per workgroup, the terms split over lane groups
 __global__ void __launch_bounds__(ADJ_NT) k_adj_tau(const AdjProb* ap, int p, int srcsel, int with_m) {
   const AdjProb& A = ap[blockIdx.y];
@@ -1943,7 +2090,16 @@ void adj_step_launch(const AdjProb* dA, const AdjShape& S, int n, bool hist, hip
     HistGeom hg = hist_geom(n, k, ntau, dd);
     hipLaunchKernelGGL(k_adj_hist, dim3(adj_blocks(hg.total), S.count), blk, 0, s, dA, n);
   }
-  if (S.sig) hipLaunchKernelGGL(k_adj_sigma, dim3(sig_geom(n, k, ntau).total, S.count), blk, 0, s, dA, n);
+  if (S.sig) {
+    dim3 gs(sig_geom(n, k, ntau).total, S.count);
+    switch (S.d) {
+      case 1: hipLaunchKernelGGL(k_adj_sigma_blk<1>, gs, blk, 0, s, dA, n); break;
+      case 2: hipLaunchKernelGGL(k_adj_sigma_blk<2>, gs, blk, 0, s, dA, n); break;
+      case 3: hipLaunchKernelGGL(k_adj_sigma_blk<3>, gs, blk, 0, s, dA, n); break;
+      case 4: hipLaunchKernelGGL(k_adj_sigma_blk<4>, gs, blk, 0, s, dA, n); break;
+      default: hipLaunchKernelGGL(k_adj_sigma, gs, blk, 0, s, dA, n); break;
+    }
+  }
   // (a trial step, hist = false, needs no M adjoint)
   int nto = (S.sig ? 1 : 0) + (hist ? 1 : 0);
   if (nto) hipLaunchKernelGGL(k_adj_tau, dim3(nto * (ntau + 1), S.count), blk, 0, s, dA, n, 0, hist ? 1 : 0);
