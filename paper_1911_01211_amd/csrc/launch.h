@@ -24,8 +24,8 @@ struct HistPlan {
   // staged path: workgroups ordered by bands of stored slices, so that the
   // two consumers of a history block (jobs 0/4, 1/5, 3/7) run close together
   int banded;         // workgroups in band order (else job by job)
-  int nband, wpb;     // bands, workgroups per band
-  int bo[7];          // offsets in a band of the jobs 0, 4, 1, 5, 3, 7
+  int nband, wpb;     // bands (wpb unused)
+  int bo[7];          // column tiles of the triangular panels and of the mixing panel
   int grid;           // history workgroups (without the set-up workgroup)
   long part_off[NJOB];  // in blocks
   // reduce tiles of the retarded, mixing and lesser rows; partial sums of

@@ -34,6 +34,14 @@ constexpr int STG_TJ = 32, STG_TJS = 16;
 
 static int cdiv_i(int a, int b) { return (a + b - 1) / b; }
 
+// Units of band c (terms 32c .. 32c + 31): the triangular panels have column
+// tiles t <= c / 2 there, the mixing panel all of its tiles. Each group of 8
+// units takes 40 workgroups.
+__host__ __device__ inline int band_tri(const HistPlan& p, int c) { return min(p.bo[0], c / 2 + 1); }
+__host__ __device__ inline int band_wgs(const HistPlan& p, int c) {
+  return 40 * ((2 * band_tri(p, c) + p.bo[1] + 7) / 8);
+}
+
 // k_tau_shared: tiles of TSM outputs x TSP problems, chunks of TSV terms;
 // the terms are split over TS_SPLIT workgroups (partial-sum chunks)
 constexpr int TSM = 32, TSP = 32, TSV = 32, TS_NTAU = 512, TS_SPLIT = 4;
@@ -92,19 +100,21 @@ HistPlan make_plan(int n, int k, int ntau, int d, int tau_split) {
   // Band order pays once the history panels of a problem no longer fit in the
   // 256 MB last-level (Infinity) cache, so that a block's second consumer
   // would otherwise read it from HBM again.
+  // Within a band the workgroups form units: one 32 x 64 tile of a panel,
+  // read by its column job (one workgroup) and its row job (four workgroups
+  // of 16 x 32). The five get the same index modulo 8, the XCD they are
+  // dispatched to, so the second consumer finds the tile in that XCD's L2.
+  // Only the tiles on or below the diagonal of the triangular panels form
+  // units, so that the eight XCDs get even shares.
   double hist_bytes = 16.0 * d * d * ((double)n * (n + 1) + (double)n * (ntau + 1));
-  p.banded = p.staged && hist_bytes > 160e6;
+  p.banded = p.staged && les_bulk && hist_bytes > 160e6;
   if (p.banded) {
-    static const int BJ[6] = {0, 4, 1, 5, 3, 7};
     p.nband = p.nch[0];
-    p.bo[0] = 0;
-    for (int i = 0; i < 6; i++) {
-      int j = BJ[i];
-      bool row = j == 4 || j == 5 || j == 7;
-      p.bo[i + 1] = p.bo[i] + (row ? 2 * p.nch[j] : p.mtiles[j]);
-    }
-    p.wpb = p.bo[6];
-    p.grid = p.nband * p.wpb + p.nch[2] * p.mtiles[2] + 1;
+    p.bo[0] = p.mtiles[0];  // column tiles of the retarded and lesser panels
+    p.bo[1] = p.mtiles[1];  // column tiles of the mixing panel
+    int w = 0;
+    for (int c = 0; c < p.nband; c++) w += band_wgs(p, c);
+    p.grid = w + p.nch[2] * p.mtiles[2] + 1;
   }
   // reduce tiles (retarded, mixing, lesser) and the per-tile partial sums of
   // the k+1 lesser boundary rows
@@ -1186,17 +1196,25 @@ __global__ __launch_bounds__(NTHR) void k_history(ProbArg pa, Scratch sc, HistPl
       mt = ch = 0;
     } else {
       b -= ntw + 1;
-      int c = b / pl.wpb, r = b % pl.wpb, i = 0;
-      while (r >= pl.bo[i + 1]) i++;
-      const int BJ[6] = {0, 4, 1, 5, 3, 7};
-      job = BJ[i];
-      int local = r - pl.bo[i];
-      if (job == 4 || job == 5 || job == 7) {
-        mt = 2 * c + local / pl.nch[job];
-        ch = local % pl.nch[job];
-      } else {
-        mt = local;
+      // band c, unit u (8 units per group of 40 workgroups), slot s: 0 the
+      // column job, 1..4 the row job's quarters of the unit's tile
+      int c = 0, w;
+      while (c < pl.nband - 1 && b >= (w = band_wgs(pl, c))) {
+        b -= w;
+        c++;
+      }
+      int g = b % 40, s = g / 8, u = (b / 40) * 8 + g % 8, nr = band_tri(pl, c);
+      if (u >= 2 * nr + pl.bo[1]) return;
+      int pn = u < nr ? 0 : (u < nr + pl.bo[1] ? 1 : 2);
+      int t = pn == 0 ? u : (pn == 1 ? u - nr : u - nr - pl.bo[1]);
+      if (s == 0) {
+        job = pn == 0 ? 0 : (pn == 1 ? 1 : 3);
+        mt = t;
         ch = c;
+      } else {
+        job = pn == 0 ? 4 : (pn == 1 ? 5 : 7);
+        mt = 2 * c + ((s - 1) >> 1);
+        ch = 2 * t + ((s - 1) & 1);
       }
       if (mt >= pl.mtiles[job] || ch >= pl.nch[job]) return;
     }
