@@ -51,28 +51,40 @@ template <class T>
 __device__ inline void gst(T* p, T v) {
   *(CNTR_GLOBAL T*)p = v;
 }
+// Complex values go through a two-double vector type: a copy of the cplx
+// structure would pass through its (generic) copy constructor and lose the
+// address space again.
+typedef double cntr_v2d __attribute__((ext_vector_type(2)));
+__device__ inline cplx gld(const cplx* p) {
+  cntr_v2d t = *(const CNTR_GLOBAL cntr_v2d*)p;
+  return cplx{t.x, t.y};
+}
+__device__ inline void gst(cplx* p, cplx v) {
+  cntr_v2d t = {v.x, v.y};
+  *(CNTR_GLOBAL cntr_v2d*)p = t;
+}
 
 // Retarded value with the continuation t < t':  X~^R_{a,b}[r][c]
 template <int D>
 __device__ inline cplx ret_ext(const cplx* X, int a, int b, int r, int c) {
-  if (a >= b) return X[(tri(a) + b) * D * D + r * D + c];
-  return -conj(X[(tri(b) + a) * D * D + c * D + r]);
+  if (a >= b) return gld(X + (tri(a) + b) * D * D + r * D + c);
+  return -conj(gld(X + (tri(b) + a) * D * D + c * D + r));
 }
 // Lesser value for any order of the arguments: X^<_{a,b}[r][c]
 template <int D>
 __device__ inline cplx les_any(const cplx* X, int a, int b, int r, int c) {
-  if (a <= b) return X[(tri(b) + a) * D * D + r * D + c];
-  return -conj(X[(tri(a) + b) * D * D + c * D + r]);
+  if (a <= b) return gld(X + (tri(b) + a) * D * D + r * D + c);
+  return -conj(gld(X + (tri(a) + b) * D * D + c * D + r));
 }
 
 // The same for a block size d known only at run time.
 __device__ inline cplx ret_ext_d(const cplx* X, int a, int b, int r, int c, int d) {
-  if (a >= b) return X[(tri(a) + b) * d * d + r * d + c];
-  return -conj(X[(tri(b) + a) * d * d + c * d + r]);
+  if (a >= b) return gld(X + (tri(a) + b) * d * d + r * d + c);
+  return -conj(gld(X + (tri(b) + a) * d * d + c * d + r));
 }
 __device__ inline cplx les_any_d(const cplx* X, int a, int b, int r, int c, int d) {
-  if (a <= b) return X[(tri(b) + a) * d * d + r * d + c];
-  return -conj(X[(tri(a) + b) * d * d + c * d + r]);
+  if (a <= b) return gld(X + (tri(b) + a) * d * d + r * d + c);
+  return -conj(gld(X + (tri(a) + b) * d * d + c * d + r));
 }
 
 // Gauss-Jordan inverse of an n x n complex matrix in LDS (in place), with

@@ -183,11 +183,11 @@ __device__ void prep_step(const Prob& P, const Scratch& sc, int pi, int n, cplx*
 #pragma unroll 4
   for (int idx = tid; idx < K1 * K1 * DD; idx += NTHR) {
     int i = idx / (K1 * DD), j = (idx / DD) % K1, e = idx % DD;
-    sw[(i * K1M + j) * DD + e] = j <= i ? P.Sret[(tri(n0 + i) + n0 + j) * DD + e] : mk(0, 0);
+    sw[(i * K1M + j) * DD + e] = j <= i ? gld(P.Sret + (tri(n0 + i) + n0 + j) * DD + e) : mk(0, 0);
   }
   for (int idx = tid; idx < K1 * DD; idx += NTHR) {
     int i = idx / DD, e = idx % DD;
-    cplx v = P.eps[(size_t)(n0 + i + 1) * DD + e];
+    cplx v = gld(P.eps + (size_t)(n0 + i + 1) * DD + e);
     if (e / D == e % D) v.x -= P.mu;
     ew[idx] = v;
   }
@@ -240,9 +240,9 @@ __device__ void prep_step(const Prob& P, const Scratch& sc, int pi, int n, cplx*
       if (row && col >= 0) {
         int l = col / D + 1, c2 = col % D;
 #pragma unroll
-        for (int cc = 0; cc < D; cc++) P.Gret[(tri(n) + n - l) * DD + cc * D + c2] = bb[cc];
+        for (int cc = 0; cc < D; cc++) gst(P.Gret + (tri(n) + n - l) * DD + cc * D + c2, bb[cc]);
       }
-      if (lane < DD) P.Gret[(tri(n) + n) * DD + lane] = (lane / D == lane % D) ? mk(0, -1) : mk(0, 0);
+      if (lane < DD) gst(P.Gret + (tri(n) + n) * DD + lane, (lane / D == lane % D) ? mk(0, -1) : mk(0, 0));
       if (n >= 2 * k + 1) {
         // source terms of the lesser boundary rows m_r = n-k+r from the
         // retarded boundary columns j = n-k..n:
@@ -423,10 +423,10 @@ __device__ void tau_boundary(const Prob& P, const Scratch& sc, int pi, int n, co
   const cplx* Srow = P.Stv + (size_t)n * (ntau + 1) * DD;
   for (int idx = tid; idx < K1 * DD; idx += NTHR) {
     int i = idx / DD, ee = idx % DD;
-    sLo[idx] = Srow[(size_t)i * DD + ee];
-    sHi[idx] = Srow[(size_t)(ntau - k + i) * DD + ee];
-    gLo[idx] = P.Gmat[(size_t)i * DD + ee];
-    gHi[idx] = P.Gmat[(size_t)(ntau - k + i) * DD + ee];
+    sLo[idx] = gld(Srow + (size_t)i * DD + ee);
+    sHi[idx] = gld(Srow + (size_t)(ntau - k + i) * DD + ee);
+    gLo[idx] = gld(P.Gmat + (size_t)i * DD + ee);
+    gHi[idx] = gld(P.Gmat + (size_t)(ntau - k + i) * DD + ee);
   }
   __syncthreads();
   for (int idx = tid; idx < 2 * K1 * DD; idx += NTHR) {
@@ -1628,12 +1628,12 @@ __global__ __launch_bounds__(NTHR) void k_reduce(ProbArg pa, Scratch sc, HistPla
   if (valid) {
     if (fam < 2) {
       for (int q = 0; q < D; q++) cfma(out, minv[a * D + q], outs[mo * DD + q * D + c]);
-      if (fam == 0) P.Gret[(tri(n) + m) * DD + e] = out;
-      else P.Gtv[((size_t)n * (ntau + 1) + m) * DD + e] = out;
+      if (fam == 0) gst(P.Gret + (tri(n) + m) * DD + e, out);
+      else gst(P.Gtv + ((size_t)n * (ntau + 1) + m) * DD + e, out);
     } else {
       // X M_L = rhs with M_L = M_R^dag:  X = rhs (M_R^-1)^dag
       for (int q = 0; q < D; q++) cfma_cb(out, outs[mo * DD + a * D + q], minv[c * D + q]);
-      P.Gles[(tri(n) + m) * DD + e] = out;
+      gst(P.Gles + (tri(n) + m) * DD + e, out);
     }
   }
   if (n >= 2 * k + 1) {  // (else the column is finished serially by k_column)
@@ -1768,6 +1768,9 @@ __global__ __launch_bounds__(NTHR) void k_reduce(ProbArg pa, Scratch sc, HistPla
   }
   __syncthreads();
   if (tid >= 64) return;  // the serial steps run on one wavefront, from LDS
+  // (a local copy of the output pointer: a store through P.Gles could alias
+  // the problem record, whose reload would wait for every store in flight)
+  cplx* const gles_n = P.Gles + tri(n) * DD;
   for (int r = 0; r <= k; r++) {
     int mr = n - k + r;
     if (tid < DD) {
@@ -1793,7 +1796,7 @@ __global__ __launch_bounds__(NTHR) void k_reduce(ProbArg pa, Scratch sc, HistPla
       cplx o = mk(0, 0);
       for (int q = 0; q < D; q++) cfma(o, s_b[r * DD + a2 * D + q], stage[q * D + c2]);
       lrow[r * DD + tid] = o;
-      P.Gles[(tri(n) + mr) * DD + tid] = o;
+      gst(gles_n + (size_t)mr * DD + tid, o);
     }
     wave_sync();
   }
