@@ -29,7 +29,9 @@ struct StreamScratch {
   size_t nprob = 0;
   double* red = nullptr;  // reduction outputs
   size_t nred = 0;
+  void* host = nullptr;   // pinned bounce buffer of the small read-backs
 };
+constexpr size_t READBACK_MAX = 4096;
 std::map<std::pair<int, hipStream_t>, StreamScratch> g_scratch;
 
 cntr_status fail(cntr_status st, const std::string& msg) {
@@ -61,6 +63,22 @@ StreamScratch* scratch_for(hipStream_t s) {
   (void)hipGetDevice(&dev);
   std::lock_guard<std::mutex> lk(g_mu);
   return &g_scratch[{dev, s}];
+}
+
+// Small device-to-host read-back on stream s (waits for the stream): through
+// a pinned buffer, so that the copy is a plain DMA of the stream.
+cntr_status readback(hipStream_t s, void* dst, const void* src, size_t bytes, const char* what) {
+  if (bytes > READBACK_MAX) return fail(CNTR_EINVAL, std::string(what) + ": read-back too large");
+  StreamScratch* sc = scratch_for(s);
+  if (!sc->host && hipHostMalloc(&sc->host, READBACK_MAX, hipHostMallocDefault) != hipSuccess) {
+    sc->host = nullptr;
+    return fail(CNTR_ENOMEM, "pinned read-back buffer");
+  }
+  hipError_t e = hipMemcpyAsync(sc->host, src, bytes, hipMemcpyDeviceToHost, s);
+  if (!e) e = hipStreamSynchronize(s);
+  if (e) return hip_fail(e, what);
+  std::memcpy(dst, sc->host, bytes);
+  return CNTR_OK;
 }
 
 cntr_status grow(hipStream_t s, StreamScratch* sc, size_t bytes, size_t nprob, size_t nred) {
@@ -271,9 +289,8 @@ cntr_status mats_solve(MatsState& st, const Prob& P, bool use_guess, double tol,
     if ((e = launch_matvec(N, d, st.A, P.Gmat, st.g, st.r, s, st.norms))) return hip_fail(e, "residual");
     if ((e = launch_axpy_norm(N * d, P.Gmat, nullptr, st.r, st.g, st.norms, s))) return hip_fail(e, "norm");
     double nrm[2];
-    if ((e = hipMemcpyAsync(nrm, st.norms, sizeof nrm, hipMemcpyDeviceToHost, s)) ||
-        (e = hipStreamSynchronize(s)))
-      return hip_fail(e, "norm readback");
+    cntr_status rs = readback(s, nrm, st.norms, sizeof nrm, "norm readback");
+    if (rs) return rs;
     double rel = std::sqrt(nrm[0] / (nrm[1] > 0 ? nrm[1] : 1.0));
     if (!std::isfinite(rel)) return fail(CNTR_ENONFINITE, "non-finite Matsubara residual");
     if (iters) *iters = it;
@@ -287,9 +304,7 @@ cntr_status mats_solve(MatsState& st, const Prob& P, bool use_guess, double tol,
         return hip_fail(e, "operator copy");
       if ((e = launch_gj_inverse(N, st.Ainv, st.work, st.piv, st.status, s))) return hip_fail(e, "inverse");
       int stat = 0;
-      if ((e = hipMemcpyAsync(&stat, st.status, sizeof(int), hipMemcpyDeviceToHost, s)) ||
-          (e = hipStreamSynchronize(s)))
-        return hip_fail(e, "inverse status");
+      if ((rs = readback(s, &stat, st.status, sizeof(int), "inverse status"))) return rs;
       if (stat != 0) return fail(CNTR_ESINGULAR, "singular Matsubara operator");
       st.have_inv = true;
       since_inv = 0;
@@ -341,11 +356,13 @@ cntr_status mats_loop_2b(const cntr_grid& g, const Prob& P, const ProbArg& pa, c
     }
     e = hipMemsetAsync(sc->red, 0, 2 * sizeof(double), s);
     if (!e) e = launch_distance(pa, po, -1, d, (int)slice_elems(g, -1), sc->red, s);
-    if (!e) e = hipMemcpyAsync(dist, sc->red, 2 * sizeof(double), hipMemcpyDeviceToHost, s);
-    if (!e) e = hipStreamSynchronize(s);
     if (e) {
       ms.release();
       return hip_fail(e, "distance");
+    }
+    if ((st = readback(s, dist, sc->red, 2 * sizeof(double), "distance"))) {
+      ms.release();
+      return st;
     }
     err = dist[0] / dist[1];
     if (err < tol) {
@@ -408,6 +425,7 @@ cntr_status cntr_finalize(void) {
     if (kv.second.buf) (void)hipFree(kv.second.buf);
     if (kv.second.probs) (void)hipFree(kv.second.probs);
     if (kv.second.red) (void)hipFree(kv.second.red);
+    if (kv.second.host) (void)hipHostFree(kv.second.host);
   }
   g_scratch.clear();
   for (hipEvent_t e : g_prof.pool) (void)hipEventDestroy(e);
@@ -870,12 +888,12 @@ cntr_status cntr_solve_2b(const cntr_grid* grid, const cntr_gf* G, const cntr_gf
   ProbArg pa{P, nullptr, 1}, po{Po, nullptr, 1};
   hipError_t e;
   double dist[2];
-  auto distance = [&](int n, double* out) -> cntr_status {
+  // distance summed over the slices n0..n1 (one read-back)
+  auto distance = [&](int n0, int n1, double* out) -> cntr_status {
     hipError_t ee = hipMemsetAsync(sc->red, 0, 2 * sizeof(double), s);
-    if (!ee) ee = launch_distance(pa, po, n, d, (int)slice_elems(g, n), sc->red, s);
-    if (!ee) ee = hipMemcpyAsync(out, sc->red, 2 * sizeof(double), hipMemcpyDeviceToHost, s);
-    if (!ee) ee = hipStreamSynchronize(s);
-    return ee ? hip_fail(ee, "distance") : CNTR_OK;
+    for (int n = n0; n <= n1 && !ee; n++) ee = launch_distance(pa, po, n, d, (int)slice_elems(g, n), sc->red, s);
+    if (ee) return hip_fail(ee, "distance");
+    return readback(s, out, sc->red, 2 * sizeof(double), "distance");
   };
   // Matsubara self-consistency. Initial G^M: free function of eps0_{-1}.
   if (!(mats_mix > 0 && mats_mix <= 1)) return fail(CNTR_EINVAL, "cntr_solve_2b: mats_mix outside (0,1]");
@@ -893,13 +911,8 @@ cntr_status cntr_solve_2b(const cntr_grid* grid, const cntr_gf* G, const cntr_gf
     for (int n = 0; n <= k; n++)
       if ((e = launch_copy(po, pa, n, d, (int)slice_elems(g, n), s))) return hip_fail(e, "copy");
     if ((e = launch_start(pa, scr, d, g.ntau, s))) return hip_fail(e, "start-up");
-    double num = 0, den = 0;
-    for (int n = 0; n <= k; n++) {
-      if ((st = distance(n, dist))) return st;
-      num += dist[0];
-      den += dist[1];
-    }
-    err = num / den;
+    if ((st = distance(0, k, dist))) return st;
+    err = dist[0] / dist[1];
     if (err < boot_tol && it > 2) {
       it++;
       break;
