@@ -286,6 +286,10 @@ typedef struct {
   int64_t steps;
 } cntr_profile;
 cntr_status cntr_profile_begin(void);
+/* The same, recording only every `every`-th time step (the 1st, the
+ * (every+1)-th, ...), so that the events add little to the timed work; the
+ * sums then cover the recorded steps only. every >= 1, else CNTR_EINVAL. */
+cntr_status cntr_profile_begin_every(int32_t every);
 cntr_status cntr_profile_end(cntr_profile* out);
 
 /* ------------------------------------------------------------- plumbing -- */

@@ -17,7 +17,7 @@ STATUS = {0: "CNTR_OK", -1: "CNTR_EINVAL", -2: "CNTR_ESHAPE", -3: "CNTR_EORDER",
 
 SYMBOLS = ["cntr_init_matsubara", "cntr_dyson_step", "cntr_convolution", "cntr_sigma_2b",
            "cntr_extrapolate", "cntr_distance", "cntr_copy_slice", "cntr_solve_2b", "cntr_sync",
-           "cntr_last_error", "cntr_finalize", "cntr_version", "cntr_profile_begin",
+           "cntr_last_error", "cntr_finalize", "cntr_version", "cntr_profile_begin", "cntr_profile_begin_every",
            "cntr_profile_end", "cntr_observables", "cntr_sigma_local", "cntr_adjoint_sweep",
            "cntr_solve_2b_batch"]
 
@@ -70,6 +70,7 @@ def lib():
                                           dbl, i32, dbl, i32, P(dbl), vp]
         L.cntr_sync.argtypes = [vp]
         L.cntr_profile_begin.argtypes = []
+        L.cntr_profile_begin_every.argtypes = [C.c_int32]
         L.cntr_profile_end.argtypes = [P(Profile)]
         L.cntr_last_error.restype = C.c_char_p
         L.cntr_version.restype = C.c_char_p

@@ -223,8 +223,9 @@ def sync(stream=None):
     _abi.check(_abi.lib().cntr_sync(_stream(stream)))
 
 
-def profile_begin():
-    _abi.check(_abi.lib().cntr_profile_begin())
+def profile_begin(every: int = 1):
+    """Record HIP events around every `every`-th time step (cntr_profile_begin_every)."""
+    _abi.check(_abi.lib().cntr_profile_begin_every(int(every)))
 
 
 def profile_end() -> dict:

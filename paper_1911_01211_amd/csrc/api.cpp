@@ -219,8 +219,9 @@ StepScratch step_layout(const cntr_grid& g) {
   size_t dd = (size_t)g.d * g.d;
   r.sc.off_status = 0;
   r.sc.off_minv = 256;
-  // step inverses (KMAX + 2 blocks) and the boundary-row source terms (KMAX + 1)
-  r.sc.off_part = 256 + round256((2 * KMAX + 4) * dd * sizeof(cplx));
+  // step inverses (KMAX + 2 blocks), the boundary-row source terms (KMAX + 1,
+  // one spare) and the boundary-row operator ((KMAX + 1)(KMAX + 2) / 2)
+  r.sc.off_part = 256 + round256((2 * KMAX + 4 + (KMAX + 1) * (KMAX + 2) / 2) * dd * sizeof(cplx));
   r.sc.off_tail = r.sc.off_part;
   r.per = r.sc.off_part + round256(step_scratch_bytes(g.nt, g.k, g.ntau, g.d));
   r.sc.stride = r.per;
@@ -385,9 +386,14 @@ extern "C" {
 
 const char* cntr_version(void) { return "cntr-gfx950 0.1"; }
 
-cntr_status cntr_profile_begin(void) {
+cntr_status cntr_profile_begin(void) { return cntr_profile_begin_every(1); }
+
+cntr_status cntr_profile_begin_every(int32_t every) {
+  if (every < 1) return fail(CNTR_EINVAL, "cntr_profile_begin_every: every < 1");
   std::lock_guard<std::mutex> lk(g_mu);
   g_prof.on = true;
+  g_prof.every = every;
+  g_prof.seen = 0;
   g_prof.used = 0;
   g_prof.rec.clear();
   return CNTR_OK;

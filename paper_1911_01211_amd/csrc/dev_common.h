@@ -23,6 +23,8 @@ struct Scratch {
   // boundary-row source terms of the retarded boundary columns (after the
   // KMAX + 2 inverses), d x d blocks of d = dd
   __device__ inline cplx* bsrc(int pi, int dd) const { return minv(pi) + (KMAX + 2) * dd; }
+  // operator of the k+1 serial boundary rows, (KMAX+1)(KMAX+2)/2 blocks
+  __device__ inline cplx* zop(int pi, int dd) const { return minv(pi) + (2 * KMAX + 4) * dd; }
   __device__ inline cplx* part(int pi) const { return (cplx*)(base + pi * stride + off_part); }
   __device__ inline cplx* tail(int pi) const { return (cplx*)(base + pi * stride + off_tail); }
   __device__ inline int* status(int pi) const { return (int*)(base + pi * stride + off_status); }

@@ -45,6 +45,8 @@ struct ProfRec {
 };
 struct ProfState {
   bool on = false;
+  int every = 1;   // record every every-th time step
+  long seen = 0;   // time steps since cntr_profile_begin
   std::vector<hipEvent_t> pool;
   size_t used = 0;
   std::vector<ProfRec> rec;

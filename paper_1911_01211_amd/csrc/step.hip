@@ -1394,8 +1394,11 @@ __global__ __launch_bounds__(NTHR) void k_history(ProbArg pa, Scratch sc, HistPl
 //                   G^lceil_{j,n} = -xi (T_{n,ntau-j})^dag
 //   lesser tile   : -i h    sum_j w(m_r,j)   Sigma^R_{m_r,j} L_{j,n}
 // and the last workgroup to finish (completion counter, no waiting) sums the
-// per-workgroup partials, adds the terms of the boundary rows themselves and
-// runs the k+1 serial steps with the inverses prepared by the step set-up.
+// per-workgroup partials and adds the terms of the boundary rows themselves.
+// The k+1 serial steps are linear in those sources: one more workgroup forms
+// their block lower-triangular solution operator Z (from the inverses of the
+// step set-up) while the tiles run, so the last workgroup applies Z in one
+// parallel product instead of k+1 dependent steps.
 // Sum of cnt values p[i * stride] (in a fixed order), B loads in flight.
 template <int B>
 __device__ inline cplx psum_b(const cplx* p, long stride, int cnt) {
@@ -1474,14 +1477,13 @@ __global__ __launch_bounds__(NTHR) void k_reduce(ProbArg pa, Scratch sc, HistPla
   __shared__ cplx outs[TM * DD];
   __shared__ cplx minv[DD];
   __shared__ cplx pre[NVMAX];
-  __shared__ cplx lrow[NVMAX];
   __shared__ cplx stage[NSTAGE];
   __shared__ cplx sigs[(KMAX + 1) * TM * DD];
   __shared__ double twt[(KMAX + 1) * TM];  // quadrature weights of the tile terms
   __shared__ cplx ser[(KMAX * (KMAX + 1) / 2 + 2 * KMAX + 1) * DD];
   __shared__ double s_om[KMAX + 1], s_ss[(KMAX + 1) * (KMAX + 1)];  // Gregory end weights
   __shared__ double s_ah[KMAX + 1];                                // a_l / h (BDF)
-  __shared__ double s_gw[(KMAX + 1) * (KMAX + 1)];                 // weights of the serial rows
+  __shared__ double s_gw[(KMAX + 1) * (KMAX + 1)];                 // weights of the boundary rows
   __shared__ int is_last;
   int pi = blockIdx.y;
   const Prob& P = pa.get(pi);
@@ -1518,7 +1520,10 @@ __global__ __launch_bounds__(NTHR) void k_reduce(ProbArg pa, Scratch sc, HistPla
       if (l <= k) r = r - s_ah[l] * v[l - 1];
     return r;
   };
-  int b_end = walk ? nwg : (int)blockIdx.x + 1;
+  // Without the walk, workgroup nwg (present when n >= 2k+1) forms the
+  // operator of the boundary rows instead of a tile; the walking workgroup
+  // forms it after its tiles.
+  int b_end = walk ? nwg : min((int)blockIdx.x + 1, nwg);
   for (int b = walk ? 0 : (int)blockIdx.x; b < b_end; b++) {
   __syncthreads();  // the LDS buffers of the previous tile are free
   int fam, mt;
@@ -1679,52 +1684,84 @@ __global__ __launch_bounds__(NTHR) void k_reduce(ProbArg pa, Scratch sc, HistPla
   }  // n >= 2k+1
   }  // tiles
   if (n < 2 * k + 1) return;
-  if (walk) {
-    __syncthreads();  // this workgroup's own partials
-  } else {
-    // completion count; every thread releases its own stores first
-    __threadfence();
-    __syncthreads();
-    if (tid == 0) is_last = atomicAdd(sc.counter(pi), 1) == nwg - 1;
-    __syncthreads();
-    if (!is_last) return;
-    __threadfence();
-  }
-  // last workgroup. The operands of the serial steps are loaded first (into
-  // registers), then the partials of all workgroups are summed (G groups per
-  // value); the loads of both overlap.
   int npk = k * (k + 1) / 2;
   cplx* s_r = ser;  // Sigma^R_{m_r, n-k+jj}, jj < r, packed at r(r-1)/2 + jj
   cplx* s_l = s_r + npk * DD;  // L_{n-2k..n-k-1, n} (BDF of the first rows)
   cplx* s_b = s_l + k * DD;    // inverted boundary step matrices
-  constexpr int NSR = (KMAX * (KMAX + 1) / 2 * DD + NTHR - 1) / NTHR;
-  constexpr int NSL = (KMAX * DD + NTHR - 1) / NTHR;
-  constexpr int NSB = ((KMAX + 1) * DD + NTHR - 1) / NTHR;
-  cplx vr[NSR], vl[NSL], vb[NSB];
-#pragma unroll
-  for (int u = 0; u < NSR; u++) {
-    int idx = tid + u * NTHR;
-    if (idx < npk * DD) {
+  int nz = (k + 1) * (k + 2) / 2;  // blocks of the operator Z, packed at r(r+1)/2 + c
+  cplx* zl = sigs;                 // Z in LDS
+  static_assert((KMAX + 1) * (KMAX + 2) / 2 * DD <= (KMAX + 1) * TM * DD, "operator exceeds its LDS");
+  if (walk || (int)blockIdx.x == nwg) {
+    // The k+1 serial rows read X_r = B_r (b_r - sum_{jj<r} C_{r,jj} X_jj), with
+    // B_r the inverted step matrix of row m_r, C_{r,jj} = (a_{r-jj}/h) 1 +
+    // i h w(m_r, n-k+jj) Sigma^R_{m_r, n-k+jj}, and b_r their sources. Their
+    // solution X = Z b with the block lower-triangular Z formed here, by
+    // forward substitution over the block rows, while the tiles run:
+    //   Z_{r,c} = B_r (delta_rc 1 - sum_{c <= jj < r} C_{r,jj} Z_{jj,c}).
+    for (int idx = tid; idx < npk * DD; idx += NTHR) {
       int pr = idx / DD, ee = idx % DD, r = 1;
       while (r * (r + 1) / 2 <= pr) r++;
       int jj = pr - r * (r - 1) / 2;
-      vr[u] = gld(P.Sret + (tri(n - k + r) + n - k + jj) * DD + ee);
+      s_r[idx] = gld(P.Sret + (tri(n - k + r) + n - k + jj) * DD + ee);
     }
+    for (int idx = tid; idx < (k + 1) * DD; idx += NTHR) s_b[idx] = gld(sc.minv(pi) + DD + idx);
+    for (int v = tid; v < (k + 1) * (k + 1); v += NTHR) {
+      int r = v / (k + 1), jj = v % (k + 1);
+      s_gw[r * K1M + jj] = jj < r ? gw(n - k + r, n - k + jj) : 0.0;
+    }
+    __syncthreads();
+    for (int r = 0; r <= k; r++) {
+      for (int v = tid; v < (r + 1) * DD; v += NTHR) {
+        int c = v / DD, e = v % DD, a2 = e / D, c2 = e % D;
+        cplx t = (c == r && a2 == c2) ? mk(1, 0) : mk(0, 0);
+        for (int jj = c; jj < r; jj++) {
+          const cplx* zb = zl + (jj * (jj + 1) / 2 + c) * DD;
+          const cplx* sb = s_r + (r * (r - 1) / 2 + jj) * DD + a2 * D;
+          cplx sz = mk(0, 0);
+          for (int q = 0; q < D; q++) cfma(sz, sb[q], zb[q * D + c2]);
+          t = t - s_ah[r - jj] * zb[e] - mul_i((h * s_gw[r * K1M + jj]) * sz);
+        }
+        stage[v] = t;
+      }
+      __syncthreads();
+      for (int v = tid; v < (r + 1) * DD; v += NTHR) {
+        int c = v / DD, e = v % DD, a2 = e / D, c2 = e % D;
+        cplx o = mk(0, 0);
+        for (int q = 0; q < D; q++) cfma(o, s_b[r * DD + a2 * D + q], stage[c * DD + q * D + c2]);
+        zl[(r * (r + 1) / 2 + c) * DD + e] = o;
+      }
+      __syncthreads();
+    }
+    if (!walk)
+      for (int idx = tid; idx < nz * DD; idx += NTHR) gst(sc.zop(pi, DD) + idx, zl[idx]);
+  }
+  if (walk) {
+    __syncthreads();  // this workgroup's own partials
+  } else {
+    // completion count (the tiles and the operator workgroup); every thread
+    // releases its own stores first
+    __threadfence();
+    __syncthreads();
+    if (tid == 0) is_last = atomicAdd(sc.counter(pi), 1) == nwg;
+    __syncthreads();
+    if (!is_last) return;
+    __threadfence();
+  }
+  // last workgroup. The operator Z and the earlier rows are loaded first
+  // (into registers), then the partials of all workgroups are summed (G
+  // groups per value); the loads of both overlap.
+  constexpr int NSL = (KMAX * DD + NTHR - 1) / NTHR;
+  constexpr int NSZ = ((KMAX + 1) * (KMAX + 2) / 2 * DD + NTHR - 1) / NTHR;
+  cplx vl[NSL], vz[NSZ];
+#pragma unroll
+  for (int u = 0; u < NSZ; u++) {
+    int idx = tid + u * NTHR;
+    if (!walk && idx < nz * DD) vz[u] = gld(sc.zop(pi, DD) + idx);
   }
 #pragma unroll
   for (int u = 0; u < NSL; u++) {
     int idx = tid + u * NTHR;
     if (idx < k * DD) vl[u] = gld(P.Gles + (tri(n) + n - 2 * k + idx / DD) * DD + idx % DD);
-  }
-#pragma unroll
-  for (int u = 0; u < NSB; u++) {
-    int idx = tid + u * NTHR;
-    if (idx < (k + 1) * DD) vb[u] = gld(sc.minv(pi) + DD + idx);
-  }
-  // Gregory weights of the serial rows, w(m_r, n-k+jj), jj < r
-  for (int v = tid; v < (k + 1) * (k + 1); v += NTHR) {
-    int r = v / (k + 1), jj = v % (k + 1);
-    s_gw[r * K1M + jj] = jj < r ? gw(n - k + r, n - k + jj) : 0.0;
   }
   int G = NV >= NTHR ? 1 : NTHR / NV;
   for (int vv = tid; vv < G * NV; vv += NTHR) {
@@ -1733,14 +1770,11 @@ __global__ __launch_bounds__(NTHR) void k_reduce(ProbArg pa, Scratch sc, HistPla
     stage[vv] = psum_b<16>(tpart + (size_t)g * NV + v, (long)G * NV, g < nwg ? (nwg - g + G - 1) / G : 0);
   }
 #pragma unroll
-  for (int u = 0; u < NSR; u++)
-    if (tid + u * NTHR < npk * DD) s_r[tid + u * NTHR] = vr[u];
+  for (int u = 0; u < NSZ; u++)
+    if (!walk && tid + u * NTHR < nz * DD) zl[tid + u * NTHR] = vz[u];
 #pragma unroll
   for (int u = 0; u < NSL; u++)
     if (tid + u * NTHR < k * DD) s_l[tid + u * NTHR] = vl[u];
-#pragma unroll
-  for (int u = 0; u < NSB; u++)
-    if (tid + u * NTHR < (k + 1) * DD) s_b[tid + u * NTHR] = vb[u];
   __syncthreads();
   for (int v = tid; v < NV; v += NTHR) {
     int r = v / DD, ee = v % DD, a2 = ee / D, c2 = ee % D;
@@ -1767,38 +1801,23 @@ __global__ __launch_bounds__(NTHR) void k_reduce(ProbArg pa, Scratch sc, HistPla
     }
   }
   __syncthreads();
-  if (tid >= 64) return;  // the serial steps run on one wavefront, from LDS
-  // (a local copy of the output pointer: a store through P.Gles could alias
-  // the problem record, whose reload would wait for every store in flight)
-  cplx* const gles_n = P.Gles + tri(n) * DD;
-  for (int r = 0; r <= k; r++) {
-    int mr = n - k + r;
-    if (tid < DD) {
-      int a2 = tid / D, c2 = tid % D;
-      cplx v = pre[r * DD + tid];
-      for (int l = 1; l <= k; l++) {
-        int row = mr - l;
-        cplx y = row >= n - k ? lrow[(row - (n - k)) * DD + tid] : s_l[(row - (n - 2 * k)) * DD + tid];
-        v = v - s_ah[l] * y;
-      }
-      cplx hs = mk(0, 0);
-      for (int jj = 0; jj < r; jj++) {
-        const cplx* sb = s_r + (r * (r - 1) / 2 + jj) * DD + a2 * D;
-        cplx s = mk(0, 0);
-        for (int q = 0; q < D; q++) cfma(s, sb[q], lrow[jj * DD + q * D + c2]);
-        hs = hs + s_gw[r * K1M + jj] * s;
-      }
-      stage[tid] = v - h * mul_i(hs);
+  // sources b_r: pre_r less the BDF terms of the rows before n-k; then X = Z b
+  for (int v = tid; v < NV; v += NTHR) {
+    int r = v / DD, ee = v % DD;
+    cplx b = pre[v];
+    for (int l = r + 1; l <= k; l++) b = b - s_ah[l] * s_l[(k + r - l) * DD + ee];
+    stage[v] = b;
+  }
+  __syncthreads();
+  cplx* const gles_b = P.Gles + (tri(n) + n - k) * DD;
+  for (int v = tid; v < NV; v += NTHR) {
+    int r = v / DD, ee = v % DD, a2 = ee / D, c2 = ee % D;
+    cplx o = mk(0, 0);
+    for (int c = 0; c <= r; c++) {
+      const cplx* zb = zl + (r * (r + 1) / 2 + c) * DD + a2 * D;
+      for (int q = 0; q < D; q++) cfma(o, zb[q], stage[c * DD + q * D + c2]);
     }
-    wave_sync();
-    if (tid < DD) {
-      int a2 = tid / D, c2 = tid % D;
-      cplx o = mk(0, 0);
-      for (int q = 0; q < D; q++) cfma(o, s_b[r * DD + a2 * D + q], stage[q * D + c2]);
-      lrow[r * DD + tid] = o;
-      gst(gles_n + (size_t)mr * DD + tid, o);
-    }
-    wave_sync();
+    gst(gles_b + v, o);
   }
 }
 
@@ -2178,14 +2197,15 @@ static hipError_t step_d(const ProbArg& pa, const Scratch& sc, int n, hipStream_
   }
   dim3 g1(pl.grid + 1, pa.count);
   hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr;
-  if (g_prof.on) {
+  bool rec = g_prof.on && g_prof.seen++ % g_prof.every == 0;
+  if (rec) {
     e0 = prof_event();
     e1 = prof_event();
     e2 = prof_event();
     if (e0) (void)hipEventRecord(e0, s);
   }
   k_history<D><<<g1, NTHR, 0, s>>>(pa, sc, pl);
-  if (g_prof.on && e1) {
+  if (rec && e1) {
     (void)hipEventRecord(e1, s);
     double dd = (double)D * D;
     double blocks = (double)n * (n + 1) / 2 + (double)n * (ntau + 1) + (n >= 2 * k + 1 ? (double)n * (n + 1) / 2 : 0);
@@ -2193,13 +2213,15 @@ static hipError_t step_d(const ProbArg& pa, const Scratch& sc, int n, hipStream_
                           8.0 * dd * D * hist_block_macs(n, k, ntau) * pa.count});
   }
   pl.walk_tiles = pa.count >= 16;
-  dim3 g2(pl.walk_tiles ? 1 : pl.red_tiles[0] + pl.red_tiles[1] + pl.red_tiles[2], pa.count);
+  // (one more workgroup forms the boundary-row operator when there are rows)
+  int ntile = pl.red_tiles[0] + pl.red_tiles[1] + pl.red_tiles[2];
+  dim3 g2(pl.walk_tiles ? 1 : ntile + (pl.red_tiles[2] > 0 ? 1 : 0), pa.count);
   k_reduce<D><<<g2, NTHR, 0, s>>>(pa, sc, pl);
   if (n < 2 * k + 1) {
     dim3 g4(1, pa.count);
     k_column<D><<<g4, NTHR, 0, s>>>(pa, sc, n);
   }
-  if (g_prof.on && e2) (void)hipEventRecord(e2, s);
+  if (rec && e2) (void)hipEventRecord(e2, s);
   return hipGetLastError();
 }
 
