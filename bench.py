@@ -35,8 +35,8 @@ HBM_PEAK_GBS = 8000.0
 # Valid only for the kernel sources it was taken on (hash below); reported
 # as null once they change.
 PROF_EVERY = 8  # time steps per recorded one (HIP events)
-TRAFFIC = {"slice": 1000, "bytes": 7.2637e8, "algorithmic_bytes": 3.5891e8,
-           "src_sha256_16": "52bea5ef83172a10",
+TRAFFIC = {"slice": 1000, "bytes": 5.1027e8, "algorithmic_bytes": 3.5891e8,
+           "src_sha256_16": "4c9bd60572ad61cb",
            "profile": "profiles/k_history_traffic_slice1000_d4.md"}
 TRAFFIC_SRCS = ("paper_1911_01211_amd/csrc/step.hip", "paper_1911_01211_amd/csrc/dev_common.h",
                 "paper_1911_01211_amd/csrc/cntr_internal.h")
@@ -388,7 +388,8 @@ def main():
     nsteps = (g.nt - g.k) * args.steps
     value = nsteps / elapsed
     hist_gbs = prof["hist_bytes"] / (prof["hist_ms"] * 1e-3) / 1e9 if prof["hist_ms"] > 0 else None
-    tflops = prof["hist_flops"] / elapsed / 1e12
+    # (the recorded steps are every PROF_EVERY-th one: scaled to all of them)
+    tflops = prof["hist_flops"] * PROF_EVERY / elapsed / 1e12
     traffic, traffic_at = traffic_entry()
     out = {
         "metric": METRIC,
