@@ -160,6 +160,24 @@ cntr_status cntr_observables(int32_t tstp, int32_t count, const cntr_grid* grids
                              const cntr_gf* Sigma, const void* const* eps0, const void* const* eps_mf,
                              double* obs, void* rho, void* stream);
 
+/* ------------------------------------------------------------------ F3 --
+ * Free Green's function of a time-dependent single-particle Hamiltonian
+ * (Sec. "Implementation: Free Green's functions", Eqs. cf4 and G0_free):
+ *   G^M       the free Matsubara function of eps(0^-) - mu (as cntr_init_matsubara's g),
+ *   G^R(t_n,t_j)      = -i U_n U_j^dag,
+ *   G^<(t_j,t_n)      = -i xi U_j rho U_n^dag,
+ *   G^rceil(t_n,tau)  = -i xi U_n R diag(f(x) e^{x tau}) R^dag,
+ * with U_n = U_{n,0} from the fourth-order commutator-free exponential
+ * U_{n+1,n} = exp[-i h (a1 e1 + a2 e2)] exp[-i h (a2 e1 + a1 e2)], e1,2 = eps at
+ * t_n + c1,2 h from the polynomial through the grid points n-k+1 .. n+1
+ * (0 .. k while n < k-1); eps(0^-) - mu = R diag(x) R^dag, f(x) = 1/(e^{beta x} - xi),
+ * rho = R diag(f(x)) R^dag. Inputs: eps[i] (DEVICE, (nt+2) d x d, entry 0 =
+ * eps(0^-), entry n+1 = eps(t_n)), grids[i] (beta, mu, sig = xi, h, k). Output:
+ * every component of G[i] for slices 0..nt (overwritten). Needs nt >= k, else
+ * CNTR_EINVAL. Uses the stream's scratch (grown as needed); asynchronous. */
+cntr_status cntr_green_from_H(int32_t count, const cntr_grid* grids, const cntr_gf* G, const void* const* eps,
+                              void* stream);
+
 /* --------------------------------------------------------------- A10, A13 --
  * Polynomial predictor T[G]_tstp -> T[G]_{tstp+1} (Eq. polyextrap, App.
  * "Extrapolation of contour functions"); needs tstp >= k. */

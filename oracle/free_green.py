@@ -102,6 +102,23 @@ def mixed_factor(x: np.ndarray, beta: float, xi: int, tau: float) -> np.ndarray:
     return out
 
 
+def green_slices(g: O.Grid, eps: np.ndarray, slices) -> dict:
+    """Rows n of G^R and G^rceil and column n of G^< (same formulas as
+    green_from_H) for the given slices only: {n: (ret[n+1], les[n+1], tv[ntau+1])}."""
+    d, ntau, xi = g.d, g.ntau, g.sig
+    x, R = np.linalg.eigh(eps[0] - g.mu * np.eye(d))
+    rho = R @ np.diag(fermi(x, g.beta, xi)) @ R.conj().T
+    F = [R @ np.diag(mixed_factor(x, g.beta, xi, m * g.htau)) @ R.conj().T for m in range(ntau + 1)]
+    U = propagators(eps, max(slices), g.k, g.h)
+    out = {}
+    for n in slices:
+        ret = np.array([-1j * U[n] @ U[j].conj().T for j in range(n + 1)])
+        les = np.array([-1j * xi * U[j] @ rho @ U[n].conj().T for j in range(n + 1)])
+        tv = np.array([-1j * xi * U[n] @ F[m] for m in range(ntau + 1)])
+        out[n] = (ret, les, tv)
+    return out
+
+
 def green_from_H(g: O.Grid, eps: np.ndarray) -> O.HM:
     """All components of G_0 on the grid g for eps[(nt+2), d, d]."""
     d, nt, ntau, xi = g.d, g.nt, g.ntau, g.sig

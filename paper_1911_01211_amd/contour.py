@@ -203,6 +203,12 @@ def adjoint_sweep(G: list, Sigma: list, eps: list, Gbar: list, eps_bar: list, Si
     return conv.value
 
 
+def green_from_H(G: list, eps: list, stream=None):
+    """Free Green's function of eps(t) into every component of each G
+    (cntr_green_from_H; eps[i]: device tensor [(nt+2), d, d], entry 0 = eps(0^-))."""
+    _abi.check(_abi.lib().cntr_green_from_H(len(G), _grids(G), _gfs(G), _ptrs(eps), _stream(stream)))
+
+
 def extrapolate(tstp: int, G: list, stream=None):
     _abi.check(_abi.lib().cntr_extrapolate(tstp, len(G), _grids(G), _gfs(G), _stream(stream)))
 

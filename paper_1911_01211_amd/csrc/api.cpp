@@ -800,6 +800,28 @@ cntr_status cntr_adjoint_sweep(int32_t count, const cntr_grid* grids, const cntr
   return CNTR_OK;
 }
 
+cntr_status cntr_green_from_H(int32_t count, const cntr_grid* grids, const cntr_gf* G, const void* const* eps,
+                              void* stream) {
+  cntr_status st = check_batch(count, grids, "cntr_green_from_H");
+  if (st) return st;
+  if (!gf_ok(G, count) || !eps) return fail(CNTR_ESHAPE, "cntr_green_from_H: null pointer");
+  size_t need = 256;
+  for (int i = 0; i < count; i++) {
+    if (!eps[i]) return fail(CNTR_ESHAPE, "cntr_green_from_H: null eps");
+    if (grids[i].nt < grids[i].k) return fail(CNTR_EINVAL, "cntr_green_from_H: nt < k");
+    need = std::max(need, free_green_scratch_bytes(grids[i].nt, grids[i].ntau, grids[i].d));
+  }
+  hipStream_t s = (hipStream_t)stream;
+  StreamScratch* sc = scratch_for(s);
+  if ((st = grow(s, sc, need, 0, 0))) return st;
+  for (int i = 0; i < count; i++) {
+    Prob P = make_prob(grids[i], &G[i], nullptr, eps[i]);
+    hipError_t e = launch_free_green(P, sc->buf, s);
+    if (e != hipSuccess) return hip_fail(e, "cntr_green_from_H");
+  }
+  return CNTR_OK;
+}
+
 cntr_status cntr_extrapolate(int32_t tstp, int32_t count, const cntr_grid* grids, const cntr_gf* G,
                              void* stream) {
   cntr_status st = check_batch(count, grids, "cntr_extrapolate");

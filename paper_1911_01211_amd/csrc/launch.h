@@ -84,6 +84,10 @@ hipError_t launch_sigma_local(const ProbArg& pa, int n, int d, int nelems, doubl
 
 // Matsubara pieces (per problem, one problem per call)
 hipError_t launch_free_mat(const Prob& P, cplx* g, hipStream_t s);
+// free Green's function of eps(t) into every component of P's G (scratch of
+// free_green_scratch_bytes)
+size_t free_green_scratch_bytes(int nt, int ntau, int d);
+hipError_t launch_free_green(const Prob& P, void* scratch, hipStream_t s);
 hipError_t launch_mat_conv(const Prob& P, const cplx* A, const cplx* B, const cplx* f,
                            cplx* out, hipStream_t s);
 hipError_t launch_mat_build(const Prob& P, const cplx* K, cplx* Amat, hipStream_t s);

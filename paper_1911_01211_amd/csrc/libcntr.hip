@@ -5,4 +5,5 @@
 #include "misc.hip"
 #include "mats.hip"
 #include "adjoint.hip"
+#include "free.hip"
 #include "api.cpp"
