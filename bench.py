@@ -141,6 +141,49 @@ def run_adjoint(g, state, args):
             "dJ_dU_sum": float(ubh.sum())}
 
 
+def run_free(args):
+    """Free Green's function of a driven Hamiltonian on the chain's grid
+    (cntr_green_from_H: nt = 1000, ntau = 400, d = 4): every component of G_0
+    from the commutator-free propagator. Timed with HIP events on the launch
+    stream; `achieved` counts the bytes of the function written (each block
+    once) over the whole call."""
+    import numpy as np
+    import torch
+
+    from paper_1911_01211_amd import contour as K
+    from paper_1911_01211_amd import workloads as W
+
+    g = workload_grid()
+    e0, _ = W.hubbard_ramp(g)
+    r = W.rng(77)
+    H1 = W.random_hermitian(r, g.d, 0.5)
+    eps = np.array(e0, np.complex128)
+    for n in range(g.nt + 1):
+        eps[n + 1] = eps[n + 1] + np.cos(0.7 * n * g.h) * H1
+    e = torch.as_tensor(eps).to("cuda:0")
+    G = K.Contour(g, "cuda:0")
+    for _ in range(3):
+        K.green_from_H([G], [e])
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 20
+    ev0.record()
+    for _ in range(reps):
+        K.green_from_H([G], [e])
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / reps
+    dd = g.d * g.d
+    nbytes = 16.0 * dd * ((g.nt + 1) * (g.nt + 2) + (g.nt + 1) * (g.ntau + 1) + (g.ntau + 1))
+    gbs = nbytes / (ms * 1e-3) / 1e9
+    return {"workload": "free G_0 of eps(t) = chain hopping + cos(0.7 t) x random hermitian, "
+                        f"nt={g.nt}, ntau={g.ntau}, d={g.d}, k={g.k}",
+            "value": (g.nt + 1) / (ms * 1e-3), "unit": "time slices/s", "ms_per_call": ms,
+            "roofline": {"bound": "hbm", "scope": "whole call (5 kernels)", "achieved": gbs,
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+                         "bytes": nbytes}}
+
+
 def run_uneven(args):
     """Uneven batch sample: 8 second-Born problems, two each of d = 1, 2, 4, 8
     orbitals, nt uniform in [300, 500], ntau = 300, beta = 10, h = 0.02, k = 5,
@@ -372,6 +415,7 @@ def main():
     ap.add_argument("--no-kpoints", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-uneven", action="store_true")
+    ap.add_argument("--no-free", action="store_true")
     ap.add_argument("--adj-niter", type=int, default=10, help="adjoint fixed-point iterations per slice")
     ap.add_argument("--profile-step", type=int, default=0,
                     help="only run the time step at this slice (counter runs), then a 1 GiB copy")
@@ -429,6 +473,8 @@ def main():
     del state
     if not args.no_uneven:
         out["uneven"] = run_uneven(args)
+    if not args.no_free:
+        out["free_propagator"] = run_free(args)
     if not args.no_kpoints:
         out["batched"] = run_kpoints(args)
     if not args.no_cpu_baseline:
