@@ -168,7 +168,7 @@ cntr_status cntr_observables(int32_t tstp, int32_t count, const cntr_grid* grids
  *   G^<(t_j,t_n)      = -i xi U_j rho U_n^dag,
  *   G^rceil(t_n,tau)  = -i xi U_n R diag(f(x) e^{x tau}) R^dag,
  * with U_n = U_{n,0} from the fourth-order commutator-free exponential
- * U_{n+1,n} = exp[-i h (a1 e1 + a2 e2)] exp[-i h (a2 e1 + a1 e2)], e1,2 = eps at
+ * U_{n+1,n} = exp[-i h (a1 e1 + a2 e2)] exp[-i h (a2 e1 + a1 e2)], e1,2 = eps - mu at
  * t_n + c1,2 h from the polynomial through the grid points n-k+1 .. n+1
  * (0 .. k while n < k-1); eps(0^-) - mu = R diag(x) R^dag, f(x) = 1/(e^{beta x} - xi),
  * rho = R diag(f(x)) R^dag. Inputs: eps[i] (DEVICE, (nt+2) d x d, entry 0 =

@@ -16,6 +16,10 @@ Follows Sec. "Implementation: Free Green's functions" of the paper:
       G^rceil(t_n, tau) = -i xi U_{n,0} R diag(f(x) e^{x tau}) R^dag,
     with eps(0^-) - mu = R diag(x) R^dag, f(x) = 1 / (e^{beta x} - xi) and
     rho = R diag(f(x)) R^dag.
+The real-time branch evolves with eps(t) - mu, as the Dyson equations of this
+library do on every branch (with mu = 0 this is the printed form; otherwise
+the two differ by the gauge phase e^{i mu (t - t')}), so that G_0 solves the
+library's own Dyson equation at Sigma = 0.
 Readings of the printed text (also listed with the design notes): the
 exponents of Eq. cf4 carry the step h (the printed form omits it; without it
 a constant Hamiltonian would not give exp(-i h eps) per step); G^R carries
@@ -61,22 +65,23 @@ def eps_at(eps: np.ndarray, n: int, k: int, t: float) -> np.ndarray:
     return sum(w[i] * eps[p + 1] for i, p in enumerate(pts))
 
 
-def step_propagator(eps: np.ndarray, n: int, k: int, h: float) -> np.ndarray:
-    """U_{n+1,n} by Eq. cf4."""
-    e1 = eps_at(eps, n, k, n + C1)
-    e2 = eps_at(eps, n, k, n + C2)
+def step_propagator(eps: np.ndarray, n: int, k: int, h: float, mu: float = 0.0) -> np.ndarray:
+    """U_{n+1,n} by Eq. cf4, for the one-body Hamiltonian eps(t) - mu."""
+    d = eps.shape[-1]
+    e1 = eps_at(eps, n, k, n + C1) - mu * np.eye(d)
+    e2 = eps_at(eps, n, k, n + C2) - mu * np.eye(d)
     left = scipy.linalg.expm(-1j * h * (A1 * e1 + A2 * e2))
     right = scipy.linalg.expm(-1j * h * (A2 * e1 + A1 * e2))
     return left @ right
 
 
-def propagators(eps: np.ndarray, nt: int, k: int, h: float) -> np.ndarray:
-    """U_{n,0}, n = 0..nt."""
+def propagators(eps: np.ndarray, nt: int, k: int, h: float, mu: float = 0.0) -> np.ndarray:
+    """U_{n,0}, n = 0..nt, for eps(t) - mu."""
     d = eps.shape[-1]
     U = np.zeros((nt + 1, d, d), np.complex128)
     U[0] = np.eye(d)
     for n in range(nt):
-        U[n + 1] = step_propagator(eps, n, k, h) @ U[n]
+        U[n + 1] = step_propagator(eps, n, k, h, mu) @ U[n]
     return U
 
 
@@ -109,7 +114,7 @@ def green_slices(g: O.Grid, eps: np.ndarray, slices) -> dict:
     x, R = np.linalg.eigh(eps[0] - g.mu * np.eye(d))
     rho = R @ np.diag(fermi(x, g.beta, xi)) @ R.conj().T
     F = [R @ np.diag(mixed_factor(x, g.beta, xi, m * g.htau)) @ R.conj().T for m in range(ntau + 1)]
-    U = propagators(eps, max(slices), g.k, g.h)
+    U = propagators(eps, max(slices), g.k, g.h, g.mu)
     out = {}
     for n in slices:
         ret = np.array([-1j * U[n] @ U[j].conj().T for j in range(n + 1)])
@@ -127,7 +132,7 @@ def green_from_H(g: O.Grid, eps: np.ndarray) -> O.HM:
     x, R = np.linalg.eigh(eps[0] - g.mu * np.eye(d))
     rho = R @ np.diag(fermi(x, g.beta, xi)) @ R.conj().T
     F = [R @ np.diag(mixed_factor(x, g.beta, xi, m * g.htau)) @ R.conj().T for m in range(ntau + 1)]
-    U = propagators(eps, nt, g.k, g.h)
+    U = propagators(eps, nt, g.k, g.h, g.mu)
     for n in range(nt + 1):
         for j in range(n + 1):
             G.R(n, j)[...] = -1j * U[n] @ U[j].conj().T

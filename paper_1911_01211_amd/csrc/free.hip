@@ -8,7 +8,8 @@
 //   G^rceil(t_n,tau) = -i xi U_n R diag(f(x) e^{x tau}) R^dag,
 // with eps(0^-) - mu = R diag(x) R^dag, f(x) = 1/(e^{beta x} - xi) and
 // rho = R diag(f(x)) R^dag (U_n = U_{n,0}). The exponents of Eq. cf4 carry
-// the step h.
+// the step h, and the real-time Hamiltonian is eps(t) - mu, as in the Dyson
+// equations of this library (for mu = 0 the printed form).
 //
 // Kernels (one problem per launch; d <= 8, so a d x d block fits one wave
 // with one element per lane):
@@ -166,6 +167,12 @@ __global__ __launch_bounds__(CF_NT) void k_cf4_steps(Prob P, FreeScratch fs) {
       cplx ev = gld(P.eps + (size_t)(j0 + m + 1) * dd + lane);
       e1 = e1 + lagrange_w(j0, k, m, n + c1) * ev;
       e2 = e2 + lagrange_w(j0, k, m, n + c2) * ev;
+    }
+    // (the Hamiltonian of the real-time branch is eps - mu, as in the Dyson
+    // equations of this library)
+    if (lane / d == lane % d) {
+      e1.x -= P.mu;
+      e2.x -= P.mu;
     }
     // exponents -i h (a1 e1 + a2 e2) (left factor) and -i h (a2 e1 + a1 e2)
     M1[lane] = mk(0, -h) * (a1 * e1 + a2 * e2);

@@ -121,3 +121,29 @@ def test_identities(O, sig):
     epsc = np.repeat(H0[None], nt + 2, axis=0)
     Gc = F.green_from_H(g, epsc)
     assert np.abs(Gc.R(9, 4) - Gc.R(6, 1)).max() < 1e-13
+
+
+def test_agrees_with_dyson_solver_at_zero_self_energy(O):
+    """Two independent discretisations of the same free function: the
+    commutator-free propagator and the Dyson time stepper (BDF + Gregory, k = 5)
+    with Sigma = 0. They differ by the integrators' errors only, and the
+    difference shrinks ~h^4 or faster when h is halved."""
+    r = W.rng(304)
+    d = 2
+    H0, H1 = herm(r, d), 0.8 * herm(r, d)
+    errs = []
+    for nt, h in ((40, 0.05), (80, 0.025)):
+        g = ogrid(O, nt, 20, d, k=5, h=h, beta=2.0, mu=0.1)
+        eps = np.zeros((nt + 2, d, d), np.complex128)
+        eps[0] = H0
+        for n in range(nt + 1):
+            eps[n + 1] = H0 + np.cos(1.3 * n * h) * H1
+        Gf = F.green_from_H(g, eps)
+        Gd = O.HM(g)
+        rc, _ = O.solve_fixed(Gd, O.HM(g), eps)
+        assert rc == 0
+        e = max(np.abs(Gd.ret - Gf.ret).max(), np.abs(Gd.les - Gf.les).max(), np.abs(Gd.tv - Gf.tv).max())
+        assert np.abs(Gd.mat - Gf.mat).max() < 1e-12
+        errs.append(e)
+    assert errs[0] < 1e-5, errs
+    assert errs[0] / errs[1] > 12.0, errs
