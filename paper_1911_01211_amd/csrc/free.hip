@@ -90,56 +90,6 @@ __device__ inline void wave_expm(int d, cplx* M, cplx* E, int lane) {
   for (int i = 0; i < s; i++) wave_prod(d, E, E, E, lane);
 }
 
-// Cyclic Jacobi rotations on the hermitian d x d matrix A in LDS (destroyed):
-// A = V diag(x) V^dag, one wave, the d rows / columns of every rotation
-// updated by d lanes at once (the rotation sequence of a one-thread sweep).
-__device__ inline void wave_jacobi(int d, cplx* A, cplx* V, double* x, int lane) {
-  int dd = d * d;
-  if (lane < dd) V[lane] = (lane / d == lane % d) ? mk(1, 0) : mk(0, 0);
-  wave_sync();
-  for (int sweep = 0; sweep < 60; sweep++) {
-    double v = lane < dd ? abs2(A[lane]) : 0.0;
-    double off = (lane < dd && lane / d != lane % d) ? v : 0.0;
-    for (int o = 32; o >= 1; o >>= 1) {
-      v += __shfl_xor(v, o);
-      off += __shfl_xor(off, o);
-    }
-    if (off <= 1e-32 * v) break;
-    for (int p = 0; p < d; p++)
-      for (int q = p + 1; q < d; q++) {
-        cplx apq = A[p * d + q];
-        double gabs = sqrt(abs2(apq));
-        if (gabs == 0) continue;
-        cplx ph = mk(apq.x / gabs, apq.y / gabs);
-        double th = (A[q * d + q].x - A[p * d + p].x) / (2 * gabs);
-        double t = (th >= 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(1 + th * th));
-        double cs = 1 / sqrt(1 + t * t), sn = t * cs;
-        wave_sync();
-        if (lane < d) {
-          int i = lane;
-          cplx aip = A[i * d + p], aiq = A[i * d + q];
-          A[i * d + p] = cs * aip - sn * (conj(ph) * aiq);
-          A[i * d + q] = sn * (ph * aip) + cs * aiq;
-        }
-        wave_sync();
-        if (lane < d) {
-          int j = lane;
-          cplx apj = A[p * d + j], aqj = A[q * d + j];
-          A[p * d + j] = cs * apj - sn * (ph * aqj);
-          A[q * d + j] = sn * (conj(ph) * apj) + cs * aqj;
-        } else if (lane >= 32 && lane < 32 + d) {
-          int i = lane - 32;
-          cplx vip = V[i * d + p], viq = V[i * d + q];
-          V[i * d + p] = cs * vip - sn * (conj(ph) * viq);
-          V[i * d + q] = sn * (ph * vip) + cs * viq;
-        }
-        wave_sync();
-      }
-  }
-  if (lane < d) x[lane] = A[lane * d + lane].x;
-  wave_sync();
-}
-
 __device__ inline double lagrange_w(int j0, int k, int i, double t) {
   double w = 1.0;
   for (int m = 0; m <= k; m++)

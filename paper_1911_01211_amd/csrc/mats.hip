@@ -55,18 +55,69 @@ __host__ __device__ inline void herm_jacobi(int d, cplx* A, cplx* V, double* x) 
   for (int i = 0; i < d; i++) x[i] = A[i * d + i].x;
 }
 
+// Cyclic Jacobi rotations on the hermitian d x d matrix A in LDS (destroyed):
+// A = V diag(x) V^dag, one wave, the d rows / columns of every rotation
+// updated by d lanes at once (the rotation sequence of a one-thread sweep).
+__device__ inline void wave_jacobi(int d, cplx* A, cplx* V, double* x, int lane) {
+  int dd = d * d;
+  if (lane < dd) V[lane] = (lane / d == lane % d) ? mk(1, 0) : mk(0, 0);
+  wave_sync();
+  for (int sweep = 0; sweep < 60; sweep++) {
+    double v = lane < dd ? abs2(A[lane]) : 0.0;
+    double off = (lane < dd && lane / d != lane % d) ? v : 0.0;
+    for (int o = 32; o >= 1; o >>= 1) {
+      v += __shfl_xor(v, o);
+      off += __shfl_xor(off, o);
+    }
+    if (off <= 1e-32 * v) break;
+    for (int p = 0; p < d; p++)
+      for (int q = p + 1; q < d; q++) {
+        cplx apq = A[p * d + q];
+        double gabs = sqrt(abs2(apq));
+        if (gabs == 0) continue;
+        cplx ph = mk(apq.x / gabs, apq.y / gabs);
+        double th = (A[q * d + q].x - A[p * d + p].x) / (2 * gabs);
+        double t = (th >= 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(1 + th * th));
+        double cs = 1 / sqrt(1 + t * t), sn = t * cs;
+        wave_sync();
+        if (lane < d) {
+          int i = lane;
+          cplx aip = A[i * d + p], aiq = A[i * d + q];
+          A[i * d + p] = cs * aip - sn * (conj(ph) * aiq);
+          A[i * d + q] = sn * (ph * aip) + cs * aiq;
+        }
+        wave_sync();
+        if (lane < d) {
+          int j = lane;
+          cplx apj = A[p * d + j], aqj = A[q * d + j];
+          A[p * d + j] = cs * apj - sn * (ph * aqj);
+          A[q * d + j] = sn * (conj(ph) * apj) + cs * aqj;
+        } else if (lane >= 32 && lane < 32 + d) {
+          int i = lane - 32;
+          cplx vip = V[i * d + p], viq = V[i * d + q];
+          V[i * d + p] = cs * vip - sn * (conj(ph) * viq);
+          V[i * d + q] = sn * (ph * vip) + cs * viq;
+        }
+        wave_sync();
+      }
+  }
+  if (lane < d) x[lane] = A[lane * d + lane].x;
+  wave_sync();
+}
+
 // g(tau) = -V diag( e^{-x tau} / (1 - xi e^{-beta x}) ) V^dag for
 // eps_{-1} - mu = V diag(x) V^dag, evaluated in the overflow-free form.
 __global__ __launch_bounds__(NT3) void k_free_mat(Prob P, cplx* g) {
   __shared__ cplx A[64], V[64];
   __shared__ double x[8];
   int d = P.d, dd = d * d, tid = threadIdx.x;
-  if (tid == 0) {
-    for (int e = 0; e < dd; e++) {
-      A[e] = P.eps[e];
-      if (e / d == e % d) A[e].x -= P.mu;
+  if (tid < 64) {
+    if (tid < dd) {
+      A[tid] = gld(P.eps + tid);
+      if (tid / d == tid % d) A[tid].x -= P.mu;
     }
-    herm_jacobi(d, A, V, x);
+    wave_sync();
+    wave_jacobi(d, A, V, x, tid);
   }
   __syncthreads();
   double xi = P.sig, beta = P.beta;
