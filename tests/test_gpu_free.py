@@ -96,3 +96,21 @@ def test_free_green_constant_hamiltonian_and_errors(O):
     bad = W.GridSpec(nt=3, ntau=20, d=2, sig=-1, k=5, beta=2.0, h=0.04, mu=0.0)
     with pytest.raises(RuntimeError):
         K.green_from_H([K.Contour(bad)], [to_dev(np.zeros((bad.nt + 2, 2, 2), np.complex128))])
+
+
+def test_free_green_batch_of_problems(O):
+    """One call for three problems sharing d, k and ntau, with different nt,
+    beta, mu and Hamiltonians: each equals its own oracle result."""
+    require_gpu()
+    say("free green batch")
+    grids = [W.GridSpec(nt=nt, ntau=30, d=3, sig=-1, k=4, beta=b, h=0.04, mu=mu)
+             for nt, b, mu in ((50, 2.0, 0.1), (17, 5.0, -0.3), (33, 1.0, 0.0))]
+    epss = [driven(W.rng(404, i), g) for i, g in enumerate(grids)]
+    Gs = [K.Contour(g) for g in grids]
+    K.green_from_H(Gs, [to_dev(e) for e in epss])
+    K.sync()
+    for g, e, G in zip(grids, epss, Gs):
+        got = G.numpy()
+        ref = F.green_from_H(ogrid(O, g), e)
+        for key in ("mat", "ret", "les", "tv"):
+            assert relerr(got[key], getattr(ref, key)) < TOL, (g.nt, key)
