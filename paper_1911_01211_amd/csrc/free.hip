@@ -13,8 +13,8 @@
 //
 // Kernels (one problem per launch; d <= 8, so a d x d block fits one wave
 // with one element per lane):
-//   k_cf4_steps : the step propagators, one wave per step (Taylor series
-//                 with scaling and squaring);
+//   k_cf4_steps : the step propagators, one wave per factor of Eq. cf4
+//                 (Taylor series with scaling and squaring);
 //   k_cf4_local : their products within chunks of CF_CH steps;
 //   k_cf4_carry : the products across chunks (one wave) and, meanwhile, the
 //                 eigenvectors of eps(0^-) - mu with rho;
@@ -97,42 +97,46 @@ __device__ inline double lagrange_w(int j0, int k, int i, double t) {
   return w;
 }
 
-// Step propagators S_n = U_{n+1,n}, one wave per step (4 per workgroup),
-// stored at loc[n+1].
+// Step propagators S_n = U_{n+1,n}, two waves per step (2 steps per
+// workgroup): the even wave of a pair forms the left factor of Eq. cf4, the
+// odd wave the right one, then the even wave multiplies them into loc[n+1].
 __global__ __launch_bounds__(CF_NT) void k_cf4_steps(Prob P, FreeScratch fs) {
-  __shared__ cplx wk[4][4][64];
+  __shared__ cplx wk[4][2][64];
   const double SQ3 = 1.7320508075688772;
   const double a1 = (3.0 - 2.0 * SQ3) / 12.0, a2 = (3.0 + 2.0 * SQ3) / 12.0;
   const double c1 = (1.0 - 1.0 / SQ3) / 2.0, c2 = (1.0 + 1.0 / SQ3) / 2.0;
   int d = P.d, dd = d * d, k = P.k;
-  int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  int n = blockIdx.x * 4 + wave;
-  if (n >= P.nt) return;  // (whole waves)
+  int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, side = wave & 1;
+  int n = blockIdx.x * 2 + (wave >> 1);
+  bool act = n < P.nt;  // (whole waves)
   double h = P.h;
-  cplx *M1 = wk[wave][0], *M2 = wk[wave][1], *E1 = wk[wave][2], *E2 = wk[wave][3];
-  int j0 = n - k + 1 > 0 ? n - k + 1 : 0;
-  if (lane < dd) {
-    cplx e1 = mk(0, 0), e2 = mk(0, 0);
-    for (int m = 0; m <= k; m++) {
-      cplx ev = gld(P.eps + (size_t)(j0 + m + 1) * dd + lane);
-      e1 = e1 + lagrange_w(j0, k, m, n + c1) * ev;
-      e2 = e2 + lagrange_w(j0, k, m, n + c2) * ev;
+  cplx *M = wk[wave][0], *E = wk[wave][1];
+  if (act) {
+    int j0 = n - k + 1 > 0 ? n - k + 1 : 0;
+    if (lane < dd) {
+      cplx e1 = mk(0, 0), e2 = mk(0, 0);
+      for (int m = 0; m <= k; m++) {
+        cplx ev = gld(P.eps + (size_t)(j0 + m + 1) * dd + lane);
+        e1 = e1 + lagrange_w(j0, k, m, n + c1) * ev;
+        e2 = e2 + lagrange_w(j0, k, m, n + c2) * ev;
+      }
+      // (the Hamiltonian of the real-time branch is eps - mu, as in the Dyson
+      // equations of this library)
+      if (lane / d == lane % d) {
+        e1.x -= P.mu;
+        e2.x -= P.mu;
+      }
+      // exponents -i h (a1 e1 + a2 e2) (left factor) and -i h (a2 e1 + a1 e2)
+      M[lane] = side == 0 ? mk(0, -h) * (a1 * e1 + a2 * e2) : mk(0, -h) * (a2 * e1 + a1 * e2);
     }
-    // (the Hamiltonian of the real-time branch is eps - mu, as in the Dyson
-    // equations of this library)
-    if (lane / d == lane % d) {
-      e1.x -= P.mu;
-      e2.x -= P.mu;
-    }
-    // exponents -i h (a1 e1 + a2 e2) (left factor) and -i h (a2 e1 + a1 e2)
-    M1[lane] = mk(0, -h) * (a1 * e1 + a2 * e2);
-    M2[lane] = mk(0, -h) * (a2 * e1 + a1 * e2);
+    wave_sync();
+    wave_expm(d, M, E, lane);
   }
-  wave_sync();
-  wave_expm(d, M1, E1, lane);
-  wave_expm(d, M2, E2, lane);
-  wave_prod(d, E1, E2, E2, lane);
-  if (lane < dd) gst(fs.loc + (size_t)(n + 1) * dd + lane, E2[lane]);
+  __syncthreads();
+  if (!act || side != 0) return;
+  cplx* EL = wk[wave][1];
+  wave_prod(d, EL, wk[wave + 1][1], EL, lane);
+  if (lane < dd) gst(fs.loc + (size_t)(n + 1) * dd + lane, EL[lane]);
 }
 
 // Products within chunk blockIdx.x (one wave):
@@ -319,7 +323,7 @@ hipError_t launch_free_green(const Prob& P, void* scratch, hipStream_t s) {
   fs.R = fs.rho + dd;
   fs.x = (double*)(fs.R + dd);
   if (nch > 0) {
-    k_cf4_steps<<<(nt + 3) / 4, CF_NT, 0, s>>>(P, fs);
+    k_cf4_steps<<<(nt + 1) / 2, CF_NT, 0, s>>>(P, fs);
     k_cf4_local<<<nch, 64, 0, s>>>(P, fs);
   }
   k_cf4_carry<<<1, 128, 0, s>>>(P, fs);
