@@ -55,7 +55,7 @@ typedef enum {
   CNTR_OK = 0,
   CNTR_EINVAL = -1,     /* k not in 1..5, d < 1 or d > 8, ntau < 2k+2, nt < k, sig not +-1, h/beta <= 0 */
   CNTR_ESHAPE = -2,     /* inconsistent instances or NULL pointers */
-  CNTR_EORDER = -3,     /* tstp out of range for the instance (causality, Tab. dyson) */
+  CNTR_EORDER = -3,     /* tstp out of range, or (order checks on) inputs of tstp not complete (Tab. dyson) */
   CNTR_ESINGULAR = -4,  /* singular step or start-up matrix (device) */
   CNTR_ENONFINITE = -5, /* non-finite value detected */
   CNTR_EHIP = -6,       /* HIP runtime error */
@@ -310,9 +310,36 @@ cntr_status cntr_profile_begin(void);
 cntr_status cntr_profile_begin_every(int32_t every);
 cntr_status cntr_profile_end(cntr_profile* out);
 
+/* --------------------------------------------------------------- checks --
+ * Optional checks of the preconditions of the Dyson equation (Tab. dyson:
+ * the step at tstp needs slices -1..tstp-1 of G) and of the values, in the
+ * spirit of the library's debug mode (Sec. "Compilation of libcntr"). Off by
+ * default; process-wide.
+ *  CNTR_CHECK_ORDER  : the library records, per instance (keyed by the
+ *     device pointer G.ret), the last completed slice: cntr_init_matsubara
+ *     sets it to -1, the start-up to k, a step at tstp to max(last, tstp),
+ *     cntr_solve_2b(_batch) to the last slice computed. cntr_dyson_step
+ *     then returns CNTR_EORDER, with nothing enqueued, for an instance that
+ *     is unknown or whose last completed slice is below tstp - 1 (below -1
+ *     for the start-up). Instances filled by other means are declared with
+ *     cntr_mark_slices. Records persist until cntr_mark_slices(.., -2),
+ *     cntr_set_checks without the flag, or cntr_finalize; an allocation
+ *     freed and reused for another instance keeps its record.
+ *  CNTR_CHECK_FINITE : after every start-up or step a device check of the
+ *     slices it wrote, the self-energy slices of the same index and eps;
+ *     a non-finite value sets the problem's status word, reported as
+ *     CNTR_ENONFINITE by cntr_sync. Costs one read of those slices. */
+#define CNTR_CHECK_ORDER 1
+#define CNTR_CHECK_FINITE 2
+cntr_status cntr_set_checks(int32_t flags);
+/* Declare slices -1..last of `count` instances complete (last = -2 removes
+ * the records). Host only; count >= 1, G non-NULL. */
+cntr_status cntr_mark_slices(int32_t count, const cntr_gf* G, int32_t last);
+
 /* ------------------------------------------------------------- plumbing -- */
 /* Wait for `stream`; report a failure recorded by kernels since the last
- * check (CNTR_ESINGULAR) or a HIP error. */
+ * check (CNTR_ESINGULAR, or CNTR_ENONFINITE with the finite check on; every
+ * problem of the last step call on the stream is scanned) or a HIP error. */
 cntr_status cntr_sync(void* stream);
 /* Message for the last failing call of this thread ("" if none). */
 const char* cntr_last_error(void);

@@ -11,6 +11,8 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libcntr.so")
 
+CHECK_ORDER, CHECK_FINITE = 1, 2
+
 STATUS = {0: "CNTR_OK", -1: "CNTR_EINVAL", -2: "CNTR_ESHAPE", -3: "CNTR_EORDER",
           -4: "CNTR_ESINGULAR", -5: "CNTR_ENONFINITE", -6: "CNTR_EHIP", -7: "CNTR_ENOMEM",
           -8: "CNTR_ENOCONV"}
@@ -19,7 +21,7 @@ SYMBOLS = ["cntr_init_matsubara", "cntr_dyson_step", "cntr_convolution", "cntr_s
            "cntr_extrapolate", "cntr_green_from_H", "cntr_distance", "cntr_copy_slice", "cntr_solve_2b", "cntr_sync",
            "cntr_last_error", "cntr_finalize", "cntr_version", "cntr_profile_begin", "cntr_profile_begin_every",
            "cntr_profile_end", "cntr_observables", "cntr_sigma_local", "cntr_adjoint_sweep",
-           "cntr_solve_2b_batch"]
+           "cntr_solve_2b_batch", "cntr_set_checks", "cntr_mark_slices"]
 
 
 class CntrError(RuntimeError):
@@ -70,6 +72,8 @@ def lib():
         L.cntr_solve_2b_batch.argtypes = [i32, P(Grid), P(GF), P(GF), P(GF), P(vp), P(vp), P(vp), dbl, i32, dbl,
                                           dbl, i32, dbl, i32, P(dbl), vp]
         L.cntr_sync.argtypes = [vp]
+        L.cntr_set_checks.argtypes = [i32]
+        L.cntr_mark_slices.argtypes = [i32, P(GF), i32]
         L.cntr_profile_begin.argtypes = []
         L.cntr_profile_begin_every.argtypes = [C.c_int32]
         L.cntr_profile_end.argtypes = [P(Profile)]

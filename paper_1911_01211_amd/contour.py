@@ -225,6 +225,16 @@ def copy_slice(tstp: int, dst: list, src: list, stream=None):
                                           _stream(stream)))
 
 
+def set_checks(order=False, finite=False):
+    """Optional precondition / value checks (cntr_set_checks)."""
+    _abi.check(_abi.lib().cntr_set_checks((_abi.CHECK_ORDER if order else 0) | (_abi.CHECK_FINITE if finite else 0)))
+
+
+def mark_slices(G: list, last: int):
+    """Declare slices -1..last of each G complete for the order checks (-2 forgets them)."""
+    _abi.check(_abi.lib().cntr_mark_slices(len(G), _gfs(G), int(last)))
+
+
 def sync(stream=None):
     _abi.check(_abi.lib().cntr_sync(_stream(stream)))
 

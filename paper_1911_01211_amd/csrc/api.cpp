@@ -22,9 +22,22 @@ thread_local std::string g_err;
 std::mutex g_mu;
 bool g_weights_ready[64] = {false};
 
+// optional checks (cntr_set_checks): the last completed slice of every
+// instance seen, keyed by its retarded-component pointer
+int g_checks = 0;
+std::map<const void*, int> g_last;
+
+// Each stream's scratch starts with STAT_WORDS status words (one per problem
+// of a call; a kernel that detects a failure writes its code there, cntr_sync
+// reports and clears them), followed by the data region of the calls.
+constexpr int STAT_WORDS = 65536;
+constexpr size_t STAT_HEAD = STAT_WORDS * sizeof(int);
 struct StreamScratch {
   char* buf = nullptr;
-  size_t bytes = 0;
+  size_t bytes = 0;  // of the data region
+  int nstat = 0;     // status words written since the last cntr_sync (problems of the largest call)
+  char* data() const { return buf + STAT_HEAD; }
+  int* stat() const { return (int*)buf; }
   Prob* probs = nullptr;  // device copies of batched descriptors (5 sets)
   size_t nprob = 0;
   double* red = nullptr;  // reduction outputs
@@ -89,12 +102,13 @@ cntr_status grow(hipStream_t s, StreamScratch* sc, size_t bytes, size_t nprob, s
     }
     sc->buf = nullptr;
     size_t nb = bytes + bytes / 4;
-    if (hipMalloc(&sc->buf, nb) != hipSuccess) {
+    if (hipMalloc(&sc->buf, nb + STAT_HEAD) != hipSuccess) {
       sc->bytes = 0;
       return fail(CNTR_ENOMEM, "scratch allocation failed");
     }
     sc->bytes = nb;
-    if (hipMemsetAsync(sc->buf, 0, nb, s) != hipSuccess) return fail(CNTR_EHIP, "scratch clear");
+    sc->nstat = 0;
+    if (hipMemsetAsync(sc->buf, 0, nb + STAT_HEAD, s) != hipSuccess) return fail(CNTR_EHIP, "scratch clear");
   }
   if (nprob > sc->nprob) {
     if (sc->probs) {
@@ -232,6 +246,39 @@ long slice_elems(const cntr_grid& g, int n) {
   long dd = (long)g.d * g.d;
   if (n < 0) return (g.ntau + 1) * dd;
   return (2L * (n + 1) + g.ntau + 1) * dd;
+}
+
+// ------------------------------------------------------- order checks
+// With CNTR_CHECK_ORDER: the step at tstp needs slices -1..tstp-1 of every
+// instance (Tab. dyson); the start-up needs the Matsubara component.
+cntr_status order_check(int tstp, int k, int count, const cntr_gf* G, const char* what) {
+  if (!(g_checks & CNTR_CHECK_ORDER)) return CNTR_OK;
+  std::lock_guard<std::mutex> lk(g_mu);
+  for (int i = 0; i < count; i++) {
+    auto it = g_last.find(G[i].ret);
+    int need = tstp <= k ? -1 : tstp - 1;
+    if (it == g_last.end() || it->second < need) {
+      char buf[256];
+      snprintf(buf, sizeof buf, "%s: instance %d has slices up to %d, slice %d needs slices -1..%d", what, i,
+               it == g_last.end() ? -2 : it->second, tstp, need);
+      return fail(CNTR_EORDER, buf);
+    }
+  }
+  return CNTR_OK;
+}
+// records slices -1..last as complete (only when order checks are on; an
+// instance is entered by the Matsubara solve or cntr_mark_slices)
+void order_mark(int count, const cntr_gf* G, int last, bool create) {
+  if (!(g_checks & CNTR_CHECK_ORDER)) return;
+  std::lock_guard<std::mutex> lk(g_mu);
+  for (int i = 0; i < count; i++) {
+    auto it = g_last.find(G[i].ret);
+    if (it != g_last.end()) {
+      if (create || last > it->second) it->second = last;
+    } else if (create) {
+      g_last[G[i].ret] = last;
+    }
+  }
 }
 
 // ------------------------------------------------- Matsubara solve state
@@ -425,6 +472,26 @@ cntr_status cntr_profile_end(cntr_profile* out) {
 
 const char* cntr_last_error(void) { return g_err.c_str(); }
 
+cntr_status cntr_set_checks(int32_t flags) {
+  if (flags & ~(CNTR_CHECK_ORDER | CNTR_CHECK_FINITE)) return fail(CNTR_EINVAL, "cntr_set_checks: unknown flag");
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (!(flags & CNTR_CHECK_ORDER)) g_last.clear();
+  g_checks = flags;
+  return CNTR_OK;
+}
+
+cntr_status cntr_mark_slices(int32_t count, const cntr_gf* G, int32_t last) {
+  if (count < 1 || !G) return fail(CNTR_ESHAPE, "cntr_mark_slices: empty batch");
+  if (last < -2) return fail(CNTR_EINVAL, "cntr_mark_slices: last < -2");
+  std::lock_guard<std::mutex> lk(g_mu);
+  for (int i = 0; i < count; i++) {
+    if (!G[i].ret) return fail(CNTR_ESHAPE, "cntr_mark_slices: null pointer");
+    if (last == -2) g_last.erase(G[i].ret);
+    else g_last[G[i].ret] = last;
+  }
+  return CNTR_OK;
+}
+
 cntr_status cntr_finalize(void) {
   std::lock_guard<std::mutex> lk(g_mu);
   for (auto& kv : g_scratch) {
@@ -434,6 +501,7 @@ cntr_status cntr_finalize(void) {
     if (kv.second.host) (void)hipHostFree(kv.second.host);
   }
   g_scratch.clear();
+  g_last.clear();
   for (hipEvent_t e : g_prof.pool) (void)hipEventDestroy(e);
   g_prof.pool.clear();
   g_prof.rec.clear();
@@ -445,18 +513,25 @@ cntr_status cntr_sync(void* stream) {
   hipStream_t s = (hipStream_t)stream;
   hipError_t e = hipStreamSynchronize(s);
   if (e != hipSuccess) return hip_fail(e, "stream synchronize");
-  StreamScratch* sc = scratch_for(s);
-  if (!sc->buf) return CNTR_OK;
-  // status words live at the start of each problem region; scan the buffer
-  // head (the first problem) and any recorded code.
   int code = 0;
-  e = hipMemcpy(&code, sc->buf, sizeof(int), hipMemcpyDeviceToHost);
+  StreamScratch* sc = scratch_for(s);
+  if (!sc->buf || sc->nstat == 0) return CNTR_OK;
+  // the status words of the problems of the calls since the last check
+  int cnt = sc->nstat;
+  std::vector<int> codes(cnt, 0);
+  e = hipMemcpy(codes.data(), sc->stat(), cnt * sizeof(int), hipMemcpyDeviceToHost);
   if (e != hipSuccess) return hip_fail(e, "status readback");
-  if (code != 0) {
-    int zero = 0;
-    (void)hipMemcpy(sc->buf, &zero, sizeof(int), hipMemcpyHostToDevice);
-    return fail((cntr_status)code, "singular step matrix detected on the device");
-  }
+  sc->nstat = 0;
+  for (int i = 0; i < cnt; i++)
+    if (codes[i] != 0) {
+      code = codes[i];
+      std::vector<int> zero(cnt, 0);
+      (void)hipMemcpy(sc->stat(), zero.data(), cnt * sizeof(int), hipMemcpyHostToDevice);
+      return fail((cntr_status)code, code == CNTR_ENONFINITE
+                                         ? "non-finite value in a time step (problem " + std::to_string(i) + ")"
+                                         : "singular step matrix detected on the device (problem " +
+                                               std::to_string(i) + ")");
+    }
   return CNTR_OK;
 }
 
@@ -464,6 +539,7 @@ cntr_status cntr_dyson_step(int32_t tstp, int32_t count, const cntr_grid* grids,
                             const cntr_gf* Sigma, const void* const* eps, void* stream) {
   cntr_status st = check_batch(count, grids, "cntr_dyson_step");
   if (st) return st;
+  if (count > STAT_WORDS) return fail(CNTR_ESHAPE, "cntr_dyson_step: more than 65536 problems");
   if (!gf_ok(G, count) || !gf_ok(Sigma, count) || !eps) return fail(CNTR_ESHAPE, "cntr_dyson_step: null pointer");
   int k = grids[0].k, d = grids[0].d, ntau = grids[0].ntau;
   int ntmax = 0;
@@ -472,6 +548,7 @@ cntr_status cntr_dyson_step(int32_t tstp, int32_t count, const cntr_grid* grids,
     if (grids[i].nt > ntmax) ntmax = grids[i].nt;
   }
   if (tstp < 0 || tstp > ntmax) return fail(CNTR_EORDER, "cntr_dyson_step: tstp outside 0..nt");
+  if ((st = order_check(tstp, k, count, G, "cntr_dyson_step"))) return st;
   if ((st = ensure_weights())) return st;
   hipStream_t s = (hipStream_t)stream;
   StreamScratch* sc = scratch_for(s);
@@ -484,12 +561,17 @@ cntr_status cntr_dyson_step(int32_t tstp, int32_t count, const cntr_grid* grids,
   ProbArg pa;
   if ((st = make_arg(s, sc, v, 0, &pa))) return st;
   Scratch scr = lay.sc;
-  scr.base = sc->buf;
+  scr.base = sc->data();
+  scr.stat = sc->stat();
+  sc->nstat = std::max(sc->nstat, (int)count);
   bool shared = true;  // one Sigma (statistics, grid) for every problem
   for (int i = 1; i < count; i++)
     shared = shared && v[i].Stv == v[0].Stv && v[i].sig == v[0].sig && grids[i].nt == grids[0].nt;
   hipError_t e = tstp <= k ? launch_start(pa, scr, d, ntau, s) : launch_step(pa, scr, tstp, d, s, shared);
+  if (e == hipSuccess && (g_checks & CNTR_CHECK_FINITE))
+    e = launch_check_finite(pa, scr, tstp <= k ? 0 : tstp, tstp <= k ? k : tstp, d, ntau, s);
   if (e != hipSuccess) return hip_fail(e, "cntr_dyson_step launch");
+  order_mark(count, G, tstp <= k ? k : tstp, false);
   return CNTR_OK;
 }
 
@@ -511,6 +593,7 @@ cntr_status cntr_init_matsubara(int32_t count, const cntr_grid* grids, const cnt
     ms.have_inv = false;
     if ((st = mats_solve(ms, P, false, tol, max_iter, s, nullptr))) return st;
   }
+  order_mark(count, G, -1, true);
   return CNTR_OK;
 }
 
@@ -670,8 +753,8 @@ cntr_status cntr_adjoint_sweep(int32_t count, const cntr_grid* grids, const cntr
   size_t per = round256(lay.total * sizeof(cplx)) + work;
   size_t head = round256(count * sizeof(int)) + 2 * round256(count * sizeof(AdjProb));
   if ((st = grow(s, sc, head + per * count, 5, 2))) return st;
-  int* dstat = (int*)sc->buf;
-  AdjProb* dA = (AdjProb*)(sc->buf + round256(count * sizeof(int)));
+  int* dstat = (int*)sc->data();
+  AdjProb* dA = (AdjProb*)(sc->data() + round256(count * sizeof(int)));
   AdjProb* dDry = (AdjProb*)((char*)dA + round256(count * sizeof(AdjProb)));
   std::vector<AdjProb> hA(count);
   for (int i = 0; i < count; i++) {
@@ -686,7 +769,7 @@ cntr_status cntr_adjoint_sweep(int32_t count, const cntr_grid* grids, const cntr
     a.sL = Sigmabar ? (cplx*)Sigmabar[i].les : nullptr;
     a.sT = Sigmabar ? (cplx*)Sigmabar[i].tv : nullptr;
     a.ge = (cplx*)eps_bar[i];
-    char* base = sc->buf + head + per * i;
+    char* base = sc->data() + head + per * i;
     a.scr = (cplx*)base;
     a.stat = dstat + i;
     if (twob) {
@@ -816,7 +899,7 @@ cntr_status cntr_green_from_H(int32_t count, const cntr_grid* grids, const cntr_
   if ((st = grow(s, sc, need, 0, 0))) return st;
   for (int i = 0; i < count; i++) {
     Prob P = make_prob(grids[i], &G[i], nullptr, eps[i]);
-    hipError_t e = launch_free_green(P, sc->buf, s);
+    hipError_t e = launch_free_green(P, sc->data(), s);
     if (e != hipSuccess) return hip_fail(e, "cntr_green_from_H");
   }
   return CNTR_OK;
@@ -907,7 +990,9 @@ cntr_status cntr_solve_2b(const cntr_grid* grid, const cntr_gf* G, const cntr_gf
   StepScratch lay = step_layout(gmax);
   if ((st = grow(s, sc, lay.per, 5, 2))) return st;
   Scratch scr = lay.sc;
-  scr.base = sc->buf;
+  scr.base = sc->data();
+  scr.stat = sc->stat();
+  sc->nstat = std::max(sc->nstat, 1);
   Prob P = make_prob(g, G, Sigma, eps_mf);
   P.U = U;
   P.eps0 = (const cplx*)eps0;
@@ -960,6 +1045,7 @@ cntr_status cntr_solve_2b(const cntr_grid* grid, const cntr_gf* G, const cntr_gf
   }
   for (int n = k + 1; n <= nt_stop; n++)
     if ((e = launch_sigma2b(pa, n, d, (int)slice_elems(g, n), nbar, s))) return hip_fail(e, "Sigma");
+  order_mark(1, G, nt_stop, true);
   return CNTR_OK;
 }
 
@@ -984,8 +1070,11 @@ cntr_status cntr_solve_2b_batch(int32_t count, const cntr_grid* grids, const cnt
   StreamScratch* sc = scratch_for(s);
   StepScratch lay = step_layout(gmax);
   if ((st = grow(s, sc, lay.per * count, 5 * (size_t)count, 2 * (size_t)count))) return st;
+  if (count > STAT_WORDS) return fail(CNTR_ESHAPE, "cntr_solve_2b_batch: more than 65536 problems");
   Scratch scr = lay.sc;
-  scr.base = sc->buf;
+  scr.base = sc->data();
+  scr.stat = sc->stat();
+  sc->nstat = std::max(sc->nstat, (int)count);
   std::vector<Prob> v(count), vo(count);
   for (int i = 0; i < count; i++) {
     v[i] = make_prob(grids[i], &G[i], &Sigma[i], eps_mf[i]);
@@ -1055,6 +1144,7 @@ cntr_status cntr_solve_2b_batch(int32_t count, const cntr_grid* grids, const cnt
   }
   for (int n = k + 1; n <= ntmax; n++)
     if ((e = launch_sigma2b(pa, n, d, (int)slice_elems(gmax, n), nbar, s))) return hip_fail(e, "Sigma");
+  for (int i = 0; i < count; i++) order_mark(1, &G[i], grids[i].nt, true);
   return CNTR_OK;
 }
 

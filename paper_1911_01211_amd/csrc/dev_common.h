@@ -14,11 +14,13 @@ struct ProbArg {
   __device__ inline const Prob& get(int i) const { return count == 1 ? one : many[i]; }
 };
 
-// Per-problem scratch region.
+// Per-problem scratch region, and one status word per problem of the call
+// (kept apart from the regions, whose layout depends on the call).
 struct Scratch {
   char* base;
   size_t stride;  // bytes per problem
   size_t off_minv, off_part, off_tail, off_status;
+  int* stat;      // status words, one per problem
   __device__ inline cplx* minv(int pi) const { return (cplx*)(base + pi * stride + off_minv); }
   // boundary-row source terms of the retarded boundary columns (after the
   // KMAX + 2 inverses), d x d blocks of d = dd
@@ -27,7 +29,7 @@ struct Scratch {
   __device__ inline cplx* zop(int pi, int dd) const { return minv(pi) + (2 * KMAX + 4) * dd; }
   __device__ inline cplx* part(int pi) const { return (cplx*)(base + pi * stride + off_part); }
   __device__ inline cplx* tail(int pi) const { return (cplx*)(base + pi * stride + off_tail); }
-  __device__ inline int* status(int pi) const { return (int*)(base + pi * stride + off_status); }
+  __device__ inline int* status(int pi) const { return stat + pi; }
   // completion counter of the boundary-row kernel (reset to 0 by its user)
   __device__ inline int* counter(int pi) const { return (int*)(base + pi * stride + off_status + 64); }
 };

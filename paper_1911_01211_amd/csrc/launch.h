@@ -64,9 +64,15 @@ size_t step_scratch_bytes(int nt, int k, int ntau, int d);
 // shared_sigma: every problem of the call has the same Sigma (pointer) and
 // statistics; for d = 1 batches the tau source is then one product of the
 // shared (Nτ+1) x (Nτ+1) operator with the problems' G^M
+// record: the profiler may record events around the step (off for callers
+// that must not create runtime objects)
 hipError_t launch_step(const ProbArg& pa, const Scratch& sc, int n, int d, hipStream_t s,
-                       bool shared_sigma = false);
+                       bool shared_sigma = false, bool record = true);
 hipError_t launch_start(const ProbArg& pa, const Scratch& sc, int d, int ntau, hipStream_t s);
+// non-finite values in slices n0..n1 of G and Sigma or in eps_n0..n1 set the
+// problem's status word to CNTR_ENONFINITE
+hipError_t launch_check_finite(const ProbArg& pa, const Scratch& sc, int n0, int n1, int d, int ntau,
+                               hipStream_t s);
 hipError_t launch_sigma2b(const ProbArg& pa, int n, int d, int nmax_elems, double nbar,
                           hipStream_t s);
 hipError_t launch_extrapolate(const ProbArg& pa, int n, int d, int nelems, hipStream_t s);

@@ -233,6 +233,39 @@ __global__ __launch_bounds__(NT2) void k_copy(ProbArg pd, ProbArg ps, int n) {
   *slice_ptr(D, s, n, D.Gret, D.Gles, D.Gtv) = *slice_ptr(S, s, n, S.Gret, S.Gles, S.Gtv);
 }
 
+// ------------------------------------------------------------ checks
+__device__ inline bool finite_c(cplx v) { return isfinite(v.x) && isfinite(v.y); }
+
+// Finite check of one time step (optional, cntr_set_checks): slice n of G
+// (the step's output) and of Sigma, and eps_n; the first non-finite value of
+// a problem sets its status word to CNTR_ENONFINITE.
+__global__ __launch_bounds__(NT2) void k_check_finite(ProbArg pa, Scratch sc, int n0, int n1) {
+  int pi = blockIdx.y;
+  const Prob& P = pa.get(pi);
+  int d = P.d, dd = d * d, ntau = P.ntau;
+  bool bad = false;
+  for (int n = n0; n <= min(n1, P.nt); n++) {
+    long total = (long)(2 * (n + 1) + ntau + 1) * dd;
+    for (long idx = (long)blockIdx.x * NT2 + threadIdx.x; idx < total; idx += (long)gridDim.x * NT2) {
+      SliceIdx s = slice_idx(idx, n, ntau, d);
+      bad = bad || !finite_c(gld(slice_ptr(P, s, n, P.Gret, P.Gles, P.Gtv)));
+      bad = bad || !finite_c(gld(slice_ptr(P, s, n, P.Sret, P.Sles, P.Stv)));
+    }
+    if (blockIdx.x == 0 && threadIdx.x < dd) bad = bad || !finite_c(gld(P.eps + (size_t)(n + 1) * dd + threadIdx.x));
+  }
+  if (bad) atomicCAS(sc.status(pi), 0, (int)CNTR_ENONFINITE);
+}
+
+hipError_t launch_check_finite(const ProbArg& pa, const Scratch& sc, int n0, int n1, int d, int ntau,
+                               hipStream_t s) {
+  long total = (long)(2 * (n1 + 1) + ntau + 1) * d * d;
+  long nb = (total + NT2 - 1) / NT2;
+  int blocks = (int)(nb < 64 ? nb : 64);
+  dim3 g(blocks, pa.count);
+  k_check_finite<<<g, NT2, 0, s>>>(pa, sc, n0, n1);
+  return hipGetLastError();
+}
+
 hipError_t launch_copy(const ProbArg& pdst, const ProbArg& psrc, int n, int d, int nelems,
                        hipStream_t s) {
   dim3 g((nelems + NT2 - 1) / NT2, pdst.count);

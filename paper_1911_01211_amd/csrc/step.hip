@@ -2183,7 +2183,8 @@ __global__ __launch_bounds__(NTHR) void k_tau_shared(ProbArg pa, Scratch sc, His
 
 // ------------------------------------------------------------ launches
 template <int D>
-static hipError_t step_d(const ProbArg& pa, const Scratch& sc, int n, hipStream_t s, bool shared_sigma) {
+static hipError_t step_d(const ProbArg& pa, const Scratch& sc, int n, hipStream_t s, bool shared_sigma,
+                         bool record) {
   const Prob& P0 = pa.one;  // d, k and ntau are uniform within a call
   int k = P0.k, ntau = P0.ntau;
   HistPlan pl = make_plan(n, k, ntau, D);
@@ -2197,7 +2198,7 @@ static hipError_t step_d(const ProbArg& pa, const Scratch& sc, int n, hipStream_
   }
   dim3 g1(pl.grid + 1, pa.count);
   hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr;
-  bool rec = g_prof.on && g_prof.seen++ % g_prof.every == 0;
+  bool rec = record && g_prof.on && g_prof.seen++ % g_prof.every == 0;
   if (rec) {
     e0 = prof_event();
     e1 = prof_event();
@@ -2225,16 +2226,17 @@ static hipError_t step_d(const ProbArg& pa, const Scratch& sc, int n, hipStream_
   return hipGetLastError();
 }
 
-hipError_t launch_step(const ProbArg& pa, const Scratch& sc, int n, int d, hipStream_t s, bool shared_sigma) {
+hipError_t launch_step(const ProbArg& pa, const Scratch& sc, int n, int d, hipStream_t s, bool shared_sigma,
+                       bool record) {
   switch (d) {
-    case 1: return step_d<1>(pa, sc, n, s, shared_sigma);
-    case 2: return step_d<2>(pa, sc, n, s, shared_sigma);
-    case 3: return step_d<3>(pa, sc, n, s, shared_sigma);
-    case 4: return step_d<4>(pa, sc, n, s, shared_sigma);
-    case 5: return step_d<5>(pa, sc, n, s, shared_sigma);
-    case 6: return step_d<6>(pa, sc, n, s, shared_sigma);
-    case 7: return step_d<7>(pa, sc, n, s, shared_sigma);
-    case 8: return step_d<8>(pa, sc, n, s, shared_sigma);
+    case 1: return step_d<1>(pa, sc, n, s, shared_sigma, record);
+    case 2: return step_d<2>(pa, sc, n, s, shared_sigma, record);
+    case 3: return step_d<3>(pa, sc, n, s, shared_sigma, record);
+    case 4: return step_d<4>(pa, sc, n, s, shared_sigma, record);
+    case 5: return step_d<5>(pa, sc, n, s, shared_sigma, record);
+    case 6: return step_d<6>(pa, sc, n, s, shared_sigma, record);
+    case 7: return step_d<7>(pa, sc, n, s, shared_sigma, record);
+    case 8: return step_d<8>(pa, sc, n, s, shared_sigma, record);
   }
   return hipErrorInvalidValue;
 }

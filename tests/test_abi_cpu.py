@@ -87,3 +87,27 @@ def test_adjoint_sweep_validation():
     assert L.cntr_adjoint_sweep(*args(n=0)) == -2
     bad = (_abi.Grid * 1)(_grid(k=7))
     assert L.cntr_adjoint_sweep(*args(gr=bad)) == -1
+
+
+def test_order_checks_track_the_last_completed_slice():
+    """With CNTR_CHECK_ORDER a step whose inputs are not complete is refused
+    on the host (Tab. dyson: the step at tstp needs slices -1..tstp-1)."""
+    L = _abi.lib()
+    g = (_abi.Grid * 1)(_grid(nt=10))
+    gf = (_abi.GF * 1)(_abi.GF(11, 12, 13, 14))
+    eps = (C.c_void_p * 1)(1)
+    assert L.cntr_set_checks(1) == 0
+    try:
+        assert L.cntr_dyson_step(5, 1, g, gf, gf, eps, None) == -3  # unknown instance
+        assert "slice" in L.cntr_last_error().decode()
+        assert L.cntr_mark_slices(1, gf, 6) == 0
+        assert L.cntr_dyson_step(8, 1, g, gf, gf, eps, None) == -3  # slice 7 missing
+        assert L.cntr_mark_slices(1, gf, 7) == 0
+        assert L.cntr_dyson_step(8, 1, g, gf, gf, eps, None) != -3  # passes the check (then needs a device)
+        assert L.cntr_mark_slices(1, gf, -2) == 0
+        assert L.cntr_dyson_step(8, 1, g, gf, gf, eps, None) == -3
+        assert L.cntr_set_checks(8) == -1
+    finally:
+        assert L.cntr_set_checks(0) == 0
+    # checks off: no tracking
+    assert L.cntr_dyson_step(5, 1, g, gf, gf, eps, None) != -3

@@ -1,0 +1,66 @@
+"""The optional checks of the library on the GPU: order tracking through the
+Matsubara solve, the start-up and the steps (CNTR_EORDER for a skipped
+slice), and the finite check (CNTR_ENONFINITE reported by cntr_sync for a
+non-finite self-energy value that the step reads only in its sums)."""
+import numpy as np
+import pytest
+import torch
+
+from paper_1911_01211_amd import _abi
+from paper_1911_01211_amd import contour as K
+from paper_1911_01211_amd import workloads as W
+from tests.test_gpu_parity import require_gpu, say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def test_order_checks_through_a_solve():
+    require_gpu()
+    say("order checks")
+    g = W.GridSpec(nt=20, ntau=30, d=2, beta=5.0, h=0.05, k=5)
+    eps, S, _ = W.two_level_embedding(g)
+    G, Sd, e = K.Contour(g), K.Contour(g, data=S), to_dev(eps)
+    K.set_checks(order=True)
+    try:
+        with pytest.raises(_abi.CntrError) as ex:
+            K.dyson_step(g.k, [G], [Sd], [e])  # no Matsubara component yet
+        assert ex.value.code == -3
+        K.init_matsubara([G], [Sd], [e])
+        K.dyson_step(g.k, [G], [Sd], [e])
+        with pytest.raises(_abi.CntrError) as ex:
+            K.dyson_step(g.k + 2, [G], [Sd], [e])  # slice k+1 missing
+        assert ex.value.code == -3
+        for n in range(g.k + 1, g.nt + 1):
+            K.dyson_step(n, [G], [Sd], [e])
+        K.dyson_step(g.nt, [G], [Sd], [e])  # a corrector pass on the last slice
+        K.sync()
+    finally:
+        K.mark_slices([G], -2)
+        K.set_checks()
+
+
+def test_finite_check_reports_nonfinite_sigma():
+    require_gpu()
+    say("finite check")
+    g = W.GridSpec(nt=20, ntau=30, d=2, beta=5.0, h=0.05, k=5)
+    r = W.rng(650)
+    G = K.Contour(g, data=W.random_contour(r, g, 0.3, decay=0.3))
+    c = W.random_contour(r, g, 0.3, decay=0.3)
+    n = 14
+    c["les"][n * (n + 1) // 2 + 3, 0, 1] = np.nan  # Sigma^<_{3,n}: enters the lesser sources only
+    S = K.Contour(g, data=c)
+    e = to_dev(np.broadcast_to(W.random_hermitian(r, 2), (g.nt + 2, 2, 2)).copy())
+    K.set_checks(finite=True)
+    try:
+        K.dyson_step(n - 1, [G], [S], [e])
+        K.sync()  # slice n - 1 is finite
+        K.dyson_step(n, [G], [S], [e])
+        with pytest.raises(_abi.CntrError) as ex:
+            K.sync()
+        assert ex.value.code == -5
+        K.sync()  # reported once
+    finally:
+        K.set_checks()
+    K.dyson_step(n, [G], [S], [e])
+    K.sync()  # checks off: nothing reported
+    assert torch.isnan(G.les[n * (n + 1) // 2:(n + 1) * (n + 2) // 2]).any()

@@ -186,3 +186,37 @@ def test_observables_free_closed_forms(O):
     for n in (0, 5, 6, 20, g1.nt):
         obs, _ = O.observables(n, Ga, Sb, e1)
         assert abs(obs[3] - ref) < 1e-8, (n, obs[3], ref)
+
+
+def test_2b_equilibrium_is_stationary(O):
+    """No quench, constant U: the self-consistent second-Born state of the
+    Matsubara branch must be a stationary state of the real-time propagation
+    with the same functional (Sigma^M and the real-time components of Eq.
+    sigma_hubb_2b describe one contour function). G^<(t,t) stays at its
+    initial value and G^R(t,t') depends on t - t' only, up to a
+    discretisation error that falls at the order of the scheme. A Matsubara
+    self-energy inconsistent with the real-time one (a sign, a transposed
+    index, U^2 on the wrong branch) starts the propagation from a state that is
+    not an equilibrium of the real-time equations, and the density moves."""
+    out = []
+    for h in (0.1, 0.05):
+        g = W.GridSpec(nt=int(round(2.0 / h)), ntau=60, d=2, beta=4.0, h=h, k=5)
+        r = W.rng(41)
+        H = W.haar_hermitian(r, 2, -1.0, 1.0)
+        e0 = np.broadcast_to(H, (g.nt + 2, 2, 2)).astype(np.complex128).copy()
+        U = np.full(g.nt + 2, 1.5)
+        G, S = hm(O, g), hm(O, g)
+        rc, emf, st = O.solve_2b(G, S, e0, U, ncorr=6)
+        assert rc == 0 and st["mats_err"] < 1e-13 and st["corr_err_max"] < 1e-10, st
+        rho0 = O.density_matrix(-1, G)
+        e = 0.0
+        for n in range(g.nt + 1):
+            e = max(e, np.abs(O.density_matrix(n, G) - rho0).max())
+            for j in range(n + 1):
+                e = max(e, np.abs(G.R(n, j) - G.R(n - j, 0)).max())
+        out.append(e)
+        # the interaction matters at this coupling: the density is not f(H)
+        x, V = np.linalg.eigh(H)
+        fH = (V / (np.exp(g.beta * x) + 1.0)) @ V.conj().T
+        assert np.abs(rho0 - fH).max() > 1e-2
+    assert out[1] < 2e-5 and np.log2(out[0] / out[1]) > 3.8, out
