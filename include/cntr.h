@@ -102,6 +102,24 @@ cntr_status cntr_init_matsubara(int32_t count, const cntr_grid* grids, const cnt
 cntr_status cntr_dyson_step(int32_t tstp, int32_t count, const cntr_grid* grids, const cntr_gf* G,
                             const cntr_gf* Sigma, const void* const* eps, void* stream);
 
+/* Allocation-free variant of cntr_dyson_step, for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc. Same arguments, kernels and results as
+ * cntr_dyson_step; it calls no hipMalloc/hipFree and creates no runtime
+ * objects (no profiler events). Its scratch (partial sums, step inverses,
+ * status words, batch descriptors) is a static device array of
+ * 64 MiB + 41 KiB held by every GPU the library runs on until the process
+ * ends; the descriptors of a batch (count > 1) are written by a small kernel
+ * whose arguments carry them, so nothing refers to host memory after the
+ * call. Limits: count <= 256, and the step regions of all problems (the step
+ * at the largest nt of the call; about 42 MB for nt = 1000, ntau = 400,
+ * d = 4) must fit in 64 MiB, else CNTR_ENOMEM with nothing enqueued. Every
+ * call on one GPU shares that GPU's array and leaves its contents for the
+ * next: calls that overlap on one GPU (two streams, two threads) race.
+ * Device-detected failures are reported by cntr_sync. */
+cntr_status cntr_dyson_step_noalloc(int32_t tstp, int32_t count, const cntr_grid* grids, const cntr_gf* G,
+                                    const cntr_gf* Sigma, const void* const* eps, void* stream);
+
 /* ------------------------------------------------------------------ A8 --
  * Contour convolution C = A * f * B on time slice tstp (Eq. convolution,
  * Tab. convolution; discretised by Eqs. cm1, cm2, cr1, ctv1-ctv3,
@@ -318,7 +336,7 @@ cntr_status cntr_profile_end(cntr_profile* out);
  *  CNTR_CHECK_ORDER  : the library records, per instance (keyed by the
  *     device pointer G.ret), the last completed slice: cntr_init_matsubara
  *     sets it to -1, the start-up to k, a step at tstp to max(last, tstp),
- *     cntr_solve_2b(_batch) to the last slice computed. cntr_dyson_step
+ *     cntr_solve_2b(_batch) to the last slice computed. cntr_dyson_step(_noalloc)
  *     then returns CNTR_EORDER, with nothing enqueued, for an instance that
  *     is unknown or whose last completed slice is below tstp - 1 (below -1
  *     for the start-up). Instances filled by other means are declared with

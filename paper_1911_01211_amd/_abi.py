@@ -21,7 +21,8 @@ SYMBOLS = ["cntr_init_matsubara", "cntr_dyson_step", "cntr_convolution", "cntr_s
            "cntr_extrapolate", "cntr_green_from_H", "cntr_distance", "cntr_copy_slice", "cntr_solve_2b", "cntr_sync",
            "cntr_last_error", "cntr_finalize", "cntr_version", "cntr_profile_begin", "cntr_profile_begin_every",
            "cntr_profile_end", "cntr_observables", "cntr_sigma_local", "cntr_adjoint_sweep",
-           "cntr_solve_2b_batch", "cntr_set_checks", "cntr_mark_slices"]
+           "cntr_solve_2b_batch", "cntr_set_checks", "cntr_mark_slices",
+           "cntr_dyson_step_noalloc"]
 
 
 class CntrError(RuntimeError):
@@ -57,6 +58,7 @@ def lib():
         P = C.POINTER
         L.cntr_init_matsubara.argtypes = [i32, P(Grid), P(GF), P(GF), P(vp), dbl, i32, vp]
         L.cntr_dyson_step.argtypes = [i32, i32, P(Grid), P(GF), P(GF), P(vp), vp]
+        L.cntr_dyson_step_noalloc.argtypes = [i32, i32, P(Grid), P(GF), P(GF), P(vp), vp]
         L.cntr_convolution.argtypes = [i32, i32, P(Grid), P(GF), P(GF), P(GF), P(GF), P(GF), P(vp), vp]
         L.cntr_sigma_2b.argtypes = [i32, i32, P(Grid), P(GF), P(vp), P(GF), P(vp), P(vp), dbl, vp]
         L.cntr_extrapolate.argtypes = [i32, i32, P(Grid), P(GF), vp]

@@ -80,6 +80,14 @@ def dyson_step(tstp: int, G: list, Sigma: list, eps: list, stream=None):
                                  _stream(stream)))
 
 
+def dyson_step_noalloc(tstp: int, G: list, Sigma: list, eps: list, stream=None):
+    """cntr_dyson_step_noalloc: the same step with the library's static device
+    scratch (no allocation; usable under graph capture)."""
+    L = _abi.lib()
+    _abi.check(L.cntr_dyson_step_noalloc(tstp, len(G), _grids(G), _gfs(G), _gfs(Sigma), _ptrs(eps),
+                                         _stream(stream)))
+
+
 def convolution(tstp: int, C_: list, A: list, Acc: list, B: list, Bcc: list, f=None, stream=None):
     L = _abi.lib()
     fp = None if f is None else _ptrs(f)

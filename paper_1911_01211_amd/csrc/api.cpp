@@ -424,6 +424,83 @@ cntr_status mats_loop_2b(const cntr_grid& g, const Prob& P, const ProbArg& pa, c
   return CNTR_OK;
 }
 
+// ------------------------------------------------- allocation-free step
+// Scratch of cntr_dyson_step_noalloc: a file-scope device array, one copy per
+// GPU, held until the process ends. In host code `scratch` names a host-side
+// stand-in, so every host use goes through the device address obtained once
+// per device with hipGetSymbolAddress (g_na_ptr). Layout: descriptor slots of
+// NA_MAX_PROBS problems, then the per-problem step regions (status word and
+// completion counter at the start of each region, as in the stream scratch).
+constexpr size_t NA_STEP_BYTES = (size_t)64 << 20;
+constexpr int NA_MAX_PROBS = 256;
+constexpr size_t NA_DESC_BYTES = (NA_MAX_PROBS * sizeof(Prob) + 255) / 256 * 256;
+constexpr size_t NA_STAT_BYTES = NA_MAX_PROBS * sizeof(int);
+__device__ __align__(256) char scratch[NA_DESC_BYTES + NA_STAT_BYTES + NA_STEP_BYTES];
+
+char* g_na_ptr[64] = {nullptr};
+int g_na_nstat[64] = {0};  // status words written since the last cntr_sync
+
+// descriptors of a batch travel in kernel arguments (no host buffer that a
+// graph replay would have to read), NA_CHUNK per launch
+constexpr int NA_CHUNK = 16;
+struct ProbChunk {
+  Prob p[NA_CHUNK];
+  int count;
+};
+__global__ void k_put_probs(ProbChunk c, Prob* dst) {
+  int i = threadIdx.x;
+  if (i < c.count) dst[i] = c.p[i];
+}
+__global__ void k_zero_words(int* p, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = 0;
+}
+
+// Device address of `scratch` on the current device (set up on first use:
+// symbol address, status words cleared by a kernel).
+cntr_status noalloc_setup(hipStream_t s, char** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (dev < 0 || dev >= 64) return fail(CNTR_EINVAL, "cntr_dyson_step_noalloc: device index above 63");
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (!g_na_ptr[dev]) {
+    char* ptr = nullptr;
+    e = hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    k_zero_words<<<1024, 256, 0, s>>>((int*)ptr, sizeof(scratch) / sizeof(int));
+    if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "scratch clear");
+    g_na_ptr[dev] = ptr;
+  }
+  *out = g_na_ptr[dev];
+  return CNTR_OK;
+}
+
+// first failure code among the status words of the allocation-free calls on
+// the current device since the last check (0 when none); clears them
+cntr_status noalloc_status(int* code) {
+  *code = 0;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return CNTR_OK;
+  char* ptr;
+  int cnt;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    ptr = g_na_ptr[dev];
+    cnt = g_na_nstat[dev];
+    g_na_nstat[dev] = 0;
+  }
+  if (!ptr || cnt == 0) return CNTR_OK;
+  int codes[NA_MAX_PROBS];
+  hipError_t e = hipMemcpy(codes, ptr + NA_DESC_BYTES, cnt * sizeof(int), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e, "status readback");
+  for (int i = 0; i < cnt && !*code; i++) *code = codes[i];
+  if (*code != 0) {
+    for (int i = 0; i < cnt; i++) codes[i] = 0;
+    (void)hipMemcpy(ptr + NA_DESC_BYTES, codes, cnt * sizeof(int), hipMemcpyHostToDevice);
+  }
+  return CNTR_OK;
+}
+
 }  // namespace
 }  // namespace cntr
 
@@ -514,6 +591,11 @@ cntr_status cntr_sync(void* stream) {
   hipError_t e = hipStreamSynchronize(s);
   if (e != hipSuccess) return hip_fail(e, "stream synchronize");
   int code = 0;
+  cntr_status st = noalloc_status(&code);
+  if (st) return st;
+  if (code != 0)
+    return fail((cntr_status)code, code == CNTR_ENONFINITE ? "non-finite value in a time step"
+                                                           : "singular step matrix detected on the device");
   StreamScratch* sc = scratch_for(s);
   if (!sc->buf || sc->nstat == 0) return CNTR_OK;
   // the status words of the problems of the calls since the last check
@@ -571,6 +653,72 @@ cntr_status cntr_dyson_step(int32_t tstp, int32_t count, const cntr_grid* grids,
   if (e == hipSuccess && (g_checks & CNTR_CHECK_FINITE))
     e = launch_check_finite(pa, scr, tstp <= k ? 0 : tstp, tstp <= k ? k : tstp, d, ntau, s);
   if (e != hipSuccess) return hip_fail(e, "cntr_dyson_step launch");
+  order_mark(count, G, tstp <= k ? k : tstp, false);
+  return CNTR_OK;
+}
+
+cntr_status cntr_dyson_step_noalloc(int32_t tstp, int32_t count, const cntr_grid* grids, const cntr_gf* G,
+                                    const cntr_gf* Sigma, const void* const* eps, void* stream) {
+  cntr_status st = check_batch(count, grids, "cntr_dyson_step_noalloc");
+  if (st) return st;
+  if (!gf_ok(G, count) || !gf_ok(Sigma, count) || !eps)
+    return fail(CNTR_ESHAPE, "cntr_dyson_step_noalloc: null pointer");
+  if (count > NA_MAX_PROBS) return fail(CNTR_ENOMEM, "cntr_dyson_step_noalloc: more than 256 problems");
+  int k = grids[0].k, d = grids[0].d, ntau = grids[0].ntau;
+  int ntmax = 0;
+  for (int i = 0; i < count; i++) {
+    if (!eps[i]) return fail(CNTR_ESHAPE, "cntr_dyson_step_noalloc: null eps");
+    if (grids[i].nt > ntmax) ntmax = grids[i].nt;
+  }
+  if (tstp < 0 || tstp > ntmax) return fail(CNTR_EORDER, "cntr_dyson_step_noalloc: tstp outside 0..nt");
+  if ((st = order_check(tstp, k, count, G, "cntr_dyson_step_noalloc"))) return st;
+  // the scratch this call needs: the regions of the step at the largest nt
+  cntr_grid gmax = grids[0];
+  gmax.nt = ntmax < k + 1 ? k + 1 : ntmax;
+  StepScratch lay = step_layout(gmax);
+  if (lay.per * (size_t)count > NA_STEP_BYTES) {
+    char buf[200];
+    snprintf(buf, sizeof buf, "cntr_dyson_step_noalloc: needs %zu bytes of scratch, the static array holds %zu",
+             lay.per * (size_t)count, NA_STEP_BYTES);
+    return fail(CNTR_ENOMEM, buf);
+  }
+  if ((st = ensure_weights())) return st;
+  hipStream_t s = (hipStream_t)stream;
+  char* ptr = nullptr;
+  if ((st = noalloc_setup(s, &ptr))) return st;
+  std::vector<Prob> v(count);
+  for (int i = 0; i < count; i++) v[i] = make_prob(grids[i], &G[i], &Sigma[i], eps[i]);
+  ProbArg pa;
+  pa.one = v[0];
+  pa.count = count;
+  pa.many = nullptr;
+  if (count > 1) {
+    Prob* dst = (Prob*)ptr;
+    for (int i0 = 0; i0 < count; i0 += NA_CHUNK) {
+      ProbChunk c;
+      c.count = std::min(NA_CHUNK, count - i0);
+      for (int i = 0; i < c.count; i++) c.p[i] = v[i0 + i];
+      k_put_probs<<<1, 64, 0, s>>>(c, dst + i0);
+    }
+    pa.many = dst;
+  }
+  Scratch scr = lay.sc;
+  scr.base = ptr + NA_DESC_BYTES + NA_STAT_BYTES;
+  scr.stat = (int*)(ptr + NA_DESC_BYTES);
+  {
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_na_nstat[dev] = std::max(g_na_nstat[dev], (int)count);
+  }
+  bool shared = true;
+  for (int i = 1; i < count; i++)
+    shared = shared && v[i].Stv == v[0].Stv && v[i].sig == v[0].sig && grids[i].nt == grids[0].nt;
+  hipError_t e = tstp <= k ? launch_start(pa, scr, d, ntau, s) : launch_step(pa, scr, tstp, d, s, shared, false);
+  if (e == hipSuccess && (g_checks & CNTR_CHECK_FINITE))
+    e = launch_check_finite(pa, scr, tstp <= k ? 0 : tstp, tstp <= k ? k : tstp, d, ntau, s);
+  if (e == hipSuccess) e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "cntr_dyson_step_noalloc launch");
   order_mark(count, G, tstp <= k ? k : tstp, false);
   return CNTR_OK;
 }
