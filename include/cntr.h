@@ -196,7 +196,27 @@ cntr_status cntr_observables(int32_t tstp, int32_t count, const cntr_grid* grids
 cntr_status cntr_green_from_H(int32_t count, const cntr_grid* grids, const cntr_gf* G, const void* const* eps,
                               void* stream);
 
-/* --------------------------------------------------------------- A10, A13 --
+/* ----------------------------------------------------------------- A12 --
+ * Peierls substitution: the vector potential as a phase factor in the
+ * hopping (Sec. "Example: GW for the translationally invariant Hubbard
+ * model"), the differentiable drive of the adjoint workload:
+ *   eps_n[a][b] = T_n[a][b] exp(i A_n Phi[a][b]),   n = -1..nt,
+ * T[i]: DEVICE (nt+2) d x d complex blocks (the bare levels, index n+1),
+ * Phi[i]: DEVICE d x d doubles (the phase pattern, e.g. +1 on a bond's
+ * i+1 <- i element, -1 on its conjugate, 0 on site energies),
+ * A[i]: DEVICE nt+2 doubles (index n+1; entry 0 is A(0^-)),
+ * eps[i]: DEVICE output of (nt+2) d x d blocks. Asynchronous. */
+cntr_status cntr_peierls(int32_t count, const cntr_grid* grids, const void* const* T, const double* const* Phi,
+                         const double* const* A, void* const* eps, void* stream);
+/* Its chain rule for a real objective J with eps_bar = dJ/dRe eps + i dJ/dIm
+ * eps (the gradient convention of cntr_adjoint_sweep):
+ *   A_bar[i][n+1] += Re sum_ab conj(eps_bar_n[a][b]) i Phi[a][b] eps_n[a][b]
+ * (eps recomputed from T, Phi, A). A_bar[i]: DEVICE nt+2 doubles (+=). d <= 8. */
+cntr_status cntr_peierls_grad(int32_t count, const cntr_grid* grids, const void* const* T,
+                              const double* const* Phi, const double* const* A, const void* const* eps_bar,
+                              double* const* A_bar, void* stream);
+
+/* --------------------------------------------------------------- A10, A13 --/* --------------------------------------------------------------- A10, A13 --
  * Polynomial predictor T[G]_tstp -> T[G]_{tstp+1} (Eq. polyextrap, App.
  * "Extrapolation of contour functions"); needs tstp >= k. */
 cntr_status cntr_extrapolate(int32_t tstp, int32_t count, const cntr_grid* grids, const cntr_gf* G,
@@ -276,15 +296,19 @@ cntr_status cntr_solve_2b(const cntr_grid* grid, const cntr_gf* G, const cntr_gf
  *   U_bar    : per problem DEVICE array of nt+2 doubles (+=), index n+1.
  *   niter    : fixed-point iterations per slice (<= 0: 10; each contracts the
  *              error by ~60x at the 2B chain's coupling).
- *   conv     : HOST double or NULL: largest relative change of a slice
- *              (or Matsubara) adjoint in its last iteration (second-Born mode).
+ *   tol      : second-Born mode, tol > 0: CNTR_ENOCONV (after the sweep, whose
+ *              outputs are then unreliable) when the largest relative change of
+ *              a slice (or Matsubara) adjoint in its last iteration exceeds tol;
+ *              tol <= 0: no check.
+ *   conv     : HOST double or NULL: that largest relative change (second-Born
+ *              mode).
  * Instances may have different nt (each is swept from its own nt). Every
  * pointer except conv is a DEVICE pointer, owned by the caller. Synchronizes
  * `stream`; CNTR_ESINGULAR if a local step or start-up matrix is singular. */
 cntr_status cntr_adjoint_sweep(int32_t count, const cntr_grid* grids, const cntr_gf* G, const cntr_gf* Sigma,
                                const void* const* eps, const double* const* U, double nbar,
                                const cntr_gf* Gbar, const cntr_gf* Sigmabar, void* const* eps_bar,
-                               double* const* U_bar, int32_t niter, double* conv, void* stream);
+                               double* const* U_bar, int32_t niter, double tol, double* conv, void* stream);
 
 /* ----------------------------------------------------------------- A11 --
  * The same self-consistent second-Born + Hartree propagation for `count`

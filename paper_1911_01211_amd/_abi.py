@@ -22,7 +22,7 @@ SYMBOLS = ["cntr_init_matsubara", "cntr_dyson_step", "cntr_convolution", "cntr_s
            "cntr_last_error", "cntr_finalize", "cntr_version", "cntr_profile_begin", "cntr_profile_begin_every",
            "cntr_profile_end", "cntr_observables", "cntr_sigma_local", "cntr_adjoint_sweep",
            "cntr_solve_2b_batch", "cntr_set_checks", "cntr_mark_slices",
-           "cntr_dyson_step_noalloc"]
+           "cntr_dyson_step_noalloc", "cntr_peierls", "cntr_peierls_grad"]
 
 
 class CntrError(RuntimeError):
@@ -70,11 +70,13 @@ def lib():
         L.cntr_observables.argtypes = [i32, i32, P(Grid), P(GF), P(GF), P(vp), P(vp), vp, vp, vp]
         L.cntr_sigma_local.argtypes = [i32, i32, P(Grid), P(GF), P(GF), dbl, vp]
         L.cntr_adjoint_sweep.argtypes = [i32, P(Grid), P(GF), P(GF), P(vp), P(vp), dbl, P(GF), P(GF), P(vp),
-                                         P(vp), i32, P(dbl), vp]
+                                         P(vp), i32, dbl, P(dbl), vp]
         L.cntr_solve_2b_batch.argtypes = [i32, P(Grid), P(GF), P(GF), P(GF), P(vp), P(vp), P(vp), dbl, i32, dbl,
                                           dbl, i32, dbl, i32, P(dbl), vp]
         L.cntr_sync.argtypes = [vp]
         L.cntr_set_checks.argtypes = [i32]
+        L.cntr_peierls.argtypes = [i32, P(Grid), P(vp), P(vp), P(vp), P(vp), vp]
+        L.cntr_peierls_grad.argtypes = [i32, P(Grid), P(vp), P(vp), P(vp), P(vp), P(vp), vp]
         L.cntr_mark_slices.argtypes = [i32, P(GF), i32]
         L.cntr_profile_begin.argtypes = []
         L.cntr_profile_begin_every.argtypes = [C.c_int32]

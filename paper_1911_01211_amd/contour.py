@@ -193,20 +193,21 @@ def observables(tstp: int, G: list, Sigma: list, eps0: list, eps_mf=None, stream
 
 
 def adjoint_sweep(G: list, Sigma: list, eps: list, Gbar: list, eps_bar: list, Sigmabar: list | None = None,
-                  U: list | None = None, U_bar: list | None = None, nbar=0.5, niter=10, stream=None):
+                  U: list | None = None, U_bar: list | None = None, nbar=0.5, niter=10, tol=0.0, stream=None):
     """Reverse-mode sweep of the Dyson solution (cntr_adjoint_sweep). Gbar
     holds dJ/dG on entry (consumed; Gbar.mat returns dJ/dM), eps_bar (+=)
     receives dJ/deps_n, Sigmabar (+=) dJ/dSigma. With U (second-Born mode:
     G, Sigma, eps the converged solution with eps = eps_mf) eps_bar receives
     dJ/deps0_n and U_bar (+=) dJ/dU_n. Returns the largest relative change of
-    a slice adjoint in its last fixed-point iteration (0 for a given Sigma).
+    a slice adjoint in its last fixed-point iteration (0 for a given Sigma);
+    with tol > 0 a change above tol raises CNTR_ENOCONV.
     Gradients are dJ/dRe + i dJ/dIm of every complex entry."""
     sb = None if Sigmabar is None else _gfs(Sigmabar)
     conv = C.c_double(0.0)
     up = None if U is None else _ptrs(U)
     ub = None if U_bar is None else _ptrs(U_bar)
     _abi.check(_abi.lib().cntr_adjoint_sweep(len(G), _grids(G), _gfs(G), _gfs(Sigma), _ptrs(eps), up, float(nbar),
-                                             _gfs(Gbar), sb, _ptrs(eps_bar), ub, int(niter), C.byref(conv),
+                                             _gfs(Gbar), sb, _ptrs(eps_bar), ub, int(niter), float(tol), C.byref(conv),
                                              _stream(stream)))
     return conv.value
 

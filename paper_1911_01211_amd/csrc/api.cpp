@@ -867,7 +867,7 @@ cntr_status cntr_observables(int32_t tstp, int32_t count, const cntr_grid* grids
 cntr_status cntr_adjoint_sweep(int32_t count, const cntr_grid* grids, const cntr_gf* G, const cntr_gf* Sigma,
                                const void* const* eps, const double* const* U, double nbar,
                                const cntr_gf* Gbar, const cntr_gf* Sigmabar, void* const* eps_bar,
-                               double* const* U_bar, int32_t niter, double* conv, void* stream) {
+                               double* const* U_bar, int32_t niter, double tol, double* conv, void* stream) {
   cntr_status st = check_batch(count, grids, "cntr_adjoint_sweep");
   if (st) return st;
   if (count > 65535) return fail(CNTR_ESHAPE, "cntr_adjoint_sweep: at most 65535 problems per call");
@@ -1008,7 +1008,7 @@ cntr_status cntr_adjoint_sweep(int32_t count, const cntr_grid* grids, const cntr
   std::vector<int> hs(count, 0);
   std::vector<std::vector<double>> hc;
   if (e == hipSuccess) e = hipMemcpyAsync(hs.data(), dstat, count * sizeof(int), hipMemcpyDeviceToHost, s);
-  if (twob && conv)
+  if (twob && (conv || tol > 0))
     for (int i = 0; i < count && e == hipSuccess; i++) {
       hc.emplace_back(2 * (grids[i].nt + 2));
       e = hipMemcpyAsync(hc.back().data(), hA[i].conv, hc.back().size() * sizeof(double), hipMemcpyDeviceToHost, s);
@@ -1017,7 +1017,7 @@ cntr_status cntr_adjoint_sweep(int32_t count, const cntr_grid* grids, const cntr
   if (e != hipSuccess) return hip_fail(e, "cntr_adjoint_sweep");
   for (int i = 0; i < count; i++)
     if (hs[i]) return fail(CNTR_ESINGULAR, "cntr_adjoint_sweep: singular local matrix in problem " + std::to_string(i));
-  if (twob && conv) {
+  if (twob && (conv || tol > 0)) {
     // slots: slice n for the steps (n > k), slot k for the start-up block
     double worst = 0.0;
     for (int i = 0; i < count; i++)
@@ -1026,7 +1026,13 @@ cntr_status cntr_adjoint_sweep(int32_t count, const cntr_grid* grids, const cntr
         double r = v > 0 ? ch / v : ch;
         worst = r > worst ? r : worst;
       }
-    *conv = worst > mats_change ? worst : mats_change;
+    worst = worst > mats_change ? worst : mats_change;
+    if (conv) *conv = worst;
+    if (tol > 0 && !(worst <= tol)) {
+      char buf[160];
+      snprintf(buf, sizeof buf, "cntr_adjoint_sweep: last fixed-point change %.3e above tol %.3e", worst, tol);
+      return fail(CNTR_ENOCONV, buf);
+    }
   }
   return CNTR_OK;
 }
@@ -1049,6 +1055,37 @@ cntr_status cntr_green_from_H(int32_t count, const cntr_grid* grids, const cntr_
     Prob P = make_prob(grids[i], &G[i], nullptr, eps[i]);
     hipError_t e = launch_free_green(P, sc->data(), s);
     if (e != hipSuccess) return hip_fail(e, "cntr_green_from_H");
+  }
+  return CNTR_OK;
+}
+
+cntr_status cntr_peierls(int32_t count, const cntr_grid* grids, const void* const* T, const double* const* Phi,
+                         const double* const* A, void* const* eps, void* stream) {
+  cntr_status st = check_batch(count, grids, "cntr_peierls");
+  if (st) return st;
+  if (!T || !Phi || !A || !eps) return fail(CNTR_ESHAPE, "cntr_peierls: null pointer");
+  hipStream_t s = (hipStream_t)stream;
+  for (int i = 0; i < count; i++) {
+    if (!T[i] || !Phi[i] || !A[i] || !eps[i]) return fail(CNTR_ESHAPE, "cntr_peierls: null pointer");
+    hipError_t e = launch_peierls((const cplx*)T[i], Phi[i], A[i], (cplx*)eps[i], grids[i].d, grids[i].nt, s);
+    if (e != hipSuccess) return hip_fail(e, "cntr_peierls launch");
+  }
+  return CNTR_OK;
+}
+
+cntr_status cntr_peierls_grad(int32_t count, const cntr_grid* grids, const void* const* T,
+                              const double* const* Phi, const double* const* A, const void* const* eps_bar,
+                              double* const* A_bar, void* stream) {
+  cntr_status st = check_batch(count, grids, "cntr_peierls_grad");
+  if (st) return st;
+  if (!T || !Phi || !A || !eps_bar || !A_bar) return fail(CNTR_ESHAPE, "cntr_peierls_grad: null pointer");
+  hipStream_t s = (hipStream_t)stream;
+  for (int i = 0; i < count; i++) {
+    if (!T[i] || !Phi[i] || !A[i] || !eps_bar[i] || !A_bar[i])
+      return fail(CNTR_ESHAPE, "cntr_peierls_grad: null pointer");
+    hipError_t e = launch_peierls_grad((const cplx*)T[i], Phi[i], A[i], (const cplx*)eps_bar[i], A_bar[i],
+                                       grids[i].d, grids[i].nt, s);
+    if (e != hipSuccess) return hip_fail(e, "cntr_peierls_grad launch");
   }
   return CNTR_OK;
 }

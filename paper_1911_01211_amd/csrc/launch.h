@@ -86,6 +86,11 @@ hipError_t launch_convolution(const ProbArg& C, const ProbArg& A, const ProbArg&
                               hipStream_t s);
 
 hipError_t launch_observables(const ProbArg& pa, int n, double* out, cplx* rho, hipStream_t s);
+// Peierls phase of the hopping and its chain rule (entries n = -1..nt)
+hipError_t launch_peierls(const cplx* T, const double* Phi, const double* A, cplx* eps, int d, int nt,
+                          hipStream_t s);
+hipError_t launch_peierls_grad(const cplx* T, const double* Phi, const double* A, const cplx* eps_bar,
+                               double* A_bar, int d, int nt, hipStream_t s);
 hipError_t launch_sigma_local(const ProbArg& pa, int n, int d, int nelems, double lam, hipStream_t s);
 
 // Matsubara pieces (per problem, one problem per call)

@@ -233,6 +233,56 @@ __global__ __launch_bounds__(NT2) void k_copy(ProbArg pd, ProbArg ps, int n) {
   *slice_ptr(D, s, n, D.Gret, D.Gles, D.Gtv) = *slice_ptr(S, s, n, S.Gret, S.Gles, S.Gtv);
 }
 
+// ------------------------------------------------------------ Peierls
+// Vector potential as a phase factor in the hopping (Peierls substitution,
+// Sec. "Example: GW for the translationally invariant Hubbard model"):
+//   eps_n[a][b] = T_n[a][b] exp(i A_n Phi[a][b]),  n = -1..nt (entry n+1),
+// with Phi the real phase pattern of the bonds (e.g. +1 / -1 on the two
+// directions of a bond, 0 on site energies).
+__global__ __launch_bounds__(NT2) void k_peierls(const cplx* T, const double* Phi, const double* A, cplx* eps,
+                                                 int dd, long total) {
+  long idx = (long)blockIdx.x * NT2 + threadIdx.x;
+  if (idx >= total) return;
+  int n1 = (int)(idx / dd), e = (int)(idx % dd);
+  double sn, cs;
+  sincos(A[n1] * Phi[e], &sn, &cs);
+  gst(eps + idx, gld(T + idx) * mk(cs, sn));
+}
+
+// Chain rule of the substitution for a real objective J with gradient
+// eps_bar = dJ/d Re eps + i dJ/d Im eps:
+//   A_bar_n += Re sum_ab conj(eps_bar_n[a][b]) i Phi[a][b] eps_n[a][b].
+// One wave per time entry, lanes over the d x d elements (d <= 8).
+__global__ __launch_bounds__(64) void k_peierls_grad(const cplx* T, const double* Phi, const double* A,
+                                                     const cplx* eps_bar, double* A_bar, int dd) {
+  int n1 = blockIdx.x, e = threadIdx.x;
+  double v = 0.0;
+  if (e < dd) {
+    long idx = (long)n1 * dd + e;
+    double sn, cs;
+    sincos(A[n1] * Phi[e], &sn, &cs);
+    cplx ep = gld(T + idx) * mk(cs, sn);
+    cplx de = mul_i(Phi[e] * ep);  // d eps / d A_n
+    cplx g = gld(eps_bar + idx);
+    v = g.x * de.x + g.y * de.y;  // Re(conj(g) de)
+  }
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  if (e == 0) A_bar[n1] += v;
+}
+
+hipError_t launch_peierls(const cplx* T, const double* Phi, const double* A, cplx* eps, int d, int nt,
+                          hipStream_t s) {
+  long total = (long)(nt + 2) * d * d;
+  k_peierls<<<(unsigned)((total + NT2 - 1) / NT2), NT2, 0, s>>>(T, Phi, A, eps, d * d, total);
+  return hipGetLastError();
+}
+
+hipError_t launch_peierls_grad(const cplx* T, const double* Phi, const double* A, const cplx* eps_bar,
+                               double* A_bar, int d, int nt, hipStream_t s) {
+  k_peierls_grad<<<nt + 2, 64, 0, s>>>(T, Phi, A, eps_bar, A_bar, d * d);
+  return hipGetLastError();
+}
+
 // ------------------------------------------------------------ checks
 __device__ inline bool finite_c(cplx v) { return isfinite(v.x) && isfinite(v.y); }
 

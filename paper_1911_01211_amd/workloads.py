@@ -205,3 +205,38 @@ def kpoint_band(g: GridSpec, nk: int = 512):
     eps[:, 0, 0, 0] = -2 * np.cos(k)
     eps[:, 1:, 0, 0] = -2 * np.cos(k[:, None] - A[None, :])
     return eps
+
+
+def ring_peierls(g: GridSpec, nsites: int = 8, J: float = 1.0):
+    """Periodic ring with a Peierls phase on the hopping: eps_{i+1,i}(t) =
+    -J e^{i A(t)} and its conjugate (Sec. "Example: GW for the translationally
+    invariant Hubbard model"). Returns the bare hopping T [nt+2, d, d]
+    (index n+1) and the phase pattern Phi [d, d] (+1 on i+1 <- i, -1 on
+    i <- i+1), so that eps_n = T * exp(i A_n Phi) elementwise."""
+    T = np.zeros((nsites, nsites), np.complex128)
+    Phi = np.zeros((nsites, nsites))
+    for i in range(nsites):
+        j = (i + 1) % nsites
+        T[j, i] = T[i, j] = -J
+        Phi[j, i], Phi[i, j] = 1.0, -1.0
+    return np.broadcast_to(T, (g.nt + 2, nsites, nsites)).copy(), Phi
+
+
+def ring_drive(g: GridSpec, key: int = 5):
+    """Seeded vector potential of the eight-site ring workload: four modes,
+    c_q ~ N(0, 0.25^2), w_q ~ U[0.5, 3], phi_q ~ U[0, 2 pi), and
+    A_n = sum_q c_q sin(w_q t_n + phi_q) (1 - exp(-t_n^2)) for n = 1..nt
+    (smooth, A(0) = 0). Returns the nt samples A_1..A_nt."""
+    r = rng(key)
+    c = r.normal(0.0, 0.25, 4)
+    w = r.uniform(0.5, 3.0, 4)
+    ph = r.uniform(0.0, 2 * np.pi, 4)
+    t = np.arange(1, g.nt + 1) * g.h
+    return (c[None, :] * np.sin(w[None, :] * t[:, None] + ph[None, :])).sum(1) * (1 - np.exp(-t * t))
+
+
+def peierls_levels(T: np.ndarray, Phi: np.ndarray, A_samples: np.ndarray) -> np.ndarray:
+    """Input levels of the ring for the oracle: eps_n = T_n exp(i A_n Phi),
+    with A = 0 at entries -1 and 0 and A_1..A_nt after them."""
+    A = np.concatenate([[0.0, 0.0], A_samples])
+    return T * np.exp(1j * A[:, None, None] * Phi[None, :, :])

@@ -75,7 +75,7 @@ def test_adjoint_sweep_validation():
     pn = (C.c_void_p * 1)(None)
     conv = C.c_double(0.0)
     args = lambda G=gf, S=gf, Gb=gf, Sb=None, U=None, Ub=None, eb=p1, n=1, gr=g: (
-        n, gr, G, S, p1, U, 0.5, Gb, Sb, eb, Ub, 4, C.byref(conv), None)
+        n, gr, G, S, p1, U, 0.5, Gb, Sb, eb, Ub, 4, 0.0, C.byref(conv), None)
     assert L.cntr_adjoint_sweep(*args(G=nul)) == -2
     assert L.cntr_adjoint_sweep(*args(Gb=nul)) == -2
     assert L.cntr_adjoint_sweep(*args(eb=pn)) == -2

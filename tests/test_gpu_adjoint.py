@@ -178,7 +178,7 @@ def setup_2b(O, d, nt, ntau, seed):
     return g, r, e0, U, C
 
 
-def gpu_gradients_2b(g, e0, U, C, niter=10):
+def gpu_gradients_2b(g, e0, U, C, niter=10, tol=1e-13):
     """GPU forward (cntr_solve_2b) then the second-Born adjoint sweep."""
     G, S, Gs = K.Contour(g), K.Contour(g), K.Contour(g)
     e0d = torch.as_tensor(e0).to(DEV)
@@ -190,12 +190,12 @@ def gpu_gradients_2b(g, e0, U, C, niter=10):
     Gb, Sb = K.Contour(g, data=seed), K.Contour(g)
     eb = torch.zeros_like(e0d)
     ub = torch.zeros_like(Ud)
-    conv = K.adjoint_sweep([G], [S], [emf], [Gb], [eb], [Sb], U=[Ud], U_bar=[ub], niter=niter)
+    conv = K.adjoint_sweep([G], [S], [emf], [Gb], [eb], [Sb], U=[Ud], U_bar=[ub], niter=niter, tol=tol)
     K.sync()
     return eb.cpu().numpy(), ub.cpu().numpy(), conv
 
 
-@pytest.mark.parametrize("d,nt,ntau", [(2, 14, 12), (1, 17, 13), (3, 12, 12)])
+@pytest.mark.parametrize("d,nt,ntau", [(2, 14, 12), (1, 17, 13), (3, 12, 12), (4, 11, 12), (8, 9, 12)])
 def test_adjoint_2b_matches_oracle_differences(O, d, nt, ntau):
     """Gradients of J = Re <C, G> of the self-consistent 2B + Hartree solution
     with respect to eps0_n and U_n, n = -1..nt (n = -1 enters through the
@@ -241,3 +241,17 @@ def test_adjoint_2b_matches_oracle_differences(O, d, nt, ntau):
         err = abs(got - ref) / max(abs(ref), 1e-2 * scale, 1e-300)
         say(f"  {name}: adjoint {got:.12e} differences {ref:.12e} rel {err:.2e}")
         assert err < TOL, (name, got, ref, err)
+
+
+def test_adjoint_2b_reports_unconverged_fixed_points(O):
+    """One fixed-point iteration per slice leaves a change far above 1e-13:
+    with that tolerance the sweep returns CNTR_ENOCONV; without it, the
+    change is still reported."""
+    from paper_1911_01211_amd import _abi
+    say("adjoint 2B tolerance")
+    g, r, e0, U, C = setup_2b(O, 2, 12, 12, 2)
+    with pytest.raises(_abi.CntrError) as ex:
+        gpu_gradients_2b(g, e0, U, C, niter=1, tol=1e-13)
+    assert ex.value.code == -8
+    _, _, conv = gpu_gradients_2b(g, e0, U, C, niter=1, tol=0.0)
+    assert conv > 1e-13

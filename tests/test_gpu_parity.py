@@ -471,11 +471,11 @@ def test_batch_matches_single_instances(O, nb, d):
 
 def test_uneven_2b_batch(O):
     """Uneven batch (cntr_solve_2b_batch through contour.solve_uneven):
-    second-Born problems with d in {1, 2, 4} and different nt, a random
+    second-Born problems with d in {1, 2, 4, 8} and different nt, a random
     hermitian H with spectrum in [-2, 2] and a constant U in [0.5, 2] each;
     every problem of the batch equals its own oracle solve."""
     require_gpu()
-    specs = [(2, 20), (2, 14), (1, 24), (4, 16), (2, 17), (1, 13), (4, 12)]
+    specs = [(2, 20), (2, 14), (1, 24), (4, 16), (2, 17), (1, 13), (4, 12), (8, 11), (8, 14)]
     problems, refs = [], []
     for i, (d, nt) in enumerate(specs):
         say(f"uneven batch problem {i}: d={d} nt={nt}")
