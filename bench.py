@@ -107,38 +107,132 @@ def run_gpu(args):
     return g, elapsed, prof, stats, dens_dev, state
 
 
-def run_adjoint(g, state, args):
-    """Adjoint sample: gradient of the kinetic energy at the last time,
-    J = 2 Re Tr[eps_kin rho(t_nt)] with rho = -i G^<(t_nt, t_nt) (both spins),
-    with respect to every eps0_n and U_n (n = -1..nt) of the 2B chain run just timed
-    (second-Born mode of cntr_adjoint_sweep on its converged solution,
-    `niter` fixed-point iterations per slice)."""
+def run_adjoint(args):
+    """Adjoint workload: 8-site Hubbard ring with a Peierls phase e^{iA(t)} on
+    the hopping, second-Born + Hartree, U = 1.5, beta = 10, ntau = 400,
+    nt = 1500, h = 0.02, k = 5; A_1..A_1500 seeded samples. J = E_kin(t_nt)
+    and its gradient with respect to all 1500 samples A_n and U through
+    DysonKineticEnergy (forward: cntr_solve_2b; backward: the second-Born
+    adjoint sweep, Matsubara solve included). Checked against central
+    differences of the same GPU forward solve (delta = 1e-5 max(1, |theta|))
+    along two seeded directions in (A, U)."""
     import numpy as np
     import torch
 
-    from paper_1911_01211_amd import contour as K
+    from paper_1911_01211_amd import autograd as AG
+    from paper_1911_01211_amd import workloads as W
 
     dev = "cuda:0"
-    G, S, emf, U = state["G"], state["S"], state["emf"], state["U"]
-    d, nt = g.d, g.nt
-    ekin = state["e0"][nt + 1] * (1 - np.eye(d))  # hopping part of eps0(t_nt)
-    Gb, Sb = K.Contour(g, dev), K.Contour(g, dev)
-    eb = torch.zeros_like(emf)
-    ub = torch.zeros_like(U)
-    # J = Re(-2i sum_ab eps_ba L_ab)  ->  dJ/dL_ab = conj(-2i eps_ba)
-    Gb.les[-1] = torch.as_tensor(np.conj(-2j * ekin.T)).to(dev)
+    g = W.GridSpec(nt=args.adj_nt, ntau=400, d=8, sig=-1, k=5, beta=10.0, h=0.02, mu=0.0)
+    T, Phi = W.ring_peierls(g, 8)
+    A = W.ring_drive(g)
+    U0 = 1.5
+    m = AG.RingModel(g=g, T=torch.as_tensor(T).to(dev), Phi=torch.as_tensor(Phi).to(dev), ncorr=args.adj_ncorr,
+                     niter=args.adj_niter)
+    At = torch.tensor(A, dtype=torch.float64, device=dev, requires_grad=True)
+    Ut = torch.tensor(U0, dtype=torch.float64, device=dev, requires_grad=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    conv = K.adjoint_sweep([G], [S], [emf], [Gb], [eb], [Sb], U=[U], U_bar=[ub], niter=args.adj_niter)
+    J = AG.kinetic_energy(At, Ut.expand(g.nt + 2), m)
     torch.cuda.synchronize()
-    el = time.perf_counter() - t0
-    ubh = ub.cpu().numpy()
-    return {"workload": "gradient of the kinetic energy at t_nt w.r.t. eps0_n and U_n (n = 0..nt) of the "
-                        "same 2B chain solution (second-Born adjoint sweep, Matsubara solve included)",
-            "value": (nt - g.k) / el, "unit": "adjoint time-steps/s", "seconds": el,
-            "fixed_point_iterations": args.adj_niter, "fixed_point_last_change": conv,
-            "forward_equivalent": "one forward time step = 5 corrector iterations",
-            "dJ_dU_sum": float(ubh.sum())}
+    t1 = time.perf_counter()
+    J.backward()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    print(f"# adjoint ring: forward {t1 - t0:.2f}s backward {t2 - t1:.2f}s", file=sys.stderr, flush=True)
+    gA, gU = At.grad.cpu().numpy(), float(Ut.grad)
+    fd = []
+    if args.adj_fd:
+        r = W.rng(191, 5)
+        for q in range(2):
+            vA, vU = r.normal(size=g.nt), float(r.normal())
+            dl = 1e-5 * max(1.0, float(np.abs(A).max()), U0)
+            Jpm = []
+            for sgn in (1.0, -1.0):
+                with torch.no_grad():
+                    Ap = torch.tensor(A + sgn * dl * vA, dtype=torch.float64, device=dev)
+                    Up = torch.full((g.nt + 2,), U0 + sgn * dl * vU, dtype=torch.float64, device=dev)
+                    Jpm.append(float(AG.kinetic_energy(Ap, Up, m)))
+            ref = (Jpm[0] - Jpm[1]) / (2 * dl)
+            got = float(np.dot(gA, vA) + gU * vU)
+            fd.append({"direction": q, "adjoint": got, "central_difference": ref,
+                       "rel_err": abs(got - ref) / max(abs(ref), 1e-300)})
+            print(f"# adjoint ring: direction {q} rel err {fd[-1]['rel_err']:.2e}", file=sys.stderr, flush=True)
+    nsl = g.nt - g.k
+    return {"workload": f"8-site Hubbard ring, Peierls phase e^(iA(t)) on the hopping, second-Born + Hartree, "
+                        f"U=1.5, beta=10, ntau=400, nt={g.nt}, h=0.02, k=5; gradient of E_kin(t_nt) w.r.t. the "
+                        f"{g.nt} samples A_n and U (torch.autograd.Function over the adjoint sweep)",
+            "value": nsl / (t2 - t1), "unit": "adjoint time-steps/s",
+            "forward_s": t1 - t0, "backward_s": t2 - t1, "backward_over_forward": (t2 - t1) / (t1 - t0),
+            "J": float(J.detach()), "dJ_dU": gU, "max_abs_dJ_dA": float(np.abs(gA).max()),
+            "fixed_point_iterations": args.adj_niter, "forward_corrector_iterations": args.adj_ncorr,
+            "fixed_point_last_change": m.stats.get("adjoint_last_change"),
+            "fd_check": fd}
+
+
+def run_cfg1(args):
+    """Plain Dyson solve of the two-level system with the bath self-energy
+    (H = [[-1, 0.5], [0.5, 1]], beta = 5, Sigma = 0.16 g_bath(eps_b = 0.3),
+    nt = 100, h = 0.05, ntau = 100, k = 5): a launch-bound run of 95 short
+    steps. Timed as whole solves (Matsubara solve, start-up, steps), the
+    start-up and steps either launched one by one or replayed from one
+    captured HIP graph (cntr_graph_*), on the same stream."""
+    import torch
+
+    from paper_1911_01211_amd import contour as K
+    from paper_1911_01211_amd import workloads as W
+
+    g = W.GridSpec(nt=100, ntau=100, d=2, beta=5.0, h=0.05, k=5)
+    eps, S, _ = W.two_level_embedding(g)
+    dev = "cuda:0"
+    G, Sd, e = K.Contour(g, dev), K.Contour(g, dev, data=S), torch.as_tensor(eps).to(dev)
+    st = torch.cuda.Stream()
+
+    def steps():
+        for n in range(g.k, g.nt + 1):
+            K.dyson_step(n, [G], [Sd], [e], stream=st)
+
+    def solve(graph=None):
+        K.init_matsubara([G], [Sd], [e], stream=st)
+        if graph is None:
+            steps()
+        else:
+            graph.launch(st)
+
+    solve()
+    st.synchronize()
+    with K.Graph(st) as gr:
+        steps()
+    times = {}
+    reps = args.cfg1_reps
+    for mode, graph in (("eager", None), ("graph", gr), ("eager", None), ("graph", gr)):
+        solve(graph)
+        st.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            solve(graph)
+        st.synchronize()
+        times[mode] = min(times.get(mode, 1e30), (time.perf_counter() - t0) / reps)
+    # the step phase alone (start-up + 95 steps), HIP events on the stream
+    ph = {}
+    for mode in ("eager", "graph"):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        for _ in range(reps):
+            if mode == "eager":
+                steps()
+            else:
+                gr.launch(st)
+        e1.record(st)
+        st.synchronize()
+        ph[mode] = e0.elapsed_time(e1) / reps
+    nsl = g.nt - g.k
+    return {"workload": "two-level system with a fixed bath self-energy, nt=100, h=0.05, ntau=100, beta=5, k=5, "
+                        "d=2 (whole solves: Matsubara, start-up, 95 steps)",
+            "value": nsl / times["graph"], "unit": "time-steps/s",
+            "eager_time_steps_per_s": nsl / times["eager"],
+            "ms_per_solve": {k: v * 1e3 for k, v in times.items()},
+            "step_phase_ms": ph, "graph_speedup_step_phase": ph["eager"] / ph["graph"]}
 
 
 def run_free(args):
@@ -277,6 +371,15 @@ def run_kpoints(args):
         torch.cuda.synchronize()
         return e0.elapsed_time(e1)
 
+    # the whole batched step (every kernel of the corrector sweeps: history
+    # sums, reduce, shared tau source, local Sigma, extrapolation) against the
+    # HBM roofline at the algorithmic bytes of the history sums (each stored
+    # block once per sweep, all instances)
+    sweep_bytes = sum(16.0 * (n * (n + 1) + n * (g.ntau + 1)) for n in range(g.k + 1, args.kp_steps + 1)) * nk
+    whole_gbs = sweep_bytes * args.ncorr / el / 1e9
+    whole = {"bound": "hbm", "scope": "whole corrector sweeps, all kernels", "bytes_per_sweep": sweep_bytes,
+             "seconds_per_sweep": el / args.ncorr, "achieved": whole_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+             "frac": whole_gbs / HBM_PEAK_GBS}
     n_last, nloop = args.kp_steps, min(16, nk)
     t_batch = min(timed(lambda: B.step(n_last)) for _ in range(3))
     t_loop = min(timed(lambda: [K.dyson_step(n_last, [G[i]], [S], [eps[i]]) for i in range(nloop)])
@@ -291,7 +394,8 @@ def run_kpoints(args):
             "roofline": {"bound": "hbm", "kernel": "k_history<1>", "achieved": gbs, "peak": HBM_PEAK_GBS,
                          "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS if gbs else None,
                          "avg_launch_us": prof["hist_ms"] * 1e3 / max(1, prof["hist_launches"])},
-            "note": "prefix of the run (the per-slice cost grows with n)"}
+            "whole_step": whole,
+            "note": ("whole run" if args.kp_steps >= g.nt else "prefix of the run (the per-slice cost grows with n)")}
 
 
 def stream_bandwidth():
@@ -411,12 +515,19 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=25.0)
     ap.add_argument("--nk", type=int, default=512, help="k-points of the batched sample")
-    ap.add_argument("--kp-steps", type=int, default=300, help="last slice of the batched sample")
+    ap.add_argument("--kp-steps", type=int, default=2000, help="last slice of the batched k-point run")
     ap.add_argument("--no-kpoints", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-uneven", action="store_true")
     ap.add_argument("--no-free", action="store_true")
+    ap.add_argument("--no-cfg1", action="store_true")
+    ap.add_argument("--cfg1-reps", type=int, default=50)
     ap.add_argument("--adj-niter", type=int, default=10, help="adjoint fixed-point iterations per slice")
+    ap.add_argument("--adj-nt", type=int, default=1500, help="time steps of the adjoint ring workload")
+    ap.add_argument("--adj-ncorr", type=int, default=8,
+                    help="corrector iterations of the ring's forward solves (the adjoint is that of the converged "
+                         "fixed point)")
+    ap.add_argument("--adj-fd", type=int, default=1, help="central-difference check of the adjoint (0: off)")
     ap.add_argument("--profile-step", type=int, default=0,
                     help="only run the time step at this slice (counter runs), then a 1 GiB copy")
     args = ap.parse_args()
@@ -468,9 +579,11 @@ def main():
                      "avg_launch_us": prof["hist_ms"] * 1e3 / max(1, prof["hist_launches"])},
         "check": {"max_density_deviation_at_nt": dens_dev},
     }
-    if not args.no_adjoint:
-        out["adjoint"] = run_adjoint(g, state, args)
     del state
+    if not args.no_adjoint:
+        out["adjoint"] = run_adjoint(args)
+    if not args.no_cfg1:
+        out["plain_two_level"] = run_cfg1(args)
     if not args.no_uneven:
         out["uneven"] = run_uneven(args)
     if not args.no_free:

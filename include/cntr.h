@@ -352,7 +352,30 @@ cntr_status cntr_profile_begin(void);
 cntr_status cntr_profile_begin_every(int32_t every);
 cntr_status cntr_profile_end(cntr_profile* out);
 
-/* --------------------------------------------------------------- checks --
+/* --------------------------------------------------------------- graphs --
+ * Capture of launch sequences into a HIP graph and its replay: the step
+ * sequences of launch-bound runs (short grids, many problems) become one
+ * graph launch. Between cntr_graph_begin(s) and cntr_graph_end(s, &g) the
+ * calls that only enqueue work on s are recorded instead of executed:
+ * cntr_dyson_step(_noalloc), cntr_sigma_2b, cntr_sigma_local,
+ * cntr_extrapolate, cntr_copy_slice, cntr_convolution, cntr_observables,
+ * cntr_green_from_H, cntr_peierls(_grad). Batch descriptors are then written
+ * by kernels whose arguments carry them, and nothing is allocated: a call
+ * whose scratch is not yet large enough returns CNTR_EINVAL (make the same
+ * call once before capturing). Calls that synchronize (cntr_init_matsubara,
+ * cntr_distance, cntr_solve_2b(_batch), cntr_adjoint_sweep, cntr_sync)
+ * return CNTR_EINVAL during capture. s must not be the default (NULL)
+ * stream. The graph refers to the device arrays and to the stream's scratch
+ * as they were at capture time: keep them alive and do not make calls with
+ * larger problems on that stream (which would reallocate its scratch) while
+ * the graph is in use. cntr_graph_launch replays the graph on any stream. */
+typedef struct cntr_graph_s* cntr_graph;
+cntr_status cntr_graph_begin(void* stream);
+cntr_status cntr_graph_end(void* stream, cntr_graph* out);
+cntr_status cntr_graph_launch(cntr_graph graph, void* stream);
+cntr_status cntr_graph_destroy(cntr_graph graph);
+
+/* --------------------------------------------------------------- checks --/* --------------------------------------------------------------- checks --
  * Optional checks of the preconditions of the Dyson equation (Tab. dyson:
  * the step at tstp needs slices -1..tstp-1 of G) and of the values, in the
  * spirit of the library's debug mode (Sec. "Compilation of libcntr"). Off by

@@ -22,7 +22,8 @@ SYMBOLS = ["cntr_init_matsubara", "cntr_dyson_step", "cntr_convolution", "cntr_s
            "cntr_last_error", "cntr_finalize", "cntr_version", "cntr_profile_begin", "cntr_profile_begin_every",
            "cntr_profile_end", "cntr_observables", "cntr_sigma_local", "cntr_adjoint_sweep",
            "cntr_solve_2b_batch", "cntr_set_checks", "cntr_mark_slices",
-           "cntr_dyson_step_noalloc", "cntr_peierls", "cntr_peierls_grad"]
+           "cntr_dyson_step_noalloc", "cntr_peierls", "cntr_peierls_grad",
+           "cntr_graph_begin", "cntr_graph_end", "cntr_graph_launch", "cntr_graph_destroy"]
 
 
 class CntrError(RuntimeError):
@@ -75,6 +76,10 @@ def lib():
                                           dbl, i32, dbl, i32, P(dbl), vp]
         L.cntr_sync.argtypes = [vp]
         L.cntr_set_checks.argtypes = [i32]
+        L.cntr_graph_begin.argtypes = [vp]
+        L.cntr_graph_end.argtypes = [vp, P(vp)]
+        L.cntr_graph_launch.argtypes = [vp, vp]
+        L.cntr_graph_destroy.argtypes = [vp]
         L.cntr_peierls.argtypes = [i32, P(Grid), P(vp), P(vp), P(vp), P(vp), vp]
         L.cntr_peierls_grad.argtypes = [i32, P(Grid), P(vp), P(vp), P(vp), P(vp), P(vp), vp]
         L.cntr_mark_slices.argtypes = [i32, P(GF), i32]

@@ -234,6 +234,36 @@ def copy_slice(tstp: int, dst: list, src: list, stream=None):
                                           _stream(stream)))
 
 
+class Graph:
+    """A captured launch sequence (cntr_graph_begin / cntr_graph_end): the
+    library calls made on `stream` inside the `with` block are recorded, then
+    replayed by launch(). stream must be a non-default torch stream."""
+
+    def __init__(self, stream):
+        self.stream = stream
+        self.h = C.c_void_p()
+
+    def __enter__(self):
+        _abi.check(_abi.lib().cntr_graph_begin(C.c_void_p(self.stream.cuda_stream)))
+        return self
+
+    def __exit__(self, exc_type, exc, tb):
+        rc = _abi.lib().cntr_graph_end(C.c_void_p(self.stream.cuda_stream), C.byref(self.h))
+        if exc_type is None:
+            _abi.check(rc)
+        return False
+
+    def launch(self, stream=None):
+        _abi.check(_abi.lib().cntr_graph_launch(self.h, _stream(stream)))
+
+    def __del__(self):
+        try:
+            if self.h:
+                _abi.lib().cntr_graph_destroy(self.h)
+        except Exception:
+            pass
+
+
 def set_checks(order=False, finite=False):
     """Optional precondition / value checks (cntr_set_checks)."""
     _abi.check(_abi.lib().cntr_set_checks((_abi.CHECK_ORDER if order else 0) | (_abi.CHECK_FINITE if finite else 0)))

@@ -47,6 +47,36 @@ struct StreamScratch {
 constexpr size_t READBACK_MAX = 4096;
 std::map<std::pair<int, hipStream_t>, StreamScratch> g_scratch;
 
+// True while `s` is being captured into a graph: then nothing may allocate,
+// synchronize or read host memory at replay time.
+bool capturing(hipStream_t s) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  return hipStreamIsCapturing(s, &cs) == hipSuccess && cs == hipStreamCaptureStatusActive;
+}
+
+// descriptors of a batch travel in kernel arguments (no host buffer that a
+// graph replay would have to read), NA_CHUNK per launch
+constexpr int NA_CHUNK = 16;
+struct ProbChunk {
+  Prob p[NA_CHUNK];
+  int count;
+};
+__global__ void k_put_probs(ProbChunk c, Prob* dst) {
+  int i = threadIdx.x;
+  if (i < c.count) dst[i] = c.p[i];
+}
+
+// Descriptors of count problems to dst, through kernel arguments.
+hipError_t put_probs(const Prob* v, int count, Prob* dst, hipStream_t s) {
+  for (int i0 = 0; i0 < count; i0 += NA_CHUNK) {
+    ProbChunk c;
+    c.count = count - i0 < NA_CHUNK ? count - i0 : NA_CHUNK;
+    for (int i = 0; i < c.count; i++) c.p[i] = v[i0 + i];
+    k_put_probs<<<1, 64, 0, s>>>(c, dst + i0);
+  }
+  return hipGetLastError();
+}
+
 cntr_status fail(cntr_status st, const std::string& msg) {
   g_err = msg;
   return st;
@@ -95,6 +125,9 @@ cntr_status readback(hipStream_t s, void* dst, const void* src, size_t bytes, co
 }
 
 cntr_status grow(hipStream_t s, StreamScratch* sc, size_t bytes, size_t nprob, size_t nred) {
+  if ((bytes > sc->bytes || nprob > sc->nprob || nred > sc->nred) && capturing(s))
+    return fail(CNTR_EINVAL, "the call would allocate scratch during graph capture: make the same call once "
+                             "before capturing");
   if (bytes > sc->bytes) {
     if (sc->buf) {
       (void)hipStreamSynchronize(s);
@@ -214,7 +247,8 @@ cntr_status make_arg(hipStream_t s, StreamScratch* sc, const std::vector<Prob>& 
   out->many = nullptr;
   if (v.size() > 1) {
     Prob* dst = sc->probs + slot * (sc->nprob / 5);
-    hipError_t e = hipMemcpyAsync(dst, v.data(), v.size() * sizeof(Prob), hipMemcpyHostToDevice, s);
+    hipError_t e = capturing(s) ? put_probs(v.data(), (int)v.size(), dst, s)
+                                : hipMemcpyAsync(dst, v.data(), v.size() * sizeof(Prob), hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return hip_fail(e, "descriptor upload");
     out->many = dst;
   }
@@ -440,17 +474,6 @@ __device__ __align__(256) char scratch[NA_DESC_BYTES + NA_STAT_BYTES + NA_STEP_B
 char* g_na_ptr[64] = {nullptr};
 int g_na_nstat[64] = {0};  // status words written since the last cntr_sync
 
-// descriptors of a batch travel in kernel arguments (no host buffer that a
-// graph replay would have to read), NA_CHUNK per launch
-constexpr int NA_CHUNK = 16;
-struct ProbChunk {
-  Prob p[NA_CHUNK];
-  int count;
-};
-__global__ void k_put_probs(ProbChunk c, Prob* dst) {
-  int i = threadIdx.x;
-  if (i < c.count) dst[i] = c.p[i];
-}
 __global__ void k_zero_words(int* p, size_t n) {
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = 0;
 }
@@ -549,6 +572,57 @@ cntr_status cntr_profile_end(cntr_profile* out) {
 
 const char* cntr_last_error(void) { return g_err.c_str(); }
 
+struct cntr_graph_s {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+cntr_status cntr_graph_begin(void* stream) {
+  hipStream_t s = (hipStream_t)stream;
+  if (s == nullptr) return fail(CNTR_EINVAL, "cntr_graph_begin: the default stream cannot be captured");
+  if (capturing(s)) return fail(CNTR_EINVAL, "cntr_graph_begin: stream already capturing");
+  cntr_status st = ensure_weights();
+  if (st) return st;
+  hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return hip_fail(e, "cntr_graph_begin");
+  return CNTR_OK;
+}
+
+cntr_status cntr_graph_end(void* stream, cntr_graph* out) {
+  hipStream_t s = (hipStream_t)stream;
+  if (!out) return fail(CNTR_ESHAPE, "cntr_graph_end: null output");
+  *out = nullptr;
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(s, &g);
+  if (e != hipSuccess || !g) return hip_fail(e, "cntr_graph_end: capture");
+  hipGraphExec_t x = nullptr;
+  e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    return hip_fail(e, "cntr_graph_end: instantiate");
+  }
+  cntr_graph h = new cntr_graph_s;
+  h->graph = g;
+  h->exec = x;
+  *out = h;
+  return CNTR_OK;
+}
+
+cntr_status cntr_graph_launch(cntr_graph g, void* stream) {
+  if (!g || !g->exec) return fail(CNTR_ESHAPE, "cntr_graph_launch: null graph");
+  hipError_t e = hipGraphLaunch(g->exec, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "cntr_graph_launch");
+  return CNTR_OK;
+}
+
+cntr_status cntr_graph_destroy(cntr_graph g) {
+  if (!g) return CNTR_OK;
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  delete g;
+  return CNTR_OK;
+}
+
 cntr_status cntr_set_checks(int32_t flags) {
   if (flags & ~(CNTR_CHECK_ORDER | CNTR_CHECK_FINITE)) return fail(CNTR_EINVAL, "cntr_set_checks: unknown flag");
   std::lock_guard<std::mutex> lk(g_mu);
@@ -587,6 +661,7 @@ cntr_status cntr_finalize(void) {
 }
 
 cntr_status cntr_sync(void* stream) {
+  if (capturing((hipStream_t)stream)) return fail(CNTR_EINVAL, "cntr_sync: synchronizes the stream, not allowed during graph capture");
   hipStream_t s = (hipStream_t)stream;
   hipError_t e = hipStreamSynchronize(s);
   if (e != hipSuccess) return hip_fail(e, "stream synchronize");
@@ -649,7 +724,8 @@ cntr_status cntr_dyson_step(int32_t tstp, int32_t count, const cntr_grid* grids,
   bool shared = true;  // one Sigma (statistics, grid) for every problem
   for (int i = 1; i < count; i++)
     shared = shared && v[i].Stv == v[0].Stv && v[i].sig == v[0].sig && grids[i].nt == grids[0].nt;
-  hipError_t e = tstp <= k ? launch_start(pa, scr, d, ntau, s) : launch_step(pa, scr, tstp, d, s, shared);
+  hipError_t e = tstp <= k ? launch_start(pa, scr, d, ntau, s)
+                           : launch_step(pa, scr, tstp, d, s, shared, !capturing(s));
   if (e == hipSuccess && (g_checks & CNTR_CHECK_FINITE))
     e = launch_check_finite(pa, scr, tstp <= k ? 0 : tstp, tstp <= k ? k : tstp, d, ntau, s);
   if (e != hipSuccess) return hip_fail(e, "cntr_dyson_step launch");
@@ -694,12 +770,8 @@ cntr_status cntr_dyson_step_noalloc(int32_t tstp, int32_t count, const cntr_grid
   pa.many = nullptr;
   if (count > 1) {
     Prob* dst = (Prob*)ptr;
-    for (int i0 = 0; i0 < count; i0 += NA_CHUNK) {
-      ProbChunk c;
-      c.count = std::min(NA_CHUNK, count - i0);
-      for (int i = 0; i < c.count; i++) c.p[i] = v[i0 + i];
-      k_put_probs<<<1, 64, 0, s>>>(c, dst + i0);
-    }
+    hipError_t e = put_probs(v.data(), count, dst, s);
+    if (e != hipSuccess) return hip_fail(e, "cntr_dyson_step_noalloc descriptors");
     pa.many = dst;
   }
   Scratch scr = lay.sc;
@@ -726,6 +798,7 @@ cntr_status cntr_dyson_step_noalloc(int32_t tstp, int32_t count, const cntr_grid
 cntr_status cntr_init_matsubara(int32_t count, const cntr_grid* grids, const cntr_gf* G,
                                 const cntr_gf* Sigma, const void* const* eps, double tol,
                                 int32_t max_iter, void* stream) {
+  if (capturing((hipStream_t)stream)) return fail(CNTR_EINVAL, "cntr_init_matsubara: synchronizes the stream, not allowed during graph capture");
   cntr_status st = check_batch(count, grids, "cntr_init_matsubara");
   if (st) return st;
   if (!gf_ok(G, count) || !gf_ok(Sigma, count) || !eps) return fail(CNTR_ESHAPE, "cntr_init_matsubara: null pointer");
@@ -868,6 +941,7 @@ cntr_status cntr_adjoint_sweep(int32_t count, const cntr_grid* grids, const cntr
                                const void* const* eps, const double* const* U, double nbar,
                                const cntr_gf* Gbar, const cntr_gf* Sigmabar, void* const* eps_bar,
                                double* const* U_bar, int32_t niter, double tol, double* conv, void* stream) {
+  if (capturing((hipStream_t)stream)) return fail(CNTR_EINVAL, "cntr_adjoint_sweep: synchronizes the stream, not allowed during graph capture");
   cntr_status st = check_batch(count, grids, "cntr_adjoint_sweep");
   if (st) return st;
   if (count > 65535) return fail(CNTR_ESHAPE, "cntr_adjoint_sweep: at most 65535 problems per call");
@@ -1133,6 +1207,7 @@ cntr_status cntr_copy_slice(int32_t tstp, int32_t count, const cntr_grid* grids,
 
 cntr_status cntr_distance(int32_t tstp, int32_t count, const cntr_grid* grids, const cntr_gf* A,
                           const cntr_gf* B, double* out, void* stream) {
+  if (capturing((hipStream_t)stream)) return fail(CNTR_EINVAL, "cntr_distance: synchronizes the stream, not allowed during graph capture");
   cntr_status st = check_batch(count, grids, "cntr_distance");
   if (st) return st;
   if (!gf_ok(A, count) || !gf_ok(B, count) || !out) return fail(CNTR_ESHAPE, "cntr_distance: null pointer");
@@ -1159,6 +1234,7 @@ cntr_status cntr_solve_2b(const cntr_grid* grid, const cntr_gf* G, const cntr_gf
                           void* eps_mf, double nbar, int32_t mats_maxit, double mats_tol,
                           double mats_mix, int32_t boot_maxit, double boot_tol, int32_t ncorr,
                           int32_t nt_stop, double* stats, void* stream) {
+  if (capturing((hipStream_t)stream)) return fail(CNTR_EINVAL, "cntr_solve_2b: synchronizes the stream, not allowed during graph capture");
   if (!grid) return fail(CNTR_ESHAPE, "cntr_solve_2b: null grid");
   cntr_status st = check_grid(*grid, "cntr_solve_2b");
   if (st) return st;
@@ -1239,6 +1315,7 @@ cntr_status cntr_solve_2b_batch(int32_t count, const cntr_grid* grids, const cnt
                                 void* const* eps_mf, double nbar, int32_t mats_maxit, double mats_tol,
                                 double mats_mix, int32_t boot_maxit, double boot_tol, int32_t ncorr,
                                 double* stats, void* stream) {
+  if (capturing((hipStream_t)stream)) return fail(CNTR_EINVAL, "cntr_solve_2b_batch: synchronizes the stream, not allowed during graph capture");
   cntr_status st = check_batch(count, grids, "cntr_solve_2b_batch");
   if (st) return st;
   if (!gf_ok(G, count) || !gf_ok(Sigma, count) || !gf_ok(Gscratch, count) || !eps0 || !U || !eps_mf)
