@@ -407,6 +407,90 @@ __device__ inline bool lane_gauss_jordan(int N, cplx (&a)[NM], cplx (&b)[NR], in
   return ok;
 }
 
+// Solve A X = B in LDS with the whole workgroup: Gauss-Jordan elimination
+// with partial pivoting, rows left in place (the pivot row of column c is
+// remembered instead of swapped, and no row is scaled until the end). Wave 0
+// finds the pivot among the rows not yet used (and its reciprocal); then
+// every other row loses its column-c part, lanes over the columns c+1..n-1
+// and the right-hand sides, waves over the rows: two barriers per column, no
+// integer division. A: n x n with leading dimension ld (padded so that the
+// column reads of the pivot search spread over the LDS banks), B: n x nrhs;
+// on return X is in B (row order of X). n <= 64, n - 1 + nrhs <= 64.
+// s_piv: LDS int[n]; s_ipv: LDS cplx; n nrhs <= 2 x the workgroup size.
+// Every thread of the workgroup calls it. Returns false (uniformly) if a
+// pivot is zero.
+template <int NWAVE>
+__device__ inline bool wg_solve(int n, int ld, int nrhs, cplx* A, cplx* B, int* s_piv, cplx* s_ipv) {
+  constexpr int RPW = 64 / NWAVE;  // rows per wave (n <= 64)
+  int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  bool used = false;  // wave 0: row `lane` already a pivot row
+  bool ok = true;
+  for (int c = 0; c < n; c++) {
+    if (wave == 0) {
+      // largest |A[r][c]| over the unused rows: a float key with the lane in
+      // its low bits, maximised by DPP steps
+      double v = (lane < n && !used) ? abs2(A[lane * ld + c]) : 0.0;
+      unsigned key = (lane < n && !used) ? ((__float_as_uint((float)v) & ~63u) | (unsigned)(63 - lane)) : 0u;
+      int p = 63 - (int)(wave_umax(key) & 63u);
+      if (lane == p) used = true;
+      if (lane == 0) {
+        s_piv[c] = p;
+        cplx pv = A[p * ld + c];
+        *s_ipv = abs2(pv) > 0 ? cdiv(mk(1, 0), pv) : mk(0, 0);
+      }
+    }
+    __syncthreads();
+    int p = s_piv[c];
+    cplx ipv = *s_ipv;
+    if (ipv.x == 0 && ipv.y == 0) ok = false;
+    int na = n - c - 1;  // columns c+1..n-1 of A, then the right-hand sides
+    if (lane < na + nrhs) {
+      bool isa = lane < na;
+      cplx pv = isa ? A[p * ld + c + 1 + lane] : B[p * nrhs + (lane - na)];
+      // the rows of this wave: all loads first, then the updates
+      cplx fr[RPW], xr[RPW];
+#pragma unroll
+      for (int i = 0; i < RPW; i++) {
+        int r = wave + NWAVE * i;
+        bool act = r < n && r != p;
+        int rr = act ? r : p;
+        fr[i] = A[rr * ld + c];
+        xr[i] = isa ? A[rr * ld + c + 1 + lane] : B[rr * nrhs + (lane - na)];
+      }
+#pragma unroll
+      for (int i = 0; i < RPW; i++) {
+        int r = wave + NWAVE * i;
+        if (r < n && r != p) {
+          cplx v = xr[i] - (fr[i] * ipv) * pv;
+          if (isa) A[r * ld + c + 1 + lane] = v;
+          else B[r * nrhs + (lane - na)] = v;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // X_c = B[p_c] / A[p_c][c]: all reads, then (after a barrier) all writes;
+  // n nrhs <= 2 x the workgroup size
+  cplx xv[2];
+#pragma unroll
+  for (int u = 0; u < 2; u++) {
+    int idx = tid + u * blockDim.x;
+    if (idx < n * nrhs) {
+      int c = idx / nrhs, q = idx - c * nrhs;
+      int p = s_piv[c];
+      xv[u] = B[p * nrhs + q] * cdiv(mk(1, 0), A[p * ld + c]);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < 2; u++) {
+    int idx = tid + u * blockDim.x;
+    if (idx < n * nrhs) B[idx] = xv[u];
+  }
+  __syncthreads();
+  return ok;
+}
+
 // Gregory weights w(N, j), N > k, from a copy of the end weights in LDS
 // (per-lane indices never reach constant or private memory in the loops).
 struct WReg {

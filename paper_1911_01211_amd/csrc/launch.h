@@ -20,7 +20,8 @@ struct HistPlan {
   int mout[NJOB];
   int nch[NJOB];
   int mtiles[NJOB];
-  int wg_off[NJOB + 1];
+  int jorder[NJOB];      // job of each dispatch position
+  int wg_off[NJOB + 1];  // first workgroup of each dispatch position
   // staged path: workgroups ordered by bands of stored slices, so that the
   // two consumers of a history block (jobs 0/4, 1/5, 3/7) run close together
   int banded;         // workgroups in band order (else job by job)

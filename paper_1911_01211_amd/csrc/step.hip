@@ -16,6 +16,9 @@
 //
 // Layout: canonical slice-major storage; a tile of consecutive outputs m
 // reads consecutive blocks of one stored row, so history reads coalesce.
+#include <map>
+#include <mutex>
+
 #include "launch.h"
 
 namespace cntr {
@@ -31,6 +34,9 @@ constexpr int hist_tj(int d) { return d == 1 ? 256 : (d >= 8 ? 32 : 64); }
 constexpr int hist_tjs(int d) { return d == 1 ? 512 : (d <= 4 ? 16 : (d >= 8 ? 16 : 32)); }
 // staged path: term chunk of the history jobs and of the tau source
 constexpr int STG_TJ = 32, STG_TJS = 16;
+// d = 8 (FP64 MFMA path): terms per workgroup of the history jobs (staged
+// shared operand: 32 KB) and of the tau source (two staged operands of 16 KB)
+constexpr int MF8_TJ = 64, MF8_TAU_TJ = 16;
 
 static int cdiv_i(int a, int b) { return (a + b - 1) / b; }
 
@@ -75,8 +81,10 @@ HistPlan make_plan(int n, int k, int ntau, int d, int tau_split) {
       p.tm[j] = row ? 16 : 64;
       p.tj[j] = j == 2 ? STG_TJS : STG_TJ;
     } else {
-      p.tm[j] = p.TM;
-      p.tj[j] = j == 2 ? p.TJS : p.TJ;
+      // d = 8: tiles of 8 outputs (two per wave) on the MFMA path, except
+      // the tau source
+      p.tm[j] = d == 8 ? 8 : p.TM;
+      p.tj[j] = d == 8 ? (j == 2 ? MF8_TAU_TJ : MF8_TJ) : (j == 2 ? p.TJS : p.TJ);
     }
   }
   // d = 1: the mixing panel is read once for both of its consumers (job 1
@@ -84,7 +92,7 @@ HistPlan make_plan(int n, int k, int ntau, int d, int tau_split) {
   p.fuse_t = d == 1;
   if (p.fuse_t) p.tj[5] = p.tj[4] = p.tj[7] = p.TM;
   long off = 0;
-  p.wg_off[0] = 0;
+  int wgs[NJOB];
   for (int j = 0; j < NJOB; j++) {
     p.mout[j] = mout[j];
     p.nch[j] = mout[j] > 0 ? cdiv_i(span[j], p.tj[j]) : 0;
@@ -92,10 +100,20 @@ HistPlan make_plan(int n, int k, int ntau, int d, int tau_split) {
     if (j == 6) p.nch[j] = p.mtiles[j] = 1;  // one workgroup: both tau ends
     if (j == 2 && tau_split > 0) p.nch[j] = tau_split;
     bool none = (j == 2 && tau_split > 0) || ((j == 4 || j == 5 || j == 7) && p.fuse_t);  // formed elsewhere
-    p.wg_off[j + 1] = p.wg_off[j] + (none ? 0 : p.nch[j] * p.mtiles[j]);
+    wgs[j] = none ? 0 : p.nch[j] * p.mtiles[j];
     p.part_off[j] = off;
     off += (long)p.nch[j] * mout[j];
   }
+  // dispatch order of the jobs' workgroups: job by job; for d = 8 the tau
+  // boundary and the tau source first (short, independent of n), so that
+  // they do not trail the history sums
+  for (int i = 0; i < NJOB; i++) p.jorder[i] = i;
+  if (d == 8) {
+    const int ord8[NJOB] = {6, 2, 0, 1, 3, 4, 5, 7};
+    for (int i = 0; i < NJOB; i++) p.jorder[i] = ord8[i];
+  }
+  p.wg_off[0] = 0;
+  for (int i = 0; i < NJOB; i++) p.wg_off[i + 1] = p.wg_off[i] + wgs[p.jorder[i]];
   p.grid = p.wg_off[NJOB];
   // Band order pays once the history panels of a problem no longer fit in the
   // 256 MB last-level (Infinity) cache, so that a block's second consumer
@@ -161,8 +179,8 @@ __device__ void prep_step(const Prob& P, const Scratch& sc, int pi, int n, cplx*
   double h = P.h;
   int N = k * D;
   int n0 = n - k;                  // first row of the (k+1) x (k+1) window
-  cplx* A = lds;                   // (kD)^2, wave 0
-  cplx* B = A + N * N;             // kD x D, wave 0
+  cplx* A = lds;                   // kD x (kD + 1) (padded rows)
+  cplx* B = A + N * (N + 1);       // kD x D
   cplx* mw = B + N * D;            // 4 x DD matrices being inverted, one per wave
   cplx* sw = mw + 4 * DD;          // Sigma^R_{n0+i, n0+j}, j <= i, (k+1)^2 blocks
   cplx* ew = sw + K1M * K1M * DD;  // eps_{n0+i} - mu, k+1 blocks
@@ -293,40 +311,16 @@ __device__ void prep_step(const Prob& P, const Scratch& sc, int pi, int n, cplx*
     }
     return;
   }
+  // d > 4: the 8 x 8 inverses on single waves (M_R on wave 0, the lesser
+  // boundary rows on waves 1..3), then the (kD) x (kD) retarded boundary
+  // system on the whole workgroup
   if (wave == 0) {
-    // M_R = step matrix of row n and its inverse
     cplx* mr = mw;
     for (int e = lane; e < DD; e += 64) mr[e] = stepmat(k, e);
     wave_sync();
     bool ok = wave_inverse(D, mr, piv[0]);
     if (!ok && lane == 0) atomicExch(sc.status(pi), CNTR_ESINGULAR);
     for (int e = lane; e < DD; e += 64) sc.minv(pi)[e] = mr[e];
-    // retarded boundary: sum_l C_{l,p}^T Y_l^T = i C_{0,p}^T  (Y_0 = -i) with
-    // C_{l,p} = h^-1 D_{p,l} + delta_{pl} i e_{n-p} + i h s_{p,l} Sigma~^R_{n-l,n-p}
-    auto Cval = [&](int l, int p, int x, int y) -> cplx {
-      cplx v = (h * tS[p * K1M + l]) * mul_i(sig(k - l, k - p, x, y));
-      if (p == l) v = v + mul_i(ew[(k - p) * DD + x * D + y]);
-      if (x == y) v.x += tD[p * K1M + l] / h;
-      return v;
-    };
-    for (int idx = lane; idx < N * N; idx += 64) {
-      int r = idx / N, q = idx % N;
-      A[idx] = Cval(q / D + 1, r / D + 1, q % D, r % D);
-    }
-    for (int idx = lane; idx < N * D; idx += 64) {
-      int r = idx / D, cc = idx % D;
-      B[idx] = mul_i(Cval(0, r / D + 1, cc, r % D));
-    }
-    wave_sync();
-    ok = wave_solve(N, D, A, B);
-    if (!ok && lane == 0) atomicExch(sc.status(pi), CNTR_ESINGULAR);
-    for (int idx = lane; idx < (k + 1) * DD; idx += 64) {
-      int l = idx / DD, e = idx % DD, cc = e / D, bb = e % D;
-      cplx v;
-      if (l == 0) v = (cc == bb) ? mk(0, -1) : mk(0, 0);
-      else v = B[((l - 1) * D + bb) * D + cc];
-      P.Gret[(tri(n) + n - l) * DD + e] = v;
-    }
   } else if (n >= 2 * k + 1) {
     // inverses of the step matrices of the lesser boundary rows m = n-k..n;
     // waves 1..3 share the rows
@@ -339,6 +333,36 @@ __device__ void prep_step(const Prob& P, const Scratch& sc, int pi, int n, cplx*
       for (int e = lane; e < DD; e += 64) sc.minv(pi)[(1 + r) * DD + e] = mb[e];
       wave_sync();
     }
+  }
+  // retarded boundary: sum_l C_{l,p}^T Y_l^T = i C_{0,p}^T  (Y_0 = -i) with
+  // C_{l,p} = h^-1 D_{p,l} + delta_{pl} i e_{n-p} + i h s_{p,l} Sigma~^R_{n-l,n-p}
+  auto Cval = [&](int l, int p, int x, int y) -> cplx {
+    cplx v = (h * tS[p * K1M + l]) * mul_i(sig(k - l, k - p, x, y));
+    if (p == l) v = v + mul_i(ew[(k - p) * DD + x * D + y]);
+    if (x == y) v.x += tD[p * K1M + l] / h;
+    return v;
+  };
+  int ld = N + 1;
+  for (int idx = tid; idx < N * N; idx += NTHR) {
+    int r = idx / N, q = idx % N;
+    A[r * ld + q] = Cval(q / D + 1, r / D + 1, q % D, r % D);
+  }
+  cplx* Bw = A + N * ld;
+  for (int idx = tid; idx < N * D; idx += NTHR) {
+    int r = idx / D, cc = idx % D;
+    Bw[idx] = mul_i(Cval(0, r / D + 1, cc, r % D));
+  }
+  __shared__ int s_piv[KMAX * D];
+  __shared__ cplx s_ipv;
+  __syncthreads();
+  bool ok = wg_solve<NTHR / 64>(N, ld, D, A, Bw, s_piv, &s_ipv);
+  if (!ok && tid == 0) atomicExch(sc.status(pi), CNTR_ESINGULAR);
+  for (int idx = tid; idx < (k + 1) * DD; idx += NTHR) {
+    int l = idx / DD, e = idx % DD, cc = e / D, bb = e % D;
+    cplx v;
+    if (l == 0) v = (cc == bb) ? mk(0, -1) : mk(0, 0);
+    else v = Bw[((l - 1) * D + bb) * D + cc];
+    P.Gret[(tri(n) + n - l) * DD + e] = v;
   }
 }
 
@@ -429,6 +453,45 @@ __device__ void tau_boundary(const Prob& P, const Scratch& sc, int pi, int n, co
     gHi[idx] = gld(P.Gmat + (size_t)(ntau - k + i) * DD + ee);
   }
   __syncthreads();
+  if constexpr (D == 8) {
+    // the block products S^rceil_{n,l} G^M_{ntau-j} (low end) and
+    // S^rceil_{n,ntau-l} G^M_j (high end) are shared by the k+1 outputs of
+    // their end: each is formed once and added with the weights R of every
+    // output. Thread t: end t / 128, half (t / 64) % 2 of the (j, l) pairs,
+    // element t % 64; the halves are added through LDS.
+    int end = tid >> 7, half = (tid >> 6) & 1, e = tid & 63, a = e / D, c = e % D;
+    cplx acc[KMAX + 1];
+#pragma unroll
+    for (int mi = 0; mi <= KMAX; mi++) acc[mi] = mk(0, 0);
+    for (int pr = half; pr < K1 * K1; pr += 2) {
+      int j = pr / K1, l = pr % K1;
+      const cplx* sa = end == 0 ? sLo + l * DD : sHi + (k - l) * DD;
+      const cplx* gb = end == 0 ? gHi + (k - j) * DD : gLo + j * DD;
+      cplx pv = mk(0, 0);
+#pragma unroll
+      for (int q = 0; q < D; q++) cfma(pv, sa[a * D + q], gb[q * D + c]);
+#pragma unroll
+      for (int mi = 0; mi <= KMAX; mi++)
+        if (mi <= k) {
+          double w = end == 0 ? xi * W.R[mi][j][l] : W.R[k - mi][j][l];
+          acc[mi] = acc[mi] + w * pv;
+        }
+    }
+    cplx* xr = gHi + K1 * DD;  // 2 ends x (k+1) outputs x DD
+    if (half == 1)
+#pragma unroll
+      for (int mi = 0; mi <= KMAX; mi++)
+        if (mi <= k) xr[(end * K1 + mi) * DD + e] = acc[mi];
+    __syncthreads();
+    if (half == 0)
+#pragma unroll
+      for (int mi = 0; mi <= KMAX; mi++)
+        if (mi <= k) {
+          int m = end == 0 ? mi : ntau - k + mi;
+          sc.part(pi)[(pl.part_off[6] + m) * DD + e] = acc[mi] + xr[(end * K1 + mi) * DD + e];
+        }
+    return;
+  }
   for (int idx = tid; idx < 2 * K1 * DD; idx += NTHR) {
     int o = idx / DD, e = idx % DD, a = e / D, c = e % D;
     cplx acc = mk(0, 0);
@@ -1152,13 +1215,336 @@ __device__ void tau_stg(const Prob& P, const Scratch& sc, int pi, int n, const H
   stg_sum_store<D>(acc, lds, false, m0, ntau + 1, sc.part(pi) + (pl.part_off[2] + (long)ch * (ntau + 1)) * DD);
 }
 
+// ------------------------------------------- HISTORY, d = 8 on FP64 MFMA
+// The d = 8 history sums are dense 8 x 8 complex block products; each is a
+// real 16 x 16 x 16 product on v_mfma_f64_16x16x4f64 (four instructions)
+// with the complex product embedded as
+//   A = [Pr -Pi; Pi Pr] (shared operand P),  B = [Qr_0 Qr_1; Qi_0 Qi_1]
+// (streamed operands of two outputs side by side), so that D rows 0..7 hold
+// Re P Q_o and rows 8..15 Im P Q_o, columns 0..7 output 0 and 8..15 output 1.
+// Lane l supplies A(l % 16, 4t + l / 16) and B(4t + l / 16, l % 16) of
+// instruction t and holds D(l / 16 + 4r, l % 16), r = 0..3.
+// Every sum has the form out_m = sum_j w(m, j) P_j Q_{j,m} (P_j shared by all
+// outputs: jobs 0, 1), or out_m = sum_j w X_{m,j} Y_j (Y_j shared: jobs 3,
+// 4, 5), computed as its transpose out^T = sum_j Y_j^T X_{m,j}^T.
+typedef double mf_v4d __attribute__((ext_vector_type(4)));
+
+__device__ inline void mfma8_term(mf_v4d& acc, cplx p0, cplx p1, bool bottom, cplx q0, cplx q1) {
+  double a0 = bottom ? p0.y : p0.x, a1 = bottom ? p1.y : p1.x;
+  double a2 = bottom ? p0.x : -p0.y, a3 = bottom ? p1.x : -p1.y;
+  acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, q0.x, acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, q1.x, acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a2, q0.y, acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a3, q1.y, acc, 0, 0, 0);
+}
+
+// Streamed block of output m and term j for the jobs above: pointer to the
+// stored 8 x 8 block, read transposed (tr) and/or as -conj (nc); w = 0 when
+// the term does not belong to the output (the pointer then stays in bounds).
+struct Mf8Src {
+  const cplx* blk;
+  bool tr, nc;
+  double w;
+};
+// Gregory weight w_{N,j} from the LDS copies of the start weights s (KP x KP)
+// and the end weights omega: no memory loads of the global kind in the term
+// loop, whose wait would also drain the prefetched blocks
+struct Mf8W {
+  const double* s;
+  const double* om;
+  int k;
+  __device__ inline double greg(int N, int j) const {
+    if (N <= k) return s[N * KP + j];
+    bool left = j <= k, right = N - j <= k;
+    if (left && right) return om[j] + om[N - j] - 1.0;
+    if (left) return om[j];
+    if (right) return om[N - j];
+    return 1.0;
+  }
+};
+template <int JOB>
+__device__ inline Mf8Src mf8_src(const Prob& P, const Mf8W& W, int n, int m, bool mvalid, int j) {
+  int k = P.k, ntau = P.ntau;
+  Mf8Src s;
+  s.tr = false;
+  s.nc = false;
+  if constexpr (JOB == 0) {  // R_{j,m}, j >= m, weight w(n-m, j-m)
+    bool in = j >= m;
+    s.blk = P.Gret + (in ? tri(j) + m : tri(m) + m) * 64;
+    s.w = in ? W.greg(n - m, j - m) : 0.0;
+  } else if constexpr (JOB == 1) {  // T_{j,m}, weight w(n, j)
+    s.blk = P.Gtv + ((size_t)j * (ntau + 1) + m) * 64;
+    s.w = W.greg(n, j);
+  } else if constexpr (JOB == 3) {  // X = L^_{m,l}: L_{m,l} (l >= m) or -(L_{l,m})^dag; Q = X^T
+    bool up = j >= m;
+    s.blk = P.Gles + (up ? tri(j) + m : tri(m) + j) * 64;
+    s.tr = up;
+    s.nc = !up;
+    s.w = W.greg(n, j);
+  } else if constexpr (JOB == 4) {  // X = R~_{m,j}: R_{m,j} (j <= m) or -(R_{j,m})^dag; Q = X^T
+    bool lo = j <= m;
+    s.blk = P.Gret + (lo ? tri(m) + j : tri(j) + m) * 64;
+    s.tr = lo;
+    s.nc = !lo;
+    s.w = j <= (m > k ? m : k) ? W.greg(m, j) : 0.0;
+  } else {  // X = T_{m,j}; Q = X^T, weight -xi w(ntau, j)
+    s.blk = P.Gtv + ((size_t)m * (ntau + 1) + j) * 64;
+    s.tr = true;
+    s.w = -(double)P.sig * W.greg(ntau, j);
+  }
+  if (!mvalid) s.w = 0.0;
+  return s;
+}
+
+// Raw Q[kb][c], Q[kb + 4][c] of one streamed block; the weight and the sign
+// of -conj are applied when the values are used, so that nothing waits for
+// the load before then.
+__device__ inline void mf8_load(const Mf8Src& s, int kb, int c, cplx& q0, cplx& q1) {
+  int i0 = s.tr ? c * 8 + kb : kb * 8 + c;
+  int i1 = s.tr ? c * 8 + kb + 4 : (kb + 4) * 8 + c;
+  q0 = gld(s.blk + i0);
+  q1 = gld(s.blk + i1);
+}
+// w q or w (-conj q)
+__device__ inline cplx mf8_scale(cplx q, double w, bool nc) { return mk(nc ? -w * q.x : w * q.x, w * q.y); }
+
+// One workgroup: 8 outputs (2 per wave) x one chunk of TJ terms of job
+// 0, 1, 3, 4 or 5; the shared operand of the chunk is staged in LDS.
+template <int JOB>
+__device__ __forceinline__ void hist_mfma8_job(const Prob& P, const Scratch& sc, int pi, int n, const HistPlan& pl,
+                                               int mt, int ch, cplx* lds) {
+  constexpr int DD = 64, TJ = MF8_TJ, PD = 8;
+  __shared__ double s_ss[KP * KP], s_om[KP];
+  int k = P.k, ntau = P.ntau;
+  int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  int mout = pl.mout[JOB], tm = pl.tm[JOB];
+  int j0 = ch * TJ;
+  int mlo = mt * tm, mhi = min(mlo + tm, mout) - 1;
+  if (JOB == 0 && j0 + TJ - 1 < mlo) return;
+  if (JOB == 4 && j0 > max(mhi, k)) return;
+  if (tid < KP * KP) s_ss[tid] = c_kw[k].s[tid / KP][tid % KP];
+  if (tid < KP) s_om[tid] = c_kw[k].omega[tid];
+  Mf8W W{s_ss, s_om, k};
+  for (int idx = tid; idx < TJ * DD; idx += NTHR) {
+    int jj = idx / DD, ee = idx % DD, j = j0 + jj;
+    cplx v = mk(0, 0);
+    if constexpr (JOB == 0 || JOB == 1 || JOB == 3) {
+      if (j < n) v = gld(P.Sret + (tri(n) + j) * DD + ee);
+    } else if constexpr (JOB == 4) {
+      if (j <= n) v = gld(P.Sles + (tri(n) + j) * DD + ee);
+    } else {
+      if (j <= ntau) v = gld(P.Stv + ((size_t)n * (ntau + 1) + ntau - j) * DD + ee);
+    }
+    lds[idx] = v;
+  }
+  __syncthreads();
+  int m0 = mlo + 2 * wv;
+  if (m0 > mhi) return;
+  int c16 = lane & 15, o = c16 >> 3, c = c16 & 7, kb = lane >> 4, r8 = lane & 7;
+  bool bottom = (lane & 15) >= 8;
+  int m = m0 + o;
+  bool mvalid = m <= mhi;
+  int mc = mvalid ? m : m0;  // clamped output of the lane
+  // term range of the chunk (uniform over the wave)
+  int jlo = j0, jhi;
+  if constexpr (JOB == 0) {
+    jlo = max(j0, m0);
+    jhi = min(n - 1, j0 + TJ - 1);
+  } else if constexpr (JOB == 1 || JOB == 3) {
+    jhi = min(n - 1, j0 + TJ - 1);
+  } else if constexpr (JOB == 4) {
+    jhi = min(max(min(m0 + 1, mhi), k), j0 + TJ - 1);
+  } else {
+    jhi = min(ntau, j0 + TJ - 1);
+  }
+  // shared operand P_j of the lane: S (jobs 0, 1), conj(S) (3, 5), S^T (4)
+  constexpr bool PT = JOB == 4, PC = JOB == 3 || JOB == 5;
+  int pi0 = PT ? kb * 8 + r8 : r8 * 8 + kb;
+  int pi1 = PT ? (kb + 4) * 8 + r8 : r8 * 8 + kb + 4;
+  mf_v4d acc = {0.0, 0.0, 0.0, 0.0};
+  if (jlo <= jhi) {
+    cplx qa[PD], qb[PD];
+    double wa[PD];
+    bool na[PD];
+#pragma unroll
+    for (int u = 0; u < PD; u++) {
+      Mf8Src sv = mf8_src<JOB>(P, W, n, mc, mvalid && jlo + u <= jhi, min(jlo + u, jhi));
+      mf8_load(sv, kb, c, qa[u], qb[u]);
+      wa[u] = sv.w;
+      na[u] = sv.nc;
+    }
+    for (int jb = jlo; jb <= jhi; jb += PD) {
+#pragma unroll
+      for (int u = 0; u < PD; u++) {
+        int j = jb + u;
+        cplx q0 = mf8_scale(qa[u], wa[u], na[u]), q1 = mf8_scale(qb[u], wa[u], na[u]);
+        int jn = j + PD;
+        Mf8Src sv = mf8_src<JOB>(P, W, n, mc, mvalid && jn <= jhi, min(jn, jhi));
+        mf8_load(sv, kb, c, qa[u], qb[u]);
+        wa[u] = sv.w;
+        na[u] = sv.nc;
+        if (j <= jhi) {
+          const cplx* sb = lds + (j - j0) * DD;
+          cplx p0 = sb[pi0], p1 = sb[pi1];
+          if (PC) {
+            p0 = conj(p0);
+            p1 = conj(p1);
+          }
+          mfma8_term(acc, p0, p1, bottom, q0, q1);
+        }
+      }
+    }
+  }
+  if (!mvalid) return;
+  // lane holds out'[kb][c] = (acc0, acc2) and out'[kb + 4][c] = (acc1, acc3)
+  constexpr bool TRANS = JOB >= 3;
+  cplx* dst = sc.part(pi) + (pl.part_off[JOB] + (long)ch * mout + m) * DD;
+  int e0 = TRANS ? c * 8 + kb : kb * 8 + c;
+  int e1 = TRANS ? c * 8 + kb + 4 : (kb + 4) * 8 + c;
+  gst(dst + e0, mk(acc[0], acc[2]));
+  gst(dst + e1, mk(acc[1], acc[3]));
+}
+
+// Tau source of d = 8 on MFMA (Gregory parts of Eqs. ctv2, ctv3), outputs
+// m = 0..ntau, terms J of the chunk:
+//   part B (m < ntau - k, J >= m): w(ntau-m, J-m) S^rceil_{n,J} G^M_{J-m}
+//                                  (shared S^rceil_{n,J}: out accumulates)
+//   part A (m > k, J <= m): xi w(m, J) S^rceil_{n,m-J} G^M_{ntau-J}
+//                            (shared G^M_{ntau-J}: out^T accumulates)
+// The two are added through LDS at the end. Every (chunk, output) of a
+// valid output is written (zeros where no term applies).
+__device__ __forceinline__ void tau_mfma8(const Prob& P, const Scratch& sc, int pi, int n, const HistPlan& pl,
+                                          int mt, int ch, cplx* lds) {
+  constexpr int DD = 64, PD = 8, TJ = MF8_TAU_TJ;
+  __shared__ double s_ss[KP * KP], s_om[KP];
+  int k = P.k, ntau = P.ntau;
+  double xi = P.sig;
+  int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  int mout = ntau + 1, tm = pl.tm[2];
+  int j0 = ch * TJ;
+  int mlo = mt * tm, mhi = min(mlo + tm, mout) - 1;
+  if (tid < KP * KP) s_ss[tid] = c_kw[k].s[tid / KP][tid % KP];
+  if (tid < KP) s_om[tid] = c_kw[k].omega[tid];
+  Mf8W W{s_ss, s_om, k};
+  cplx* sS = lds;            // S^rceil_{n,J}, J in the chunk
+  cplx* sM = lds + TJ * DD;  // G^M_{ntau-J}
+  for (int idx = tid; idx < TJ * DD; idx += NTHR) {
+    int J = j0 + idx / DD, ee = idx % DD;
+    bool in = J <= ntau;
+    sS[idx] = in ? gld(P.Stv + ((size_t)n * (ntau + 1) + J) * DD + ee) : mk(0, 0);
+    sM[idx] = in ? gld(P.Gmat + (size_t)(ntau - J) * DD + ee) : mk(0, 0);
+  }
+  __syncthreads();
+  int m0 = mlo + 2 * wv;
+  if (m0 > mhi) return;
+  int c16 = lane & 15, o = c16 >> 3, c = c16 & 7, kb = lane >> 4, r8 = lane & 7;
+  bool bottom = (lane & 15) >= 8;
+  int m = m0 + o;
+  bool mvalid = m <= mhi;
+  int mc = mvalid ? m : m0;
+  int m1 = min(m0 + 1, mhi);
+  int Jend = min(ntau, j0 + TJ - 1);
+  mf_v4d accB = {0.0, 0.0, 0.0, 0.0}, accA = {0.0, 0.0, 0.0, 0.0};
+  // part B: J in [max(j0, m0), Jend]; P = S_J (direct), Q = G^M_{J-m} (direct)
+  {
+    int jlo = max(j0, m0), jhi = Jend;
+    auto src = [&](int J, bool ok, const cplx*& blk, double& w) {
+      bool in = ok && mvalid && J >= mc && mc < ntau - k;
+      blk = P.Gmat + (size_t)(in ? J - mc : 0) * DD;
+      w = in ? W.greg(ntau - mc, J - mc) : 0.0;
+    };
+    if (jlo <= jhi) {
+      cplx qa[PD], qb[PD];
+      double wa[PD];
+#pragma unroll
+      for (int u = 0; u < PD; u++) {
+        const cplx* blk;
+        src(min(jlo + u, jhi), jlo + u <= jhi, blk, wa[u]);
+        qa[u] = gld(blk + kb * 8 + c);
+        qb[u] = gld(blk + (kb + 4) * 8 + c);
+      }
+      for (int jb = jlo; jb <= jhi; jb += PD) {
+#pragma unroll
+        for (int u = 0; u < PD; u++) {
+          int J = jb + u;
+          cplx q0 = wa[u] * qa[u], q1 = wa[u] * qb[u];
+          const cplx* blk;
+          src(min(J + PD, jhi), J + PD <= jhi, blk, wa[u]);
+          qa[u] = gld(blk + kb * 8 + c);
+          qb[u] = gld(blk + (kb + 4) * 8 + c);
+          if (J <= jhi) {
+            const cplx* sb = sS + (J - j0) * DD;
+            mfma8_term(accB, sb[r8 * 8 + kb], sb[r8 * 8 + kb + 4], bottom, q0, q1);
+          }
+        }
+      }
+    }
+  }
+  // part A: J in [j0, min(Jend, m1)]; P = (G^M_{ntau-J})^T, Q = (S^rceil_{n,m-J})^T
+  {
+    int jlo = j0, jhi = min(Jend, m1);
+    auto src = [&](int J, bool ok, const cplx*& blk, double& w) {
+      bool in = ok && mvalid && J <= mc && mc > k;
+      blk = P.Stv + ((size_t)n * (ntau + 1) + (in ? mc - J : 0)) * DD;
+      w = in ? xi * W.greg(mc, J) : 0.0;
+    };
+    if (jlo <= jhi) {
+      cplx qa[PD], qb[PD];
+      double wa[PD];
+#pragma unroll
+      for (int u = 0; u < PD; u++) {
+        const cplx* blk;
+        src(min(jlo + u, jhi), jlo + u <= jhi, blk, wa[u]);
+        qa[u] = gld(blk + c * 8 + kb);
+        qb[u] = gld(blk + c * 8 + kb + 4);
+      }
+      for (int jb = jlo; jb <= jhi; jb += PD) {
+#pragma unroll
+        for (int u = 0; u < PD; u++) {
+          int J = jb + u;
+          cplx q0 = wa[u] * qa[u], q1 = wa[u] * qb[u];
+          const cplx* blk;
+          src(min(J + PD, jhi), J + PD <= jhi, blk, wa[u]);
+          qa[u] = gld(blk + c * 8 + kb);
+          qb[u] = gld(blk + c * 8 + kb + 4);
+          if (J <= jhi) {
+            const cplx* sb = sM + (J - j0) * DD;
+            mfma8_term(accA, sb[kb * 8 + r8], sb[(kb + 4) * 8 + r8], bottom, q0, q1);
+          }
+        }
+      }
+    }
+  }
+  // out = accB + (accA)^T: the transposed part through this wave's LDS tile
+  cplx* xt = lds + 2 * TJ * DD + wv * 2 * DD;
+  xt[o * DD + c * 8 + kb] = mk(accA[0], accA[2]);
+  xt[o * DD + c * 8 + kb + 4] = mk(accA[1], accA[3]);
+  wave_sync();
+  cplx t0 = xt[o * DD + kb * 8 + c], t1 = xt[o * DD + (kb + 4) * 8 + c];
+  if (!mvalid) return;
+  cplx* dst = sc.part(pi) + (pl.part_off[2] + (long)ch * mout + m) * DD;
+  gst(dst + kb * 8 + c, mk(accB[0], accB[2]) + t0);
+  gst(dst + (kb + 4) * 8 + c, mk(accB[1], accB[3]) + t1);
+}
+
+__device__ __forceinline__ void hist_mfma8(const Prob& P, const Scratch& sc, int pi, int n, const HistPlan& pl,
+                                           int job, int mt, int ch, cplx* lds) {
+  switch (job) {
+    case 0: hist_mfma8_job<0>(P, sc, pi, n, pl, mt, ch, lds); break;
+    case 1: hist_mfma8_job<1>(P, sc, pi, n, pl, mt, ch, lds); break;
+    case 3: hist_mfma8_job<3>(P, sc, pi, n, pl, mt, ch, lds); break;
+    case 4: hist_mfma8_job<4>(P, sc, pi, n, pl, mt, ch, lds); break;
+    case 5: hist_mfma8_job<5>(P, sc, pi, n, pl, mt, ch, lds); break;
+  }
+}
+
 // ------------------------------------------------------------- HISTORY
 template <int D>
 __global__ __launch_bounds__(NTHR) void k_history(ProbArg pa, Scratch sc, HistPlan pl) {
   constexpr int DD = D * D;
   constexpr int TM = NTHR / DD > 0 ? NTHR / DD : 1;
   constexpr int TJ = D >= 8 ? 32 : 64;
-  constexpr int PREPN = (KMAX * D) * (KMAX * D) + KMAX * D * D + 4 * DD + (KMAX + 1) * (KMAX + 1) * DD +
+  constexpr int PREPN = (KMAX * D) * (KMAX * D + 1) + KMAX * D * D + 4 * DD + (KMAX + 1) * (KMAX + 1) * DD +
                         (KMAX + 1) * DD + (D <= 4 ? (KMAX + 1) * (KMAX + 1) * DD : 0);
   constexpr int TSN = 2 * (D >= 8 ? 16 : 32) * DD + 2 * (TM + (D >= 8 ? 16 : 32) - 1) * DD;
   constexpr int LDSA = (2 * TJ * DD) > PREPN ? (2 * TJ * DD) : PREPN;
@@ -1168,7 +1554,8 @@ __global__ __launch_bounds__(NTHR) void k_history(ProbArg pa, Scratch sc, HistPl
   constexpr int LDSB1 = hist_tj(D) * DD > 2 * hist_tjs(D) * DD ? hist_tj(D) * DD : 2 * hist_tjs(D) * DD;
   constexpr int LDSR1 = D <= 4 && LDSB1 > LDSR0 ? LDSB1 : LDSR0;  // operands of the block-per-lane path
   constexpr int LDSR = STG ? 4 * Stg<D>::WBUF : LDSR1;              // staged path buffers
-  constexpr int LDSN = STG ? (PREPN > LDSR ? PREPN : LDSR) : (LDSB > LDSR ? LDSB : LDSR);
+  constexpr int LDS8 = MF8_TJ * DD > 2 * MF8_TAU_TJ * DD + 8 * DD ? MF8_TJ * DD : 2 * MF8_TAU_TJ * DD + 8 * DD;
+  constexpr int LDSN = D == 8 ? LDS8 : (STG ? (PREPN > LDSR ? PREPN : LDSR) : (LDSB > LDSR ? LDSB : LDSR));
   __shared__ cplx lds[LDSN];
   // shared operand of a staged chunk (a separate array: its reads never wait
   // for the copies in flight into lds)
@@ -1180,7 +1567,8 @@ __global__ __launch_bounds__(NTHR) void k_history(ProbArg pa, Scratch sc, HistPl
   // workgroup 0 sets up the step (dispatched first, it overlaps the sums)
   int b = blockIdx.x - 1;
   if (b < 0) {
-    prep_step<D>(P, sc, pi, n, lds);
+    // (d = 8: the set-up has a kernel of its own, k_prep, launched before)
+    if constexpr (D != 8) prep_step<D>(P, sc, pi, n, lds);
     return;
   }
   int job = 0, mt, ch;
@@ -1219,8 +1607,10 @@ __global__ __launch_bounds__(NTHR) void k_history(ProbArg pa, Scratch sc, HistPl
       if (mt >= pl.mtiles[job] || ch >= pl.nch[job]) return;
     }
   } else {
-    while (b >= pl.wg_off[job + 1]) job++;
-    int local = b - pl.wg_off[job];
+    int i = 0;
+    while (b >= pl.wg_off[i + 1]) i++;
+    job = pl.jorder[i];
+    int local = b - pl.wg_off[i];
     mt = local / pl.nch[job];
     ch = local % pl.nch[job];
   }
@@ -1240,6 +1630,11 @@ __global__ __launch_bounds__(NTHR) void k_history(ProbArg pa, Scratch sc, HistPl
     }
     return;
   }
+  if constexpr (D == 8) {
+    if (job == 2) tau_mfma8(P, sc, pi, n, pl, mt, ch, lds);
+    else hist_mfma8(P, sc, pi, n, pl, job, mt, ch, lds);
+    return;
+  } else {
   if (job == 2) {
     tau_source_tile<D>(P, sc, pi, n, pl, mt, ch, lds);
     return;
@@ -1380,6 +1775,22 @@ __global__ __launch_bounds__(NTHR) void k_history(ProbArg pa, Scratch sc, HistPl
     } break;
   }
   sc.part(pi)[(pl.part_off[job] + (long)ch * mout + m) * DD + e] = acc;
+  }
+}
+
+// Set-up of a time step in a kernel of its own (d = 8: the 40 x 40 register
+// solve would otherwise set the register and LDS budget of every history
+// workgroup).
+template <int D>
+__global__ __launch_bounds__(NTHR) void k_prep(ProbArg pa, Scratch sc, int n) {
+  constexpr int DD = D * D;
+  constexpr int PREPN = (KMAX * D) * (KMAX * D + 1) + KMAX * D * D + 4 * DD + (KMAX + 1) * (KMAX + 1) * DD +
+                        (KMAX + 1) * DD + (D <= 4 ? (KMAX + 1) * (KMAX + 1) * DD : 0);
+  __shared__ cplx lds[PREPN];
+  int pi = blockIdx.y;
+  const Prob& P = pa.get(pi);
+  if (n > P.nt) return;
+  prep_step<D>(P, sc, pi, n, lds);
 }
 
 // -------------------------------------------------------------- REDUCE
@@ -2181,6 +2592,36 @@ __global__ __launch_bounds__(NTHR) void k_tau_shared(ProbArg pa, Scratch sc, His
     }
 }
 
+// ------------------------------------------------------------ side streams
+// One side stream (default priority, non-blocking) and a fork / join event
+// pair per (device, stream) of the caller, created on first use and kept
+// until the process ends.
+struct SideStream {
+  hipStream_t s = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+};
+static SideStream* side_stream(hipStream_t main) {
+  static std::mutex mu;
+  static std::map<std::pair<int, hipStream_t>, SideStream> tab;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+  std::lock_guard<std::mutex> lk(mu);
+  SideStream& x = tab[{dev, main}];
+  if (!x.s) {
+    if (hipStreamCreateWithFlags(&x.s, hipStreamNonBlocking) != hipSuccess) {
+      x.s = nullptr;
+      return nullptr;
+    }
+    if (hipEventCreateWithFlags(&x.fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&x.join, hipEventDisableTiming) != hipSuccess) {
+      (void)hipStreamDestroy(x.s);
+      x = SideStream{};
+      return nullptr;
+    }
+  }
+  return &x;
+}
+
 // ------------------------------------------------------------ launches
 template <int D>
 static hipError_t step_d(const ProbArg& pa, const Scratch& sc, int n, hipStream_t s, bool shared_sigma,
@@ -2205,7 +2646,23 @@ static hipError_t step_d(const ProbArg& pa, const Scratch& sc, int n, hipStream_
     e2 = prof_event();
     if (e0) (void)hipEventRecord(e0, s);
   }
+  // d = 8: the set-up kernel runs beside the history sums, on a side stream
+  // forked from s and joined before the reduction (serially on s when the
+  // caller creates no runtime objects or captures a graph)
+  SideStream* side = nullptr;
+  if constexpr (D == 8) {
+    side = record ? side_stream(s) : nullptr;
+    if (side) {
+      (void)hipEventRecord(side->fork, s);
+      (void)hipStreamWaitEvent(side->s, side->fork, 0);
+      k_prep<D><<<dim3(1, pa.count), NTHR, 0, side->s>>>(pa, sc, n);
+      (void)hipEventRecord(side->join, side->s);
+    } else {
+      k_prep<D><<<dim3(1, pa.count), NTHR, 0, s>>>(pa, sc, n);
+    }
+  }
   k_history<D><<<g1, NTHR, 0, s>>>(pa, sc, pl);
+  if (side) (void)hipStreamWaitEvent(s, side->join, 0);
   if (rec && e1) {
     (void)hipEventRecord(e1, s);
     double dd = (double)D * D;
