@@ -279,14 +279,17 @@ def run_free(args):
 
 
 def run_uneven(args):
-    """Uneven batch sample: 8 second-Born problems, two each of d = 1, 2, 4, 8
-    orbitals, nt uniform in [300, 500], ntau = 300, beta = 10, h = 0.02, k = 5,
-    a random hermitian H with spectrum in [-2, 2] and a constant U uniform in
-    [0.5, 2] per problem (seeded). Timed twice on the same problems: batched
-    (one cntr_solve_2b_batch per orbital count: every problem of a group
-    advances in one launch per kernel and step) and the per-instance loop
-    (cntr_solve_2b per problem). Both include the Matsubara loops and the
-    bootstrap."""
+    """Uneven batch: the first `uneven_count` of the 384 seeded problems of
+    data/uneven_batch_384.npz (d in {1, 2, 4, 8}, nt in [400, 3000], U in
+    [0.5, 2], random hermitian H with spectrum [-2, 2]; beta = 10, ntau = 300,
+    h = 0.02, k = 5, local second-Born + Hartree), every problem run over its
+    first `uneven_nt` slices (a causal prefix: those slices do not depend on
+    the later ones). Timed twice on the same problems, whole solves
+    (Matsubara loops, bootstrap, time steps): one cntr_solve_2b_uneven call
+    (the orbital-count groups side by side, each group one launch per kernel
+    and step) against the per-instance loop (cntr_solve_2b per problem).
+    Also reported: the wave plan of the full 384-problem batch at its full
+    lengths under a 200 GB cap (planning only)."""
     import numpy as np
     import torch
 
@@ -294,14 +297,14 @@ def run_uneven(args):
     from paper_1911_01211_amd import workloads as W
 
     dev = "cuda:0"
+    allp = W.load_uneven(os.path.join(ROOT, "paper_1911_01211_amd", "data", "uneven_batch_384.npz"))
+    sel = allp[:args.uneven_count]
     problems = []
-    for i, d in enumerate([1, 1, 2, 2, 4, 4, 8, 8]):
-        r = W.rng(700, i)
-        nt = int(r.integers(300, 501))
+    for d, nt_full, U0, H in sel:
+        nt = min(nt_full, args.uneven_nt)
         g = W.GridSpec(nt=nt, ntau=300, d=d, sig=-1, k=5, beta=10.0, h=0.02, mu=0.0)
-        H = W.haar_hermitian(r, d)
         e0 = torch.as_tensor(np.broadcast_to(H, (nt + 2, d, d)).copy()).to(dev)
-        U = torch.full((nt + 2,), float(r.uniform(0.5, 2.0)), dtype=torch.float64, device=dev)
+        U = torch.full((nt + 2,), U0, dtype=torch.float64, device=dev)
         problems.append(dict(G=K.Contour(g, dev), Sigma=K.Contour(g, dev), Gscratch=K.Contour(g, dev), eps0=e0,
                              U=U, eps_mf=torch.zeros_like(e0)))
     slices = sum(p["G"].g.nt - p["G"].g.k for p in problems)
@@ -320,11 +323,18 @@ def run_uneven(args):
                 K.solve_2b(p["G"], p["Sigma"], p["Gscratch"], p["eps0"], p["U"], p["eps_mf"], **opts)
         torch.cuda.synchronize()
         times[mode] = time.perf_counter() - t0
-    return {"workload": "8 second-Born problems, d = 1, 1, 2, 2, 4, 4, 8, 8, nt in [300, 500], ntau = 300, "
-                        "beta = 10, random H (spectrum [-2, 2]), U in [0.5, 2]; whole solves",
+        print(f"# uneven {mode}: {times[mode]:.2f}s", file=sys.stderr, flush=True)
+    foot = [3 * 16.0 * d * d * ((nt + 1) * (nt + 2) + (nt + 1) * 301 + 301) for d, nt, _, _ in allp]
+    waves = K.plan_waves(foot, 200e9)
+    counts = {str(d): sum(1 for p in sel if p[0] == d) for d in (1, 2, 4, 8)}
+    return {"workload": f"first {len(sel)} of the 384 seeded uneven second-Born problems (d counts {counts}), "
+                        f"slices 0..min(nt, {args.uneven_nt}), ntau=300, beta=10, h=0.02, k=5; whole solves",
             "value": slices / times["batched"], "unit": "instance time-steps/s",
             "per_instance_loop": slices / times["loop"], "speedup_vs_loop": times["loop"] / times["batched"],
-            "seconds": times, "corrector_iterations": args.ncorr}
+            "seconds": times, "corrector_iterations": args.ncorr,
+            "full_batch_waves": {"cap_bytes": 200e9, "waves": len(waves), "problems": len(allp),
+                                 "bytes_total": sum(foot),
+                                 "bytes_per_wave": [sum(foot[i] for i in w) for w in waves]}}
 
 
 def run_kpoints(args):
@@ -521,6 +531,9 @@ def main():
     ap.add_argument("--no-uneven", action="store_true")
     ap.add_argument("--no-free", action="store_true")
     ap.add_argument("--no-cfg1", action="store_true")
+    ap.add_argument("--no-tune-cache", action="store_true", help="built-in term chunks instead of tune_cache.json")
+    ap.add_argument("--uneven-count", type=int, default=64, help="problems of the uneven batch (of 384)")
+    ap.add_argument("--uneven-nt", type=int, default=400, help="slices of each uneven problem (causal prefix)")
     ap.add_argument("--cfg1-reps", type=int, default=50)
     ap.add_argument("--adj-niter", type=int, default=10, help="adjoint fixed-point iterations per slice")
     ap.add_argument("--adj-nt", type=int, default=1500, help="time steps of the adjoint ring workload")
@@ -538,6 +551,8 @@ def main():
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(the per-GPU share of a sharded run is the single-GPU workload).", file=sys.stderr)
         sys.exit(2)
+    from paper_1911_01211_amd import autotune
+    tiles = autotune.apply_cache() if not args.no_tune_cache else None
     g, elapsed, prof, stats, dens_dev, state = run_gpu(args)
     stream_gbs = stream_bandwidth()
     nsteps = (g.nt - g.k) * args.steps
@@ -578,6 +593,7 @@ def main():
                      "launches": prof["hist_launches"], "every": PROF_EVERY,
                      "avg_launch_us": prof["hist_ms"] * 1e3 / max(1, prof["hist_launches"])},
         "check": {"max_density_deviation_at_nt": dens_dev},
+        "tiles": None if tiles is None else {d: {"n_hi": e["n_hi"], "tj": e["tj"]} for d, e in tiles["entries"].items()},
     }
     del state
     if not args.no_adjoint:

@@ -327,7 +327,23 @@ cntr_status cntr_solve_2b_batch(int32_t count, const cntr_grid* grids, const cnt
                                 double mats_mix, int32_t boot_maxit, double boot_tol, int32_t ncorr,
                                 double* stats, void* stream);
 
-/* ------------------------------------------------------------ profiling --
+/* ----------------------------------------------------------------- A11 --
+ * The same self-consistent propagation for problems of different orbital
+ * counts (d, and k or ntau, may differ between problems). The problems are
+ * grouped by (d, k, ntau); each group is solved as by cntr_solve_2b_batch on
+ * a stream of its own (forked from `stream`, default priority, kept by the
+ * library), and slice n of every group is enqueued in turn, so that the
+ * groups' kernels run side by side on the device; `stream` waits for all
+ * groups at the end. At most 16 groups. Arguments, loop controls and stats as
+ * cntr_solve_2b_batch (stats: largest over the groups). Synchronizes `stream`
+ * during the Matsubara and bootstrap loops. */
+cntr_status cntr_solve_2b_uneven(int32_t count, const cntr_grid* grids, const cntr_gf* G, const cntr_gf* Sigma,
+                                 const cntr_gf* Gscratch, const void* const* eps0, const double* const* U,
+                                 void* const* eps_mf, double nbar, int32_t mats_maxit, double mats_tol,
+                                 double mats_mix, int32_t boot_maxit, double boot_tol, int32_t ncorr,
+                                 double* stats, void* stream);
+
+/* ------------------------------------------------------------ profiling --/* ------------------------------------------------------------ profiling --
  * Device-time accounting of the time step, measured with HIP events
  * recorded on the stream each kernel is launched on. Between
  * cntr_profile_begin and cntr_profile_end every time step (n > k) records
@@ -375,7 +391,18 @@ cntr_status cntr_graph_end(void* stream, cntr_graph* out);
 cntr_status cntr_graph_launch(cntr_graph graph, void* stream);
 cntr_status cntr_graph_destroy(cntr_graph graph);
 
-/* --------------------------------------------------------------- checks --/* --------------------------------------------------------------- checks --
+/* ---------------------------------------------------------------- tiles --
+ * Term chunks of the history sums picked by an autotuner (the Python module
+ * paper_1911_01211_amd.autotune times the candidates on the device and keeps
+ * a cache): for problems of orbital count d, time steps at slices
+ * n <= n_hi[0] use chunk tj[0], n <= n_hi[1] tj[1], ..., later slices the
+ * last chunk. nbands = 0 restores the built-in chunk. Tunable: d = 1 (tj in
+ * 32, 64, 128, 256; built-in 256) and d = 8 (16, 32, 64; built-in 64);
+ * else CNTR_EINVAL. At most 8 bands, edges increasing. Process-wide; the
+ * results change only in the summation order of the history sums. */
+cntr_status cntr_set_tiles(int32_t d, int32_t nbands, const int32_t* n_hi, const int32_t* tj);
+
+/* --------------------------------------------------------------- checks --/* --------------------------------------------------------------- checks --/* --------------------------------------------------------------- checks --
  * Optional checks of the preconditions of the Dyson equation (Tab. dyson:
  * the step at tstp needs slices -1..tstp-1 of G) and of the values, in the
  * spirit of the library's debug mode (Sec. "Compilation of libcntr"). Off by

@@ -23,7 +23,8 @@ SYMBOLS = ["cntr_init_matsubara", "cntr_dyson_step", "cntr_convolution", "cntr_s
            "cntr_profile_end", "cntr_observables", "cntr_sigma_local", "cntr_adjoint_sweep",
            "cntr_solve_2b_batch", "cntr_set_checks", "cntr_mark_slices",
            "cntr_dyson_step_noalloc", "cntr_peierls", "cntr_peierls_grad",
-           "cntr_graph_begin", "cntr_graph_end", "cntr_graph_launch", "cntr_graph_destroy"]
+           "cntr_graph_begin", "cntr_graph_end", "cntr_graph_launch", "cntr_graph_destroy",
+           "cntr_solve_2b_uneven", "cntr_set_tiles"]
 
 
 class CntrError(RuntimeError):
@@ -74,6 +75,9 @@ def lib():
                                          P(vp), i32, dbl, P(dbl), vp]
         L.cntr_solve_2b_batch.argtypes = [i32, P(Grid), P(GF), P(GF), P(GF), P(vp), P(vp), P(vp), dbl, i32, dbl,
                                           dbl, i32, dbl, i32, P(dbl), vp]
+        L.cntr_solve_2b_uneven.argtypes = [i32, P(Grid), P(GF), P(GF), P(GF), P(vp), P(vp), P(vp), dbl, i32, dbl,
+                                           dbl, i32, dbl, i32, P(dbl), vp]
+        L.cntr_set_tiles.argtypes = [i32, i32, P(C.c_int32), P(C.c_int32)]
         L.cntr_sync.argtypes = [vp]
         L.cntr_set_checks.argtypes = [i32]
         L.cntr_graph_begin.argtypes = [vp]

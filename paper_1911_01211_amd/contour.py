@@ -324,15 +324,36 @@ def solve_2b_batch(G: list, Sigma: list, Gscratch: list, eps0: list, U: list, ep
     return Solve2BStats(int(st[0]), int(st[1]), st[2], st[3])
 
 
-def solve_uneven(problems: list, **kw) -> dict:
+def solve_uneven(problems: list, nbar=0.5, mats_maxit=200, mats_tol=1e-14, mats_mix=0.5, boot_maxit=100,
+                 boot_tol=1e-14, ncorr=6, stream=None) -> Solve2BStats:
     """An uneven set of second-Born problems (dicts with G, Sigma, Gscratch,
-    eps0, U, eps_mf; any d and nt): one batched solve per orbital count d.
-    Returns the stats per d."""
-    by_d = {}
-    for p in problems:
-        by_d.setdefault(p["G"].g.d, []).append(p)
-    out = {}
-    for d, ps in sorted(by_d.items()):
-        out[d] = solve_2b_batch([p["G"] for p in ps], [p["Sigma"] for p in ps], [p["Gscratch"] for p in ps],
-                                [p["eps0"] for p in ps], [p["U"] for p in ps], [p["eps_mf"] for p in ps], **kw)
-    return out
+    eps0, U, eps_mf; any d and nt) in one call (cntr_solve_2b_uneven): the
+    groups of equal orbital count advance side by side on streams of their
+    own."""
+    st = (C.c_double * 4)()
+    G = [p["G"] for p in problems]
+    _abi.check(_abi.lib().cntr_solve_2b_uneven(len(G), _grids(G), _gfs(G), _gfs([p["Sigma"] for p in problems]),
+                                               _gfs([p["Gscratch"] for p in problems]),
+                                               _ptrs([p["eps0"] for p in problems]), _ptrs([p["U"] for p in problems]),
+                                               _ptrs([p["eps_mf"] for p in problems]), nbar, mats_maxit, mats_tol,
+                                               mats_mix, boot_maxit, boot_tol, ncorr, st, _stream(stream)))
+    return Solve2BStats(int(st[0]), int(st[1]), st[2], st[3])
+
+
+def plan_waves(footprints: list, cap_bytes: float) -> list:
+    """Waves of problems whose device footprints fit under cap_bytes each
+    (first fit in order of decreasing footprint): lists of problem indices."""
+    order = sorted(range(len(footprints)), key=lambda i: -footprints[i])
+    waves, used = [], []
+    for i in order:
+        if footprints[i] > cap_bytes:
+            raise ValueError(f"problem {i} needs {footprints[i]:.3g} B, above the wave cap {cap_bytes:.3g} B")
+        for w in range(len(waves)):
+            if used[w] + footprints[i] <= cap_bytes:
+                waves[w].append(i)
+                used[w] += footprints[i]
+                break
+        else:
+            waves.append([i])
+            used.append(footprints[i])
+    return [sorted(w) for w in waves]

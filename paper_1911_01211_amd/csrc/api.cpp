@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <tuple>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -620,6 +621,25 @@ cntr_status cntr_graph_destroy(cntr_graph g) {
   if (g->exec) (void)hipGraphExecDestroy(g->exec);
   if (g->graph) (void)hipGraphDestroy(g->graph);
   delete g;
+  return CNTR_OK;
+}
+
+cntr_status cntr_set_tiles(int32_t d, int32_t nbands, const int32_t* n_hi, const int32_t* tj) {
+  if (d < 1 || d > 8) return fail(CNTR_EINVAL, "cntr_set_tiles: d outside 1..8");
+  if (nbands < 0 || nbands > TUNE_BANDS) return fail(CNTR_EINVAL, "cntr_set_tiles: 0..8 bands");
+  if (nbands > 0 && (!n_hi || !tj)) return fail(CNTR_ESHAPE, "cntr_set_tiles: null pointer");
+  for (int b = 0; b < nbands; b++) {
+    if (!tile_allowed(d, tj[b])) return fail(CNTR_EINVAL, "cntr_set_tiles: chunk not available for this d");
+    if (b > 0 && n_hi[b] <= n_hi[b - 1]) return fail(CNTR_EINVAL, "cntr_set_tiles: band edges must increase");
+  }
+  std::lock_guard<std::mutex> lk(g_mu);
+  TileTable t;
+  t.nb = nbands;
+  for (int b = 0; b < nbands; b++) {
+    t.n_hi[b] = n_hi[b];
+    t.tj[b] = tj[b];
+  }
+  g_tiles[d] = t;
   return CNTR_OK;
 }
 
@@ -1310,75 +1330,94 @@ cntr_status cntr_solve_2b(const cntr_grid* grid, const cntr_gf* G, const cntr_gf
   return CNTR_OK;
 }
 
-cntr_status cntr_solve_2b_batch(int32_t count, const cntr_grid* grids, const cntr_gf* G, const cntr_gf* Sigma,
-                                const cntr_gf* Gscratch, const void* const* eps0, const double* const* U,
-                                void* const* eps_mf, double nbar, int32_t mats_maxit, double mats_tol,
-                                double mats_mix, int32_t boot_maxit, double boot_tol, int32_t ncorr,
-                                double* stats, void* stream) {
-  if (capturing((hipStream_t)stream)) return fail(CNTR_EINVAL, "cntr_solve_2b_batch: synchronizes the stream, not allowed during graph capture");
-  cntr_status st = check_batch(count, grids, "cntr_solve_2b_batch");
+
+}  // extern "C"
+
+namespace cntr {
+namespace {
+
+// Problems of one orbital count (and k, ntau) of a second-Born batch: the
+// descriptors and scratch of their stream, and the phases of the solve.
+struct Group2B {
+  std::vector<int> idx;
+  std::vector<Prob> v, vo;
+  cntr_grid gmax{};
+  int k = 0, d = 0, ntmax = 0;
+  hipStream_t s = nullptr;
+  StreamScratch* sc = nullptr;
+  Scratch scr{};
+  ProbArg pa{}, po{};
+};
+
+cntr_status group_setup(Group2B& g, const cntr_grid* grids, const cntr_gf* G, const cntr_gf* Sigma,
+                        const cntr_gf* Gscratch, const void* const* eps0, const double* const* U,
+                        void* const* eps_mf, hipStream_t s) {
+  int count = (int)g.idx.size();
+  g.s = s;
+  g.k = grids[g.idx[0]].k;
+  g.d = grids[g.idx[0]].d;
+  g.ntmax = 0;
+  for (int i : g.idx) g.ntmax = std::max(g.ntmax, (int)grids[i].nt);
+  g.gmax = grids[g.idx[0]];
+  g.gmax.nt = g.ntmax < g.k + 1 ? g.k + 1 : g.ntmax;
+  g.sc = scratch_for(s);
+  StepScratch lay = step_layout(g.gmax);
+  cntr_status st = grow(s, g.sc, lay.per * count, 5 * (size_t)count, 2 * (size_t)count);
   if (st) return st;
-  if (!gf_ok(G, count) || !gf_ok(Sigma, count) || !gf_ok(Gscratch, count) || !eps0 || !U || !eps_mf)
-    return fail(CNTR_ESHAPE, "cntr_solve_2b_batch: null pointer");
-  for (int i = 0; i < count; i++)
-    if (!eps0[i] || !U[i] || !eps_mf[i]) return fail(CNTR_ESHAPE, "cntr_solve_2b_batch: null eps0, U or eps_mf");
-  if (!(mats_mix > 0 && mats_mix <= 1)) return fail(CNTR_EINVAL, "cntr_solve_2b_batch: mats_mix outside (0,1]");
-  if ((st = ensure_weights())) return st;
-  hipStream_t s = (hipStream_t)stream;
-  int k = grids[0].k, d = grids[0].d, ntmax = 0;
-  for (int i = 0; i < count; i++) ntmax = grids[i].nt > ntmax ? grids[i].nt : ntmax;
-  cntr_grid gmax = grids[0];
-  gmax.nt = ntmax < k + 1 ? k + 1 : ntmax;
-  StreamScratch* sc = scratch_for(s);
-  StepScratch lay = step_layout(gmax);
-  if ((st = grow(s, sc, lay.per * count, 5 * (size_t)count, 2 * (size_t)count))) return st;
-  if (count > STAT_WORDS) return fail(CNTR_ESHAPE, "cntr_solve_2b_batch: more than 65536 problems");
-  Scratch scr = lay.sc;
-  scr.base = sc->data();
-  scr.stat = sc->stat();
-  sc->nstat = std::max(sc->nstat, (int)count);
-  std::vector<Prob> v(count), vo(count);
-  for (int i = 0; i < count; i++) {
-    v[i] = make_prob(grids[i], &G[i], &Sigma[i], eps_mf[i]);
-    v[i].U = U[i];
-    v[i].eps0 = (const cplx*)eps0[i];
-    v[i].eps_mf = (cplx*)eps_mf[i];
-    vo[i] = make_prob(grids[i], &Gscratch[i], nullptr, nullptr);
+  g.scr = lay.sc;
+  g.scr.base = g.sc->data();
+  g.scr.stat = g.sc->stat();
+  g.sc->nstat = std::max(g.sc->nstat, count);
+  g.v.resize(count);
+  g.vo.resize(count);
+  for (int q = 0; q < count; q++) {
+    int i = g.idx[q];
+    g.v[q] = make_prob(grids[i], &G[i], &Sigma[i], eps_mf[i]);
+    g.v[q].U = U[i];
+    g.v[q].eps0 = (const cplx*)eps0[i];
+    g.v[q].eps_mf = (cplx*)eps_mf[i];
+    g.vo[q] = make_prob(grids[i], &Gscratch[i], nullptr, nullptr);
   }
-  // Matsubara loops one problem at a time (each has its own dense solve)
-  int itmax = 0;
-  double errmax = 0;
-  for (int i = 0; i < count; i++) {
-    ProbArg p1{v[i], nullptr, 1}, o1{vo[i], nullptr, 1};
+  if ((st = make_arg(s, g.sc, g.v, 0, &g.pa)) || (st = make_arg(s, g.sc, g.vo, 1, &g.po))) return st;
+  return CNTR_OK;
+}
+
+// Matsubara loops one problem at a time (each has its own dense solve)
+cntr_status group_mats(Group2B& g, const cntr_grid* grids, double nbar, int mats_maxit, double mats_tol,
+                       double mats_mix, int* itmax, double* errmax) {
+  for (size_t q = 0; q < g.idx.size(); q++) {
+    ProbArg p1{g.v[q], nullptr, 1}, o1{g.vo[q], nullptr, 1};
     int it = 0;
     double err = 0;
-    if ((st = mats_loop_2b(grids[i], v[i], p1, o1, sc, nbar, mats_maxit, mats_tol, mats_mix, s, &it, &err)))
-      return st;
-    itmax = it > itmax ? it : itmax;
-    errmax = err > errmax ? err : errmax;
+    cntr_status st = mats_loop_2b(grids[g.idx[q]], g.v[q], p1, o1, g.sc, nbar, mats_maxit, mats_tol, mats_mix, g.s,
+                                  &it, &err);
+    if (st) return st;
+    *itmax = std::max(*itmax, it);
+    *errmax = std::max(*errmax, err);
   }
-  if (stats) {
-    stats[0] = itmax;
-    stats[2] = errmax;
-  }
-  // bootstrap and time steps: one launch per kernel for the whole batch
-  ProbArg pa, po;
-  if ((st = make_arg(s, sc, v, 0, &pa)) || (st = make_arg(s, sc, vo, 1, &po))) return st;
+  return CNTR_OK;
+}
+
+// bootstrap of slices 0..k, one launch per kernel for the group; the
+// tolerance applies to the largest relative distance of the group
+cntr_status group_boot(Group2B& g, double nbar, int boot_maxit, double boot_tol, int* iters, double* err_out) {
+  int count = (int)g.idx.size(), k = g.k, d = g.d;
+  hipStream_t s = g.s;
   hipError_t e;
   std::vector<double> dist(2 * (size_t)count);
   int it;
   double err = 0;
   for (it = 0; it < boot_maxit; it++) {
     for (int n = 0; n <= k; n++)
-      if ((e = launch_sigma2b(pa, n, d, (int)slice_elems(gmax, n), nbar, s))) return hip_fail(e, "Sigma start");
+      if ((e = launch_sigma2b(g.pa, n, d, (int)slice_elems(g.gmax, n), nbar, s))) return hip_fail(e, "Sigma start");
     for (int n = 0; n <= k; n++)
-      if ((e = launch_copy(po, pa, n, d, (int)slice_elems(gmax, n), s))) return hip_fail(e, "copy");
-    if ((e = launch_start(pa, scr, d, gmax.ntau, s))) return hip_fail(e, "start-up");
+      if ((e = launch_copy(g.po, g.pa, n, d, (int)slice_elems(g.gmax, n), s))) return hip_fail(e, "copy");
+    if ((e = launch_start(g.pa, g.scr, d, g.gmax.ntau, s))) return hip_fail(e, "start-up");
     std::vector<double> num(count, 0.0), den(count, 0.0);
     for (int n = 0; n <= k; n++) {
-      e = hipMemsetAsync(sc->red, 0, 2 * (size_t)count * sizeof(double), s);
-      if (!e) e = launch_distance(pa, po, n, d, (int)slice_elems(gmax, n), sc->red, s);
-      if (!e) e = hipMemcpyAsync(dist.data(), sc->red, 2 * (size_t)count * sizeof(double), hipMemcpyDeviceToHost, s);
+      e = hipMemsetAsync(g.sc->red, 0, 2 * (size_t)count * sizeof(double), s);
+      if (!e) e = launch_distance(g.pa, g.po, n, d, (int)slice_elems(g.gmax, n), g.sc->red, s);
+      if (!e) e = hipMemcpyAsync(dist.data(), g.sc->red, 2 * (size_t)count * sizeof(double), hipMemcpyDeviceToHost, s);
       if (!e) e = hipStreamSynchronize(s);
       if (e) return hip_fail(e, "distance");
       for (int i = 0; i < count; i++) {
@@ -1393,19 +1432,163 @@ cntr_status cntr_solve_2b_batch(int32_t count, const cntr_grid* grids, const cnt
       break;
     }
   }
-  if (stats) {
-    stats[1] = it;
-    stats[3] = err;
+  *iters = it;
+  *err_out = err;
+  return CNTR_OK;
+}
+
+// predictor and ncorr corrector iterations of slice n for the problems of
+// the group still running (enqueued on the group's stream, no waiting)
+cntr_status group_step(Group2B& g, int n, int ncorr, double nbar) {
+  if (n > g.ntmax) return CNTR_OK;
+  hipError_t e;
+  int d = g.d;
+  if ((e = launch_extrapolate(g.pa, n - 1, d, (int)slice_elems(g.gmax, n), g.s))) return hip_fail(e, "extrapolate");
+  for (int c = 0; c < ncorr; c++) {
+    if ((e = launch_sigma2b(g.pa, n, d, (int)slice_elems(g.gmax, n), nbar, g.s))) return hip_fail(e, "Sigma");
+    if ((e = launch_step(g.pa, g.scr, n, d, g.s))) return hip_fail(e, "step");
   }
-  for (int n = k + 1; n <= ntmax; n++) {
-    if ((e = launch_extrapolate(pa, n - 1, d, (int)slice_elems(gmax, n), s))) return hip_fail(e, "extrapolate");
-    for (int c = 0; c < ncorr; c++) {
-      if ((e = launch_sigma2b(pa, n, d, (int)slice_elems(gmax, n), nbar, s))) return hip_fail(e, "Sigma");
-      if ((e = launch_step(pa, scr, n, d, s))) return hip_fail(e, "step");
+  if ((e = launch_sigma2b(g.pa, n, d, (int)slice_elems(g.gmax, n), nbar, g.s))) return hip_fail(e, "Sigma");
+  return CNTR_OK;
+}
+
+// one stream per orbital-count group beside the caller's (default priority)
+hipStream_t group_stream(hipStream_t main, int slot) {
+  static std::map<std::tuple<int, hipStream_t, int>, hipStream_t> tab;
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  std::lock_guard<std::mutex> lk(g_mu);
+  hipStream_t& x = tab[{dev, main, slot}];
+  if (!x && hipStreamCreateWithFlags(&x, hipStreamNonBlocking) != hipSuccess) x = nullptr;
+  return x;
+}
+
+cntr_status check_2b_args(int count, const cntr_gf* G, const cntr_gf* Sigma, const cntr_gf* Gscratch,
+                          const void* const* eps0, const double* const* U, void* const* eps_mf, double mats_mix,
+                          const char* what) {
+  if (!gf_ok(G, count) || !gf_ok(Sigma, count) || !gf_ok(Gscratch, count) || !eps0 || !U || !eps_mf)
+    return fail(CNTR_ESHAPE, std::string(what) + ": null pointer");
+  for (int i = 0; i < count; i++)
+    if (!eps0[i] || !U[i] || !eps_mf[i]) return fail(CNTR_ESHAPE, std::string(what) + ": null eps0, U or eps_mf");
+  if (!(mats_mix > 0 && mats_mix <= 1)) return fail(CNTR_EINVAL, std::string(what) + ": mats_mix outside (0,1]");
+  if (count > STAT_WORDS) return fail(CNTR_ESHAPE, std::string(what) + ": more than 65536 problems");
+  return CNTR_OK;
+}
+
+}  // namespace
+}  // namespace cntr
+
+extern "C" {
+
+cntr_status cntr_solve_2b_batch(int32_t count, const cntr_grid* grids, const cntr_gf* G, const cntr_gf* Sigma,
+                                const cntr_gf* Gscratch, const void* const* eps0, const double* const* U,
+                                void* const* eps_mf, double nbar, int32_t mats_maxit, double mats_tol,
+                                double mats_mix, int32_t boot_maxit, double boot_tol, int32_t ncorr,
+                                double* stats, void* stream) {
+  if (capturing((hipStream_t)stream))
+    return fail(CNTR_EINVAL, "cntr_solve_2b_batch: synchronizes the stream, not allowed during graph capture");
+  cntr_status st = check_batch(count, grids, "cntr_solve_2b_batch");
+  if (st) return st;
+  if ((st = check_2b_args(count, G, Sigma, Gscratch, eps0, U, eps_mf, mats_mix, "cntr_solve_2b_batch"))) return st;
+  if ((st = ensure_weights())) return st;
+  Group2B g;
+  for (int i = 0; i < count; i++) g.idx.push_back(i);
+  if ((st = group_setup(g, grids, G, Sigma, Gscratch, eps0, U, eps_mf, (hipStream_t)stream))) return st;
+  int itmax = 0, bit = 0;
+  double errmax = 0, berr = 0;
+  if ((st = group_mats(g, grids, nbar, mats_maxit, mats_tol, mats_mix, &itmax, &errmax))) return st;
+  if (stats) {
+    stats[0] = itmax;
+    stats[2] = errmax;
+  }
+  if ((st = group_boot(g, nbar, boot_maxit, boot_tol, &bit, &berr))) return st;
+  if (stats) {
+    stats[1] = bit;
+    stats[3] = berr;
+  }
+  for (int n = g.k + 1; n <= g.ntmax; n++)
+    if ((st = group_step(g, n, ncorr, nbar))) return st;
+  for (int i = 0; i < count; i++) order_mark(1, &G[i], grids[i].nt, true);
+  return CNTR_OK;
+}
+
+cntr_status cntr_solve_2b_uneven(int32_t count, const cntr_grid* grids, const cntr_gf* G, const cntr_gf* Sigma,
+                                 const cntr_gf* Gscratch, const void* const* eps0, const double* const* U,
+                                 void* const* eps_mf, double nbar, int32_t mats_maxit, double mats_tol,
+                                 double mats_mix, int32_t boot_maxit, double boot_tol, int32_t ncorr,
+                                 double* stats, void* stream) {
+  hipStream_t s = (hipStream_t)stream;
+  if (capturing(s))
+    return fail(CNTR_EINVAL, "cntr_solve_2b_uneven: synchronizes the stream, not allowed during graph capture");
+  if (count < 1 || !grids) return fail(CNTR_ESHAPE, "cntr_solve_2b_uneven: empty batch");
+  cntr_status st;
+  for (int i = 0; i < count; i++)
+    if ((st = check_grid(grids[i], "cntr_solve_2b_uneven"))) return st;
+  if ((st = check_2b_args(count, G, Sigma, Gscratch, eps0, U, eps_mf, mats_mix, "cntr_solve_2b_uneven"))) return st;
+  if ((st = ensure_weights())) return st;
+  // groups of equal (d, k, ntau), in order of first appearance
+  std::vector<Group2B> gs;
+  for (int i = 0; i < count; i++) {
+    size_t q = 0;
+    for (; q < gs.size(); q++) {
+      const cntr_grid& a = grids[gs[q].idx[0]];
+      if (a.d == grids[i].d && a.k == grids[i].k && a.ntau == grids[i].ntau) break;
     }
+    if (q == gs.size()) gs.emplace_back();
+    gs[q].idx.push_back(i);
+  }
+  if (gs.size() > 16) return fail(CNTR_ESHAPE, "cntr_solve_2b_uneven: more than 16 groups of (d, k, ntau)");
+  // every group on a stream of its own, forked from s
+  hipEvent_t fork = nullptr;
+  hipError_t e = hipEventCreateWithFlags(&fork, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventRecord(fork, s);
+  if (e != hipSuccess) return hip_fail(e, "cntr_solve_2b_uneven: fork");
+  for (size_t q = 0; q < gs.size(); q++) {
+    hipStream_t gsq = group_stream(s, (int)q);
+    if (!gsq) {
+      (void)hipEventDestroy(fork);
+      return fail(CNTR_EHIP, "cntr_solve_2b_uneven: group stream");
+    }
+    if ((e = hipStreamWaitEvent(gsq, fork, 0))) return hip_fail(e, "cntr_solve_2b_uneven: fork wait");
+    if ((st = group_setup(gs[q], grids, G, Sigma, Gscratch, eps0, U, eps_mf, gsq))) return st;
+  }
+  (void)hipEventDestroy(fork);
+  int itmax = 0, bmax = 0;
+  double errmax = 0, bemax = 0;
+  for (auto& g : gs)
+    if ((st = group_mats(g, grids, nbar, mats_maxit, mats_tol, mats_mix, &itmax, &errmax))) return st;
+  for (auto& g : gs) {
+    int bit = 0;
+    double berr = 0;
+    if ((st = group_boot(g, nbar, boot_maxit, boot_tol, &bit, &berr))) return st;
+    bmax = std::max(bmax, bit);
+    bemax = std::max(bemax, berr);
+  }
+  if (stats) {
+    stats[0] = itmax;
+    stats[1] = bmax;
+    stats[2] = errmax;
+    stats[3] = bemax;
+  }
+  // time steps: slice n of every group in turn, each group on its stream, so
+  // that the groups' kernels run side by side
+  int ntmax = 0, k = gs[0].k;
+  for (auto& g : gs) {
+    ntmax = std::max(ntmax, g.ntmax);
+    k = std::min(k, g.k);
   }
   for (int n = k + 1; n <= ntmax; n++)
-    if ((e = launch_sigma2b(pa, n, d, (int)slice_elems(gmax, n), nbar, s))) return hip_fail(e, "Sigma");
+    for (auto& g : gs)
+      if (n > g.k && (st = group_step(g, n, ncorr, nbar))) return st;
+  // join: s waits for every group
+  for (auto& g : gs) {
+    hipEvent_t j = nullptr;
+    e = hipEventCreateWithFlags(&j, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventRecord(j, g.s);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s, j, 0);
+    if (j) (void)hipEventDestroy(j);
+    if (e != hipSuccess) return hip_fail(e, "cntr_solve_2b_uneven: join");
+  }
   for (int i = 0; i < count; i++) order_mark(1, &G[i], grids[i].nt, true);
   return CNTR_OK;
 }

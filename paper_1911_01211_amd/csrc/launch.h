@@ -55,6 +55,16 @@ struct ProfState {
 extern ProfState g_prof;
 
 
+// autotuned term chunks of the history jobs, per orbital count (see make_plan)
+constexpr int TUNE_BANDS = 8;
+struct TileTable {
+  int nb = 0;
+  int n_hi[TUNE_BANDS];
+  int tj[TUNE_BANDS];
+};
+extern TileTable g_tiles[9];
+bool tile_allowed(int d, int tj);
+
 int hist_tm(int d);
 // tau_split > 0: the tau source comes from k_tau_shared in tau_split chunks
 // (no history workgroups for it)

@@ -60,11 +60,32 @@ constexpr int TSM = 32, TSP = 32, TSV = 32, TS_NTAU = 512, TS_SPLIT = 4;
 // panel.
 constexpr bool hist_staged(int d) { return d == 2 || d == 4; }
 
+// Term chunks of the history jobs chosen by the autotuner (cntr_set_tiles):
+// per orbital count, up to TUNE_BANDS bands of slices n <= n_hi[b], each with
+// its chunk; 0 bands = the built-in default. Tunable: d = 1 (one block per
+// lane: chunks 32..256) and d = 8 (MFMA path: chunks 16..64).
+TileTable g_tiles[9];
+
+int tuned_tj(int d, int n) {
+  const TileTable& t = g_tiles[d];
+  for (int b = 0; b < t.nb; b++)
+    if (n <= t.n_hi[b]) return t.tj[b];
+  return t.nb > 0 ? t.tj[t.nb - 1] : 0;
+}
+
+bool tile_allowed(int d, int tj) {
+  if (d == 1) return tj == 32 || tj == 64 || tj == 128 || tj == 256;
+  if (d == 8) return tj == 16 || tj == 32 || tj == 64;
+  return false;
+}
+
 HistPlan make_plan(int n, int k, int ntau, int d, int tau_split) {
   HistPlan p{};
   p.n = n;
   p.staged = hist_staged(d);
   p.TJ = hist_tj(d);
+  int ttj = (d == 1 || d == 8) ? tuned_tj(d, n) : 0;
+  if (d == 1 && ttj) p.TJ = ttj;
   p.TM = hist_tm(d);
   p.TJS = hist_tjs(d);
   int nb = n - k;  // bulk outputs m = 0..n-k-1
@@ -84,7 +105,7 @@ HistPlan make_plan(int n, int k, int ntau, int d, int tau_split) {
       // d = 8: tiles of 8 outputs (two per wave) on the MFMA path, except
       // the tau source
       p.tm[j] = d == 8 ? 8 : p.TM;
-      p.tj[j] = d == 8 ? (j == 2 ? MF8_TAU_TJ : MF8_TJ) : (j == 2 ? p.TJS : p.TJ);
+      p.tj[j] = d == 8 ? (j == 2 ? MF8_TAU_TJ : (ttj ? ttj : MF8_TJ)) : (j == 2 ? p.TJS : p.TJ);
     }
   }
   // d = 1: the mixing panel is read once for both of its consumers (job 1
@@ -149,13 +170,24 @@ HistPlan make_plan(int n, int k, int ntau, int d, int tau_split) {
 
 size_t step_scratch_bytes(int nt, int k, int ntau, int d) {
   size_t mx = 0;
-  // partial storage grows with n; check the largest few n (monotone)
-  for (int n = nt; n >= nt - 1 && n > k; n--)
+  // for one term chunk the partial storage grows with n: check the largest
+  // few n of every band of chunks (the last slices, and the last slices of
+  // each autotuned band)
+  std::vector<int> ns = {nt, nt - 1};
+  const TileTable& t = g_tiles[d];
+  for (int b = 0; b < t.nb; b++) {
+    int e = t.n_hi[b] < nt ? t.n_hi[b] : nt;
+    ns.push_back(e);
+    ns.push_back(e - 1);
+  }
+  for (int n : ns) {
+    if (n <= k) continue;
     for (int ts : {0, TS_SPLIT}) {
       HistPlan p = make_plan(n, k, ntau, d, d == 1 ? ts : 0);
       size_t blocks = (size_t)p.total_blocks;
       if (blocks > mx) mx = blocks;
     }
+  }
   return mx * d * d * sizeof(cplx);
 }
 
@@ -1313,11 +1345,12 @@ __device__ inline cplx mf8_scale(cplx q, double w, bool nc) { return mk(nc ? -w 
 template <int JOB>
 __device__ __forceinline__ void hist_mfma8_job(const Prob& P, const Scratch& sc, int pi, int n, const HistPlan& pl,
                                                int mt, int ch, cplx* lds) {
-  constexpr int DD = 64, TJ = MF8_TJ, PD = 8;
+  constexpr int DD = 64, PD = 8;
   __shared__ double s_ss[KP * KP], s_om[KP];
   int k = P.k, ntau = P.ntau;
   int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   int mout = pl.mout[JOB], tm = pl.tm[JOB];
+  int TJ = pl.tj[JOB];  // <= MF8_TJ (the staging buffer)
   int j0 = ch * TJ;
   int mlo = mt * tm, mhi = min(mlo + tm, mout) - 1;
   if (JOB == 0 && j0 + TJ - 1 < mlo) return;

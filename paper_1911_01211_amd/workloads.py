@@ -240,3 +240,24 @@ def peierls_levels(T: np.ndarray, Phi: np.ndarray, A_samples: np.ndarray) -> np.
     with A = 0 at entries -1 and 0 and A_1..A_nt after them."""
     A = np.concatenate([[0.0, 0.0], A_samples])
     return T * np.exp(1j * A[:, None, None] * Phi[None, :, :])
+
+
+def uneven_problem(p: int):
+    """Problem p of the uneven batch: from PCG64(SeedSequence([191101211, p]))
+    draw d from {1, 2, 4, 8}, nt uniform in [400, 3000], U uniform in
+    [0.5, 2], then a hermitian H with spectrum uniform in [-2, 2] and a Haar
+    distributed eigenbasis. Returns (d, nt, U, H)."""
+    r = rng(p)
+    d = int(r.choice([1, 2, 4, 8]))
+    nt = int(r.integers(400, 3001))
+    U = float(r.uniform(0.5, 2.0))
+    H = haar_hermitian(r, d, -2.0, 2.0)
+    return d, nt, U, H
+
+
+def load_uneven(path: str):
+    """The uneven batch as stored by data/make_uneven_batch.py: a list of
+    (d, nt, U, H) per problem."""
+    z = np.load(path)
+    return [(int(d), int(nt), float(U), np.array(z["H"][i, :d, :d]))
+            for i, (d, nt, U) in enumerate(zip(z["d"], z["nt"], z["U"]))]
