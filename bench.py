@@ -114,8 +114,9 @@ def run_adjoint(args):
     and its gradient with respect to all 1500 samples A_n and U through
     DysonKineticEnergy (forward: cntr_solve_2b; backward: the second-Born
     adjoint sweep, Matsubara solve included). Checked against central
-    differences of the same GPU forward solve (delta = 1e-5 max(1, |theta|))
-    along two seeded directions in (A, U)."""
+    differences of the same GPU forward solve (steps delta and delta/2,
+    delta = 1e-5 max(1, |theta|), Richardson-combined) along seeded
+    directions in (A, U)."""
     import numpy as np
     import torch
 
@@ -142,22 +143,25 @@ def run_adjoint(args):
     print(f"# adjoint ring: forward {t1 - t0:.2f}s backward {t2 - t1:.2f}s", file=sys.stderr, flush=True)
     gA, gU = At.grad.cpu().numpy(), float(Ut.grad)
     fd = []
-    if args.adj_fd:
-        r = W.rng(191, 5)
-        for q in range(2):
-            vA, vU = r.normal(size=g.nt), float(r.normal())
-            dl = 1e-5 * max(1.0, float(np.abs(A).max()), U0)
+    r = W.rng(191, 5)
+    for q in range(args.adj_fd):
+        vA, vU = r.normal(size=g.nt), float(r.normal())
+        dl = 1e-5 * max(1.0, float(np.abs(A).max()), U0)
+        diffs = []
+        for t in (dl, dl / 2):  # Richardson over two steps removes the O(t^2) term
             Jpm = []
             for sgn in (1.0, -1.0):
                 with torch.no_grad():
-                    Ap = torch.tensor(A + sgn * dl * vA, dtype=torch.float64, device=dev)
-                    Up = torch.full((g.nt + 2,), U0 + sgn * dl * vU, dtype=torch.float64, device=dev)
+                    Ap = torch.tensor(A + sgn * t * vA, dtype=torch.float64, device=dev)
+                    Up = torch.full((g.nt + 2,), U0 + sgn * t * vU, dtype=torch.float64, device=dev)
                     Jpm.append(float(AG.kinetic_energy(Ap, Up, m)))
-            ref = (Jpm[0] - Jpm[1]) / (2 * dl)
-            got = float(np.dot(gA, vA) + gU * vU)
-            fd.append({"direction": q, "adjoint": got, "central_difference": ref,
-                       "rel_err": abs(got - ref) / max(abs(ref), 1e-300)})
-            print(f"# adjoint ring: direction {q} rel err {fd[-1]['rel_err']:.2e}", file=sys.stderr, flush=True)
+            diffs.append((Jpm[0] - Jpm[1]) / (2 * t))
+        ref = (4 * diffs[1] - diffs[0]) / 3
+        got = float(np.dot(gA, vA) + gU * vU)
+        fd.append({"direction": q, "adjoint": got, "central_difference": diffs, "richardson": ref,
+                   "rel_err": abs(got - ref) / max(abs(ref), 1e-300)})
+        print(f"# adjoint ring: direction {q} rel err {fd[-1]['rel_err']:.2e} (raw differences {diffs})",
+              file=sys.stderr, flush=True)
     nsl = g.nt - g.k
     return {"workload": f"8-site Hubbard ring, Peierls phase e^(iA(t)) on the hopping, second-Born + Hartree, "
                         f"U=1.5, beta=10, ntau=400, nt={g.nt}, h=0.02, k=5; gradient of E_kin(t_nt) w.r.t. the "
@@ -540,7 +544,7 @@ def main():
     ap.add_argument("--adj-ncorr", type=int, default=8,
                     help="corrector iterations of the ring's forward solves (the adjoint is that of the converged "
                          "fixed point)")
-    ap.add_argument("--adj-fd", type=int, default=1, help="central-difference check of the adjoint (0: off)")
+    ap.add_argument("--adj-fd", type=int, default=2, help="directions of the central-difference check of the adjoint (0: off)")
     ap.add_argument("--profile-step", type=int, default=0,
                     help="only run the time step at this slice (counter runs), then a 1 GiB copy")
     args = ap.parse_args()

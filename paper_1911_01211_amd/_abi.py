@@ -55,6 +55,10 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"HIP library {LIB_PATH} is not built; run __graft_entry__.build()")
+        # torch ships its own HIP runtime under the same soname as the
+        # system one; loading torch first makes the library bind to that
+        # copy, so both share one runtime (two in one process see no device)
+        import torch  # noqa: F401
         L = C.CDLL(LIB_PATH)
         vp, i32, dbl = C.c_void_p, C.c_int32, C.c_double
         P = C.POINTER
