@@ -37,7 +37,28 @@ struct HistPlan {
   int fuse_t;         // d = 1: job 1 also forms the job-5 row sums (no job-5 workgroups)
   long tail_off;      // in blocks
   long total_blocks;  // scratch blocks of the step
+  // d = 4: each stored panel (R, L, T) feeds its column and its row sums in
+  // one pass (workgroup units of 16 du_nsb slices x DU_TT positions, after
+  // the tau jobs' workgroups)
+  int dual;
+  int du_nsb;            // sub-tile rows of 16 slices per unit (1, 2, 4)
+  int du_ns;             // slice chunks (all panels)
+  int du_nt, du_ntau;    // position chunks of the triangular panels / of T
+  int du_np;             // triangular panels with units: 1 (R), 2 (R, L)
+  int du_full, du_part;  // units per triangular panel below the diagonal / meeting it
+  int du_total;          // units per problem
 };
+
+// d = 4 one-pass units: positions per unit and the chunk bounds of the units
+// of position chunk c of a triangular panel: slice chunks [lo, ns) meet the
+// stored triangle s >= t; those from cf on lie entirely below the diagonal.
+constexpr int DU_TT = 32;
+__host__ __device__ inline void du_range(int c, int TS, int ns, int& lo, int& cf) {
+  lo = (c * DU_TT) / TS;
+  cf = (c * DU_TT + DU_TT - 1 + TS - 1) / TS;
+  if (lo > ns) lo = ns;
+  if (cf > ns) cf = ns;
+}
 
 // event-based device timing of time steps (cntr_profile_begin/end)
 struct ProfRec {
@@ -68,7 +89,9 @@ bool tile_allowed(int d, int tj);
 int hist_tm(int d);
 // tau_split > 0: the tau source comes from k_tau_shared in tau_split chunks
 // (no history workgroups for it)
-HistPlan make_plan(int n, int k, int ntau, int d, int tau_split = 0);
+// du_nsb > 0 fixes the unit height of the d = 4 one-pass path (else chosen
+// from the number of units)
+HistPlan make_plan(int n, int k, int ntau, int d, int tau_split = 0, int du_nsb = 0);
 // scratch bytes (per problem) for the step at the largest n = nt
 size_t step_scratch_bytes(int nt, int k, int ntau, int d);
 

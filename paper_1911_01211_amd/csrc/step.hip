@@ -79,7 +79,23 @@ bool tile_allowed(int d, int tj) {
   return false;
 }
 
-HistPlan make_plan(int n, int k, int ntau, int d, int tau_split) {
+// d = 4 one-pass units of slice n with units of 16 nsb slices
+static int du_units(int n, int k, int ntau, int nsb) {
+  int TS = 16 * nsb, nb = n - k;
+  int ns = cdiv_i(n, TS), nt = cdiv_i(nb, DU_TT), ntt = cdiv_i(ntau + 1, DU_TT);
+  int tri = 0;
+  for (int c = 0; c < nt; c++) {
+    int lo, cf;
+    du_range(c, TS, ns, lo, cf);
+    tri += ns - lo;
+  }
+  return (n >= 2 * k + 1 ? 2 : 1) * tri + ns * ntt;
+}
+// the tallest units of which there are still about six per compute unit
+// (two run at once on each), so that the last ones finish close together
+constexpr int DU_TARGET = 1400;
+
+HistPlan make_plan(int n, int k, int ntau, int d, int tau_split, int du_nsb) {
   HistPlan p{};
   p.n = n;
   p.staged = hist_staged(d);
@@ -112,6 +128,23 @@ HistPlan make_plan(int n, int k, int ntau, int d, int tau_split) {
   // forms the job-5 row sums of each 64-column tile)
   p.fuse_t = d == 1;
   if (p.fuse_t) p.tj[5] = p.tj[4] = p.tj[7] = p.TM;
+  // d = 4: every panel is read once for both of its consumers; the column
+  // sums come in chunks of the unit height, the row sums in chunks of DU_TT
+  p.dual = d == 4;
+  if (p.dual) {
+    int nsb = du_nsb;
+    if (nsb <= 0) {
+      nsb = 1;
+      for (int c : {4, 2})
+        if (du_units(n, k, ntau, c) >= DU_TARGET) {
+          nsb = c;
+          break;
+        }
+    }
+    p.du_nsb = nsb;
+    p.tj[0] = p.tj[1] = p.tj[3] = 16 * nsb;
+    p.tj[4] = p.tj[5] = p.tj[7] = DU_TT;
+  }
   long off = 0;
   int wgs[NJOB];
   for (int j = 0; j < NJOB; j++) {
@@ -120,7 +153,8 @@ HistPlan make_plan(int n, int k, int ntau, int d, int tau_split) {
     p.mtiles[j] = mout[j] > 0 ? cdiv_i(mout[j], p.tm[j]) : 0;
     if (j == 6) p.nch[j] = p.mtiles[j] = 1;  // one workgroup: both tau ends
     if (j == 2 && tau_split > 0) p.nch[j] = tau_split;
-    bool none = (j == 2 && tau_split > 0) || ((j == 4 || j == 5 || j == 7) && p.fuse_t);  // formed elsewhere
+    bool none = (j == 2 && tau_split > 0) || ((j == 4 || j == 5 || j == 7) && p.fuse_t) ||
+                (p.dual && j != 2 && j != 6);  // formed elsewhere
     wgs[j] = none ? 0 : p.nch[j] * p.mtiles[j];
     p.part_off[j] = off;
     off += (long)p.nch[j] * mout[j];
@@ -146,7 +180,23 @@ HistPlan make_plan(int n, int k, int ntau, int d, int tau_split) {
   // Only the tiles on or below the diagonal of the triangular panels form
   // units, so that the eight XCDs get even shares.
   double hist_bytes = 16.0 * d * d * ((double)n * (n + 1) + (double)n * (ntau + 1));
-  p.banded = p.staged && les_bulk && hist_bytes > 160e6;
+  p.banded = p.staged && !p.dual && les_bulk && hist_bytes > 160e6;
+  if (p.dual) {
+    int TS = 16 * p.du_nsb;
+    p.du_ns = cdiv_i(n, TS);
+    p.du_nt = cdiv_i(nb, DU_TT);
+    p.du_ntau = cdiv_i(ntau + 1, DU_TT);
+    p.du_np = les_bulk ? 2 : 1;
+    p.du_full = p.du_part = 0;
+    for (int c = 0; c < p.du_nt; c++) {
+      int lo, cf;
+      du_range(c, TS, p.du_ns, lo, cf);
+      p.du_full += p.du_ns - cf;
+      p.du_part += cf - lo;
+    }
+    p.du_total = p.du_np * (p.du_full + p.du_part) + p.du_ns * p.du_ntau;
+    p.grid += p.du_total;
+  }
   if (p.banded) {
     p.nband = p.nch[0];
     p.bo[0] = p.mtiles[0];  // column tiles of the retarded and lesser panels
@@ -182,11 +232,13 @@ size_t step_scratch_bytes(int nt, int k, int ntau, int d) {
   }
   for (int n : ns) {
     if (n <= k) continue;
-    for (int ts : {0, TS_SPLIT}) {
-      HistPlan p = make_plan(n, k, ntau, d, d == 1 ? ts : 0);
-      size_t blocks = (size_t)p.total_blocks;
-      if (blocks > mx) mx = blocks;
-    }
+    for (int ts : {0, TS_SPLIT})
+      for (int nsb : {1, 2, 4}) {  // (every unit height the d = 4 path may choose)
+        if (d != 4 && nsb > 1) continue;
+        HistPlan p = make_plan(n, k, ntau, d, d == 1 ? ts : 0, nsb);
+        size_t blocks = (size_t)p.total_blocks;
+        if (blocks > mx) mx = blocks;
+      }
   }
   return mx * d * d * sizeof(cplx);
 }
@@ -1247,6 +1299,298 @@ __device__ void tau_stg(const Prob& P, const Scratch& sc, int pi, int n, const H
   stg_sum_store<D>(acc, lds, false, m0, ntau + 1, sc.part(pi) + (pl.part_off[2] + (long)ch * (ntau + 1)) * DD);
 }
 
+// ------------------------------------- HISTORY, d = 4: one pass per panel
+// Each stored panel feeds two sums of slice n: column sums (an output per
+// position t, terms over the stored slices s) and row sums (an output per
+// slice s, terms over the positions t):
+//   R = G^R_{s,t} (t <= s):   column  w(n-t, s-t) S^R_{n,s} R_{s,t}           job 0
+//                             row     w(s, t) R_{s,t} S^<_{t,n}               job 4
+//                                     (starting weights s_{s,t} for s <= k)
+//   L (block (s, t), t <= s): column  w(n, s) L_{s,t} (S^R_{n,s})^dag          job 3
+//                             row     -(w(n, t) S^R_{n,t} L_{s,t})^dag, t < s  job 7
+//   T = G^rceil_{s,tau}:      column  w(n, s) S^R_{n,s} T_{s,tau}             job 1
+//                             row     (-xi) w(ntau, tau) T_{s,tau} (S^rceil_{n,ntau-tau})^dag
+//                                                                             job 5
+// (the terms of Eqs. for the retarded, left-mixing and lesser components
+// written as column and row sums of the stored panels; the lesser row sums
+// of job 4 with t in (s, k] for s < k come from the reduction kernel).
+// A workgroup takes a unit of 16 nsb slices x DU_TT positions and walks its
+// sub-tiles of 16 x 16 blocks (64 KB): while one sub-tile, staged in LDS,
+// feeds both sums, the next one is loaded into registers. In a column step
+// a wave takes one slice s of the sub-tile and its lane (t, p) column (or
+// row) p of block (s, t); in a row step one position t and lane (s, p). The
+// Sigma blocks of the sub-tile's slices and positions are staged with it;
+// those of a step are the same for the whole wave (broadcast LDS reads).
+// (Scalar loads would serialize: every wait on them drains all that are in
+// flight.) The column sums over the unit's slices are written once per
+// unit, the row sums over its positions once per sub-tile row: the partials
+// of the per-job path's jobs, in column chunks of 16 nsb slices and row
+// chunks of DU_TT positions.
+constexpr int DU_BS = 17;              // LDS units (16 B) per staged block, one of padding
+constexpr int DU_SS = 16 * DU_BS + 1;  // LDS units per staged slice
+constexpr int DU_DAT = 16 * DU_SS;     // one staged sub-tile
+constexpr int DU_LDS = DU_DAT + 512;   // and its 32 Sigma blocks
+
+template <int PANEL>
+__device__ __forceinline__ void hist_dual_panel(const Prob& P, const Scratch& sc, int pi, int n, const HistPlan& pl,
+                                                int cs, int ct, cplx* lds, const double* s_om, const double* s_s) {
+  constexpr int DD = 16, K1 = KMAX + 1;
+  constexpr bool TRI = PANEL != 2;
+  constexpr bool LEFT_COL = PANEL != 1;   // column sums S X (else X S^dag)
+  constexpr bool RIGHT_ROW = PANEL != 1;  // row sums X S or X S^dag (else S X)
+  constexpr int JC = PANEL == 0 ? 0 : (PANEL == 1 ? 3 : 1);
+  constexpr int JR = PANEL == 0 ? 4 : (PANEL == 1 ? 7 : 5);
+  const int k = P.k, ntau = P.ntau, NT1 = ntau + 1, tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int o = lane & 15, p = lane >> 4;
+  const double xi = P.sig;
+  const int nb = n - k, TS = 16 * pl.du_nsb, nq = 2 * pl.du_nsb;
+  const int tlim = TRI ? nb : NT1;
+  const int mcol = pl.mout[JC], mrow = pl.mout[JR];
+  const cplx* X = PANEL == 0 ? P.Gret : (PANEL == 1 ? P.Gles : P.Gtv);
+  const cplx* Fc = P.Sret + tri(n) * DD;  // S^R_{n,s}
+  const cplx* Fr = PANEL == 0 ? P.Sles + tri(n) * DD : (PANEL == 1 ? P.Sret + tri(n) * DD : P.Stv + (size_t)n * NT1 * DD);
+  cplx* pcol = sc.part(pi) + (pl.part_off[JC] + (long)cs * mcol) * DD;
+  cplx* prow = sc.part(pi) + (pl.part_off[JR] + (long)ct * mrow) * DD;
+  const int sbase = cs * TS, tbase = ct * DU_TT;
+  auto gw = [&](int N, int j) -> double {
+    bool left = j <= k, right = N - j <= k;
+    double wl = s_om[left ? j : 0], wr = s_om[right ? N - j : 0];
+    return left ? (right ? wl + wr - 1.0 : wl) : (right ? wr : 1.0);
+  };
+  // sub-tile q: slices sbase + 16 (q >> 1) + 0..15, positions tbase + 16 (q & 1) + 0..15
+  auto valid = [&](int q) {
+    int s0 = sbase + 16 * (q >> 1), t0 = tbase + 16 * (q & 1);
+    return s0 < n && t0 < tlim && (!TRI || t0 <= s0 + 15);
+  };
+  auto next_valid = [&](int q) {
+    for (q++; q < nq; q++)
+      if (valid(q)) return q;
+    return -1;
+  };
+  // wave w loads slices 4w..4w+3 of a sub-tile, each in four 1 KB pieces;
+  // blocks outside the stored panel are read at a stored position (their
+  // weights are zero)
+  // and the Sigma blocks: 16 of the column sums (slices), 16 of the row sums
+  // (positions), two values per thread
+  cntr_v2d pre[16], pref[2];
+  auto load = [&](int q) {
+    int s0 = sbase + 16 * (q >> 1), t0 = tbase + 16 * (q & 1);
+#pragma unroll
+    for (int i = 0; i < 16; i++) {
+      int sl = 4 * wave + (i >> 2), tl = 4 * (i & 3) + (lane >> 4), e = lane & 15;
+      int s = min(s0 + sl, n - 1), t = t0 + tl;
+      size_t bi = TRI ? tri(s) + min(t, s) : (size_t)s * NT1 + min(t, ntau);
+      pre[i] = *(const CNTR_GLOBAL cntr_v2d*)(X + bi * DD + e);
+    }
+#pragma unroll
+    for (int j = 0; j < 2; j++) {
+      int f = 2 * tid + j, fb = f >> 4, e = f & 15;
+      const cplx* src;
+      if (fb < 16) {
+        src = Fc + (size_t)min(s0 + fb, n - 1) * DD;
+      } else {
+        int tc = min(t0 + fb - 16, tlim - 1);
+        src = Fr + (size_t)(PANEL == 2 ? ntau - tc : tc) * DD;
+      }
+      pref[j] = *(const CNTR_GLOBAL cntr_v2d*)(src + e);
+    }
+  };
+  CNTR_LDS cntr_v2d* lv = (CNTR_LDS cntr_v2d*)lds;
+  auto store = [&]() {
+#pragma unroll
+    for (int i = 0; i < 16; i++) {
+      int sl = 4 * wave + (i >> 2), tl = 4 * (i & 3) + (lane >> 4), e = lane & 15;
+      lv[sl * DU_SS + tl * DU_BS + e] = pre[i];
+    }
+#pragma unroll
+    for (int j = 0; j < 2; j++) lv[DU_DAT + 2 * tid + j] = pref[j];
+  };
+  auto lget = [&](int idx) {
+    cntr_v2d t = lv[idx];
+    return cplx{t.x, t.y};
+  };
+  cplx ca[4], cb[4], ra[4];  // column sums of this position half / of the other; row sums
+#pragma unroll
+  for (int r = 0; r < 4; r++) ca[r] = cb[r] = ra[r] = mk(0, 0);
+
+  // One step: the lane's four values of its block and the step's Sigma block
+  // are all read from LDS before any product (the reads stay in flight
+  // together; a scheduling barrier keeps the compiler from interleaving them
+  // with the products, which would leave one or two reads in flight).
+  // column step i of the wave on sub-tile (s0, t0): slice s0 + 4 wave + i
+  auto col_step = [&](int s0, int t0, int i) {
+    int sl = 4 * wave + i, s = s0 + sl, t = t0 + o;
+    bool ok = s < n && t < mcol && (!TRI || s >= t);
+    int F = DU_DAT + sl * DD;  // staged S^R_{n,s}
+    int b = sl * DU_SS + o * DU_BS;
+    cplx v[4], f[16];
+#pragma unroll
+    for (int q = 0; q < 4; q++) v[q] = lget(LEFT_COL ? b + 4 * q + p : b + 4 * p + q);
+#pragma unroll
+    for (int x = 0; x < 16; x++) f[x] = lget(F + x);
+    double w = 0.0;
+    if (ok) w = PANEL == 0 ? gw(n - t, s - t) : gw(n, s);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int q = 0; q < 4; q++) v[q] = w * v[q];
+#pragma unroll
+    for (int r = 0; r < 4; r++)
+#pragma unroll
+      for (int q = 0; q < 4; q++) {
+        if constexpr (LEFT_COL) cfma(ca[r], f[4 * r + q], v[q]);  // ca[r] = (S X)[r][p]
+        else cfma_cb(ca[r], v[q], f[4 * r + q]);                 // ca[r] = (X S^dag)[p][r]
+      }
+  };
+  // row step i of the wave on sub-tile (s0, t0): position t0 + 4 wave + i
+  auto row_step = [&](int s0, int t0, int i) {
+    int tl = 4 * wave + i, t = t0 + tl, s = s0 + o;
+    bool ok = s < mrow && t < tlim && (PANEL == 0 ? t <= s : (PANEL == 1 ? t < s : true));
+    int E = DU_DAT + (16 + tl) * DD;  // staged Sigma block of position t
+    int b = o * DU_SS + tl * DU_BS;
+    cplx v[4], f[16];
+#pragma unroll
+    for (int q = 0; q < 4; q++) v[q] = lget(RIGHT_ROW ? b + 4 * p + q : b + 4 * q + p);
+#pragma unroll
+    for (int x = 0; x < 16; x++) f[x] = lget(E + x);
+    double w = 0.0;
+    if (ok) {
+      if (PANEL == 0) w = s > k ? gw(s, t) : s_s[s * K1 + t];
+      else if (PANEL == 1) w = gw(n, t);
+      else w = -xi * gw(ntau, t);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int q = 0; q < 4; q++) v[q] = w * v[q];
+#pragma unroll
+    for (int r = 0; r < 4; r++)
+#pragma unroll
+      for (int q = 0; q < 4; q++) {
+        if constexpr (PANEL == 0) cfma(ra[r], v[q], f[4 * q + r]);     // ra[r] = (X E)[p][r]
+        else if constexpr (PANEL == 2) cfma_cb(ra[r], v[q], f[4 * r + q]);  // (X E^dag)[p][r]
+        else cfma(ra[r], f[4 * r + q], v[q]);                         // ra[r] = (E X)[r][p]
+      }
+  };
+  CNTR_LDS cntr_v2d* red = lv;  // the staging buffer, when free
+  auto put = [&](int idx, cplx v) { red[idx] = cntr_v2d{v.x, v.y}; };
+  auto get = [&](int idx) {
+    cntr_v2d t = red[idx];
+    return cplx{t.x, t.y};
+  };
+  // the four waves' row sums of slices s0..s0+15 (fixed order) to the partials
+  auto row_flush = [&](int s0) {
+#pragma unroll
+    for (int r = 0; r < 4; r++) put((wave * 4 + r) * 64 + lane, ra[r]);
+    __syncthreads();
+    int oo = tid >> 4, e = tid & 15, L = (e >> 2) * 16 + oo, rr = e & 3;
+    cplx sum = ((get(rr * 64 + L) + get((4 + rr) * 64 + L)) + get((8 + rr) * 64 + L)) + get((12 + rr) * 64 + L);
+    if (PANEL == 1) sum = -conj(sum);
+    int s = s0 + oo;
+    if (s < mrow) gst(prow + (size_t)s * DD + e, sum);
+    __syncthreads();
+  };
+
+  int cur = valid(0) ? 0 : next_valid(0);
+  int half = cur >= 0 ? (cur & 1) : 0;  // position half of ca
+  if (cur >= 0) {
+    load(cur);
+    store();
+  }
+  __syncthreads();
+  while (cur >= 0) {
+    int nxt = next_valid(cur);
+    if (nxt >= 0) load(nxt);
+    int s0 = sbase + 16 * (cur >> 1), t0 = tbase + 16 * (cur & 1);
+#pragma unroll 1
+    for (int i = 0; i < 4; i++) col_step(s0, t0, i);
+#pragma unroll 1
+    for (int i = 0; i < 4; i++) row_step(s0, t0, i);
+    __syncthreads();
+    if (nxt < 0 || (nxt >> 1) != (cur >> 1)) {
+      row_flush(s0);
+#pragma unroll
+      for (int r = 0; r < 4; r++) ra[r] = mk(0, 0);
+    }
+    if (nxt >= 0) {
+      store();
+      if ((nxt & 1) != half) {
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+          cplx t = ca[r];
+          ca[r] = cb[r];
+          cb[r] = t;
+        }
+        half = nxt & 1;
+      }
+    }
+    __syncthreads();
+    cur = nxt;
+  }
+  // column sums of the unit's 32 positions (the four waves' in a fixed order)
+#pragma unroll
+  for (int r = 0; r < 4; r++) {
+    put(((wave * 2 + 0) * 4 + r) * 64 + lane, ca[r]);
+    put(((wave * 2 + 1) * 4 + r) * 64 + lane, cb[r]);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int h2 = 0; h2 < 2; h2++) {
+    int v = tid + 256 * h2, h = v >> 8, oo = (v >> 4) & 15, e = v & 15;
+    int pp = LEFT_COL ? (e & 3) : (e >> 2), rr = LEFT_COL ? (e >> 2) : (e & 3), L = pp * 16 + oo;
+    cplx sum = mk(0, 0);
+#pragma unroll
+    for (int w = 0; w < 4; w++) sum = sum + get(((w * 2 + h) * 4 + rr) * 64 + L);
+    int t = tbase + 16 * (h == 0 ? half : 1 - half) + oo;
+    if (t < mcol) gst(pcol + (size_t)t * DD + e, sum);
+  }
+}
+
+// unit u: the units below the diagonal of the triangular panels (R and L
+// alternating), the mixing panel's, then the triangular units that meet the
+// diagonal (fewer blocks), so that the short units come last
+template <int D>
+__device__ void hist_dual(const Prob& P, const Scratch& sc, int pi, int n, const HistPlan& pl, int u, cplx* lds) {
+  constexpr int K1 = KMAX + 1;
+  __shared__ double s_om[K1];
+  __shared__ double s_s[K1 * K1];
+  const KW& W = c_kw[P.k];
+  int tid = threadIdx.x;
+  if (tid <= KMAX) s_om[tid] = W.omega[tid];
+  if (tid < K1 * K1) s_s[tid] = W.s[tid / K1][tid % K1];
+  // (published by the first barrier of the panel walk)
+  int TS = 16 * pl.du_nsb, np = pl.du_np;
+  int nfull = np * pl.du_full, ntt = pl.du_ns * pl.du_ntau;
+  int panel = 2, cs = 0, ct = 0;
+  auto tri_unit = [&](int v, bool full) {
+    for (int c = 0; c < pl.du_nt; c++) {
+      int lo, cf;
+      du_range(c, TS, pl.du_ns, lo, cf);
+      int a = full ? cf : lo, b = full ? pl.du_ns : cf;
+      if (v < b - a) {
+        ct = c;
+        cs = b - 1 - v;
+        return;
+      }
+      v -= b - a;
+    }
+  };
+  if (u < nfull) {
+    panel = np == 2 ? (u & 1) : 0;
+    tri_unit(u / np, true);
+  } else if (u < nfull + ntt) {
+    int v = u - nfull;
+    cs = pl.du_ns - 1 - v / pl.du_ntau;
+    ct = v % pl.du_ntau;
+  } else {
+    int v = u - nfull - ntt;
+    panel = np == 2 ? (v & 1) : 0;
+    tri_unit(v / np, false);
+  }
+  if (panel == 0) hist_dual_panel<0>(P, sc, pi, n, pl, cs, ct, lds, s_om, s_s);
+  else if (panel == 1) hist_dual_panel<1>(P, sc, pi, n, pl, cs, ct, lds, s_om, s_s);
+  else hist_dual_panel<2>(P, sc, pi, n, pl, cs, ct, lds, s_om, s_s);
+}
+
 // ------------------------------------------- HISTORY, d = 8 on FP64 MFMA
 // The d = 8 history sums are dense 8 x 8 complex block products; each is a
 // real 16 x 16 x 16 product on v_mfma_f64_16x16x4f64 (four instructions)
@@ -1588,11 +1932,14 @@ __global__ __launch_bounds__(NTHR) void k_history(ProbArg pa, Scratch sc, HistPl
   constexpr int LDSR1 = D <= 4 && LDSB1 > LDSR0 ? LDSB1 : LDSR0;  // operands of the block-per-lane path
   constexpr int LDSR = STG ? 4 * Stg<D>::WBUF : LDSR1;              // staged path buffers
   constexpr int LDS8 = MF8_TJ * DD > 2 * MF8_TAU_TJ * DD + 8 * DD ? MF8_TJ * DD : 2 * MF8_TAU_TJ * DD + 8 * DD;
-  constexpr int LDSN = D == 8 ? LDS8 : (STG ? (PREPN > LDSR ? PREPN : LDSR) : (LDSB > LDSR ? LDSB : LDSR));
+  constexpr int LDSS = PREPN > LDSR ? PREPN : LDSR;
+  constexpr int LDSN = D == 8 ? LDS8 : (STG ? (D == 4 && DU_LDS > LDSS ? DU_LDS : LDSS) : (LDSB > LDSR ? LDSB : LDSR));
   __shared__ cplx lds[LDSN];
   // shared operand of a staged chunk (a separate array: its reads never wait
   // for the copies in flight into lds)
-  __shared__ cplx shop[STG ? STG_TJ * DD : 1];
+  __shared__ cplx shop[STG && D != 4 ? STG_TJ * DD : 1];
+  // (d = 4: the tau jobs' shared operands go to the one-pass kernel's Sigma area)
+  cplx* shp = D == 4 ? lds + DU_DAT : shop;
   int pi = blockIdx.y;
   const Prob& P = pa.get(pi);
   int n = pl.n;
@@ -1603,6 +1950,12 @@ __global__ __launch_bounds__(NTHR) void k_history(ProbArg pa, Scratch sc, HistPl
     // (d = 8: the set-up has a kernel of its own, k_prep, launched before)
     if constexpr (D != 8) prep_step<D>(P, sc, pi, n, lds);
     return;
+  }
+  if constexpr (D == 4) {  // (one-pass units after the tau jobs)
+    if (b >= pl.wg_off[NJOB]) {
+      hist_dual<D>(P, sc, pi, n, pl, b - pl.wg_off[NJOB], lds);
+      return;
+    }
   }
   int job = 0, mt, ch;
   if (pl.banded) {
@@ -1652,8 +2005,8 @@ __global__ __launch_bounds__(NTHR) void k_history(ProbArg pa, Scratch sc, HistPl
     return;
   }
   if constexpr (STG) {
-    if (job == 2) tau_stg<D>(P, sc, pi, n, pl, mt, ch, lds, shop);
-    else hist_stg<D>(P, sc, pi, n, pl, job, mt, ch, lds, shop);
+    if (job == 2) tau_stg<D>(P, sc, pi, n, pl, mt, ch, lds, shp);
+    else if constexpr (D != 4) hist_stg<D>(P, sc, pi, n, pl, job, mt, ch, lds, shop);
     return;
   } else if constexpr (D <= 4) {
     if (job == 2) {
@@ -2042,7 +2395,7 @@ __global__ __launch_bounds__(NTHR) void k_reduce(ProbArg pa, Scratch sc, HistPla
       int cn[4] = {pl.nch[3] - c3, n7, jmax / pl.tj[4] + 1, pl.nch[5]};
       cplx sm[4];
       msum<4, MSB>(ps, cn, cs, sm);
-      if (pl.fuse_t && m < k) {
+      if ((pl.fuse_t || pl.dual) && m < k) {
         // terms j in (m, k] of C^<_1 (start-up weights), R~_{m,j} = -(R_{j,m})^dag
         cplx cr = mk(0, 0);
         for (int j = m + 1; j <= k; j++) {
