@@ -1311,9 +1311,10 @@ __device__ void tau_stg(const Prob& P, const Scratch& sc, int pi, int n, const H
 //   T = G^rceil_{s,tau}:      column  w(n, s) S^R_{n,s} T_{s,tau}             job 1
 //                             row     (-xi) w(ntau, tau) T_{s,tau} (S^rceil_{n,ntau-tau})^dag
 //                                                                             job 5
-// (the terms of Eqs. for the retarded, left-mixing and lesser components
-// written as column and row sums of the stored panels; the lesser row sums
-// of job 4 with t in (s, k] for s < k come from the reduction kernel).
+// (the history integrals of the retarded, left-mixing and lesser equations
+// of the time step written as column and row sums of the stored panels;
+// the row sums of R for s < k also take the terms t in (s, k], from the
+// stored blocks (t, s)).
 // A workgroup takes a unit of 16 nsb slices x DU_TT positions and walks its
 // sub-tiles of 16 x 16 blocks (64 KB): while one sub-tile, staged in LDS,
 // feeds both sums, the next one is loaded into registers. In a column step
@@ -1448,9 +1449,20 @@ __device__ __forceinline__ void hist_dual_panel(const Prob& P, const Scratch& sc
     bool ok = s < mrow && t < tlim && (PANEL == 0 ? t <= s : (PANEL == 1 ? t < s : true));
     int E = DU_DAT + (16 + tl) * DD;  // staged Sigma block of position t
     int b = o * DU_SS + tl * DU_BS;
+    // R, first rows s < k: the terms t in (s, k] take -(R_{t,s})^dag, the
+    // stored block (t, s) of the same (first) sub-tile, with the starting
+    // weights s_{s,t}
+    bool trn = PANEL == 0 && s0 == 0 && t0 == 0 && t <= k;  // (uniform)
+    bool tl_ = trn && s < t && s < mrow;
     cplx v[4], f[16];
 #pragma unroll
     for (int q = 0; q < 4; q++) v[q] = lget(RIGHT_ROW ? b + 4 * p + q : b + 4 * q + p);
+    if (trn) {
+      int bt = tl * DU_SS + o * DU_BS;  // block (t, s): slice t, position s
+#pragma unroll
+      for (int q = 0; q < 4; q++)
+        if (tl_) v[q] = -conj(lget(bt + 4 * q + p));
+    }
 #pragma unroll
     for (int x = 0; x < 16; x++) f[x] = lget(E + x);
     double w = 0.0;
@@ -1459,6 +1471,7 @@ __device__ __forceinline__ void hist_dual_panel(const Prob& P, const Scratch& sc
       else if (PANEL == 1) w = gw(n, t);
       else w = -xi * gw(ntau, t);
     }
+    if (tl_) w = s_s[s * K1 + t];
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int q = 0; q < 4; q++) v[q] = w * v[q];
@@ -2199,6 +2212,7 @@ __global__ __launch_bounds__(NTHR) void k_prep(ProbArg pa, Scratch sc, int n) {
 // Sum of cnt values p[i * stride] (in a fixed order), B loads in flight.
 template <int B>
 __device__ inline cplx psum_b(const cplx* p, long stride, int cnt) {
+  static_assert((B & (B - 1)) == 0, "pairwise sum over a power of two");
   cplx s[B];
 #pragma unroll
   for (int u = 0; u < B; u++) s[u] = mk(0, 0);
@@ -2395,7 +2409,7 @@ __global__ __launch_bounds__(NTHR) void k_reduce(ProbArg pa, Scratch sc, HistPla
       int cn[4] = {pl.nch[3] - c3, n7, jmax / pl.tj[4] + 1, pl.nch[5]};
       cplx sm[4];
       msum<4, MSB>(ps, cn, cs, sm);
-      if ((pl.fuse_t || pl.dual) && m < k) {
+      if (pl.fuse_t && m < k) {
         // terms j in (m, k] of C^<_1 (start-up weights), R~_{m,j} = -(R_{j,m})^dag
         cplx cr = mk(0, 0);
         for (int j = m + 1; j <= k; j++) {
@@ -2560,12 +2574,24 @@ __global__ __launch_bounds__(NTHR) void k_reduce(ProbArg pa, Scratch sc, HistPla
     int idx = tid + u * NTHR;
     if (idx < k * DD) vl[u] = gld(P.Gles + (tri(n) + n - 2 * k + idx / DD) * DD + idx % DD);
   }
+  // (the retarded boundary sources of d <= 4 are loaded in the same round)
+  constexpr int NSB = (NVMAX + NTHR - 1) / NTHR;
+  cplx vb[NSB];
+#pragma unroll
+  for (int u = 0; u < NSB; u++) {
+    int idx = tid + u * NTHR;
+    if (D <= 4 && idx < NV) vb[u] = gld(sc.bsrc(pi, DD) + idx);
+  }
   int G = NV >= NTHR ? 1 : NTHR / NV;
   for (int vv = tid; vv < G * NV; vv += NTHR) {
     int g = vv / NV, v = vv % NV;
-    // workgroups g, g+G, g+2G, ... of value v
-    stage[vv] = psum_b<16>(tpart + (size_t)g * NV + v, (long)G * NV, g < nwg ? (nwg - g + G - 1) / G : 0);
+    // workgroups g, g+G, g+2G, ... of value v (32 loads in flight: fewer
+    // memory rounds over the tiles)
+    stage[vv] = psum_b<32>(tpart + (size_t)g * NV + v, (long)G * NV, g < nwg ? (nwg - g + G - 1) / G : 0);
   }
+#pragma unroll
+  for (int u = 0; u < NSB; u++)
+    if (D <= 4 && tid + u * NTHR < NV) pre[tid + u * NTHR] = vb[u];
 #pragma unroll
   for (int u = 0; u < NSZ; u++)
     if (!walk && tid + u * NTHR < nz * DD) zl[tid + u * NTHR] = vz[u];
@@ -2580,7 +2606,7 @@ __global__ __launch_bounds__(NTHR) void k_reduce(ProbArg pa, Scratch sc, HistPla
     for (int g = 0; g < G; g++) s = s + stage[g * NV + v];
     if constexpr (D <= 4) {
       // the retarded boundary columns j = n-k..n were summed by the step set-up
-      pre[v] = s + gld(sc.bsrc(pi, DD) + v);
+      pre[v] = s + pre[v];
     } else {
       cplx pb = mk(0, 0);
 #pragma unroll
