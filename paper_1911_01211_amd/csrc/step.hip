@@ -2238,24 +2238,33 @@ __device__ inline cplx psum_b(const cplx* p, long stride, int cnt) {
   return s[0];
 }
 
-// Sums of NS sequences p[s][i * stride], i < cnt[s]: the first B terms of
-// every sequence are loaded together (one memory round when all counts are
-// <= B), longer tails follow with psum_b. Fixed summation order.
+// Sums of NS sequences p[s][i * stride], i < cnt[s], in rounds of B terms of
+// every sequence loaded together: a round's loads are all in flight at once,
+// so the sums take ceil(max cnt / B) memory rounds (not one per sequence and
+// tail). Fixed summation order.
 template <int NS, int B>
 __device__ inline void msum(const cplx* const (&p)[NS], const int (&cnt)[NS], long stride, cplx (&out)[NS]) {
-  cplx v[NS][B];
-#pragma unroll
-  for (int q = 0; q < NS; q++)
-#pragma unroll
-    for (int u = 0; u < B; u++) v[q][u] = u < cnt[q] ? gld(p[q] + (long)u * stride) : mk(0, 0);
+  static_assert((B & (B - 1)) == 0, "pairwise sum over a power of two");
+  int mx = 0;
 #pragma unroll
   for (int q = 0; q < NS; q++) {
+    out[q] = mk(0, 0);
+    mx = cnt[q] > mx ? cnt[q] : mx;
+  }
+  for (int i0 = 0; i0 < mx; i0 += B) {
+    cplx v[NS][B];
 #pragma unroll
-    for (int w = B / 2; w >= 1; w /= 2)
+    for (int q = 0; q < NS; q++)
 #pragma unroll
-      for (int u = 0; u < w; u++) v[q][u] = v[q][u] + v[q][u + w];
-    out[q] = v[q][0];
-    if (cnt[q] > B) out[q] = out[q] + psum_b<B>(p[q] + B * stride, stride, cnt[q] - B);
+      for (int u = 0; u < B; u++) v[q][u] = i0 + u < cnt[q] ? gld(p[q] + (long)(i0 + u) * stride) : mk(0, 0);
+#pragma unroll
+    for (int q = 0; q < NS; q++) {
+#pragma unroll
+      for (int w = B / 2; w >= 1; w /= 2)
+#pragma unroll
+        for (int u = 0; u < w; u++) v[q][u] = v[q][u] + v[q][u + w];
+      out[q] = out[q] + v[q][0];
+    }
   }
 }
 
