@@ -1908,6 +1908,152 @@ __global__ void __launch_bounds__(ADJ_NT) k_adj_sigma_blk(const AdjProb* ap, int
     o[tid] = o[tid] + v;
   }
 }
+// The same reductions for d >= 5: a d x d block term does not fit a thread's
+// registers, so the output block is split into four sub-blocks of
+// SB = ceil(d / 2) rows and columns; thread (sub-block, lane) accumulates its
+// sub-block over the terms lane, lane + 64, ... (per term it loads SB rows
+// or columns of each factor: a quarter of the element-per-thread loads),
+// and the 64 lane sums of each element are added in a fixed order.
+// acc += f X Y^H (AHB false) or acc += f X^H Y (AHB true) on the sub-block
+// at (r0, c0); X(a, b), Y(a, b) give block elements.
+template <int D, int SB, bool AHB, class XA, class YA>
+__device__ inline void sub_term(cplx (&acc)[SB * SB], cplx f, int r0, int c0, XA X, YA Y) {
+#pragma unroll
+  for (int q = 0; q < D; q++) {
+    cplx xs[SB], ys[SB];
+#pragma unroll
+    for (int i = 0; i < SB; i++) {
+      int r = r0 + i;
+      xs[i] = r < D ? f * (AHB ? conj(X(q, r)) : X(r, q)) : mk(0, 0);
+    }
+#pragma unroll
+    for (int j = 0; j < SB; j++) {
+      int c = c0 + j;
+      ys[j] = c < D ? (AHB ? Y(q, c) : conj(Y(c, q))) : mk(0, 0);
+    }
+#pragma unroll
+    for (int i = 0; i < SB; i++)
+#pragma unroll
+      for (int j = 0; j < SB; j++) cfma(acc[i * SB + j], xs[i], ys[j]);
+  }
+}
+// element accessors of a stored block and of the conjugate transpose of one
+// (-(P_{b,a})^dag: the continued R~ and L^ blocks)
+template <int D>
+struct BlkA {
+  const cplx* p;
+  bool tr;
+  __device__ inline cplx operator()(int a, int b) const { return tr ? -conj(p[b * D + a]) : p[a * D + b]; }
+};
+// term t of output block ob on the thread's sub-block (the terms of sig_term_blk)
+template <int D, int SB>
+__device__ inline void sig_term_sub(const AdjView& V, int n, int ob, int t, int r0, int c0, cplx (&acc)[SB * SB]) {
+  constexpr int DD = D * D;
+  SigGeom G = sig_geom(n, V.k, V.ntau);
+  int k = V.k, ntau = V.ntau, nb = n - k;
+  double h = V.h;
+  const cplx* rL = V.scr(V.lay.rhoL);
+  const cplx* rT = V.scr(V.lay.rhoT);
+  const cplx* rR = V.scr(V.lay.rhoR);
+  if (ob < G.nR) {
+    int j = ob, na = (j < nb - 1 ? j : nb - 1) + 1;
+    if (t < na) {
+      int m = t;
+      sub_term<D, SB, false>(acc, mk(0, h * adj_w(V.W, n - m, j - m)), r0, c0, BlkA<D>{rR + (size_t)m * DD, false},
+                             BlkA<D>{V.GR(j, m), false});
+      return;
+    }
+    t -= na;
+    if (t <= ntau) {
+      sub_term<D, SB, false>(acc, mk(0, h * adj_w(V.W, n, j)), r0, c0, BlkA<D>{rT + (size_t)t * DD, false},
+                             BlkA<D>{V.GT(j, t), false});
+      return;
+    }
+    int m = t - (ntau + 1);
+    BlkA<D> Y = m <= j ? BlkA<D>{V.GL(m, j), false} : BlkA<D>{V.GL(j, m), true};
+    sub_term<D, SB, true>(acc, mk(0, h * adj_w(V.W, n, j)), r0, c0, BlkA<D>{rL + (size_t)m * DD, false}, Y);
+    return;
+  }
+  if (ob < G.nR + G.nL) {
+    int j = ob - G.nR;
+    int na = j <= k ? (k < nb - 1 ? k : nb - 1) + 1 : 0;
+    int m;
+    double wt;
+    if (t < na) {
+      m = t;
+      wt = V.W.s[m][j];
+    } else {
+      m = (j > k + 1 ? j : k + 1) + (t - na);
+      wt = adj_w(V.W, m, j);
+    }
+    BlkA<D> X = m >= j ? BlkA<D>{V.GR(m, j), false} : BlkA<D>{V.GR(j, m), true};
+    sub_term<D, SB, true>(acc, mk(0, -(h * wt)), r0, c0, X, BlkA<D>{rL + (size_t)m * DD, false});
+    return;
+  }
+  int tau = ob - G.nR - G.nL, m = t, j = ntau - tau;
+  sub_term<D, SB, true>(acc, mk(-V.xi * V.ht * adj_w(V.W, ntau, j), 0), r0, c0, BlkA<D>{rL + (size_t)m * DD, false},
+                        BlkA<D>{V.GT(m, j), false});
+}
+// the 64 lanes' sums of the four sub-blocks, added in a fixed order, onto o
+template <int D, int SB, int NL>
+__device__ inline void sub_flush(cplx (&acc)[SB * SB], cplx* red, cplx* o) {
+  int tid = threadIdx.x, sb = tid & 3, lane = tid >> 2;
+#pragma unroll
+  for (int e = 0; e < SB * SB; e++) red[(sb * NL + lane) * SB * SB + e] = acc[e];
+  __syncthreads();
+  if (tid < D * D) {
+    int r = tid / D, c = tid % D, s2 = (r / SB) * 2 + c / SB, e = (r % SB) * SB + c % SB;
+    cplx v = mk(0, 0);
+    for (int l = 0; l < NL; l++) v = v + red[(s2 * NL + l) * SB * SB + e];
+    o[tid] = o[tid] + v;
+  }
+}
+template <int D>
+__global__ void __launch_bounds__(ADJ_NT) k_adj_sigma_sub(const AdjProb* ap, int n) {
+  constexpr int SB = (D + 1) / 2, NL = ADJ_NT / 4;
+  __shared__ cplx red[4 * NL * SB * SB];
+  const AdjProb& A = ap[blockIdx.y];
+  if (n > A.p.nt) return;
+  AdjView V(A, c_kw[A.p.k]);
+  int ob = blockIdx.x;
+  if (ob >= sig_geom(n, V.k, V.ntau).total) return;
+  int tid = threadIdx.x, sb = tid & 3, lane = tid >> 2;
+  int r0 = (sb >> 1) * SB, c0 = (sb & 1) * SB;
+  cplx acc[SB * SB];
+#pragma unroll
+  for (int e = 0; e < SB * SB; e++) acc[e] = mk(0, 0);
+  int nt = sig_nterms(V, n, ob);
+  for (int t = lane; t < nt; t += NL) sig_term_sub<D, SB>(V, n, ob, t, r0, c0, acc);
+  sub_flush<D, SB, NL>(acc, red, sig_out(V, n, ob));
+}
+// tau terms (tau_contrib) on the thread's sub-block
+template <int D>
+__global__ void __launch_bounds__(ADJ_NT) k_adj_tau_sub(const AdjProb* ap, int p, int srcsel, int with_m) {
+  constexpr int SB = (D + 1) / 2, NL = ADJ_NT / 4, DD = D * D;
+  __shared__ cplx red[4 * NL * SB * SB];
+  const AdjProb& A = ap[blockIdx.y];
+  if (p > A.p.nt) return;
+  AdjView V(A, c_kw[A.p.k]);
+  bool isM;
+  int x;
+  if (!tau_out(A, V.ntau, blockIdx.x, with_m != 0, isM, x)) return;
+  const cplx* src = srcsel == 0 ? V.scr(V.lay.rhoT) : V.scr(V.lay.psi) + (size_t)(p - 1) * (V.ntau + 1) * DD;
+  int tid = threadIdx.x, sb = tid & 3, lane = tid >> 2;
+  int r0 = (sb >> 1) * SB, c0 = (sb & 1) * SB;
+  cplx acc[SB * SB];
+#pragma unroll
+  for (int e = 0; e < SB * SB; e++) acc[e] = mk(0, 0);
+  int nterm = tau_nterms(V.k, V.ntau, isM, x);
+  for (int t = lane; t < nterm; t += NL) {
+    int m, y;
+    double coef;
+    if (!tau_term(V.W, V.k, V.ntau, V.ht, V.xi, isM, x, t, m, y, coef)) continue;
+    BlkA<D> g{src + (size_t)m * DD, false};
+    if (!isM) sub_term<D, SB, false>(acc, mk(0, coef), r0, c0, g, BlkA<D>{V.GM(y), false});
+    else sub_term<D, SB, true>(acc, mk(0, coef), r0, c0, BlkA<D>{V.ST(p, y), false}, g);
+  }
+  sub_flush<D, SB, NL>(acc, red, tau_dst(V, p, isM, x));
+}
 // one output block per workgroup, the terms split over lane groups
 __global__ void __launch_bounds__(ADJ_NT) k_adj_tau(const AdjProb* ap, int p, int srcsel, int with_m) {
   const AdjProb& A = ap[blockIdx.y];
@@ -2077,6 +2223,18 @@ void adj_prep_launch(const AdjProb* dA, const AdjShape& S, int n, hipStream_t s)
   hipLaunchKernelGGL(k_adj_prep, dim3(1, S.count), dim3(ADJ_NT), 0, s, dA, n);
 }
 
+// tau-term kernel of the orbital count: sub-blocks for d >= 5
+static void adj_tau_launch(int d, dim3 g, hipStream_t s, const AdjProb* dA, int p, int srcsel, int with_m) {
+  dim3 blk(ADJ_NT);
+  switch (d) {
+    case 5: hipLaunchKernelGGL(k_adj_tau_sub<5>, g, blk, 0, s, dA, p, srcsel, with_m); break;
+    case 6: hipLaunchKernelGGL(k_adj_tau_sub<6>, g, blk, 0, s, dA, p, srcsel, with_m); break;
+    case 7: hipLaunchKernelGGL(k_adj_tau_sub<7>, g, blk, 0, s, dA, p, srcsel, with_m); break;
+    case 8: hipLaunchKernelGGL(k_adj_tau_sub<8>, g, blk, 0, s, dA, p, srcsel, with_m); break;
+    default: hipLaunchKernelGGL(k_adj_tau, g, blk, 0, s, dA, p, srcsel, with_m); break;
+  }
+}
+
 // reverse step of slice n > k (hist: also scatter into the history of slices < n)
 void adj_step_launch(const AdjProb* dA, const AdjShape& S, int n, bool hist, hipStream_t s) {
   int k = S.k, ntau = S.ntau, dd = S.dd;
@@ -2097,12 +2255,16 @@ void adj_step_launch(const AdjProb* dA, const AdjShape& S, int n, bool hist, hip
       case 2: hipLaunchKernelGGL(k_adj_sigma_blk<2>, gs, blk, 0, s, dA, n); break;
       case 3: hipLaunchKernelGGL(k_adj_sigma_blk<3>, gs, blk, 0, s, dA, n); break;
       case 4: hipLaunchKernelGGL(k_adj_sigma_blk<4>, gs, blk, 0, s, dA, n); break;
+      case 5: hipLaunchKernelGGL(k_adj_sigma_sub<5>, gs, blk, 0, s, dA, n); break;
+      case 6: hipLaunchKernelGGL(k_adj_sigma_sub<6>, gs, blk, 0, s, dA, n); break;
+      case 7: hipLaunchKernelGGL(k_adj_sigma_sub<7>, gs, blk, 0, s, dA, n); break;
+      case 8: hipLaunchKernelGGL(k_adj_sigma_sub<8>, gs, blk, 0, s, dA, n); break;
       default: hipLaunchKernelGGL(k_adj_sigma, gs, blk, 0, s, dA, n); break;
     }
   }
   // (a trial step, hist = false, needs no M adjoint)
   int nto = (S.sig ? 1 : 0) + (hist ? 1 : 0);
-  if (nto) hipLaunchKernelGGL(k_adj_tau, dim3(nto * (ntau + 1), S.count), blk, 0, s, dA, n, 0, hist ? 1 : 0);
+  if (nto) adj_tau_launch(S.d, dim3(nto * (ntau + 1), S.count), s, dA, n, 0, hist ? 1 : 0);
   hipLaunchKernelGGL(k_adj_rbound, dim3(1, S.count), blk, 0, s, dA, n);
 }
 
@@ -2118,8 +2280,7 @@ void adj_start_launch(const AdjProb* dA, const AdjShape& S, hipStream_t s) {
   hipLaunchKernelGGL(k_adj_tpsi, dim3(adj_blocks((size_t)k * (ntau + 1) * dd), S.count), blk, 0, s, dA);
   hipLaunchKernelGGL(k_adj_ty0, dim3(adj_blocks((size_t)(ntau + 1) * dd), S.count), blk, 0, s, dA);
   hipLaunchKernelGGL(k_adj_tp, dim3(k * (k + 1), S.count), blk, 0, s, dA);
-  for (int p = 1; p <= k; p++)
-    hipLaunchKernelGGL(k_adj_tau, dim3((S.sig ? 2 : 1) * (ntau + 1), S.count), blk, 0, s, dA, p, 1, 1);
+  for (int p = 1; p <= k; p++) adj_tau_launch(S.d, dim3((S.sig ? 2 : 1) * (ntau + 1), S.count), s, dA, p, 1, 1);
   hipLaunchKernelGGL(k_adj_rstart, dim3(1, S.count), blk, 0, s, dA);
 }
 
