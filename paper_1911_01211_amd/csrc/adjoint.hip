@@ -1918,7 +1918,7 @@ __global__ void __launch_bounds__(ADJ_NT) k_adj_sigma_blk(const AdjProb* ap, int
 // at (r0, c0); X(a, b), Y(a, b) give block elements.
 template <int D, int SB, bool AHB, class XA, class YA>
 __device__ inline void sub_term(cplx (&acc)[SB * SB], cplx f, int r0, int c0, XA X, YA Y) {
-#pragma unroll
+#pragma unroll 2
   for (int q = 0; q < D; q++) {
     cplx xs[SB], ys[SB];
 #pragma unroll
@@ -2009,7 +2009,8 @@ __device__ inline void sub_flush(cplx (&acc)[SB * SB], cplx* red, cplx* o) {
   }
 }
 template <int D>
-__global__ void __launch_bounds__(ADJ_NT) k_adj_sigma_sub(const AdjProb* ap, int n) {
+__global__ void __launch_bounds__(ADJ_NT) __attribute__((amdgpu_waves_per_eu(2))) k_adj_sigma_sub(const AdjProb* ap,
+                                                                                               int n) {
   constexpr int SB = (D + 1) / 2, NL = ADJ_NT / 4;
   __shared__ cplx red[4 * NL * SB * SB];
   const AdjProb& A = ap[blockIdx.y];
