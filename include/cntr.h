@@ -86,6 +86,27 @@ cntr_status cntr_init_matsubara(int32_t count, const cntr_grid* grids, const cnt
                                 const cntr_gf* Sigma, const void* const* eps, double tol,
                                 int32_t max_iter, void* stream);
 
+/* Fourier-series Matsubara solve (Sec. "Implementation: dyson", Matsubara,
+ * "Fourier series representation"; the paper's fast initial guess): with
+ * x = eps(0^-) - mu and frequencies w = (2m+1) pi/beta, m = -Nw..Nw-1
+ * (fermions) or 2 m pi/beta, m = -Nw..Nw (bosons), Nw = oversample * ntau,
+ *   Sigma(i w) = integral of the piecewise-cubic interpolant of Sigma^M
+ *                times e^{i w tau} over [0, beta] (on each interval the cubic
+ *                through the grid points J-1..J+2, one-sided at the ends),
+ *   G(i w)     = [i w - x - Sigma(i w)]^{-1},
+ *   G^M(tau_j) = (1/beta) sum_w e^{-i w tau_j} [G(i w) - 1/(i w)] - c(tau_j) 1,
+ *                c = 1/2 (fermions), 1/2 - tau/beta (bosons; no 1/(i w) at w = 0).
+ * Average error O(h_tau^2), largest (at tau = 0, beta) O(1/Nw) against the
+ * continuous solution; cntr_init_matsubara solves the discrete equation
+ * exactly. Inputs: grids[i] (ntau >= 3, beta, mu, sig), Sigma[i].mat (DEVICE;
+ * Sigma == NULL: Sigma = 0), eps[i] (DEVICE, entry 0 = eps(0^-)), oversample
+ * in 1..64 (the paper's default is 10). Output: G[i].mat (overwritten; the
+ * other components untouched). Uses the stream's scratch ((2 Nw + 1) d^2
+ * complex values), asynchronous. Errors: CNTR_EINVAL (ntau < 3, oversample
+ * out of range), CNTR_ESHAPE (null pointers). */
+cntr_status cntr_matsubara_fourier(int32_t count, const cntr_grid* grids, const cntr_gf* G, const cntr_gf* Sigma,
+                                   const void* const* eps, int32_t oversample, void* stream);
+
 /* ---------------------------------------------------------------- A2-A7 --
  * Dyson equation (Eq. dyson, Sec. "Implementation: dyson").
  *  tstp <= k : start-up, computes slices 0..k from T[G]_{-1}, Sigma slices

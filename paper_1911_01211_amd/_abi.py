@@ -18,7 +18,7 @@ STATUS = {0: "CNTR_OK", -1: "CNTR_EINVAL", -2: "CNTR_ESHAPE", -3: "CNTR_EORDER",
           -8: "CNTR_ENOCONV"}
 
 SYMBOLS = ["cntr_init_matsubara", "cntr_dyson_step", "cntr_convolution", "cntr_sigma_2b",
-           "cntr_extrapolate", "cntr_green_from_H", "cntr_distance", "cntr_copy_slice", "cntr_solve_2b", "cntr_sync",
+           "cntr_extrapolate", "cntr_green_from_H", "cntr_matsubara_fourier", "cntr_distance", "cntr_copy_slice", "cntr_solve_2b", "cntr_sync",
            "cntr_last_error", "cntr_finalize", "cntr_version", "cntr_profile_begin", "cntr_profile_begin_every",
            "cntr_profile_end", "cntr_observables", "cntr_sigma_local", "cntr_adjoint_sweep",
            "cntr_solve_2b_batch", "cntr_set_checks", "cntr_mark_slices",
@@ -69,6 +69,7 @@ def lib():
         L.cntr_sigma_2b.argtypes = [i32, i32, P(Grid), P(GF), P(vp), P(GF), P(vp), P(vp), dbl, vp]
         L.cntr_extrapolate.argtypes = [i32, i32, P(Grid), P(GF), vp]
         L.cntr_green_from_H.argtypes = [i32, P(Grid), P(GF), P(vp), vp]
+        L.cntr_matsubara_fourier.argtypes = [i32, P(Grid), P(GF), P(GF), P(vp), i32, vp]
         L.cntr_distance.argtypes = [i32, i32, P(Grid), P(GF), P(GF), P(dbl), vp]
         L.cntr_copy_slice.argtypes = [i32, i32, P(Grid), P(GF), P(GF), vp]
         L.cntr_solve_2b.argtypes = [P(Grid), P(GF), P(GF), P(GF), vp, vp, vp, dbl, i32, dbl, dbl,

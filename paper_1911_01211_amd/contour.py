@@ -218,6 +218,15 @@ def green_from_H(G: list, eps: list, stream=None):
     _abi.check(_abi.lib().cntr_green_from_H(len(G), _grids(G), _gfs(G), _ptrs(eps), _stream(stream)))
 
 
+def matsubara_fourier(G: list, Sigma, eps: list, oversample: int = 10, stream=None):
+    """G^M of each G by the Fourier-series method (cntr_matsubara_fourier;
+    Sigma: list of contours, or None for Sigma = 0; eps[i]: device tensor
+    [(nt+2), d, d], entry 0 = eps(0^-))."""
+    S = _gfs(Sigma) if Sigma is not None else None
+    _abi.check(_abi.lib().cntr_matsubara_fourier(len(G), _grids(G), _gfs(G), S, _ptrs(eps), int(oversample),
+                                                  _stream(stream)))
+
+
 def extrapolate(tstp: int, G: list, stream=None):
     _abi.check(_abi.lib().cntr_extrapolate(tstp, len(G), _grids(G), _gfs(G), _stream(stream)))
 

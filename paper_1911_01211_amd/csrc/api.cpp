@@ -1153,6 +1153,30 @@ cntr_status cntr_green_from_H(int32_t count, const cntr_grid* grids, const cntr_
   return CNTR_OK;
 }
 
+cntr_status cntr_matsubara_fourier(int32_t count, const cntr_grid* grids, const cntr_gf* G, const cntr_gf* Sigma,
+                                   const void* const* eps, int32_t oversample, void* stream) {
+  cntr_status st = check_batch(count, grids, "cntr_matsubara_fourier");
+  if (st) return st;
+  if (!gf_ok(G, count) || !eps) return fail(CNTR_ESHAPE, "cntr_matsubara_fourier: null pointer");
+  if (oversample < 1 || oversample > 64) return fail(CNTR_EINVAL, "cntr_matsubara_fourier: oversampling outside 1..64");
+  size_t need = 256;
+  for (int i = 0; i < count; i++) {
+    if (!eps[i]) return fail(CNTR_ESHAPE, "cntr_matsubara_fourier: null eps");
+    if (grids[i].ntau < 3) return fail(CNTR_EINVAL, "cntr_matsubara_fourier: ntau < 3");
+    if (Sigma && !Sigma[i].mat) return fail(CNTR_ESHAPE, "cntr_matsubara_fourier: null Sigma^M");
+    need = std::max(need, mats_fourier_scratch_bytes(grids[i].ntau, grids[i].d, oversample));
+  }
+  hipStream_t s = (hipStream_t)stream;
+  StreamScratch* sc = scratch_for(s);
+  if ((st = grow(s, sc, need, 0, 0))) return st;
+  for (int i = 0; i < count; i++) {
+    Prob P = make_prob(grids[i], &G[i], Sigma ? &Sigma[i] : nullptr, eps[i]);
+    hipError_t e = launch_mats_fourier(P, oversample, (cplx*)sc->data(), s);
+    if (e != hipSuccess) return hip_fail(e, "cntr_matsubara_fourier");
+  }
+  return CNTR_OK;
+}
+
 cntr_status cntr_peierls(int32_t count, const cntr_grid* grids, const void* const* T, const double* const* Phi,
                          const double* const* A, void* const* eps, void* stream) {
   cntr_status st = check_batch(count, grids, "cntr_peierls");

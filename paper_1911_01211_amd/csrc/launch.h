@@ -136,6 +136,10 @@ hipError_t launch_free_green(const Prob& P, void* scratch, hipStream_t s);
 hipError_t launch_mat_conv(const Prob& P, const cplx* A, const cplx* B, const cplx* f,
                            cplx* out, hipStream_t s);
 hipError_t launch_mat_build(const Prob& P, const cplx* K, cplx* Amat, hipStream_t s);
+// Fourier-series solve of the Matsubara equation into P.Gmat (P.Smat null: Sigma = 0),
+// oversampling p (work: mats_fourier_scratch_bytes)
+size_t mats_fourier_scratch_bytes(int ntau, int d, int p);
+hipError_t launch_mats_fourier(const Prob& P, int p, cplx* work, hipStream_t s);
 hipError_t launch_gj_inverse(int N, cplx* Amat, cplx* work, int* piv, int* status,
                              hipStream_t s);
 // complex elements of the work buffer of launch_gj_inverse

@@ -653,4 +653,156 @@ hipError_t launch_mix(int len, cplx* x, cplx* keep, double a, bool first, hipStr
   return hipGetLastError();
 }
 
+// ------------------------------------------- Fourier-series Matsubara solve
+// The method of the "Fourier series representation" (Sec. "Implementation:
+// dyson", Matsubara), a fast solve of O(h_tau^2) average accuracy:
+//   Sigma(i w_m) = int_0^beta Sigma^M(tau) e^{i w_m tau} dtau, integrating the
+//     piecewise-cubic interpolant of the samples exactly (the cubically
+//     corrected transform): on [tau_J, tau_J+1] the cubic through the grid
+//     points J-1..J+2 (J..J+3 on the first interval, J-2..J+1 on the last);
+//   G(i w_m) = [i w_m - x - Sigma(i w_m)]^{-1}, x = eps(0^-) - mu (the
+//     algebraic Dyson equation);
+//   G^M(tau) = (1/beta) sum_m e^{-i w_m tau} G~(i w_m) - c(tau) 1 with
+//     G~(i w) = G(i w) - 1/(i w) (none at the bosonic w = 0), c = 1/2
+//     (fermions) or 1/2 - tau/beta (bosons): the jump G^M(0+) - xi G^M(beta-)
+//     = -1 removed, so that the sum converges.
+// Frequencies w = q pi / beta: fermions q = 2m+1, m = -Nw..Nw-1; bosons
+// q = 2m, m = -Nw..Nw; Nw = p Ntau. Phases are reduced exactly in integers:
+// w_m tau_j = pi (q j mod 2 Ntau) / Ntau.
+__device__ inline int mf_q(int f, int nw, int xi) { return xi == -1 ? 2 * (f - nw) + 1 : 2 * (f - nw); }
+
+// mu_k = int_0^1 u^k e^{i th u} du, k = 0..3 (series below |th| = 1, where
+// the recursion would cancel)
+__device__ inline void mf_moments(double th, cplx (&mu)[4]) {
+  if (fabs(th) < 1.0) {
+#pragma unroll
+    for (int k = 0; k < 4; k++) mu[k] = mk(0, 0);
+    cplx t = mk(1, 0);  // (i th)^n / n!
+    for (int n = 0; n < 24; n++) {
+#pragma unroll
+      for (int k = 0; k < 4; k++) mu[k] = mu[k] + (1.0 / (n + k + 1)) * t;
+      t = (1.0 / (n + 1)) * (t * mk(0, th));
+    }
+    return;
+  }
+  double sn, cs;
+  sincos(th, &sn, &cs);
+  cplx e = mk(cs, sn), iz = mk(0, -1.0 / th);  // 1 / (i th)
+  mu[0] = (e - mk(1, 0)) * iz;
+#pragma unroll
+  for (int k = 1; k < 4; k++) mu[k] = (e - (double)k * mu[k - 1]) * iz;
+}
+// int_0^1 L_i(u) e^{i th u} du for the Lagrange basis of the nodes o..o+3
+__device__ inline void mf_weights(int o, const cplx (&mu)[4], cplx (&w)[4]) {
+#pragma unroll
+  for (int i = 0; i < 4; i++) {
+    double a[4] = {1, 0, 0, 0}, den = 1;
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+      if (j == i) continue;
+      double xj = o + j;
+#pragma unroll
+      for (int k = 3; k >= 1; k--) a[k] = a[k - 1] - xj * a[k];
+      a[0] = -xj * a[0];
+      den *= (double)(i - j);
+    }
+    cplx v = mk(0, 0);
+#pragma unroll
+    for (int k = 0; k < 4; k++) v = v + (a[k] / den) * mu[k];
+    w[i] = v;
+  }
+}
+// Sigma(i w_f) for one element: thread (f, e)
+__global__ __launch_bounds__(NT3) void k_mf_sigma(Prob P, int nw, int nf, cplx* W) {
+  int dd = P.d * P.d, N = P.ntau;
+  int idx = blockIdx.x * NT3 + threadIdx.x;
+  if (idx >= nf * dd) return;
+  int f = idx / dd, e = idx % dd;
+  int q = mf_q(f, nw, P.sig);
+  cplx mu[4], wf[4], wi[4], wl[4];
+  mf_moments(M_PI * q / N, mu);
+  mf_weights(0, mu, wf);
+  mf_weights(-1, mu, wi);
+  mf_weights(-2, mu, wl);
+  const cplx* S = P.Smat;
+  cplx acc = mk(0, 0);
+  for (int J = 0; J < N; J++) {
+    int s = min(max(J - 1, 0), N - 3), o = s - J;
+    cplx v = mk(0, 0);
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+      cplx wv = o == 0 ? wf[i] : (o == -1 ? wi[i] : wl[i]);
+      v = v + wv * gld(S + (size_t)(s + i) * dd + e);
+    }
+    long r = ((long)q * J) % (2L * N);
+    if (r < 0) r += 2L * N;
+    double sn, cs;
+    sincos(M_PI * (double)r / N, &sn, &cs);
+    acc = acc + mk(cs, sn) * v;
+  }
+  W[(size_t)f * dd + e] = (P.beta / N) * acc;
+}
+// G~(i w_f) = [i w - x - Sigma(i w)]^{-1} - 1/(i w): one wave per frequency
+__global__ __launch_bounds__(NT3) void k_mf_solve(Prob P, int nw, int nf, cplx* W, int has_sigma) {
+  __shared__ cplx A[NT3 / 64][64];
+  __shared__ int piv[NT3 / 64][8];
+  int d = P.d, dd = d * d, wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  int f = blockIdx.x * (NT3 / 64) + wave;
+  if (f >= nf) return;  // (whole waves)
+  int q = mf_q(f, nw, P.sig);
+  double w = M_PI * q / P.beta;
+  int r = lane / d, c = lane % d;
+  if (lane < dd) {
+    cplx v = -gld(P.eps + lane);  // eps(0^-)
+    if (r == c) v = v + mk(P.mu, w);
+    if (has_sigma) v = v - W[(size_t)f * dd + lane];
+    A[wave][lane] = v;
+  }
+  wave_sync();
+  wave_inverse(d, A[wave], piv[wave]);
+  if (lane < dd) {
+    cplx g = A[wave][lane];
+    if (q != 0 && r == c) g = g + mk(0, 1.0 / w);  // - 1/(i w)
+    W[(size_t)f * dd + lane] = g;
+  }
+}
+// G^M(tau_j): one workgroup per j, thread (frequency group, element); the
+// groups' sums are added in a fixed order
+__global__ __launch_bounds__(NT3) void k_mf_back(Prob P, int nw, int nf, const cplx* W) {
+  __shared__ cplx red[NT3];
+  int dd = P.d * P.d, N = P.ntau, j = blockIdx.x, t = threadIdx.x;
+  int G = NT3 / dd, e = t % dd, g = t / dd;
+  cplx acc = mk(0, 0);
+  if (g < G)
+    for (int f = g; f < nf; f += G) {
+      int q = mf_q(f, nw, P.sig);
+      long r = ((long)q * j) % (2L * N);
+      if (r < 0) r += 2L * N;
+      double sn, cs;
+      sincos(M_PI * (double)r / N, &sn, &cs);
+      acc = acc + mk(cs, -sn) * W[(size_t)f * dd + e];
+    }
+  red[t] = acc;
+  __syncthreads();
+  if (t < dd) {
+    cplx v = mk(0, 0);
+    for (int gg = 0; gg < G; gg++) v = v + red[gg * dd + t];
+    v = (1.0 / P.beta) * v;
+    if (t / P.d == t % P.d) v = v - mk(P.sig == -1 ? 0.5 : 0.5 - (double)j / N, 0);
+    gst(P.Gmat + (size_t)j * dd + t, v);
+  }
+}
+
+size_t mats_fourier_scratch_bytes(int ntau, int d, int p) {
+  return (size_t)(2 * (size_t)p * ntau + 1) * d * d * sizeof(cplx);
+}
+
+hipError_t launch_mats_fourier(const Prob& P, int p, cplx* work, hipStream_t s) {
+  int nw = p * P.ntau, nf = P.sig == -1 ? 2 * nw : 2 * nw + 1, dd = P.d * P.d;
+  if (P.Smat) k_mf_sigma<<<(nf * dd + NT3 - 1) / NT3, NT3, 0, s>>>(P, nw, nf, work);
+  k_mf_solve<<<(nf + NT3 / 64 - 1) / (NT3 / 64), NT3, 0, s>>>(P, nw, nf, work, P.Smat ? 1 : 0);
+  k_mf_back<<<P.ntau + 1, NT3, 0, s>>>(P, nw, nf, work);
+  return hipGetLastError();
+}
+
 }  // namespace cntr
