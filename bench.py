@@ -541,10 +541,39 @@ def cpu_baseline(g, ncorr, mats_iter, budget_s):
     O.dyson_start(G, S, e0)
     t_start_up = time.perf_counter() - t
     total = t_steps + mats_iter * t_mat + 10 * t_start_up
+    # one host thread: the same corrector iteration at eight slices spread
+    # over the run, scaled by its ratio to the multi-threaded time there
+    cores = O.num_threads()
+    picks = [n for n in range(g.k + 1, g.nt + 1, max(1, (g.nt - g.k) // 8)) if n in measured][:8]
+    ratio = None
+    if picks:
+        O.set_threads(1)
+        try:
+            r1 = []
+            for n in picks:
+                t = time.perf_counter()
+                O.sigma_2b(n, G, U, S)
+                O.dyson_timestep(n, G, S, e0, "B")
+                r1.append((time.perf_counter() - t) / measured[n])
+            ratio = float(np.mean(r1))
+        finally:
+            O.set_threads(cores)
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     return {
         "value": (g.nt - g.k) / total,
         "unit": "time-steps/s",
-        "cores": O.num_threads(),
+        "cores": cores,
+        "cpu_model": model,
+        "single_thread_value": (g.nt - g.k) / (total * ratio) if ratio else None,
+        "single_thread_sample": f"slices {picks} on one thread, {ratio:.2f} x their {cores}-thread time" if ratio else None,
         "kind": "oracle",
         "sample": (f"oracle (B) time step + Sigma_2B, one corrector iteration at {len(samples)} of the "
                    f"{g.nt - g.k} slices n > k on a seeded history of the workload's shape, one "

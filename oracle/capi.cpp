@@ -215,6 +215,12 @@ int oracle_solve_fixed(const oracle_grid* g, HMARGS(G), HMARGS(S), const void* e
   return ok ? 0 : -4;
 }
 
+void oracle_set_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#endif
+}
+
 int oracle_num_threads(void) {
 #ifdef _OPENMP
   return omp_get_max_threads();

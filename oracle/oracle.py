@@ -312,3 +312,7 @@ def solve_local(Gs, S: HM, eps, lam, mats_iters=30, boot_iters=8, ncorr=5, nt_st
 
 def num_threads():
     return lib().oracle_num_threads()
+
+
+def set_threads(n: int):
+    lib().oracle_set_threads(int(n))
