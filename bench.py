@@ -164,7 +164,16 @@ def run_adjoint(args):
         print(f"# adjoint ring: direction {q} rel err {fd[-1]['rel_err']:.2e} (raw differences {diffs})",
               file=sys.stderr, flush=True)
     nsl = g.nt - g.k
-    return {"workload": f"8-site Hubbard ring, Peierls phase e^(iA(t)) on the hopping, second-Born + Hartree, "
+    # FP64 work of the backward's dominant reductions (the Sigma-bar sums of
+    # every reverse step: d x d block products, 8 d^3 flops each; counted
+    # from the kernels' term ranges) against the whole backward wall time
+    sig_flops = (args.adj_niter + 1) * 8.0 * g.d ** 3 * sum(adj_sigma_products(n, g.k, g.ntau)
+                                                           for n in range(g.k + 1, g.nt + 1))
+    out_roof = {"bound": "fp64", "scope": "Sigma-bar block products / whole backward wall time",
+                "achieved": sig_flops / (t2 - t1) / 1e12, "peak": 78.6, "unit": "TFLOP/s",
+                "frac": sig_flops / (t2 - t1) / 1e12 / 78.6, "flops": sig_flops}
+    return {"roofline": out_roof,
+            "workload": f"8-site Hubbard ring, Peierls phase e^(iA(t)) on the hopping, second-Born + Hartree, "
                         f"U=1.5, beta=10, ntau=400, nt={g.nt}, h=0.02, k=5; gradient of E_kin(t_nt) w.r.t. the "
                         f"{g.nt} samples A_n and U (torch.autograd.Function over the adjoint sweep)",
             "value": nsl / (t2 - t1), "unit": "adjoint time-steps/s",
@@ -206,6 +215,24 @@ def run_mats_fourier(state):
             "ms_per_solve": times, "speedup_vs_exact": times["exact"] / times["fourier"],
             "max_abs_deviation": float(dev.max()), "mean_abs_deviation": float(dev.mean()),
             "max_abs_GM": float(Gx.mat.abs().max())}
+
+
+def adj_sigma_products(n, k, ntau):
+    """Block products of the Sigma-bar reductions of reverse step n (the term
+    ranges of the adjoint kernels: retarded outputs j < n with min(j, nb-1)+1
+    retarded, ntau+1 mixing and nb lesser terms; lesser outputs j <= n; mixing
+    outputs ntau+1 with nb terms each; nb = n - k; lesser and mixing only for
+    n > 2k)."""
+    nb = n - k
+    tot = 0
+    for j in range(n):
+        tot += min(j, nb - 1) + 1 + (ntau + 1) + (nb if n > 2 * k else 0)
+    if n > 2 * k:
+        for j in range(n + 1):
+            a = min(k, nb - 1) + 1 if j <= k else 0
+            tot += a + max(0, nb - max(j, k + 1))
+        tot += (ntau + 1) * nb
+    return tot
 
 
 def run_cfg1(args):

@@ -60,7 +60,8 @@ typedef enum {
   CNTR_ENONFINITE = -5, /* non-finite value detected */
   CNTR_EHIP = -6,       /* HIP runtime error */
   CNTR_ENOMEM = -7,     /* device allocation failed */
-  CNTR_ENOCONV = -8     /* iteration did not reach its tolerance */
+  CNTR_ENOCONV = -8,    /* iteration did not reach its tolerance */
+  CNTR_ESYMMETRY = -9   /* (symmetry checks on) a self-energy violates hermitian symmetry */
 } cntr_status;
 
 typedef struct {
@@ -441,9 +442,18 @@ cntr_status cntr_set_tiles(int32_t d, int32_t nbands, const int32_t* n_hi, const
  *  CNTR_CHECK_FINITE : after every start-up or step a device check of the
  *     slices it wrote, the self-energy slices of the same index and eps;
  *     a non-finite value sets the problem's status word, reported as
- *     CNTR_ENONFINITE by cntr_sync. Costs one read of those slices. */
+ *     CNTR_ENONFINITE by cntr_sync. Costs one read of those slices.
+ *  CNTR_CHECK_SYMMETRY : with every start-up or step a device check that the
+ *     self-energy it reads is a hermitian contour function (Sec. "Contour
+ *     Green's functions", the hermitian symmetry the Dyson solver assumes):
+ *     the equal-time blocks Sigma^<_{n,n} and Sigma^R_{n,n} anti-hermitian at
+ *     every slice the call reads (0..k for the start-up, tstp for a step),
+ *     and for the start-up Sigma^M(tau) hermitian at every tau; a block
+ *     with max|X + X^dag| > 1e-10 max|X| sets the problem's status word,
+ *     reported as CNTR_ESYMMETRY by cntr_sync. */
 #define CNTR_CHECK_ORDER 1
 #define CNTR_CHECK_FINITE 2
+#define CNTR_CHECK_SYMMETRY 4
 cntr_status cntr_set_checks(int32_t flags);
 /* Declare slices -1..last of `count` instances complete (last = -2 removes
  * the records). Host only; count >= 1, G non-NULL. */

@@ -11,11 +11,11 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libcntr.so")
 
-CHECK_ORDER, CHECK_FINITE = 1, 2
+CHECK_ORDER, CHECK_FINITE, CHECK_SYMMETRY = 1, 2, 4
 
 STATUS = {0: "CNTR_OK", -1: "CNTR_EINVAL", -2: "CNTR_ESHAPE", -3: "CNTR_EORDER",
           -4: "CNTR_ESINGULAR", -5: "CNTR_ENONFINITE", -6: "CNTR_EHIP", -7: "CNTR_ENOMEM",
-          -8: "CNTR_ENOCONV"}
+          -8: "CNTR_ENOCONV", -9: "CNTR_ESYMMETRY"}
 
 SYMBOLS = ["cntr_init_matsubara", "cntr_dyson_step", "cntr_convolution", "cntr_sigma_2b",
            "cntr_extrapolate", "cntr_green_from_H", "cntr_matsubara_fourier", "cntr_distance", "cntr_copy_slice", "cntr_solve_2b", "cntr_sync",

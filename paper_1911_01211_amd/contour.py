@@ -273,9 +273,10 @@ class Graph:
             pass
 
 
-def set_checks(order=False, finite=False):
+def set_checks(order=False, finite=False, symmetry=False):
     """Optional precondition / value checks (cntr_set_checks)."""
-    _abi.check(_abi.lib().cntr_set_checks((_abi.CHECK_ORDER if order else 0) | (_abi.CHECK_FINITE if finite else 0)))
+    _abi.check(_abi.lib().cntr_set_checks((_abi.CHECK_ORDER if order else 0) | (_abi.CHECK_FINITE if finite else 0) |
+                                          (_abi.CHECK_SYMMETRY if symmetry else 0)))
 
 
 def mark_slices(G: list, last: int):

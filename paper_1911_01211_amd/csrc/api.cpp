@@ -644,7 +644,8 @@ cntr_status cntr_set_tiles(int32_t d, int32_t nbands, const int32_t* n_hi, const
 }
 
 cntr_status cntr_set_checks(int32_t flags) {
-  if (flags & ~(CNTR_CHECK_ORDER | CNTR_CHECK_FINITE)) return fail(CNTR_EINVAL, "cntr_set_checks: unknown flag");
+  if (flags & ~(CNTR_CHECK_ORDER | CNTR_CHECK_FINITE | CNTR_CHECK_SYMMETRY))
+    return fail(CNTR_EINVAL, "cntr_set_checks: unknown flag");
   std::lock_guard<std::mutex> lk(g_mu);
   if (!(flags & CNTR_CHECK_ORDER)) g_last.clear();
   g_checks = flags;
@@ -680,6 +681,14 @@ cntr_status cntr_finalize(void) {
   return CNTR_OK;
 }
 
+// text of a device status word (problem i, or -1: not known)
+static std::string status_text(int code, int i) {
+  std::string what = code == CNTR_ENONFINITE    ? "non-finite value in a time step"
+                     : code == CNTR_ESYMMETRY ? "self-energy violates hermitian symmetry"
+                                              : "singular step matrix detected on the device";
+  return i >= 0 ? what + " (problem " + std::to_string(i) + ")" : what;
+}
+
 cntr_status cntr_sync(void* stream) {
   if (capturing((hipStream_t)stream)) return fail(CNTR_EINVAL, "cntr_sync: synchronizes the stream, not allowed during graph capture");
   hipStream_t s = (hipStream_t)stream;
@@ -689,8 +698,7 @@ cntr_status cntr_sync(void* stream) {
   cntr_status st = noalloc_status(&code);
   if (st) return st;
   if (code != 0)
-    return fail((cntr_status)code, code == CNTR_ENONFINITE ? "non-finite value in a time step"
-                                                           : "singular step matrix detected on the device");
+    return fail((cntr_status)code, status_text(code, -1));
   StreamScratch* sc = scratch_for(s);
   if (!sc->buf || sc->nstat == 0) return CNTR_OK;
   // the status words of the problems of the calls since the last check
@@ -704,10 +712,7 @@ cntr_status cntr_sync(void* stream) {
       code = codes[i];
       std::vector<int> zero(cnt, 0);
       (void)hipMemcpy(sc->stat(), zero.data(), cnt * sizeof(int), hipMemcpyHostToDevice);
-      return fail((cntr_status)code, code == CNTR_ENONFINITE
-                                         ? "non-finite value in a time step (problem " + std::to_string(i) + ")"
-                                         : "singular step matrix detected on the device (problem " +
-                                               std::to_string(i) + ")");
+      return fail((cntr_status)code, status_text(code, i));
     }
   return CNTR_OK;
 }
@@ -748,6 +753,8 @@ cntr_status cntr_dyson_step(int32_t tstp, int32_t count, const cntr_grid* grids,
                            : launch_step(pa, scr, tstp, d, s, shared, !capturing(s));
   if (e == hipSuccess && (g_checks & CNTR_CHECK_FINITE))
     e = launch_check_finite(pa, scr, tstp <= k ? 0 : tstp, tstp <= k ? k : tstp, d, ntau, s);
+  if (e == hipSuccess && (g_checks & CNTR_CHECK_SYMMETRY))
+    e = launch_check_symmetry(pa, scr, tstp <= k ? -1 : tstp, tstp <= k ? k : tstp, ntau, s);
   if (e != hipSuccess) return hip_fail(e, "cntr_dyson_step launch");
   order_mark(count, G, tstp <= k ? k : tstp, false);
   return CNTR_OK;
@@ -809,6 +816,8 @@ cntr_status cntr_dyson_step_noalloc(int32_t tstp, int32_t count, const cntr_grid
   hipError_t e = tstp <= k ? launch_start(pa, scr, d, ntau, s) : launch_step(pa, scr, tstp, d, s, shared, false);
   if (e == hipSuccess && (g_checks & CNTR_CHECK_FINITE))
     e = launch_check_finite(pa, scr, tstp <= k ? 0 : tstp, tstp <= k ? k : tstp, d, ntau, s);
+  if (e == hipSuccess && (g_checks & CNTR_CHECK_SYMMETRY))
+    e = launch_check_symmetry(pa, scr, tstp <= k ? -1 : tstp, tstp <= k ? k : tstp, ntau, s);
   if (e == hipSuccess) e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "cntr_dyson_step_noalloc launch");
   order_mark(count, G, tstp <= k ? k : tstp, false);

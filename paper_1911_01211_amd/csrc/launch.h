@@ -107,6 +107,9 @@ hipError_t launch_start(const ProbArg& pa, const Scratch& sc, int d, int ntau, h
 // problem's status word to CNTR_ENONFINITE
 hipError_t launch_check_finite(const ProbArg& pa, const Scratch& sc, int n0, int n1, int d, int ntau,
                                hipStream_t s);
+// self-energy symmetry of slices n0..n1 (n0 = -1: also Sigma^M) sets the
+// problem's status word to CNTR_ESYMMETRY
+hipError_t launch_check_symmetry(const ProbArg& pa, const Scratch& sc, int n0, int n1, int ntau, hipStream_t s);
 hipError_t launch_sigma2b(const ProbArg& pa, int n, int d, int nmax_elems, double nbar,
                           hipStream_t s);
 hipError_t launch_extrapolate(const ProbArg& pa, int n, int d, int nelems, hipStream_t s);

@@ -316,6 +316,47 @@ hipError_t launch_check_finite(const ProbArg& pa, const Scratch& sc, int n0, int
   return hipGetLastError();
 }
 
+// Symmetry check (optional, cntr_set_checks): the self-energy read by a
+// start-up or step is a hermitian contour function, so its equal-time
+// blocks Sigma^<_{n,n} and Sigma^R_{n,n} are anti-hermitian and Sigma^M(tau)
+// is hermitian. One thread per block; a violation sets the problem's status
+// word to CNTR_ESYMMETRY.
+__global__ __launch_bounds__(NT2) void k_check_symm(ProbArg pa, Scratch sc, int n0, int n1) {
+  int pi = blockIdx.y;
+  const Prob& P = pa.get(pi);
+  int d = P.d, dd = d * d, ntau = P.ntau;
+  int nreal = n1 >= 0 ? n1 - max(n0, 0) + 1 : 0, nmat = n0 < 0 ? ntau + 1 : 0;
+  int v = blockIdx.x * NT2 + threadIdx.x;
+  if (v >= 2 * nreal + nmat) return;
+  const cplx* X;
+  double sgn;  // +1: anti-hermitian, -1: hermitian
+  if (v < 2 * nreal) {
+    int n = max(n0, 0) + v / 2;
+    if (n > P.nt) return;
+    X = (v & 1 ? P.Sret : P.Sles) + tri(n) * dd + (size_t)n * dd;
+    sgn = 1.0;
+  } else {
+    X = P.Smat + (size_t)(v - 2 * nreal) * dd;
+    sgn = -1.0;
+  }
+  double dev = 0, mag = 0;
+  for (int a = 0; a < d; a++)
+    for (int b = 0; b < d; b++) {
+      cplx x = gld(X + a * d + b), y = gld(X + b * d + a);
+      cplx s = x + sgn * conj(y);
+      dev = fmax(dev, fmax(fabs(s.x), fabs(s.y)));
+      mag = fmax(mag, fmax(fabs(x.x), fabs(x.y)));
+    }
+  if (!(dev <= 1e-10 * mag)) atomicCAS(sc.status(pi), 0, (int)CNTR_ESYMMETRY);
+}
+
+hipError_t launch_check_symmetry(const ProbArg& pa, const Scratch& sc, int n0, int n1, int ntau, hipStream_t s) {
+  int nreal = n1 >= 0 ? n1 - (n0 > 0 ? n0 : 0) + 1 : 0, nmat = n0 < 0 ? ntau + 1 : 0;
+  dim3 g((2 * nreal + nmat + NT2 - 1) / NT2, pa.count);
+  k_check_symm<<<g, NT2, 0, s>>>(pa, sc, n0, n1);
+  return hipGetLastError();
+}
+
 hipError_t launch_copy(const ProbArg& pdst, const ProbArg& psrc, int n, int d, int nelems,
                        hipStream_t s) {
   dim3 g((nelems + NT2 - 1) / NT2, pdst.count);

@@ -1,7 +1,10 @@
 """The optional checks of the library on the GPU: order tracking through the
 Matsubara solve, the start-up and the steps (CNTR_EORDER for a skipped
-slice), and the finite check (CNTR_ENONFINITE reported by cntr_sync for a
-non-finite self-energy value that the step reads only in its sums)."""
+slice), the finite check (CNTR_ENONFINITE reported by cntr_sync for a
+non-finite self-energy value that the step reads only in its sums) and the
+symmetry check (CNTR_ESYMMETRY for a self-energy that is not a hermitian
+contour function: an equal-time lesser block that is not anti-hermitian, a
+Matsubara value that is not hermitian)."""
 import numpy as np
 import pytest
 import torch
@@ -64,3 +67,40 @@ def test_finite_check_reports_nonfinite_sigma():
     K.dyson_step(n, [G], [S], [e])
     K.sync()  # checks off: nothing reported
     assert torch.isnan(G.les[n * (n + 1) // 2:(n + 1) * (n + 2) // 2]).any()
+
+
+def test_symmetry_check_reports_nonhermitian_sigma():
+    require_gpu()
+    say("symmetry check")
+    g = W.GridSpec(nt=20, ntau=30, d=2, beta=5.0, h=0.05, k=5)
+    eps, S, _ = W.two_level_embedding(g)  # a physical (hermitian) self-energy
+    G, Sd, e = K.Contour(g), K.Contour(g, data=S), to_dev(eps)
+    K.set_checks(symmetry=True)
+    try:
+        K.init_matsubara([G], [Sd], [e])
+        K.dyson_step(g.k, [G], [Sd], [e])
+        for n in range(g.k + 1, 15):
+            K.dyson_step(n, [G], [Sd], [e])
+        K.sync()  # the bath self-energy passes
+        n = 15
+        bad = dict(S)
+        bad["les"] = S["les"].copy()
+        bad["les"][n * (n + 1) // 2 + n, 0, 1] += 0.05  # Sigma^<_{n,n} no longer anti-hermitian
+        Sb = K.Contour(g, data=bad)
+        K.dyson_step(n, [G], [Sb], [e])
+        with pytest.raises(_abi.CntrError) as ex:
+            K.sync()
+        assert ex.value.code == -9
+        K.sync()  # reported once
+        bad = dict(S)
+        bad["mat"] = S["mat"].copy()
+        bad["mat"][7, 0, 1] += 0.05j  # Sigma^M(tau_7) no longer hermitian
+        Sm = K.Contour(g, data=bad)
+        K.dyson_step(g.k, [G], [Sm], [e])  # the start-up reads Sigma^M
+        with pytest.raises(_abi.CntrError) as ex:
+            K.sync()
+        assert ex.value.code == -9
+    finally:
+        K.set_checks()
+    K.dyson_step(n, [G], [Sb], [e])
+    K.sync()  # checks off: nothing reported
