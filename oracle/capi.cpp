@@ -88,6 +88,18 @@ int oracle_dyson_timestep(int n, const oracle_grid* g, HMARGS(G), HMARGS(S), con
   return dyson_timestep(n, HMV(g, G), HMV(g, S), e, (char)variant) ? 0 : -4;
 }
 
+int oracle_vie2_mat(const oracle_grid* g, HMARGS(G), HMARGS(F), HMARGS(Q)) {
+  return vie2_mat(HMV(g, G), HMV(g, F), HMV(g, Q)) ? 0 : -4;
+}
+
+int oracle_vie2_start(const oracle_grid* g, HMARGS(G), HMARGS(F), HMARGS(Fcc), HMARGS(Q)) {
+  return vie2_start(HMV(g, G), HMV(g, F), HMV(g, Fcc), HMV(g, Q)) ? 0 : -4;
+}
+
+int oracle_vie2_timestep(int n, const oracle_grid* g, HMARGS(G), HMARGS(F), HMARGS(Fcc), HMARGS(Q)) {
+  return vie2_timestep(n, HMV(g, G), HMV(g, F), HMV(g, Fcc), HMV(g, Q)) ? 0 : -4;
+}
+
 void oracle_sigma_2b(int n, const oracle_grid* g, HMARGS(G), const double* U, HMARGS(S)) {
   sigma_2b(n, HMV(g, G), U, HMV(g, S));
 }

@@ -101,6 +101,10 @@ Mat Rt(const HM& G, int a, int b) { return retx(G, G, a, b); }
 Mat Lh(const HM& G, int a, int b) { return lesx(G, G, a, b); }
 Mat Adv(const HM& G, int a, int b) { return advx(G, G, a, b); }
 Mat Vt(const HM& G, int j, int n) { return vtx(G, G, j, n); }
+Mat RtX(const HM& X, const HM& Xc, int a, int b) { return retx(X, Xc, a, b); }
+Mat LhX(const HM& X, const HM& Xc, int a, int b) { return lesx(X, Xc, a, b); }
+Mat AdvX(const HM& X, const HM& Xc, int a, int b) { return advx(X, Xc, a, b); }
+Mat VtX(const HM& X, const HM& Xc, int j, int n) { return vtx(X, Xc, j, n); }
 
 Mat cm12(int m, const HM& A, const HM& B, const cd* f) { return cm12_impl(m, A, B, f); }
 Mat ctv23(int n, int m, const HM& A, const HM& B, const cd* f) { return ctv23_impl(n, m, A, B, f); }

@@ -103,6 +103,12 @@ Mat Rt(const HM& G, int a, int b);   // G^R_{a,b} for any a,b (b>a extended)
 Mat Lh(const HM& G, int a, int b);   // G^<_{a,b} for any a,b
 Mat Adv(const HM& G, int a, int b);  // G^A_{a,b} = (G~^R_{b,a})^dag
 Mat Vt(const HM& G, int j, int n);   // G^lceil(tau_j, t_n) = -xi (T_{n,ntau-j})^dag
+// The same for a function X that is not hermitian, with Xc = X^ddagger
+// supplying the values outside X's stored triangles.
+Mat RtX(const HM& X, const HM& Xc, int a, int b);   // X~^R_{a,b}
+Mat LhX(const HM& X, const HM& Xc, int a, int b);   // X^<_{a,b}
+Mat AdvX(const HM& X, const HM& Xc, int a, int b);  // X^A_{a,b} = ([Xc]~^R_{b,a})^dag
+Mat VtX(const HM& X, const HM& Xc, int j, int n);   // X^lceil(tau_j, t_n)
 
 // ------------------------------------------------------------ convolution
 // Sec. "Numerical details: convolution integrals": T[C]_n of C = A*f*B.
@@ -127,6 +133,17 @@ bool dyson_start(const HM& G, const HM& Sig, const Fn& eps);
 // non-conjugate/conjugate single steps, k+1 boundary points serial);
 // variant 'A': fully serial form.
 bool dyson_timestep(int n, const HM& G, const HM& Sig, const Fn& eps, char variant);
+
+// ------------------------------------------------------------------- vie2
+// Dyson equation in integral form, (1 + F) * G = Q with F^ddagger = Fcc
+// (Sec. "vie2: Dyson equation in integral form", Sec. "Implementation: vie2").
+// Matsubara: dense solve of the discrete Eq. vie2_langreth_m.
+bool vie2_mat(const HM& G, const HM& F, const HM& Q);
+// Start-up: slices 0..k (Sec. "Start" of the vie2 implementation).
+bool vie2_start(const HM& G, const HM& F, const HM& Fcc, const HM& Q);
+// Time step n > k: retarded and left-mixing rows by Eq. MBCVSAMx01_t, the
+// lesser column by the conjugate equation (variant B) for every row m <= n.
+bool vie2_timestep(int n, const HM& G, const HM& F, const HM& Fcc, const HM& Q);
 
 // --------------------------------------------------------- self-energies
 // Second-Born self-energy (Eq. sigma_hubb_2b, spin-symmetric) on slice n

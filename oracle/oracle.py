@@ -17,7 +17,7 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(HERE, "liboracle.so")
-SOURCES = ["weights.cpp", "linalg.cpp", "convolution.cpp", "dyson.cpp", "sigma.cpp", "capi.cpp"]
+SOURCES = ["weights.cpp", "linalg.cpp", "convolution.cpp", "dyson.cpp", "vie2.cpp", "sigma.cpp", "capi.cpp"]
 
 
 def build(verbose: bool = False) -> str:
@@ -181,6 +181,30 @@ def dyson_timestep(n, G: HM, S: HM, eps, variant="B"):
     e = np.ascontiguousarray(eps, np.complex128)
     return lib().oracle_dyson_timestep(n, C.byref(G.g.c()), *G.args(), *S.args(), _p(e),
                                        ord(variant))
+
+
+def vie2_mat(G: HM, F: HM, Q: HM):
+    """Matsubara part of (1 + F) * G = Q (Eq. vie2_langreth_m)."""
+    return lib().oracle_vie2_mat(C.byref(G.g.c()), *G.args(), *F.args(), *Q.args())
+
+
+def vie2_start(G: HM, F: HM, Fcc: HM, Q: HM):
+    """Slices 0..k of (1 + F) * G = Q (Sec. "Implementation: vie2", Start)."""
+    return lib().oracle_vie2_start(C.byref(G.g.c()), *G.args(), *F.args(), *Fcc.args(), *Q.args())
+
+
+def vie2_timestep(n, G: HM, F: HM, Fcc: HM, Q: HM):
+    """Slice n > k of (1 + F) * G = Q (Sec. "Implementation: vie2", Time stepping)."""
+    return lib().oracle_vie2_timestep(n, C.byref(G.g.c()), *G.args(), *F.args(), *Fcc.args(), *Q.args())
+
+
+def solve_vie2(G: HM, F: HM, Fcc: HM, Q: HM, nt_stop=None):
+    """Matsubara, start-up and every time step up to nt_stop; 0 or the first error."""
+    nt_stop = G.g.nt if nt_stop is None else nt_stop
+    rc = vie2_mat(G, F, Q) or vie2_start(G, F, Fcc, Q)
+    for n in range(G.g.k + 1, nt_stop + 1):
+        rc = rc or vie2_timestep(n, G, F, Fcc, Q)
+    return rc
 
 
 def sigma_2b(n, G: HM, U, S: HM):
