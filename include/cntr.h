@@ -142,6 +142,47 @@ cntr_status cntr_dyson_step(int32_t tstp, int32_t count, const cntr_grid* grids,
 cntr_status cntr_dyson_step_noalloc(int32_t tstp, int32_t count, const cntr_grid* grids, const cntr_gf* G,
                                     const cntr_gf* Sigma, const void* const* eps, void* stream);
 
+/* ------------------------------------------------------------------ F1 --
+ * Dyson equation in integral form (Sec. "vie2: Dyson equation in integral
+ * form", Tab. vie2; implementation Sec. "Implementation: vie2"):
+ *   (1 + F) * G = Q  (Eq. vie2),  equivalently  G * (1 + F^ddagger) = Q,
+ * for G and Q hermitian (Eq. ,masbX,. holds for the usual inputs, e.g.
+ * F = -G0 * Sigma, F^ddagger = -Sigma * G0, Q = G0). F[i] is not hermitian:
+ * Fcc[i] is its hermitian conjugate F^ddagger, which supplies the values
+ * outside F's stored triangles (and vice versa). Layouts as for G; every
+ * pointer is DEVICE memory, owned by the caller.
+ *
+ * cntr_vie2_matsubara: G^M + [F * G]^M = Q^M (Eq. vie2_langreth_m), the
+ * convolution by Eqs. cm1 + cm2, as one dense (ntau+1) d system: an explicit
+ * inverse (Gauss-Jordan, partial pivoting) and residual refinement to the
+ * relative tolerance tol (<= 0: 1e-14) in at most max_iter rounds (<= 0:
+ * 200). Reads F[i].mat and Q[i].mat, writes G[i].mat. Synchronizes the
+ * stream (norm readbacks), so it may not be captured. Errors: CNTR_ESHAPE
+ * (null pointers), CNTR_ESINGULAR, CNTR_ENOCONV, CNTR_ENOMEM.
+ *
+ * cntr_vie2_step:
+ *  tstp <= k : start-up, slices 0..k (Tab. vie2 row vie2_start): retarded
+ *              columns from the (k-m) d systems of Sec. "Start" with
+ *              G^R_{m,m} = Q^R_{m,m}; mixing rows per tau index and lesser
+ *              columns per n from the second-kind start-up rule
+ *              (Eq. MBCVSAMx01_start, kernel F^R). Reads slices -1..k of G
+ *              (G^M), F, Fcc and Q.
+ *  tstp  > k : time step (row vie2_timestep): slice tstp from slices
+ *              -1..tstp-1 of G, slices 0..tstp of F and Fcc, slice tstp of Q.
+ *              Retarded row and mixing row by one step of Eq. MBCVSAMx01_t
+ *              per column / tau index, the lesser column by one step of the
+ *              conjugate equation per row (variant B; every row m < tstp is
+ *              independent), then G^<_{tstp,tstp}.
+ * Instances with nt < tstp are skipped; writes slice(s) of G[i] only.
+ * Asynchronous on `stream`; uses the stream's step scratch (the size of the
+ * Dyson step's). A singular local step matrix is reported by cntr_sync
+ * (CNTR_ESINGULAR). Errors: CNTR_ESHAPE (null pointers, mixed d/k/ntau),
+ * CNTR_EORDER (tstp outside 0..nt, or, with order checks on, slices missing). */
+cntr_status cntr_vie2_matsubara(int32_t count, const cntr_grid* grids, const cntr_gf* G, const cntr_gf* F,
+                                const cntr_gf* Q, double tol, int32_t max_iter, void* stream);
+cntr_status cntr_vie2_step(int32_t tstp, int32_t count, const cntr_grid* grids, const cntr_gf* G, const cntr_gf* F,
+                           const cntr_gf* Fcc, const cntr_gf* Q, void* stream);
+
 /* ------------------------------------------------------------------ A8 --
  * Contour convolution C = A * f * B on time slice tstp (Eq. convolution,
  * Tab. convolution; discretised by Eqs. cm1, cm2, cr1, ctv1-ctv3,

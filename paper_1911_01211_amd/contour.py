@@ -88,6 +88,29 @@ def dyson_step_noalloc(tstp: int, G: list, Sigma: list, eps: list, stream=None):
                                          _stream(stream)))
 
 
+def vie2_matsubara(G: list, F: list, Q: list, tol=1e-14, max_iter=200, stream=None):
+    """G^M of (1 + F) * G = Q for each instance (cntr_vie2_matsubara)."""
+    _abi.check(_abi.lib().cntr_vie2_matsubara(len(G), _grids(G), _gfs(G), _gfs(F), _gfs(Q), tol, max_iter,
+                                               _stream(stream)))
+
+
+def vie2_step(tstp: int, G: list, F: list, Fcc: list, Q: list, stream=None):
+    """Start-up (tstp <= k: slices 0..k) or time step tstp of (1 + F) * G = Q
+    (cntr_vie2_step); Fcc[i] is the hermitian conjugate of F[i]."""
+    _abi.check(_abi.lib().cntr_vie2_step(tstp, len(G), _grids(G), _gfs(G), _gfs(F), _gfs(Fcc), _gfs(Q),
+                                          _stream(stream)))
+
+
+def solve_vie2(G: list, F: list, Fcc: list, Q: list, nt_stop=None, stream=None):
+    """Matsubara, start-up and every time step up to nt_stop."""
+    g = G[0].g
+    nt_stop = g.nt if nt_stop is None else nt_stop
+    vie2_matsubara(G, F, Q, stream=stream)
+    vie2_step(g.k, G, F, Fcc, Q, stream)
+    for n in range(g.k + 1, nt_stop + 1):
+        vie2_step(n, G, F, Fcc, Q, stream)
+
+
 def convolution(tstp: int, C_: list, A: list, Acc: list, B: list, Bcc: list, f=None, stream=None):
     L = _abi.lib()
     fp = None if f is None else _ptrs(f)

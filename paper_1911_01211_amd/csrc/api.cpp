@@ -356,14 +356,25 @@ struct MatsState {
 // Solve the discrete Matsubara equation for P (eps = eps_{-1} at entry 0,
 // Sigma^M in P.Smat) into P.Gmat. The current P.Gmat is the initial guess
 // when use_guess; the inverse of an earlier operator is reused when present.
+// The refinement of mats_solve for an operator in st.A and a right-hand side
+// in st.g (the current P.Gmat is the initial guess when use_guess, else st.g).
+cntr_status mats_refine(MatsState& st, const Prob& P, bool use_guess, double tol, int max_iter,
+                        hipStream_t s, int* iters);
+
 cntr_status mats_solve(MatsState& st, const Prob& P, bool use_guess, double tol, int max_iter,
                        hipStream_t s, int* iters) {
   hipError_t e;
-  int N = st.N, d = st.d;
-  size_t vec = (size_t)N * d * sizeof(cplx);
   if ((e = launch_free_mat(P, st.g, s))) return hip_fail(e, "free Matsubara function");
   if ((e = launch_mat_conv(P, st.g, P.Smat, nullptr, st.K, s))) return hip_fail(e, "[g*Sigma]^M");
   if ((e = launch_mat_build(P, st.K, st.A, s))) return hip_fail(e, "Matsubara operator");
+  return mats_refine(st, P, use_guess, tol, max_iter, s, iters);
+}
+
+cntr_status mats_refine(MatsState& st, const Prob& P, bool use_guess, double tol, int max_iter,
+                        hipStream_t s, int* iters) {
+  hipError_t e;
+  int N = st.N, d = st.d;
+  size_t vec = (size_t)N * d * sizeof(cplx);
   if (!use_guess && (e = hipMemcpyAsync(P.Gmat, st.g, vec, hipMemcpyDeviceToDevice, s)))
     return hip_fail(e, "initial guess");
   double prev = -1;
@@ -844,6 +855,87 @@ cntr_status cntr_init_matsubara(int32_t count, const cntr_grid* grids, const cnt
     if ((st = mats_solve(ms, P, false, tol, max_iter, s, nullptr))) return st;
   }
   order_mark(count, G, -1, true);
+  return CNTR_OK;
+}
+
+// ------------------------------------------ Dyson equation in integral form
+// Problem descriptor of (1 + F) * G = Q (the layout described at Prob).
+static Prob vie2_prob(const cntr_grid& g, const cntr_gf* G, const cntr_gf* F, const cntr_gf* Fcc, const cntr_gf* Q) {
+  Prob p = make_prob(g, G, nullptr, nullptr);
+  p.Smat = (cplx*)F->mat;
+  p.Sret = (cplx*)F->ret;
+  p.Stv = (cplx*)F->tv;
+  p.Fles = (const cplx*)F->les;
+  if (Fcc) {
+    p.Sles = (cplx*)Fcc->les;
+    p.Fcret = (const cplx*)Fcc->ret;
+  }
+  p.Qmat = (const cplx*)Q->mat;
+  p.Qret = (const cplx*)Q->ret;
+  p.Qles = (const cplx*)Q->les;
+  p.Qtv = (const cplx*)Q->tv;
+  return p;
+}
+
+cntr_status cntr_vie2_matsubara(int32_t count, const cntr_grid* grids, const cntr_gf* G, const cntr_gf* F,
+                                const cntr_gf* Q, double tol, int32_t max_iter, void* stream) {
+  if (capturing((hipStream_t)stream))
+    return fail(CNTR_EINVAL, "cntr_vie2_matsubara: synchronizes the stream, not allowed during graph capture");
+  cntr_status st = check_batch(count, grids, "cntr_vie2_matsubara");
+  if (st) return st;
+  if (!gf_ok(G, count) || !gf_ok(F, count) || !gf_ok(Q, count))
+    return fail(CNTR_ESHAPE, "cntr_vie2_matsubara: null pointer");
+  if ((st = ensure_weights())) return st;
+  hipStream_t s = (hipStream_t)stream;
+  if (tol <= 0) tol = 1e-14;
+  if (max_iter <= 0) max_iter = 200;
+  MatsState ms;
+  if ((st = ms.alloc(grids[0].ntau, grids[0].d))) return st;
+  size_t vec = (size_t)ms.N * ms.d * sizeof(cplx);
+  for (int i = 0; i < count; i++) {
+    Prob P = vie2_prob(grids[i], &G[i], &F[i], nullptr, &Q[i]);
+    hipError_t e;
+    // G_m + [F * G]^M(m) = Q_m (Eq. vie2_langreth_m) as one dense system
+    if ((e = launch_mat_build(P, P.Smat, ms.A, s, +1.0))) return hip_fail(e, "vie2 Matsubara operator");
+    if ((e = hipMemcpyAsync(ms.g, P.Qmat, vec, hipMemcpyDeviceToDevice, s))) return hip_fail(e, "vie2 source");
+    ms.have_inv = false;
+    if ((st = mats_refine(ms, P, false, tol, max_iter, s, nullptr))) return st;
+  }
+  order_mark(count, G, -1, true);
+  return CNTR_OK;
+}
+
+cntr_status cntr_vie2_step(int32_t tstp, int32_t count, const cntr_grid* grids, const cntr_gf* G, const cntr_gf* F,
+                           const cntr_gf* Fcc, const cntr_gf* Q, void* stream) {
+  cntr_status st = check_batch(count, grids, "cntr_vie2_step");
+  if (st) return st;
+  if (count > STAT_WORDS) return fail(CNTR_ESHAPE, "cntr_vie2_step: more than 65536 problems");
+  if (!gf_ok(G, count) || !gf_ok(F, count) || !gf_ok(Fcc, count) || !gf_ok(Q, count))
+    return fail(CNTR_ESHAPE, "cntr_vie2_step: null pointer");
+  int k = grids[0].k, d = grids[0].d, ntau = grids[0].ntau;
+  int ntmax = 0;
+  for (int i = 0; i < count; i++)
+    if (grids[i].nt > ntmax) ntmax = grids[i].nt;
+  if (tstp < 0 || tstp > ntmax) return fail(CNTR_EORDER, "cntr_vie2_step: tstp outside 0..nt");
+  if ((st = order_check(tstp, k, count, G, "cntr_vie2_step"))) return st;
+  if ((st = ensure_weights())) return st;
+  hipStream_t s = (hipStream_t)stream;
+  StreamScratch* sc = scratch_for(s);
+  cntr_grid gmax = grids[0];
+  gmax.nt = ntmax < k + 1 ? k + 1 : ntmax;
+  StepScratch lay = step_layout(gmax);
+  if ((st = grow(s, sc, lay.per * count, 5 * (size_t)count, 2 * (size_t)count))) return st;
+  std::vector<Prob> v(count);
+  for (int i = 0; i < count; i++) v[i] = vie2_prob(grids[i], &G[i], &F[i], &Fcc[i], &Q[i]);
+  ProbArg pa;
+  if ((st = make_arg(s, sc, v, 0, &pa))) return st;
+  Scratch scr = lay.sc;
+  scr.base = sc->data();
+  scr.stat = sc->stat();
+  sc->nstat = std::max(sc->nstat, (int)count);
+  hipError_t e = tstp <= k ? launch_vie2_start(pa, scr, d, ntau, s) : launch_vie2_step(pa, scr, tstp, d, s);
+  if (e != hipSuccess) return hip_fail(e, "cntr_vie2_step launch");
+  order_mark(count, G, tstp <= k ? k : tstp, false);
   return CNTR_OK;
 }
 

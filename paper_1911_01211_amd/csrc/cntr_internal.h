@@ -92,6 +92,11 @@ struct Prob {
   const cplx* eps0;  // (nt+2) d*d
   cplx* eps_mf;      // (nt+2) d*d or null
   const cplx* f;     // (nt+2) d*d or null (convolution weight function)
+  // Dyson equation in integral form, (1 + F) * G = Q: the S pointers hold
+  // F^M, F^R, F^rceil and Fcc^< (Fcc = F^ddagger); the start-up also reads
+  // F^< (rows m > j come from Fcc^<) and Fcc^R (F^R continued to t < t')
+  const cplx *Qmat, *Qret, *Qles, *Qtv;
+  const cplx *Fles, *Fcret;
 };
 
 __host__ __device__ inline size_t tri(int n) { return (size_t)n * (n + 1) / 2; }

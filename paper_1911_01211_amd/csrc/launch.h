@@ -47,6 +47,9 @@ struct HistPlan {
   int du_np;             // triangular panels with units: 1 (R), 2 (R, L)
   int du_full, du_part;  // units per triangular panel below the diagonal / meeting it
   int du_total;          // units per problem
+  // Dyson equation in integral form: the set-up workgroup forms the
+  // second-kind step matrices instead of the Dyson set-up
+  int vie2;
 };
 
 // d = 4 one-pass units: positions per unit and the chunk bounds of the units
@@ -130,6 +133,11 @@ hipError_t launch_peierls_grad(const cplx* T, const double* Phi, const double* A
                                double* A_bar, int d, int nt, hipStream_t s);
 hipError_t launch_sigma_local(const ProbArg& pa, int n, int d, int nelems, double lam, hipStream_t s);
 
+// Dyson equation in integral form, (1 + F) * G = Q: start-up (slices 0..k)
+// and time step n > k (problem descriptors as described at Prob)
+hipError_t launch_vie2_start(const ProbArg& pa, const Scratch& sc, int d, int ntau, hipStream_t s);
+hipError_t launch_vie2_step(const ProbArg& pa, const Scratch& sc, int n, int d, hipStream_t s);
+
 // Matsubara pieces (per problem, one problem per call)
 hipError_t launch_free_mat(const Prob& P, cplx* g, hipStream_t s);
 // free Green's function of eps(t) into every component of P's G (scratch of
@@ -138,7 +146,8 @@ size_t free_green_scratch_bytes(int nt, int ntau, int d);
 hipError_t launch_free_green(const Prob& P, void* scratch, hipStream_t s);
 hipError_t launch_mat_conv(const Prob& P, const cplx* A, const cplx* B, const cplx* f,
                            cplx* out, hipStream_t s);
-hipError_t launch_mat_build(const Prob& P, const cplx* K, cplx* Amat, hipStream_t s);
+// sgn = -1: A = 1 - B[K] (Dyson, K = [g * Sigma]^M); sgn = +1: A = 1 + B[K]
+hipError_t launch_mat_build(const Prob& P, const cplx* K, cplx* Amat, hipStream_t s, double sgn = -1.0);
 // Fourier-series solve of the Matsubara equation into P.Gmat (P.Smat null: Sigma = 0),
 // oversampling p (work: mats_fourier_scratch_bytes)
 size_t mats_fourier_scratch_bytes(int ntau, int d, int p);

@@ -2,6 +2,7 @@
 // are shared by every kernel without relocatable device code).
 #include "weights.cpp"
 #include "step.hip"
+#include "vie2.hip"
 #include "misc.hip"
 #include "mats.hip"
 #include "adjoint.hip"

@@ -141,9 +141,9 @@ hipError_t launch_free_mat(const Prob& P, cplx* g, hipStream_t s) {
 }
 
 // ------------------------------------------------------ dense operator
-// A = 1 - B with B_{m,l} the coefficient of G^M_l in [K * G]^M(m)
+// A = 1 + sgn B with B_{m,l} the coefficient of G^M_l in [K * G]^M(m)
 // (Eqs. cm1, cm2 with f = 1).
-__global__ __launch_bounds__(NT3) void k_mat_build(Prob P, const cplx* K, cplx* Amat) {
+__global__ __launch_bounds__(NT3) void k_mat_build(Prob P, const cplx* K, cplx* Amat, double sgn) {
   int d = P.d, dd = d * d, nt = P.ntau, k = P.k;
   long N = (long)(nt + 1) * d;
   long idx = (long)blockIdx.x * NT3 + threadIdx.x;
@@ -167,15 +167,15 @@ __global__ __launch_bounds__(NT3) void k_mat_build(Prob P, const cplx* K, cplx* 
   } else if (l >= m) {
     v = v + (ht * xi * greg(W, nt - m, l - m)) * K[(size_t)(nt - (l - m)) * dd + a * d + b];
   }
-  v = -v;
+  v = sgn * v;
   if (row == col) v.x += 1.0;
   Amat[idx] = v;
 }
 
-hipError_t launch_mat_build(const Prob& P, const cplx* K, cplx* Amat, hipStream_t s) {
+hipError_t launch_mat_build(const Prob& P, const cplx* K, cplx* Amat, hipStream_t s, double sgn) {
   long N = (long)(P.ntau + 1) * P.d;
   long tot = N * N;
-  k_mat_build<<<(unsigned)((tot + NT3 - 1) / NT3), NT3, 0, s>>>(P, K, Amat);
+  k_mat_build<<<(unsigned)((tot + NT3 - 1) / NT3), NT3, 0, s>>>(P, K, Amat, sgn);
   return hipGetLastError();
 }
 

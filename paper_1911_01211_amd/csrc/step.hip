@@ -1928,6 +1928,10 @@ __device__ __forceinline__ void hist_mfma8(const Prob& P, const Scratch& sc, int
   }
 }
 
+// set-up of a time step of the Dyson equation in integral form (vie2.hip)
+template <int D>
+__device__ void v2_prep(const Prob& P, const Scratch& sc, int pi, int n, cplx* lds);
+
 // ------------------------------------------------------------- HISTORY
 template <int D>
 __global__ __launch_bounds__(NTHR) void k_history(ProbArg pa, Scratch sc, HistPlan pl) {
@@ -1961,7 +1965,8 @@ __global__ __launch_bounds__(NTHR) void k_history(ProbArg pa, Scratch sc, HistPl
   int b = blockIdx.x - 1;
   if (b < 0) {
     // (d = 8: the set-up has a kernel of its own, k_prep, launched before)
-    if constexpr (D != 8) prep_step<D>(P, sc, pi, n, lds);
+    if (pl.vie2) v2_prep<D>(P, sc, pi, n, lds);
+    else if constexpr (D != 8) prep_step<D>(P, sc, pi, n, lds);
     return;
   }
   if constexpr (D == 4) {  // (one-pass units after the tau jobs)
