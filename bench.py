@@ -217,6 +217,87 @@ def run_mats_fourier(state):
             "max_abs_GM": float(Gx.mat.abs().max())}
 
 
+def run_vie2(state):
+    """Dyson equation in integral form (cntr_vie2_matsubara, cntr_vie2_step) on
+    the chain's grid: Q = G_0 (free function of the converged mean-field
+    levels), F = -G_0 * Sigma, Fcc = -Sigma * G_0 (Sigma the converged 2B
+    self-energy, held fixed; built with cntr_green_from_H and cntr_convolution
+    before the timed region). Timed with HIP events on the launch stream: the
+    whole solve (Matsubara, start-up, 995 steps) and the steps alone; beside
+    it the integro-differential solve of the same equation (fixed Sigma) and
+    the largest deviation of the two solutions. `achieved` counts the history
+    bytes of the steps (each stored block of G and of F's row once per step)
+    over the step phase."""
+    import torch
+
+    from paper_1911_01211_amd import contour as K
+
+    G, S, emf = state["G"], state["S"], state["emf"]
+    g = G.g
+    dev = "cuda:0"
+    G0, F, Fcc, Gv, Gd = (K.Contour(g, dev) for _ in range(5))
+    K.green_from_H([G0], [emf])
+    for n in range(-1, g.nt + 1):
+        K.convolution(n, [F], [G0], [G0], [S], [S])
+        K.convolution(n, [Fcc], [S], [S], [G0], [G0])
+    for X in (F, Fcc):
+        for key in K.KEYS:
+            getattr(X, key).neg_()
+    torch.cuda.synchronize()
+
+    def ev():
+        return torch.cuda.Event(enable_timing=True)
+
+    # warm-up, then the timed solves
+    K.solve_vie2([Gv], [F], [Fcc], [G0])
+    K.sync()
+    reps, whole, steps = 2, [], []
+    for _ in range(reps):
+        e0, e1, e2 = ev(), ev(), ev()
+        e0.record()
+        K.vie2_matsubara([Gv], [F], [G0])
+        K.vie2_step(g.k, [Gv], [F], [Fcc], [G0])
+        e1.record()
+        for n in range(g.k + 1, g.nt + 1):
+            K.vie2_step(n, [Gv], [F], [Fcc], [G0])
+        e2.record()
+        torch.cuda.synchronize()
+        whole.append(e0.elapsed_time(e2))
+        steps.append(e1.elapsed_time(e2))
+    K.sync()
+    # the integro-differential form of the same equation
+    B = K.Batch([Gd], [S], [emf])
+    d0, d1, d2 = ev(), ev(), ev()
+    d0.record()
+    B.init_matsubara()
+    B.step(g.k)
+    d1.record()
+    for n in range(g.k + 1, g.nt + 1):
+        B.step(n)
+    d2.record()
+    torch.cuda.synchronize()
+    K.sync()
+    dev_max = max(float((getattr(Gv, key) - getattr(Gd, key)).abs().max()) for key in K.KEYS)
+    ref = max(float(getattr(Gd, key).abs().max()) for key in K.KEYS)
+    nsteps = g.nt - g.k
+    st_ms = min(steps)
+    dd = g.d * g.d
+    nbytes = 0.0
+    for n in range(g.k + 1, g.nt + 1):
+        blocks = n * (n + 1) / 2 + n * (g.ntau + 1) + (n * (n + 1) / 2 if n >= 2 * g.k + 1 else 0)
+        nbytes += 16.0 * dd * blocks
+    gbs = nbytes / (st_ms * 1e-3) / 1e9
+    return {"workload": "Dyson equation of the converged 2B chain in integral form (d=4, nt=1000, ntau=400, "
+                        "k=5): Q = G_0, F = -G_0*Sigma, Fcc = -Sigma*G_0, Sigma fixed",
+            "value": nsteps / (min(whole) * 1e-3), "unit": "time-steps/s",
+            "ms_per_solve": min(whole), "ms_steps": st_ms, "us_per_step": st_ms * 1e3 / nsteps,
+            "dyson_form": {"ms_per_solve": d0.elapsed_time(d2), "ms_steps": d1.elapsed_time(d2)},
+            "max_abs_deviation_from_dyson_form": dev_max, "max_abs_G": ref,
+            "roofline": {"bound": "hbm", "scope": "time steps (k_v2_side, k_history, k_v2_reduce, k_v2_final)",
+                         "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+                         "bytes": nbytes}}
+
+
 def adj_sigma_products(n, k, ntau):
     """Block products of the Sigma-bar reductions of reverse step n (the term
     ranges of the adjoint kernels: retarded outputs j < n with min(j, nb-1)+1
@@ -625,6 +706,7 @@ def main():
     ap.add_argument("--no-uneven", action="store_true")
     ap.add_argument("--no-free", action="store_true")
     ap.add_argument("--no-cfg1", action="store_true")
+    ap.add_argument("--no-vie2", action="store_true")
     ap.add_argument("--no-tune-cache", action="store_true", help="built-in term chunks instead of tune_cache.json")
     ap.add_argument("--uneven-count", type=int, default=64, help="problems of the uneven batch (of 384)")
     ap.add_argument("--uneven-nt", type=int, default=400, help="slices of each uneven problem (causal prefix)")
@@ -690,6 +772,8 @@ def main():
         "tiles": None if tiles is None else {d: {"n_hi": e["n_hi"], "tj": e["tj"]} for d, e in tiles["entries"].items()},
     }
     out["matsubara_fourier"] = run_mats_fourier(state)
+    if not args.no_vie2:
+        out["vie2"] = run_vie2(state)
     del state
     if not args.no_adjoint:
         out["adjoint"] = run_adjoint(args)

@@ -47,9 +47,12 @@ struct HistPlan {
   int du_np;             // triangular panels with units: 1 (R), 2 (R, L)
   int du_full, du_part;  // units per triangular panel below the diagonal / meeting it
   int du_total;          // units per problem
-  // Dyson equation in integral form: the set-up workgroup forms the
-  // second-kind step matrices instead of the Dyson set-up
+  // Dyson equation in integral form: no Dyson set-up in the history kernel;
+  // v2_rows x v2_nch workgroups of k_v2_side sum the lesser rows v2_lo.. in
+  // chunks of v2_ch terms
   int vie2;
+  int v2_lo, v2_rows, v2_ch, v2_nch;
+  long v2_off, v2_doff;  // partials of those rows, and of G^<_{n,n} (in blocks)
 };
 
 // d = 4 one-pass units: positions per unit and the chunk bounds of the units

@@ -214,6 +214,19 @@ HistPlan make_plan(int n, int k, int ntau, int d, int tau_split, int du_nsb) {
   p.red_tiles[2] = les_bulk ? cdiv_i(nb, rtm) : 0;
   p.tail_off = off;
   off += (long)(p.red_tiles[0] + p.red_tiles[1] + p.red_tiles[2]) * (k + 1);
+  // Dyson equation in integral form: the lesser rows without history-job
+  // outputs (m >= n-k; every m < n for n <= 2k) are summed in chunks of
+  // v2_ch terms by extra workgroups (row m has max(m,k)+1 + n + ntau+1
+  // terms); their partials, then one partial of G^<_{n,n} per reduce
+  // workgroup
+  p.v2_lo = les_bulk ? nb : 0;
+  p.v2_rows = n - p.v2_lo;
+  p.v2_ch = 4 * rtm;
+  p.v2_nch = cdiv_i((n - 1 > k ? n - 1 : k) + 1 + n + ntau + 1, p.v2_ch);
+  p.v2_off = off;
+  off += (long)p.v2_rows * p.v2_nch;
+  p.v2_doff = off;
+  off += p.red_tiles[0] + p.red_tiles[1] + p.red_tiles[2] + 1;
   p.total_blocks = off;
   return p;
 }
@@ -224,6 +237,9 @@ size_t step_scratch_bytes(int nt, int k, int ntau, int d) {
   // few n of every band of chunks (the last slices, and the last slices of
   // each autotuned band)
   std::vector<int> ns = {nt, nt - 1};
+  // (up to n = 2k the boundary lesser rows of the integral form are every
+  // row, so a smaller n can need more)
+  for (int n = k + 1; n <= nt && n <= 2 * k + 2; n++) ns.push_back(n);
   const TileTable& t = g_tiles[d];
   for (int b = 0; b < t.nb; b++) {
     int e = t.n_hi[b] < nt ? t.n_hi[b] : nt;
@@ -255,7 +271,7 @@ __device__ inline cplx ehat(const Prob& P, int n, int x, int y) {
 // M_R^-1 for the step and the retarded boundary R_{n,n-l}, l = 0..k
 // (conjugate start-up, Eq. MBCVSAMx_cc_start).
 template <int D>
-__device__ void prep_step(const Prob& P, const Scratch& sc, int pi, int n, cplx* lds) {
+__device__ __forceinline__ void prep_step(const Prob& P, const Scratch& sc, int pi, int n, cplx* lds) {
   constexpr int DD = D * D;
   constexpr int K1M = KMAX + 1;
   const KW& W = c_kw[P.k];
@@ -456,7 +472,7 @@ __device__ void prep_step(const Prob& P, const Scratch& sc, int pi, int n, cplx*
 // and sum_J w(ntau-m, J-m) Sigma^rceil_{n,J} G^M_{J-m} for m < ntau-k. Both
 // bands of operands are staged in LDS.
 template <int D>
-__device__ void tau_source_tile(const Prob& P, const Scratch& sc, int pi, int n, const HistPlan& pl,
+__device__ __forceinline__ void tau_source_tile(const Prob& P, const Scratch& sc, int pi, int n, const HistPlan& pl,
                                 int mt, int ch, cplx* lds) {
   constexpr int DD = D * D;
   constexpr int TM = NTHR / DD > 0 ? NTHR / DD : 1;
@@ -801,7 +817,7 @@ __device__ __forceinline__ void rows_fused(int jb, int je, int j0, int nro, cplx
 }
 
 template <int D>
-__device__ void hist_blk(const Prob& P, const Scratch& sc, int pi, int n, const HistPlan& pl, int job,
+__device__ __forceinline__ void hist_blk(const Prob& P, const Scratch& sc, int pi, int n, const HistPlan& pl, int job,
                          int mt, int ch, cplx* lds) {
   constexpr int DD = D * D;
   constexpr int K1 = KMAX + 1;
@@ -954,7 +970,7 @@ __device__ void hist_blk(const Prob& P, const Scratch& sc, int pi, int n, const 
 // The operands indexed by J alone are staged in LDS, the banded ones are read
 // per lane from the (cache-resident) Sigma row and G^M.
 template <int D>
-__device__ void tau_blk(const Prob& P, const Scratch& sc, int pi, int n, const HistPlan& pl, int mt, int ch,
+__device__ __forceinline__ void tau_blk(const Prob& P, const Scratch& sc, int pi, int n, const HistPlan& pl, int mt, int ch,
                         cplx* lds) {
   constexpr int DD = D * D;
   const KW& W = c_kw[P.k];
@@ -1035,6 +1051,11 @@ struct Stg {
   }
 };
 
+// The functions that stage through LDS are inlined into the kernels
+// (__forceinline__): there the buffers are known LDS, and the compiler waits
+// for a step's direct-to-LDS copy before its reads. Compiled as a called
+// function with a generic buffer pointer, the reads became flat loads that
+// were not ordered after the copies.
 // Copy the 64 blocks of one step into wbuf; baddr(b) gives block b (readable).
 template <int D, class BAddr>
 __device__ inline void stg_copy(cplx* wbuf, BAddr baddr) {
@@ -1097,7 +1118,7 @@ __device__ inline void stg_sum_store(cplx (&acc)[D * D], cplx* red, bool row, in
 }
 
 template <int D>
-__device__ void hist_stg(const Prob& P, const Scratch& sc, int pi, int n, const HistPlan& pl, int job,
+__device__ __forceinline__ void hist_stg(const Prob& P, const Scratch& sc, int pi, int n, const HistPlan& pl, int job,
                          int mt, int ch, cplx* lds, cplx* sh) {
   using S = Stg<D>;
   constexpr int DD = D * D;
@@ -1245,7 +1266,7 @@ __device__ void hist_stg(const Prob& P, const Scratch& sc, int pi, int n, const 
 // xi w(m,J) Sigma^rceil_{n,m-J} G^M_{ntau-J} (m > k, J <= m) and band 2
 // w(ntau-m, J-m) Sigma^rceil_{n,J} G^M_{J-m} (m < ntau-k, J >= m).
 template <int D>
-__device__ void tau_stg(const Prob& P, const Scratch& sc, int pi, int n, const HistPlan& pl, int mt, int ch,
+__device__ __forceinline__ void tau_stg(const Prob& P, const Scratch& sc, int pi, int n, const HistPlan& pl, int mt, int ch,
                         cplx* lds, cplx* sh) {
   using S = Stg<D>;
   constexpr int DD = D * D;
@@ -1562,7 +1583,7 @@ __device__ __forceinline__ void hist_dual_panel(const Prob& P, const Scratch& sc
 // alternating), the mixing panel's, then the triangular units that meet the
 // diagonal (fewer blocks), so that the short units come last
 template <int D>
-__device__ void hist_dual(const Prob& P, const Scratch& sc, int pi, int n, const HistPlan& pl, int u, cplx* lds) {
+__device__ __forceinline__ void hist_dual(const Prob& P, const Scratch& sc, int pi, int n, const HistPlan& pl, int u, cplx* lds) {
   constexpr int K1 = KMAX + 1;
   __shared__ double s_om[K1];
   __shared__ double s_s[K1 * K1];
@@ -1928,10 +1949,6 @@ __device__ __forceinline__ void hist_mfma8(const Prob& P, const Scratch& sc, int
   }
 }
 
-// set-up of a time step of the Dyson equation in integral form (vie2.hip)
-template <int D>
-__device__ void v2_prep(const Prob& P, const Scratch& sc, int pi, int n, cplx* lds);
-
 // ------------------------------------------------------------- HISTORY
 template <int D>
 __global__ __launch_bounds__(NTHR) void k_history(ProbArg pa, Scratch sc, HistPlan pl) {
@@ -1965,8 +1982,9 @@ __global__ __launch_bounds__(NTHR) void k_history(ProbArg pa, Scratch sc, HistPl
   int b = blockIdx.x - 1;
   if (b < 0) {
     // (d = 8: the set-up has a kernel of its own, k_prep, launched before)
-    if (pl.vie2) v2_prep<D>(P, sc, pi, n, lds);
-    else if constexpr (D != 8) prep_step<D>(P, sc, pi, n, lds);
+    // (the integral form sets its step up in k_v2_side)
+    if constexpr (D != 8)
+      if (!pl.vie2) prep_step<D>(P, sc, pi, n, lds);
     return;
   }
   if constexpr (D == 4) {  // (one-pass units after the tau jobs)

@@ -8,7 +8,7 @@
 // and F^M, the lesser jobs read Fcc^< and, through the conjugate relations
 // Fcc^A_{l,n} = (F^R_{n,l})^dag and Fcc^lceil(tau_j, t_n) = -xi
 // (F^rceil_{n,ntau-j})^dag, F^R and F^rceil. So k_history runs unchanged (its
-// set-up workgroup forms the step matrices below), and k_v2_reduce applies the
+// set-up is k_v2_side's), and k_v2_reduce applies the
 // second-kind local step (Eq. MBCVSAMx01_t and its conjugate):
 //   G^R_{n,m}       = [1 + h w F^R_{n,n}]^-1 (Q^R_{n,m} - h C^R_{n,m}),
 //   G^rceil_{n,m}   = [1 + h omega_0 F^R_{n,n}]^-1 (Q^rceil_{n,m} - C^rceil_{n,m}),
@@ -16,8 +16,11 @@
 // with w = omega_0 for n - m > k and w = s_{n-m,0} for the rows n-m <= k,
 // whose interval is shorter than k+1 points (Eq. cr1, second case; summed
 // directly, as are the lesser rows m >= n-k, for which the history kernel
-// has no outputs). 1 + h omega_0 Fcc^A_{n,n} is the adjoint of the retarded
-// step matrix. k_v2_diag finally forms G^<_{n,n} from the finished column.
+// has no outputs: k_v2_side sums those in chunks,
+// k_v2_final solves them). 1 + h omega_0 Fcc^A_{n,n} is the adjoint of the
+// retarded step matrix. G^<_{n,n} needs the finished row and column of
+// slice n: every reduce workgroup adds its outputs' terms into a partial,
+// k_v2_final sums them and solves.
 //
 // Start-up (slices 0..k): the retarded columns m = 0..k-1 from the
 // (k-m) d system of Sec. "Start" (one workgroup per problem, in order of m),
@@ -46,8 +49,8 @@ __device__ inline cplx v2_fles(const Prob& P, int m, int j, int x, int y) {
 // Inverses of the local step matrices 1 + h w F^R_{n,n} into slots r = 0..k
 // of the problem's matrix scratch: w = omega_0 (slot 0: rows with n - m > k,
 // the mixing row, and the lesser column through the adjoint) and
-// w = s_{r,0} (slot r: the retarded row m = n - r). Run by the first
-// workgroup of k_history, beside the history sums.
+// w = s_{r,0} (slot r: the retarded row m = n - r). The first workgroup of
+// k_v2_side.
 template <int D>
 __device__ void v2_prep(const Prob& P, const Scratch& sc, int pi, int n, cplx* lds) {
   constexpr int DD = D * D;
@@ -70,94 +73,119 @@ __device__ void v2_prep(const Prob& P, const Scratch& sc, int pi, int n, cplx* l
   for (int idx = tid; idx < (k + 1) * DD; idx += NTHR) gst(sc.minv(pi) + idx, lds[idx]);
 }
 
-// ---------------------------------------------------------- lesser by rows
-// Row m <= n of the lesser column n by direct sums (variant B), the whole
-// workgroup: NTHR / d^2 thread groups take every NG-th term, their sums are
-// added in a fixed order.
+// ------------------------------------------------- lesser boundary rows
+// Lesser rows m = v2_lo .. n-1 of column n, for which the history jobs have
+// no outputs (m >= n-k; every m < n for n <= 2k), by the other workgroups
+// of k_v2_side (they read only earlier slices). With the terms of row m
+// numbered t < T1 (C1, j = t), T1 <= t < T1 + n (C2, l = t - T1) and the
+// ntau+1 tau terms after them, workgroup (r, ch) sums the terms
+// ch*v2_ch .. +v2_ch-1 of row v2_lo + r into one d x d partial of
 //   C^<_{m,n} = h (C1 + C2) - i h_tau C3,
-//   C1 = sum_j w G~^R_{m,j} Fcc^<_{j,n}                         (Eq. cles1)
-//   C2 = sum_{l<n} w(n,l) G^<_{m,l} (F^R_{n,l})^dag              (Eq. cles2, l = n local)
-//   C3 = sum_j w(ntau,j) G^rceil_{m,j} (-xi) (F^rceil_{n,ntau-j})^dag   (Eq. cles3)
-// and G^<_{m,n} = (Q^<_{m,n} - C^<_{m,n}) (M^-1)^dag, M^-1 = minv (slot 0).
+//   C1 = sum_j w G~^R_{m,j} Fcc^<_{j,n}                          (Eq. cles1)
+//   C2 = sum_{l<n} w(n,l) G^<_{m,l} (F^R_{n,l})^dag  (Fcc^A; Eq. cles2, l = n local)
+//   C3 = sum_j w(ntau,j) G^rceil_{m,j} (-xi) (F^rceil_{n,ntau-j})^dag  (Fcc^lceil; Eq. cles3)
+// (NTHR / d^2 thread groups, four terms each, summed in a fixed order).
 template <int D>
-__device__ void v2_les_row(const Prob& P, int n, int m, const cplx* minv, cplx* red) {
+__device__ void v2_edge_part(const Prob& P, const Scratch& sc, int pi, int n, const HistPlan& pl, int r, int ch,
+                             cplx* lds) {
   constexpr int DD = D * D, NG = NTHR / DD > 0 ? NTHR / DD : 1;
   const KW& W = c_kw[P.k];
   int k = P.k, ntau = P.ntau, tid = threadIdx.x;
   double h = P.h, ht = P.htau, xi = P.sig;
+  int m = pl.v2_lo + r;
+  int T1 = (m > k ? m : k) + 1, T2 = T1 + n, T3 = T2 + ntau + 1;
   int g = tid / DD, e = tid % DD, a = e / D, c = e % D;
-  cplx s12 = mk(0, 0), s3 = mk(0, 0);
   if (g < NG) {
-    int j1 = m > k ? m : k;
-    for (int j = g; j <= j1; j += NG) {
-      double w = m > k ? greg(W, m, j) : W.s[m][j];
-      cplx t = mk(0, 0);
+    cplx acc = mk(0, 0);
 #pragma unroll
-      for (int q = 0; q < D; q++) cfma(t, ret_ext_d(P.Gret, m, j, a, q, D), gld(P.Sles + (tri(n) + j) * DD + q * D + c));
-      s12 = s12 + w * t;
-    }
-#pragma unroll 2
-    for (int l = g; l < n; l += NG) {
-      cplx t = mk(0, 0);
+    for (int i = 0; i < 4; i++) {
+      int t = ch * pl.v2_ch + i * NG + g;
+      if (t < T1) {
+        int j = t;
+        double w = m > k ? greg(W, m, j) : W.s[m][j];
+        cplx s = mk(0, 0);
 #pragma unroll
-      for (int q = 0; q < D; q++) cfma_cb(t, les_any_d(P.Gles, m, l, a, q, D), gld(P.Sret + (tri(n) + l) * DD + c * D + q));
-      s12 = s12 + greg(W, n, l) * t;
-    }
-#pragma unroll 2
-    for (int j = g; j <= ntau; j += NG) {
-      cplx t = mk(0, 0);
-      const cplx* gt = P.Gtv + ((size_t)m * (ntau + 1) + j) * DD + a * D;
-      const cplx* ft = P.Stv + ((size_t)n * (ntau + 1) + ntau - j) * DD + c * D;
+        for (int q = 0; q < D; q++) cfma(s, ret_ext_d(P.Gret, m, j, a, q, D), gld(P.Sles + (tri(n) + j) * DD + q * D + c));
+        acc = acc + (h * w) * s;
+      } else if (t < T2) {
+        int l = t - T1;
+        cplx s = mk(0, 0);
 #pragma unroll
-      for (int q = 0; q < D; q++) cfma_cb(t, gld(gt + q), gld(ft + q));
-      s3 = s3 + (-xi * greg(W, ntau, j)) * t;
+        for (int q = 0; q < D; q++) cfma_cb(s, les_any_d(P.Gles, m, l, a, q, D), gld(P.Sret + (tri(n) + l) * DD + c * D + q));
+        acc = acc + (h * greg(W, n, l)) * s;
+      } else if (t < T3) {
+        int j = t - T2;
+        const cplx* gt = P.Gtv + ((size_t)m * (ntau + 1) + j) * DD + a * D;
+        const cplx* ft = P.Stv + ((size_t)n * (ntau + 1) + ntau - j) * DD + c * D;
+        cplx s = mk(0, 0);
+#pragma unroll
+        for (int q = 0; q < D; q++) cfma_cb(s, gld(gt + q), gld(ft + q));
+        acc = acc - mul_i((ht * -xi * greg(W, ntau, j)) * s);
+      }
     }
-    red[g * DD + e] = h * s12 - ht * mul_i(s3);
+    lds[g * DD + e] = acc;
   }
   __syncthreads();
   if (tid < DD) {
     cplx sum = mk(0, 0);
-    for (int gg = 0; gg < NG; gg++) sum = sum + red[gg * DD + tid];
-    red[NG * DD + tid] = gld(P.Qles + (tri(n) + m) * DD + tid) - sum;
+    for (int gg = 0; gg < NG; gg++) sum = sum + lds[gg * DD + tid];
+    gst(sc.part(pi) + (pl.v2_off + (long)r * pl.v2_nch + ch) * DD + tid, sum);
   }
-  __syncthreads();
-  if (tid < DD) {
-    const cplx* rhs = red + NG * DD;
-    cplx out = mk(0, 0);
-    // X M = rhs with M = 1 + h omega_0 Fcc^A_{n,n} = (1 + h omega_0 F^R_{n,n})^dag,
-    // so X = rhs (minv)^dag
-#pragma unroll
-    for (int q = 0; q < D; q++) cfma_cb(out, rhs[a * D + q], minv[c * D + q]);
-    gst(P.Gles + (tri(n) + m) * DD + tid, out);
+}
+
+// Step set-up (workgroup 0) and the boundary lesser rows' chunks (the
+// others), launched before the history sums; nothing here reads slice n of G.
+template <int D>
+__global__ __launch_bounds__(NTHR) void k_v2_side(ProbArg pa, Scratch sc, HistPlan pl) {
+  constexpr int DD = D * D, NG = NTHR / DD > 0 ? NTHR / DD : 1;
+  constexpr int NP = (KMAX + 1) * DD + (KMAX + 1) * D;  // matrices and pivot ints
+  __shared__ cplx lds[NP > NG * DD ? NP : NG * DD];
+  int pi = blockIdx.y;
+  const Prob& P = pa.get(pi);
+  int n = pl.n;
+  if (n > P.nt) return;
+  int b = blockIdx.x;
+  if (b == 0) {
+    v2_prep<D>(P, sc, pi, n, lds);
+  } else {
+    int u = b - 1;
+    v2_edge_part<D>(P, sc, pi, n, pl, u / pl.v2_nch, u % pl.v2_nch, lds);
   }
 }
 
 // ------------------------------------------------------------------ reduce
-// Workgroups: the reduce tiles of the Dyson step (retarded rows m < n-k,
-// the mixing row, lesser rows m < n-k when n > 2k), then one workgroup for
-// the retarded rows m = n-k..n, then one per lesser row m = lo..n-1 (lo =
-// n-k for n > 2k, else 0).
+// Workgroups: the reduce tiles of the Dyson step (retarded rows m < n-k, the
+// mixing row, lesser rows m < n-k when n > 2k), then one for the retarded
+// rows m = n-k..n. Each also adds its fresh outputs to the sums of
+// G^<_{n,n} (the lesser row m = n, Eq. cles1-cles3 with the new row and
+// column of slice n):
+//   retarded outputs  h w(n,m) G^R_{n,m} Fcc^<_{m,n}             (C1)
+//   mixing outputs   -i h_tau w(ntau,m) G^rceil_{n,m} Fcc^lceil_{m,n}   (C3)
+//   lesser outputs    h w(n,l) G^<_{n,l} Fcc^A_{l,n},  G^<_{n,l} = -(G^<_{l,n})^dag  (C2)
+// into a d x d partial per workgroup; k_v2_final adds them up.
 template <int D>
 __global__ __launch_bounds__(NTHR) void k_v2_reduce(ProbArg pa, Scratch sc, HistPlan pl) {
   constexpr int DD = D * D;
   constexpr int TM = NTHR / DD > 0 ? NTHR / DD : 1;
   constexpr int MSB = D >= 2 ? 16 : 8;
-  constexpr int NG = NTHR / DD > 0 ? NTHR / DD : 1;
-  constexpr int NRED = (NG + 1) * DD > (KMAX + 1) * DD ? (NG + 1) * DD : (KMAX + 1) * DD;
+  constexpr int NOUT = TM * DD > (KMAX + 1) * DD ? TM * DD : (KMAX + 1) * DD;
   __shared__ cplx minv[(KMAX + 1) * DD];
-  __shared__ cplx outs[NRED > TM * DD ? NRED : TM * DD];
+  __shared__ cplx outs[NOUT];
+  __shared__ cplx sol[NOUT];
   int pi = blockIdx.y;
   const Prob& P = pa.get(pi);
   int n = pl.n;
   if (n > P.nt) return;
   const KW& W = c_kw[P.k];
   int k = P.k, ntau = P.ntau, tid = threadIdx.x;
-  double h = P.h, ht = P.htau;
+  double h = P.h, ht = P.htau, xi = P.sig;
   int t0 = pl.red_tiles[0], t1 = pl.red_tiles[1], t2 = pl.red_tiles[2];
+  int nwg = t0 + t1 + t2 + 1;
   int b = blockIdx.x;
   for (int idx = tid; idx < (k + 1) * DD; idx += NTHR) minv[idx] = gld(sc.minv(pi) + idx);
   __syncthreads();
-  if (b < t0 + t1 + t2) {
+  cplx* dpart = sc.part(pi) + pl.v2_doff * DD;
+  if (b < nwg - 1) {
     int fam, mt;
     if (b < t0) {
       fam = 0;
@@ -173,6 +201,7 @@ __global__ __launch_bounds__(NTHR) void k_v2_reduce(ProbArg pa, Scratch sc, Hist
     int m = mt * TM + mo;
     int mout = fam == 1 ? ntau + 1 : n - k;
     bool valid = mo < TM && m < mout;
+    int mlo = mt * TM, nm = min(mlo + TM, mout) - mlo;
     const cplx* part = sc.part(pi);
     if (valid) {
       cplx r;
@@ -231,11 +260,36 @@ __global__ __launch_bounds__(NTHR) void k_v2_reduce(ProbArg pa, Scratch sc, Hist
         for (int q = 0; q < D; q++) cfma_cb(out, outs[mo * DD + a * D + q], minv[c * D + q]);
         gst(P.Gles + (tri(n) + m) * DD + e, out);
       }
+      sol[mo * DD + e] = out;
     }
-    return;
-  }
-  b -= t0 + t1 + t2;
-  if (b == 0) {
+    __syncthreads();
+    // this tile's terms of G^<_{n,n}
+    if (tid < DD) {
+      int a2 = tid / D, c2 = tid % D;
+      cplx acc = mk(0, 0);
+      for (int mm = 0; mm < nm; mm++) {
+        int j = mlo + mm;
+        const cplx* x = sol + mm * DD;
+        cplx t = mk(0, 0);
+        if (fam == 0) {
+#pragma unroll
+          for (int q = 0; q < D; q++) cfma(t, x[a2 * D + q], gld(P.Sles + (tri(n) + j) * DD + q * D + c2));
+          acc = acc + (h * greg(W, n, j)) * t;
+        } else if (fam == 1) {
+#pragma unroll
+          for (int q = 0; q < D; q++)
+            cfma_cb(t, x[a2 * D + q], gld(P.Stv + ((size_t)n * (ntau + 1) + ntau - j) * DD + c2 * D + q));
+          acc = acc - mul_i((ht * -xi * greg(W, ntau, j)) * t);
+        } else {
+          // G^<_{n,l} Fcc^A_{l,n} = -conj(sum_q G^<_{l,n}[q][a] F^R_{n,l}[c][q])
+#pragma unroll
+          for (int q = 0; q < D; q++) cfma(t, x[q * D + a2], gld(P.Sret + (tri(n) + j) * DD + c2 * D + q));
+          acc = acc - (h * greg(W, n, j)) * conj(t);
+        }
+      }
+      gst(dpart + (size_t)b * DD + tid, acc);
+    }
+  } else {
     // retarded rows m = n - r, r = 0..k: G^R_{n,n} = Q^R_{n,n}; for r >= 1 the
     // k+1 points n-k..n with start-up weights s_{r,j} and G^R continued to
     // t < t' (Eq. cr1, second case; Eq. y_to_GR)
@@ -266,28 +320,83 @@ __global__ __launch_bounds__(NTHR) void k_v2_reduce(ProbArg pa, Scratch sc, Hist
         for (int q = 0; q < D; q++) cfma(out, minv[r * DD + a * D + q], outs[r * DD + q * D + c]);
       }
       gst(P.Gret + (tri(n) + m) * DD + e, out);
+      sol[idx] = out;
     }
-    return;
+    __syncthreads();
+    if (tid < DD) {
+      int a2 = tid / D, c2 = tid % D;
+      cplx acc = mk(0, 0);
+      for (int r = 0; r <= k; r++) {
+        int j = n - r;
+        cplx t = mk(0, 0);
+#pragma unroll
+        for (int q = 0; q < D; q++) cfma(t, sol[r * DD + a2 * D + q], gld(P.Sles + (tri(n) + j) * DD + q * D + c2));
+        acc = acc + (h * greg(W, n, j)) * t;
+      }
+      gst(dpart + (size_t)b * DD + tid, acc);
+    }
   }
-  int lo = n >= 2 * k + 1 ? n - k : 0;
-  int m = lo + b - 1;
-  if (m >= n) return;
-  v2_les_row<D>(P, n, m, minv, outs);
 }
 
-// G^<_{n,n} from the finished row and column of slice n.
+// The boundary lesser rows from the partials of the extra history
+// workgroups, their C2 terms of G^<_{n,n}, and G^<_{n,n} from the partials of
+// every reduce workgroup (one workgroup per problem, after k_v2_reduce).
 template <int D>
-__global__ __launch_bounds__(NTHR) void k_v2_diag(ProbArg pa, Scratch sc, int n) {
+__global__ __launch_bounds__(NTHR) void k_v2_final(ProbArg pa, Scratch sc, HistPlan pl) {
   constexpr int DD = D * D;
-  constexpr int NG = NTHR / DD > 0 ? NTHR / DD : 1;
   __shared__ cplx minv[DD];
-  __shared__ cplx red[(NG + 1) * DD];
+  __shared__ cplx xe[2 * KMAX * DD], xo[2 * KMAX * DD];  // boundary rows: right-hand sides, solutions
+  __shared__ cplx dg[DD];
   int pi = blockIdx.y;
   const Prob& P = pa.get(pi);
+  int n = pl.n;
   if (n > P.nt) return;
-  if (threadIdx.x < DD) minv[threadIdx.x] = gld(sc.minv(pi) + threadIdx.x);
+  const KW& W = c_kw[P.k];
+  int tid = threadIdx.x;
+  double h = P.h;
+  int nwg = pl.red_tiles[0] + pl.red_tiles[1] + pl.red_tiles[2] + 1;
+  if (tid < DD) minv[tid] = gld(sc.minv(pi) + tid);
+  const cplx* dpart = sc.part(pi) + pl.v2_doff * DD;
+  const cplx* epart = sc.part(pi) + pl.v2_off * DD;
+  int nr = pl.v2_rows;
+  // X_r M = Q^<_{m,n} - (sum of the chunk partials of row m)
+  for (int idx = tid; idx < nr * DD; idx += NTHR) {
+    int r = idx / DD, e = idx % DD, m = pl.v2_lo + r;
+    cplx hs = psum_b<8>(epart + (size_t)r * pl.v2_nch * DD + e, DD, pl.v2_nch);
+    xe[idx] = gld(P.Qles + (tri(n) + m) * DD + e) - hs;
+  }
   __syncthreads();
-  v2_les_row<D>(P, n, n, minv, red);
+  for (int idx = tid; idx < nr * DD; idx += NTHR) {
+    int r = idx / DD, e = idx % DD, a = e / D, c = e % D, m = pl.v2_lo + r;
+    cplx out = mk(0, 0);
+#pragma unroll
+    for (int q = 0; q < D; q++) cfma_cb(out, xe[r * DD + a * D + q], minv[c * D + q]);
+    gst(P.Gles + (tri(n) + m) * DD + e, out);
+    xo[idx] = out;
+  }
+  __syncthreads();
+  if (tid < DD) {
+    int a2 = tid / D, c2 = tid % D;
+    // their C2 terms, then the partials of every reduce workgroup in order
+    cplx acc = mk(0, 0);
+    for (int r = 0; r < nr; r++) {
+      int l = pl.v2_lo + r;
+      cplx t = mk(0, 0);
+#pragma unroll
+      for (int q = 0; q < D; q++) cfma(t, xo[r * DD + q * D + a2], gld(P.Sret + (tri(n) + l) * DD + c2 * D + q));
+      acc = acc - (h * greg(W, n, l)) * conj(t);
+    }
+    acc = acc + psum_b<8>(dpart + tid, DD, nwg);
+    dg[tid] = gld(P.Qles + (tri(n) + n) * DD + tid) - acc;
+  }
+  __syncthreads();
+  if (tid < DD) {
+    int a2 = tid / D, c2 = tid % D;
+    cplx out = mk(0, 0);
+#pragma unroll
+    for (int q = 0; q < D; q++) cfma_cb(out, dg[a2 * D + q], minv[c2 * D + q]);
+    gst(P.Gles + (tri(n) + n) * DD + tid, out);
+  }
 }
 
 // ---------------------------------------------------------------- start-up
@@ -490,11 +599,11 @@ static hipError_t vie2_step_d(const ProbArg& pa, const Scratch& sc, int n, hipSt
   int k = pa.one.k, ntau = pa.one.ntau;
   HistPlan pl = make_plan(n, k, ntau, D);
   pl.vie2 = 1;
+  k_v2_side<D><<<dim3(1 + pl.v2_rows * pl.v2_nch, pa.count), NTHR, 0, s>>>(pa, sc, pl);
   k_history<D><<<dim3(pl.grid + 1, pa.count), NTHR, 0, s>>>(pa, sc, pl);
-  int nle = n - (n >= 2 * k + 1 ? n - k : 0);
   int ntile = pl.red_tiles[0] + pl.red_tiles[1] + pl.red_tiles[2];
-  k_v2_reduce<D><<<dim3(ntile + 1 + nle, pa.count), NTHR, 0, s>>>(pa, sc, pl);
-  k_v2_diag<D><<<dim3(1, pa.count), NTHR, 0, s>>>(pa, sc, n);
+  k_v2_reduce<D><<<dim3(ntile + 1, pa.count), NTHR, 0, s>>>(pa, sc, pl);
+  k_v2_final<D><<<dim3(1, pa.count), NTHR, 0, s>>>(pa, sc, pl);
   return hipGetLastError();
 }
 
