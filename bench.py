@@ -252,14 +252,15 @@ def run_vie2(state):
     K.solve_vie2([Gv], [F], [Fcc], [G0])
     K.sync()
     reps, whole, steps = 2, [], []
+    V = K.Vie2Batch([Gv], [F], [Fcc], [G0])
     for _ in range(reps):
         e0, e1, e2 = ev(), ev(), ev()
         e0.record()
-        K.vie2_matsubara([Gv], [F], [G0])
-        K.vie2_step(g.k, [Gv], [F], [Fcc], [G0])
+        V.matsubara()
+        V.step(g.k)
         e1.record()
         for n in range(g.k + 1, g.nt + 1):
-            K.vie2_step(n, [Gv], [F], [Fcc], [G0])
+            V.step(n)
         e2.record()
         torch.cuda.synchronize()
         whole.append(e0.elapsed_time(e2))

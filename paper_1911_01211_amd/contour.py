@@ -101,14 +101,33 @@ def vie2_step(tstp: int, G: list, F: list, Fcc: list, Q: list, stream=None):
                                           _stream(stream)))
 
 
+class Vie2Batch:
+    """The C-ABI argument arrays of a fixed batch of (1 + F) * G = Q problems,
+    built once (as Batch does for the Dyson step)."""
+
+    def __init__(self, G: list, F: list, Fcc: list, Q: list):
+        self.count = len(G)
+        self.grids = _grids(G)
+        self.gfs, self.f, self.fcc, self.q = _gfs(G), _gfs(F), _gfs(Fcc), _gfs(Q)
+
+    def matsubara(self, tol=1e-14, max_iter=200, stream=None):
+        _abi.check(_abi.lib().cntr_vie2_matsubara(self.count, self.grids, self.gfs, self.f, self.q, tol, max_iter,
+                                                   _stream(stream)))
+
+    def step(self, tstp: int, stream=None):
+        _abi.check(_abi.lib().cntr_vie2_step(tstp, self.count, self.grids, self.gfs, self.f, self.fcc, self.q,
+                                              _stream(stream)))
+
+
 def solve_vie2(G: list, F: list, Fcc: list, Q: list, nt_stop=None, stream=None):
     """Matsubara, start-up and every time step up to nt_stop."""
     g = G[0].g
     nt_stop = g.nt if nt_stop is None else nt_stop
-    vie2_matsubara(G, F, Q, stream=stream)
-    vie2_step(g.k, G, F, Fcc, Q, stream)
+    B = Vie2Batch(G, F, Fcc, Q)
+    B.matsubara(stream=stream)
+    B.step(g.k, stream)
     for n in range(g.k + 1, nt_stop + 1):
-        vie2_step(n, G, F, Fcc, Q, stream)
+        B.step(n, stream)
 
 
 def convolution(tstp: int, C_: list, A: list, Acc: list, B: list, Bcc: list, f=None, stream=None):

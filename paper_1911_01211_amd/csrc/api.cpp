@@ -2,6 +2,7 @@
 // (weight tables, per-stream scratch), and the host-side sequencing of the
 // Matsubara solve and the self-consistent second-Born propagation.
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -263,7 +264,28 @@ struct StepScratch {
   size_t per;
 };
 
+// the step layout depends on the grid shape and the tile table; every step
+// call needs it, so it is computed once per shape (and table version)
+static int g_tiles_gen = 0;
+StepScratch step_layout_uncached(const cntr_grid& g);
 StepScratch step_layout(const cntr_grid& g) {
+  static std::mutex mu;
+  static std::map<std::array<int, 5>, StepScratch> memo;
+  std::array<int, 5> key;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    key = {g.nt, g.k, g.ntau, g.d, g_tiles_gen};
+  }
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = memo.find(key);
+  if (it != memo.end()) return it->second;
+  if (memo.size() > 256) memo.clear();
+  StepScratch r = step_layout_uncached(g);
+  memo[key] = r;
+  return r;
+}
+
+StepScratch step_layout_uncached(const cntr_grid& g) {
   StepScratch r{};
   size_t dd = (size_t)g.d * g.d;
   r.sc.off_status = 0;
@@ -651,6 +673,7 @@ cntr_status cntr_set_tiles(int32_t d, int32_t nbands, const int32_t* n_hi, const
     t.tj[b] = tj[b];
   }
   g_tiles[d] = t;
+  g_tiles_gen++;
   return CNTR_OK;
 }
 
@@ -933,7 +956,7 @@ cntr_status cntr_vie2_step(int32_t tstp, int32_t count, const cntr_grid* grids, 
   scr.base = sc->data();
   scr.stat = sc->stat();
   sc->nstat = std::max(sc->nstat, (int)count);
-  hipError_t e = tstp <= k ? launch_vie2_start(pa, scr, d, ntau, s) : launch_vie2_step(pa, scr, tstp, d, s);
+  hipError_t e = tstp <= k ? launch_vie2_start(pa, scr, d, ntau, s) : launch_vie2_step(pa, scr, tstp, d, s, !capturing(s));
   if (e != hipSuccess) return hip_fail(e, "cntr_vie2_step launch");
   order_mark(count, G, tstp <= k ? k : tstp, false);
   return CNTR_OK;

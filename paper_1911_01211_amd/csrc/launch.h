@@ -139,7 +139,8 @@ hipError_t launch_sigma_local(const ProbArg& pa, int n, int d, int nelems, doubl
 // Dyson equation in integral form, (1 + F) * G = Q: start-up (slices 0..k)
 // and time step n > k (problem descriptors as described at Prob)
 hipError_t launch_vie2_start(const ProbArg& pa, const Scratch& sc, int d, int ntau, hipStream_t s);
-hipError_t launch_vie2_step(const ProbArg& pa, const Scratch& sc, int n, int d, hipStream_t s);
+// side_ok: the step may run its side kernel on a forked stream
+hipError_t launch_vie2_step(const ProbArg& pa, const Scratch& sc, int n, int d, hipStream_t s, bool side_ok = true);
 
 // Matsubara pieces (per problem, one problem per call)
 hipError_t launch_free_mat(const Prob& P, cplx* g, hipStream_t s);

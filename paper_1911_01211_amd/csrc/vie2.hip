@@ -17,10 +17,10 @@
 // whose interval is shorter than k+1 points (Eq. cr1, second case; summed
 // directly, as are the lesser rows m >= n-k, for which the history kernel
 // has no outputs: k_v2_side sums those in chunks,
-// k_v2_final solves them). 1 + h omega_0 Fcc^A_{n,n} is the adjoint of the
-// retarded step matrix. G^<_{n,n} needs the finished row and column of
-// slice n: every reduce workgroup adds its outputs' terms into a partial,
-// k_v2_final sums them and solves.
+// the last reduce workgroup solves them). 1 + h omega_0 Fcc^A_{n,n} is the
+// adjoint of the retarded step matrix. G^<_{n,n} needs the finished row and
+// column of slice n: every reduce workgroup adds its outputs' terms into a
+// partial, the last one to finish (completion count) sums them and solves.
 //
 // Start-up (slices 0..k): the retarded columns m = 0..k-1 from the
 // (k-m) d system of Sec. "Start" (one workgroup per problem, in order of m),
@@ -58,6 +58,8 @@ __device__ void v2_prep(const Prob& P, const Scratch& sc, int pi, int n, cplx* l
   int k = P.k, tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   double h = P.h;
   int* piv = (int*)(lds + (KMAX + 1) * DD);
+  // the reduce of this step starts its completion count at 0
+  if (tid == 0) *sc.counter(pi) = 0;
   for (int idx = tid; idx < (k + 1) * DD; idx += NTHR) {
     int r = idx / DD, e = idx % DD;
     double w = r == 0 ? greg(W, n, n) : W.s[r][0];
@@ -153,6 +155,67 @@ __global__ __launch_bounds__(NTHR) void k_v2_side(ProbArg pa, Scratch sc, HistPl
   }
 }
 
+// The boundary lesser rows from the chunk partials of k_v2_side, their C2
+// terms of G^<_{n,n}, and G^<_{n,n} from the partials of every reduce
+// workgroup (run by the last reduce workgroup of the problem; minv: slot 0).
+template <int D>
+__device__ void v2_final(const Prob& P, const Scratch& sc, int pi, int n, const HistPlan& pl, const cplx* minv,
+                         cplx* xe, cplx* xo, cplx* dg) {
+  constexpr int DD = D * D;
+  const KW& W = c_kw[P.k];
+  int tid = threadIdx.x;
+  double h = P.h;
+  int nwg = pl.red_tiles[0] + pl.red_tiles[1] + pl.red_tiles[2] + 1;
+  const cplx* dpart = sc.part(pi) + pl.v2_doff * DD;
+  const cplx* epart = sc.part(pi) + pl.v2_off * DD;
+  int nr = pl.v2_rows;
+  // G thread groups per value sum every G-th partial of G^<_{n,n} (fixed
+  // order), loaded in the same memory round as the rows' chunk partials
+  constexpr int G = NTHR / DD > 0 ? NTHR / DD : 1;
+  for (int vv = tid; vv < G * DD; vv += NTHR) {
+    int g = vv / DD, e = vv % DD;
+    dg[vv] = psum_b<16>(dpart + (size_t)g * DD + e, (long)G * DD, g < nwg ? (nwg - g + G - 1) / G : 0);
+  }
+  // X_r M = Q^<_{m,n} - (sum of the chunk partials of row m)
+  for (int idx = tid; idx < nr * DD; idx += NTHR) {
+    int r = idx / DD, e = idx % DD, m = pl.v2_lo + r;
+    cplx hs = psum_b<16>(epart + (size_t)r * pl.v2_nch * DD + e, DD, pl.v2_nch);
+    xe[idx] = gld(P.Qles + (tri(n) + m) * DD + e) - hs;
+  }
+  __syncthreads();
+  for (int idx = tid; idx < nr * DD; idx += NTHR) {
+    int r = idx / DD, e = idx % DD, a = e / D, c = e % D, m = pl.v2_lo + r;
+    cplx out = mk(0, 0);
+#pragma unroll
+    for (int q = 0; q < D; q++) cfma_cb(out, xe[r * DD + a * D + q], minv[c * D + q]);
+    gst(P.Gles + (tri(n) + m) * DD + e, out);
+    xo[idx] = out;
+  }
+  __syncthreads();
+  if (tid < DD) {
+    int a2 = tid / D, c2 = tid % D;
+    // their C2 terms, then the partials of every reduce workgroup in order
+    cplx acc = mk(0, 0);
+    for (int r = 0; r < nr; r++) {
+      int l = pl.v2_lo + r;
+      cplx t = mk(0, 0);
+#pragma unroll
+      for (int q = 0; q < D; q++) cfma(t, xo[r * DD + q * D + a2], gld(P.Sret + (tri(n) + l) * DD + c2 * D + q));
+      acc = acc - (h * greg(W, n, l)) * conj(t);
+    }
+    for (int g = 0; g < G; g++) acc = acc + dg[g * DD + tid];
+    xe[tid] = gld(P.Qles + (tri(n) + n) * DD + tid) - acc;
+  }
+  __syncthreads();
+  if (tid < DD) {
+    int a2 = tid / D, c2 = tid % D;
+    cplx out = mk(0, 0);
+#pragma unroll
+    for (int q = 0; q < D; q++) cfma_cb(out, xe[a2 * D + q], minv[c2 * D + q]);
+    gst(P.Gles + (tri(n) + n) * DD + tid, out);
+  }
+}
+
 // ------------------------------------------------------------------ reduce
 // Workgroups: the reduce tiles of the Dyson step (retarded rows m < n-k, the
 // mixing row, lesser rows m < n-k when n > 2k), then one for the retarded
@@ -162,7 +225,7 @@ __global__ __launch_bounds__(NTHR) void k_v2_side(ProbArg pa, Scratch sc, HistPl
 //   retarded outputs  h w(n,m) G^R_{n,m} Fcc^<_{m,n}             (C1)
 //   mixing outputs   -i h_tau w(ntau,m) G^rceil_{n,m} Fcc^lceil_{m,n}   (C3)
 //   lesser outputs    h w(n,l) G^<_{n,l} Fcc^A_{l,n},  G^<_{n,l} = -(G^<_{l,n})^dag  (C2)
-// into a d x d partial per workgroup; k_v2_final adds them up.
+// into a d x d partial per workgroup; the last workgroup adds them up.
 template <int D>
 __global__ __launch_bounds__(NTHR) void k_v2_reduce(ProbArg pa, Scratch sc, HistPlan pl) {
   constexpr int DD = D * D;
@@ -172,6 +235,9 @@ __global__ __launch_bounds__(NTHR) void k_v2_reduce(ProbArg pa, Scratch sc, Hist
   __shared__ cplx minv[(KMAX + 1) * DD];
   __shared__ cplx outs[NOUT];
   __shared__ cplx sol[NOUT];
+  __shared__ cplx xe[2 * KMAX * DD], xo[2 * KMAX * DD];  // boundary rows: right-hand sides, solutions
+  __shared__ cplx dg[NTHR];
+  __shared__ int is_last;
   int pi = blockIdx.y;
   const Prob& P = pa.get(pi);
   int n = pl.n;
@@ -263,30 +329,32 @@ __global__ __launch_bounds__(NTHR) void k_v2_reduce(ProbArg pa, Scratch sc, Hist
       sol[mo * DD + e] = out;
     }
     __syncthreads();
-    // this tile's terms of G^<_{n,n}
-    if (tid < DD) {
-      int a2 = tid / D, c2 = tid % D;
-      cplx acc = mk(0, 0);
-      for (int mm = 0; mm < nm; mm++) {
-        int j = mlo + mm;
-        const cplx* x = sol + mm * DD;
-        cplx t = mk(0, 0);
-        if (fam == 0) {
+    // this tile's terms of G^<_{n,n}: one output per thread group (one
+    // memory round), then summed over the outputs in order
+    if (valid) {
+      int j = m;
+      const cplx* x = sol + mo * DD;
+      cplx t = mk(0, 0), v;
+      if (fam == 0) {
 #pragma unroll
-          for (int q = 0; q < D; q++) cfma(t, x[a2 * D + q], gld(P.Sles + (tri(n) + j) * DD + q * D + c2));
-          acc = acc + (h * greg(W, n, j)) * t;
-        } else if (fam == 1) {
+        for (int q = 0; q < D; q++) cfma(t, x[a * D + q], gld(P.Sles + (tri(n) + j) * DD + q * D + c));
+        v = (h * greg(W, n, j)) * t;
+      } else if (fam == 1) {
 #pragma unroll
-          for (int q = 0; q < D; q++)
-            cfma_cb(t, x[a2 * D + q], gld(P.Stv + ((size_t)n * (ntau + 1) + ntau - j) * DD + c2 * D + q));
-          acc = acc - mul_i((ht * -xi * greg(W, ntau, j)) * t);
-        } else {
-          // G^<_{n,l} Fcc^A_{l,n} = -conj(sum_q G^<_{l,n}[q][a] F^R_{n,l}[c][q])
+        for (int q = 0; q < D; q++) cfma_cb(t, x[a * D + q], gld(P.Stv + ((size_t)n * (ntau + 1) + ntau - j) * DD + c * D + q));
+        v = -mul_i((ht * -xi * greg(W, ntau, j)) * t);
+      } else {
+        // G^<_{n,l} Fcc^A_{l,n} = -conj(sum_q G^<_{l,n}[q][a] F^R_{n,l}[c][q])
 #pragma unroll
-          for (int q = 0; q < D; q++) cfma(t, x[q * D + a2], gld(P.Sret + (tri(n) + j) * DD + c2 * D + q));
-          acc = acc - (h * greg(W, n, j)) * conj(t);
-        }
+        for (int q = 0; q < D; q++) cfma(t, x[q * D + a], gld(P.Sret + (tri(n) + j) * DD + c * D + q));
+        v = -(h * greg(W, n, j)) * conj(t);
       }
+      outs[mo * DD + e] = v;
+    }
+    __syncthreads();
+    if (tid < DD) {
+      cplx acc = mk(0, 0);
+      for (int mm = 0; mm < nm; mm++) acc = acc + outs[mm * DD + tid];
       gst(dpart + (size_t)b * DD + tid, acc);
     }
   } else {
@@ -323,80 +391,29 @@ __global__ __launch_bounds__(NTHR) void k_v2_reduce(ProbArg pa, Scratch sc, Hist
       sol[idx] = out;
     }
     __syncthreads();
-    if (tid < DD) {
-      int a2 = tid / D, c2 = tid % D;
-      cplx acc = mk(0, 0);
-      for (int r = 0; r <= k; r++) {
-        int j = n - r;
-        cplx t = mk(0, 0);
+    for (int idx = tid; idx < (k + 1) * DD; idx += NTHR) {
+      int r = idx / DD, e = idx % DD, a = e / D, c = e % D, j = n - r;
+      cplx t = mk(0, 0);
 #pragma unroll
-        for (int q = 0; q < D; q++) cfma(t, sol[r * DD + a2 * D + q], gld(P.Sles + (tri(n) + j) * DD + q * D + c2));
-        acc = acc + (h * greg(W, n, j)) * t;
-      }
+      for (int q = 0; q < D; q++) cfma(t, sol[r * DD + a * D + q], gld(P.Sles + (tri(n) + j) * DD + q * D + c));
+      outs[idx] = (h * greg(W, n, j)) * t;
+    }
+    __syncthreads();
+    if (tid < DD) {
+      cplx acc = mk(0, 0);
+      for (int r = 0; r <= k; r++) acc = acc + outs[r * DD + tid];
       gst(dpart + (size_t)b * DD + tid, acc);
     }
   }
-}
-
-// The boundary lesser rows from the partials of the extra history
-// workgroups, their C2 terms of G^<_{n,n}, and G^<_{n,n} from the partials of
-// every reduce workgroup (one workgroup per problem, after k_v2_reduce).
-template <int D>
-__global__ __launch_bounds__(NTHR) void k_v2_final(ProbArg pa, Scratch sc, HistPlan pl) {
-  constexpr int DD = D * D;
-  __shared__ cplx minv[DD];
-  __shared__ cplx xe[2 * KMAX * DD], xo[2 * KMAX * DD];  // boundary rows: right-hand sides, solutions
-  __shared__ cplx dg[DD];
-  int pi = blockIdx.y;
-  const Prob& P = pa.get(pi);
-  int n = pl.n;
-  if (n > P.nt) return;
-  const KW& W = c_kw[P.k];
-  int tid = threadIdx.x;
-  double h = P.h;
-  int nwg = pl.red_tiles[0] + pl.red_tiles[1] + pl.red_tiles[2] + 1;
-  if (tid < DD) minv[tid] = gld(sc.minv(pi) + tid);
-  const cplx* dpart = sc.part(pi) + pl.v2_doff * DD;
-  const cplx* epart = sc.part(pi) + pl.v2_off * DD;
-  int nr = pl.v2_rows;
-  // X_r M = Q^<_{m,n} - (sum of the chunk partials of row m)
-  for (int idx = tid; idx < nr * DD; idx += NTHR) {
-    int r = idx / DD, e = idx % DD, m = pl.v2_lo + r;
-    cplx hs = psum_b<8>(epart + (size_t)r * pl.v2_nch * DD + e, DD, pl.v2_nch);
-    xe[idx] = gld(P.Qles + (tri(n) + m) * DD + e) - hs;
-  }
+  // completion count (reset by k_v2_side); every thread releases its own
+  // stores first, and the last workgroup to arrive finishes the column
+  __threadfence();
   __syncthreads();
-  for (int idx = tid; idx < nr * DD; idx += NTHR) {
-    int r = idx / DD, e = idx % DD, a = e / D, c = e % D, m = pl.v2_lo + r;
-    cplx out = mk(0, 0);
-#pragma unroll
-    for (int q = 0; q < D; q++) cfma_cb(out, xe[r * DD + a * D + q], minv[c * D + q]);
-    gst(P.Gles + (tri(n) + m) * DD + e, out);
-    xo[idx] = out;
-  }
+  if (tid == 0) is_last = atomicAdd(sc.counter(pi), 1) == nwg - 1;
   __syncthreads();
-  if (tid < DD) {
-    int a2 = tid / D, c2 = tid % D;
-    // their C2 terms, then the partials of every reduce workgroup in order
-    cplx acc = mk(0, 0);
-    for (int r = 0; r < nr; r++) {
-      int l = pl.v2_lo + r;
-      cplx t = mk(0, 0);
-#pragma unroll
-      for (int q = 0; q < D; q++) cfma(t, xo[r * DD + q * D + a2], gld(P.Sret + (tri(n) + l) * DD + c2 * D + q));
-      acc = acc - (h * greg(W, n, l)) * conj(t);
-    }
-    acc = acc + psum_b<8>(dpart + tid, DD, nwg);
-    dg[tid] = gld(P.Qles + (tri(n) + n) * DD + tid) - acc;
-  }
-  __syncthreads();
-  if (tid < DD) {
-    int a2 = tid / D, c2 = tid % D;
-    cplx out = mk(0, 0);
-#pragma unroll
-    for (int q = 0; q < D; q++) cfma_cb(out, dg[a2 * D + q], minv[c2 * D + q]);
-    gst(P.Gles + (tri(n) + n) * DD + tid, out);
-  }
+  if (!is_last) return;
+  __threadfence();
+  v2_final<D>(P, sc, pi, n, pl, minv, xe, xo, dg);
 }
 
 // ---------------------------------------------------------------- start-up
@@ -594,29 +611,41 @@ __global__ __launch_bounds__(NTHR) void k_v2_start_les(ProbArg pa, Scratch sc) {
 }
 
 // ---------------------------------------------------------------- launches
+// k_v2_side reads only earlier slices: it runs beside the history sums on a
+// stream forked from s and joined before the reduce (serially on s when the
+// call may not create runtime objects or is being captured)
 template <int D>
-static hipError_t vie2_step_d(const ProbArg& pa, const Scratch& sc, int n, hipStream_t s) {
+static hipError_t vie2_step_d(const ProbArg& pa, const Scratch& sc, int n, hipStream_t s, bool side_ok) {
   int k = pa.one.k, ntau = pa.one.ntau;
   HistPlan pl = make_plan(n, k, ntau, D);
   pl.vie2 = 1;
-  k_v2_side<D><<<dim3(1 + pl.v2_rows * pl.v2_nch, pa.count), NTHR, 0, s>>>(pa, sc, pl);
+  SideStream* side = side_ok ? side_stream(s) : nullptr;
+  dim3 gs(1 + pl.v2_rows * pl.v2_nch, pa.count);
+  if (side) {
+    (void)hipEventRecord(side->fork, s);
+    (void)hipStreamWaitEvent(side->s, side->fork, 0);
+    k_v2_side<D><<<gs, NTHR, 0, side->s>>>(pa, sc, pl);
+    (void)hipEventRecord(side->join, side->s);
+  } else {
+    k_v2_side<D><<<gs, NTHR, 0, s>>>(pa, sc, pl);
+  }
   k_history<D><<<dim3(pl.grid + 1, pa.count), NTHR, 0, s>>>(pa, sc, pl);
+  if (side) (void)hipStreamWaitEvent(s, side->join, 0);
   int ntile = pl.red_tiles[0] + pl.red_tiles[1] + pl.red_tiles[2];
   k_v2_reduce<D><<<dim3(ntile + 1, pa.count), NTHR, 0, s>>>(pa, sc, pl);
-  k_v2_final<D><<<dim3(1, pa.count), NTHR, 0, s>>>(pa, sc, pl);
   return hipGetLastError();
 }
 
-hipError_t launch_vie2_step(const ProbArg& pa, const Scratch& sc, int n, int d, hipStream_t s) {
+hipError_t launch_vie2_step(const ProbArg& pa, const Scratch& sc, int n, int d, hipStream_t s, bool side_ok) {
   switch (d) {
-    case 1: return vie2_step_d<1>(pa, sc, n, s);
-    case 2: return vie2_step_d<2>(pa, sc, n, s);
-    case 3: return vie2_step_d<3>(pa, sc, n, s);
-    case 4: return vie2_step_d<4>(pa, sc, n, s);
-    case 5: return vie2_step_d<5>(pa, sc, n, s);
-    case 6: return vie2_step_d<6>(pa, sc, n, s);
-    case 7: return vie2_step_d<7>(pa, sc, n, s);
-    case 8: return vie2_step_d<8>(pa, sc, n, s);
+    case 1: return vie2_step_d<1>(pa, sc, n, s, side_ok);
+    case 2: return vie2_step_d<2>(pa, sc, n, s, side_ok);
+    case 3: return vie2_step_d<3>(pa, sc, n, s, side_ok);
+    case 4: return vie2_step_d<4>(pa, sc, n, s, side_ok);
+    case 5: return vie2_step_d<5>(pa, sc, n, s, side_ok);
+    case 6: return vie2_step_d<6>(pa, sc, n, s, side_ok);
+    case 7: return vie2_step_d<7>(pa, sc, n, s, side_ok);
+    case 8: return vie2_step_d<8>(pa, sc, n, s, side_ok);
   }
   return hipErrorInvalidValue;
 }
