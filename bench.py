@@ -294,7 +294,7 @@ def run_vie2(state):
             "ms_per_solve": min(whole), "ms_steps": st_ms, "us_per_step": st_ms * 1e3 / nsteps,
             "dyson_form": {"ms_per_solve": d0.elapsed_time(d2), "ms_steps": d1.elapsed_time(d2)},
             "max_abs_deviation_from_dyson_form": dev_max, "max_abs_G": ref,
-            "roofline": {"bound": "hbm", "scope": "time steps (k_v2_side, k_history, k_v2_reduce, k_v2_final)",
+            "roofline": {"bound": "hbm", "scope": "time steps (k_v2_side beside k_history, then k_v2_reduce)",
                          "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
                          "bytes": nbytes}}
 
