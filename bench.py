@@ -237,16 +237,24 @@ def run_vie2(state):
     dev = "cuda:0"
     G0, F, Fcc, Gv, Gd = (K.Contour(g, dev) for _ in range(5))
     K.green_from_H([G0], [emf])
+
+    def ev():
+        return torch.cuda.Event(enable_timing=True)
+
+    # the inputs: 2 x (nt + 2) convolution calls (cntr_convolution), timed
+    c0, c1 = ev(), ev()
+    torch.cuda.synchronize()
+    c0.record()
     for n in range(-1, g.nt + 1):
         K.convolution(n, [F], [G0], [G0], [S], [S])
         K.convolution(n, [Fcc], [S], [S], [G0], [G0])
+    c1.record()
+    torch.cuda.synchronize()
+    conv_ms = c0.elapsed_time(c1)
     for X in (F, Fcc):
         for key in K.KEYS:
             getattr(X, key).neg_()
     torch.cuda.synchronize()
-
-    def ev():
-        return torch.cuda.Event(enable_timing=True)
 
     # warm-up, then the timed solves
     K.solve_vie2([Gv], [F], [Fcc], [G0])
@@ -288,12 +296,23 @@ def run_vie2(state):
         blocks = n * (n + 1) / 2 + n * (g.ntau + 1) + (n * (n + 1) / 2 if n >= 2 * g.k + 1 else 0)
         nbytes += 16.0 * dd * blocks
     gbs = nbytes / (st_ms * 1e-3) / 1e9
+    # convolution bytes: per slice n the blocks of the factors' histories that
+    # the three components read (B^R and A^R, A^< triangles, A^rceil and
+    # B^rceil panels), each once
+    cbytes = 0.0
+    for n in range(0, g.nt + 1):
+        cbytes += 16.0 * dd * (3 * n * (n + 1) / 2 + 2 * (n + 1) * (g.ntau + 1))
+    cbytes *= 2
+    conv = {"calls": 2 * (g.nt + 2), "ms_per_call": conv_ms / (2 * (g.nt + 2)),
+            "roofline": {"bound": "hbm", "achieved": cbytes / (conv_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": cbytes / (conv_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "bytes": cbytes}}
     return {"workload": "Dyson equation of the converged 2B chain in integral form (d=4, nt=1000, ntau=400, "
                         "k=5): Q = G_0, F = -G_0*Sigma, Fcc = -Sigma*G_0, Sigma fixed",
             "value": nsteps / (min(whole) * 1e-3), "unit": "time-steps/s",
             "ms_per_solve": min(whole), "ms_steps": st_ms, "us_per_step": st_ms * 1e3 / nsteps,
             "dyson_form": {"ms_per_solve": d0.elapsed_time(d2), "ms_steps": d1.elapsed_time(d2)},
             "max_abs_deviation_from_dyson_form": dev_max, "max_abs_G": ref,
+            "convolution": conv,
             "roofline": {"bound": "hbm", "scope": "time steps (k_v2_side beside k_history, then k_v2_reduce)",
                          "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
                          "bytes": nbytes}}

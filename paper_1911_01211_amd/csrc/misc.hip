@@ -406,72 +406,34 @@ __device__ inline const cplx* fat(const cplx* f, int t, int d) {
   return f == nullptr ? nullptr : f + (size_t)(t + 1) * d * d;
 }
 
-// Matsubara convolution, Eqs. cm1 + cm2, element (a,c) of C^M_m.
-__device__ inline cplx mat_conv_elem(const Prob& P, const cplx* A, const cplx* B, const cplx* f,
-                                     int m, int a, int c) {
-  const KW& W = c_kw[P.k];
-  int d = P.d, dd = d * d, k = P.k, nt = P.ntau;
-  double ht = P.htau, xi = P.sig;
-  const cplx* fm = fat(f, -1, d);
-  cplx acc = mk(0, 0);
-  auto pr = [&](int ia, int ib) {
-    return triple(d, [&](int x, int y) { return A[(size_t)ia * dd + x * d + y]; }, fm,
-                  [&](int x, int y) { return B[(size_t)ib * dd + x * d + y]; }, a, c);
-  };
-  if (m <= k) {
-    for (int j = 0; j <= k; j++)
-      for (int l = 0; l <= k; l++) acc = acc + (ht * W.R[m][j][l]) * pr(j, l);
-  } else {
-    for (int l = 0; l <= m; l++) acc = acc + (ht * greg(W, m, l)) * pr(m - l, l);
-  }
-  if (m >= nt - k) {
-    for (int j = 0; j <= k; j++)
-      for (int l = 0; l <= k; l++) acc = acc + (ht * xi * W.R[nt - m][j][l]) * pr(nt - j, nt - l);
-  } else {
-    for (int l = 0; l <= nt - m; l++) acc = acc + (ht * xi * greg(W, nt - m, l)) * pr(nt - l, m + l);
-  }
-  return acc;
-}
+// Terms of one output element split over GC consecutive lanes (term index
+// = lane mod GC), summed with shuffles in a fixed order: the sums over the
+// n + Ntau terms of a slice would otherwise run serially in one thread.
+constexpr int GC = 16;
+__device__ cplx mat_conv_part(const Prob& P, const cplx* A, const cplx* B, const cplx* f, int m, int a, int c,
+                              int g);
 
-__global__ __launch_bounds__(NT2) void k_convolution(ProbArg pc, ProbArg pa, ProbArg pac,
-                                                     ProbArg pb, ProbArg pbc, int n) {
-  int pi = blockIdx.y;
-  const Prob& C = pc.get(pi);
-  const Prob& A = pa.get(pi);
-  const Prob& Ac = pac.get(pi);
-  const Prob& B = pb.get(pi);
-  const Prob& Bc = pbc.get(pi);
+__device__ inline cplx conv_part(const Prob& C, const Prob& A, const Prob& Ac, const Prob& B, const Prob& Bc,
+                                 int n, const SliceIdx& s, int g) {
   const cplx* f = C.f;
   const KW& W = c_kw[C.k];
-  int d = C.d, dd = d * d, ntau = C.ntau, k = C.k;
+  int d = C.d, dd = d * d, ntau = C.ntau, k = C.k, K1 = k + 1;
   double h = C.h, ht = C.htau;
-  long idx = (long)blockIdx.x * NT2 + threadIdx.x;
-  if (n == -1) {
-    if (idx < (long)(ntau + 1) * dd) {
-      int m = idx / dd, e = idx % dd;
-      C.Gmat[idx] = mat_conv_elem(C, A.Gmat, B.Gmat, f, m, e / d, e % d);
-    }
-    return;
-  }
-  if (n > C.nt) return;
-  long total = (long)(2 * (n + 1) + ntau + 1) * dd;
-  if (idx >= total) return;
-  SliceIdx s = slice_idx(idx, n, ntau, d);
   int a = s.a, c = s.c, m = s.j;
   cplx acc = mk(0, 0);
   if (s.comp == 0) {  // Eq. cr1, C^R(t_n, t_m)
     if (n > k && n - m > k) {
-      for (int j = m; j <= n; j++)
+      for (int j = m + g; j <= n; j += GC)
         acc = acc + (h * greg(W, n - m, j - m)) *
                         triple(d, [&](int x, int y) { return A.Gret[(tri(n) + j) * dd + x * d + y]; },
                                fat(f, j, d), [&](int x, int y) { return B.Gret[(tri(j) + m) * dd + x * d + y]; }, a, c);
     } else if (n > k) {
-      for (int j = 0; j <= k; j++)
+      for (int j = g; j <= k; j += GC)
         acc = acc + (h * greg(W, n - m, j)) *
                         triple(d, [&](int x, int y) { return A.Gret[(tri(n) + n - j) * dd + x * d + y]; },
                                fat(f, n - j, d), [&](int x, int y) { return cv_ret(B, Bc, n - j, m, x, y); }, a, c);
     } else {
-      for (int j = 0; j <= k; j++)
+      for (int j = g; j <= k; j += GC)
         acc = acc + (h * W.I[m][n][j]) *
                         triple(d, [&](int x, int y) { return cv_ret(A, Ac, n, j, x, y); }, fat(f, j, d),
                                [&](int x, int y) { return cv_ret(B, Bc, j, m, x, y); }, a, c);
@@ -484,19 +446,23 @@ __global__ __launch_bounds__(NT2) void k_convolution(ProbArg pc, ProbArg pa, Pro
     };
     double xi = C.sig;
     if (m <= k) {
-      for (int j = 0; j <= k; j++)
-        for (int l = 0; l <= k; l++) acc = acc + (ht * xi * W.R[m][j][l]) * pr(l, ntau - j);
+      for (int t = g; t < K1 * K1; t += GC) {
+        int j = t / K1, l = t % K1;
+        acc = acc + (ht * xi * W.R[m][j][l]) * pr(l, ntau - j);
+      }
     } else {
-      for (int l = 0; l <= m; l++) acc = acc + (ht * xi * greg(W, m, l)) * pr(m - l, ntau - l);
+      for (int l = g; l <= m; l += GC) acc = acc + (ht * xi * greg(W, m, l)) * pr(m - l, ntau - l);
     }
     if (m >= ntau - k) {
-      for (int j = 0; j <= k; j++)
-        for (int l = 0; l <= k; l++) acc = acc + (ht * W.R[ntau - m][j][l]) * pr(ntau - l, j);
+      for (int t = g; t < K1 * K1; t += GC) {
+        int j = t / K1, l = t % K1;
+        acc = acc + (ht * W.R[ntau - m][j][l]) * pr(ntau - l, j);
+      }
     } else {
-      for (int l = 0; l <= ntau - m; l++) acc = acc + (ht * greg(W, ntau - m, l)) * pr(m + l, l);
+      for (int l = g; l <= ntau - m; l += GC) acc = acc + (ht * greg(W, ntau - m, l)) * pr(m + l, l);
     }
     int jmax = n > k ? n : k;
-    for (int j = 0; j <= jmax; j++) {
+    for (int j = g; j <= jmax; j += GC) {
       double w = n > k ? greg(W, n, j) : W.s[n][j];
       acc = acc + (h * w) * triple(d, [&](int x, int y) { return cv_ret(A, Ac, n, j, x, y); }, fat(f, j, d),
                                    [&](int x, int y) { return B.Gtv[((size_t)j * (ntau + 1) + m) * dd + x * d + y]; },
@@ -504,26 +470,61 @@ __global__ __launch_bounds__(NT2) void k_convolution(ProbArg pc, ProbArg pa, Pro
     }
   } else {  // C^<(t_m, t_n): Eqs. cles1 + cles2 + cles3
     int j1 = m > k ? m : k;
-    for (int j = 0; j <= j1; j++) {
+    for (int j = g; j <= j1; j += GC) {
       double w = m > k ? greg(W, m, j) : W.s[m][j];
       acc = acc + (h * w) * triple(d, [&](int x, int y) { return cv_ret(A, Ac, m, j, x, y); }, fat(f, j, d),
                                    [&](int x, int y) { return cv_les(B, Bc, j, n, x, y); }, a, c);
     }
     int j2 = n > k ? n : k;
-    for (int j = 0; j <= j2; j++) {
+    for (int j = g; j <= j2; j += GC) {
       double w = n > k ? greg(W, n, j) : W.s[n][j];
       acc = acc + (h * w) * triple(d, [&](int x, int y) { return cv_les(A, Ac, m, j, x, y); }, fat(f, j, d),
                                    [&](int x, int y) { return cv_adv(B, Bc, j, n, x, y); }, a, c);
     }
     const cplx* fm = fat(f, -1, d);
     cplx s3 = mk(0, 0);
-    for (int j = 0; j <= ntau; j++)
+    for (int j = g; j <= ntau; j += GC)
       s3 = s3 + (ht * greg(W, ntau, j)) *
                     triple(d, [&](int x, int y) { return A.Gtv[((size_t)m * (ntau + 1) + j) * dd + x * d + y]; }, fm,
                            [&](int x, int y) { return cv_vt(B, Bc, j, n, x, y); }, a, c);
     acc = acc - mul_i(s3);
   }
-  *slice_ptr(C, s, n, C.Gret, C.Gles, C.Gtv) = acc;
+  return acc;
+}
+
+__global__ __launch_bounds__(NT2) void k_convolution(ProbArg pc, ProbArg pa, ProbArg pac,
+                                                     ProbArg pb, ProbArg pbc, int n) {
+  int pi = blockIdx.y;
+  const Prob& C = pc.get(pi);
+  const Prob& A = pa.get(pi);
+  const Prob& Ac = pac.get(pi);
+  const Prob& B = pb.get(pi);
+  const Prob& Bc = pbc.get(pi);
+  int d = C.d, dd = d * d, ntau = C.ntau;
+  long gidx = (long)blockIdx.x * NT2 + threadIdx.x;
+  long idx = gidx / GC;
+  int g = (int)(gidx % GC);
+  if (n > C.nt) return;  // (uniform over the workgroup)
+  long total = n == -1 ? (long)(ntau + 1) * dd : (long)(2 * (n + 1) + ntau + 1) * dd;
+  bool valid = idx < total;
+  cplx acc = mk(0, 0);
+  SliceIdx s{};
+  if (valid) {
+    if (n == -1) {
+      int m = idx / dd, e = idx % dd;
+      acc = mat_conv_part(C, A.Gmat, B.Gmat, C.f, m, e / d, e % d, g);
+    } else {
+      s = slice_idx(idx, n, ntau, d);
+      acc = conv_part(C, A, Ac, B, Bc, n, s, g);
+    }
+  }
+  for (int off = 1; off < GC; off <<= 1) {
+    acc.x += __shfl_xor(acc.x, off);
+    acc.y += __shfl_xor(acc.y, off);
+  }
+  if (!valid || g != 0) return;
+  if (n == -1) C.Gmat[idx] = acc;
+  else *slice_ptr(C, s, n, C.Gret, C.Gles, C.Gtv) = acc;
 }
 
 // --------------------------------------------------------- local Sigma
@@ -697,7 +698,7 @@ hipError_t launch_observables(const ProbArg& pa, int n, double* out, cplx* rho, 
 hipError_t launch_convolution(const ProbArg& C, const ProbArg& A, const ProbArg& Acc,
                               const ProbArg& B, const ProbArg& Bcc, int n, int d, int nelems,
                               hipStream_t s) {
-  dim3 g((nelems + NT2 - 1) / NT2, C.count);
+  dim3 g((unsigned)(((long)nelems * GC + NT2 - 1) / NT2), C.count);
   k_convolution<<<g, NT2, 0, s>>>(C, A, Acc, B, Bcc, n);
   return hipGetLastError();
 }
@@ -709,9 +710,9 @@ namespace cntr {
 // Matsubara convolution with the terms of an element split over GM = 16
 // consecutive lanes (term index = lane mod 16), summed with shuffles in a
 // fixed order.
-constexpr int GM = 16;
-__device__ inline cplx mat_conv_part(const Prob& P, const cplx* A, const cplx* B, const cplx* f, int m, int a,
-                                     int c, int g) {
+constexpr int GM = GC;  // (the same lane groups as k_convolution)
+__device__ cplx mat_conv_part(const Prob& P, const cplx* A, const cplx* B, const cplx* f, int m, int a,
+                              int c, int g) {
   const KW& W = c_kw[P.k];
   int d = P.d, dd = d * d, k = P.k, nt = P.ntau;
   double ht = P.htau, xi = P.sig;
