@@ -183,6 +183,28 @@ cntr_status cntr_vie2_matsubara(int32_t count, const cntr_grid* grids, const cnt
 cntr_status cntr_vie2_step(int32_t tstp, int32_t count, const cntr_grid* grids, const cntr_gf* G, const cntr_gf* F,
                            const cntr_gf* Fcc, const cntr_gf* Q, void* stream);
 
+/* ------------------------------------------------------------------ F2 --
+ * Momentum-convolution self-energies of the k-space GW example (Sec.
+ * "Example: GW for the translationally invariant Hubbard model", Eqs. Pol
+ * and Sigmak), for a lattice of nk momenta k = 0..nk-1 (k + q, k - q taken
+ * mod nk), element by element in the orbital indices:
+ *   cntr_polarization_k: Pi_k(t,t')    = -(i/nk) sum_q G_{k+q}(t,t') G_q(t',t)
+ *                        (Pi_{k,ij} from G_{k+q,ij} and G_{q,ji}),
+ *   cntr_sigma_gw_k:     Sigma_k(t,t') =  (i/nk) sum_q G_{k-q}(t,t') dW_q(t,t')
+ *                        (Sigma_{k,ij} from G_{k-q,ij} and dW_{q,ij}),
+ * on the stored components of time slice tstp (tstp = -1: the Matsubara
+ * component), by the Langreth rules of the two contour products (Eqs.
+ * def_bubble1, def_bubble2). G, dW hermitian; grids[0..nk-1] one grid
+ * (d, k, ntau, nt, statistics of G). G[k], dW[k], Pi[k], Sigma[k]: DEVICE
+ * contour functions of momentum k, owned by the caller; writes slice tstp
+ * of Pi / Sigma only. Asynchronous on `stream`. Errors: CNTR_EINVAL
+ * (nk > 1024, bad grid), CNTR_ESHAPE (null pointers, grids that differ),
+ * CNTR_EORDER (tstp outside -1..nt). */
+cntr_status cntr_polarization_k(int32_t tstp, int32_t nk, const cntr_grid* grids, const cntr_gf* G,
+                                const cntr_gf* Pi, void* stream);
+cntr_status cntr_sigma_gw_k(int32_t tstp, int32_t nk, const cntr_grid* grids, const cntr_gf* G, const cntr_gf* dW,
+                            const cntr_gf* Sigma, void* stream);
+
 /* ------------------------------------------------------------------ A8 --
  * Contour convolution C = A * f * B on time slice tstp (Eq. convolution,
  * Tab. convolution; discretised by Eqs. cm1, cm2, cr1, ctv1-ctv3,

@@ -24,7 +24,8 @@ SYMBOLS = ["cntr_init_matsubara", "cntr_dyson_step", "cntr_convolution", "cntr_s
            "cntr_solve_2b_batch", "cntr_set_checks", "cntr_mark_slices",
            "cntr_dyson_step_noalloc", "cntr_peierls", "cntr_peierls_grad",
            "cntr_graph_begin", "cntr_graph_end", "cntr_graph_launch", "cntr_graph_destroy",
-           "cntr_solve_2b_uneven", "cntr_set_tiles", "cntr_vie2_matsubara", "cntr_vie2_step"]
+           "cntr_solve_2b_uneven", "cntr_set_tiles", "cntr_vie2_matsubara", "cntr_vie2_step",
+           "cntr_polarization_k", "cntr_sigma_gw_k"]
 
 
 class CntrError(RuntimeError):
@@ -85,6 +86,8 @@ def lib():
         L.cntr_set_tiles.argtypes = [i32, i32, P(C.c_int32), P(C.c_int32)]
         L.cntr_vie2_matsubara.argtypes = [i32, P(Grid), P(GF), P(GF), P(GF), dbl, i32, vp]
         L.cntr_vie2_step.argtypes = [i32, i32, P(Grid), P(GF), P(GF), P(GF), P(GF), vp]
+        L.cntr_polarization_k.argtypes = [i32, i32, P(Grid), P(GF), P(GF), vp]
+        L.cntr_sigma_gw_k.argtypes = [i32, i32, P(Grid), P(GF), P(GF), P(GF), vp]
         L.cntr_sync.argtypes = [vp]
         L.cntr_set_checks.argtypes = [i32]
         L.cntr_graph_begin.argtypes = [vp]

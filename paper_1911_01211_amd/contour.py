@@ -130,6 +130,17 @@ def solve_vie2(G: list, F: list, Fcc: list, Q: list, nt_stop=None, stream=None):
         B.step(n, stream)
 
 
+def polarization_k(tstp: int, G: list, Pi: list, stream=None):
+    """Pi_k = -(i/Nk) sum_q G_{k+q}(t,t') G_q(t',t) on slice tstp (cntr_polarization_k)."""
+    _abi.check(_abi.lib().cntr_polarization_k(tstp, len(G), _grids(G), _gfs(G), _gfs(Pi), _stream(stream)))
+
+
+def sigma_gw_k(tstp: int, G: list, dW: list, Sigma: list, stream=None):
+    """Sigma_k = (i/Nk) sum_q G_{k-q}(t,t') dW_q(t,t') on slice tstp (cntr_sigma_gw_k)."""
+    _abi.check(_abi.lib().cntr_sigma_gw_k(tstp, len(G), _grids(G), _gfs(G), _gfs(dW), _gfs(Sigma),
+                                           _stream(stream)))
+
+
 def convolution(tstp: int, C_: list, A: list, Acc: list, B: list, Bcc: list, f=None, stream=None):
     L = _abi.lib()
     fp = None if f is None else _ptrs(f)

@@ -962,6 +962,45 @@ cntr_status cntr_vie2_step(int32_t tstp, int32_t count, const cntr_grid* grids, 
   return CNTR_OK;
 }
 
+// ------------------------------------------ momentum-convolution bubbles
+static cntr_status kspace_call(int mode, int32_t tstp, int32_t nk, const cntr_grid* grids, const cntr_gf* G,
+                               const cntr_gf* dW, const cntr_gf* Out, void* stream, const char* what) {
+  cntr_status st = check_batch(nk, grids, what);
+  if (st) return st;
+  if (nk > 1024) return fail(CNTR_EINVAL, std::string(what) + ": more than 1024 momenta");
+  if (!gf_ok(G, nk) || !gf_ok(Out, nk) || (mode == 2 && !gf_ok(dW, nk)))
+    return fail(CNTR_ESHAPE, std::string(what) + ": null pointer");
+  for (int i = 1; i < nk; i++)
+    if (grids[i].nt != grids[0].nt || grids[i].sig != grids[0].sig)
+      return fail(CNTR_ESHAPE, std::string(what) + ": the momenta must share one grid");
+  if (tstp < -1 || tstp > grids[0].nt) return fail(CNTR_EORDER, std::string(what) + ": tstp outside -1..nt");
+  hipStream_t s = (hipStream_t)stream;
+  StreamScratch* sc = scratch_for(s);
+  if ((st = grow(s, sc, 256, 5 * (size_t)nk, 2))) return st;
+  std::vector<Prob> vg(nk), vw(nk), vo(nk);
+  for (int i = 0; i < nk; i++) {
+    vg[i] = make_prob(grids[i], &G[i], nullptr, nullptr);
+    vo[i] = make_prob(grids[i], &Out[i], nullptr, nullptr);
+    vw[i] = mode == 2 ? make_prob(grids[i], &dW[i], nullptr, nullptr) : vg[i];
+  }
+  ProbArg pg, pw, po;
+  if ((st = make_arg(s, sc, vg, 0, &pg)) || (st = make_arg(s, sc, vw, 1, &pw)) || (st = make_arg(s, sc, vo, 2, &po)))
+    return st;
+  hipError_t e = launch_kbubble(mode, pg, pw, po, tstp, grids[0].d, grids[0].ntau, s);
+  if (e != hipSuccess) return hip_fail(e, (std::string(what) + " launch").c_str());
+  return CNTR_OK;
+}
+
+cntr_status cntr_polarization_k(int32_t tstp, int32_t nk, const cntr_grid* grids, const cntr_gf* G,
+                                const cntr_gf* Pi, void* stream) {
+  return kspace_call(1, tstp, nk, grids, G, nullptr, Pi, stream, "cntr_polarization_k");
+}
+
+cntr_status cntr_sigma_gw_k(int32_t tstp, int32_t nk, const cntr_grid* grids, const cntr_gf* G, const cntr_gf* dW,
+                            const cntr_gf* Sigma, void* stream) {
+  return kspace_call(2, tstp, nk, grids, G, dW, Sigma, stream, "cntr_sigma_gw_k");
+}
+
 cntr_status cntr_convolution(int32_t tstp, int32_t count, const cntr_grid* grids, const cntr_gf* C,
                              const cntr_gf* A, const cntr_gf* Acc, const cntr_gf* B,
                              const cntr_gf* Bcc, const void* const* f, void* stream) {

@@ -142,6 +142,12 @@ hipError_t launch_vie2_start(const ProbArg& pa, const Scratch& sc, int d, int nt
 // side_ok: the step may run its side kernel on a forked stream
 hipError_t launch_vie2_step(const ProbArg& pa, const Scratch& sc, int n, int d, hipStream_t s, bool side_ok = true);
 
+// momentum-convolution bubbles of the k-space GW example: mode 1 the
+// polarization of pg into po, mode 2 the self-energy of (pg, pw) into po;
+// the count of pg is the number of momenta (<= 1024)
+hipError_t launch_kbubble(int mode, const ProbArg& pg, const ProbArg& pw, const ProbArg& po, int n, int d,
+                          int ntau, hipStream_t s);
+
 // Matsubara pieces (per problem, one problem per call)
 hipError_t launch_free_mat(const Prob& P, cplx* g, hipStream_t s);
 // free Green's function of eps(t) into every component of P's G (scratch of

@@ -7,4 +7,5 @@
 #include "mats.hip"
 #include "adjoint.hip"
 #include "free.hip"
+#include "kspace.hip"
 #include "api.cpp"
