@@ -194,16 +194,18 @@ cntr_status cntr_vie2_step(int32_t tstp, int32_t count, const cntr_grid* grids, 
  *                        (Sigma_{k,ij} from G_{k-q,ij} and dW_{q,ij}),
  * on the stored components of time slice tstp (tstp = -1: the Matsubara
  * component), by the Langreth rules of the two contour products (Eqs.
- * def_bubble1, def_bubble2). G, dW hermitian; grids[0..nk-1] one grid
+ * def_bubble1, def_bubble2), times the real factor alpha (e.g. -U for the
+ * kernel F = -U Pi of the screened interaction's integral equation, as the
+ * paper's example multiplies Pol by U). G, dW hermitian; grids[0..nk-1] one grid
  * (d, k, ntau, nt, statistics of G). G[k], dW[k], Pi[k], Sigma[k]: DEVICE
  * contour functions of momentum k, owned by the caller; writes slice tstp
  * of Pi / Sigma only. Asynchronous on `stream`. Errors: CNTR_EINVAL
  * (nk > 1024, bad grid), CNTR_ESHAPE (null pointers, grids that differ),
  * CNTR_EORDER (tstp outside -1..nt). */
 cntr_status cntr_polarization_k(int32_t tstp, int32_t nk, const cntr_grid* grids, const cntr_gf* G,
-                                const cntr_gf* Pi, void* stream);
+                                const cntr_gf* Pi, double alpha, void* stream);
 cntr_status cntr_sigma_gw_k(int32_t tstp, int32_t nk, const cntr_grid* grids, const cntr_gf* G, const cntr_gf* dW,
-                            const cntr_gf* Sigma, void* stream);
+                            const cntr_gf* Sigma, double alpha, void* stream);
 
 /* ------------------------------------------------------------------ A8 --
  * Contour convolution C = A * f * B on time slice tstp (Eq. convolution,

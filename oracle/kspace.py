@@ -108,23 +108,72 @@ def _store(n, C: O.HM, blocks: dict, scale):
     C.tv[n * (g.ntau + 1):(n + 1) * (g.ntau + 1)] = scale * blocks["tv"]
 
 
-def polarization(n, G: list, Pi: list):
-    """Pi_k = -(1/Nk) sum_q Bubble1(G_{k+q}, G_q) on slice n, for every k."""
+def polarization(n, G: list, Pi: list, alpha=1.0):
+    """alpha Pi_k, Pi_k = -(1/Nk) sum_q Bubble1(G_{k+q}, G_q), on slice n, for every k."""
     nk = len(G)
     for k in range(nk):
         acc = None
         for q in range(nk):
             b = bubble1(n, G[(k + q) % nk], G[q])
             acc = b if acc is None else {c: acc[c] + b[c] for c in acc}
-        _store(n, Pi[k], acc, -1.0 / nk)
+        _store(n, Pi[k], acc, -alpha / nk)
 
 
-def sigma_gw(n, G: list, dW: list, Sigma: list):
-    """Sigma_k = (1/Nk) sum_q Bubble2(G_{k-q}, dW_q) on slice n, for every k."""
+def sigma_gw(n, G: list, dW: list, Sigma: list, alpha=1.0):
+    """alpha Sigma_k, Sigma_k = (1/Nk) sum_q Bubble2(G_{k-q}, dW_q), on slice n, for every k."""
     nk = len(G)
     for k in range(nk):
         acc = None
         for q in range(nk):
             b = bubble2(n, G[(k - q) % nk], dW[q])
             acc = b if acc is None else {c: acc[c] + b[c] for c in acc}
-        _store(n, Sigma[k], acc, 1.0 / nk)
+        _store(n, Sigma[k], acc, alpha / nk)
+
+
+def solve_gw(G: list, eps: list, U: float, mats_iters=10, boot_iters=6, ncorr=3, nt_stop=None):
+    """Self-consistent k-space GW propagation (correlation part; Sec. "Example:
+    GW for the translationally invariant Hubbard model"): with the bosonic
+    kernel F_k = -U Pi_k, the screened interaction dW_k = U Pi_k U + U Pi_k * dW_k
+    is dW_k = -U X_k with (1 + F_k) * X_k = F_k (the integral form, Eq. vie2),
+    and Sigma_k = -U (i/Nk) sum_q G_{k-q} X_q.
+      Matsubara: mats_iters x {Pi, X, Sigma on the Matsubara branch; G^M},
+      start-up:  boot_iters x {Pi, X, Sigma on slices 0..k; start-up of G},
+      steps:     extrapolation of G, then ncorr x {Pi, X, Sigma on slice n; step n}.
+    G[k] are the momenta's functions (zero on entry), eps[k] their levels
+    ((nt+2) x d x d, entry 0 = eps(0^-)). Returns (F, X, Sigma)."""
+    g = G[0].g
+    nk, k = len(G), g.k
+    nt_stop = g.nt if nt_stop is None else nt_stop
+    gb = O.Grid(g.nt, g.ntau, g.d, 1, g.k, g.beta, g.h, g.mu)
+    F = [O.HM(gb) for _ in range(nk)]
+    X = [O.HM(gb) for _ in range(nk)]
+    S = [O.HM(g) for _ in range(nk)]
+    for q in range(nk):
+        assert O.dyson_mat(G[q], S[q], eps[q][0]) == 0
+    for _ in range(mats_iters):
+        polarization(-1, G, F, -U)
+        for q in range(nk):
+            assert O.vie2_mat(X[q], F[q], F[q]) == 0
+        sigma_gw(-1, G, X, S, -U)
+        for q in range(nk):
+            assert O.dyson_mat(G[q], S[q], eps[q][0]) == 0
+    for _ in range(boot_iters):
+        for n in range(k + 1):
+            polarization(n, G, F, -U)
+        for q in range(nk):
+            assert O.vie2_start(X[q], F[q], F[q], F[q]) == 0
+        for n in range(k + 1):
+            sigma_gw(n, G, X, S, -U)
+        for q in range(nk):
+            assert O.dyson_start(G[q], S[q], eps[q]) == 0
+    for n in range(k + 1, nt_stop + 1):
+        for q in range(nk):
+            O.extrapolate(n - 1, G[q])
+        for _ in range(ncorr):
+            polarization(n, G, F, -U)
+            for q in range(nk):
+                assert O.vie2_timestep(n, X[q], F[q], F[q], F[q]) == 0
+            sigma_gw(n, G, X, S, -U)
+            for q in range(nk):
+                assert O.dyson_timestep(n, G[q], S[q], eps[q]) == 0
+    return F, X, S

@@ -86,8 +86,8 @@ def lib():
         L.cntr_set_tiles.argtypes = [i32, i32, P(C.c_int32), P(C.c_int32)]
         L.cntr_vie2_matsubara.argtypes = [i32, P(Grid), P(GF), P(GF), P(GF), dbl, i32, vp]
         L.cntr_vie2_step.argtypes = [i32, i32, P(Grid), P(GF), P(GF), P(GF), P(GF), vp]
-        L.cntr_polarization_k.argtypes = [i32, i32, P(Grid), P(GF), P(GF), vp]
-        L.cntr_sigma_gw_k.argtypes = [i32, i32, P(Grid), P(GF), P(GF), P(GF), vp]
+        L.cntr_polarization_k.argtypes = [i32, i32, P(Grid), P(GF), P(GF), dbl, vp]
+        L.cntr_sigma_gw_k.argtypes = [i32, i32, P(Grid), P(GF), P(GF), P(GF), dbl, vp]
         L.cntr_sync.argtypes = [vp]
         L.cntr_set_checks.argtypes = [i32]
         L.cntr_graph_begin.argtypes = [vp]

@@ -130,14 +130,15 @@ def solve_vie2(G: list, F: list, Fcc: list, Q: list, nt_stop=None, stream=None):
         B.step(n, stream)
 
 
-def polarization_k(tstp: int, G: list, Pi: list, stream=None):
-    """Pi_k = -(i/Nk) sum_q G_{k+q}(t,t') G_q(t',t) on slice tstp (cntr_polarization_k)."""
-    _abi.check(_abi.lib().cntr_polarization_k(tstp, len(G), _grids(G), _gfs(G), _gfs(Pi), _stream(stream)))
+def polarization_k(tstp: int, G: list, Pi: list, alpha: float = 1.0, stream=None):
+    """alpha Pi_k, Pi_k = -(i/Nk) sum_q G_{k+q}(t,t') G_q(t',t), on slice tstp (cntr_polarization_k)."""
+    _abi.check(_abi.lib().cntr_polarization_k(tstp, len(G), _grids(G), _gfs(G), _gfs(Pi), float(alpha),
+                                               _stream(stream)))
 
 
-def sigma_gw_k(tstp: int, G: list, dW: list, Sigma: list, stream=None):
-    """Sigma_k = (i/Nk) sum_q G_{k-q}(t,t') dW_q(t,t') on slice tstp (cntr_sigma_gw_k)."""
-    _abi.check(_abi.lib().cntr_sigma_gw_k(tstp, len(G), _grids(G), _gfs(G), _gfs(dW), _gfs(Sigma),
+def sigma_gw_k(tstp: int, G: list, dW: list, Sigma: list, alpha: float = 1.0, stream=None):
+    """alpha Sigma_k, Sigma_k = (i/Nk) sum_q G_{k-q}(t,t') dW_q(t,t'), on slice tstp (cntr_sigma_gw_k)."""
+    _abi.check(_abi.lib().cntr_sigma_gw_k(tstp, len(G), _grids(G), _gfs(G), _gfs(dW), _gfs(Sigma), float(alpha),
                                            _stream(stream)))
 
 
@@ -224,6 +225,48 @@ def solve_local(G: list, Sigma, eps: list, lam: float, mats_iters=30, boot_iters
             B.step(n, stream)
         B.sigma_local(n, lam, stream)
     return B
+
+
+def solve_gw_k(G: list, eps: list, U: float, mats_iters=10, boot_iters=6, ncorr=3, nt_stop=None, stream=None):
+    """Self-consistent k-space GW propagation (correlation part) of the
+    momenta's functions G[k] (zero on entry; levels eps[k], device tensors
+    [(nt+2), d, d]): the bosonic kernel F_k = -U Pi_k (cntr_polarization_k
+    with alpha = -U), X_k from (1 + F_k) * X_k = F_k (one batched
+    cntr_vie2_step per slice; dW_k = -U X_k is the screened interaction's
+    dynamic part), Sigma_k = -U (i/Nk) sum_q G_{k-q} X_q (cntr_sigma_gw_k), and
+    the batched Dyson step of every G_k; the iteration counts as in
+    solve_local. Returns (F, X, Sigma) as lists of contours."""
+    g = G[0].g
+    k, nk = g.k, len(G)
+    nt_stop = g.nt if nt_stop is None else nt_stop
+    gb = dataclasses.replace(g, sig=1)
+    dev = G[0].ret.device
+    F = [Contour(gb, dev) for _ in range(nk)]
+    X = [Contour(gb, dev) for _ in range(nk)]
+    S = [Contour(g, dev) for _ in range(nk)]
+    B = Batch(G, S, eps)
+    V = Vie2Batch(X, F, F, F)
+    B.init_matsubara(stream=stream)
+    for _ in range(mats_iters):
+        polarization_k(-1, G, F, -U, stream)
+        V.matsubara(stream=stream)
+        sigma_gw_k(-1, G, X, S, -U, stream)
+        B.init_matsubara(stream=stream)
+    for _ in range(boot_iters):
+        for n in range(k + 1):
+            polarization_k(n, G, F, -U, stream)
+        V.step(k, stream)
+        for n in range(k + 1):
+            sigma_gw_k(n, G, X, S, -U, stream)
+        B.step(k, stream)
+    for n in range(k + 1, nt_stop + 1):
+        B.extrapolate(n - 1, stream)
+        for _ in range(ncorr):
+            polarization_k(n, G, F, -U, stream)
+            V.step(n, stream)
+            sigma_gw_k(n, G, X, S, -U, stream)
+            B.step(n, stream)
+    return F, X, S
 
 
 OBS_NAMES = ("N", "E1", "Emf", "Ecorr", "Etot")

@@ -964,7 +964,7 @@ cntr_status cntr_vie2_step(int32_t tstp, int32_t count, const cntr_grid* grids, 
 
 // ------------------------------------------ momentum-convolution bubbles
 static cntr_status kspace_call(int mode, int32_t tstp, int32_t nk, const cntr_grid* grids, const cntr_gf* G,
-                               const cntr_gf* dW, const cntr_gf* Out, void* stream, const char* what) {
+                               const cntr_gf* dW, const cntr_gf* Out, double alpha, void* stream, const char* what) {
   cntr_status st = check_batch(nk, grids, what);
   if (st) return st;
   if (nk > 1024) return fail(CNTR_EINVAL, std::string(what) + ": more than 1024 momenta");
@@ -986,19 +986,19 @@ static cntr_status kspace_call(int mode, int32_t tstp, int32_t nk, const cntr_gr
   ProbArg pg, pw, po;
   if ((st = make_arg(s, sc, vg, 0, &pg)) || (st = make_arg(s, sc, vw, 1, &pw)) || (st = make_arg(s, sc, vo, 2, &po)))
     return st;
-  hipError_t e = launch_kbubble(mode, pg, pw, po, tstp, grids[0].d, grids[0].ntau, s);
+  hipError_t e = launch_kbubble(mode, pg, pw, po, tstp, grids[0].d, grids[0].ntau, alpha, s);
   if (e != hipSuccess) return hip_fail(e, (std::string(what) + " launch").c_str());
   return CNTR_OK;
 }
 
 cntr_status cntr_polarization_k(int32_t tstp, int32_t nk, const cntr_grid* grids, const cntr_gf* G,
-                                const cntr_gf* Pi, void* stream) {
-  return kspace_call(1, tstp, nk, grids, G, nullptr, Pi, stream, "cntr_polarization_k");
+                                const cntr_gf* Pi, double alpha, void* stream) {
+  return kspace_call(1, tstp, nk, grids, G, nullptr, Pi, alpha, stream, "cntr_polarization_k");
 }
 
 cntr_status cntr_sigma_gw_k(int32_t tstp, int32_t nk, const cntr_grid* grids, const cntr_gf* G, const cntr_gf* dW,
-                            const cntr_gf* Sigma, void* stream) {
-  return kspace_call(2, tstp, nk, grids, G, dW, Sigma, stream, "cntr_sigma_gw_k");
+                            const cntr_gf* Sigma, double alpha, void* stream) {
+  return kspace_call(2, tstp, nk, grids, G, dW, Sigma, alpha, stream, "cntr_sigma_gw_k");
 }
 
 cntr_status cntr_convolution(int32_t tstp, int32_t count, const cntr_grid* grids, const cntr_gf* C,

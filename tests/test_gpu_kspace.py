@@ -72,12 +72,12 @@ def test_kspace_bubbles_parity(O, d, nk, nt, ntau, kord):
     for n in slices:
         Pi = [O.HM(g) for _ in range(nk)]
         Sg = [O.HM(g) for _ in range(nk)]
-        KS.polarization(n, G, Pi)
-        KS.sigma_gw(n, G, Wb, Sg)
+        KS.polarization(n, G, Pi, 0.7)
+        KS.sigma_gw(n, G, Wb, Sg, -1.3)
         Pid = [K.Contour(spec(g), "cuda") for _ in range(nk)]
         Sgd = [K.Contour(spec(g), "cuda") for _ in range(nk)]
-        K.polarization_k(n, Gd, Pid)
-        K.sigma_gw_k(n, Gd, Wd, Sgd)
+        K.polarization_k(n, Gd, Pid, 0.7)
+        K.sigma_gw_k(n, Gd, Wd, Sgd, -1.3)
         K.sync()
         for name, ref, got in (("Pi", Pi, Pid), ("Sigma", Sg, Sgd)):
             # (a component can vanish identically, e.g. Pi^R at t = t' off the
@@ -91,6 +91,35 @@ def test_kspace_bubbles_parity(O, d, nk, nt, ntau, kord):
         say(f"  slices {slices} ok")
 
 
+def test_kspace_equal_time_lesser_as_stored(O):
+    """A computed G^<(t,t) is anti-hermitian only up to the solver's error:
+    the bubbles take the stored equal-time lesser value as it is (the oracle
+    reads it so). Inputs whose G^<(t_n,t_n) carry a hermitian part of 1e-2."""
+    require_gpu()
+    d, nk, nt, ntau = 2, 3, 6, 8
+    G = band(nk, d, 2, nt, ntau, -1, seed=14, korder=2)
+    Wb = band(nk, d, 2, nt, ntau, 1, seed=15, korder=2)
+    r = W.rng(1915, 0)
+    for X in G + Wb:
+        for n in range(nt + 1):
+            X.les[n * (n + 1) // 2 + n] += 1e-2 * herm(r, d)
+    g = G[0].g
+    Gd, Wd = [dev(x) for x in G], [dev(x) for x in Wb]
+    for n in (0, 3, nt):
+        Pi, Sg = [O.HM(g) for _ in range(nk)], [O.HM(g) for _ in range(nk)]
+        KS.polarization(n, G, Pi)
+        KS.sigma_gw(n, G, Wb, Sg)
+        Pid, Sgd = [K.Contour(spec(g), "cuda") for _ in range(nk)], [K.Contour(spec(g), "cuda") for _ in range(nk)]
+        K.polarization_k(n, Gd, Pid)
+        K.sigma_gw_k(n, Gd, Wd, Sgd)
+        K.sync()
+        for name, ref, got in (("Pi", Pi, Pid), ("Sigma", Sg, Sgd)):
+            for comp, sl in comp_slices(g, n).items():
+                rr = np.stack([getattr(x, comp)[sl] for x in ref])
+                o = np.stack([getattr(x, comp)[sl].cpu().numpy() for x in got])
+                assert np.abs(o - rr).max() <= 1e-12 * max(1.0, np.abs(rr).max()), (name, n, comp)
+
+
 def test_kspace_errors(O):
     require_gpu()
     G = band(2, 1, 2, 4, 6, -1, seed=13, korder=2)
@@ -99,5 +128,29 @@ def test_kspace_errors(O):
         K.polarization_k(5, Gd, [K.Contour(spec(G[0].g), "cuda") for _ in range(2)])
     assert e.value.code == -3
     L = _abi.lib()
-    rc = L.cntr_sigma_gw_k(1, 2, K._grids(Gd), K._gfs(Gd), None, K._gfs(Gd), K._stream())
+    rc = L.cntr_sigma_gw_k(1, 2, K._grids(Gd), K._gfs(Gd), None, K._gfs(Gd), 1.0, K._stream())
     assert rc == -2
+
+
+def test_gw_propagation_matches_oracle(O):
+    """The whole self-consistent GW loop (Matsubara, start-up, predictor-
+    corrector steps) on four momenta with a field pulse: every component of
+    every G_k and Sigma_k against the oracle's solve_gw."""
+    require_gpu()
+    import torch
+    from tests.test_oracle_kspace import gw_band
+    say("gw loop nk=4 nt=16")
+    g, eps = gw_band(16, 0.1, ntau=20)
+    G = [O.HM(g) for _ in range(4)]
+    _, _, S = KS.solve_gw(G, eps, 1.0, mats_iters=6, boot_iters=4, ncorr=3)
+    Gd = [K.Contour(spec(g), "cuda") for _ in range(4)]
+    ed = [torch.as_tensor(e).to("cuda") for e in eps]
+    _, _, Sd = K.solve_gw_k(Gd, ed, 1.0, mats_iters=6, boot_iters=4, ncorr=3)
+    K.sync()
+    for name, ref, got in (("G", G, Gd), ("Sigma", S, Sd)):
+        for comp in K.KEYS:
+            r = np.stack([getattr(x, comp) for x in ref])
+            o = np.stack([getattr(x, comp).cpu().numpy() for x in got])
+            e = float(np.abs(o - r).max() / np.abs(r).max())
+            say(f"  {name} {comp}: {e:.2e}")
+            assert e <= 1e-10, (name, comp, e)
