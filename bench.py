@@ -28,6 +28,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Dyson time-steps/s + FP64 TFLOP/s, batched/adjoint vs plain at <=1e-10 rel err"
 HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6  # FP64 vector (and dense FP64 MFMA) peak of MI355X
 
 # HBM traffic of one history-kernel launch at slice n = 1000, from the
 # FETCH_SIZE / WRITE_SIZE counter runs of `bench.py --profile-step 1000`
@@ -574,6 +575,100 @@ def run_kpoints(args):
             "note": ("whole run" if args.kp_steps >= g.nt else "prefix of the run (the per-slice cost grows with n)")}
 
 
+def bubble_flops(n, nk, d, ntau, mode):
+    """Real flops of one momentum-convolution call on slice n (a complex
+    product 6, a complex sum 2; per element, momentum k and term q):
+    Bubble1 R 16, < 10, rceil 8; Bubble2 R 24, < 8, rceil 8."""
+    per = (16 * (n + 1) + 10 * (n + 1) + 8 * (ntau + 1)) if mode == 1 else (24 * (n + 1) + 8 * (n + 1) + 8 * (ntau + 1))
+    return float(per) * d * d * nk * nk
+
+
+def run_gw(args):
+    """k-space GW (Eqs. Pol, Sigmak, the screened interaction by the integral
+    form) on the batched lattice: nk momenta of eps_k(t) = -2 cos(k - A(t)),
+    d = 1, U = 2, beta = 10, ntau = 500, h = 0.02, k = 5; untimed Matsubara
+    loop and start-up, then the timed steps k+1..nt, each an extrapolation and
+    ncorr x {Pi_k, (1 + F_k) * X_k = F_k, Sigma_k, Dyson step} for all
+    momenta (one launch sequence per call). At the last slice every call is
+    timed with HIP events on the launch stream; the momentum sums are counted
+    in real flops against the FP64 vector peak (plain FMA arithmetic from LDS)."""
+    import dataclasses
+
+    import torch
+
+    from paper_1911_01211_amd import contour as K
+    from paper_1911_01211_amd import workloads as W
+
+    nk, U, ncorr = args.gw_nk, 2.0, 3
+    g = W.GridSpec(nt=args.gw_nt, ntau=500, d=1, sig=-1, k=5, beta=10.0, h=0.02, mu=0.0)
+    eps = [torch.as_tensor(e).to("cuda:0") for e in W.kpoint_band(g, nk)]
+    gb = dataclasses.replace(g, sig=1)
+    G = [K.Contour(g, "cuda:0") for _ in range(nk)]
+    F = [K.Contour(gb, "cuda:0") for _ in range(nk)]
+    X = [K.Contour(gb, "cuda:0") for _ in range(nk)]
+    S = [K.Contour(g, "cuda:0") for _ in range(nk)]
+    B = K.Batch(G, S, eps)
+    V = K.Vie2Batch(X, F, F, F)
+    KB = K.KBatch(G, F, X, S)
+    B.init_matsubara()
+    for _ in range(10):
+        KB.polarization(-1, -U)
+        V.matsubara()
+        KB.sigma(-1, -U)
+        B.init_matsubara()
+    for _ in range(6):
+        for n in range(g.k + 1):
+            KB.polarization(n, -U)
+        V.step(g.k)
+        for n in range(g.k + 1):
+            KB.sigma(n, -U)
+        B.step(g.k)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for n in range(g.k + 1, g.nt + 1):
+        B.extrapolate(n - 1)
+        for _ in range(ncorr):
+            KB.polarization(n, -U)
+            V.step(n)
+            KB.sigma(n, -U)
+            B.step(n)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+
+    def timed(f, reps=5):
+        # a GPU-side wait first, so that the calls are queued before the
+        # first event and the interval holds the kernels alone
+        torch.cuda._sleep(20_000_000)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            f()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    n = g.nt
+    ms = {"polarization_k": timed(lambda: KB.polarization(n, -U)),
+          "vie2_step": timed(lambda: V.step(n)),
+          "sigma_gw_k": timed(lambda: KB.sigma(n, -U)),
+          "dyson_step": timed(lambda: B.step(n))}
+    fl = {"polarization_k": bubble_flops(n, nk, g.d, g.ntau, 1), "sigma_gw_k": bubble_flops(n, nk, g.d, g.ntau, 2)}
+    tf = {c: fl[c] / (ms[c] * 1e-3) / 1e12 for c in fl}
+    # particle number sum_k n_k(t) = sum_k Im G_k^<(t,t) is conserved by GW
+    dens = []
+    for m in (0, n // 2, n):
+        o = m * (m + 1) // 2 + m
+        dens.append(float(sum(x.les[o, 0, 0].imag.item() for x in G)))
+    return {"workload": f"k-space GW, {nk} momenta, eps_k = -2 cos(k - A(t)), d=1, U={U}, beta=10, ntau=500, "
+                        f"h=0.02, k=5; steps {g.k + 1}..{g.nt} timed, {ncorr} corrector iterations each",
+            "value": (g.nt - g.k) * nk / el, "unit": "instance time-steps/s", "seconds": el,
+            "ms_per_call_at_last_slice": ms, "slice": n,
+            "roofline": {"bound": "alu", "kernel": "k_kbubble<1> (polarization_k)", "achieved": tf["polarization_k"],
+                         "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": tf["polarization_k"] / FP64_PEAK_TFLOPS,
+                         "flops": fl["polarization_k"], "sigma_gw_k_tflops": tf["sigma_gw_k"]},
+            "check": {"particle_number": dens, "drift": max(abs(x - dens[0]) for x in dens)}}
+
+
 def stream_bandwidth():
     """Device copy of 1 GiB (1 GiB read + 1 GiB written), best of 5, in GB/s:
     the attainable HBM rate that the roofline is also quoted against."""
@@ -727,6 +822,9 @@ def main():
     ap.add_argument("--no-free", action="store_true")
     ap.add_argument("--no-cfg1", action="store_true")
     ap.add_argument("--no-vie2", action="store_true")
+    ap.add_argument("--no-gw", action="store_true")
+    ap.add_argument("--gw-nk", type=int, default=256, help="momenta of the k-space GW sample")
+    ap.add_argument("--gw-nt", type=int, default=400, help="last slice of the k-space GW sample")
     ap.add_argument("--no-tune-cache", action="store_true", help="built-in term chunks instead of tune_cache.json")
     ap.add_argument("--uneven-count", type=int, default=64, help="problems of the uneven batch (of 384)")
     ap.add_argument("--uneven-nt", type=int, default=400, help="slices of each uneven problem (causal prefix)")
@@ -805,6 +903,8 @@ def main():
         out["free_propagator"] = run_free(args)
     if not args.no_kpoints:
         out["batched"] = run_kpoints(args)
+    if not args.no_gw:
+        out["gw_kspace"] = run_gw(args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(g, args.ncorr, stats.mats_iter, args.cpu_budget)
     print(json.dumps(out), flush=True)

@@ -196,7 +196,9 @@ cntr_status cntr_vie2_step(int32_t tstp, int32_t count, const cntr_grid* grids, 
  * component), by the Langreth rules of the two contour products (Eqs.
  * def_bubble1, def_bubble2), times the real factor alpha (e.g. -U for the
  * kernel F = -U Pi of the screened interaction's integral equation, as the
- * paper's example multiplies Pol by U). G, dW hermitian; grids[0..nk-1] one grid
+ * paper's example multiplies Pol by U). G, dW hermitian (a lesser value
+ * below the stored triangle is -[X^<(t',t)]^dagger; the stored X^<(t,t) is
+ * used as it is); grids[0..nk-1] one grid
  * (d, k, ntau, nt, statistics of G). G[k], dW[k], Pi[k], Sigma[k]: DEVICE
  * contour functions of momentum k, owned by the caller; writes slice tstp
  * of Pi / Sigma only. Asynchronous on `stream`. Errors: CNTR_EINVAL

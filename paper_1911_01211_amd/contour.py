@@ -130,6 +130,25 @@ def solve_vie2(G: list, F: list, Fcc: list, Q: list, nt_stop=None, stream=None):
         B.step(n, stream)
 
 
+class KBatch:
+    """The C-ABI argument arrays of the momentum-convolution calls over fixed
+    lists of momenta (G_k, Pi_k, dW_k, Sigma_k), built once: marshalling
+    hundreds of contours per call costs more host time than the kernel."""
+
+    def __init__(self, G: list, Pi: list, dW: list, Sigma: list):
+        self.nk = len(G)
+        self.grids = _grids(G)
+        self.g, self.pi, self.w, self.s = _gfs(G), _gfs(Pi), _gfs(dW), _gfs(Sigma)
+
+    def polarization(self, tstp: int, alpha: float = 1.0, stream=None):
+        _abi.check(_abi.lib().cntr_polarization_k(tstp, self.nk, self.grids, self.g, self.pi, float(alpha),
+                                                   _stream(stream)))
+
+    def sigma(self, tstp: int, alpha: float = 1.0, stream=None):
+        _abi.check(_abi.lib().cntr_sigma_gw_k(tstp, self.nk, self.grids, self.g, self.w, self.s, float(alpha),
+                                               _stream(stream)))
+
+
 def polarization_k(tstp: int, G: list, Pi: list, alpha: float = 1.0, stream=None):
     """alpha Pi_k, Pi_k = -(i/Nk) sum_q G_{k+q}(t,t') G_q(t',t), on slice tstp (cntr_polarization_k)."""
     _abi.check(_abi.lib().cntr_polarization_k(tstp, len(G), _grids(G), _gfs(G), _gfs(Pi), float(alpha),
@@ -246,25 +265,26 @@ def solve_gw_k(G: list, eps: list, U: float, mats_iters=10, boot_iters=6, ncorr=
     S = [Contour(g, dev) for _ in range(nk)]
     B = Batch(G, S, eps)
     V = Vie2Batch(X, F, F, F)
+    KB = KBatch(G, F, X, S)
     B.init_matsubara(stream=stream)
     for _ in range(mats_iters):
-        polarization_k(-1, G, F, -U, stream)
+        KB.polarization(-1, -U, stream)
         V.matsubara(stream=stream)
-        sigma_gw_k(-1, G, X, S, -U, stream)
+        KB.sigma(-1, -U, stream)
         B.init_matsubara(stream=stream)
     for _ in range(boot_iters):
         for n in range(k + 1):
-            polarization_k(n, G, F, -U, stream)
+            KB.polarization(n, -U, stream)
         V.step(k, stream)
         for n in range(k + 1):
-            sigma_gw_k(n, G, X, S, -U, stream)
+            KB.sigma(n, -U, stream)
         B.step(k, stream)
     for n in range(k + 1, nt_stop + 1):
         B.extrapolate(n - 1, stream)
         for _ in range(ncorr):
-            polarization_k(n, G, F, -U, stream)
+            KB.polarization(n, -U, stream)
             V.step(n, stream)
-            sigma_gw_k(n, G, X, S, -U, stream)
+            KB.sigma(n, -U, stream)
             B.step(n, stream)
     return F, X, S
 

@@ -144,9 +144,10 @@ hipError_t launch_vie2_step(const ProbArg& pa, const Scratch& sc, int n, int d, 
 
 // momentum-convolution bubbles of the k-space GW example: mode 1 the
 // polarization of pg into po, mode 2 the self-energy of (pg, pw) into po;
-// the count of pg is the number of momenta (<= 1024); the result times alpha
-hipError_t launch_kbubble(int mode, const ProbArg& pg, const ProbArg& pw, const ProbArg& po, int n, int d,
-                          int ntau, double alpha, hipStream_t s);
+// pg, pw, po: device descriptor arrays of nk momenta (<= 1024) sharing one
+// grid (d, ntau, the statistics sig of G); the result times alpha
+hipError_t launch_kbubble(int mode, const Prob* pg, const Prob* pw, const Prob* po, int nk, int d, int ntau,
+                          int sig, int n, double alpha, hipStream_t s);
 
 // Matsubara pieces (per problem, one problem per call)
 hipError_t launch_free_mat(const Prob& P, cplx* g, hipStream_t s);
