@@ -448,6 +448,99 @@ struct MatsState {
   ~MatsState() { release(); }
 };
 
+cntr_status mats_refine(MatsState& st, const Prob& P, bool use_guess, double tol, int max_iter,
+                        hipStream_t s, int* iters);
+
+// Operators, right-hand sides and inverses of B Matsubara problems of one
+// size side by side, for one batched inverse launch sequence.
+struct MatsGroup {
+  int N = 0, B = 0;
+  size_t ws = 0, gs = 0;
+  cplx *g = nullptr, *A = nullptr, *Ainv = nullptr, *work = nullptr;
+  int *piv = nullptr, *status = nullptr;
+  cntr_status alloc(int ntau, int dd, int b) {
+    N = (ntau + 1) * dd;
+    B = b;
+    ws = gj_work_elems(N);
+    gs = (size_t)(ntau + 1) * dd * dd;
+    size_t nn = (size_t)N * N;
+    if (hipMalloc(&g, B * gs * sizeof(cplx)) || hipMalloc(&A, B * nn * sizeof(cplx)) ||
+        hipMalloc(&Ainv, B * nn * sizeof(cplx)) || hipMalloc(&work, B * ws * sizeof(cplx)) ||
+        hipMalloc(&piv, (size_t)B * N * sizeof(int)) || hipMalloc(&status, (size_t)B * sizeof(int))) {
+      release();
+      return fail(CNTR_ENOMEM, "Matsubara batch workspace allocation failed");
+    }
+    return CNTR_OK;
+  }
+  void release() {
+    for (void* p : {(void*)g, (void*)A, (void*)Ainv, (void*)work, (void*)piv, (void*)status})
+      if (p) (void)hipFree(p);
+    g = A = Ainv = work = nullptr;
+    piv = status = nullptr;
+  }
+  ~MatsGroup() { release(); }
+};
+
+// A MatsState that borrows the memory of a group and of a state (frees nothing)
+struct MatsView : MatsState {
+  ~MatsView() {
+    g = K = A = Ainv = r = dx = work = smix = emix = nullptr;
+    piv = status = nullptr;
+    norms = nullptr;
+  }
+};
+
+// Matsubara solves of count problems of one size: build(i, A, g) enqueues
+// problem i's operator into A and its right-hand side into g and returns its
+// descriptor. The operators of a group (at most 256, at most 2 GiB of
+// matrices) are inverted by one batched launch sequence, then each problem
+// is refined with its own inverse (the inverse and the refinement of a
+// single solve, so the results are those of the one-problem path).
+template <class Build>
+static cntr_status mats_solve_batch(int count, MatsState& ms, int ntau, Build build, double tol, int max_iter,
+                                    hipStream_t s) {
+  int N = ms.N, d = ms.d;
+  size_t nn = (size_t)N * N;
+  size_t fit = ((size_t)2 << 30) / (2 * nn * sizeof(cplx));
+  int gmax = (int)std::max<size_t>(1, std::min<size_t>(256, fit));
+  for (int i0 = 0; i0 < count; i0 += gmax) {
+    int B = std::min(gmax, count - i0);
+    MatsGroup grp;
+    cntr_status st = grp.alloc(ntau, d, B);
+    if (st) return st;
+    std::vector<Prob> P(B);
+    hipError_t e = hipSuccess;
+    for (int b = 0; b < B && e == hipSuccess; b++) e = build(i0 + b, grp.A + b * nn, grp.g + b * grp.gs, &P[b]);
+    if (e != hipSuccess) return hip_fail(e, "Matsubara operators");
+    if ((e = hipMemcpyAsync(grp.Ainv, grp.A, B * nn * sizeof(cplx), hipMemcpyDeviceToDevice, s)) ||
+        (e = hipMemsetAsync(grp.status, 0, (size_t)B * sizeof(int), s)) ||
+        (e = launch_gj_inverse_batch(N, B, grp.Ainv, grp.work, grp.piv, grp.status, s)))
+      return hip_fail(e, "batched inverse");
+    std::vector<int> stat(B);
+    if ((st = readback(s, stat.data(), grp.status, (size_t)B * sizeof(int), "inverse status"))) return st;
+    for (int b = 0; b < B; b++)
+      if (stat[b] != 0) return fail(CNTR_ESINGULAR, "singular Matsubara operator");
+    for (int b = 0; b < B; b++) {
+      MatsView v;
+      v.N = N;
+      v.d = d;
+      v.g = grp.g + b * grp.gs;
+      v.K = ms.K;
+      v.A = grp.A + b * nn;
+      v.Ainv = grp.Ainv + b * nn;
+      v.r = ms.r;
+      v.dx = ms.dx;
+      v.work = grp.work + b * grp.ws;
+      v.piv = grp.piv + (size_t)b * N;
+      v.status = grp.status + b;
+      v.norms = ms.norms;
+      v.have_inv = true;
+      if ((st = mats_refine(v, P[b], false, tol, max_iter, s, nullptr))) return st;
+    }
+  }
+  return CNTR_OK;
+}
+
 // Solve the discrete Matsubara equation for P (eps = eps_{-1} at entry 0,
 // Sigma^M in P.Smat) into P.Gmat. The current P.Gmat is the initial guess
 // when use_guess; the inverse of an earlier operator is reused when present.
@@ -944,13 +1037,26 @@ cntr_status cntr_init_matsubara(int32_t count, const cntr_grid* grids, const cnt
   hipStream_t s = (hipStream_t)stream;
   if (tol <= 0) tol = 1e-14;
   if (max_iter <= 0) max_iter = 200;
+  for (int i = 0; i < count; i++)
+    if (!eps[i]) return fail(CNTR_ESHAPE, "cntr_init_matsubara: null eps");
   MatsState ms;
   if ((st = ms.alloc(grids[0].ntau, grids[0].d))) return st;
-  for (int i = 0; i < count; i++) {
-    if (!eps[i]) return fail(CNTR_ESHAPE, "cntr_init_matsubara: null eps");
-    Prob P = make_prob(grids[i], &G[i], &Sigma[i], eps[i]);
-    ms.have_inv = false;
-    if ((st = mats_solve(ms, P, false, tol, max_iter, s, nullptr))) return st;
+  if (count > 1 && ms.N <= GJ_BATCH_MAX_N) {
+    auto build = [&](int i, cplx* A, cplx* g, Prob* P) -> hipError_t {
+      *P = make_prob(grids[i], &G[i], &Sigma[i], eps[i]);
+      hipError_t e;
+      if ((e = launch_free_mat(*P, g, s)) || (e = launch_mat_conv(*P, g, P->Smat, nullptr, ms.K, s)) ||
+          (e = launch_mat_build(*P, ms.K, A, s)))
+        return e;
+      return hipSuccess;
+    };
+    if ((st = mats_solve_batch(count, ms, grids[0].ntau, build, tol, max_iter, s))) return st;
+  } else {
+    for (int i = 0; i < count; i++) {
+      Prob P = make_prob(grids[i], &G[i], &Sigma[i], eps[i]);
+      ms.have_inv = false;
+      if ((st = mats_solve(ms, P, false, tol, max_iter, s, nullptr))) return st;
+    }
   }
   order_mark(count, G, -1, true);
   return CNTR_OK;
@@ -990,14 +1096,25 @@ cntr_status cntr_vie2_matsubara(int32_t count, const cntr_grid* grids, const cnt
   MatsState ms;
   if ((st = ms.alloc(grids[0].ntau, grids[0].d))) return st;
   size_t vec = (size_t)ms.N * ms.d * sizeof(cplx);
-  for (int i = 0; i < count; i++) {
-    Prob P = vie2_prob(grids[i], &G[i], &F[i], nullptr, &Q[i]);
-    hipError_t e;
-    // G_m + [F * G]^M(m) = Q_m (Eq. vie2_langreth_m) as one dense system
-    if ((e = launch_mat_build(P, P.Smat, ms.A, s, +1.0))) return hip_fail(e, "vie2 Matsubara operator");
-    if ((e = hipMemcpyAsync(ms.g, P.Qmat, vec, hipMemcpyDeviceToDevice, s))) return hip_fail(e, "vie2 source");
-    ms.have_inv = false;
-    if ((st = mats_refine(ms, P, false, tol, max_iter, s, nullptr))) return st;
+  if (count > 1 && ms.N <= GJ_BATCH_MAX_N) {
+    // G_m + [F * G]^M(m) = Q_m (Eq. vie2_langreth_m) as one dense system each
+    auto build = [&](int i, cplx* A, cplx* g, Prob* P) -> hipError_t {
+      *P = vie2_prob(grids[i], &G[i], &F[i], nullptr, &Q[i]);
+      hipError_t e;
+      if ((e = launch_mat_build(*P, P->Smat, A, s, +1.0))) return e;
+      return hipMemcpyAsync(g, P->Qmat, vec, hipMemcpyDeviceToDevice, s);
+    };
+    if ((st = mats_solve_batch(count, ms, grids[0].ntau, build, tol, max_iter, s))) return st;
+  } else {
+    for (int i = 0; i < count; i++) {
+      Prob P = vie2_prob(grids[i], &G[i], &F[i], nullptr, &Q[i]);
+      hipError_t e;
+      // G_m + [F * G]^M(m) = Q_m (Eq. vie2_langreth_m) as one dense system
+      if ((e = launch_mat_build(P, P.Smat, ms.A, s, +1.0))) return hip_fail(e, "vie2 Matsubara operator");
+      if ((e = hipMemcpyAsync(ms.g, P.Qmat, vec, hipMemcpyDeviceToDevice, s))) return hip_fail(e, "vie2 source");
+      ms.have_inv = false;
+      if ((st = mats_refine(ms, P, false, tol, max_iter, s, nullptr))) return st;
+    }
   }
   order_mark(count, G, -1, true);
   return CNTR_OK;

@@ -167,6 +167,11 @@ hipError_t launch_gj_inverse(int N, cplx* Amat, cplx* work, int* piv, int* statu
                              hipStream_t s);
 // complex elements of the work buffer of launch_gj_inverse
 size_t gj_work_elems(int N);
+// The blocked inverse of B matrices of one size N <= GJ_BATCH_MAX_N side by
+// side in one launch sequence (matrices N*N apart, work regions
+// gj_work_elems(N) apart, pivots N apart, one status word each).
+constexpr int GJ_BATCH_MAX_N = 2048;
+hipError_t launch_gj_inverse_batch(int N, int B, cplx* A, cplx* work, int* piv, int* status, hipStream_t s);
 // y = X v  (X: N x N, v, y: N x nrhs); y = b - X v when b != nullptr;
 // zero2[0..1] = 0 when zero2 != nullptr (accumulators of a following norm)
 hipError_t launch_matvec(int N, int nrhs, const cplx* X, const cplx* v, const cplx* b, cplx* y,

@@ -243,7 +243,10 @@ __global__ __launch_bounds__(NT3) void k_gj_update(int N, int c, cplx* A, const 
 }
 
 // undo the row interchanges: column swaps in reverse order, row by row
+// (grid z: the problems of a batch, matrices N*N apart)
 __global__ __launch_bounds__(NT3) void k_gj_unpivot(int N, cplx* A, const int* piv) {
+  A += (size_t)blockIdx.z * N * N;
+  piv += (size_t)blockIdx.z * N;
   long r = (long)blockIdx.x * NT3 + threadIdx.x;
   if (r >= N) return;
   cplx* row = A + r * N;
@@ -269,6 +272,7 @@ __global__ __launch_bounds__(NT3) void k_gj_unpivot(int N, cplx* A, const int* p
 // its steps and A_1j the pivot rows before them.
 constexpr int GJB = 8;
 constexpr int GJT = 512, GJH = 4;  // panel workgroup: GJT threads, GJH rows each (N <= GJT GJH)
+static_assert(GJT * GJH == GJ_BATCH_MAX_N, "blocked inverse size limit");
 
 __device__ inline void gj_argmax(double& v, int& i) {
   // ties: smaller index
@@ -283,8 +287,18 @@ __device__ inline void gj_argmax(double& v, int& i) {
   }
 }
 
+// (grid z: the problems of a batch; matrices N*N apart, work regions ws
+// elements apart, pivots N apart, one status word each)
 __global__ __launch_bounds__(GJT) void k_gjb_panel(int N, int c0, int nb, cplx* A, cplx* ob, int* rlist,
-                                                   int* piv, int* status) {
+                                                   int* piv, int* status, size_t ws) {
+  {
+    size_t z = blockIdx.z;
+    A += z * N * N;
+    ob += z * ws;
+    rlist = (int*)((cplx*)rlist + z * ws);
+    piv += z * N;
+    status += z;
+  }
   // per-step LDS, double-buffered by the parity of the step (one barrier
   // fewer per step)
   __shared__ double wv[2][GJT / 64];
@@ -474,7 +488,13 @@ __global__ __launch_bounds__(GJT) void k_gjb_panel(int N, int c0, int nb, cplx* 
 // interchanges take their (interchanged) old values from ob.
 constexpr int GJR = 16;
 __global__ __launch_bounds__(NT3) void k_gjb_update(int N, int c0, int nb, cplx* A, const cplx* ob,
-                                                    const int* rlist) {
+                                                    const int* rlist, size_t ws) {
+  {
+    size_t z = blockIdx.z;
+    A += z * N * N;
+    ob += z * ws;
+    rlist = (const int*)((const cplx*)rlist + z * ws);
+  }
   __shared__ cplx ps[GJR][GJB];
   __shared__ int rl[2 * GJB + 1];
   int t = threadIdx.x;
@@ -516,24 +536,29 @@ __global__ __launch_bounds__(NT3) void k_gjb_update(int N, int c0, int nb, cplx*
 // ob (2 GJB rows of N) and the list of the rows involved (2 GJB + 1 ints)
 size_t gj_work_elems(int N) { return (size_t)(2 * GJB) * N + 4 * GJB; }
 
+hipError_t launch_gj_inverse_batch(int N, int B, cplx* A, cplx* work, int* piv, int* status, hipStream_t s) {
+  if (N > GJT * GJH) return hipErrorInvalidValue;
+  size_t ws = gj_work_elems(N);
+  dim3 gu((N + NT3 - 1) / NT3, (N + GJR - 1) / GJR, B);
+  for (int c0 = 0; c0 < N; c0 += GJB) {
+    int nb = N - c0 < GJB ? N - c0 : GJB;
+    int* rlist = (int*)(work + (size_t)(2 * GJB) * N);
+    k_gjb_panel<<<dim3(1, 1, B), GJT, 0, s>>>(N, c0, nb, A, work, rlist, piv, status, ws);
+    k_gjb_update<<<gu, NT3, 0, s>>>(N, c0, nb, A, work, rlist, ws);
+  }
+  k_gj_unpivot<<<dim3((N + NT3 - 1) / NT3, 1, B), NT3, 0, s>>>(N, A, piv);
+  return hipGetLastError();
+}
+
 hipError_t launch_gj_inverse(int N, cplx* A, cplx* work, int* piv, int* status, hipStream_t s) {
-  if (N <= GJT * GJH) {
-    dim3 gu((N + NT3 - 1) / NT3, (N + GJR - 1) / GJR);
-    for (int c0 = 0; c0 < N; c0 += GJB) {
-      int nb = N - c0 < GJB ? N - c0 : GJB;
-      int* rlist = (int*)(work + (size_t)(2 * GJB) * N);
-      k_gjb_panel<<<1, GJT, 0, s>>>(N, c0, nb, A, work, rlist, piv, status);
-      k_gjb_update<<<gu, NT3, 0, s>>>(N, c0, nb, A, work, rlist);
-    }
-  } else {
-    cplx* col = work;
-    cplx* prow = work + N;
-    long tot = (long)N * N;
-    unsigned nbk = (unsigned)((tot + NT3 - 1) / NT3);
-    for (int c = 0; c < N; c++) {
-      k_gj_pivot<<<1, NGJ, 0, s>>>(N, c, A, col, prow, piv, status);
-      k_gj_update<<<nbk, NT3, 0, s>>>(N, c, A, col, prow);
-    }
+  if (N <= GJT * GJH) return launch_gj_inverse_batch(N, 1, A, work, piv, status, s);
+  cplx* col = work;
+  cplx* prow = work + N;
+  long tot = (long)N * N;
+  unsigned nbk = (unsigned)((tot + NT3 - 1) / NT3);
+  for (int c = 0; c < N; c++) {
+    k_gj_pivot<<<1, NGJ, 0, s>>>(N, c, A, col, prow, piv, status);
+    k_gj_update<<<nbk, NT3, 0, s>>>(N, c, A, col, prow);
   }
   k_gj_unpivot<<<(N + NT3 - 1) / NT3, NT3, 0, s>>>(N, A, piv);
   return hipGetLastError();
