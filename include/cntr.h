@@ -209,6 +209,48 @@ cntr_status cntr_polarization_k(int32_t tstp, int32_t nk, const cntr_grid* grids
 cntr_status cntr_sigma_gw_k(int32_t tstp, int32_t nk, const cntr_grid* grids, const cntr_gf* G, const cntr_gf* dW,
                             const cntr_gf* Sigma, double alpha, void* stream);
 
+/* ------------------------------------------------------------------ F4 --
+ * Pieces of the Holstein-model DMFT with the unrenormalized Migdal impurity
+ * solver (Sec. "DMFT for the Holstein model"; the Bethe-lattice loop itself
+ * is host code over these calls, cntr_sigma_gw_k and cntr_dyson_step).
+ *
+ * cntr_phonon_free: the free phonon propagator D0(z,z') = -i <T_C X(z) X(z')>_0
+ *   of one mode X = a + a^dagger of frequency w0[i] > 0 at the grid's inverse
+ *   temperature, into every component of D[i] (all slices 0..nt and the
+ *   Matsubara branch): D0^R(t,t') = -2 sin(w0 (t - t')), D0^< and the mixing
+ *   component from the Bose factor nB = 1/(e^{beta w0} - 1), D0^M(tau) =
+ *   -[(1 + nB) e^{-w0 tau} + nB e^{w0 tau}]. grids: bosonic (sig = +1), d = 1;
+ *   w0: HOST array of count values. Errors: CNTR_ESHAPE (d != 1, sig != +1,
+ *   null pointers), CNTR_EINVAL (w0 <= 0).
+ *
+ * cntr_scale_slice: C = beta C + f(t) A(t,t') f(t') on slice tstp (tstp = -1:
+ *   the Matsubara component, both times on the vertical branch, f(0^-)): the
+ *   Bethe-lattice hybridization Delta = J G J (Eq. bethe_condition), the
+ *   coupled propagator g D0 g of the uMig self-energy (Eq. uMig_el), and
+ *   Delta + Sigma (f = 1, beta = 1). f[i]: DEVICE array of nt+2 real values,
+ *   entry 0 on the Matsubara branch, entry n+1 at t_n. C may be A. With
+ *   beta = 0 C is not read. Any d. Errors: CNTR_ESHAPE, CNTR_EORDER (tstp
+ *   outside -1..nt).
+ *
+ * cntr_holstein_mf: the phonon displacement of Eq. X,
+ *   X(t_n) = -2 g(0) n(0)/w0 + int_0^{t_n} D0^R(t_n,s) [g(s) n(s) - g(0) n(0)] ds,
+ *   n(t) = 2 Im G^<(t,t) (both spins), by the library's quadrature of order k
+ *   (start weights over slices 0..k for tstp <= k, Gregory weights beyond), and
+ *   the mean-field level e0 + g(t_n) X(t_n) (Eq. H_mf_Holstein); tstp = -1:
+ *   the equilibrium X(0^-) = -2 g(0^-) n / w0 with n = -2 G^M(beta^-). Writes
+ *   X[i][tstp+1] and eps[i][tstp+1] (one complex value, the d = 1 level of
+ *   the Dyson calls). g[i], X[i]: DEVICE arrays of nt+2 reals (same indexing
+ *   as f above); eps[i]: DEVICE array of nt+2 complex values; w0: HOST array.
+ *   Reads slices 0..max(tstp, k) of G. Errors: CNTR_ESHAPE (d != 1, null
+ *   pointers), CNTR_EINVAL (w0 <= 0), CNTR_EORDER (tstp outside -1..nt). */
+cntr_status cntr_phonon_free(int32_t count, const cntr_grid* grids, const cntr_gf* D, const double* w0,
+                             void* stream);
+cntr_status cntr_scale_slice(int32_t tstp, int32_t count, const cntr_grid* grids, const cntr_gf* C,
+                             const cntr_gf* A, const void* const* f, double beta, void* stream);
+cntr_status cntr_holstein_mf(int32_t tstp, int32_t count, const cntr_grid* grids, const cntr_gf* G,
+                             const void* const* g, const double* w0, double e0, void* const* X, void* const* eps,
+                             void* stream);
+
 /* ------------------------------------------------------------------ A8 --
  * Contour convolution C = A * f * B on time slice tstp (Eq. convolution,
  * Tab. convolution; discretised by Eqs. cm1, cm2, cr1, ctv1-ctv3,

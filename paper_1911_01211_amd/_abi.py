@@ -25,7 +25,8 @@ SYMBOLS = ["cntr_init_matsubara", "cntr_dyson_step", "cntr_convolution", "cntr_s
            "cntr_dyson_step_noalloc", "cntr_peierls", "cntr_peierls_grad",
            "cntr_graph_begin", "cntr_graph_end", "cntr_graph_launch", "cntr_graph_destroy",
            "cntr_solve_2b_uneven", "cntr_set_tiles", "cntr_vie2_matsubara", "cntr_vie2_step",
-           "cntr_polarization_k", "cntr_sigma_gw_k"]
+           "cntr_polarization_k", "cntr_sigma_gw_k", "cntr_phonon_free", "cntr_scale_slice",
+           "cntr_holstein_mf"]
 
 
 class CntrError(RuntimeError):
@@ -88,6 +89,9 @@ def lib():
         L.cntr_vie2_step.argtypes = [i32, i32, P(Grid), P(GF), P(GF), P(GF), P(GF), vp]
         L.cntr_polarization_k.argtypes = [i32, i32, P(Grid), P(GF), P(GF), dbl, vp]
         L.cntr_sigma_gw_k.argtypes = [i32, i32, P(Grid), P(GF), P(GF), P(GF), dbl, vp]
+        L.cntr_phonon_free.argtypes = [i32, P(Grid), P(GF), P(dbl), vp]
+        L.cntr_scale_slice.argtypes = [i32, i32, P(Grid), P(GF), P(GF), P(vp), dbl, vp]
+        L.cntr_holstein_mf.argtypes = [i32, i32, P(Grid), P(GF), P(vp), P(dbl), dbl, P(vp), P(vp), vp]
         L.cntr_sync.argtypes = [vp]
         L.cntr_set_checks.argtypes = [i32]
         L.cntr_graph_begin.argtypes = [vp]

@@ -289,6 +289,81 @@ def solve_gw_k(G: list, eps: list, U: float, mats_iters=10, boot_iters=6, ncorr=
     return F, X, S
 
 
+def phonon_free(D: list, w0: list, stream=None):
+    """D0 of X = a + a^dag for each mode frequency w0[i] into the bosonic D[i] (cntr_phonon_free)."""
+    w = (C.c_double * len(D))(*[float(x) for x in w0])
+    _abi.check(_abi.lib().cntr_phonon_free(len(D), _grids(D), _gfs(D), w, _stream(stream)))
+
+
+def scale_slice(tstp: int, C_: list, A: list, f: list, beta: float = 0.0, stream=None):
+    """C = beta C + f(t) A(t,t') f(t') on slice tstp (cntr_scale_slice); f[i] a device float64 tensor of nt+2."""
+    _abi.check(_abi.lib().cntr_scale_slice(tstp, len(C_), _grids(C_), _gfs(C_), _gfs(A), _ptrs(f), float(beta),
+                                            _stream(stream)))
+
+
+def holstein_mf(tstp: int, G: list, g: list, w0: list, e0: float, X: list, eps: list, stream=None):
+    """Phonon displacement X(t_tstp) of Eq. X and the level e0 + g X (cntr_holstein_mf)."""
+    w = (C.c_double * len(G))(*[float(x) for x in w0])
+    _abi.check(_abi.lib().cntr_holstein_mf(tstp, len(G), _grids(G), _gfs(G), _ptrs(g), w, float(e0), _ptrs(X),
+                                            _ptrs(eps), _stream(stream)))
+
+
+def solve_holstein(G, J, gel, w0: float, e0: float = 0.0, mats_iters=30, boot_iters=8, ncorr=4, nt_stop=None,
+                   stream=None):
+    """Bethe-lattice DMFT with the unrenormalized Migdal impurity solver for
+    the local G (a zero Contour on entry, d = 1): Delta = J G J, Sigma =
+    i g g D0 G (cntr_sigma_gw_k with one momentum and g D0 g), the level
+    e0 + g X with X of Eq. X, Dyson's self-energy Delta + Sigma. J, gel:
+    device float64 tensors of nt+2 (entry 0: Matsubara branch). The sequence:
+      Matsubara: mats_iters x {X, Delta^M, Sigma^M; G^M},
+      start-up:  boot_iters x {X, Delta, Sigma on slices 0..k; start-up of G},
+      steps:     extrapolation of G, then ncorr x {X, Delta, Sigma on slice n; step n}.
+    Returns (D0g, Delta, Sigma, X, eps) on the device."""
+    g = G.g
+    k = g.k
+    nt_stop = g.nt if nt_stop is None else nt_stop
+    dev = G.ret.device
+    gb = dataclasses.replace(g, sig=1, mu=0.0)
+    D0, D0g = Contour(gb, dev), Contour(gb, dev)
+    phonon_free([D0], [w0], stream)
+    for n in range(-1, g.nt + 1):
+        scale_slice(n, [D0g], [D0], [gel], 0.0, stream)
+    Delta, S, St = Contour(g, dev), Contour(g, dev), Contour(g, dev)
+    X = torch.zeros(g.nt + 2, dtype=torch.float64, device=dev)
+    eps = torch.zeros((g.nt + 2, 1, 1), dtype=torch.complex128, device=dev)
+    eps[0] = e0
+    ones = torch.ones(g.nt + 2, dtype=torch.float64, device=dev)
+    KB = KBatch([G], [S], [D0g], [S])
+    B = Batch([G], [St], [eps])
+
+    def selfenergies(n):
+        scale_slice(n, [Delta], [G], [J], 0.0, stream)
+        KB.sigma(n, 1.0, stream)
+        scale_slice(n, [St], [S], [ones], 0.0, stream)
+        scale_slice(n, [St], [Delta], [ones], 1.0, stream)
+
+    def mf(n):
+        holstein_mf(n, [G], [gel], [w0], e0, [X], [eps], stream)
+
+    B.init_matsubara(stream=stream)
+    for _ in range(mats_iters):
+        mf(-1)
+        selfenergies(-1)
+        B.init_matsubara(stream=stream)
+    for _ in range(boot_iters):
+        for n in range(k + 1):
+            mf(n)
+            selfenergies(n)
+        B.step(k, stream)
+    for n in range(k + 1, nt_stop + 1):
+        B.extrapolate(n - 1, stream)
+        for _ in range(ncorr):
+            mf(n)
+            selfenergies(n)
+            B.step(n, stream)
+    return D0g, Delta, S, X, eps
+
+
 OBS_NAMES = ("N", "E1", "Emf", "Ecorr", "Etot")
 
 

@@ -1199,6 +1199,91 @@ cntr_status cntr_sigma_gw_k(int32_t tstp, int32_t nk, const cntr_grid* grids, co
   return kspace_call(2, tstp, nk, grids, G, dW, Sigma, alpha, stream, "cntr_sigma_gw_k");
 }
 
+// ------------------------------------------------- Holstein DMFT pieces
+cntr_status cntr_phonon_free(int32_t count, const cntr_grid* grids, const cntr_gf* D, const double* w0,
+                             void* stream) {
+  cntr_status st = check_batch(count, grids, "cntr_phonon_free");
+  if (st) return st;
+  if (!gf_ok(D, count) || !w0) return fail(CNTR_ESHAPE, "cntr_phonon_free: null pointer");
+  int ntmax = 0;
+  for (int i = 0; i < count; i++) {
+    if (grids[i].d != 1 || grids[i].sig != 1)
+      return fail(CNTR_ESHAPE, "cntr_phonon_free: one bosonic mode per problem (d = 1, sig = +1)");
+    if (!(w0[i] > 0) || !std::isfinite(w0[i])) return fail(CNTR_EINVAL, "cntr_phonon_free: w0 must be > 0");
+    ntmax = std::max(ntmax, (int)grids[i].nt);
+  }
+  hipStream_t s = (hipStream_t)stream;
+  StreamScratch* sc = scratch_for(s);
+  if ((st = grow(s, sc, 256, 5 * (size_t)count, 2))) return st;
+  std::vector<Prob> v(count);
+  for (int i = 0; i < count; i++) {
+    v[i] = make_prob(grids[i], &D[i], nullptr, nullptr);
+    v[i].par = w0[i];
+  }
+  ProbArg pa;
+  if ((st = make_arg(s, sc, v, 0, &pa))) return st;
+  hipError_t e = launch_phonon_free(pa, ntmax, grids[0].ntau, s);
+  if (e != hipSuccess) return hip_fail(e, "cntr_phonon_free launch");
+  return CNTR_OK;
+}
+
+cntr_status cntr_scale_slice(int32_t tstp, int32_t count, const cntr_grid* grids, const cntr_gf* C,
+                             const cntr_gf* A, const void* const* f, double beta, void* stream) {
+  cntr_status st = check_batch(count, grids, "cntr_scale_slice");
+  if (st) return st;
+  if (!gf_ok(C, count) || !gf_ok(A, count) || !f) return fail(CNTR_ESHAPE, "cntr_scale_slice: null pointer");
+  for (int i = 0; i < count; i++) {
+    if (!f[i]) return fail(CNTR_ESHAPE, "cntr_scale_slice: null f");
+    if (tstp < -1 || tstp > grids[i].nt) return fail(CNTR_EORDER, "cntr_scale_slice: tstp outside -1..nt");
+  }
+  hipStream_t s = (hipStream_t)stream;
+  StreamScratch* sc = scratch_for(s);
+  if ((st = grow(s, sc, 256, 5 * (size_t)count, 2))) return st;
+  std::vector<Prob> vc(count), va(count);
+  for (int i = 0; i < count; i++) {
+    vc[i] = make_prob(grids[i], &C[i], nullptr, nullptr);
+    vc[i].U = (const double*)f[i];
+    va[i] = make_prob(grids[i], &A[i], nullptr, nullptr);
+  }
+  ProbArg pc, pa;
+  if ((st = make_arg(s, sc, vc, 0, &pc)) || (st = make_arg(s, sc, va, 1, &pa))) return st;
+  hipError_t e = launch_scale_slice(pc, pa, tstp, grids[0].d, grids[0].ntau, beta, s);
+  if (e != hipSuccess) return hip_fail(e, "cntr_scale_slice launch");
+  return CNTR_OK;
+}
+
+cntr_status cntr_holstein_mf(int32_t tstp, int32_t count, const cntr_grid* grids, const cntr_gf* G,
+                             const void* const* g, const double* w0, double e0, void* const* X, void* const* eps,
+                             void* stream) {
+  cntr_status st = check_batch(count, grids, "cntr_holstein_mf");
+  if (st) return st;
+  if (!gf_ok(G, count) || !g || !w0 || !X || !eps) return fail(CNTR_ESHAPE, "cntr_holstein_mf: null pointer");
+  for (int i = 0; i < count; i++) {
+    if (grids[i].d != 1) return fail(CNTR_ESHAPE, "cntr_holstein_mf: single band (d = 1)");
+    if (!g[i] || !X[i] || !eps[i]) return fail(CNTR_ESHAPE, "cntr_holstein_mf: null series");
+    if (!(w0[i] > 0) || !std::isfinite(w0[i])) return fail(CNTR_EINVAL, "cntr_holstein_mf: w0 must be > 0");
+    if (tstp < -1 || tstp > grids[i].nt || grids[i].k > grids[i].nt)
+      return fail(CNTR_EORDER, "cntr_holstein_mf: tstp outside -1..nt (or k > nt)");
+  }
+  if ((st = ensure_weights())) return st;
+  hipStream_t s = (hipStream_t)stream;
+  StreamScratch* sc = scratch_for(s);
+  if ((st = grow(s, sc, 256, 5 * (size_t)count, 2))) return st;
+  std::vector<Prob> v(count);
+  for (int i = 0; i < count; i++) {
+    v[i] = make_prob(grids[i], &G[i], nullptr, nullptr);
+    v[i].U = (const double*)g[i];
+    v[i].par = w0[i];
+    v[i].aux = (double*)X[i];
+    v[i].eps_mf = (cplx*)eps[i];
+  }
+  ProbArg pa;
+  if ((st = make_arg(s, sc, v, 0, &pa))) return st;
+  hipError_t e = launch_holstein_mf(pa, tstp, e0, s);
+  if (e != hipSuccess) return hip_fail(e, "cntr_holstein_mf launch");
+  return CNTR_OK;
+}
+
 cntr_status cntr_convolution(int32_t tstp, int32_t count, const cntr_grid* grids, const cntr_gf* C,
                              const cntr_gf* A, const cntr_gf* Acc, const cntr_gf* B,
                              const cntr_gf* Bcc, const void* const* f, void* stream) {

@@ -97,6 +97,10 @@ struct Prob {
   // F^< (rows m > j come from Fcc^<) and Fcc^R (F^R continued to t < t')
   const cplx *Qmat, *Qret, *Qles, *Qtv;
   const cplx *Fles, *Fcret;
+  // Holstein pieces: a per-problem real series (nt+2, index n+1; entry 0 the
+  // Matsubara branch) and a per-problem parameter
+  double* aux;
+  double par;
 };
 
 __host__ __device__ inline size_t tri(int n) { return (size_t)n * (n + 1) / 2; }

@@ -149,6 +149,16 @@ hipError_t launch_vie2_step(const ProbArg& pa, const Scratch& sc, int n, int d, 
 hipError_t launch_kbubble(int mode, const Prob* pg, const Prob* pw, const Prob* po, int nk, int d, int ntau,
                           int sig, int n, double alpha, hipStream_t s);
 
+// Holstein DMFT pieces (d = 1 for the phonon propagator and the displacement):
+// the free propagator of X = a + a^dag into every component (w0 = P.par,
+// bosonic grids); C = beta C + f A f on slice n (f = C's series U); the
+// displacement X(t_n) (into P.aux) and the level e0 + g X (into P.eps_mf),
+// g = P.U, w0 = P.par
+hipError_t launch_phonon_free(const ProbArg& pa, int nt_max, int ntau, hipStream_t s);
+hipError_t launch_scale_slice(const ProbArg& pc, const ProbArg& pa, int n, int d, int ntau, double beta,
+                              hipStream_t s);
+hipError_t launch_holstein_mf(const ProbArg& pg, int n, double e0, hipStream_t s);
+
 // Matsubara pieces (per problem, one problem per call)
 hipError_t launch_free_mat(const Prob& P, cplx* g, hipStream_t s);
 // free Green's function of eps(t) into every component of P's G (scratch of

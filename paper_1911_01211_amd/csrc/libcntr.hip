@@ -8,4 +8,5 @@
 #include "adjoint.hip"
 #include "free.hip"
 #include "kspace.hip"
+#include "holstein.hip"
 #include "api.cpp"
