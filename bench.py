@@ -669,6 +669,56 @@ def run_gw(args):
             "check": {"particle_number": dens, "drift": max(abs(x - dens[0]) for x in dens)}}
 
 
+def run_holstein(args):
+    """Holstein DMFT on the Bethe lattice with the uMig impurity solver at the
+    parameters of the paper's example: g = 0.5, w0 = 0.5, beta = 10, half
+    filling (mu = g X = -2 g^2 / w0), J = 1, the coupling and the hopping
+    modulated with a sin^2 envelope (Omega = 1.2, t_end = 15.7, dg = 0.05,
+    dJ = 0.1); h = 0.02, nt = 1000, ntau = 400, k = 5, 30 Matsubara and 8
+    start-up iterations, 4 corrector iterations per step. One impurity: the
+    step is a short sequence of small launches (displacement, three slice
+    scalings, the bubble, the Dyson step). Timed: the whole solve, and the
+    same solve stopped after the start-up (the difference is the steps)."""
+    import torch
+
+    from paper_1911_01211_amd import contour as K
+    from paper_1911_01211_amd import workloads as W
+
+    g0, w0 = 0.5, 0.5
+    g = W.GridSpec(nt=1000, ntau=400, d=1, sig=-1, k=5, beta=10.0, h=0.02, mu=-2 * g0 * g0 / w0)
+    J, gel = W.holstein_drive(g, g0=g0)
+    Jd, gd = torch.as_tensor(J).to("cuda:0"), torch.as_tensor(gel).to("cuda:0")
+    kw = dict(mats_iters=30, boot_iters=8, ncorr=4)
+
+    def solve(nt_stop):
+        G = K.Contour(g, "cuda:0")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = K.solve_holstein(G, Jd, gd, w0, nt_stop=nt_stop, **kw)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, G, out
+
+    solve(g.k)  # warm-up (library scratch, weights)
+    t_set, _, _ = solve(g.k)
+    K.profile_begin(PROF_EVERY)
+    t_all, G, (_, _, _, X, _) = solve(g.nt)
+    prof = K.profile_end()
+    t_steps = t_all - t_set
+    nsteps = g.nt - g.k
+    dens = [2.0 * G.les[m * (m + 1) // 2 + m, 0, 0].imag.item() for m in range(0, g.nt + 1, 100)]
+    Xh = X.cpu().numpy()
+    gbs = prof["hist_bytes"] / (prof["hist_ms"] * 1e-3) / 1e9 if prof["hist_ms"] > 0 else None
+    return {"workload": "Holstein DMFT (Bethe lattice, uMig), g=0.5, w0=0.5, beta=10, half filling, g(t) and J(t) "
+                        "modulated (Omega=1.2, t_end=15.7, dg=0.05, dJ=0.1), h=0.02, nt=1000, ntau=400, k=5",
+            "value": nsteps / t_steps, "unit": "time-steps/s", "seconds": {"whole": t_all, "setup": t_set},
+            "us_per_step": t_steps / nsteps * 1e6, "corrector_iterations": kw["ncorr"],
+            "roofline": {"bound": "hbm", "kernel": "k_history<1>", "achieved": gbs, "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS if gbs else None,
+                         "avg_launch_us": prof["hist_ms"] * 1e3 / max(1, prof["hist_launches"])},
+            "check": {"density_every_100": dens, "X_min_max": [float(Xh[1:].min()), float(Xh[1:].max())],
+                      "X_eq": float(Xh[0])}}
+
+
 def stream_bandwidth():
     """Device copy of 1 GiB (1 GiB read + 1 GiB written), best of 5, in GB/s:
     the attainable HBM rate that the roofline is also quoted against."""
@@ -823,6 +873,7 @@ def main():
     ap.add_argument("--no-cfg1", action="store_true")
     ap.add_argument("--no-vie2", action="store_true")
     ap.add_argument("--no-gw", action="store_true")
+    ap.add_argument("--no-holstein", action="store_true")
     ap.add_argument("--gw-nk", type=int, default=256, help="momenta of the k-space GW sample")
     ap.add_argument("--gw-nt", type=int, default=400, help="last slice of the k-space GW sample")
     ap.add_argument("--no-tune-cache", action="store_true", help="built-in term chunks instead of tune_cache.json")
@@ -905,6 +956,8 @@ def main():
         out["batched"] = run_kpoints(args)
     if not args.no_gw:
         out["gw_kspace"] = run_gw(args)
+    if not args.no_holstein:
+        out["holstein"] = run_holstein(args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(g, args.ncorr, stats.mats_iter, args.cpu_budget)
     print(json.dumps(out), flush=True)

@@ -195,6 +195,18 @@ def peierls_pulse(t: np.ndarray, E0: float = 1.0, omega: float = 2.0, t0: float 
     return E0 * np.sin(omega * t) * np.exp(-((t - t0) ** 2) / (2 * s * s))
 
 
+def holstein_drive(g: GridSpec, g0: float = 0.5, dg: float = 0.05, J0: float = 1.0, dJ: float = 0.1,
+                   omega: float = 1.2, t_end: float = 15.7):
+    """Hopping J(t) and electron-phonon coupling g(t) of the Holstein example,
+    both modulated as x0 + dx sin^2(pi t / t_end) sin(omega t) for t < t_end:
+    returns (J, g), each nt + 2 real values (entry 0: the Matsubara branch)."""
+    t = np.arange(g.nt + 1) * g.h
+    env = np.where(t < t_end, np.sin(np.pi * t / t_end) ** 2, 0.0) * np.sin(omega * t)
+    J = np.concatenate([[J0], J0 + dJ * env])
+    gel = np.concatenate([[g0], g0 + dg * env])
+    return J, gel
+
+
 def kpoint_band(g: GridSpec, nk: int = 512):
     """Single-band lattice eps_k(t) = -2 cos(k - A(t)) for nk uniform k:
     returns eps [nk, nt+2, 1, 1] with eps_k(0^-) = -2 cos k."""
