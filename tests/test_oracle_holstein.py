@@ -71,7 +71,8 @@ def test_displacement_quadrature_order(O):
         for n in range(nt + 1):
             H.displacement(n, G, gel, w0, X)
         errs.append(max(abs(X[n + 1] - exact(n * h)) for n in range(nt + 1)))
-    assert errs[0] < 1e-6, errs
+    # (observed 1.7e-8 and 1.4e-10: order ~7)
+    assert errs[0] < 1e-7, errs
     assert errs[1] < errs[0] / 2 ** 5, errs
 
 
@@ -85,8 +86,9 @@ def test_bethe_at_g0_is_the_semicircle(O):
         H.solve_holstein(G, J, gel, 0.5, mats_iters=40, boot_iters=8, ncorr=6)
         ref = [-1j * (j1(2 * n * h) / (n * h) if n else 1.0) for n in range(nt + 1)]
         errs.append(max(abs(G.R(n, 0)[0, 0] - ref[n]) for n in range(nt + 1)))
+    # (observed 6.3e-6 and 2.0e-7: order ~5)
     assert errs[0] < 1e-5, errs
-    assert errs[1] < errs[0] / 8, errs
+    assert errs[1] < errs[0] / 16, errs
 
 
 def drive(nt, h):
