@@ -172,14 +172,15 @@ __device__ void v2_final(const Prob& P, const Scratch& sc, int pi, int n, const 
   // G thread groups per value sum every G-th partial of G^<_{n,n} (fixed
   // order), loaded in the same memory round as the rows' chunk partials
   constexpr int G = NTHR / DD > 0 ? NTHR / DD : 1;
+  constexpr int PB = D >= 2 ? 16 : 4;
   for (int vv = tid; vv < G * DD; vv += NTHR) {
     int g = vv / DD, e = vv % DD;
-    dg[vv] = psum_b<16>(dpart + (size_t)g * DD + e, (long)G * DD, g < nwg ? (nwg - g + G - 1) / G : 0);
+    dg[vv] = psum_b<PB>(dpart + (size_t)g * DD + e, (long)G * DD, g < nwg ? (nwg - g + G - 1) / G : 0);
   }
   // X_r M = Q^<_{m,n} - (sum of the chunk partials of row m)
   for (int idx = tid; idx < nr * DD; idx += NTHR) {
     int r = idx / DD, e = idx % DD, m = pl.v2_lo + r;
-    cplx hs = psum_b<16>(epart + (size_t)r * pl.v2_nch * DD + e, DD, pl.v2_nch);
+    cplx hs = psum_b<PB>(epart + (size_t)r * pl.v2_nch * DD + e, DD, pl.v2_nch);
     xe[idx] = gld(P.Qles + (tri(n) + m) * DD + e) - hs;
   }
   __syncthreads();
@@ -203,7 +204,7 @@ __device__ void v2_final(const Prob& P, const Scratch& sc, int pi, int n, const 
       for (int q = 0; q < D; q++) cfma(t, xo[r * DD + q * D + a2], gld(P.Sret + (tri(n) + l) * DD + c2 * D + q));
       acc = acc - (h * greg(W, n, l)) * conj(t);
     }
-    for (int g = 0; g < G; g++) acc = acc + dg[g * DD + tid];
+    for (int g = 0; g < G && g < nwg; g++) acc = acc + dg[g * DD + tid];  // (groups g >= nwg hold no partial)
     xe[tid] = gld(P.Qles + (tri(n) + n) * DD + tid) - acc;
   }
   __syncthreads();
@@ -230,7 +231,9 @@ template <int D>
 __global__ __launch_bounds__(NTHR) void k_v2_reduce(ProbArg pa, Scratch sc, HistPlan pl) {
   constexpr int DD = D * D;
   constexpr int TM = NTHR / DD > 0 ? NTHR / DD : 1;
-  constexpr int MSB = D >= 2 ? 16 : 8;
+  // partials per sequence and round: d = 1 outputs have few chunks, and
+  // fewer registers let more reduce workgroups run at once
+  constexpr int MSB = D >= 2 ? 16 : 4;
   constexpr int NOUT = TM * DD > (KMAX + 1) * DD ? TM * DD : (KMAX + 1) * DD;
   __shared__ cplx minv[(KMAX + 1) * DD];
   __shared__ cplx outs[NOUT];
@@ -351,12 +354,17 @@ __global__ __launch_bounds__(NTHR) void k_v2_reduce(ProbArg pa, Scratch sc, Hist
       }
       outs[mo * DD + e] = v;
     }
-    __syncthreads();
-    if (tid < DD) {
-      cplx acc = mk(0, 0);
-      for (int mm = 0; mm < nm; mm++) acc = acc + outs[mm * DD + tid];
-      gst(dpart + (size_t)b * DD + tid, acc);
+    // summed over the tile's outputs by a pairwise tree (fixed order)
+    constexpr int TP = TM <= 1 ? 1 : (TM <= 2 ? 2 : (TM <= 4 ? 4 : (TM <= 8 ? 8 : (TM <= 16 ? 16 : (TM <= 32 ? 32 : (TM <= 64 ? 64 : (TM <= 128 ? 128 : 256)))))));
+    for (int w = TP / 2; w >= 1; w /= 2) {
+      __syncthreads();
+      for (int idx = tid; idx < w * DD; idx += NTHR) {
+        int mm = idx / DD, e2 = idx % DD;
+        if (mm + w < nm) outs[mm * DD + e2] = outs[mm * DD + e2] + outs[(mm + w) * DD + e2];
+      }
     }
+    __syncthreads();
+    if (tid < DD) gst(dpart + (size_t)b * DD + tid, outs[tid]);
   } else {
     // retarded rows m = n - r, r = 0..k: G^R_{n,n} = Q^R_{n,n}; for r >= 1 the
     // k+1 points n-k..n with start-up weights s_{r,j} and G^R continued to
