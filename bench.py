@@ -678,7 +678,11 @@ def run_holstein(args):
     start-up iterations, 4 corrector iterations per step. One impurity: the
     step is a short sequence of small launches (displacement, three slice
     scalings, the bubble, the Dyson step). Timed: the whole solve, and the
-    same solve stopped after the start-up (the difference is the steps)."""
+    same solve stopped after the start-up (the difference is the steps).
+    Then a batch of impurities (couplings 0.3..0.6) the same way."""
+    import dataclasses
+
+    import numpy as np
     import torch
 
     from paper_1911_01211_amd import contour as K
@@ -708,6 +712,28 @@ def run_holstein(args):
     dens = [2.0 * G.les[m * (m + 1) // 2 + m, 0, 0].imag.item() for m in range(0, g.nt + 1, 100)]
     Xh = X.cpu().numpy()
     gbs = prof["hist_bytes"] / (prof["hist_ms"] * 1e-3) / 1e9 if prof["hist_ms"] > 0 else None
+
+    # a batch of impurities (a sweep of the coupling g0, each at its half
+    # filling) advanced together: one launch per call for all of them
+    nb = args.holstein_batch
+    g0s = np.linspace(0.3, 0.6, nb)
+    gsb = [dataclasses.replace(g, mu=-2 * x * x / w0) for x in g0s]
+    gelb = [torch.as_tensor(W.holstein_drive(gg, g0=x)[1]).to("cuda:0") for gg, x in zip(gsb, g0s)]
+
+    def solve_batch(nt_stop):
+        Gb = [K.Contour(gg, "cuda:0") for gg in gsb]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        K.solve_holstein(Gb, [Jd] * nb, gelb, [w0] * nb, nt_stop=nt_stop, **kw)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    tb_set = solve_batch(g.k)
+    tb_all = solve_batch(g.nt)
+    batch = {"impurities": nb, "g0": [float(g0s[0]), float(g0s[-1])],
+             "value": nsteps * nb / (tb_all - tb_set), "unit": "instance time-steps/s",
+             "us_per_step": (tb_all - tb_set) / nsteps * 1e6, "seconds": {"whole": tb_all, "setup": tb_set},
+             "speedup_vs_single": nsteps * nb / (tb_all - tb_set) / (nsteps / t_steps)}
     return {"workload": "Holstein DMFT (Bethe lattice, uMig), g=0.5, w0=0.5, beta=10, half filling, g(t) and J(t) "
                         "modulated (Omega=1.2, t_end=15.7, dg=0.05, dJ=0.1), h=0.02, nt=1000, ntau=400, k=5",
             "value": nsteps / t_steps, "unit": "time-steps/s", "seconds": {"whole": t_all, "setup": t_set},
@@ -716,7 +742,8 @@ def run_holstein(args):
                          "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS if gbs else None,
                          "avg_launch_us": prof["hist_ms"] * 1e3 / max(1, prof["hist_launches"])},
             "check": {"density_every_100": dens, "X_min_max": [float(Xh[1:].min()), float(Xh[1:].max())],
-                      "X_eq": float(Xh[0])}}
+                      "X_eq": float(Xh[0])},
+            "batch": batch}
 
 
 def stream_bandwidth():
@@ -874,6 +901,7 @@ def main():
     ap.add_argument("--no-vie2", action="store_true")
     ap.add_argument("--no-gw", action="store_true")
     ap.add_argument("--no-holstein", action="store_true")
+    ap.add_argument("--holstein-batch", type=int, default=64, help="impurities of the batched Holstein sample")
     ap.add_argument("--gw-nk", type=int, default=256, help="momenta of the k-space GW sample")
     ap.add_argument("--gw-nt", type=int, default=400, help="last slice of the k-space GW sample")
     ap.add_argument("--no-tune-cache", action="store_true", help="built-in term chunks instead of tune_cache.json")

@@ -209,6 +209,16 @@ cntr_status cntr_polarization_k(int32_t tstp, int32_t nk, const cntr_grid* grids
 cntr_status cntr_sigma_gw_k(int32_t tstp, int32_t nk, const cntr_grid* grids, const cntr_gf* G, const cntr_gf* dW,
                             const cntr_gf* Sigma, double alpha, void* stream);
 
+/* The same contour product for independent instances (no momentum sum):
+ * C_i(t,t') = alpha i A_i(t,t') B_i(t,t') element by element (Eq.
+ * def_bubble2), on the stored components of slice tstp, for count <= 65535
+ * instances sharing d and ntau (e.g. the uMig self-energy i g g D0 G of each
+ * impurity of a Holstein batch, Eq. uMig_el). A, B hermitian DEVICE contour
+ * functions, C written on slice tstp only; asynchronous. Errors:
+ * CNTR_ESHAPE (null pointers), CNTR_EORDER (tstp outside -1..nt). */
+cntr_status cntr_bubble2_local(int32_t tstp, int32_t count, const cntr_grid* grids, const cntr_gf* A,
+                               const cntr_gf* B, const cntr_gf* C, double alpha, void* stream);
+
 /* ------------------------------------------------------------------ F4 --
  * Pieces of the Holstein-model DMFT with the unrenormalized Migdal impurity
  * solver (Sec. "DMFT for the Holstein model"; the Bethe-lattice loop itself

@@ -26,7 +26,7 @@ SYMBOLS = ["cntr_init_matsubara", "cntr_dyson_step", "cntr_convolution", "cntr_s
            "cntr_graph_begin", "cntr_graph_end", "cntr_graph_launch", "cntr_graph_destroy",
            "cntr_solve_2b_uneven", "cntr_set_tiles", "cntr_vie2_matsubara", "cntr_vie2_step",
            "cntr_polarization_k", "cntr_sigma_gw_k", "cntr_phonon_free", "cntr_scale_slice",
-           "cntr_holstein_mf"]
+           "cntr_holstein_mf", "cntr_bubble2_local"]
 
 
 class CntrError(RuntimeError):
@@ -89,6 +89,7 @@ def lib():
         L.cntr_vie2_step.argtypes = [i32, i32, P(Grid), P(GF), P(GF), P(GF), P(GF), vp]
         L.cntr_polarization_k.argtypes = [i32, i32, P(Grid), P(GF), P(GF), dbl, vp]
         L.cntr_sigma_gw_k.argtypes = [i32, i32, P(Grid), P(GF), P(GF), P(GF), dbl, vp]
+        L.cntr_bubble2_local.argtypes = [i32, i32, P(Grid), P(GF), P(GF), P(GF), dbl, vp]
         L.cntr_phonon_free.argtypes = [i32, P(Grid), P(GF), P(dbl), vp]
         L.cntr_scale_slice.argtypes = [i32, i32, P(Grid), P(GF), P(GF), P(vp), dbl, vp]
         L.cntr_holstein_mf.argtypes = [i32, i32, P(Grid), P(GF), P(vp), P(dbl), dbl, P(vp), P(vp), vp]

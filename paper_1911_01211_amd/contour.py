@@ -289,6 +289,12 @@ def solve_gw_k(G: list, eps: list, U: float, mats_iters=10, boot_iters=6, ncorr=
     return F, X, S
 
 
+def bubble2_local(tstp: int, A: list, B: list, C_: list, alpha: float = 1.0, stream=None):
+    """C_i = alpha i A_i B_i elementwise on slice tstp for each instance (cntr_bubble2_local)."""
+    _abi.check(_abi.lib().cntr_bubble2_local(tstp, len(A), _grids(A), _gfs(A), _gfs(B), _gfs(C_), float(alpha),
+                                              _stream(stream)))
+
+
 def phonon_free(D: list, w0: list, stream=None):
     """D0 of X = a + a^dag for each mode frequency w0[i] into the bosonic D[i] (cntr_phonon_free)."""
     w = (C.c_double * len(D))(*[float(x) for x in w0])
@@ -308,42 +314,55 @@ def holstein_mf(tstp: int, G: list, g: list, w0: list, e0: float, X: list, eps: 
                                             _ptrs(eps), _stream(stream)))
 
 
-def solve_holstein(G, J, gel, w0: float, e0: float = 0.0, mats_iters=30, boot_iters=8, ncorr=4, nt_stop=None,
+def solve_holstein(G, J, gel, w0, e0: float = 0.0, mats_iters=30, boot_iters=8, ncorr=4, nt_stop=None,
                    stream=None):
     """Bethe-lattice DMFT with the unrenormalized Migdal impurity solver for
     the local G (a zero Contour on entry, d = 1): Delta = J G J, Sigma =
-    i g g D0 G (cntr_sigma_gw_k with one momentum and g D0 g), the level
-    e0 + g X with X of Eq. X, Dyson's self-energy Delta + Sigma. J, gel:
-    device float64 tensors of nt+2 (entry 0: Matsubara branch). The sequence:
+    i g g D0 G (the bubble of G and g D0 g), the level
+    e0 + g X with X of Eq. X, Dyson's self-energy Delta + Sigma (Sigma by
+    cntr_bubble2_local, one launch for every impurity). J, gel:
+    device float64 tensors of nt+2 (entry 0: Matsubara branch). G, J, gel and
+    w0 may also be lists of equal length: independent impurities (one grid
+    shape) advanced together, one launch per call for all of them. The
+    sequence:
       Matsubara: mats_iters x {X, Delta^M, Sigma^M; G^M},
       start-up:  boot_iters x {X, Delta, Sigma on slices 0..k; start-up of G},
       steps:     extrapolation of G, then ncorr x {X, Delta, Sigma on slice n; step n}.
-    Returns (D0g, Delta, Sigma, X, eps) on the device."""
-    g = G.g
+    Returns (D0g, Delta, Sigma, X, eps) on the device (lists for list input)."""
+    many = isinstance(G, (list, tuple))
+    Gs = list(G) if many else [G]
+    Js = list(J) if many else [J]
+    gels = list(gel) if many else [gel]
+    w0s = [float(x) for x in w0] if many else [float(w0)]
+    nb = len(Gs)
+    g = Gs[0].g
     k = g.k
     nt_stop = g.nt if nt_stop is None else nt_stop
-    dev = G.ret.device
+    dev = Gs[0].ret.device
     gb = dataclasses.replace(g, sig=1, mu=0.0)
-    D0, D0g = Contour(gb, dev), Contour(gb, dev)
-    phonon_free([D0], [w0], stream)
+    D0 = [Contour(gb, dev) for _ in range(nb)]
+    D0g = [Contour(gb, dev) for _ in range(nb)]
+    phonon_free(D0, w0s, stream)
     for n in range(-1, g.nt + 1):
-        scale_slice(n, [D0g], [D0], [gel], 0.0, stream)
-    Delta, S, St = Contour(g, dev), Contour(g, dev), Contour(g, dev)
-    X = torch.zeros(g.nt + 2, dtype=torch.float64, device=dev)
-    eps = torch.zeros((g.nt + 2, 1, 1), dtype=torch.complex128, device=dev)
-    eps[0] = e0
-    ones = torch.ones(g.nt + 2, dtype=torch.float64, device=dev)
-    KB = KBatch([G], [S], [D0g], [S])
-    B = Batch([G], [St], [eps])
+        scale_slice(n, D0g, D0, gels, 0.0, stream)
+    Delta = [Contour(x.g, dev) for x in Gs]
+    S = [Contour(x.g, dev) for x in Gs]
+    St = [Contour(x.g, dev) for x in Gs]
+    X = [torch.zeros(g.nt + 2, dtype=torch.float64, device=dev) for _ in range(nb)]
+    eps = [torch.zeros((g.nt + 2, 1, 1), dtype=torch.complex128, device=dev) for _ in range(nb)]
+    for e in eps:
+        e[0] = e0
+    ones = [torch.ones(g.nt + 2, dtype=torch.float64, device=dev)] * nb
+    B = Batch(Gs, St, eps)
 
     def selfenergies(n):
-        scale_slice(n, [Delta], [G], [J], 0.0, stream)
-        KB.sigma(n, 1.0, stream)
-        scale_slice(n, [St], [S], [ones], 0.0, stream)
-        scale_slice(n, [St], [Delta], [ones], 1.0, stream)
+        scale_slice(n, Delta, Gs, Js, 0.0, stream)
+        bubble2_local(n, Gs, D0g, S, 1.0, stream)
+        scale_slice(n, St, S, ones, 0.0, stream)
+        scale_slice(n, St, Delta, ones, 1.0, stream)
 
     def mf(n):
-        holstein_mf(n, [G], [gel], [w0], e0, [X], [eps], stream)
+        holstein_mf(n, Gs, gels, w0s, e0, X, eps, stream)
 
     B.init_matsubara(stream=stream)
     for _ in range(mats_iters):
@@ -361,7 +380,9 @@ def solve_holstein(G, J, gel, w0: float, e0: float = 0.0, mats_iters=30, boot_it
             mf(n)
             selfenergies(n)
             B.step(n, stream)
-    return D0g, Delta, S, X, eps
+    if many:
+        return D0g, Delta, S, X, eps
+    return D0g[0], Delta[0], S[0], X[0], eps[0]
 
 
 OBS_NAMES = ("N", "E1", "Emf", "Ecorr", "Etot")

@@ -1199,6 +1199,32 @@ cntr_status cntr_sigma_gw_k(int32_t tstp, int32_t nk, const cntr_grid* grids, co
   return kspace_call(2, tstp, nk, grids, G, dW, Sigma, alpha, stream, "cntr_sigma_gw_k");
 }
 
+cntr_status cntr_bubble2_local(int32_t tstp, int32_t count, const cntr_grid* grids, const cntr_gf* A,
+                               const cntr_gf* B, const cntr_gf* C, double alpha, void* stream) {
+  cntr_status st = check_batch(count, grids, "cntr_bubble2_local");
+  if (st) return st;
+  if (count > 65535) return fail(CNTR_EINVAL, "cntr_bubble2_local: more than 65535 instances");
+  if (!gf_ok(A, count) || !gf_ok(B, count) || !gf_ok(C, count))
+    return fail(CNTR_ESHAPE, "cntr_bubble2_local: null pointer");
+  for (int i = 0; i < count; i++)
+    if (tstp < -1 || tstp > grids[i].nt) return fail(CNTR_EORDER, "cntr_bubble2_local: tstp outside -1..nt");
+  hipStream_t s = (hipStream_t)stream;
+  StreamScratch* sc = scratch_for(s);
+  if ((st = grow(s, sc, 256, 5 * (size_t)count, 2))) return st;
+  std::vector<Prob> va(count), vb(count), vc(count);
+  for (int i = 0; i < count; i++) {
+    va[i] = make_prob(grids[i], &A[i], nullptr, nullptr);
+    vb[i] = make_prob(grids[i], &B[i], nullptr, nullptr);
+    vc[i] = make_prob(grids[i], &C[i], nullptr, nullptr);
+  }
+  ProbArg pa, pb, pc;
+  if ((st = make_arg(s, sc, va, 0, &pa)) || (st = make_arg(s, sc, vb, 1, &pb)) || (st = make_arg(s, sc, vc, 2, &pc)))
+    return st;
+  hipError_t e = launch_bubble2_local(pa, pb, pc, tstp, grids[0].d, grids[0].ntau, alpha, s);
+  if (e != hipSuccess) return hip_fail(e, "cntr_bubble2_local launch");
+  return CNTR_OK;
+}
+
 // ------------------------------------------------- Holstein DMFT pieces
 cntr_status cntr_phonon_free(int32_t count, const cntr_grid* grids, const cntr_gf* D, const double* w0,
                              void* stream) {

@@ -326,6 +326,54 @@ __global__ __launch_bounds__(NKB) void k_kbubble(const Prob* first, const Prob* 
   }
 }
 
+// C_i = alpha i A_i B_i element by element for independent instances (the
+// local Bubble2, no momentum sum): one thread per stored element of slice n,
+// grid y = instance
+__global__ __launch_bounds__(NKB) void k_bubble2_local(ProbArg pa, ProbArg pb, ProbArg pc, int n, double alpha) {
+  const Prob& A = pa.get(blockIdx.y);
+  const Prob& B = pb.get(blockIdx.y);
+  const Prob& C = pc.get(blockIdx.y);
+  const int d = C.d, dd = d * d, ntau = C.ntau;
+  const long idx = (long)blockIdx.x * NKB + threadIdx.x;
+  const long bl = idx / dd;
+  const int e = (int)(idx % dd), a = e / d, c = e % d;
+  if (n == -1) {
+    if (bl > ntau) return;
+    size_t o = (size_t)bl * dd + e;
+    gst(C.Gmat + o, alpha * (gld(A.Gmat + o) * gld(B.Gmat + o)));
+    return;
+  }
+  cplx v;
+  cplx* dst;
+  if (bl <= n) {  // R(n, m), m = bl
+    int m = (int)bl;
+    size_t o = (tri(n) + m) * dd + e;
+    cplx ra = gld(A.Gret + o), rb = gld(B.Gret + o);
+    cplx la = les_below(A.Gles, d, n, m, a, c), lb = les_below(B.Gles, d, n, m, a, c);
+    v = mul_i((ra + la) * rb + ra * lb);
+    dst = C.Gret + o;
+  } else if (bl <= 2 * (long)n + 1) {  // L(m, n)
+    size_t o = (tri(n) + (bl - n - 1)) * dd + e;
+    v = mul_i(gld(A.Gles + o) * gld(B.Gles + o));
+    dst = C.Gles + o;
+  } else {  // T(n, m)
+    long m = bl - 2 * (long)n - 2;
+    if (m > ntau) return;
+    size_t o = ((size_t)n * (ntau + 1) + m) * dd + e;
+    v = mul_i(gld(A.Gtv + o) * gld(B.Gtv + o));
+    dst = C.Gtv + o;
+  }
+  gst(dst, alpha * v);
+}
+
+hipError_t launch_bubble2_local(const ProbArg& pa, const ProbArg& pb, const ProbArg& pc, int n, int d, int ntau,
+                                double alpha, hipStream_t s) {
+  long nel = (n == -1 ? (long)(ntau + 1) : (long)(2 * (n + 1) + ntau + 1)) * d * d;
+  dim3 g((unsigned)((nel + NKB - 1) / NKB), (unsigned)pc.count);
+  k_bubble2_local<<<g, NKB, 0, s>>>(pa, pb, pc, n, alpha);
+  return hipGetLastError();
+}
+
 hipError_t launch_kbubble(int mode, const Prob* pg, const Prob* pw, const Prob* po, int nk, int d, int ntau,
                           int sig, int n, double alpha, hipStream_t s) {
   int dd = d * d;

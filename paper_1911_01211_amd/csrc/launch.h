@@ -148,6 +148,9 @@ hipError_t launch_vie2_step(const ProbArg& pa, const Scratch& sc, int n, int d, 
 // grid (d, ntau, the statistics sig of G); the result times alpha
 hipError_t launch_kbubble(int mode, const Prob* pg, const Prob* pw, const Prob* po, int nk, int d, int ntau,
                           int sig, int n, double alpha, hipStream_t s);
+// C_i = alpha i A_i B_i (local Bubble2) on slice n for every instance
+hipError_t launch_bubble2_local(const ProbArg& pa, const ProbArg& pb, const ProbArg& pc, int n, int d, int ntau,
+                                double alpha, hipStream_t s);
 
 // Holstein DMFT pieces (d = 1 for the phonon propagator and the displacement):
 // the free propagator of X = a + a^dag into every component (w0 = P.par,

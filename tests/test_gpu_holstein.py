@@ -130,3 +130,57 @@ def test_holstein_errors(O):
         K.scale_slice(5, [D1], [D1], [f])
     assert e.value.code == -3
     assert L.cntr_scale_slice(0, 1, K._grids([D1]), K._gfs([D1]), K._gfs([D1]), None, 0.0, K._stream()) == -2
+
+
+@pytest.mark.parametrize("d", [1, 2])
+def test_bubble2_local_parity(O, d):
+    """cntr_bubble2_local: C_i = alpha i A_i B_i per instance (no momentum sum)
+    against the oracle's one-momentum Sigma (oracle/kspace.py)."""
+    require_gpu()
+    from oracle import kspace as KS
+    g = O.Grid(8, 12, d, -1, 3, 2.0, 0.1, 0.0)
+    r = W.rng(1919, d)
+    As, Bs = [], []
+    for _ in range(3):
+        for L in (As, Bs):
+            X = O.HM(g)
+            data = W.random_contour(r, spec(g), 1.0)
+            for f in K.KEYS:
+                getattr(X, f)[...] = data[f]
+            L.append(X)
+    Cs = [O.HM(g) for _ in range(3)]
+    Ad = [K.Contour(spec(g), "cuda", data={k: getattr(x, k) for k in K.KEYS}) for x in As]
+    Bd = [K.Contour(spec(g), "cuda", data={k: getattr(x, k) for k in K.KEYS}) for x in Bs]
+    Cd = [K.Contour(spec(g), "cuda") for _ in range(3)]
+    for n in (-1, 0, 5, 8):
+        for i in range(3):
+            KS.sigma_gw(n, [As[i]], [Bs[i]], [Cs[i]], -0.8)
+        K.bubble2_local(n, Ad, Bd, Cd, -0.8)
+    K.sync()
+    for i in range(3):
+        check(Cd[i], Cs[i], 1e-13, f"bubble2_local d={d} i={i}")
+
+
+def test_holstein_batch_is_the_single_solve(O):
+    """Three impurities (couplings 0.4, 0.5, 0.6 with their half-filling mu)
+    advanced together equal three single solves, bit for bit."""
+    require_gpu()
+    nt, h = 16, 0.1
+    gs, Js, gels, Gs = [], [], [], []
+    for g0 in (0.4, 0.5, 0.6):
+        gg = W.GridSpec(nt=nt, ntau=20, d=1, sig=-1, k=5, beta=2.0, h=h, mu=-2 * g0 * g0 / 0.5)
+        J, gel = drive(nt, h)
+        gel = gel - 0.5 + g0
+        gs.append(gg)
+        Js.append(torch.as_tensor(J).to("cuda"))
+        gels.append(torch.as_tensor(gel).to("cuda"))
+        Gs.append(K.Contour(gg, "cuda"))
+    kw = dict(mats_iters=10, boot_iters=4, ncorr=3)
+    _, _, _, Xb, _ = K.solve_holstein(Gs, Js, gels, [0.5] * 3, **kw)
+    for i in range(3):
+        G1 = K.Contour(gs[i], "cuda")
+        _, _, _, X1, _ = K.solve_holstein(G1, Js[i], gels[i], 0.5, **kw)
+        K.sync()
+        for f in K.KEYS:
+            assert torch.equal(getattr(Gs[i], f), getattr(G1, f)), (i, f)
+        assert torch.equal(Xb[i], X1), i
