@@ -250,10 +250,12 @@ __global__ __launch_bounds__(NTHR) void k_v2_reduce(ProbArg pa, Scratch sc, Hist
   double h = P.h, ht = P.htau, xi = P.sig;
   int t0 = pl.red_tiles[0], t1 = pl.red_tiles[1], t2 = pl.red_tiles[2];
   int nwg = t0 + t1 + t2 + 1;
-  int b = blockIdx.x;
   for (int idx = tid; idx < (k + 1) * DD; idx += NTHR) minv[idx] = gld(sc.minv(pi) + idx);
   __syncthreads();
   cplx* dpart = sc.part(pi) + pl.v2_doff * DD;
+  // one workgroup per tile, or (large batches) one per problem walking its tiles
+  const int bw0 = pl.walk_tiles ? 0 : (int)blockIdx.x, bw1 = pl.walk_tiles ? nwg : bw0 + 1;
+  for (int b = bw0; b < bw1; b++) {
   if (b < nwg - 1) {
     int fam, mt;
     if (b < t0) {
@@ -413,14 +415,19 @@ __global__ __launch_bounds__(NTHR) void k_v2_reduce(ProbArg pa, Scratch sc, Hist
       gst(dpart + (size_t)b * DD + tid, acc);
     }
   }
+  __syncthreads();
+  }
   // completion count (reset by k_v2_side); every thread releases its own
-  // stores first, and the last workgroup to arrive finishes the column
+  // stores first, and the last workgroup to arrive finishes the column (a
+  // walking workgroup is the only one of its problem)
   __threadfence();
   __syncthreads();
-  if (tid == 0) is_last = atomicAdd(sc.counter(pi), 1) == nwg - 1;
-  __syncthreads();
-  if (!is_last) return;
-  __threadfence();
+  if (!pl.walk_tiles) {
+    if (tid == 0) is_last = atomicAdd(sc.counter(pi), 1) == nwg - 1;
+    __syncthreads();
+    if (!is_last) return;
+    __threadfence();
+  }
   v2_final<D>(P, sc, pi, n, pl, minv, xe, xo, dg);
 }
 
@@ -640,7 +647,8 @@ static hipError_t vie2_step_d(const ProbArg& pa, const Scratch& sc, int n, hipSt
   k_history<D><<<dim3(pl.grid + 1, pa.count), NTHR, 0, s>>>(pa, sc, pl);
   if (side) (void)hipStreamWaitEvent(s, side->join, 0);
   int ntile = pl.red_tiles[0] + pl.red_tiles[1] + pl.red_tiles[2];
-  k_v2_reduce<D><<<dim3(ntile + 1, pa.count), NTHR, 0, s>>>(pa, sc, pl);
+  pl.walk_tiles = pa.count >= 16;
+  k_v2_reduce<D><<<dim3(pl.walk_tiles ? 1 : ntile + 1, pa.count), NTHR, 0, s>>>(pa, sc, pl);
   return hipGetLastError();
 }
 

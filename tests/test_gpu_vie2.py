@@ -110,6 +110,35 @@ def test_vie2_batch_uneven_lengths(O):
         compare(O, g, Gd, G, f"nt={g.nt}")
 
 
+@pytest.mark.parametrize("d", [1, 4])
+def test_vie2_large_batch_is_the_single_solve(O, d):
+    """18 problems of one call (from 16 on, one reduce workgroup per problem
+    walks its tiles) with nt up to 40: bit for bit the one-problem solves,
+    and the oracle for two of them."""
+    require_gpu()
+    say(f"vie2 batch of 18, d={d}")
+    probs = [inputs("inst", d, 5, 24 + (i % 3) * 8, 14, -1, seed=40 + i) for i in range(18)]
+    Gs = [K.Contour(spec(g), "cuda") for g, _, _, _ in probs]
+    Fs = [dev(g, F) for g, F, _, _ in probs]
+    Fccs = [dev(g, Fcc) for g, _, Fcc, _ in probs]
+    Qs = [dev(g, Q) for g, _, _, Q in probs]
+    K.vie2_matsubara(Gs, Fs, Qs)
+    K.vie2_step(5, Gs, Fs, Fccs, Qs)
+    for n in range(6, 41):
+        K.vie2_step(n, Gs, Fs, Fccs, Qs)
+    for i in (0, 7, 17):
+        G1 = K.Contour(spec(probs[i][0]), "cuda")
+        K.solve_vie2([G1], [Fs[i]], [Fccs[i]], [Qs[i]])
+        K.sync()
+        for f in K.KEYS:
+            assert torch.equal(getattr(Gs[i], f), getattr(G1, f)), (i, f)
+    for i in (0, 17):
+        g, F, Fcc, Q = probs[i]
+        G = O.HM(g)
+        assert O.solve_vie2(G, F, Fcc, Q) == 0
+        compare(O, g, Gs[i], G, f"batch member {i}")
+
+
 def test_vie2_errors(O):
     require_gpu()
     g, F, Fcc, Q = inputs("inst", 2, 2, 8, 6, -1)
