@@ -130,6 +130,23 @@ def test_holstein_errors(O):
         K.scale_slice(5, [D1], [D1], [f])
     assert e.value.code == -3
     assert L.cntr_scale_slice(0, 1, K._grids([D1]), K._gfs([D1]), K._gfs([D1]), None, 0.0, K._stream()) == -2
+    # the local bubble: slice outside -1..nt, null outputs
+    with pytest.raises(_abi.CntrError) as e:
+        K.bubble2_local(5, [D1], [D1], [D1])
+    assert e.value.code == -3
+    assert L.cntr_bubble2_local(0, 1, K._grids([D1]), K._gfs([D1]), K._gfs([D1]), None, 1.0, K._stream()) == -2
+    # the displacement: single band only, slices -1..nt, w0 > 0
+    X = torch.zeros(g1.nt + 2, dtype=torch.float64, device="cuda")
+    ep = torch.zeros((g1.nt + 2, 1, 1), dtype=torch.complex128, device="cuda")
+    with pytest.raises(_abi.CntrError) as e:
+        K.holstein_mf(0, [D], [f], [0.5], 0.0, [X], [ep])
+    assert e.value.code == -2
+    with pytest.raises(_abi.CntrError) as e:
+        K.holstein_mf(g1.nt + 1, [D1], [f], [0.5], 0.0, [X], [ep])
+    assert e.value.code == -3
+    with pytest.raises(_abi.CntrError) as e:
+        K.holstein_mf(0, [D1], [f], [-1.0], 0.0, [X], [ep])
+    assert e.value.code == -1
 
 
 @pytest.mark.parametrize("d", [1, 2])
