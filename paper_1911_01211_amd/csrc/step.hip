@@ -2316,7 +2316,7 @@ __global__ __launch_bounds__(NTHR) void k_reduce(ProbArg pa, Scratch sc, HistPla
   constexpr int NSTAGE = NVMAX > NTHR ? NVMAX : NTHR;
   // partial sums loaded per sequence in one round (one workgroup per compute
   // unit for d >= 2, so registers are plentiful)
-  constexpr int MSB = D >= 2 ? 16 : 8;
+  constexpr int MSB = D == 4 ? 8 : (D >= 2 ? 16 : 8);
   __shared__ cplx outs[TM * DD];
   __shared__ cplx minv[DD];
   __shared__ cplx pre[NVMAX];
