@@ -5,7 +5,9 @@
 //   self-energy   Sigma_k =  (1/Nk) sum_q Bubble2(G_{k-q}, dW_q)   (Eq. Sigmak)
 // with Bubble1: C(t,t') = i A(t,t') B(t',t), C_ij from A_ij and B_ji, and
 // Bubble2: C(t,t') = i A(t,t') B(t,t') (Eqs. def_bubble1, def_bubble2), on
-// the stored components of one time slice (tstp = -1: Matsubara).
+// the stored components of one time slice (tstp = -1: Matsubara). The same
+// product without a momentum sum (C_i = i A_i B_i for independent instances)
+// is k_bubble2_local at the end of the file.
 //
 // A workgroup takes a tile of TJ consecutive stored elements of one
 // component (flat index over (time or tau index, orbital pair), contiguous in
@@ -16,7 +18,9 @@
 // wave's load touches four momenta's pages rather than sixty-four. Each
 // thread owns R consecutive outputs k of one element and keeps the first
 // factor's R window values in registers, shifting in one value per term; the
-// terms of each output are added in order q = 0 .. Nk-1.
+// terms of each output are accumulated with fused multiply-adds in order
+// q = 0 .. Nk-1 (the second product of a two-term rule in a sum of its own,
+// added at the end).
 #include "launch.h"
 
 namespace cntr {
