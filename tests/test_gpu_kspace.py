@@ -154,3 +154,51 @@ def test_gw_propagation_matches_oracle(O):
             e = float(np.abs(o - r).max() / np.abs(r).max())
             say(f"  {name} {comp}: {e:.2e}")
             assert e <= 1e-10, (name, comp, e)
+
+
+def test_kspace_bench_shape_sampled(O):
+    """The momentum sums at the bench's shape (256 momenta, d = 1, ntau = 500,
+    slice 400, and the Matsubara slice) on seeded random contour functions:
+    every component of Pi_k and Sigma_k for three sampled momenta against the
+    oracle's sums over q written out here (Eqs. Pol, Sigmak), <= 1e-10
+    relative to the slice's largest value."""
+    require_gpu()
+    nk, n = 256, 400
+    g = O.Grid(n, 500, 1, -1, 5, 10.0, 0.02, 0.0)
+    gb = O.Grid(n, 500, 1, 1, 5, 10.0, 0.02, 0.0)
+    say(f"kspace bench shape nk={nk} n={n}")
+    r = W.rng(1920, 0)
+
+    def rnd(gg):
+        X = O.HM(gg)
+        data = W.random_contour(r, spec(gg), 0.5)
+        for f in K.KEYS:
+            getattr(X, f)[...] = data[f]
+        return X
+
+    G = [rnd(g) for _ in range(nk)]
+    Wq = [rnd(gb) for _ in range(nk)]
+    Gd, Wd = [dev(x) for x in G], [dev(x) for x in Wq]
+    Pid = [K.Contour(spec(g), "cuda") for _ in range(nk)]
+    Sgd = [K.Contour(spec(g), "cuda") for _ in range(nk)]
+    KB = K.KBatch(Gd, Pid, Wd, Sgd)
+    for tstp in (-1, n):
+        KB.polarization(tstp, 1.0)
+        KB.sigma(tstp, 1.0)
+    K.sync()
+    for kk in (0, 97, 255):
+        for tstp in (-1, n):
+            pi = None
+            sg = None
+            for q in range(nk):
+                b1 = KS.bubble1(tstp, G[(kk + q) % nk], G[q])
+                b2 = KS.bubble2(tstp, G[(kk - q) % nk], Wq[q])
+                pi = b1 if pi is None else {c: pi[c] + b1[c] for c in pi}
+                sg = b2 if sg is None else {c: sg[c] + b2[c] for c in sg}
+            for name, ref, got, sc in (("Pi", pi, Pid[kk], -1.0 / nk), ("Sigma", sg, Sgd[kk], 1.0 / nk)):
+                sl = comp_slices(g, tstp)
+                scale = max(np.abs(sc * ref[c]).max() for c in sl)
+                for comp, s_ in sl.items():
+                    e = float(np.abs(getattr(got, comp)[s_].cpu().numpy() - sc * ref[comp]).max() / scale)
+                    assert e <= 1e-10, (name, kk, tstp, comp, e)
+    say("  sampled momenta 0, 97, 255 ok")
