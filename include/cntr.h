@@ -194,7 +194,10 @@ cntr_status cntr_vie2_step(int32_t tstp, int32_t count, const cntr_grid* grids, 
  *                        (Sigma_{k,ij} from G_{k-q,ij} and dW_{q,ij}),
  * on the stored components of time slice tstp (tstp = -1: the Matsubara
  * component), by the Langreth rules of the two contour products (Eqs.
- * def_bubble1, def_bubble2), times the real factor alpha (e.g. -U for the
+ * def_bubble1, def_bubble2; the Matsubara component from X^M(tau) =
+ * -i X(-i tau, 0), the form in which X^rceil(0, tau) = i xi X^M(beta - tau):
+ * Bubble1^M = -xi A^M(tau) B^M(beta - tau)^T, Bubble2^M = -A^M B^M), times
+ * the real factor alpha (e.g. -U for the
  * kernel F = -U Pi of the screened interaction's integral equation, as the
  * paper's example multiplies Pol by U). G, dW hermitian (a lesser value
  * below the stored triangle is -[X^<(t',t)]^dagger; the stored X^<(t,t) is
@@ -211,7 +214,8 @@ cntr_status cntr_sigma_gw_k(int32_t tstp, int32_t nk, const cntr_grid* grids, co
 
 /* The same contour product for independent instances (no momentum sum):
  * C_i(t,t') = alpha i A_i(t,t') B_i(t,t') element by element (Eq.
- * def_bubble2), on the stored components of slice tstp, for count <= 65535
+ * def_bubble2; Matsubara: C^M = -alpha A^M B^M), on the stored components
+ * of slice tstp, for count <= 65535
  * instances sharing d and ntau (e.g. the uMig self-energy i g g D0 G of each
  * impurity of a Holstein batch, Eq. uMig_el). A, B hermitian DEVICE contour
  * functions, C written on slice tstp only; asynchronous. Errors:

@@ -68,7 +68,10 @@ def bubble1(n, Aa: O.HM, Bb: O.HM):
     g = Aa.g
     out = {}
     if n == -1:
-        out["mat"] = np.array([Aa.M(m) * Mneg(Bb, m).T for m in range(g.ntau + 1)])
+        # X^M(tau) = -i X(-i tau, 0) for every contour function (the form that
+        # gives X^rceil(0, tau) = i xi X^M(beta - tau)), so
+        # C^M(tau) = A(-i tau, 0) B(0, -i tau) = (i A^M(tau)) (i B^M(-tau))
+        out["mat"] = np.array([-Aa.M(m) * Mneg(Bb, m).T for m in range(g.ntau + 1)])
         return out
     # C^R(t,t') = i A^R(t,t') B^<(t',t) + i A^<(t,t') B^A(t',t)
     out["ret"] = np.array([1j * R(Aa, n, m) * L(Bb, m, n).T + 1j * L(Aa, n, m) * A(Bb, m, n).T
@@ -85,7 +88,8 @@ def bubble2(n, Aa: O.HM, Bb: O.HM):
     g = Aa.g
     out = {}
     if n == -1:
-        out["mat"] = np.array([Aa.M(m) * Bb.M(m) for m in range(g.ntau + 1)])
+        # C^M(tau) = -i C(-i tau, 0) = A(-i tau, 0) B(-i tau, 0) = (i A^M) (i B^M)
+        out["mat"] = np.array([-Aa.M(m) * Bb.M(m) for m in range(g.ntau + 1)])
         return out
     # C^R = i A^R B^R + i A^< B^R + i A^R B^<   (at (t_n, t_m), n >= m)
     out["ret"] = np.array([1j * R(Aa, n, m) * R(Bb, n, m) + 1j * L(Aa, n, m) * R(Bb, n, m)

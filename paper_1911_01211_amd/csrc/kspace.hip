@@ -32,16 +32,18 @@ constexpr int KB_KC = KB_R * (NKB / KB_TJ);  // output momenta per workgroup (64
 constexpr int KB_QC = 32;          // terms per staged chunk
 constexpr int KB_XW = KB_KC + KB_QC;         // window of first-factor momenta
 
-// Langreth rules on element (comp, j, a, c) of slice n. Bubble1 with
+// Langreth rules on element (comp, j, a, c) of slice n (the Matsubara rules
+// from X^M(tau) = -i X(-i tau, 0), the form in which X^rceil(0, tau) =
+// i xi X^M(beta - tau)). Bubble1 with
 // A = G_{k+q}, B = G_q:
 //   R (n, m):  i A^R(n,m)[a][c] B^<(m,n)[c][a] + i A^<(n,m)[a][c] B^A(m,n)[c][a],
 //              B^A(m,n)[c][a] = conj(B^R(n,m)[a][c])
 //   < (m, n):  i A^<(m,n)[a][c] B^>(n,m)[c][a],  B^> = B^R + B^<
 //   rceil:     i A^rceil(n,m)[a][c] B^lceil(m,n)[c][a],  B^lceil(m,n) = -xi conj(B^rceil(n,ntau-m))
-//   M (m):     A^M(m)[a][c] xi B^M(ntau-m)[c][a]
+//   M (m):     -xi A^M(m)[a][c] B^M(ntau-m)[c][a]
 // Bubble2 with A = G_{k-q}, B = dW_q, element [a][c] of each factor:
 //   R:   i [A^R B^R + A^<(n,m) B^R + A^R B^<(n,m)]
-//   <:   i A^< B^<;  rceil: i A^rceil B^rceil;  M: A^M B^M
+//   <:   i A^< B^<;  rceil: i A^rceil B^rceil;  M: -A^M B^M
 // A lesser value below the stored triangle, X^<(n,m) with m < n, is
 // -conj(L_{m,n}) transposed; at m = n the stored L_{n,n} itself is used (a
 // computed G^<(t,t) is anti-hermitian only up to the solver's error).
@@ -88,9 +90,9 @@ __device__ inline cplx les_below(const cplx* les, int d, int n, int m, int a, in
 //   Bubble1  R:  xa = A^R,  xb = A^<(n,m);  ya = B^<(m,n)^T,  yb = conj(B^R)   [B^A(m,n)^T]
 //            <:  xa = A^<;  ya = (B^R + B^<(n,m))^T
 //            rceil: xa = A^rceil;  ya = -xi conj(B^rceil(n, ntau-m))
-//            M:  xa = A^M;  ya = xi B^M(ntau-m)^T
+//            M:  xa = A^M;  ya = -xi B^M(ntau-m)^T
 //   Bubble2  R:  xa = A^R + A^<(n,m),  xb = A^R;  ya = B^R,  yb = B^<(n,m)
-//            <, rceil, M:  xa = A,  ya = B  (same component)
+//            <, rceil:  xa = A,  ya = B  (same component);  M:  xa = A^M,  ya = -B^M
 template <int MODE, int COMP>
 __device__ inline void kb_first(const KPtr& P, int d, int ntau, int n, int j, int a, int c, cplx& xa, cplx& xb) {
   int dd = d * d;
@@ -118,7 +120,7 @@ __device__ inline void kb_second(const KPtr& P, int d, int ntau, int n, int j, i
                                  cplx& yb) {
   int dd = d * d;
   if (MODE == 2) {
-    if (COMP == 3) ya = gld(P.a + (size_t)j * dd + a * d + c);
+    if (COMP == 3) ya = -gld(P.a + (size_t)j * dd + a * d + c);
     else if (COMP == 2) ya = gld(P.a + ((size_t)n * (ntau + 1) + j) * dd + a * d + c);
     else if (COMP == 1) ya = gld(P.b + (tri(n) + j) * dd + a * d + c);
     else {
@@ -128,7 +130,7 @@ __device__ inline void kb_second(const KPtr& P, int d, int ntau, int n, int j, i
     return;
   }
   if (COMP == 3) {
-    ya = xi * gld(P.a + (size_t)(ntau - j) * dd + c * d + a);
+    ya = (-xi) * gld(P.a + (size_t)(ntau - j) * dd + c * d + a);
   } else if (COMP == 2) {
     ya = (-xi) * conj(gld(P.a + ((size_t)n * (ntau + 1) + ntau - j) * dd + a * d + c));
   } else if (COMP == 1) {
@@ -344,7 +346,7 @@ __global__ __launch_bounds__(NKB) void k_bubble2_local(ProbArg pa, ProbArg pb, P
   if (n == -1) {
     if (bl > ntau) return;
     size_t o = (size_t)bl * dd + e;
-    gst(C.Gmat + o, alpha * (gld(A.Gmat + o) * gld(B.Gmat + o)));
+    gst(C.Gmat + o, (-alpha) * (gld(A.Gmat + o) * gld(B.Gmat + o)));
     return;
   }
   cplx v;
