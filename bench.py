@@ -586,7 +586,7 @@ def bubble_flops(n, nk, d, ntau, mode):
 def run_gw(args):
     """k-space GW (Eqs. Pol, Sigmak, the screened interaction by the integral
     form) on the batched lattice: nk momenta of eps_k(t) = -2 cos(k - A(t)),
-    d = 1, U = 1, beta = 10, ntau = 500, h = 0.02, k = 5; untimed Matsubara
+    d = 1, U = 2, beta = 10, ntau = 500, h = 0.02, k = 5; untimed Matsubara
     loop and start-up, then the timed steps k+1..nt, each an extrapolation and
     ncorr x {Pi_k, (1 + F_k) * X_k = F_k, Sigma_k, Dyson step} for all
     momenta (one launch sequence per call). At the last slice every call is
@@ -599,8 +599,7 @@ def run_gw(args):
     from paper_1911_01211_amd import contour as K
     from paper_1911_01211_amd import workloads as W
 
-    # (U = 1: the unmixed Matsubara loop converges; at U = 2 it does not)
-    nk, U, ncorr = args.gw_nk, 1.0, 3
+    nk, U, ncorr = args.gw_nk, 2.0, 3
     g = W.GridSpec(nt=args.gw_nt, ntau=500, d=1, sig=-1, k=5, beta=10.0, h=0.02, mu=0.0)
     eps = [torch.as_tensor(e).to("cuda:0") for e in W.kpoint_band(g, nk)]
     gb = dataclasses.replace(g, sig=1)
