@@ -201,3 +201,27 @@ def test_holstein_batch_is_the_single_solve(O):
         for f in K.KEYS:
             assert torch.equal(getattr(Gs[i], f), getattr(G1, f)), (i, f)
         assert torch.equal(Xb[i], X1), i
+
+
+def test_holstein_dmft_long_matches_oracle(O):
+    """The loop to nt = 280 (the d = 1 history sums span two term chunks of
+    256): every component of G, Delta and Sigma and the displacement against
+    the oracle."""
+    require_gpu()
+    nt, h = 280, 0.05
+    say(f"holstein dmft nt={nt}")
+    g = O.Grid(nt, 30, 1, -1, 5, 2.0, h, -1.3)
+    J, gel = drive(nt, h)
+    G = O.HM(g)
+    kw = dict(mats_iters=10, boot_iters=4, ncorr=3)
+    _, Dr, Sr, Xr, er = H.solve_holstein(G, J, gel, 0.5, **kw)
+    Gd = K.Contour(spec(g), "cuda")
+    _, Dd, Sd, Xd, ed = K.solve_holstein(Gd, torch.as_tensor(J).to("cuda"), torch.as_tensor(gel).to("cuda"), 0.5,
+                                         **kw)
+    K.sync()
+    for name, ref, got in (("G", G, Gd), ("Delta", Dr, Dd), ("Sigma", Sr, Sd)):
+        for f in K.KEYS:
+            e = rel(getattr(got, f).cpu().numpy(), getattr(ref, f))
+            assert e <= 1e-10, (name, f, e)
+    assert rel(Xd.cpu().numpy(), Xr) <= 1e-10
+    assert rel(ed.cpu().numpy(), er) <= 1e-10
