@@ -68,6 +68,28 @@ __device__ inline void gst(cplx* p, cplx v) {
   *(CNTR_GLOBAL cntr_v2d*)p = t;
 }
 
+// Completion count of the workgroups of one problem (the last to arrive
+// finishes the work; no workgroup waits for another). Every wave first waits
+// until its own global stores are complete in the L2 (s_waitcnt vmcnt(0):
+// 0xF70 also leaves expcnt and lgkmcnt at their maxima), the workgroup meets
+// at a barrier, and one thread releases them all at agent scope and counts:
+// one L2 write-back per workgroup instead of one per wave. True in every
+// thread of the workgroup whose count reaches `expect`, after an agent-scope
+// acquire of the others' stores.
+__device__ inline bool last_to_arrive(int* counter, int expect, int& flag) {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_s_waitcnt(0xF70);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    flag = atomicAdd(counter, 1) == expect;
+  }
+  __syncthreads();
+  bool last = flag != 0;
+  if (last) __threadfence();
+  return last;
+}
+
 // Retarded value with the continuation t < t':  X~^R_{a,b}[r][c]
 template <int D>
 __device__ inline cplx ret_ext(const cplx* X, int a, int b, int r, int c) {

@@ -2581,14 +2581,8 @@ __global__ __launch_bounds__(NTHR) void k_reduce(ProbArg pa, Scratch sc, HistPla
   if (walk) {
     __syncthreads();  // this workgroup's own partials
   } else {
-    // completion count (the tiles and the operator workgroup); every thread
-    // releases its own stores first
-    __threadfence();
-    __syncthreads();
-    if (tid == 0) is_last = atomicAdd(sc.counter(pi), 1) == nwg;
-    __syncthreads();
-    if (!is_last) return;
-    __threadfence();
+    // completion count (the tiles and the operator workgroup)
+    if (!last_to_arrive(sc.counter(pi), nwg, is_last)) return;
   }
   // last workgroup. The operator Z and the earlier rows are loaded first
   // (into registers), then the partials of all workgroups are summed (G

@@ -417,17 +417,10 @@ __global__ __launch_bounds__(NTHR) void k_v2_reduce(ProbArg pa, Scratch sc, Hist
   }
   __syncthreads();
   }
-  // completion count (reset by k_v2_side); every thread releases its own
-  // stores first, and the last workgroup to arrive finishes the column (a
-  // walking workgroup is the only one of its problem)
-  __threadfence();
-  __syncthreads();
-  if (!pl.walk_tiles) {
-    if (tid == 0) is_last = atomicAdd(sc.counter(pi), 1) == nwg - 1;
-    __syncthreads();
-    if (!is_last) return;
-    __threadfence();
-  }
+  // completion count (reset by k_v2_side): the last workgroup to arrive
+  // finishes the column (a walking workgroup is the only one of its problem)
+  if (pl.walk_tiles) __syncthreads();
+  else if (!last_to_arrive(sc.counter(pi), nwg - 1, is_last)) return;
   v2_final<D>(P, sc, pi, n, pl, minv, xe, xo, dg);
 }
 
