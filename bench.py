@@ -36,8 +36,8 @@ FP64_PEAK_TFLOPS = 78.6  # FP64 vector (and dense FP64 MFMA) peak of MI355X
 # Valid only for the kernel sources it was taken on (hash below); reported
 # as null once they change.
 PROF_EVERY = 8  # time steps per recorded one (HIP events)
-TRAFFIC = {"slice": 1000, "bytes": 3.9805e8, "algorithmic_bytes": 3.5891e8,
-           "src_sha256_16": "5ddd76ef7ee9588f",
+TRAFFIC = {"slice": 1000, "bytes": 3.9809e8, "algorithmic_bytes": 3.5891e8,
+           "src_sha256_16": "cdd6d266151dfea9",
            "profile": "profiles/k_history_traffic_slice1000_d4.md"}
 TRAFFIC_SRCS = ("paper_1911_01211_amd/csrc/step.hip", "paper_1911_01211_amd/csrc/dev_common.h",
                 "paper_1911_01211_amd/csrc/cntr_internal.h")

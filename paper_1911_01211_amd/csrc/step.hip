@@ -3108,7 +3108,7 @@ static hipError_t step_d(const ProbArg& pa, const Scratch& sc, int n, hipStream_
     g_prof.rec.push_back({e0, e1, e2, 16.0 * dd * blocks * pa.count,
                           8.0 * dd * D * hist_block_macs(n, k, ntau) * pa.count});
   }
-  pl.walk_tiles = pa.count >= 16;
+  pl.walk_tiles = pa.count >= REDUCE_WALK_MIN;
   // (one more workgroup forms the boundary-row operator when there are rows)
   int ntile = pl.red_tiles[0] + pl.red_tiles[1] + pl.red_tiles[2];
   dim3 g2(pl.walk_tiles ? 1 : ntile + (pl.red_tiles[2] > 0 ? 1 : 0), pa.count);

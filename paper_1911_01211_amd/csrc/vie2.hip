@@ -640,7 +640,7 @@ static hipError_t vie2_step_d(const ProbArg& pa, const Scratch& sc, int n, hipSt
   k_history<D><<<dim3(pl.grid + 1, pa.count), NTHR, 0, s>>>(pa, sc, pl);
   if (side) (void)hipStreamWaitEvent(s, side->join, 0);
   int ntile = pl.red_tiles[0] + pl.red_tiles[1] + pl.red_tiles[2];
-  pl.walk_tiles = pa.count >= 16;
+  pl.walk_tiles = pa.count >= REDUCE_WALK_MIN;
   k_v2_reduce<D><<<dim3(pl.walk_tiles ? 1 : ntile + 1, pa.count), NTHR, 0, s>>>(pa, sc, pl);
   return hipGetLastError();
 }

@@ -110,14 +110,14 @@ def test_vie2_batch_uneven_lengths(O):
         compare(O, g, Gd, G, f"nt={g.nt}")
 
 
-@pytest.mark.parametrize("d", [1, 4])
-def test_vie2_large_batch_is_the_single_solve(O, d):
-    """18 problems of one call (from 16 on, one reduce workgroup per problem
-    walks its tiles) with nt up to 40: bit for bit the one-problem solves,
-    and the oracle for two of them."""
+@pytest.mark.parametrize("nb,d", [(18, 1), (18, 4), (130, 1)])
+def test_vie2_large_batch_is_the_single_solve(O, nb, d):
+    """nb problems of one call (a reduce workgroup per tile, or from 128 on
+    one per problem, which walks its tiles) with nt up to 40: bit for bit the
+    one-problem solves, and the oracle for two of them."""
     require_gpu()
-    say(f"vie2 batch of 18, d={d}")
-    probs = [inputs("inst", d, 5, 24 + (i % 3) * 8, 14, -1, seed=40 + i) for i in range(18)]
+    say(f"vie2 batch of {nb}, d={d}")
+    probs = [inputs("inst", d, 5, 24 + (i % 3) * 8, 14, -1, seed=40 + i) for i in range(nb)]
     Gs = [K.Contour(spec(g), "cuda") for g, _, _, _ in probs]
     Fs = [dev(g, F) for g, F, _, _ in probs]
     Fccs = [dev(g, Fcc) for g, _, Fcc, _ in probs]
@@ -126,13 +126,13 @@ def test_vie2_large_batch_is_the_single_solve(O, d):
     K.vie2_step(5, Gs, Fs, Fccs, Qs)
     for n in range(6, 41):
         K.vie2_step(n, Gs, Fs, Fccs, Qs)
-    for i in (0, 7, 17):
+    for i in (0, 7, nb - 1):
         G1 = K.Contour(spec(probs[i][0]), "cuda")
         K.solve_vie2([G1], [Fs[i]], [Fccs[i]], [Qs[i]])
         K.sync()
         for f in K.KEYS:
             assert torch.equal(getattr(Gs[i], f), getattr(G1, f)), (i, f)
-    for i in (0, 17):
+    for i in (0, nb - 1):
         g, F, Fcc, Q = probs[i]
         G = O.HM(g)
         assert O.solve_vie2(G, F, Fcc, Q) == 0
