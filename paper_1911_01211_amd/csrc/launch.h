@@ -60,12 +60,14 @@ struct HistPlan {
 // stored triangle s >= t; those from cf on lie entirely below the diagonal.
 constexpr int DU_TT = 32;
 // Reductions of the time step and of the integral-form step: from this many
-// problems in one call on, one workgroup per problem walks all of its tiles
-// (the batch alone fills the 256 compute units, and there is no completion
-// count); smaller batches get one workgroup per tile. Measured on the
-// batched legs: 256 and 512 problems of d = 1 run 23-30 % faster walking,
-// 16 to 64 problems 3-10 % faster with a workgroup per tile.
-constexpr int REDUCE_WALK_MIN = 128;
+// problems in one call on (one per compute unit), one workgroup per problem
+// walks all of its tiles (the batch alone fills the chip, and there is no
+// completion count); smaller batches get one workgroup per tile, since a
+// walking batch would leave compute units idle while each walks its tiles
+// (152 at d = 4 and slice 1000). Measured on the batched legs: 256 and 512
+// problems of d = 1 run 23-30 % faster walking, 16 to 64 problems 3-10 %
+// faster with a workgroup per tile.
+constexpr int REDUCE_WALK_MIN = 256;
 __host__ __device__ inline void du_range(int c, int TS, int ns, int& lo, int& cf) {
   lo = (c * DU_TT) / TS;
   cf = (c * DU_TT + DU_TT - 1 + TS - 1) / TS;

@@ -440,11 +440,11 @@ def test_full_size_2b_prefix(O):
 
 
 # ------------------------------------------------------------ batching
-@pytest.mark.parametrize("nb,d", [(3, 2), (20, 2), (20, 4), (18, 1), (130, 1), (130, 4)])
+@pytest.mark.parametrize("nb,d", [(3, 2), (20, 2), (20, 4), (18, 1), (260, 1), (260, 4)])
 def test_batch_matches_single_instances(O, nb, d):
     """Batched step (one launch for all instances, uneven nt: instances with
     nt < n are skipped) equals the single-instance step bitwise; batches of
-    128 or more use one reduce workgroup per instance, which walks its tiles."""
+    256 or more use one reduce workgroup per instance, which walks its tiles."""
     require_gpu()
     say(f"batch nb={nb} d={d}")
     base = W.GridSpec(nt=30, ntau=40, d=d, beta=3.0, h=0.04, k=5, mu=0.1)

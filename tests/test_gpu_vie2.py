@@ -110,9 +110,9 @@ def test_vie2_batch_uneven_lengths(O):
         compare(O, g, Gd, G, f"nt={g.nt}")
 
 
-@pytest.mark.parametrize("nb,d", [(18, 1), (18, 4), (130, 1)])
+@pytest.mark.parametrize("nb,d", [(18, 1), (18, 4), (260, 1)])
 def test_vie2_large_batch_is_the_single_solve(O, nb, d):
-    """nb problems of one call (a reduce workgroup per tile, or from 128 on
+    """nb problems of one call (a reduce workgroup per tile, or from 256 on
     one per problem, which walks its tiles) with nt up to 40: bit for bit the
     one-problem solves, and the oracle for two of them."""
     require_gpu()
